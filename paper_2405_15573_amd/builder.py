@@ -1,0 +1,506 @@
+"""Host-side builder: point cloud -> H-matrix -> uniform H-matrix (UH-matrix).
+
+Steps, in the paper's order:
+
+1. Cluster tree (Definition 2.1): geometric bisection of the longest bounding-box axis at
+   the median position, to a fixed depth D = ceil(log2(N/leaf)), so that every leaf sits
+   at depth D and holds at most ``leaf`` points.  The children of a cluster partition it
+   and are contiguous in cluster order (``perm`` maps cluster order to user order).
+2. Block cluster tree (Definition 2.2) with the level-conserving subdivision
+   s(tau x sigma) = s(tau) x s(sigma) and the weak admissibility condition
+   eta * dist(tau, sigma) > min(diam tau, diam sigma) (section 3.2), with diameters and
+   distances measured on axis-aligned bounding boxes (section 6.1).  Inadmissible leaf
+   pairs are stored dense.
+3. Admissible blocks: ACA with partial pivoting (section 2.3), then algebraic
+   recompression A|_b ~ U_b Sigma_b V_b^* from the QRs of both factors and the SVD of the
+   small core (section 2.3), truncated relative to the block's largest singular value.
+4. Uniform compression (Algorithm 2 with the agglomeration X_{tau|b} = U_b Sigma_b that
+   section 4.3 uses): per row cluster, the SVD of X_tau = [U_b Sigma_b]_{sigma in row(tau)}
+   gives U_tau (leading left singular vectors above the relative tolerance) and
+   U_tau^* U_b Sigma_b = (Sigma V^*)[:l_tau, cols of b].  The coupling matrix is assembled,
+   S_b = (U_tau^* U_b Sigma_b) Sigma_b^{-1} (V_sigma^* V_b Sigma_b)^*, and stored whole.
+5. Symmetry (Remark 4.4, used in section 6.1): the kernel is symmetric and the rows and
+   columns share one tree, so ACA runs on one block of each mirrored pair and the mirrored
+   block is its transpose exactly.  Then the column agglomeration of a cluster is the
+   complex conjugate of its row agglomeration and V_sigma = conj(U_sigma).  The stored
+   operator still carries both triangles and separate U and V, as a general UH-matrix.
+
+The result is a ``HostOperator`` holding both the H form (for the H-MVP comparator) and
+the UH form, in the flat, cluster-ordered layout declared in ``include/uhm.h``.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import time
+from dataclasses import dataclass, field
+
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+from .inputs import PointCloud
+
+try:  # keep LAPACK single-threaded inside the worker threads
+    from threadpoolctl import threadpool_limits
+except ImportError:  # pragma: no cover
+    threadpool_limits = None
+
+_LIB = None
+
+
+def _native():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(os.path.dirname(__file__), "libuhm_builder.so")
+        if not os.path.exists(path):
+            raise RuntimeError(
+                f"builder library {path} is missing: run __graft_entry__.build() first")
+        lib = ctypes.CDLL(path)
+        P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        lib.uhmb_dense_blocks.argtypes = [P, D, D, I64, P, P, P, P, P, P]
+        lib.uhmb_dense_blocks.restype = ctypes.c_int
+        lib.uhmb_aca_run.argtypes = [P, D, D, I64, P, P, P, P, D, I32, P]
+        lib.uhmb_aca_run.restype = ctypes.c_void_p
+        lib.uhmb_aca_copy.argtypes = [P, I64, P, I64, I64, I64, P, P]
+        lib.uhmb_aca_copy.restype = ctypes.c_int
+        lib.uhmb_aca_free.argtypes = [P]
+        lib.uhmb_aca_free.restype = None
+        lib.uhmb_num_threads.argtypes = []
+        lib.uhmb_num_threads.restype = ctypes.c_int
+        _LIB = lib
+    return _LIB
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+# --------------------------------------------------------------------------- tree
+@dataclass
+class ClusterTree:
+    perm: np.ndarray    # (N,) int64: cluster position -> user index
+    off: np.ndarray     # (nc,) int64
+    size: np.ndarray    # (nc,) int64
+    level: np.ndarray   # (nc,) int32
+    parent: np.ndarray  # (nc,) int32, -1 at the root
+    child: np.ndarray   # (nc, 2) int32, -1 at leaves
+    lo: np.ndarray      # (nc, 3) bounding box
+    hi: np.ndarray
+    depth: int          # D: leaves are at level D
+
+    @property
+    def nclusters(self) -> int:
+        return int(self.off.shape[0])
+
+    def diam(self) -> np.ndarray:
+        return np.linalg.norm(self.hi - self.lo, axis=1)
+
+    def leaves(self) -> np.ndarray:
+        return np.nonzero(self.child[:, 0] < 0)[0]
+
+
+def build_tree(points: np.ndarray, leaf: int) -> ClusterTree:
+    n = points.shape[0]
+    if leaf < 2:
+        raise ValueError("leaf size must be >= 2")
+    depth = max(0, math.ceil(math.log2(n / leaf))) if n > leaf else 0
+    perm = np.arange(n, dtype=np.int64)
+    off, size, level, parent = [0], [n], [0], [-1]
+    child = [[-1, -1]]
+    current = [0]
+    for lev in range(depth):
+        nxt = []
+        for c in current:
+            o, s = off[c], size[c]
+            idx = perm[o:o + s]
+            p = points[idx]
+            ax = int(np.argmax(p.max(0) - p.min(0)))
+            order = np.lexsort((idx, p[:, ax]))
+            perm[o:o + s] = idx[order]
+            m = s // 2
+            kids = []
+            for co, cs in ((o, m), (o + m, s - m)):
+                kids.append(len(off))
+                off.append(co)
+                size.append(cs)
+                level.append(lev + 1)
+                parent.append(c)
+                child.append([-1, -1])
+            child[c] = kids
+            nxt.extend(kids)
+        current = nxt
+    off_a = np.asarray(off, np.int64)
+    size_a = np.asarray(size, np.int64)
+    sorted_pts = points[perm]
+    # bounding boxes from the cluster-ordered points (reduceat over contiguous segments)
+    lo = np.empty((len(off), 3))
+    hi = np.empty((len(off), 3))
+    for c in range(len(off)):
+        seg = sorted_pts[off_a[c]:off_a[c] + size_a[c]]
+        lo[c] = seg.min(0)
+        hi[c] = seg.max(0)
+    return ClusterTree(perm, off_a, size_a, np.asarray(level, np.int32), np.asarray(parent, np.int32),
+                       np.asarray(child, np.int32), lo, hi, depth)
+
+
+def build_block_tree(tree: ClusterTree, eta: float):
+    """Return (adm, den): int32 arrays of (row cluster, column cluster) leaf pairs."""
+    diam = tree.diam()
+    pairs = np.zeros((1, 2), np.int64)
+    adm_parts, den_parts = [], []
+    while pairs.shape[0]:
+        t, s = pairs[:, 0], pairs[:, 1]
+        gap = np.maximum(0.0, np.maximum(tree.lo[t] - tree.hi[s], tree.lo[s] - tree.hi[t]))
+        dist = np.linalg.norm(gap, axis=1)
+        adm = eta * dist > np.minimum(diam[t], diam[s])
+        adm_parts.append(pairs[adm])
+        rest = pairs[~adm]
+        leaf_t = tree.child[rest[:, 0], 0] < 0
+        leaf_s = tree.child[rest[:, 1], 0] < 0
+        stop = leaf_t | leaf_s
+        den_parts.append(rest[stop])
+        rest = rest[~stop]
+        ct = tree.child[rest[:, 0]]
+        cs = tree.child[rest[:, 1]]
+        pairs = np.concatenate([np.stack([ct[:, a], cs[:, b]], 1) for a in (0, 1) for b in (0, 1)], 0) \
+            if rest.shape[0] else np.zeros((0, 2), np.int64)
+    adm = np.concatenate(adm_parts, 0).astype(np.int64)
+    den = np.concatenate(den_parts, 0).astype(np.int64)
+    adm = adm[np.lexsort((adm[:, 1], adm[:, 0]))]
+    den = den[np.lexsort((den[:, 1], den[:, 0]))]
+    return adm, den
+
+
+# --------------------------------------------------------------------------- operator
+@dataclass
+class HostOperator:
+    """Both forms of one operator in the flat, cluster-ordered host layout.
+
+    Complex arrays are complex128 and flat; every per-cluster or per-block matrix is
+    column-major at its element offset.
+    """
+    n: int
+    perm: np.ndarray
+    off: np.ndarray
+    size: np.ndarray
+    level: np.ndarray
+    parent: np.ndarray
+    rank_row: np.ndarray   # int32, l_tau (0 if tau not in L'_I)
+    rank_col: np.ndarray   # int32, l_sigma (0 if sigma not in L'_J)
+    U_off: np.ndarray      # int64, -1 if no basis
+    V_off: np.ndarray
+    U: np.ndarray
+    V: np.ndarray
+    adm_row: np.ndarray    # int32
+    adm_col: np.ndarray
+    S_off: np.ndarray      # int64
+    S: np.ndarray
+    adm_rank: np.ndarray   # int32, k_b of the H form
+    X_off: np.ndarray      # int64
+    Y_off: np.ndarray
+    X: np.ndarray          # H form: A|_b ~ X_b Y_b^*, X_b = U_b Sigma_b, Y_b = V_b
+    Y: np.ndarray
+    den_row: np.ndarray
+    den_col: np.ndarray
+    D_off: np.ndarray
+    D: np.ndarray
+    kappa: float
+    h: float
+    leaf: int
+    eta: float
+    eps_aca: float
+    eps_comp: float
+    depth: int
+    sv_dropped: np.ndarray = field(default=None)   # per cluster: sigma_{l+1}(X_tau) (0 if none)
+    sv_tail: np.ndarray = field(default=None)      # per cluster: sqrt(sum_{i>l} sigma_i^2)
+    timings: dict = field(default_factory=dict)
+
+    @property
+    def nclusters(self) -> int:
+        return int(self.off.shape[0])
+
+    @property
+    def nadm(self) -> int:
+        return int(self.adm_row.shape[0])
+
+    @property
+    def nden(self) -> int:
+        return int(self.den_row.shape[0])
+
+    def stats(self) -> dict:
+        r = self.rank_row[self.rank_row > 0]
+        rows = np.bincount(self.adm_row, minlength=self.nclusters)
+        cols = np.bincount(self.adm_col, minlength=self.nclusters)
+        return {
+            "n": self.n, "depth": self.depth, "nclusters": self.nclusters,
+            "nadm": self.nadm, "nden": self.nden,
+            "c_sp": int(max(rows.max(initial=0), cols.max(initial=0))),
+            "l_max": int(r.max(initial=0)), "l_mean": float(r.mean()) if r.size else 0.0,
+            "k_max": int(self.adm_rank.max(initial=0)),
+            "elems_U": int(self.U.size), "elems_V": int(self.V.size), "elems_S": int(self.S.size),
+            "elems_D": int(self.D.size), "elems_XY": int(self.X.size + self.Y.size),
+            "bytes_uh_c128": 16 * int(self.U.size + self.V.size + self.S.size + self.D.size),
+            "bytes_h_c128": 16 * int(self.X.size + self.Y.size + self.D.size),
+        }
+
+
+def _chunks(items, per_item_bytes, budget=1 << 28, parts=1):
+    """Split items into pieces of bounded memory, and into at least ``parts`` pieces."""
+    step = max(1, int(budget // max(1, per_item_bytes)))
+    step = max(1, min(step, -(-len(items) // max(1, parts))))
+    for a in range(0, len(items), step):
+        yield items[a:a + step]
+
+
+def _workers() -> int:
+    n = os.environ.get("UHM_BUILD_THREADS") or os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1
+    return max(1, min(64, int(n)))
+
+
+def _pmap(fn, items):
+    """Map fn over items on a thread pool, with LAPACK/BLAS pinned to one thread each."""
+    items = list(items)
+    nw = min(_workers(), len(items))
+    if nw <= 1:
+        return [fn(x) for x in items]
+    ctx = threadpool_limits(1) if threadpool_limits is not None else None
+    try:
+        if ctx is not None:
+            ctx.__enter__()
+        with ThreadPoolExecutor(nw) as ex:
+            return list(ex.map(fn, items))
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+
+
+def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca: float = 1e-6,
+                   eps_comp: float = 1e-6, eps_rec: float | None = None, kcap: int = 1024,
+                   verbose: bool = False) -> HostOperator:
+    """Build the H form and the UH form of the point-kernel matrix A_ij = g(x_i, x_j),
+    A_ii = 1/(2h), for one seeded cloud."""
+    lib = _native()
+    if eps_rec is None:
+        eps_rec = eps_aca / 10.0
+    t0 = time.perf_counter()
+    tim = {}
+    tree = build_tree(cloud.points, leaf)
+    pts = np.ascontiguousarray(cloud.points[tree.perm])
+    diag = 1.0 / (2.0 * cloud.h)
+    kappa = cloud.kappa
+    adm, den = build_block_tree(tree, eta)
+    tim["tree"] = time.perf_counter() - t0
+    nc = tree.nclusters
+    off, size = tree.off, tree.size
+
+    # ---- admissible blocks: ACA + recompression on one block of each mirrored pair
+    lower = adm[adm[:, 0] < adm[:, 1]]
+    if np.any(adm[:, 0] == adm[:, 1]):
+        raise RuntimeError("a cluster is admissible with itself")
+    fac_U, fac_V, fac_s = {}, {}, {}   # keyed by (tau, sigma) with tau < sigma
+    t1 = time.perf_counter()
+    levels = tree.level[lower[:, 0]] if lower.shape[0] else np.zeros(0, np.int32)
+    t_aca = t_rec = 0.0
+    for lev in np.unique(levels):
+        blk = lower[levels == lev]
+        nb = blk.shape[0]
+        roff = np.ascontiguousarray(off[blk[:, 0]])
+        rsz = np.ascontiguousarray(size[blk[:, 0]])
+        coff = np.ascontiguousarray(off[blk[:, 1]])
+        csz = np.ascontiguousarray(size[blk[:, 1]])
+        kout = np.zeros(nb, np.int32)
+        ta = time.perf_counter()
+        handle = lib.uhmb_aca_run(_ptr(pts), kappa, diag, nb, _ptr(roff), _ptr(rsz), _ptr(coff), _ptr(csz),
+                                  eps_aca, kcap, _ptr(kout))
+        if not handle:
+            raise MemoryError("ACA batch allocation failed")
+        t_aca += time.perf_counter() - ta
+        tr = time.perf_counter()
+        def recompress(job):
+            part, m, n, kp = job
+            cnt = len(part)
+            X = np.empty((cnt, m, kp), np.complex128)
+            Y = np.empty((cnt, n, kp), np.complex128)
+            idx = np.ascontiguousarray(part, dtype=np.int64)
+            lib.uhmb_aca_copy(handle, cnt, _ptr(idx), int(m), int(n), kp, _ptr(X), _ptr(Y))
+            QX, RX = np.linalg.qr(X)
+            QY, RY = np.linalg.qr(Y)
+            del X, Y
+            W, s, Zh = np.linalg.svd(RX @ np.conj(np.swapaxes(RY, 1, 2)), full_matrices=False)
+            out = []
+            for c, b in enumerate(part):
+                sc = s[c]
+                k = max(1, int(np.count_nonzero(sc > eps_rec * sc[0]))) if sc.size and sc[0] > 0.0 else 1
+                out.append(((int(blk[b, 0]), int(blk[b, 1])), QX[c] @ W[c][:, :k],
+                            QY[c] @ np.conj(Zh[c][:k, :]).T, sc[:k].copy()))
+            return out
+
+        try:
+            jobs = []
+            shapes = np.stack([rsz, csz], 1)
+            for (m, n) in np.unique(shapes, axis=0):
+                sel = np.nonzero((rsz == m) & (csz == n))[0]
+                kp = int(kout[sel].max())
+                for part in _chunks(sel, 16 * (m + n) * kp * 4, parts=4 * _workers()):
+                    jobs.append((part, int(m), int(n), kp))
+            for res in _pmap(recompress, jobs):
+                for key, Ub, Vb, sb in res:
+                    fac_U[key] = Ub
+                    fac_V[key] = Vb
+                    fac_s[key] = sb
+        finally:
+            lib.uhmb_aca_free(handle)
+        t_rec += time.perf_counter() - tr
+        if verbose:
+            print(f"  level {lev}: {nb} ACA blocks, k_max {int(kout.max())}", flush=True)
+    tim["aca"] = t_aca
+    tim["recompress"] = t_rec
+
+    def block_factors(t, s):
+        """(U_b, Sigma_b, V_b) of block t x s, using the mirror for t > s."""
+        if t < s:
+            return fac_U[(t, s)], fac_s[(t, s)], fac_V[(t, s)]
+        return np.conj(fac_V[(s, t)]), fac_s[(s, t)], np.conj(fac_U[(s, t)])
+
+    # ---- uniform compression, one SVD per cluster (row side; column side by symmetry)
+    t2 = time.perf_counter()
+    row_blocks = {}
+    for t, s in adm:
+        row_blocks.setdefault(int(t), []).append(int(s))
+    rank = np.zeros(nc, np.int32)
+    Ubasis = {}
+    Lmat = {}  # (t, s) -> U_t^* U_b Sigma_b   (l_t x k_b)
+    sv_dropped = np.zeros(nc)
+    sv_tail = np.zeros(nc)
+    clusters = np.array(sorted(row_blocks), dtype=np.int64)
+    groups = {}
+    for t in clusters:
+        ks = sum(fac_s[(min(t, s), max(t, s))].size for s in row_blocks[t])
+        groups.setdefault((int(size[t])), []).append((int(t), ks))
+    def compress(part):
+        nt = int(size[part[0][0]])
+        kp = max(k for _, k in part)
+        Xb = np.zeros((len(part), nt, kp), np.complex128)
+        cols = []
+        for c, (t, _) in enumerate(part):
+            j = 0
+            cl = []
+            for s in row_blocks[t]:
+                Ub, sb, _ = block_factors(t, s)
+                kb = sb.size
+                Xb[c, :, j:j + kb] = Ub * sb[None, :]
+                cl.append((s, j, kb))
+                j += kb
+            cols.append(cl)
+        Uh, sh, Vh = np.linalg.svd(Xb, full_matrices=False)
+        del Xb
+        out = []
+        for c, (t, ks) in enumerate(part):
+            sv = sh[c]
+            l = max(1, int(np.count_nonzero(sv > eps_comp * sv[0]))) if sv[0] > 0 else 1
+            l = min(l, ks)
+            SV = sv[:l, None] * Vh[c][:l, :]
+            out.append((t, l, np.ascontiguousarray(Uh[c][:, :l]), sv[l] if l < sv.size else 0.0,
+                        float(np.sqrt(np.sum(sv[l:] ** 2))),
+                        [(s, np.ascontiguousarray(SV[:, j:j + kb])) for s, j, kb in cols[c]]))
+        return out
+
+    jobs = []
+    for nt, members in groups.items():
+        kp_all = max(k for _, k in members)
+        jobs.extend(_chunks(members, 16 * nt * kp_all * 3, parts=2 * _workers()))
+    for res in _pmap(compress, jobs):
+        for t, l, Ut, dropped, tail, Ls in res:
+            rank[t] = l
+            Ubasis[t] = Ut
+            sv_dropped[t] = dropped
+            sv_tail[t] = tail
+            for s, Lb in Ls:
+                Lmat[(t, s)] = Lb
+    tim["compress"] = time.perf_counter() - t2
+
+    # ---- couplings S_b = L_b Sigma_b^{-1} L_{b~}^T, b~ the mirrored block
+    t3 = time.perf_counter()
+    nadm = adm.shape[0]
+    S_off = np.zeros(nadm, np.int64)
+    sizes = rank[adm[:, 0]].astype(np.int64) * rank[adm[:, 1]].astype(np.int64)
+    S_off[1:] = np.cumsum(sizes)[:-1]
+    S = np.empty(int(sizes.sum()), np.complex128)
+    adm_rank = np.zeros(nadm, np.int32)
+    for b in range(nadm):
+        t, s = int(adm[b, 0]), int(adm[b, 1])
+        sb = fac_s[(min(t, s), max(t, s))]
+        Sb = (Lmat[(t, s)] / sb[None, :]) @ Lmat[(s, t)].T
+        S[S_off[b]:S_off[b] + sizes[b]] = Sb.ravel(order="F")
+        adm_rank[b] = sb.size
+    tim["couplings"] = time.perf_counter() - t3
+
+    # ---- bases (V = conj(U) by symmetry), H factors
+    U_off = np.full(nc, -1, np.int64)
+    usz = size * rank
+    has = rank > 0
+    U_off[has] = np.concatenate([[0], np.cumsum(usz[has])[:-1]]) if has.any() else []
+    U = np.empty(int(usz.sum()), np.complex128)
+    for t, Ut in Ubasis.items():
+        U[U_off[t]:U_off[t] + usz[t]] = Ut.ravel(order="F")
+    V = np.conj(U)
+
+    xs = size[adm[:, 0]] * adm_rank
+    ys = size[adm[:, 1]] * adm_rank
+    X_off = np.concatenate([[0], np.cumsum(xs)[:-1]]).astype(np.int64)
+    Y_off = np.concatenate([[0], np.cumsum(ys)[:-1]]).astype(np.int64)
+    Xh = np.empty(int(xs.sum()), np.complex128)
+    Yh = np.empty(int(ys.sum()), np.complex128)
+    for b in range(nadm):
+        t, s = int(adm[b, 0]), int(adm[b, 1])
+        Ub, sb, Vb = block_factors(t, s)
+        Xh[X_off[b]:X_off[b] + xs[b]] = (Ub * sb[None, :]).ravel(order="F")
+        Yh[Y_off[b]:Y_off[b] + ys[b]] = Vb.ravel(order="F")
+    del fac_U, fac_V, Lmat
+
+    # ---- dense near field
+    t4 = time.perf_counter()
+    nden = den.shape[0]
+    dsz = size[den[:, 0]] * size[den[:, 1]]
+    D_off = np.concatenate([[0], np.cumsum(dsz)[:-1]]).astype(np.int64) if nden else np.zeros(0, np.int64)
+    D = np.empty(int(dsz.sum()), np.complex128)
+    if nden:
+        d_ro = np.ascontiguousarray(off[den[:, 0]])
+        d_rs = np.ascontiguousarray(size[den[:, 0]])
+        d_co = np.ascontiguousarray(off[den[:, 1]])
+        d_cs = np.ascontiguousarray(size[den[:, 1]])
+        lib.uhmb_dense_blocks(_ptr(pts), kappa, diag, nden, _ptr(d_ro), _ptr(d_rs), _ptr(d_co), _ptr(d_cs),
+                              _ptr(D_off), _ptr(D))
+    tim["dense"] = time.perf_counter() - t4
+    tim["total"] = time.perf_counter() - t0
+
+    return HostOperator(
+        n=cloud.n, perm=tree.perm, off=tree.off, size=tree.size, level=tree.level, parent=tree.parent,
+        rank_row=rank.copy(), rank_col=rank.copy(), U_off=U_off, V_off=U_off.copy(), U=U, V=V,
+        adm_row=adm[:, 0].astype(np.int32), adm_col=adm[:, 1].astype(np.int32), S_off=S_off, S=S,
+        adm_rank=adm_rank, X_off=X_off, Y_off=Y_off, X=Xh, Y=Yh,
+        den_row=den[:, 0].astype(np.int32), den_col=den[:, 1].astype(np.int32), D_off=D_off, D=D,
+        kappa=kappa, h=cloud.h, leaf=leaf, eta=eta, eps_aca=eps_aca, eps_comp=eps_comp, depth=tree.depth,
+        sv_dropped=sv_dropped, sv_tail=sv_tail, timings=tim)
+
+
+def save_operator(op: HostOperator, path: str) -> None:
+    arrays = {k: v for k, v in op.__dict__.items() if isinstance(v, np.ndarray)}
+    scalars = {k: v for k, v in op.__dict__.items() if isinstance(v, (int, float)) and not isinstance(v, bool)}
+    np.savez(path, **arrays, **{"_scalar_" + k: np.asarray(v) for k, v in scalars.items()})
+
+
+def load_operator(path: str) -> HostOperator:
+    z = np.load(path, allow_pickle=False)
+    kw = {}
+    for k in z.files:
+        if k.startswith("_scalar_"):
+            v = z[k]
+            kw[k[8:]] = v.item()
+        else:
+            kw[k] = z[k]
+    for k in ("n", "leaf", "depth"):
+        kw[k] = int(kw[k])
+    return HostOperator(**kw)
