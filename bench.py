@@ -1,0 +1,201 @@
+"""Benchmark: FP64 uniform H-matrix MVP against the plain H-matrix MVP of the same operator.
+
+Default workload: N = 262144 quasi-uniform points on the unit sphere (seeded jittered
+Fibonacci lattice), kernel exp(i kappa r)/(4 pi r) with kappa*h = 0.6, diagonal 1/(2h),
+geometric bisection tree with leaf 64, weak admissibility eta = 1, ACA and compression
+tolerance 1e-6, one complex128 right-hand side x ~ CN(0,1).
+
+One step = one product y = A x through the C-ABI (forward, coupling, backward and near
+field kernels), with the operator and x already resident in HBM.  Also reported: the
+H-matrix product of the same operator on the same GPU, per-kernel times, a roofline line
+for the dominant kernel, sampled parity against the CPU oracle, and the CPU oracle
+(Algorithm 6 in C/OpenMP) timed on this host's cores on a bounded sample.
+
+Prints exactly one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "uniform-H MVP GB/s & MVPs/s vs plain H-MVP at N=256K; p99 GMRES solve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(info: dict, n: int, nrhs: int = 1) -> dict:
+    """Bytes each kernel must move per product: stored operator elements once, vectors once."""
+    e = info["elem_bytes"]
+    f = 16 if info["storage"] == 0 else 8
+    rs = info["rank_space"]
+    out = {
+        "k_forward": e * info["elems_forward"] + f * nrhs * (n + rs),
+        "k_backward": e * (info["elems_backward"] + info["elems_near"]) + f * nrhs * (2 * n),
+    }
+    if info["kind"] == 0:
+        out["k_coupling"] = e * info["elems_coupling"] + f * nrhs * 2 * rs
+        out["k_backward"] += f * nrhs * rs
+    else:
+        out["k_backward"] += f * nrhs * rs
+    out["total"] = (e * (info["elems_forward"] + info["elems_coupling"] + info["elems_backward"] + info["elems_near"])
+                    + f * nrhs * (2 * n + 2 * rs + (2 * rs if info["kind"] == 0 else 0)))
+    return out
+
+
+def time_products(torch, dop, x, y, steps, warmup, stream):
+    for _ in range(warmup):
+        dop.matvec(x, y, stream=stream)
+    torch.cuda.synchronize()
+    dop.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dop.matvec(x, y, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = dop.kernel_times()
+    dop.set_timing(False)
+    return (t1 - t0) / steps, {k: (v[0] / max(1, v[1]), v[1]) for k, v in kt.items() if v[1] > 0}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=262144)
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-h", action="store_true")
+    ap.add_argument("--parity-leaves", type=int, default=6)
+    ap.add_argument("--traffic", type=str, default="", help="JSON file with counter-derived HBM bytes per launch")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a design "
+              "described in DESIGN.md and is not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2405_15573_amd import binding, builder, inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    binding.load_library()
+
+    t0 = time.perf_counter()
+    cloud = inputs.make_cloud("sphere", args.n, seed=args.seed)
+    log(f"building operator N={cloud.n} kappa={cloud.kappa:.3f} h={cloud.h:.5f}")
+    op = builder.build_operator(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, verbose=True)
+    st = op.stats()
+    log(f"built in {time.perf_counter() - t0:.1f} s: {json.dumps(op.timings)}")
+    log(json.dumps(st))
+
+    stream = torch.cuda.Stream()
+    t1 = time.perf_counter()
+    duh = binding.upload(op, stream=stream)
+    log(f"UH upload {time.perf_counter() - t1:.1f} s")
+    info = duh.info()
+    x_np = inputs.make_rhs(cloud.n, 1, seed=args.seed)[:, 0]
+    x = torch.from_numpy(x_np).to("cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+
+    t_uh, k_uh = time_products(torch, duh, x, y, args.steps, args.warmup, stream)
+    y_uh = y.cpu().numpy()
+    ab = algorithmic_bytes(info, cloud.n)
+    log(f"UH MVP {t_uh * 1e3:.3f} ms; kernels " + json.dumps({k: round(v[0], 4) for k, v in k_uh.items()}))
+
+    # sampled parity at full size against the oracle (block-wise definition, restricted rows)
+    from oracle import uniform
+    leaves = np.nonzero(np.bincount(op.parent[op.parent >= 0], minlength=op.nclusters) == 0)[0]
+    rng = np.random.default_rng(12345)
+    pick = rng.choice(leaves, size=min(args.parity_leaves, leaves.size), replace=False)
+    pos = np.concatenate([np.arange(op.off[c], op.off[c] + op.size[c]) for c in pick])
+    tp = time.perf_counter()
+    ref, users = uniform.uh_mvp_rows(vars(op), x_np, pos)
+    parity = float(np.linalg.norm(y_uh[users] - ref[:, 0]) / np.linalg.norm(ref[:, 0]))
+    log(f"sampled parity ({pos.size} rows) {parity:.3e} in {time.perf_counter() - tp:.1f} s")
+
+    res_h = None
+    if not args.no_h:
+        t2 = time.perf_counter()
+        dh = binding.upload_h(op, stream=stream)
+        log(f"H upload {time.perf_counter() - t2:.1f} s")
+        t_h, k_h = time_products(torch, dh, x, y, args.steps, args.warmup, stream)
+        hinfo = dh.info()
+        abh = algorithmic_bytes(hinfo, cloud.n)
+        res_h = {"ms_per_mvp": t_h * 1e3, "mvps_per_s": 1.0 / t_h, "gbs": abh["total"] / t_h / 1e9,
+                 "bytes": abh["total"], "kernels_ms": {k: v[0] for k, v in k_h.items()}}
+        log(f"H MVP {t_h * 1e3:.3f} ms")
+        dh.free()
+
+    cpu = None
+    if not args.no_cpu:
+        ncores = uniform.max_threads()
+        tc = time.perf_counter()
+        uniform.alg6(vars(op), x_np)  # warm-up (first touch of the operator pages)
+        first = time.perf_counter() - tc
+        reps = max(1, min(10, int(args.cpu_seconds / max(first, 1e-3))))
+        tc = time.perf_counter()
+        for _ in range(reps):
+            uniform.alg6(vars(op), x_np)
+        tcpu = (time.perf_counter() - tc) / reps
+        cpu = {"value": 1.0 / tcpu, "unit": "MVPs/s", "cores": ncores, "kind": "oracle",
+               "sample": f"{reps} full products of the same N={cloud.n} operator with the C Algorithm 6 "
+                         f"oracle (OpenMP, {ncores} threads) after one warm-up",
+               "gbs": ab["total"] / tcpu / 1e9, "ms_per_mvp": tcpu * 1e3}
+        log(f"CPU oracle {tcpu * 1e3:.1f} ms per MVP on {ncores} threads")
+
+    # dominant kernel and its roofline
+    dom = max((k for k in k_uh if k in ab), key=lambda k: k_uh[k][0])
+    achieved = ab[dom] / (k_uh[dom][0] * 1e-3) / 1e9
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        tr = json.load(open(args.traffic))
+        traffic = tr.get(dom)
+    line = {
+        "metric": METRIC,
+        "value": 1.0 / t_uh,
+        "unit": "MVPs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_uh * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"uniform-H MVP, sphere N={cloud.n}, kappa*h=0.6, leaf {args.leaf}, eta 1, "
+                               f"ACA/compression tol 1e-6, 1 RHS complex128",
+                   "n": cloud.n, "nrhs": 1, "storage": "complex128", "leaf": args.leaf, "eta": 1.0, "eps": 1e-6,
+                   "seed": args.seed},
+        "gbs": ab["total"] / t_uh / 1e9,
+        "bytes_per_mvp": ab["total"],
+        "kernels_ms": {k: v[0] for k, v in k_uh.items()},
+        "h_mvp": res_h,
+        "uh_speedup_over_h": (res_h["ms_per_mvp"] / (t_uh * 1e3)) if res_h else None,
+        "parity_sampled_rel_err": parity,
+        "operator": {k: st[k] for k in ("nadm", "nden", "c_sp", "l_max", "k_max", "bytes_uh_c128", "bytes_h_c128")},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * uhm.h -- uniform H-matrix (UH-matrix) matrix-vector products on AMD Instinct MI355X.
+ *
+ * A UH-matrix (Definition 2.4 of Bruyninckx, Huybrechs, Meerbergen, "Uniform H-matrix
+ * compression with applications to boundary integral equations") stores, for a block
+ * partition P = P+ u P- of I x J:
+ *   - one orthonormal basis U_tau (|tau| x l_tau) per row cluster tau of an admissible block,
+ *   - one orthonormal basis V_sigma (|sigma| x l_sigma) per column cluster,
+ *   - one coupling matrix S_b (l_tau x l_sigma) per admissible block b = tau x sigma, so that
+ *     A|_b = U_tau S_b V_sigma^*,
+ *   - the inadmissible blocks A|_b, b in P-, dense.
+ * The product w = A v (section 4.4, Algorithm 6) runs in four stages on the GPU:
+ *   forward   u_sigma = V_sigma^* v|_sigma for every column cluster,
+ *   coupling  u_tau   = sum_{sigma in row(tau)} S_b u_sigma for every row cluster,
+ *   backward  w|_tau += U_tau u_tau,
+ *   near field w|_tau += A|_b v|_sigma for b in P-.
+ * The H-matrix form (Definition 2.3: A|_b = X_b Y_b^* per admissible block, Algorithm 5)
+ * is supported as well, as a comparator for the same operator.
+ *
+ * Conventions shared by every entry point
+ *   - Complex numbers are interleaved (re, im); complex128 = two doubles.
+ *   - Every stored matrix is column-major at its element offset (offsets count complex
+ *     elements, not bytes).
+ *   - Square operators only: rows and columns share one cluster tree over n points.
+ *   - "Cluster order": clusters own contiguous ranges [off, off+size) of positions
+ *     0..n-1; perm[position] is the user index of that position.  The children of a
+ *     cluster partition it.  Vectors passed to the library are in user order.
+ *   - Errors are returned as negative ints (no exceptions cross the ABI); uhm_strerror
+ *     gives text, uhm_last_error the detail of the last failure in the calling thread.
+ *   - Host arrays given to an upload are BORROWED for the duration of the call only.
+ *   - An uploaded operator is read-only.  Calls on one operator share its workspace, so
+ *     they must be ordered on one stream (or otherwise serialized by the caller).
+ */
+#ifndef UHM_H
+#define UHM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  UHM_OK = 0,
+  UHM_EINVAL = -1,   /* null pointer, bad size, inconsistent operator, dtype mismatch */
+  UHM_ENOMEM = -2,   /* a device or host allocation failed; the call had no side effects */
+  UHM_EHIP = -3,     /* a HIP runtime call failed; see uhm_last_error */
+  UHM_ENOCONV = -4,  /* an iterative solve stopped at its iteration limit */
+  UHM_ENOTSUP = -5   /* valid request that this build does not support */
+};
+
+/* Storage precision of the uploaded operator. */
+typedef enum {
+  UHM_C128 = 0,      /* complex128 storage and arithmetic; vectors complex128 */
+  UHM_C64 = 1,       /* complex64 storage, FP32 accumulation; vectors complex64 */
+  UHM_BF16PAIR = 2   /* (re, im) bfloat16 pairs, FP32 accumulation; vectors complex64 */
+} uhm_storage;
+
+typedef struct uhm_op uhm_op; /* opaque; owned by the library until uhm_free */
+
+/*
+ * Host image of a UH-matrix (Definition 2.4), produced by the host builder.
+ * Cluster tree: nclusters clusters with off/size/parent (parent = -1 at the root).
+ * Bases: cluster c has a row basis iff rank_row[c] > 0 (c in L'_I of eq.
+ * clusters_in_partition), stored at U + 2*U_off[c] as size[c] x rank_row[c]; likewise V.
+ * Admissible block b: rows adm_row[b], columns adm_col[b], S_b at S + 2*S_off[b] as
+ * rank_row[adm_row[b]] x rank_col[adm_col[b]].
+ * Dense block b: den_row[b] x den_col[b] at D + 2*D_off[b] as size x size.
+ * *_len are the lengths of the flat arrays in complex elements (used for bounds checks).
+ */
+typedef struct {
+  int64_t n;
+  const int64_t* perm;       /* [n] cluster position -> user index, a permutation */
+  int32_t nclusters;
+  const int64_t* off;        /* [nclusters] */
+  const int64_t* size;       /* [nclusters] */
+  const int32_t* parent;     /* [nclusters] */
+  const int32_t* rank_row;   /* [nclusters] l_tau, 0 if none */
+  const int32_t* rank_col;   /* [nclusters] l_sigma, 0 if none */
+  const int64_t* U_off;      /* [nclusters] */
+  const int64_t* V_off;      /* [nclusters] */
+  const double* U; int64_t U_len;
+  const double* V; int64_t V_len;
+  int64_t nadm;
+  const int32_t* adm_row;    /* [nadm] */
+  const int32_t* adm_col;    /* [nadm] */
+  const int64_t* S_off;      /* [nadm] */
+  const double* S; int64_t S_len;
+  int64_t nden;
+  const int32_t* den_row;    /* [nden] */
+  const int32_t* den_col;    /* [nden] */
+  const int64_t* D_off;      /* [nden] */
+  const double* D; int64_t D_len;
+} uhm_host_operator;
+
+/*
+ * Host image of the H-matrix of the same partition (Definition 2.3): admissible block b
+ * stores X_b (size[adm_row[b]] x adm_rank[b]) at X + 2*X_off[b] and Y_b
+ * (size[adm_col[b]] x adm_rank[b]) at Y + 2*Y_off[b], A|_b = X_b Y_b^*.
+ */
+typedef struct {
+  int64_t n;
+  const int64_t* perm;
+  int32_t nclusters;
+  const int64_t* off;
+  const int64_t* size;
+  const int32_t* parent;
+  int64_t nadm;
+  const int32_t* adm_row;
+  const int32_t* adm_col;
+  const int32_t* adm_rank;
+  const int64_t* X_off;
+  const int64_t* Y_off;
+  const double* X; int64_t X_len;
+  const double* Y; int64_t Y_len;
+  int64_t nden;
+  const int32_t* den_row;
+  const int32_t* den_col;
+  const int64_t* D_off;
+  const double* D; int64_t D_len;
+} uhm_host_hmatrix;
+
+/* Sizes and algorithmic traffic of an uploaded operator. */
+typedef struct {
+  int64_t n;
+  int32_t kind;              /* 0 = UH-matrix, 1 = H-matrix */
+  int32_t storage;           /* uhm_storage */
+  int32_t nleaves;
+  int32_t elem_bytes;        /* bytes per stored complex element */
+  int64_t nadm, nden;
+  int64_t elems_forward;     /* sum n_sigma l_sigma (UH) or sum_b n_sigma k_b (H) */
+  int64_t elems_coupling;    /* sum_b l_tau l_sigma (UH), 0 (H) */
+  int64_t elems_backward;    /* sum n_tau l_tau (UH) or sum_b n_tau k_b (H) */
+  int64_t elems_near;        /* sum_b n_tau n_sigma over P- */
+  int64_t rank_space;        /* sum l_sigma (UH) or sum k_b (H): length of the rank-space vectors */
+  int64_t device_bytes;      /* device memory held by the operator, workspace excluded */
+} uhm_op_info;
+
+/*
+ * Upload a UH-matrix (Definition 2.4) to the current HIP device, re-laid out for the
+ * product (per-leaf panels of the bases, row-chunked couplings).  The host arrays are
+ * validated (tree, offsets, bounds) and only read during the call; the copies are
+ * enqueued on `hip_stream` (a hipStream_t, or NULL for the default stream) and complete
+ * before the call returns.  *out receives an operator to free with uhm_free.
+ * Errors: UHM_EINVAL (null pointer, inconsistent operator), UHM_ENOMEM, UHM_EHIP.
+ */
+int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream, uhm_op** out);
+
+/*
+ * Upload the H-matrix form (Definition 2.3) of an operator, for the H-matrix product of
+ * Algorithm 5 (section 4.4).  Same semantics and errors as uhm_upload.
+ */
+int uhm_upload_h(const uhm_host_hmatrix* h, uhm_storage storage, void* hip_stream, uhm_op** out);
+
+/*
+ * Y = A X  (w = A v of Algorithms 5 and 6, section 4.4; Y is overwritten).
+ * X: device pointer, n x nrhs column-major, leading dimension ldx >= n, user order.
+ * Y: device pointer, n x nrhs column-major, leading dimension ldy >= n; must not overlap X.
+ * Element type: complex128 for UHM_C128 operators, complex64 otherwise.
+ * Asynchronous on `hip_stream`.  nrhs == 0 is a no-op.  Errors: UHM_EINVAL (null
+ * pointer, nrhs < 0, ld < n), UHM_ENOMEM (workspace growth failed), UHM_EHIP.
+ */
+int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs,
+               void* hip_stream);
+
+/* Fill *info for an uploaded operator.  Errors: UHM_EINVAL. */
+int uhm_op_info_get(const uhm_op* op, uhm_op_info* info);
+
+/*
+ * Kernel timing: while enabled, uhm_matvec records HIP events around each of its kernel
+ * launches (on the stream of the call) and accumulates per-kernel milliseconds.
+ * uhm_kernel_times writes up to `cap` entries (name pointer, total ms, launch count) and
+ * returns the number of kernels; names stay valid until uhm_free.  Reading the times
+ * synchronizes with the recorded events.  Enabling resets the totals.
+ */
+int uhm_set_timing(uhm_op* op, int enabled);
+int uhm_kernel_times(uhm_op* op, const char** names, double* total_ms, int64_t* launches, int32_t cap);
+
+/* Release every device allocation of the operator.  NULL is a no-op. */
+void uhm_free(uhm_op* op);
+
+const char* uhm_strerror(int code);
+const char* uhm_last_error(void);
+int uhm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UHM_H */

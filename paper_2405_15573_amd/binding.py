@@ -1,0 +1,261 @@
+"""Python binding of libuhm.so (include/uhm.h): argument marshalling only.
+
+Every step of the product runs in the HIP library.  PyTorch is used for device memory
+(the vectors are torch tensors on a HIP device) and for streams.  If libuhm.so is
+missing this module raises on first use: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libuhm.so")
+
+UHM_OK, UHM_EINVAL, UHM_ENOMEM, UHM_EHIP, UHM_ENOCONV, UHM_ENOTSUP = 0, -1, -2, -3, -4, -5
+STORAGE = {"c128": 0, "c64": 1, "bf16pair": 2}
+
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+I32 = ctypes.c_int32
+
+
+class HostOperator(ctypes.Structure):
+    _fields_ = [("n", I64), ("perm", P), ("nclusters", I32), ("off", P), ("size", P), ("parent", P),
+                ("rank_row", P), ("rank_col", P), ("U_off", P), ("V_off", P),
+                ("U", P), ("U_len", I64), ("V", P), ("V_len", I64),
+                ("nadm", I64), ("adm_row", P), ("adm_col", P), ("S_off", P), ("S", P), ("S_len", I64),
+                ("nden", I64), ("den_row", P), ("den_col", P), ("D_off", P), ("D", P), ("D_len", I64)]
+
+
+class HostHMatrix(ctypes.Structure):
+    _fields_ = [("n", I64), ("perm", P), ("nclusters", I32), ("off", P), ("size", P), ("parent", P),
+                ("nadm", I64), ("adm_row", P), ("adm_col", P), ("adm_rank", P), ("X_off", P), ("Y_off", P),
+                ("X", P), ("X_len", I64), ("Y", P), ("Y_len", I64),
+                ("nden", I64), ("den_row", P), ("den_col", P), ("D_off", P), ("D", P), ("D_len", I64)]
+
+
+class OpInfo(ctypes.Structure):
+    _fields_ = [("n", I64), ("kind", I32), ("storage", I32), ("nleaves", I32), ("elem_bytes", I32),
+                ("nadm", I64), ("nden", I64), ("elems_forward", I64), ("elems_coupling", I64),
+                ("elems_backward", I64), ("elems_near", I64), ("rank_space", I64), ("device_bytes", I64)]
+
+
+EXPORTS = ("uhm_upload", "uhm_upload_h", "uhm_matvec", "uhm_op_info_get", "uhm_set_timing", "uhm_kernel_times",
+           "uhm_free", "uhm_strerror", "uhm_last_error", "uhm_version")
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libuhm.so and declare its signatures.  Raises if the library is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    lib.uhm_upload.argtypes = [ctypes.POINTER(HostOperator), I32, P, ctypes.POINTER(P)]
+    lib.uhm_upload.restype = ctypes.c_int
+    lib.uhm_upload_h.argtypes = [ctypes.POINTER(HostHMatrix), I32, P, ctypes.POINTER(P)]
+    lib.uhm_upload_h.restype = ctypes.c_int
+    lib.uhm_matvec.argtypes = [P, P, I64, P, I64, I32, P]
+    lib.uhm_matvec.restype = ctypes.c_int
+    lib.uhm_op_info_get.argtypes = [P, ctypes.POINTER(OpInfo)]
+    lib.uhm_op_info_get.restype = ctypes.c_int
+    lib.uhm_set_timing.argtypes = [P, ctypes.c_int]
+    lib.uhm_set_timing.restype = ctypes.c_int
+    lib.uhm_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(I64), I32]
+    lib.uhm_kernel_times.restype = ctypes.c_int
+    lib.uhm_free.argtypes = [P]
+    lib.uhm_free.restype = None
+    lib.uhm_strerror.argtypes = [ctypes.c_int]
+    lib.uhm_strerror.restype = ctypes.c_char_p
+    lib.uhm_last_error.argtypes = []
+    lib.uhm_last_error.restype = ctypes.c_char_p
+    lib.uhm_version.restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+class UhmError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        lib = load_library()
+        self.code = code
+        super().__init__(f"{where}: {lib.uhm_strerror(code).decode()} ({code}): {lib.uhm_last_error().decode()}")
+
+
+def _check(rc: int, where: str):
+    if rc != UHM_OK:
+        raise UhmError(rc, where)
+
+
+def _arr(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, ctypes.c_void_p(a.ctypes.data) if a.size else ctypes.c_void_p(0)
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream), stream
+
+
+class DeviceOperator:
+    """An operator uploaded to the current HIP device (UH form or H form)."""
+
+    def __init__(self, handle, kind: str, storage: str, n: int):
+        self._h = handle
+        self.kind = kind
+        self.storage = storage
+        self.n = n
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        inf = OpInfo()
+        _check(load_library().uhm_op_info_get(self._h, ctypes.byref(inf)), "uhm_op_info_get")
+        return {name: getattr(inf, name) for name, _ in OpInfo._fields_}
+
+    def matvec(self, x, y=None, stream=None):
+        """y = A x for a torch tensor x (n,) or (n, r) on the device; returns y."""
+        import torch
+        want = torch.complex128 if self.storage == "c128" else torch.complex64
+        if x.dtype != want or not x.is_cuda:
+            raise ValueError(f"x must be a {want} device tensor")
+        vec = x.dim() == 1
+        x2 = x.reshape(self.n, 1) if vec else x
+        if x2.shape[0] != self.n:
+            raise ValueError("x has the wrong number of rows")
+        # column-major view: stride (1, ld)
+        if x2.stride(0) != 1:
+            x2 = x2.t().contiguous().t()
+        nrhs = x2.shape[1]
+        if y is None:
+            y2 = torch.empty((nrhs, self.n), dtype=want, device=x.device).t()
+        else:
+            y2 = y.reshape(self.n, 1) if y.dim() == 1 else y
+            if y2.stride(0) != 1 or y2.dtype != want or tuple(y2.shape) != (self.n, nrhs):
+                raise ValueError("y must be a column-major (n, nrhs) tensor of the operator's dtype")
+        ldx = x2.stride(1) if nrhs > 1 else self.n
+        ldy = y2.stride(1) if nrhs > 1 else self.n
+        sh, _ = _stream_handle(stream)
+        rc = load_library().uhm_matvec(self._h, ctypes.c_void_p(x2.data_ptr()), ldx, ctypes.c_void_p(y2.data_ptr()),
+                                       ldy, nrhs, sh)
+        _check(rc, "uhm_matvec")
+        if y is not None:
+            return y
+        return y2.reshape(self.n) if vec else y2
+
+    def set_timing(self, enabled: bool):
+        _check(load_library().uhm_set_timing(self._h, int(bool(enabled))), "uhm_set_timing")
+
+    def kernel_times(self) -> dict:
+        cap = 16
+        names = (ctypes.c_char_p * cap)()
+        ms = (ctypes.c_double * cap)()
+        cnt = (I64 * cap)()
+        k = load_library().uhm_kernel_times(self._h, names, ms, cnt, cap)
+        if k < 0:
+            _check(k, "uhm_kernel_times")
+        return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(min(k, cap))}
+
+    def free(self):
+        if self._h:
+            load_library().uhm_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def upload(op, storage: str = "c128", stream=None) -> DeviceOperator:
+    """Upload the UH form of a host operator (builder.HostOperator or a mapping with the
+    same keys)."""
+    g = (lambda k: op[k]) if isinstance(op, dict) else (lambda k: getattr(op, k))
+    keep = {}
+
+    def a(name, dtype):
+        arr, p = _arr(g(name), dtype)
+        keep[name] = arr
+        return p
+
+    h = HostOperator()
+    h.n = int(g("n"))
+    h.perm = a("perm", np.int64)
+    h.nclusters = int(np.asarray(g("off")).size)
+    h.off = a("off", np.int64)
+    h.size = a("size", np.int64)
+    h.parent = a("parent", np.int32)
+    h.rank_row = a("rank_row", np.int32)
+    h.rank_col = a("rank_col", np.int32)
+    h.U_off = a("U_off", np.int64)
+    h.V_off = a("V_off", np.int64)
+    h.U = a("U", np.complex128)
+    h.U_len = keep["U"].size
+    h.V = a("V", np.complex128)
+    h.V_len = keep["V"].size
+    h.nadm = int(np.asarray(g("adm_row")).size)
+    h.adm_row = a("adm_row", np.int32)
+    h.adm_col = a("adm_col", np.int32)
+    h.S_off = a("S_off", np.int64)
+    h.S = a("S", np.complex128)
+    h.S_len = keep["S"].size
+    h.nden = int(np.asarray(g("den_row")).size)
+    h.den_row = a("den_row", np.int32)
+    h.den_col = a("den_col", np.int32)
+    h.D_off = a("D_off", np.int64)
+    h.D = a("D", np.complex128)
+    h.D_len = keep["D"].size
+    out = P()
+    sh, _ = _stream_handle(stream)
+    _check(load_library().uhm_upload(ctypes.byref(h), STORAGE[storage], sh, ctypes.byref(out)), "uhm_upload")
+    return DeviceOperator(out, "uh", storage, h.n)
+
+
+def upload_h(op, storage: str = "c128", stream=None) -> DeviceOperator:
+    """Upload the H form (X_b, Y_b and the dense blocks) of a host operator."""
+    g = (lambda k: op[k]) if isinstance(op, dict) else (lambda k: getattr(op, k))
+    keep = {}
+
+    def a(name, dtype):
+        arr, p = _arr(g(name), dtype)
+        keep[name] = arr
+        return p
+
+    h = HostHMatrix()
+    h.n = int(g("n"))
+    h.perm = a("perm", np.int64)
+    h.nclusters = int(np.asarray(g("off")).size)
+    h.off = a("off", np.int64)
+    h.size = a("size", np.int64)
+    h.parent = a("parent", np.int32)
+    h.nadm = int(np.asarray(g("adm_row")).size)
+    h.adm_row = a("adm_row", np.int32)
+    h.adm_col = a("adm_col", np.int32)
+    h.adm_rank = a("adm_rank", np.int32)
+    h.X_off = a("X_off", np.int64)
+    h.Y_off = a("Y_off", np.int64)
+    h.X = a("X", np.complex128)
+    h.X_len = keep["X"].size
+    h.Y = a("Y", np.complex128)
+    h.Y_len = keep["Y"].size
+    h.nden = int(np.asarray(g("den_row")).size)
+    h.den_row = a("den_row", np.int32)
+    h.den_col = a("den_col", np.int32)
+    h.D_off = a("D_off", np.int64)
+    h.D = a("D", np.complex128)
+    h.D_len = keep["D"].size
+    out = P()
+    sh, _ = _stream_handle(stream)
+    _check(load_library().uhm_upload_h(ctypes.byref(h), STORAGE[storage], sh, ctypes.byref(out)), "uhm_upload_h")
+    return DeviceOperator(out, "h", storage, h.n)

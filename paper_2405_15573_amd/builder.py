@@ -449,8 +449,8 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
 
     xs = size[adm[:, 0]] * adm_rank
     ys = size[adm[:, 1]] * adm_rank
-    X_off = np.concatenate([[0], np.cumsum(xs)[:-1]]).astype(np.int64)
-    Y_off = np.concatenate([[0], np.cumsum(ys)[:-1]]).astype(np.int64)
+    X_off = np.concatenate([[0], np.cumsum(xs)[:-1]]).astype(np.int64)[:nadm]
+    Y_off = np.concatenate([[0], np.cumsum(ys)[:-1]]).astype(np.int64)[:nadm]
     Xh = np.empty(int(xs.sum()), np.complex128)
     Yh = np.empty(int(ys.sum()), np.complex128)
     for b in range(nadm):

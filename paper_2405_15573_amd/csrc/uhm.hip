@@ -1,0 +1,1248 @@
+// Uniform H-matrix (and H-matrix) matrix-vector products for gfx950 (MI355X).
+//
+// Device layout (built by uhm_upload from the host image of include/uhm.h):
+//
+//  Forward panel F_lambda, one per leaf lambda: the rows of lambda of every basis V_sigma
+//    of an ancestor sigma (root first), side by side: F_lambda = [V_s1|lambda, V_s2|lambda, ...]
+//    (n_lambda x C_lambda).  It is stored tile-major: 64-column tiles, each tile row-major,
+//    so one wavefront streams one contiguous tile with one lane per column and needs no
+//    cross-lane reduction: lane c accumulates conj(F[i,c]) x_i over the leaf rows i.
+//    The per-leaf partial sums are added over the leaves of each cluster in a fixed order
+//    (deterministic), giving u_sigma = V_sigma^* v|_sigma (Algorithm 6, first loop).
+//  Couplings: the blocks of row cluster tau, [S_b1 S_b2 ...] (l_tau x K_tau), are stored in
+//    row chunks of at most 64 rows, each chunk column-major and contiguous.  A wavefront
+//    takes a range of columns of one chunk with one lane per row (no cross-lane reduction),
+//    the partial row sums go to a buffer and are added per chunk in a fixed order, giving
+//    u_tau = sum_{sigma in row(tau)} S_b u_sigma (Algorithm 6, second loop).
+//  Backward panel B_lambda, one per leaf: [U_t1|lambda, U_t2|lambda, ..., A|_b1, A|_b2, ...]
+//    (n_lambda x K_lambda, column-major): the rows of lambda of every ancestor basis U_tau,
+//    then the dense blocks of lambda's rows.  With z_lambda = [u_t1; u_t2; ...; v|_s1; ...]
+//    gathered into LDS, w|_lambda = B_lambda z_lambda: one lane per row (leaf size <= 64 =
+//    wavefront size), each output element written exactly once, no atomics.  The user-order
+//    permutation is folded into the gathers of v and the scatter of w.
+//
+// The H-matrix form uses the same forward / reduce / backward kernels with panels built
+// from Y_b (forward, one segment per block) and X_b (backward).
+//
+// Every index the kernels use comes from arrays this file builds after validating the
+// host image, so device accesses stay inside the allocations by construction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "uhm.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define UHM_HIP(call)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? UHM_ENOMEM : UHM_EHIP,                         \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                       \
+    }                                                                                        \
+  } while (0)
+
+constexpr int kLeafMax = 64;     // leaf size bound: one lane per leaf row
+constexpr int kTile = 64;        // forward-panel tile width (one lane per column)
+constexpr int kRowChunk = 64;    // coupling row chunk (one lane per row)
+constexpr int kCoupCols = 256;   // coupling columns per wavefront tile
+constexpr int kFwdWaves = 4;
+constexpr int kBwdWaves = 4;
+constexpr int kBwdChunk = 512;   // z entries staged in LDS per round
+constexpr int kCoupWaves = 4;
+
+using cd = double2;
+
+// ------------------------------------------------------------------ device kernels
+
+// Map workgroup ids so that each XCD (workgroups are dealt round-robin over 8 XCDs)
+// receives a contiguous range of leaves: neighbouring leaves share ancestors, whose
+// rank-space vectors then stay in that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = bid & 7, k = bid >> 3;
+  return x * q + min(x, r) + k;
+}
+
+__global__ __launch_bounds__(64 * kFwdWaves) void k_forward(
+    const cd* __restrict__ F, const int64_t* __restrict__ fwd_off, const int32_t* __restrict__ fwd_cols,
+    const int32_t* __restrict__ leaf_pos, const int32_t* __restrict__ leaf_n, const int32_t* __restrict__ perm,
+    const cd* __restrict__ x, const int64_t* __restrict__ poff, cd* __restrict__ p, int nleaves) {
+  const int leaf = xcd_remap(blockIdx.x, nleaves);
+  const int C = fwd_cols[leaf];
+  if (C == 0) return;
+  __shared__ cd xs[kLeafMax];
+  const int n = leaf_n[leaf];
+  const int t = threadIdx.x;
+  if (t < n) xs[t] = x[perm[leaf_pos[leaf] + t]];
+  __syncthreads();
+  const int lane = t & 63, w = t >> 6;
+  const cd* base = F + fwd_off[leaf];
+  cd* pl = p + poff[leaf];
+  const int ntile = (C + kTile - 1) / kTile;
+  for (int j = w; j < ntile; j += kFwdWaves) {
+    const int wj = min(kTile, C - kTile * j);
+    if (lane >= wj) continue;
+    const cd* q = base + (int64_t)kTile * j * n + lane;
+    double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+    int i = 0;
+    for (; i + 4 <= n; i += 4) {
+      const cd v0 = q[(i + 0) * wj], v1 = q[(i + 1) * wj], v2 = q[(i + 2) * wj], v3 = q[(i + 3) * wj];
+      const cd x0 = xs[i + 0], x1 = xs[i + 1], x2 = xs[i + 2], x3 = xs[i + 3];
+      re0 = fma(v0.x, x0.x, fma(v0.y, x0.y, re0));
+      im0 = fma(v0.x, x0.y, fma(-v0.y, x0.x, im0));
+      re1 = fma(v1.x, x1.x, fma(v1.y, x1.y, re1));
+      im1 = fma(v1.x, x1.y, fma(-v1.y, x1.x, im1));
+      re0 = fma(v2.x, x2.x, fma(v2.y, x2.y, re0));
+      im0 = fma(v2.x, x2.y, fma(-v2.y, x2.x, im0));
+      re1 = fma(v3.x, x3.x, fma(v3.y, x3.y, re1));
+      im1 = fma(v3.x, x3.y, fma(-v3.y, x3.x, im1));
+    }
+    for (; i < n; ++i) {
+      const cd v = q[i * wj], xv = xs[i];
+      re0 = fma(v.x, xv.x, fma(v.y, xv.y, re0));
+      im0 = fma(v.x, xv.y, fma(-v.y, xv.x, im0));
+    }
+    pl[kTile * j + lane] = make_double2(re0 + re1, im0 + im1);
+  }
+}
+
+// out[e] = sum over the leaves of segment seg(e) of p[leaf][col(seg) + e - start(seg)],
+// leaves taken in cluster order.
+__global__ __launch_bounds__(256) void k_reduce_segments(
+    const cd* __restrict__ p, const int64_t* __restrict__ poff, const int32_t* __restrict__ out_seg,
+    const int64_t* __restrict__ seg_start, const int32_t* __restrict__ seg_leaf0, const int32_t* __restrict__ seg_nleaf,
+    const int32_t* __restrict__ seg_col, int64_t nout, cd* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nout) return;
+  const int s = out_seg[e];
+  const int col = seg_col[s] + (int)(e - seg_start[s]);
+  const int l0 = seg_leaf0[s], nl = seg_nleaf[s];
+  double re = 0.0, im = 0.0;
+  for (int q = 0; q < nl; ++q) {
+    const cd v = p[poff[l0 + q] + col];
+    re += v.x;
+    im += v.y;
+  }
+  out[e] = make_double2(re, im);
+}
+
+struct CoupTile {
+  int64_t s_base;     // element offset of the tile's first column
+  int32_t h;          // rows in the chunk (<= 64)
+  int32_t ncols;      // columns in the tile
+  int32_t first_blk;  // index into the block list of the tile's first column
+  int32_t first_col;  // column within that block
+};
+
+// part[tile][r] = sum_c S_chunk[r, c] * xh[src(c)] over the tile's columns.
+__global__ __launch_bounds__(64 * kCoupWaves) void k_coupling(
+    const cd* __restrict__ S, const CoupTile* __restrict__ tiles, int32_t ntiles, const int2* __restrict__ cblk,
+    const cd* __restrict__ xh, cd* __restrict__ part) {
+  const int tile = blockIdx.x * kCoupWaves + (threadIdx.x >> 6);
+  if (tile >= ntiles) return;
+  const int lane = threadIdx.x & 63;
+  const CoupTile T = tiles[tile];
+  double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+  const int h = T.h;
+  const bool act = lane < h;
+  const cd* col = S + T.s_base + (act ? lane : 0);
+  int b = T.first_blk, j = T.first_col, rem = T.ncols;
+  while (rem > 0) {
+    const int2 bl = cblk[b];
+    const int cnt = min(bl.x - j, rem);
+    const cd* xv = xh + bl.y + j;
+    int q = 0;
+    for (; q + 2 <= cnt; q += 2) {
+      const cd s0 = col[(int64_t)q * h], s1 = col[(int64_t)(q + 1) * h];
+      const cd x0 = xv[q], x1 = xv[q + 1];
+      re0 = fma(s0.x, x0.x, fma(-s0.y, x0.y, re0));
+      im0 = fma(s0.x, x0.y, fma(s0.y, x0.x, im0));
+      re1 = fma(s1.x, x1.x, fma(-s1.y, x1.y, re1));
+      im1 = fma(s1.x, x1.y, fma(s1.y, x1.x, im1));
+    }
+    if (q < cnt) {
+      const cd s0 = col[(int64_t)q * h], x0 = xv[q];
+      re0 = fma(s0.x, x0.x, fma(-s0.y, x0.y, re0));
+      im0 = fma(s0.x, x0.y, fma(s0.y, x0.x, im0));
+    }
+    col += (int64_t)cnt * h;
+    rem -= cnt;
+    ++b;
+    j = 0;
+  }
+  if (act) part[(int64_t)tile * kRowChunk + lane] = make_double2(re0 + re1, im0 + im1);
+}
+
+// yh[e] = sum_{t in tiles of e's chunk} part[t][r(e)], tiles in column order.
+__global__ __launch_bounds__(256) void k_reduce_coupling(
+    const cd* __restrict__ part, const int32_t* __restrict__ yh_grp, const int64_t* __restrict__ grp_start,
+    const int32_t* __restrict__ grp_t0, const int32_t* __restrict__ grp_nt, int64_t nout, cd* __restrict__ yh) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nout) return;
+  const int g = yh_grp[e];
+  const int r = (int)(e - grp_start[g]);
+  const int t0 = grp_t0[g], nt = grp_nt[g];
+  double re = 0.0, im = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    const cd v = part[(int64_t)(t0 + t) * kRowChunk + r];
+    re += v.x;
+    im += v.y;
+  }
+  yh[e] = make_double2(re, im);
+}
+
+// w|_lambda = B_lambda z_lambda with z gathered from the rank-space vector (index >= 0)
+// or from the user-order input (index = -1 - user index).
+__global__ __launch_bounds__(64 * kBwdWaves) void k_backward(
+    const cd* __restrict__ B, const int64_t* __restrict__ bwd_off, const int32_t* __restrict__ bwd_cols,
+    const int64_t* __restrict__ zoff, const int32_t* __restrict__ zmap, const int32_t* __restrict__ leaf_pos,
+    const int32_t* __restrict__ leaf_n, const int32_t* __restrict__ perm, const cd* __restrict__ yh,
+    const cd* __restrict__ x, cd* __restrict__ y, int nleaves) {
+  const int leaf = xcd_remap(blockIdx.x, nleaves);
+  const int K = bwd_cols[leaf], n = leaf_n[leaf];
+  __shared__ cd zs[kBwdChunk];
+  __shared__ cd red[kBwdWaves][kLeafMax];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const cd* Bl = B + bwd_off[leaf];
+  const int32_t* zm = zmap + zoff[leaf];
+  double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+  const bool act = lane < n;
+  for (int c0 = 0; c0 < K; c0 += kBwdChunk) {
+    const int cn = min(kBwdChunk, K - c0);
+    __syncthreads();
+    for (int c = t; c < cn; c += 64 * kBwdWaves) {
+      const int m = zm[c0 + c];
+      zs[c] = m >= 0 ? yh[m] : x[-1 - m];
+    }
+    __syncthreads();
+    const int per = (cn + kBwdWaves - 1) / kBwdWaves;
+    const int a = w * per, e = min(cn, a + per);
+    if (act) {
+      const cd* col = Bl + (int64_t)(c0 + a) * n + lane;
+      int c = a;
+      for (; c + 2 <= e; c += 2, col += 2 * n) {
+        const cd b0 = col[0], b1 = col[n];
+        const cd z0 = zs[c], z1 = zs[c + 1];
+        re0 = fma(b0.x, z0.x, fma(-b0.y, z0.y, re0));
+        im0 = fma(b0.x, z0.y, fma(b0.y, z0.x, im0));
+        re1 = fma(b1.x, z1.x, fma(-b1.y, z1.y, re1));
+        im1 = fma(b1.x, z1.y, fma(b1.y, z1.x, im1));
+      }
+      if (c < e) {
+        const cd b0 = col[0], z0 = zs[c];
+        re0 = fma(b0.x, z0.x, fma(-b0.y, z0.y, re0));
+        im0 = fma(b0.x, z0.y, fma(b0.y, z0.x, im0));
+      }
+    }
+  }
+  red[w][lane] = make_double2(re0 + re1, im0 + im1);
+  __syncthreads();
+  if (w == 0 && act) {
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q < kBwdWaves; ++q) {
+      sr += red[q][lane].x;
+      si += red[q][lane].y;
+    }
+    y[perm[leaf_pos[leaf] + lane]] = make_double2(sr, si);
+  }
+}
+
+// ------------------------------------------------------------------ host structures
+
+template <class T>
+struct DevArray {
+  T* p = nullptr;
+  int64_t n = 0;
+  ~DevArray() {
+    if (p) (void)hipFree(p);
+  }
+  int alloc(int64_t count) {
+    n = count;
+    if (count == 0) return UHM_OK;
+    hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)count);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return fail(e == hipErrorOutOfMemory ? UHM_ENOMEM : UHM_EHIP,
+                  std::string("hipMalloc(") + std::to_string(sizeof(T) * (size_t)count) + " B): " + hipGetErrorString(e));
+    }
+    return UHM_OK;
+  }
+  int upload(const std::vector<T>& v, hipStream_t s) {
+    int rc = alloc((int64_t)v.size());
+    if (rc) return rc;
+    if (!v.empty()) UHM_HIP(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+    return UHM_OK;
+  }
+  size_t bytes() const { return sizeof(T) * (size_t)n; }
+};
+
+// Streams host-packed data into a device array through two pinned staging buffers.
+struct Stager {
+  cd* dev = nullptr;
+  int64_t total = 0, written = 0;
+  hipStream_t s = nullptr;
+  cd* host[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool pending[2] = {false, false};
+  int64_t cap = 0, fill = 0;
+  int cur = 0;
+  int err = UHM_OK;
+
+  int init(cd* d, int64_t tot, hipStream_t st) {
+    dev = d;
+    total = tot;
+    s = st;
+    cap = std::max<int64_t>(1, std::min<int64_t>(tot, (int64_t)(64 << 20) / (int64_t)sizeof(cd)));
+    for (int b = 0; b < 2; ++b) {
+      UHM_HIP(hipHostMalloc(reinterpret_cast<void**>(&host[b]), sizeof(cd) * (size_t)cap, hipHostMallocDefault));
+      UHM_HIP(hipEventCreateWithFlags(&ev[b], hipEventDisableTiming));
+    }
+    return UHM_OK;
+  }
+  // Room for k <= cap elements in the current staging buffer.
+  cd* span(int64_t k) {
+    if (fill + k > cap) flush();
+    cd* r = host[cur] + fill;
+    fill += k;
+    return r;
+  }
+  void flush() {
+    if (fill == 0 || err) return;
+    if (written + fill > total) {
+      err = fail(UHM_EINVAL, "internal: staged more elements than allocated");
+      return;
+    }
+    hipError_t e = hipMemcpyAsync(dev + written, host[cur], sizeof(cd) * (size_t)fill, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[cur], s);
+    if (e != hipSuccess) {
+      err = fail(UHM_EHIP, std::string("staged copy: ") + hipGetErrorString(e));
+      return;
+    }
+    pending[cur] = true;
+    written += fill;
+    fill = 0;
+    cur ^= 1;
+    if (pending[cur]) {
+      e = hipEventSynchronize(ev[cur]);
+      pending[cur] = false;
+      if (e != hipSuccess) err = fail(UHM_EHIP, std::string("staged copy sync: ") + hipGetErrorString(e));
+    }
+  }
+  int finish() {
+    flush();
+    for (int b = 0; b < 2; ++b)
+      if (pending[b]) {
+        (void)hipEventSynchronize(ev[b]);
+        pending[b] = false;
+      }
+    if (!err && written != total) err = fail(UHM_EINVAL, "internal: staged element count mismatch");
+    return err;
+  }
+  ~Stager() {
+    for (int b = 0; b < 2; ++b) {
+      if (pending[b]) (void)hipEventSynchronize(ev[b]);
+      if (host[b]) (void)hipHostFree(host[b]);
+      if (ev[b]) (void)hipEventDestroy(ev[b]);
+    }
+  }
+};
+
+struct TreeInfo {
+  int64_t n = 0;
+  int32_t nc = 0;
+  std::vector<int32_t> leaves;              // leaf cluster ids, by position
+  std::vector<int32_t> leaf_first, leaf_cnt;  // per cluster: its leaves in `leaves`
+  std::vector<std::vector<int32_t>> anc;    // per leaf: ancestors, root first, leaf last
+};
+
+int check_tree(int64_t n, const int64_t* perm, int32_t nc, const int64_t* off, const int64_t* size,
+               const int32_t* parent, TreeInfo& T) {
+  if (n < 1 || n > INT32_MAX) return fail(UHM_EINVAL, "n must be in [1, 2^31)");
+  if (!perm || !off || !size || !parent || nc < 1) return fail(UHM_EINVAL, "null cluster tree array");
+  std::vector<char> seen(n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (perm[i] < 0 || perm[i] >= n || seen[perm[i]]) return fail(UHM_EINVAL, "perm is not a permutation");
+    seen[perm[i]] = 1;
+  }
+  int root = -1;
+  std::vector<int32_t> nchild(nc, 0);
+  for (int32_t c = 0; c < nc; ++c) {
+    if (size[c] < 1 || off[c] < 0 || off[c] + size[c] > n) return fail(UHM_EINVAL, "cluster range out of [0, n)");
+    if (parent[c] < 0) {
+      if (root >= 0) return fail(UHM_EINVAL, "more than one root cluster");
+      root = c;
+      if (off[c] != 0 || size[c] != n) return fail(UHM_EINVAL, "root must cover [0, n)");
+    } else {
+      const int32_t p = parent[c];
+      if (p >= nc || p == c) return fail(UHM_EINVAL, "bad parent index");
+      if (off[c] < off[p] || off[c] + size[c] > off[p] + size[p]) return fail(UHM_EINVAL, "child outside parent");
+      nchild[p]++;
+    }
+  }
+  if (root < 0) return fail(UHM_EINVAL, "no root cluster");
+  // children partition their parent
+  std::vector<std::vector<int32_t>> kids(nc);
+  for (int32_t c = 0; c < nc; ++c)
+    if (parent[c] >= 0) kids[parent[c]].push_back(c);
+  for (int32_t c = 0; c < nc; ++c) {
+    if (kids[c].empty()) continue;
+    std::sort(kids[c].begin(), kids[c].end(), [&](int32_t a, int32_t b) { return off[a] < off[b]; });
+    int64_t pos = off[c];
+    for (int32_t k : kids[c]) {
+      if (off[k] != pos) return fail(UHM_EINVAL, "children do not partition their parent");
+      pos += size[k];
+    }
+    if (pos != off[c] + size[c]) return fail(UHM_EINVAL, "children do not partition their parent");
+  }
+  T.n = n;
+  T.nc = nc;
+  for (int32_t c = 0; c < nc; ++c)
+    if (nchild[c] == 0) T.leaves.push_back(c);
+  std::sort(T.leaves.begin(), T.leaves.end(), [&](int32_t a, int32_t b) { return off[a] < off[b]; });
+  int64_t pos = 0;
+  for (int32_t l : T.leaves) {
+    if (off[l] != pos) return fail(UHM_EINVAL, "leaves do not tile [0, n)");
+    if (size[l] > kLeafMax) return fail(UHM_ENOTSUP, "leaf larger than 64 points");
+    pos += size[l];
+  }
+  if (pos != n) return fail(UHM_EINVAL, "leaves do not tile [0, n)");
+  const int32_t nl = (int32_t)T.leaves.size();
+  std::vector<int64_t> loff(nl);
+  for (int32_t i = 0; i < nl; ++i) loff[i] = off[T.leaves[i]];
+  T.leaf_first.assign(nc, 0);
+  T.leaf_cnt.assign(nc, 0);
+  for (int32_t c = 0; c < nc; ++c) {
+    const int32_t a = (int32_t)(std::lower_bound(loff.begin(), loff.end(), off[c]) - loff.begin());
+    const int32_t b = (int32_t)(std::lower_bound(loff.begin(), loff.end(), off[c] + size[c]) - loff.begin());
+    T.leaf_first[c] = a;
+    T.leaf_cnt[c] = b - a;
+  }
+  T.anc.resize(nl);
+  for (int32_t i = 0; i < nl; ++i) {
+    std::vector<int32_t>& a = T.anc[i];
+    int32_t c = T.leaves[i];
+    int guard = 0;
+    while (c >= 0) {
+      a.push_back(c);
+      c = parent[c];
+      if (++guard > nc) return fail(UHM_EINVAL, "cycle in the parent array");
+    }
+    std::reverse(a.begin(), a.end());
+  }
+  return UHM_OK;
+}
+
+struct Timer {
+  const char* name;
+  double total_ms = 0.0;
+  int64_t launches = 0;
+};
+
+struct PendingEvent {
+  hipEvent_t a, b;
+  int kernel;
+};
+
+}  // namespace
+
+struct uhm_op {
+  int kind = 0;  // 0 UH, 1 H
+  int storage = UHM_C128;
+  int64_t n = 0;
+  int32_t nleaves = 0;
+  uhm_op_info info{};
+
+  DevArray<int32_t> perm, leaf_pos, leaf_n;
+  // forward panels and partial sums
+  DevArray<cd> F;
+  DevArray<int64_t> fwd_off, poff;
+  DevArray<int32_t> fwd_cols;
+  int64_t p_len = 0;
+  // segments of the rank-space vector (u_sigma per cluster, or Y_b^* v per block)
+  DevArray<int32_t> out_seg, seg_leaf0, seg_nleaf, seg_col;
+  DevArray<int64_t> seg_start;
+  int64_t nxh = 0;
+  // couplings
+  DevArray<cd> S;
+  DevArray<CoupTile> ctiles;
+  DevArray<int2> cblk;
+  DevArray<int32_t> yh_grp, grp_t0, grp_nt;
+  DevArray<int64_t> grp_start;
+  int32_t nctiles = 0;
+  int64_t nyh = 0;
+  // backward panels
+  DevArray<cd> B;
+  DevArray<int64_t> bwd_off, zoff;
+  DevArray<int32_t> bwd_cols, zmap;
+  // workspace
+  DevArray<cd> ws_p, ws_xh, ws_part, ws_yh;
+  // timing
+  bool timing = false;
+  std::vector<Timer> timers;
+  std::vector<PendingEvent> pending;
+  std::vector<hipEvent_t> free_events;
+
+  ~uhm_op() {
+    for (auto& e : pending) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    for (auto e : free_events) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+enum { K_FORWARD = 0, K_REDUCE_FWD, K_COUPLING, K_REDUCE_COUP, K_BACKWARD, K_COUNT };
+const char* kKernelNames[K_COUNT] = {"k_forward", "k_reduce_segments", "k_coupling", "k_reduce_coupling",
+                                     "k_backward"};
+
+hipEvent_t get_event(uhm_op* op) {
+  if (!op->free_events.empty()) {
+    hipEvent_t e = op->free_events.back();
+    op->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct ScopedTiming {
+  uhm_op* op;
+  hipStream_t s;
+  int k;
+  hipEvent_t a = nullptr;
+  ScopedTiming(uhm_op* o, hipStream_t st, int kernel) : op(o), s(st), k(kernel) {
+    if (op->timing) {
+      a = get_event(op);
+      if (a) (void)hipEventRecord(a, s);
+    }
+  }
+  ~ScopedTiming() {
+    if (!a) return;
+    hipEvent_t b = get_event(op);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    op->pending.push_back({a, b, k});
+  }
+};
+
+int common_tree_upload(uhm_op* op, const TreeInfo& T, const int64_t* perm, const int64_t* off, const int64_t* size,
+                       hipStream_t s) {
+  std::vector<int32_t> p32(T.n), lp(T.leaves.size()), ln(T.leaves.size());
+  for (int64_t i = 0; i < T.n; ++i) p32[i] = (int32_t)perm[i];
+  for (size_t i = 0; i < T.leaves.size(); ++i) {
+    lp[i] = (int32_t)off[T.leaves[i]];
+    ln[i] = (int32_t)size[T.leaves[i]];
+  }
+  int rc;
+  if ((rc = op->perm.upload(p32, s)) || (rc = op->leaf_pos.upload(lp, s)) || (rc = op->leaf_n.upload(ln, s))) return rc;
+  UHM_HIP(hipStreamSynchronize(s));
+  op->n = T.n;
+  op->nleaves = (int32_t)T.leaves.size();
+  return UHM_OK;
+}
+
+// A column source of a forward or backward panel: `len` columns of a column-major
+// matrix `src` (rows `nrows`), starting at row `row0` for this leaf.
+struct PanelSeg {
+  const cd* src;
+  int64_t nrows;
+  int64_t row0;
+  int32_t len;
+  int32_t zbase;  // backward: rank-space index of the first column, or -1 for dense
+  const int64_t* dense_cols;  // backward dense: perm + off[sigma]
+};
+
+// Forward panel of one leaf: tile-major, tiles of 64 columns, each row-major.
+int stage_forward_leaf(Stager& st, const std::vector<PanelSeg>& segs, int32_t C, int32_t n) {
+  // column c -> (segment, column within segment)
+  std::vector<std::pair<int32_t, int32_t>> cmap;
+  cmap.reserve(C);
+  for (int32_t si = 0; si < (int32_t)segs.size(); ++si)
+    for (int32_t j = 0; j < segs[si].len; ++j) cmap.push_back({si, j});
+  for (int32_t j0 = 0; j0 < C; j0 += kTile) {
+    const int32_t wj = std::min(kTile, C - j0);
+    cd* tile = st.span((int64_t)wj * n);
+    for (int32_t c = 0; c < wj; ++c) {
+      const PanelSeg& sg = segs[cmap[j0 + c].first];
+      const cd* colp = sg.src + (int64_t)cmap[j0 + c].second * sg.nrows + sg.row0;
+      for (int32_t i = 0; i < n; ++i) tile[(int64_t)i * wj + c] = colp[i];
+    }
+  }
+  return st.err;
+}
+
+// Backward panel of one leaf: column-major n x K.
+int stage_backward_leaf(Stager& st, const std::vector<PanelSeg>& segs, int32_t n) {
+  for (const PanelSeg& sg : segs)
+    for (int32_t j = 0; j < sg.len; ++j) {
+      cd* dst = st.span(n);
+      std::memcpy(static_cast<void*>(dst), sg.src + (int64_t)j * sg.nrows + sg.row0, sizeof(cd) * (size_t)n);
+    }
+  return st.err;
+}
+
+struct SegDesc {
+  int64_t start;
+  int32_t len;
+  int32_t leaf0, nleaf, col;
+};
+
+int upload_segments(uhm_op* op, const std::vector<SegDesc>& segs, int64_t nout, hipStream_t s) {
+  std::vector<int32_t> out_seg(nout), leaf0(segs.size()), nleaf(segs.size()), col(segs.size());
+  std::vector<int64_t> start(segs.size());
+  for (size_t k = 0; k < segs.size(); ++k) {
+    for (int32_t j = 0; j < segs[k].len; ++j) out_seg[segs[k].start + j] = (int32_t)k;
+    start[k] = segs[k].start;
+    leaf0[k] = segs[k].leaf0;
+    nleaf[k] = segs[k].nleaf;
+    col[k] = segs[k].col;
+  }
+  int rc;
+  if ((rc = op->out_seg.upload(out_seg, s)) || (rc = op->seg_start.upload(start, s)) ||
+      (rc = op->seg_leaf0.upload(leaf0, s)) || (rc = op->seg_nleaf.upload(nleaf, s)) ||
+      (rc = op->seg_col.upload(col, s)))
+    return rc;
+  UHM_HIP(hipStreamSynchronize(s));
+  op->nxh = nout;
+  return UHM_OK;
+}
+
+bool in_bounds(int64_t off, int64_t count, int64_t len) { return off >= 0 && count >= 0 && off + count <= len; }
+
+int grow_workspace(uhm_op* op) {
+  // single-RHS workspace; columns are processed one at a time
+  int rc;
+  if (op->ws_p.n < op->p_len && (rc = op->ws_p.alloc(op->p_len))) return rc;
+  if (op->ws_xh.n < op->nxh && (rc = op->ws_xh.alloc(op->nxh))) return rc;
+  if (op->kind == 0) {
+    if (op->ws_part.n < (int64_t)op->nctiles * kRowChunk && (rc = op->ws_part.alloc((int64_t)op->nctiles * kRowChunk)))
+      return rc;
+    if (op->ws_yh.n < op->nyh && (rc = op->ws_yh.alloc(op->nyh))) return rc;
+  }
+  return UHM_OK;
+}
+
+// Host check of every index the kernels form, against the sizes of the arrays they
+// touch.  Runs at the end of each upload, before the operator can be launched.
+struct LayoutView {
+  int64_t n, nleaves, ftot, ptot, btot, ztot, nz, nxh;
+  const std::vector<int32_t>* leaf_n;
+  const std::vector<int64_t>* fwd_off;
+  const std::vector<int32_t>* fwd_cols;
+  const std::vector<int64_t>* poff;
+  const std::vector<SegDesc>* segs;
+  const std::vector<int64_t>* bwd_off;
+  const std::vector<int32_t>* bwd_cols;
+  const std::vector<int64_t>* zoff;
+  const std::vector<int32_t>* zmap;
+};
+
+int check_layout(const LayoutView& L) {
+  for (int64_t i = 0; i < L.nleaves; ++i) {
+    const int64_t n = (*L.leaf_n)[i], C = (*L.fwd_cols)[i], K = (*L.bwd_cols)[i];
+    if (n < 1 || n > kLeafMax) return fail(UHM_EINVAL, "layout: leaf size");
+    if ((*L.fwd_off)[i] < 0 || (*L.fwd_off)[i] + C * n > L.ftot) return fail(UHM_EINVAL, "layout: forward panel");
+    if ((*L.poff)[i] < 0 || (*L.poff)[i] + C > L.ptot) return fail(UHM_EINVAL, "layout: partial sums");
+    if ((*L.bwd_off)[i] < 0 || (*L.bwd_off)[i] + K * n > L.btot) return fail(UHM_EINVAL, "layout: backward panel");
+    if ((*L.zoff)[i] < 0 || (*L.zoff)[i] + K > L.ztot) return fail(UHM_EINVAL, "layout: gather map");
+  }
+  for (const SegDesc& sg : *L.segs) {
+    if (sg.start < 0 || sg.start + sg.len > L.nxh || sg.leaf0 < 0 || sg.nleaf < 1 || sg.leaf0 + sg.nleaf > L.nleaves)
+      return fail(UHM_EINVAL, "layout: segment");
+    for (int32_t q = 0; q < sg.nleaf; ++q)
+      if (sg.col < 0 || sg.col + sg.len > (*L.fwd_cols)[sg.leaf0 + q]) return fail(UHM_EINVAL, "layout: segment column");
+  }
+  for (int32_t m : *L.zmap)
+    if (m >= L.nz || (m < 0 && -1 - (int64_t)m >= L.n)) return fail(UHM_EINVAL, "layout: gather index");
+  return UHM_OK;
+}
+
+int check_coupling(const std::vector<CoupTile>& tiles, const std::vector<int2>& cblk, int64_t stot, int64_t nxh,
+                   const std::vector<int32_t>& grp_t0, const std::vector<int32_t>& grp_nt,
+                   const std::vector<int64_t>& grp_start, int64_t nyh) {
+  for (const int2& b : cblk)
+    if (b.x < 1 || b.y < 0 || (int64_t)b.y + b.x > nxh) return fail(UHM_EINVAL, "layout: coupling block");
+  for (const CoupTile& T : tiles) {
+    if (T.h < 1 || T.h > kRowChunk || T.ncols < 1 || T.s_base < 0 || T.s_base + (int64_t)T.ncols * T.h > stot)
+      return fail(UHM_EINVAL, "layout: coupling tile");
+    int64_t b = T.first_blk, j = T.first_col, rem = T.ncols;
+    while (rem > 0) {
+      if (b < 0 || b >= (int64_t)cblk.size() || j < 0 || j >= cblk[b].x) return fail(UHM_EINVAL, "layout: coupling walk");
+      rem -= std::min<int64_t>(cblk[b].x - j, rem);
+      ++b;
+      j = 0;
+    }
+  }
+  for (size_t g = 0; g < grp_t0.size(); ++g) {
+    if (grp_t0[g] < 0 || grp_nt[g] < 1 || (size_t)grp_t0[g] + grp_nt[g] > tiles.size())
+      return fail(UHM_EINVAL, "layout: coupling group");
+    const int32_t h = tiles[grp_t0[g]].h;
+    if (grp_start[g] < 0 || grp_start[g] + h > nyh) return fail(UHM_EINVAL, "layout: coupling group rows");
+  }
+  return UHM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int uhm_version(void) { return 1; }
+
+const char* uhm_strerror(int code) {
+  switch (code) {
+    case UHM_OK: return "success";
+    case UHM_EINVAL: return "invalid argument";
+    case UHM_ENOMEM: return "out of memory";
+    case UHM_EHIP: return "HIP runtime error";
+    case UHM_ENOCONV: return "iteration limit reached without convergence";
+    case UHM_ENOTSUP: return "not supported by this build";
+    default: return "unknown error";
+  }
+}
+
+const char* uhm_last_error(void) { return g_err.c_str(); }
+
+int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream, uhm_op** out) {
+  if (!h || !out) return fail(UHM_EINVAL, "null argument");
+  *out = nullptr;
+  if (storage != UHM_C128) return fail(UHM_ENOTSUP, "storage precision not available in this build");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  TreeInfo T;
+  int rc = check_tree(h->n, h->perm, h->nclusters, h->off, h->size, h->parent, T);
+  if (rc) return rc;
+  const int32_t nc = h->nclusters;
+  if (!h->rank_row || !h->rank_col || !h->U_off || !h->V_off) return fail(UHM_EINVAL, "null basis arrays");
+  if ((h->nadm > 0 && (!h->adm_row || !h->adm_col || !h->S_off || !h->S)) ||
+      (h->nden > 0 && (!h->den_row || !h->den_col || !h->D_off || !h->D)) || h->nadm < 0 || h->nden < 0)
+    return fail(UHM_EINVAL, "null block arrays");
+  for (int32_t c = 0; c < nc; ++c) {
+    if (h->rank_row[c] < 0 || h->rank_col[c] < 0 || h->rank_row[c] > h->size[c] || h->rank_col[c] > h->size[c])
+      return fail(UHM_EINVAL, "cluster rank out of range");
+    if (h->rank_row[c] > 0 && (!h->U || !in_bounds(h->U_off[c], h->size[c] * h->rank_row[c], h->U_len)))
+      return fail(UHM_EINVAL, "U_off out of bounds");
+    if (h->rank_col[c] > 0 && (!h->V || !in_bounds(h->V_off[c], h->size[c] * h->rank_col[c], h->V_len)))
+      return fail(UHM_EINVAL, "V_off out of bounds");
+  }
+  for (int64_t b = 0; b < h->nadm; ++b) {
+    const int32_t t = h->adm_row[b], sg = h->adm_col[b];
+    if (t < 0 || t >= nc || sg < 0 || sg >= nc) return fail(UHM_EINVAL, "admissible block cluster out of range");
+    if (h->rank_row[t] < 1 || h->rank_col[sg] < 1) return fail(UHM_EINVAL, "admissible block without bases");
+    if (!in_bounds(h->S_off[b], (int64_t)h->rank_row[t] * h->rank_col[sg], h->S_len))
+      return fail(UHM_EINVAL, "S_off out of bounds");
+  }
+  for (int64_t b = 0; b < h->nden; ++b) {
+    const int32_t t = h->den_row[b], sg = h->den_col[b];
+    if (t < 0 || t >= nc || sg < 0 || sg >= nc) return fail(UHM_EINVAL, "dense block cluster out of range");
+    if (!in_bounds(h->D_off[b], h->size[t] * h->size[sg], h->D_len)) return fail(UHM_EINVAL, "D_off out of bounds");
+  }
+  std::unique_ptr<uhm_op> op(new (std::nothrow) uhm_op);
+  if (!op) return fail(UHM_ENOMEM, "host allocation");
+  op->kind = 0;
+  op->storage = storage;
+  if ((rc = common_tree_upload(op.get(), T, h->perm, h->off, h->size, s))) return rc;
+  const int32_t nl = op->nleaves;
+  const cd* U = reinterpret_cast<const cd*>(h->U);
+  const cd* V = reinterpret_cast<const cd*>(h->V);
+  const cd* Sh = reinterpret_cast<const cd*>(h->S);
+  const cd* D = reinterpret_cast<const cd*>(h->D);
+
+  // ---- rank-space vectors: u_sigma at xh_off[sigma], u_tau at yh_off[tau]
+  std::vector<int64_t> xh_off(nc, -1), yh_off(nc, -1);
+  int64_t nxh = 0, nyh = 0;
+  for (int32_t c = 0; c < nc; ++c) {
+    if (h->rank_col[c] > 0) { xh_off[c] = nxh; nxh += h->rank_col[c]; }
+    if (h->rank_row[c] > 0) { yh_off[c] = nyh; nyh += h->rank_row[c]; }
+  }
+  if (nxh > INT32_MAX || nyh > INT32_MAX) return fail(UHM_ENOTSUP, "rank space too large");
+
+  // ---- forward panels
+  std::vector<int64_t> fwd_off(nl), poff(nl);
+  std::vector<int32_t> fwd_cols(nl);
+  std::vector<int32_t> seg_col_of(nc, -1);  // column of cluster sigma's segment in its leaves' panels
+  int64_t ftot = 0, ptot = 0;
+  for (int32_t i = 0; i < nl; ++i) {
+    int32_t C = 0;
+    for (int32_t a : T.anc[i])
+      if (h->rank_col[a] > 0) {
+        if (seg_col_of[a] < 0) seg_col_of[a] = C;
+        C += h->rank_col[a];
+      }
+    fwd_cols[i] = C;
+    fwd_off[i] = ftot;
+    poff[i] = ptot;
+    ftot += (int64_t)C * h->size[T.leaves[i]];
+    ptot += C;
+  }
+  if ((rc = op->F.alloc(ftot))) return rc;
+  {
+    Stager st;
+    if ((rc = st.init(op->F.p, ftot, s))) return rc;
+    std::vector<PanelSeg> segs;
+    for (int32_t i = 0; i < nl && !st.err; ++i) {
+      const int32_t lf = T.leaves[i];
+      segs.clear();
+      for (int32_t a : T.anc[i])
+        if (h->rank_col[a] > 0)
+          segs.push_back({V + h->V_off[a], h->size[a], h->off[lf] - h->off[a], h->rank_col[a], -1, nullptr});
+      if ((rc = stage_forward_leaf(st, segs, fwd_cols[i], (int32_t)h->size[lf]))) return rc;
+    }
+    if ((rc = st.finish())) return rc;
+  }
+  if ((rc = op->fwd_off.upload(fwd_off, s)) || (rc = op->fwd_cols.upload(fwd_cols, s)) ||
+      (rc = op->poff.upload(poff, s)))
+    return rc;
+  op->p_len = ptot;
+  {
+    std::vector<SegDesc> segs;
+    for (int32_t c = 0; c < nc; ++c)
+      if (h->rank_col[c] > 0) segs.push_back({xh_off[c], h->rank_col[c], T.leaf_first[c], T.leaf_cnt[c], seg_col_of[c]});
+    if ((rc = upload_segments(op.get(), segs, nxh, s))) return rc;
+  }
+
+  // ---- couplings, grouped by row cluster, in row chunks
+  std::vector<std::vector<int64_t>> rowblk(nc);
+  for (int64_t b = 0; b < h->nadm; ++b) rowblk[h->adm_row[b]].push_back(b);
+  std::vector<CoupTile> tiles;
+  std::vector<int2> cblk;
+  std::vector<int32_t> grp_t0, grp_nt, yh_grp(nyh);
+  std::vector<int64_t> grp_start;
+  int64_t stot = 0;
+  for (int32_t t = 0; t < nc; ++t) {
+    if (rowblk[t].empty()) continue;
+    std::sort(rowblk[t].begin(), rowblk[t].end());
+    const int32_t lt = h->rank_row[t];
+    int64_t K = 0;
+    for (int64_t b : rowblk[t]) K += h->rank_col[h->adm_col[b]];
+    const int32_t blk0 = (int32_t)cblk.size();
+    for (int64_t b : rowblk[t]) cblk.push_back(make_int2(h->rank_col[h->adm_col[b]], (int32_t)xh_off[h->adm_col[b]]));
+    for (int32_t r0 = 0; r0 < lt; r0 += kRowChunk) {
+      const int32_t hh = std::min(kRowChunk, lt - r0);
+      const int32_t g = (int32_t)grp_start.size();
+      grp_start.push_back(yh_off[t] + r0);
+      grp_t0.push_back((int32_t)tiles.size());
+      for (int32_t r = 0; r < hh; ++r) yh_grp[yh_off[t] + r0 + r] = g;
+      int32_t bi = 0, bj = 0;
+      for (int64_t c0 = 0; c0 < K; c0 += kCoupCols) {
+        const int32_t nc_ = (int32_t)std::min<int64_t>(kCoupCols, K - c0);
+        tiles.push_back({stot + c0 * hh, hh, nc_, blk0 + bi, bj});
+        // advance the block cursor by nc_ columns
+        int32_t left = nc_;
+        while (left > 0) {
+          const int32_t len = cblk[blk0 + bi].x;
+          const int32_t take = std::min(len - bj, left);
+          left -= take;
+          bj += take;
+          if (bj == len) { ++bi; bj = 0; }
+        }
+      }
+      grp_nt.push_back((int32_t)tiles.size() - grp_t0.back());
+      stot += K * hh;
+    }
+  }
+  if (tiles.size() > (size_t)INT32_MAX / kRowChunk) return fail(UHM_ENOTSUP, "too many coupling tiles");
+  if ((rc = op->S.alloc(stot))) return rc;
+  if (stot > 0) {
+    Stager st;
+    if ((rc = st.init(op->S.p, stot, s))) return rc;
+    for (int32_t t = 0; t < nc && !st.err; ++t) {
+      if (rowblk[t].empty()) continue;
+      const int32_t lt = h->rank_row[t];
+      for (int32_t r0 = 0; r0 < lt; r0 += kRowChunk) {
+        const int32_t hh = std::min(kRowChunk, lt - r0);
+        for (int64_t b : rowblk[t]) {
+          const int32_t ls = h->rank_col[h->adm_col[b]];
+          const cd* Sb = Sh + h->S_off[b];
+          for (int32_t j = 0; j < ls; ++j) {
+            cd* dst = st.span(hh);
+            std::memcpy(static_cast<void*>(dst), Sb + (int64_t)j * lt + r0, sizeof(cd) * (size_t)hh);
+          }
+        }
+      }
+    }
+    if ((rc = st.finish())) return rc;
+  }
+  if ((rc = op->ctiles.upload(tiles, s)) || (rc = op->cblk.upload(cblk, s)) || (rc = op->yh_grp.upload(yh_grp, s)) ||
+      (rc = op->grp_start.upload(grp_start, s)) || (rc = op->grp_t0.upload(grp_t0, s)) ||
+      (rc = op->grp_nt.upload(grp_nt, s)))
+    return rc;
+  op->nctiles = (int32_t)tiles.size();
+  op->nyh = nyh;
+
+  // ---- backward panels: ancestor bases, then dense blocks of the leaf's rows
+  std::vector<std::vector<int64_t>> denrow(nc);
+  for (int64_t b = 0; b < h->nden; ++b) denrow[h->den_row[b]].push_back(b);
+  std::vector<int64_t> bwd_off(nl), zoff(nl);
+  std::vector<int32_t> bwd_cols(nl);
+  int64_t btot = 0, ztot = 0;
+  for (int32_t i = 0; i < nl; ++i) {
+    int64_t K = 0;
+    for (int32_t a : T.anc[i]) {
+      K += h->rank_row[a];
+      for (int64_t b : denrow[a]) K += h->size[h->den_col[b]];
+    }
+    if (K > INT32_MAX) return fail(UHM_ENOTSUP, "backward panel too wide");
+    bwd_cols[i] = (int32_t)K;
+    bwd_off[i] = btot;
+    zoff[i] = ztot;
+    btot += K * h->size[T.leaves[i]];
+    ztot += K;
+  }
+  std::vector<int32_t> zmap(ztot);
+  if ((rc = op->B.alloc(btot))) return rc;
+  {
+    Stager st;
+    if ((rc = st.init(op->B.p, btot, s))) return rc;
+    std::vector<PanelSeg> segs;
+    for (int32_t i = 0; i < nl && !st.err; ++i) {
+      const int32_t lf = T.leaves[i];
+      segs.clear();
+      int64_t z = zoff[i];
+      for (int32_t a : T.anc[i])
+        if (h->rank_row[a] > 0) {
+          segs.push_back({U + h->U_off[a], h->size[a], h->off[lf] - h->off[a], h->rank_row[a], 0, nullptr});
+          for (int32_t j = 0; j < h->rank_row[a]; ++j) zmap[z++] = (int32_t)(yh_off[a] + j);
+        }
+      for (int32_t a : T.anc[i])
+        for (int64_t b : denrow[a]) {
+          const int32_t sg = h->den_col[b];
+          segs.push_back({D + h->D_off[b], h->size[a], h->off[lf] - h->off[a], (int32_t)h->size[sg], -1, nullptr});
+          for (int64_t j = 0; j < h->size[sg]; ++j) zmap[z++] = (int32_t)(-1 - h->perm[h->off[sg] + j]);
+        }
+      if ((rc = stage_backward_leaf(st, segs, (int32_t)h->size[lf]))) return rc;
+    }
+    if ((rc = st.finish())) return rc;
+  }
+  if ((rc = op->bwd_off.upload(bwd_off, s)) || (rc = op->bwd_cols.upload(bwd_cols, s)) ||
+      (rc = op->zoff.upload(zoff, s)) || (rc = op->zmap.upload(zmap, s)))
+    return rc;
+  UHM_HIP(hipStreamSynchronize(s));
+  {
+    std::vector<int32_t> leaf_n(nl);
+    for (int32_t i = 0; i < nl; ++i) leaf_n[i] = (int32_t)h->size[T.leaves[i]];
+    std::vector<SegDesc> segs;
+    for (int32_t c = 0; c < nc; ++c)
+      if (h->rank_col[c] > 0) segs.push_back({xh_off[c], h->rank_col[c], T.leaf_first[c], T.leaf_cnt[c], seg_col_of[c]});
+    LayoutView L{h->n, nl, ftot, ptot, btot, ztot, nyh, nxh, &leaf_n, &fwd_off, &fwd_cols, &poff, &segs,
+                 &bwd_off, &bwd_cols, &zoff, &zmap};
+    if ((rc = check_layout(L))) return rc;
+    if ((rc = check_coupling(tiles, cblk, stot, nxh, grp_t0, grp_nt, grp_start, nyh))) return rc;
+  }
+
+  uhm_op_info& I = op->info;
+  I.n = h->n;
+  I.kind = 0;
+  I.storage = storage;
+  I.nleaves = nl;
+  I.elem_bytes = 16;
+  I.nadm = h->nadm;
+  I.nden = h->nden;
+  I.elems_forward = I.elems_backward = 0;
+  for (int32_t c = 0; c < nc; ++c) {
+    I.elems_forward += h->size[c] * h->rank_col[c];
+    I.elems_backward += h->size[c] * h->rank_row[c];
+  }
+  I.elems_coupling = stot;
+  I.elems_near = 0;
+  for (int64_t b = 0; b < h->nden; ++b) I.elems_near += h->size[h->den_row[b]] * h->size[h->den_col[b]];
+  I.rank_space = nxh;
+  I.device_bytes = (int64_t)(op->F.bytes() + op->S.bytes() + op->B.bytes() + op->zmap.bytes() + op->perm.bytes() +
+                             op->ctiles.bytes() + op->cblk.bytes() + op->out_seg.bytes() + op->yh_grp.bytes());
+  *out = op.release();
+  return UHM_OK;
+}
+
+int uhm_upload_h(const uhm_host_hmatrix* h, uhm_storage storage, void* hip_stream, uhm_op** out) {
+  if (!h || !out) return fail(UHM_EINVAL, "null argument");
+  *out = nullptr;
+  if (storage != UHM_C128) return fail(UHM_ENOTSUP, "storage precision not available in this build");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  TreeInfo T;
+  int rc = check_tree(h->n, h->perm, h->nclusters, h->off, h->size, h->parent, T);
+  if (rc) return rc;
+  const int32_t nc = h->nclusters;
+  if ((h->nadm > 0 && (!h->adm_row || !h->adm_col || !h->adm_rank || !h->X_off || !h->Y_off || !h->X || !h->Y)) ||
+      (h->nden > 0 && (!h->den_row || !h->den_col || !h->D_off || !h->D)) || h->nadm < 0 || h->nden < 0)
+    return fail(UHM_EINVAL, "null block arrays");
+  for (int64_t b = 0; b < h->nadm; ++b) {
+    const int32_t t = h->adm_row[b], sg = h->adm_col[b];
+    if (t < 0 || t >= nc || sg < 0 || sg >= nc) return fail(UHM_EINVAL, "admissible block cluster out of range");
+    const int32_t k = h->adm_rank[b];
+    if (k < 1 || k > std::min(h->size[t], h->size[sg])) return fail(UHM_EINVAL, "block rank out of range");
+    if (!in_bounds(h->X_off[b], h->size[t] * k, h->X_len) || !in_bounds(h->Y_off[b], h->size[sg] * k, h->Y_len))
+      return fail(UHM_EINVAL, "X_off/Y_off out of bounds");
+  }
+  for (int64_t b = 0; b < h->nden; ++b) {
+    const int32_t t = h->den_row[b], sg = h->den_col[b];
+    if (t < 0 || t >= nc || sg < 0 || sg >= nc) return fail(UHM_EINVAL, "dense block cluster out of range");
+    if (!in_bounds(h->D_off[b], h->size[t] * h->size[sg], h->D_len)) return fail(UHM_EINVAL, "D_off out of bounds");
+  }
+  std::unique_ptr<uhm_op> op(new (std::nothrow) uhm_op);
+  if (!op) return fail(UHM_ENOMEM, "host allocation");
+  op->kind = 1;
+  op->storage = storage;
+  if ((rc = common_tree_upload(op.get(), T, h->perm, h->off, h->size, s))) return rc;
+  const int32_t nl = op->nleaves;
+  const cd* X = reinterpret_cast<const cd*>(h->X);
+  const cd* Y = reinterpret_cast<const cd*>(h->Y);
+  const cd* D = reinterpret_cast<const cd*>(h->D);
+  std::vector<std::vector<int64_t>> colblk(nc), rowblk(nc), denrow(nc);
+  for (int64_t b = 0; b < h->nadm; ++b) {
+    colblk[h->adm_col[b]].push_back(b);
+    rowblk[h->adm_row[b]].push_back(b);
+  }
+  for (int64_t b = 0; b < h->nden; ++b) denrow[h->den_row[b]].push_back(b);
+  // t_b = Y_b^* v|_sigma at t_off[b]
+  std::vector<int64_t> t_off(h->nadm);
+  int64_t nt = 0;
+  for (int64_t b = 0; b < h->nadm; ++b) { t_off[b] = nt; nt += h->adm_rank[b]; }
+  if (nt > INT32_MAX) return fail(UHM_ENOTSUP, "rank space too large");
+
+  // ---- forward panels from Y_b, one segment per block of each ancestor column cluster
+  std::vector<int64_t> fwd_off(nl), poff(nl);
+  std::vector<int32_t> fwd_cols(nl);
+  std::vector<int32_t> bcol(h->nadm, -1);
+  int64_t ftot = 0, ptot = 0;
+  for (int32_t i = 0; i < nl; ++i) {
+    int64_t C = 0;
+    for (int32_t a : T.anc[i])
+      for (int64_t b : colblk[a]) {
+        if (bcol[b] < 0) bcol[b] = (int32_t)C;
+        C += h->adm_rank[b];
+      }
+    if (C > INT32_MAX) return fail(UHM_ENOTSUP, "forward panel too wide");
+    fwd_cols[i] = (int32_t)C;
+    fwd_off[i] = ftot;
+    poff[i] = ptot;
+    ftot += C * h->size[T.leaves[i]];
+    ptot += C;
+  }
+  if ((rc = op->F.alloc(ftot))) return rc;
+  {
+    Stager st;
+    if ((rc = st.init(op->F.p, ftot, s))) return rc;
+    std::vector<PanelSeg> segs;
+    for (int32_t i = 0; i < nl && !st.err; ++i) {
+      const int32_t lf = T.leaves[i];
+      segs.clear();
+      for (int32_t a : T.anc[i])
+        for (int64_t b : colblk[a])
+          segs.push_back({Y + h->Y_off[b], h->size[a], h->off[lf] - h->off[a], h->adm_rank[b], -1, nullptr});
+      if ((rc = stage_forward_leaf(st, segs, fwd_cols[i], (int32_t)h->size[lf]))) return rc;
+    }
+    if ((rc = st.finish())) return rc;
+  }
+  if ((rc = op->fwd_off.upload(fwd_off, s)) || (rc = op->fwd_cols.upload(fwd_cols, s)) ||
+      (rc = op->poff.upload(poff, s)))
+    return rc;
+  op->p_len = ptot;
+  {
+    std::vector<SegDesc> segs;
+    for (int64_t b = 0; b < h->nadm; ++b) {
+      const int32_t sg = h->adm_col[b];
+      segs.push_back({t_off[b], h->adm_rank[b], T.leaf_first[sg], T.leaf_cnt[sg], bcol[b]});
+    }
+    if ((rc = upload_segments(op.get(), segs, nt, s))) return rc;
+  }
+
+  // ---- backward panels from X_b, then dense blocks
+  std::vector<int64_t> bwd_off(nl), zoff(nl);
+  std::vector<int32_t> bwd_cols(nl);
+  int64_t btot = 0, ztot = 0;
+  for (int32_t i = 0; i < nl; ++i) {
+    int64_t K = 0;
+    for (int32_t a : T.anc[i]) {
+      for (int64_t b : rowblk[a]) K += h->adm_rank[b];
+      for (int64_t b : denrow[a]) K += h->size[h->den_col[b]];
+    }
+    if (K > INT32_MAX) return fail(UHM_ENOTSUP, "backward panel too wide");
+    bwd_cols[i] = (int32_t)K;
+    bwd_off[i] = btot;
+    zoff[i] = ztot;
+    btot += K * h->size[T.leaves[i]];
+    ztot += K;
+  }
+  std::vector<int32_t> zmap(ztot);
+  if ((rc = op->B.alloc(btot))) return rc;
+  {
+    Stager st;
+    if ((rc = st.init(op->B.p, btot, s))) return rc;
+    std::vector<PanelSeg> segs;
+    for (int32_t i = 0; i < nl && !st.err; ++i) {
+      const int32_t lf = T.leaves[i];
+      segs.clear();
+      int64_t z = zoff[i];
+      for (int32_t a : T.anc[i])
+        for (int64_t b : rowblk[a]) {
+          segs.push_back({X + h->X_off[b], h->size[a], h->off[lf] - h->off[a], h->adm_rank[b], 0, nullptr});
+          for (int32_t j = 0; j < h->adm_rank[b]; ++j) zmap[z++] = (int32_t)(t_off[b] + j);
+        }
+      for (int32_t a : T.anc[i])
+        for (int64_t b : denrow[a]) {
+          const int32_t sg = h->den_col[b];
+          segs.push_back({D + h->D_off[b], h->size[a], h->off[lf] - h->off[a], (int32_t)h->size[sg], -1, nullptr});
+          for (int64_t j = 0; j < h->size[sg]; ++j) zmap[z++] = (int32_t)(-1 - h->perm[h->off[sg] + j]);
+        }
+      if ((rc = stage_backward_leaf(st, segs, (int32_t)h->size[lf]))) return rc;
+    }
+    if ((rc = st.finish())) return rc;
+  }
+  if ((rc = op->bwd_off.upload(bwd_off, s)) || (rc = op->bwd_cols.upload(bwd_cols, s)) ||
+      (rc = op->zoff.upload(zoff, s)) || (rc = op->zmap.upload(zmap, s)))
+    return rc;
+  UHM_HIP(hipStreamSynchronize(s));
+  {
+    std::vector<int32_t> leaf_n(nl);
+    for (int32_t i = 0; i < nl; ++i) leaf_n[i] = (int32_t)h->size[T.leaves[i]];
+    std::vector<SegDesc> segs;
+    for (int64_t b = 0; b < h->nadm; ++b) {
+      const int32_t sg = h->adm_col[b];
+      segs.push_back({t_off[b], h->adm_rank[b], T.leaf_first[sg], T.leaf_cnt[sg], bcol[b]});
+    }
+    LayoutView L{h->n, nl, ftot, ptot, btot, ztot, nt, nt, &leaf_n, &fwd_off, &fwd_cols, &poff, &segs,
+                 &bwd_off, &bwd_cols, &zoff, &zmap};
+    if ((rc = check_layout(L))) return rc;
+  }
+
+  uhm_op_info& I = op->info;
+  I.n = h->n;
+  I.kind = 1;
+  I.storage = storage;
+  I.nleaves = nl;
+  I.elem_bytes = 16;
+  I.nadm = h->nadm;
+  I.nden = h->nden;
+  I.elems_forward = I.elems_backward = 0;
+  for (int64_t b = 0; b < h->nadm; ++b) {
+    I.elems_forward += h->size[h->adm_col[b]] * h->adm_rank[b];
+    I.elems_backward += h->size[h->adm_row[b]] * h->adm_rank[b];
+  }
+  I.elems_coupling = 0;
+  I.elems_near = 0;
+  for (int64_t b = 0; b < h->nden; ++b) I.elems_near += h->size[h->den_row[b]] * h->size[h->den_col[b]];
+  I.rank_space = nt;
+  I.device_bytes = (int64_t)(op->F.bytes() + op->B.bytes() + op->zmap.bytes() + op->perm.bytes() + op->out_seg.bytes());
+  *out = op.release();
+  return UHM_OK;
+}
+
+int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs, void* hip_stream) {
+  if (!op) return fail(UHM_EINVAL, "null operator");
+  if (nrhs < 0) return fail(UHM_EINVAL, "nrhs < 0");
+  if (nrhs == 0) return UHM_OK;
+  if (!X || !Y) return fail(UHM_EINVAL, "null vector pointer");
+  if (ldx < op->n || ldy < op->n) return fail(UHM_EINVAL, "leading dimension smaller than n");
+  const char* xb = static_cast<const char*>(X);
+  const char* yb = static_cast<const char*>(Y);
+  const size_t es = sizeof(cd);
+  if (xb < yb + (size_t)((nrhs - 1) * ldy + op->n) * es && yb < xb + (size_t)((nrhs - 1) * ldx + op->n) * es)
+    return fail(UHM_EINVAL, "X and Y overlap");
+  int rc = grow_workspace(op);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int nl = op->nleaves;
+  for (int32_t r = 0; r < nrhs; ++r) {
+    const cd* x = static_cast<const cd*>(X) + (int64_t)r * ldx;
+    cd* y = static_cast<cd*>(Y) + (int64_t)r * ldy;
+    if (op->nxh > 0) {
+      {
+        ScopedTiming tm(op, s, K_FORWARD);
+        hipLaunchKernelGGL(k_forward, dim3(nl), dim3(64 * kFwdWaves), 0, s, op->F.p, op->fwd_off.p, op->fwd_cols.p,
+                           op->leaf_pos.p, op->leaf_n.p, op->perm.p, x, op->poff.p, op->ws_p.p, nl);
+      }
+      {
+        ScopedTiming tm(op, s, K_REDUCE_FWD);
+        hipLaunchKernelGGL(k_reduce_segments, dim3((unsigned)((op->nxh + 255) / 256)), dim3(256), 0, s, op->ws_p.p,
+                           op->poff.p, op->out_seg.p, op->seg_start.p, op->seg_leaf0.p, op->seg_nleaf.p, op->seg_col.p,
+                           op->nxh, op->ws_xh.p);
+      }
+    }
+    const cd* zsrc = op->ws_xh.p;
+    if (op->kind == 0 && op->nctiles > 0) {
+      {
+        ScopedTiming tm(op, s, K_COUPLING);
+        hipLaunchKernelGGL(k_coupling, dim3((unsigned)((op->nctiles + kCoupWaves - 1) / kCoupWaves)),
+                           dim3(64 * kCoupWaves), 0, s, op->S.p, op->ctiles.p, op->nctiles, op->cblk.p, op->ws_xh.p,
+                           op->ws_part.p);
+      }
+      {
+        ScopedTiming tm(op, s, K_REDUCE_COUP);
+        hipLaunchKernelGGL(k_reduce_coupling, dim3((unsigned)((op->nyh + 255) / 256)), dim3(256), 0, s,
+                           op->ws_part.p, op->yh_grp.p, op->grp_start.p, op->grp_t0.p, op->grp_nt.p, op->nyh,
+                           op->ws_yh.p);
+      }
+      zsrc = op->ws_yh.p;
+    }
+    {
+      ScopedTiming tm(op, s, K_BACKWARD);
+      hipLaunchKernelGGL(k_backward, dim3(nl), dim3(64 * kBwdWaves), 0, s, op->B.p, op->bwd_off.p, op->bwd_cols.p,
+                         op->zoff.p, op->zmap.p, op->leaf_pos.p, op->leaf_n.p, op->perm.p, zsrc, x, y, nl);
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(UHM_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return UHM_OK;
+}
+
+int uhm_op_info_get(const uhm_op* op, uhm_op_info* info) {
+  if (!op || !info) return fail(UHM_EINVAL, "null argument");
+  *info = op->info;
+  return UHM_OK;
+}
+
+int uhm_set_timing(uhm_op* op, int enabled) {
+  if (!op) return fail(UHM_EINVAL, "null operator");
+  for (auto& e : op->pending) {
+    op->free_events.push_back(e.a);
+    op->free_events.push_back(e.b);
+  }
+  op->pending.clear();
+  op->timers.clear();
+  for (int k = 0; k < K_COUNT; ++k) op->timers.push_back({kKernelNames[k], 0.0, 0});
+  op->timing = enabled != 0;
+  return UHM_OK;
+}
+
+int uhm_kernel_times(uhm_op* op, const char** names, double* total_ms, int64_t* launches, int32_t cap) {
+  if (!op) return fail(UHM_EINVAL, "null operator");
+  if (op->timers.empty())
+    for (int k = 0; k < K_COUNT; ++k) op->timers.push_back({kKernelNames[k], 0.0, 0});
+  for (auto& e : op->pending) {
+    UHM_HIP(hipEventSynchronize(e.b));
+    float ms = 0.f;
+    UHM_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+    op->timers[e.kernel].total_ms += ms;
+    op->timers[e.kernel].launches += 1;
+    op->free_events.push_back(e.a);
+    op->free_events.push_back(e.b);
+  }
+  op->pending.clear();
+  const int32_t nk = (int32_t)op->timers.size();
+  for (int32_t k = 0; k < std::min(nk, cap); ++k) {
+    if (names) names[k] = op->timers[k].name;
+    if (total_ms) total_ms[k] = op->timers[k].total_ms;
+    if (launches) launches[k] = op->timers[k].launches;
+  }
+  return nk;
+}
+
+void uhm_free(uhm_op* op) { delete op; }
+
+}  // extern "C"
