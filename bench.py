@@ -77,7 +77,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-h", action="store_true")
     ap.add_argument("--parity-leaves", type=int, default=6)
-    ap.add_argument("--traffic", type=str, default="", help="JSON file with counter-derived HBM bytes per launch")
+    ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_sphere262k_c128.json"),
+                    help="JSON file with counter-derived HBM bytes per launch (used only if it was taken on the "
+                         "current kernel source)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (the calibration kernel for the byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a design "
@@ -94,6 +98,16 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     binding.load_library()
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 26, dtype=torch.complex128, device="cuda")  # 1 GiB
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("copy calibration: 3 copies of 1 GiB")
 
     t0 = time.perf_counter()
     cloud = inputs.make_cloud("sphere", args.n, seed=args.seed)
@@ -164,8 +178,10 @@ def main():
     achieved = ab[dom] / (k_uh[dom][0] * 1e-3) / 1e9
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
+        from paper_2405_15573_amd import traffic as trmod
         tr = json.load(open(args.traffic))
-        traffic = tr.get(dom)
+        if tr.get("source_sha256") == trmod.kernel_source_sha256() and tr.get("n") == cloud.n:
+            traffic = tr.get("bytes_per_launch", {}).get(dom)
     line = {
         "metric": METRIC,
         "value": 1.0 / t_uh,

@@ -33,6 +33,7 @@ from __future__ import annotations
 import ctypes
 import math
 import os
+import sys
 import time
 from dataclasses import dataclass, field
 
@@ -354,9 +355,11 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
             lib.uhmb_aca_free(handle)
         t_rec += time.perf_counter() - tr
         if verbose:
-            print(f"  level {lev}: {nb} ACA blocks, k_max {int(kout.max())}", flush=True)
+            print(f"  level {lev}: {nb} ACA blocks, k_max {int(kout.max())}", file=sys.stderr, flush=True)
     tim["aca"] = t_aca
     tim["recompress"] = t_rec
+    if verbose:
+        print(f"  ACA {t_aca:.1f} s, recompression {t_rec:.1f} s", file=sys.stderr, flush=True)
 
     def block_factors(t, s):
         """(U_b, Sigma_b, V_b) of block t x s, using the mirror for t > s."""
@@ -420,6 +423,8 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
             for s, Lb in Ls:
                 Lmat[(t, s)] = Lb
     tim["compress"] = time.perf_counter() - t2
+    if verbose:
+        print(f"  uniform compression {tim['compress']:.1f} s", file=sys.stderr, flush=True)
 
     # ---- couplings S_b = L_b Sigma_b^{-1} L_{b~}^T, b~ the mirrored block
     t3 = time.perf_counter()
@@ -436,6 +441,8 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
         S[S_off[b]:S_off[b] + sizes[b]] = Sb.ravel(order="F")
         adm_rank[b] = sb.size
     tim["couplings"] = time.perf_counter() - t3
+    if verbose:
+        print(f"  couplings {tim['couplings']:.1f} s", file=sys.stderr, flush=True)
 
     # ---- bases (V = conj(U) by symmetry), H factors
     U_off = np.full(nc, -1, np.int64)

@@ -78,6 +78,7 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   return x * q + min(x, r) + k;
 }
 
+template <int FORM>
 __global__ __launch_bounds__(64 * kFwdWaves) void k_forward(
     const cd* __restrict__ F, const int64_t* __restrict__ fwd_off, const int32_t* __restrict__ fwd_cols,
     const int32_t* __restrict__ leaf_pos, const int32_t* __restrict__ leaf_n, const int32_t* __restrict__ perm,
@@ -100,17 +101,18 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_forward(
     const cd* q = base + (int64_t)kTile * j * n + lane;
     double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
     int i = 0;
-    for (; i + 4 <= n; i += 4) {
-      const cd v0 = q[(i + 0) * wj], v1 = q[(i + 1) * wj], v2 = q[(i + 2) * wj], v3 = q[(i + 3) * wj];
-      const cd x0 = xs[i + 0], x1 = xs[i + 1], x2 = xs[i + 2], x3 = xs[i + 3];
-      re0 = fma(v0.x, x0.x, fma(v0.y, x0.y, re0));
-      im0 = fma(v0.x, x0.y, fma(-v0.y, x0.x, im0));
-      re1 = fma(v1.x, x1.x, fma(v1.y, x1.y, re1));
-      im1 = fma(v1.x, x1.y, fma(-v1.y, x1.x, im1));
-      re0 = fma(v2.x, x2.x, fma(v2.y, x2.y, re0));
-      im0 = fma(v2.x, x2.y, fma(-v2.y, x2.x, im0));
-      re1 = fma(v3.x, x3.x, fma(v3.y, x3.y, re1));
-      im1 = fma(v3.x, x3.y, fma(-v3.y, x3.x, im1));
+    for (; i + 8 <= n; i += 8) {
+      cd v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = q[(i + k) * wj];
+#pragma unroll
+      for (int k = 0; k < 8; k += 2) {
+        const cd x0 = xs[i + k], x1 = xs[i + k + 1];
+        re0 = fma(v[k].x, x0.x, fma(v[k].y, x0.y, re0));
+        im0 = fma(v[k].x, x0.y, fma(-v[k].y, x0.x, im0));
+        re1 = fma(v[k + 1].x, x1.x, fma(v[k + 1].y, x1.y, re1));
+        im1 = fma(v[k + 1].x, x1.y, fma(-v[k + 1].y, x1.x, im1));
+      }
     }
     for (; i < n; ++i) {
       const cd v = q[i * wj], xv = xs[i];
@@ -123,6 +125,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_forward(
 
 // out[e] = sum over the leaves of segment seg(e) of p[leaf][col(seg) + e - start(seg)],
 // leaves taken in cluster order.
+template <int FORM>
 __global__ __launch_bounds__(256) void k_reduce_segments(
     const cd* __restrict__ p, const int64_t* __restrict__ poff, const int32_t* __restrict__ out_seg,
     const int64_t* __restrict__ seg_start, const int32_t* __restrict__ seg_leaf0, const int32_t* __restrict__ seg_nleaf,
@@ -132,8 +135,23 @@ __global__ __launch_bounds__(256) void k_reduce_segments(
   const int s = out_seg[e];
   const int col = seg_col[s] + (int)(e - seg_start[s]);
   const int l0 = seg_leaf0[s], nl = seg_nleaf[s];
+  // fixed summation order (leaf order), eight independent loads in flight
   double re = 0.0, im = 0.0;
-  for (int q = 0; q < nl; ++q) {
+  int q = 0;
+  for (; q + 8 <= nl; q += 8) {
+    int64_t o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = poff[l0 + q + k];
+    cd v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = p[o[k] + col];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      re += v[k].x;
+      im += v[k].y;
+    }
+  }
+  for (; q < nl; ++q) {
     const cd v = p[poff[l0 + q] + col];
     re += v.x;
     im += v.y;
@@ -153,7 +171,9 @@ struct CoupTile {
 __global__ __launch_bounds__(64 * kCoupWaves) void k_coupling(
     const cd* __restrict__ S, const CoupTile* __restrict__ tiles, int32_t ntiles, const int2* __restrict__ cblk,
     const cd* __restrict__ xh, cd* __restrict__ part) {
-  const int tile = blockIdx.x * kCoupWaves + (threadIdx.x >> 6);
+  // wave-uniform tile index: the descriptors and the rank-space values then come
+  // through scalar loads
+  const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * kCoupWaves + (threadIdx.x >> 6));
   if (tile >= ntiles) return;
   const int lane = threadIdx.x & 63;
   const CoupTile T = tiles[tile];
@@ -167,15 +187,20 @@ __global__ __launch_bounds__(64 * kCoupWaves) void k_coupling(
     const int cnt = min(bl.x - j, rem);
     const cd* xv = xh + bl.y + j;
     int q = 0;
-    for (; q + 2 <= cnt; q += 2) {
-      const cd s0 = col[(int64_t)q * h], s1 = col[(int64_t)(q + 1) * h];
-      const cd x0 = xv[q], x1 = xv[q + 1];
-      re0 = fma(s0.x, x0.x, fma(-s0.y, x0.y, re0));
-      im0 = fma(s0.x, x0.y, fma(s0.y, x0.x, im0));
-      re1 = fma(s1.x, x1.x, fma(-s1.y, x1.y, re1));
-      im1 = fma(s1.x, x1.y, fma(s1.y, x1.x, im1));
+    for (; q + 8 <= cnt; q += 8) {
+      cd sv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sv[k] = col[(int64_t)(q + k) * h];
+#pragma unroll
+      for (int k = 0; k < 8; k += 2) {
+        const cd x0 = xv[q + k], x1 = xv[q + k + 1];
+        re0 = fma(sv[k].x, x0.x, fma(-sv[k].y, x0.y, re0));
+        im0 = fma(sv[k].x, x0.y, fma(sv[k].y, x0.x, im0));
+        re1 = fma(sv[k + 1].x, x1.x, fma(-sv[k + 1].y, x1.y, re1));
+        im1 = fma(sv[k + 1].x, x1.y, fma(sv[k + 1].y, x1.x, im1));
+      }
     }
-    if (q < cnt) {
+    for (; q < cnt; ++q) {
       const cd s0 = col[(int64_t)q * h], x0 = xv[q];
       re0 = fma(s0.x, x0.x, fma(-s0.y, x0.y, re0));
       im0 = fma(s0.x, x0.y, fma(s0.y, x0.x, im0));
@@ -208,6 +233,7 @@ __global__ __launch_bounds__(256) void k_reduce_coupling(
 
 // w|_lambda = B_lambda z_lambda with z gathered from the rank-space vector (index >= 0)
 // or from the user-order input (index = -1 - user index).
+template <int FORM>
 __global__ __launch_bounds__(64 * kBwdWaves) void k_backward(
     const cd* __restrict__ B, const int64_t* __restrict__ bwd_off, const int32_t* __restrict__ bwd_cols,
     const int64_t* __restrict__ zoff, const int32_t* __restrict__ zmap, const int32_t* __restrict__ leaf_pos,
@@ -235,15 +261,20 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_backward(
     if (act) {
       const cd* col = Bl + (int64_t)(c0 + a) * n + lane;
       int c = a;
-      for (; c + 2 <= e; c += 2, col += 2 * n) {
-        const cd b0 = col[0], b1 = col[n];
-        const cd z0 = zs[c], z1 = zs[c + 1];
-        re0 = fma(b0.x, z0.x, fma(-b0.y, z0.y, re0));
-        im0 = fma(b0.x, z0.y, fma(b0.y, z0.x, im0));
-        re1 = fma(b1.x, z1.x, fma(-b1.y, z1.y, re1));
-        im1 = fma(b1.x, z1.y, fma(b1.y, z1.x, im1));
+      for (; c + 8 <= e; c += 8, col += 8 * n) {
+        cd bv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) bv[k] = col[k * n];
+#pragma unroll
+        for (int k = 0; k < 8; k += 2) {
+          const cd z0 = zs[c + k], z1 = zs[c + k + 1];
+          re0 = fma(bv[k].x, z0.x, fma(-bv[k].y, z0.y, re0));
+          im0 = fma(bv[k].x, z0.y, fma(bv[k].y, z0.x, im0));
+          re1 = fma(bv[k + 1].x, z1.x, fma(-bv[k + 1].y, z1.y, re1));
+          im1 = fma(bv[k + 1].x, z1.y, fma(bv[k + 1].y, z1.x, im1));
+        }
       }
-      if (c < e) {
+      for (; c < e; ++c, col += n) {
         const cd b0 = col[0], z0 = zs[c];
         re0 = fma(b0.x, z0.x, fma(-b0.y, z0.y, re0));
         im0 = fma(b0.x, z0.y, fma(b0.y, z0.x, im0));
@@ -1164,12 +1195,12 @@ int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int
     if (op->nxh > 0) {
       {
         ScopedTiming tm(op, s, K_FORWARD);
-        hipLaunchKernelGGL(k_forward, dim3(nl), dim3(64 * kFwdWaves), 0, s, op->F.p, op->fwd_off.p, op->fwd_cols.p,
+        hipLaunchKernelGGL(op->kind == 0 ? k_forward<0> : k_forward<1>, dim3(nl), dim3(64 * kFwdWaves), 0, s, op->F.p, op->fwd_off.p, op->fwd_cols.p,
                            op->leaf_pos.p, op->leaf_n.p, op->perm.p, x, op->poff.p, op->ws_p.p, nl);
       }
       {
         ScopedTiming tm(op, s, K_REDUCE_FWD);
-        hipLaunchKernelGGL(k_reduce_segments, dim3((unsigned)((op->nxh + 255) / 256)), dim3(256), 0, s, op->ws_p.p,
+        hipLaunchKernelGGL(op->kind == 0 ? k_reduce_segments<0> : k_reduce_segments<1>, dim3((unsigned)((op->nxh + 255) / 256)), dim3(256), 0, s, op->ws_p.p,
                            op->poff.p, op->out_seg.p, op->seg_start.p, op->seg_leaf0.p, op->seg_nleaf.p, op->seg_col.p,
                            op->nxh, op->ws_xh.p);
       }
@@ -1192,7 +1223,7 @@ int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int
     }
     {
       ScopedTiming tm(op, s, K_BACKWARD);
-      hipLaunchKernelGGL(k_backward, dim3(nl), dim3(64 * kBwdWaves), 0, s, op->B.p, op->bwd_off.p, op->bwd_cols.p,
+      hipLaunchKernelGGL(op->kind == 0 ? k_backward<0> : k_backward<1>, dim3(nl), dim3(64 * kBwdWaves), 0, s, op->B.p, op->bwd_off.p, op->bwd_cols.p,
                          op->zoff.p, op->zmap.p, op->leaf_pos.p, op->leaf_n.p, op->perm.p, zsrc, x, y, nl);
     }
   }

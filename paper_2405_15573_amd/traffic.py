@@ -1,0 +1,85 @@
+"""HBM traffic per kernel launch from two rocprofv3 counter runs.
+
+rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE each write a counter_collection.csv with
+one row per dispatch and counter (values in KiB).  Each counter is scaled by what it
+reads for a plain device copy of known size (a 1 GiB copy run in the same program), so
+that the result is in bytes of the same scale as the algorithmic byte counts.
+
+    python -m paper_2405_15573_amd.traffic FETCH.csv WRITE.csv --n 262144 -o out.json
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 1 << 30
+
+
+def kernel_source_sha256() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(HERE, "csrc", "uhm.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def _short(name: str) -> str:
+    base = name.split("(")[0]
+    base = base.replace("(anonymous namespace)::", "")
+    return base
+
+
+def per_kernel(path: str, counter: str) -> dict:
+    vals = defaultdict(list)
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            vals[_short(row["Kernel_Name"])].append(float(row["Counter_Value"]))
+    return vals
+
+
+def summarize(fetch_csv: str, write_csv: str) -> dict:
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    copy_f = [v for k, lst in fetch.items() if "copy" in k.lower() or "elementwise" in k.lower() for v in lst]
+    copy_w = [v for k, lst in write.items() if "copy" in k.lower() or "elementwise" in k.lower() for v in lst]
+    if not copy_f or not copy_w:
+        raise RuntimeError("no copy kernel found for calibration")
+    # the largest copy dispatches are the 1 GiB calibration copies
+    cf = sorted(copy_f)[-1] * 1024.0
+    cw = sorted(copy_w)[-1] * 1024.0
+    sf, sw = COPY_BYTES / cf, COPY_BYTES / cw
+    out = {}
+    for k in set(fetch) | set(write):
+        if not k.startswith("k_"):
+            continue
+        f = sum(fetch.get(k, [0.0])) / max(1, len(fetch.get(k, [])))
+        w = sum(write.get(k, [0.0])) / max(1, len(write.get(k, [])))
+        out[k] = {"fetch_bytes": f * 1024.0 * sf, "write_bytes": w * 1024.0 * sw,
+                  "bytes": f * 1024.0 * sf + w * 1024.0 * sw, "dispatches": len(fetch.get(k, []))}
+    return {"copy_fetch_scale": sf, "copy_write_scale": sw, "kernels": out}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("fetch_csv")
+    ap.add_argument("write_csv")
+    ap.add_argument("--n", type=int, required=True)
+    ap.add_argument("-o", "--out", required=True)
+    a = ap.parse_args()
+    s = summarize(a.fetch_csv, a.write_csv)
+    s["n"] = a.n
+    s["source_sha256"] = kernel_source_sha256()
+    s["bytes_per_launch"] = {k: v["bytes"] for k, v in s["kernels"].items()}
+    with open(a.out, "w") as f:
+        json.dump(s, f, indent=1)
+    print(json.dumps(s["bytes_per_launch"]))
+
+
+if __name__ == "__main__":
+    main()
