@@ -26,47 +26,126 @@
 //
 // Every index the kernels use comes from arrays this file builds after validating the
 // host image, so device accesses stay inside the allocations by construction.
-#include <hip/hip_runtime.h>
+#include "uhm_internal.h"
 
-#include <algorithm>
-#include <cstdint>
-#include <cstdio>
-#include <cstring>
-#include <memory>
-#include <new>
-#include <string>
-#include <vector>
-
-#include "uhm.h"
-
-namespace {
+namespace uhm_detail {
 
 thread_local std::string g_err;
 
-int fail(int code, const std::string& msg) {
-  g_err = msg;
-  return code;
+const char* const kKernelNames[K_COUNT] = {
+    "k_forward", "k_reduce_segments", "k_coupling", "k_reduce_coupling", "k_backward",
+    "k_lp_gather", "k_lp_forward", "k_lp_reduce_segments", "k_lp_coupling", "k_lp_reduce_coupling",
+    "k_lp_backward", "k_lp_scatter"};
+
+int check_tree(int64_t n, const int64_t* perm, int32_t nc, const int64_t* off, const int64_t* size,
+               const int32_t* parent, TreeInfo& T) {
+  if (n < 1 || n > INT32_MAX) return fail(UHM_EINVAL, "n must be in [1, 2^31)");
+  if (!perm || !off || !size || !parent || nc < 1) return fail(UHM_EINVAL, "null cluster tree array");
+  std::vector<char> seen(n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (perm[i] < 0 || perm[i] >= n || seen[perm[i]]) return fail(UHM_EINVAL, "perm is not a permutation");
+    seen[perm[i]] = 1;
+  }
+  int root = -1;
+  std::vector<int32_t> nchild(nc, 0);
+  for (int32_t c = 0; c < nc; ++c) {
+    if (size[c] < 1 || off[c] < 0 || off[c] + size[c] > n) return fail(UHM_EINVAL, "cluster range out of [0, n)");
+    if (parent[c] < 0) {
+      if (root >= 0) return fail(UHM_EINVAL, "more than one root cluster");
+      root = c;
+      if (off[c] != 0 || size[c] != n) return fail(UHM_EINVAL, "root must cover [0, n)");
+    } else {
+      const int32_t p = parent[c];
+      if (p >= nc || p == c) return fail(UHM_EINVAL, "bad parent index");
+      if (off[c] < off[p] || off[c] + size[c] > off[p] + size[p]) return fail(UHM_EINVAL, "child outside parent");
+      nchild[p]++;
+    }
+  }
+  if (root < 0) return fail(UHM_EINVAL, "no root cluster");
+  // children partition their parent
+  std::vector<std::vector<int32_t>> kids(nc);
+  for (int32_t c = 0; c < nc; ++c)
+    if (parent[c] >= 0) kids[parent[c]].push_back(c);
+  for (int32_t c = 0; c < nc; ++c) {
+    if (kids[c].empty()) continue;
+    std::sort(kids[c].begin(), kids[c].end(), [&](int32_t a, int32_t b) { return off[a] < off[b]; });
+    int64_t pos = off[c];
+    for (int32_t k : kids[c]) {
+      if (off[k] != pos) return fail(UHM_EINVAL, "children do not partition their parent");
+      pos += size[k];
+    }
+    if (pos != off[c] + size[c]) return fail(UHM_EINVAL, "children do not partition their parent");
+  }
+  T.n = n;
+  T.nc = nc;
+  for (int32_t c = 0; c < nc; ++c)
+    if (nchild[c] == 0) T.leaves.push_back(c);
+  std::sort(T.leaves.begin(), T.leaves.end(), [&](int32_t a, int32_t b) { return off[a] < off[b]; });
+  int64_t pos = 0;
+  for (int32_t l : T.leaves) {
+    if (off[l] != pos) return fail(UHM_EINVAL, "leaves do not tile [0, n)");
+    if (size[l] > kLeafMax) return fail(UHM_ENOTSUP, "leaf larger than 64 points");
+    pos += size[l];
+  }
+  if (pos != n) return fail(UHM_EINVAL, "leaves do not tile [0, n)");
+  const int32_t nl = (int32_t)T.leaves.size();
+  std::vector<int64_t> loff(nl);
+  for (int32_t i = 0; i < nl; ++i) loff[i] = off[T.leaves[i]];
+  T.leaf_first.assign(nc, 0);
+  T.leaf_cnt.assign(nc, 0);
+  for (int32_t c = 0; c < nc; ++c) {
+    const int32_t a = (int32_t)(std::lower_bound(loff.begin(), loff.end(), off[c]) - loff.begin());
+    const int32_t b = (int32_t)(std::lower_bound(loff.begin(), loff.end(), off[c] + size[c]) - loff.begin());
+    T.leaf_first[c] = a;
+    T.leaf_cnt[c] = b - a;
+  }
+  T.anc.resize(nl);
+  for (int32_t i = 0; i < nl; ++i) {
+    std::vector<int32_t>& a = T.anc[i];
+    int32_t c = T.leaves[i];
+    int guard = 0;
+    while (c >= 0) {
+      a.push_back(c);
+      c = parent[c];
+      if (++guard > nc) return fail(UHM_EINVAL, "cycle in the parent array");
+    }
+    std::reverse(a.begin(), a.end());
+  }
+  return UHM_OK;
 }
 
-#define UHM_HIP(call)                                                                        \
-  do {                                                                                       \
-    hipError_t e_ = (call);                                                                  \
-    if (e_ != hipSuccess) {                                                                  \
-      return fail(e_ == hipErrorOutOfMemory ? UHM_ENOMEM : UHM_EHIP,                         \
-                  std::string(#call) + ": " + hipGetErrorString(e_));                       \
-    }                                                                                        \
-  } while (0)
+hipEvent_t get_event(uhm_op* op) {
+  if (!op->free_events.empty()) {
+    hipEvent_t e = op->free_events.back();
+    op->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
 
-constexpr int kLeafMax = 64;     // leaf size bound: one lane per leaf row
-constexpr int kTile = 64;        // forward-panel tile width (one lane per column)
-constexpr int kRowChunk = 64;    // coupling row chunk (one lane per row)
-constexpr int kCoupCols = 256;   // coupling columns per wavefront tile
-constexpr int kFwdWaves = 4;
-constexpr int kBwdWaves = 4;
-constexpr int kBwdChunk = 512;   // z entries staged in LDS per round
-constexpr int kCoupWaves = 4;
+int common_tree_upload(uhm_op* op, const TreeInfo& T, const int64_t* perm, const int64_t* off, const int64_t* size,
+                       hipStream_t s) {
+  std::vector<int32_t> p32(T.n), lp(T.leaves.size()), ln(T.leaves.size());
+  for (int64_t i = 0; i < T.n; ++i) p32[i] = (int32_t)perm[i];
+  for (size_t i = 0; i < T.leaves.size(); ++i) {
+    lp[i] = (int32_t)off[T.leaves[i]];
+    ln[i] = (int32_t)size[T.leaves[i]];
+  }
+  int rc;
+  if ((rc = op->perm.upload(p32, s)) || (rc = op->leaf_pos.upload(lp, s)) || (rc = op->leaf_n.upload(ln, s))) return rc;
+  UHM_HIP(hipStreamSynchronize(s));
+  op->n = T.n;
+  op->nleaves = (int32_t)T.leaves.size();
+  return UHM_OK;
+}
 
-using cd = double2;
+}  // namespace uhm_detail
+
+using namespace uhm_detail;
+
+namespace {
 
 // ------------------------------------------------------------------ device kernels
 
@@ -159,13 +238,7 @@ __global__ __launch_bounds__(256) void k_reduce_segments(
   out[e] = make_double2(re, im);
 }
 
-struct CoupTile {
-  int64_t s_base;     // element offset of the tile's first column
-  int32_t h;          // rows in the chunk (<= 64)
-  int32_t ncols;      // columns in the tile
-  int32_t first_blk;  // index into the block list of the tile's first column
-  int32_t first_col;  // column within that block
-};
+
 
 // part[tile][r] = sum_c S_chunk[r, c] * xh[src(c)] over the tile's columns.
 __global__ __launch_bounds__(64 * kCoupWaves) void k_coupling(
@@ -295,301 +368,6 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_backward(
 
 // ------------------------------------------------------------------ host structures
 
-template <class T>
-struct DevArray {
-  T* p = nullptr;
-  int64_t n = 0;
-  ~DevArray() {
-    if (p) (void)hipFree(p);
-  }
-  int alloc(int64_t count) {
-    n = count;
-    if (count == 0) return UHM_OK;
-    hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)count);
-    if (e != hipSuccess) {
-      p = nullptr;
-      return fail(e == hipErrorOutOfMemory ? UHM_ENOMEM : UHM_EHIP,
-                  std::string("hipMalloc(") + std::to_string(sizeof(T) * (size_t)count) + " B): " + hipGetErrorString(e));
-    }
-    return UHM_OK;
-  }
-  int upload(const std::vector<T>& v, hipStream_t s) {
-    int rc = alloc((int64_t)v.size());
-    if (rc) return rc;
-    if (!v.empty()) UHM_HIP(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
-    return UHM_OK;
-  }
-  size_t bytes() const { return sizeof(T) * (size_t)n; }
-};
-
-// Streams host-packed data into a device array through two pinned staging buffers.
-struct Stager {
-  cd* dev = nullptr;
-  int64_t total = 0, written = 0;
-  hipStream_t s = nullptr;
-  cd* host[2] = {nullptr, nullptr};
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  bool pending[2] = {false, false};
-  int64_t cap = 0, fill = 0;
-  int cur = 0;
-  int err = UHM_OK;
-
-  int init(cd* d, int64_t tot, hipStream_t st) {
-    dev = d;
-    total = tot;
-    s = st;
-    cap = std::max<int64_t>(1, std::min<int64_t>(tot, (int64_t)(64 << 20) / (int64_t)sizeof(cd)));
-    for (int b = 0; b < 2; ++b) {
-      UHM_HIP(hipHostMalloc(reinterpret_cast<void**>(&host[b]), sizeof(cd) * (size_t)cap, hipHostMallocDefault));
-      UHM_HIP(hipEventCreateWithFlags(&ev[b], hipEventDisableTiming));
-    }
-    return UHM_OK;
-  }
-  // Room for k <= cap elements in the current staging buffer.
-  cd* span(int64_t k) {
-    if (fill + k > cap) flush();
-    cd* r = host[cur] + fill;
-    fill += k;
-    return r;
-  }
-  void flush() {
-    if (fill == 0 || err) return;
-    if (written + fill > total) {
-      err = fail(UHM_EINVAL, "internal: staged more elements than allocated");
-      return;
-    }
-    hipError_t e = hipMemcpyAsync(dev + written, host[cur], sizeof(cd) * (size_t)fill, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipEventRecord(ev[cur], s);
-    if (e != hipSuccess) {
-      err = fail(UHM_EHIP, std::string("staged copy: ") + hipGetErrorString(e));
-      return;
-    }
-    pending[cur] = true;
-    written += fill;
-    fill = 0;
-    cur ^= 1;
-    if (pending[cur]) {
-      e = hipEventSynchronize(ev[cur]);
-      pending[cur] = false;
-      if (e != hipSuccess) err = fail(UHM_EHIP, std::string("staged copy sync: ") + hipGetErrorString(e));
-    }
-  }
-  int finish() {
-    flush();
-    for (int b = 0; b < 2; ++b)
-      if (pending[b]) {
-        (void)hipEventSynchronize(ev[b]);
-        pending[b] = false;
-      }
-    if (!err && written != total) err = fail(UHM_EINVAL, "internal: staged element count mismatch");
-    return err;
-  }
-  ~Stager() {
-    for (int b = 0; b < 2; ++b) {
-      if (pending[b]) (void)hipEventSynchronize(ev[b]);
-      if (host[b]) (void)hipHostFree(host[b]);
-      if (ev[b]) (void)hipEventDestroy(ev[b]);
-    }
-  }
-};
-
-struct TreeInfo {
-  int64_t n = 0;
-  int32_t nc = 0;
-  std::vector<int32_t> leaves;              // leaf cluster ids, by position
-  std::vector<int32_t> leaf_first, leaf_cnt;  // per cluster: its leaves in `leaves`
-  std::vector<std::vector<int32_t>> anc;    // per leaf: ancestors, root first, leaf last
-};
-
-int check_tree(int64_t n, const int64_t* perm, int32_t nc, const int64_t* off, const int64_t* size,
-               const int32_t* parent, TreeInfo& T) {
-  if (n < 1 || n > INT32_MAX) return fail(UHM_EINVAL, "n must be in [1, 2^31)");
-  if (!perm || !off || !size || !parent || nc < 1) return fail(UHM_EINVAL, "null cluster tree array");
-  std::vector<char> seen(n, 0);
-  for (int64_t i = 0; i < n; ++i) {
-    if (perm[i] < 0 || perm[i] >= n || seen[perm[i]]) return fail(UHM_EINVAL, "perm is not a permutation");
-    seen[perm[i]] = 1;
-  }
-  int root = -1;
-  std::vector<int32_t> nchild(nc, 0);
-  for (int32_t c = 0; c < nc; ++c) {
-    if (size[c] < 1 || off[c] < 0 || off[c] + size[c] > n) return fail(UHM_EINVAL, "cluster range out of [0, n)");
-    if (parent[c] < 0) {
-      if (root >= 0) return fail(UHM_EINVAL, "more than one root cluster");
-      root = c;
-      if (off[c] != 0 || size[c] != n) return fail(UHM_EINVAL, "root must cover [0, n)");
-    } else {
-      const int32_t p = parent[c];
-      if (p >= nc || p == c) return fail(UHM_EINVAL, "bad parent index");
-      if (off[c] < off[p] || off[c] + size[c] > off[p] + size[p]) return fail(UHM_EINVAL, "child outside parent");
-      nchild[p]++;
-    }
-  }
-  if (root < 0) return fail(UHM_EINVAL, "no root cluster");
-  // children partition their parent
-  std::vector<std::vector<int32_t>> kids(nc);
-  for (int32_t c = 0; c < nc; ++c)
-    if (parent[c] >= 0) kids[parent[c]].push_back(c);
-  for (int32_t c = 0; c < nc; ++c) {
-    if (kids[c].empty()) continue;
-    std::sort(kids[c].begin(), kids[c].end(), [&](int32_t a, int32_t b) { return off[a] < off[b]; });
-    int64_t pos = off[c];
-    for (int32_t k : kids[c]) {
-      if (off[k] != pos) return fail(UHM_EINVAL, "children do not partition their parent");
-      pos += size[k];
-    }
-    if (pos != off[c] + size[c]) return fail(UHM_EINVAL, "children do not partition their parent");
-  }
-  T.n = n;
-  T.nc = nc;
-  for (int32_t c = 0; c < nc; ++c)
-    if (nchild[c] == 0) T.leaves.push_back(c);
-  std::sort(T.leaves.begin(), T.leaves.end(), [&](int32_t a, int32_t b) { return off[a] < off[b]; });
-  int64_t pos = 0;
-  for (int32_t l : T.leaves) {
-    if (off[l] != pos) return fail(UHM_EINVAL, "leaves do not tile [0, n)");
-    if (size[l] > kLeafMax) return fail(UHM_ENOTSUP, "leaf larger than 64 points");
-    pos += size[l];
-  }
-  if (pos != n) return fail(UHM_EINVAL, "leaves do not tile [0, n)");
-  const int32_t nl = (int32_t)T.leaves.size();
-  std::vector<int64_t> loff(nl);
-  for (int32_t i = 0; i < nl; ++i) loff[i] = off[T.leaves[i]];
-  T.leaf_first.assign(nc, 0);
-  T.leaf_cnt.assign(nc, 0);
-  for (int32_t c = 0; c < nc; ++c) {
-    const int32_t a = (int32_t)(std::lower_bound(loff.begin(), loff.end(), off[c]) - loff.begin());
-    const int32_t b = (int32_t)(std::lower_bound(loff.begin(), loff.end(), off[c] + size[c]) - loff.begin());
-    T.leaf_first[c] = a;
-    T.leaf_cnt[c] = b - a;
-  }
-  T.anc.resize(nl);
-  for (int32_t i = 0; i < nl; ++i) {
-    std::vector<int32_t>& a = T.anc[i];
-    int32_t c = T.leaves[i];
-    int guard = 0;
-    while (c >= 0) {
-      a.push_back(c);
-      c = parent[c];
-      if (++guard > nc) return fail(UHM_EINVAL, "cycle in the parent array");
-    }
-    std::reverse(a.begin(), a.end());
-  }
-  return UHM_OK;
-}
-
-struct Timer {
-  const char* name;
-  double total_ms = 0.0;
-  int64_t launches = 0;
-};
-
-struct PendingEvent {
-  hipEvent_t a, b;
-  int kernel;
-};
-
-}  // namespace
-
-struct uhm_op {
-  int kind = 0;  // 0 UH, 1 H
-  int storage = UHM_C128;
-  int64_t n = 0;
-  int32_t nleaves = 0;
-  uhm_op_info info{};
-
-  DevArray<int32_t> perm, leaf_pos, leaf_n;
-  // forward panels and partial sums
-  DevArray<cd> F;
-  DevArray<int64_t> fwd_off, poff;
-  DevArray<int32_t> fwd_cols;
-  int64_t p_len = 0;
-  // segments of the rank-space vector (u_sigma per cluster, or Y_b^* v per block)
-  DevArray<int32_t> out_seg, seg_leaf0, seg_nleaf, seg_col;
-  DevArray<int64_t> seg_start;
-  int64_t nxh = 0;
-  // couplings
-  DevArray<cd> S;
-  DevArray<CoupTile> ctiles;
-  DevArray<int2> cblk;
-  DevArray<int32_t> yh_grp, grp_t0, grp_nt;
-  DevArray<int64_t> grp_start;
-  int32_t nctiles = 0;
-  int64_t nyh = 0;
-  // backward panels
-  DevArray<cd> B;
-  DevArray<int64_t> bwd_off, zoff;
-  DevArray<int32_t> bwd_cols, zmap;
-  // workspace
-  DevArray<cd> ws_p, ws_xh, ws_part, ws_yh;
-  // timing
-  bool timing = false;
-  std::vector<Timer> timers;
-  std::vector<PendingEvent> pending;
-  std::vector<hipEvent_t> free_events;
-
-  ~uhm_op() {
-    for (auto& e : pending) {
-      (void)hipEventDestroy(e.a);
-      (void)hipEventDestroy(e.b);
-    }
-    for (auto e : free_events) (void)hipEventDestroy(e);
-  }
-};
-
-namespace {
-
-enum { K_FORWARD = 0, K_REDUCE_FWD, K_COUPLING, K_REDUCE_COUP, K_BACKWARD, K_COUNT };
-const char* kKernelNames[K_COUNT] = {"k_forward", "k_reduce_segments", "k_coupling", "k_reduce_coupling",
-                                     "k_backward"};
-
-hipEvent_t get_event(uhm_op* op) {
-  if (!op->free_events.empty()) {
-    hipEvent_t e = op->free_events.back();
-    op->free_events.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-struct ScopedTiming {
-  uhm_op* op;
-  hipStream_t s;
-  int k;
-  hipEvent_t a = nullptr;
-  ScopedTiming(uhm_op* o, hipStream_t st, int kernel) : op(o), s(st), k(kernel) {
-    if (op->timing) {
-      a = get_event(op);
-      if (a) (void)hipEventRecord(a, s);
-    }
-  }
-  ~ScopedTiming() {
-    if (!a) return;
-    hipEvent_t b = get_event(op);
-    if (!b) return;
-    (void)hipEventRecord(b, s);
-    op->pending.push_back({a, b, k});
-  }
-};
-
-int common_tree_upload(uhm_op* op, const TreeInfo& T, const int64_t* perm, const int64_t* off, const int64_t* size,
-                       hipStream_t s) {
-  std::vector<int32_t> p32(T.n), lp(T.leaves.size()), ln(T.leaves.size());
-  for (int64_t i = 0; i < T.n; ++i) p32[i] = (int32_t)perm[i];
-  for (size_t i = 0; i < T.leaves.size(); ++i) {
-    lp[i] = (int32_t)off[T.leaves[i]];
-    ln[i] = (int32_t)size[T.leaves[i]];
-  }
-  int rc;
-  if ((rc = op->perm.upload(p32, s)) || (rc = op->leaf_pos.upload(lp, s)) || (rc = op->leaf_n.upload(ln, s))) return rc;
-  UHM_HIP(hipStreamSynchronize(s));
-  op->n = T.n;
-  op->nleaves = (int32_t)T.leaves.size();
-  return UHM_OK;
-}
-
 // A column source of a forward or backward panel: `len` columns of a column-major
 // matrix `src` (rows `nrows`), starting at row `row0` for this leaf.
 struct PanelSeg {
@@ -656,7 +434,6 @@ int upload_segments(uhm_op* op, const std::vector<SegDesc>& segs, int64_t nout, 
   return UHM_OK;
 }
 
-bool in_bounds(int64_t off, int64_t count, int64_t len) { return off >= 0 && count >= 0 && off + count <= len; }
 
 int grow_workspace(uhm_op* op) {
   // single-RHS workspace; columns are processed one at a time
@@ -754,7 +531,8 @@ const char* uhm_last_error(void) { return g_err.c_str(); }
 int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream, uhm_op** out) {
   if (!h || !out) return fail(UHM_EINVAL, "null argument");
   *out = nullptr;
-  if (storage != UHM_C128) return fail(UHM_ENOTSUP, "storage precision not available in this build");
+  if (storage != UHM_C128 && storage != UHM_C64 && storage != UHM_BF16PAIR)
+    return fail(UHM_EINVAL, "unknown storage precision");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   TreeInfo T;
   int rc = check_tree(h->n, h->perm, h->nclusters, h->off, h->size, h->parent, T);
@@ -789,6 +567,11 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
   op->kind = 0;
   op->storage = storage;
   if ((rc = common_tree_upload(op.get(), T, h->perm, h->off, h->size, s))) return rc;
+  if (storage != UHM_C128) {
+    if ((rc = lowp_upload(h, storage, s, T, op.get()))) return rc;
+    *out = op.release();
+    return UHM_OK;
+  }
   const int32_t nl = op->nleaves;
   const cd* U = reinterpret_cast<const cd*>(h->U);
   const cd* V = reinterpret_cast<const cd*>(h->V);
@@ -1182,12 +965,13 @@ int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int
   if (ldx < op->n || ldy < op->n) return fail(UHM_EINVAL, "leading dimension smaller than n");
   const char* xb = static_cast<const char*>(X);
   const char* yb = static_cast<const char*>(Y);
-  const size_t es = sizeof(cd);
+  const size_t es = op->storage == UHM_C128 ? sizeof(cd) : sizeof(float2);
   if (xb < yb + (size_t)((nrhs - 1) * ldy + op->n) * es && yb < xb + (size_t)((nrhs - 1) * ldx + op->n) * es)
     return fail(UHM_EINVAL, "X and Y overlap");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (op->lp) return lowp_matvec(op, X, ldx, Y, ldy, nrhs, s);
   int rc = grow_workspace(op);
   if (rc) return rc;
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const int nl = op->nleaves;
   for (int32_t r = 0; r < nrhs; ++r) {
     const cd* x = static_cast<const cd*>(X) + (int64_t)r * ldx;

@@ -1,0 +1,276 @@
+// Internal declarations shared by the translation units of libuhm.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "uhm.h"
+
+namespace uhm_detail {
+
+extern thread_local std::string g_err;
+
+inline int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define UHM_HIP(call)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? UHM_ENOMEM : UHM_EHIP,                         \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                       \
+    }                                                                                        \
+  } while (0)
+
+constexpr int kLeafMax = 64;     // leaf size bound: one lane per leaf row
+constexpr int kTile = 64;        // forward-panel tile width (one lane per column)
+constexpr int kRowChunk = 64;    // coupling row chunk (one lane per row)
+constexpr int kCoupCols = 256;   // coupling columns per wavefront tile
+constexpr int kFwdWaves = 4;
+constexpr int kBwdWaves = 4;
+constexpr int kBwdChunk = 512;   // z entries staged in LDS per round
+constexpr int kCoupWaves = 4;
+
+using cd = double2;
+struct CoupTile {
+  int64_t s_base;     // element offset of the tile's first column
+  int32_t h;          // rows in the chunk (<= 64)
+  int32_t ncols;      // columns in the tile
+  int32_t first_blk;  // index into the block list of the tile's first column
+  int32_t first_col;  // column within that block
+};
+
+template <class T>
+struct DevArray {
+  T* p = nullptr;
+  int64_t n = 0;
+  ~DevArray() {
+    if (p) (void)hipFree(p);
+  }
+  int alloc(int64_t count) {
+    n = count;
+    if (count == 0) return UHM_OK;
+    hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)count);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return fail(e == hipErrorOutOfMemory ? UHM_ENOMEM : UHM_EHIP,
+                  std::string("hipMalloc(") + std::to_string(sizeof(T) * (size_t)count) + " B): " + hipGetErrorString(e));
+    }
+    return UHM_OK;
+  }
+  int upload(const std::vector<T>& v, hipStream_t s) {
+    int rc = alloc((int64_t)v.size());
+    if (rc) return rc;
+    if (!v.empty()) UHM_HIP(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+    return UHM_OK;
+  }
+  size_t bytes() const { return sizeof(T) * (size_t)n; }
+};
+
+// Streams host-packed data into a device array through two pinned staging buffers.
+template <class E>
+struct StagerT {
+  E* dev = nullptr;
+  int64_t total = 0, written = 0;
+  hipStream_t s = nullptr;
+  E* host[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool pending[2] = {false, false};
+  int64_t cap = 0, fill = 0;
+  int cur = 0;
+  int err = UHM_OK;
+
+  int init(E* d, int64_t tot, hipStream_t st) {
+    dev = d;
+    total = tot;
+    s = st;
+    cap = std::max<int64_t>(1, std::min<int64_t>(tot, (int64_t)(64 << 20) / (int64_t)sizeof(E)));
+    for (int b = 0; b < 2; ++b) {
+      UHM_HIP(hipHostMalloc(reinterpret_cast<void**>(&host[b]), sizeof(E) * (size_t)cap, hipHostMallocDefault));
+      UHM_HIP(hipEventCreateWithFlags(&ev[b], hipEventDisableTiming));
+    }
+    return UHM_OK;
+  }
+  // Room for k <= cap elements in the current staging buffer.
+  E* span(int64_t k) {
+    if (fill + k > cap) flush();
+    E* r = host[cur] + fill;
+    fill += k;
+    return r;
+  }
+  void flush() {
+    if (fill == 0 || err) return;
+    if (written + fill > total) {
+      err = fail(UHM_EINVAL, "internal: staged more elements than allocated");
+      return;
+    }
+    hipError_t e = hipMemcpyAsync(dev + written, host[cur], sizeof(E) * (size_t)fill, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[cur], s);
+    if (e != hipSuccess) {
+      err = fail(UHM_EHIP, std::string("staged copy: ") + hipGetErrorString(e));
+      return;
+    }
+    pending[cur] = true;
+    written += fill;
+    fill = 0;
+    cur ^= 1;
+    if (pending[cur]) {
+      e = hipEventSynchronize(ev[cur]);
+      pending[cur] = false;
+      if (e != hipSuccess) err = fail(UHM_EHIP, std::string("staged copy sync: ") + hipGetErrorString(e));
+    }
+  }
+  int finish() {
+    flush();
+    for (int b = 0; b < 2; ++b)
+      if (pending[b]) {
+        (void)hipEventSynchronize(ev[b]);
+        pending[b] = false;
+      }
+    if (!err && written != total) err = fail(UHM_EINVAL, "internal: staged element count mismatch");
+    return err;
+  }
+  ~StagerT() {
+    for (int b = 0; b < 2; ++b) {
+      if (pending[b]) (void)hipEventSynchronize(ev[b]);
+      if (host[b]) (void)hipHostFree(host[b]);
+      if (ev[b]) (void)hipEventDestroy(ev[b]);
+    }
+  }
+};
+
+using Stager = StagerT<cd>;
+
+struct TreeInfo {
+  int64_t n = 0;
+  int32_t nc = 0;
+  std::vector<int32_t> leaves;              // leaf cluster ids, by position
+  std::vector<int32_t> leaf_first, leaf_cnt;  // per cluster: its leaves in `leaves`
+  std::vector<std::vector<int32_t>> anc;    // per leaf: ancestors, root first, leaf last
+};
+
+int check_tree(int64_t n, const int64_t* perm, int32_t nc, const int64_t* off, const int64_t* size,
+               const int32_t* parent, TreeInfo& T);
+
+struct Timer {
+  const char* name;
+  double total_ms = 0.0;
+  int64_t launches = 0;
+};
+
+struct PendingEvent {
+  hipEvent_t a, b;
+  int kernel;
+};
+
+struct LowpOp;  // low-precision (MFMA) operator state, defined with its kernels
+void lowp_delete(LowpOp* lp);
+
+}  // namespace uhm_detail
+
+struct uhm_op {
+  using cd = uhm_detail::cd;
+  template <class T>
+  using DevArray = uhm_detail::DevArray<T>;
+  using CoupTile = uhm_detail::CoupTile;
+  using Timer = uhm_detail::Timer;
+  using PendingEvent = uhm_detail::PendingEvent;
+  int kind = 0;  // 0 UH, 1 H
+  int storage = UHM_C128;
+  int64_t n = 0;
+  int32_t nleaves = 0;
+  uhm_op_info info{};
+
+  DevArray<int32_t> perm, leaf_pos, leaf_n;
+  // forward panels and partial sums
+  DevArray<cd> F;
+  DevArray<int64_t> fwd_off, poff;
+  DevArray<int32_t> fwd_cols;
+  int64_t p_len = 0;
+  // segments of the rank-space vector (u_sigma per cluster, or Y_b^* v per block)
+  DevArray<int32_t> out_seg, seg_leaf0, seg_nleaf, seg_col;
+  DevArray<int64_t> seg_start;
+  int64_t nxh = 0;
+  // couplings
+  DevArray<cd> S;
+  DevArray<CoupTile> ctiles;
+  DevArray<int2> cblk;
+  DevArray<int32_t> yh_grp, grp_t0, grp_nt;
+  DevArray<int64_t> grp_start;
+  int32_t nctiles = 0;
+  int64_t nyh = 0;
+  // backward panels
+  DevArray<cd> B;
+  DevArray<int64_t> bwd_off, zoff;
+  DevArray<int32_t> bwd_cols, zmap;
+  // workspace
+  DevArray<cd> ws_p, ws_xh, ws_part, ws_yh;
+  // timing
+  bool timing = false;
+  std::vector<Timer> timers;
+  std::vector<PendingEvent> pending;
+  std::vector<hipEvent_t> free_events;
+
+  uhm_detail::LowpOp* lp = nullptr;
+
+  ~uhm_op() {
+    if (lp) uhm_detail::lowp_delete(lp);
+    for (auto& e : pending) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    for (auto e : free_events) (void)hipEventDestroy(e);
+  }
+};
+
+namespace uhm_detail {
+
+enum {
+  K_FORWARD = 0, K_REDUCE_FWD, K_COUPLING, K_REDUCE_COUP, K_BACKWARD,
+  K_LP_GATHER, K_LP_FORWARD, K_LP_REDUCE_FWD, K_LP_COUPLING, K_LP_REDUCE_COUP, K_LP_BACKWARD, K_LP_SCATTER,
+  K_COUNT
+};
+extern const char* const kKernelNames[K_COUNT];
+
+hipEvent_t get_event(uhm_op* op);
+
+struct ScopedTiming {
+  uhm_op* op;
+  hipStream_t s;
+  int k;
+  hipEvent_t a = nullptr;
+  ScopedTiming(uhm_op* o, hipStream_t st, int kernel) : op(o), s(st), k(kernel) {
+    if (op->timing) {
+      a = get_event(op);
+      if (a) (void)hipEventRecord(a, s);
+    }
+  }
+  ~ScopedTiming() {
+    if (!a) return;
+    hipEvent_t b = get_event(op);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    op->pending.push_back({a, b, k});
+  }
+};
+
+inline bool in_bounds(int64_t off, int64_t count, int64_t len) { return off >= 0 && count >= 0 && off + count <= len; }
+
+int common_tree_upload(uhm_op* op, const TreeInfo& T, const int64_t* perm, const int64_t* off, const int64_t* size,
+                       hipStream_t s);
+
+// Low-precision storage (complex64 or bf16 pairs): MFMA kernels, own device layout.
+int lowp_upload(const uhm_host_operator* h, uhm_storage storage, hipStream_t s, const TreeInfo& T, uhm_op* op);
+int lowp_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs, hipStream_t s);
+
+}  // namespace uhm_detail
