@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-h", action="store_true")
+    ap.add_argument("--no-lowp", action="store_true", help="skip the complex64 / bf16-pair multi-RHS forms")
+    ap.add_argument("--lowp-rhs", type=int, default=64)
     ap.add_argument("--parity-leaves", type=int, default=6)
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_sphere262k_c128.json"),
                     help="JSON file with counter-derived HBM bytes per launch (used only if it was taken on the "
@@ -156,6 +158,39 @@ def main():
         log(f"H MVP {t_h * 1e3:.3f} ms")
         dh.free()
 
+    lowp = None
+    if not args.no_lowp:
+        lowp = {}
+        M_uh = info["elems_forward"] + info["elems_coupling"] + info["elems_backward"] + info["elems_near"]
+        r = args.lowp_rhs
+        X64 = inputs.make_rhs(cloud.n, r, seed=args.seed + 7)
+        Xd = torch.from_numpy(np.ascontiguousarray(X64.T.astype(np.complex64))).to("cuda").t()
+        Yd = torch.empty((r, cloud.n), dtype=torch.complex64, device="cuda").t()
+        x1 = x.to(torch.complex64)
+        y1 = torch.empty_like(x1)
+        for st_name, peak_tf, e_bytes in (("c64", 157.3, 8), ("bf16pair", 2500.0, 4)):
+            tl = time.perf_counter()
+            dl = binding.upload(op, storage=st_name, stream=stream)
+            log(f"{st_name} upload {time.perf_counter() - tl:.1f} s")
+            t_r, k_r = time_products(torch, dl, Xd, Yd, max(5, args.steps // 5), 2, stream)
+            t_1, k_1 = time_products(torch, dl, x1, y1, args.steps, args.warmup, stream)
+            y1n = y1.cpu().numpy().astype(np.complex128)
+            err_vs_fp64 = float(np.linalg.norm(y1n - y_uh) / np.linalg.norm(y_uh))
+            flops = 8.0 * r * M_uh
+            bytes_r = e_bytes * M_uh + 8 * r * (2 * cloud.n + 4 * info["rank_space"])
+            lowp[st_name] = {
+                "nrhs": r, "ms_per_mvp": t_r * 1e3, "rhs_per_s": r / t_r,
+                "tflops": flops / t_r / 1e12, "mfma_peak_tflops": peak_tf, "mfma_frac": flops / t_r / 1e12 / peak_tf,
+                "gbs": bytes_r / t_r / 1e9, "hbm_frac": bytes_r / t_r / 1e9 / HBM_PEAK_GBS,
+                "kernels_ms": {k: v[0] for k, v in k_r.items()},
+                "single_rhs_ms": t_1 * 1e3, "single_rhs_gbs": (e_bytes * M_uh + 16 * cloud.n) / t_1 / 1e9,
+                "rel_err_vs_fp64": err_vs_fp64,
+            }
+            log(f"{st_name}: {r} RHS {t_r * 1e3:.3f} ms ({flops / t_r / 1e12:.1f} TFLOP/s), 1 RHS {t_1 * 1e3:.3f} ms, "
+                f"err vs FP64 {err_vs_fp64:.2e}")
+            dl.free()
+        del Xd, Yd
+
     cpu = None
     if not args.no_cpu:
         ncores = uniform.max_threads()
@@ -208,6 +243,7 @@ def main():
         "operator": {k: st[k] for k in ("nadm", "nden", "c_sp", "l_max", "k_max", "bytes_uh_c128", "bytes_h_c128")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "precision_forms": lowp,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -163,6 +163,48 @@ int uhm_upload_h(const uhm_host_hmatrix* h, uhm_storage storage, void* hip_strea
 int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs,
                void* hip_stream);
 
+/* Options of uhm_solve_gmres; a NULL pointer selects the defaults in brackets. */
+typedef struct {
+  int32_t restart;          /* Krylov dimension m of each GMRES(m) cycle [50] */
+  int32_t max_iterations;   /* cap on Krylov iterations per solve, all cycles and refinements [2000] */
+  int32_t max_refinements;  /* outer refinement steps when an inner operator is given [30] */
+  double inner_tol;         /* residual reduction asked of each inner solve of the refinement [1e-4] */
+} uhm_gmres_opts;
+
+/* What uhm_solve_gmres did. */
+typedef struct {
+  int32_t iterations;       /* Krylov iterations (products with the Krylov operator) */
+  int32_t restarts;         /* GMRES(m) cycles started after the first */
+  int32_t refinements;      /* outer refinement steps (0 without an inner operator) */
+  int32_t converged;        /* right-hand sides whose final true relative residual <= tol */
+  double rel_residual;      /* max over right-hand sides of ||b - A x||_2 / ||b||_2, FP64 operator */
+  double seconds_total;     /* wall clock of the solve (synchronized) */
+  double seconds_products;  /* of which spent in operator products */
+  double seconds_arnoldi;   /* of which spent in the orthogonalisation and updates */
+} uhm_gmres_info;
+
+/*
+ * Solve A X = B by restarted GMRES(m) (textbook GMRES with classical Gram-Schmidt
+ * applied twice, FP64 Krylov vectors, Givens least-squares), for nrhs right-hand sides
+ * at once, each with its own Krylov space.  X starts at zero and is overwritten.
+ *   op:    the operator A, complex128 storage (the true-residual operator).
+ *   inner: NULL for plain GMRES on op; otherwise an operator of the same matrix in
+ *          complex64 or bf16-pair storage, and the solve is mixed-precision iterative
+ *          refinement: r = B - A X with op (FP64), an inner GMRES(m) solves
+ *          A_inner D = r to inner_tol (products with `inner`, everything else FP64),
+ *          X += D, until max_j ||r_j|| / ||b_j|| <= tol.
+ * B (ldb >= n), X (ldx >= n): complex128 device arrays, n x nrhs column-major, user order.
+ * Synchronous on `hip_stream`; allocates its workspace ((m+1) n nrhs complex128 for the
+ * Krylov basis plus a few vectors) for the duration of the call.
+ * Returns UHM_OK when every right-hand side reaches tol, UHM_ENOCONV when the iteration
+ * or refinement cap is reached first (X holds the last iterate, *info is filled),
+ * UHM_EINVAL (bad arguments, n mismatch, op not complex128, inner not low precision),
+ * UHM_ENOMEM, UHM_EHIP.  Textbook GMRES (Saad and Schultz); the refinement follows
+ * Carson and Higham's GMRES-IR.
+ */
+int uhm_solve_gmres(uhm_op* op, uhm_op* inner, const void* B, int64_t ldb, void* X, int64_t ldx, int32_t nrhs,
+                    double tol, const uhm_gmres_opts* opts, uhm_gmres_info* info, void* hip_stream);
+
 /* Fill *info for an uploaded operator.  Errors: UHM_EINVAL. */
 int uhm_op_info_get(const uhm_op* op, uhm_op_info* info);
 

@@ -43,8 +43,18 @@ class OpInfo(ctypes.Structure):
                 ("elems_backward", I64), ("elems_near", I64), ("rank_space", I64), ("device_bytes", I64)]
 
 
-EXPORTS = ("uhm_upload", "uhm_upload_h", "uhm_matvec", "uhm_op_info_get", "uhm_set_timing", "uhm_kernel_times",
-           "uhm_free", "uhm_strerror", "uhm_last_error", "uhm_version")
+class GmresOpts(ctypes.Structure):
+    _fields_ = [("restart", I32), ("max_iterations", I32), ("max_refinements", I32), ("inner_tol", ctypes.c_double)]
+
+
+class GmresInfo(ctypes.Structure):
+    _fields_ = [("iterations", I32), ("restarts", I32), ("refinements", I32), ("converged", I32),
+                ("rel_residual", ctypes.c_double), ("seconds_total", ctypes.c_double),
+                ("seconds_products", ctypes.c_double), ("seconds_arnoldi", ctypes.c_double)]
+
+
+EXPORTS = ("uhm_upload", "uhm_upload_h", "uhm_matvec", "uhm_solve_gmres", "uhm_op_info_get", "uhm_set_timing",
+           "uhm_kernel_times", "uhm_free", "uhm_strerror", "uhm_last_error", "uhm_version")
 
 _LIB = None
 
@@ -63,6 +73,9 @@ def load_library(path: str = LIB_PATH):
     lib.uhm_upload_h.restype = ctypes.c_int
     lib.uhm_matvec.argtypes = [P, P, I64, P, I64, I32, P]
     lib.uhm_matvec.restype = ctypes.c_int
+    lib.uhm_solve_gmres.argtypes = [P, P, P, I64, P, I64, I32, ctypes.c_double, ctypes.POINTER(GmresOpts),
+                                    ctypes.POINTER(GmresInfo), P]
+    lib.uhm_solve_gmres.restype = ctypes.c_int
     lib.uhm_op_info_get.argtypes = [P, ctypes.POINTER(OpInfo)]
     lib.uhm_op_info_get.restype = ctypes.c_int
     lib.uhm_set_timing.argtypes = [P, ctypes.c_int]
@@ -259,3 +272,37 @@ def upload_h(op, storage: str = "c128", stream=None) -> DeviceOperator:
     sh, _ = _stream_handle(stream)
     _check(load_library().uhm_upload_h(ctypes.byref(h), STORAGE[storage], sh, ctypes.byref(out)), "uhm_upload_h")
     return DeviceOperator(out, "h", storage, h.n)
+
+
+def solve_gmres(op: DeviceOperator, b, tol: float, inner: DeviceOperator | None = None, restart: int = 50,
+                max_iterations: int = 2000, max_refinements: int = 30, inner_tol: float = 1e-4, x=None,
+                stream=None, raise_on_noconv: bool = True):
+    """Solve A X = B with GMRES(restart) (inner=None) or GMRES-IR with the low-precision
+    operator `inner`.  b: complex128 device tensor (n,) or (n, r).  Returns (x, info dict, code)."""
+    import torch
+    if op.storage != "c128":
+        raise ValueError("the residual operator must be complex128")
+    vec = b.dim() == 1
+    b2 = b.reshape(op.n, 1) if vec else b
+    if b2.dtype != torch.complex128:
+        raise ValueError("b must be complex128")
+    if b2.stride(0) != 1:
+        b2 = b2.t().contiguous().t()
+    r = b2.shape[1]
+    if x is None:
+        x2 = torch.empty((r, op.n), dtype=torch.complex128, device=b.device).t()
+    else:
+        x2 = x.reshape(op.n, 1) if x.dim() == 1 else x
+    ldb = b2.stride(1) if r > 1 else op.n
+    ldx = x2.stride(1) if r > 1 else op.n
+    o = GmresOpts(restart, max_iterations, max_refinements, inner_tol)
+    inf = GmresInfo()
+    sh, _ = _stream_handle(stream)
+    rc = load_library().uhm_solve_gmres(op.handle, inner.handle if inner is not None else None,
+                                        ctypes.c_void_p(b2.data_ptr()), ldb, ctypes.c_void_p(x2.data_ptr()), ldx, r,
+                                        float(tol), ctypes.byref(o), ctypes.byref(inf), sh)
+    info = {name: getattr(inf, name) for name, _ in GmresInfo._fields_}
+    if rc not in (UHM_OK, UHM_ENOCONV) or (rc == UHM_ENOCONV and raise_on_noconv):
+        raise UhmError(rc, "uhm_solve_gmres")
+    out = x if x is not None else (x2.reshape(op.n) if vec else x2)
+    return out, info, rc

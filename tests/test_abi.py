@@ -29,13 +29,16 @@ def test_library_exports_every_declared_symbol():
     assert lib.uhm_strerror(binding.UHM_EINVAL) == b"invalid argument"
 
 
+STRUCTS = (("uhm_host_operator", binding.HostOperator), ("uhm_host_hmatrix", binding.HostHMatrix),
+           ("uhm_op_info", binding.OpInfo), ("uhm_gmres_opts", binding.GmresOpts), ("uhm_gmres_info", binding.GmresInfo))
+
+
 def test_struct_layouts_match_header(tmp_path):
     """Every ctypes field offset equals offsetof() of the C struct compiled from uhm.h."""
     import ctypes
     import subprocess
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "uhm.h"', "int main(void) {"]
-    for cname, py in (("uhm_host_operator", binding.HostOperator), ("uhm_host_hmatrix", binding.HostHMatrix),
-                      ("uhm_op_info", binding.OpInfo)):
+    for cname, py in STRUCTS:
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
             lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
@@ -46,8 +49,7 @@ def test_struct_layouts_match_header(tmp_path):
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
                                                          check=True).stdout.split("\n") if l)
-    for cname, py in (("uhm_host_operator", binding.HostOperator), ("uhm_host_hmatrix", binding.HostHMatrix),
-                      ("uhm_op_info", binding.OpInfo)):
+    for cname, py in STRUCTS:
         assert int(got[cname]) == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)

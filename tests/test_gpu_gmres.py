@@ -1,0 +1,89 @@
+"""GMRES(m) and GMRES-IR on the GPU through the C-ABI, checked by the CPU oracle.
+
+The oracle's reference solution is the plain definition x* = A^{-1} b, from a dense LU
+solve of the assembled FP64 UH-matrix (numpy), and the true residual ||b - A x|| / ||b|| is
+recomputed with the oracle's block-wise product.
+"""
+import numpy as np
+import pytest
+
+from conftest import operator
+from oracle import uniform
+from paper_2405_15573_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    from paper_2405_15573_amd import binding
+    binding.load_library()
+    return torch
+
+
+def _solve(torch, op, b, tol, inner_storage=None, **kw):
+    from paper_2405_15573_amd import binding
+    dop = binding.upload(op)
+    inner = binding.upload(op, storage=inner_storage) if inner_storage else None
+    bt = torch.from_numpy(np.ascontiguousarray(b.T)).to("cuda").t()
+    x, info, rc = binding.solve_gmres(dop, bt, tol, inner=inner, **kw)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), info, rc
+
+
+@pytest.mark.parametrize("inner", [None, "c64", "bf16pair"])
+def test_gmres_solves_against_dense_solution(torch_dev, inner):
+    print(f"case gmres inner={inner}", flush=True)
+    cloud, op = operator()
+    o = vars(op)
+    b = inputs.make_rhs(cloud.n, 2, seed=31)
+    tol = 1e-8
+    x, info, rc = _solve(torch_dev, op, b, tol, inner, restart=50)
+    print(f"  {info}", flush=True)
+    assert rc == 0 and info["converged"] == 2
+    res = np.linalg.norm(b - uniform.uh_mvp(o, x), axis=0) / np.linalg.norm(b, axis=0)
+    assert res.max() <= tol * 1.01
+    assert abs(res.max() - info["rel_residual"]) <= 1e-3 * tol + 1e-14
+    a = uniform.assemble_uh(o)
+    xs = np.linalg.solve(a, b)
+    cond = np.linalg.cond(a)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= max(cond * tol, 1e-12)
+    if inner is not None:
+        assert info["refinements"] >= 1
+
+
+def test_gmres_restarts_and_ragged(torch_dev):
+    # restart 20 on a ragged cube cloud: several cycles (very short restarts stagnate on this
+    # indefinite Helmholtz system, a property of restarted GMRES)
+    cloud, op = operator(surface="cube", n=1300, seed=5)
+    b = inputs.make_rhs(cloud.n, 1, seed=32)
+    x, info, rc = _solve(torch_dev, op, b, 1e-8, None, restart=20)
+    assert rc == 0 and info["restarts"] >= 1
+    res = np.linalg.norm(b - uniform.uh_mvp(vars(op), x)) / np.linalg.norm(b)
+    assert res <= 1e-8 * 1.01
+
+
+def test_gmres_iteration_cap_reports_noconv(torch_dev):
+    from paper_2405_15573_amd import binding
+    cloud, op = operator()
+    b = inputs.make_rhs(cloud.n, 1, seed=33)
+    x, info, rc = _solve(torch_dev, op, b, 1e-12, None, restart=50, max_iterations=1)
+    # forced from the host: the cap stops the solve, X holds the last iterate
+    assert rc == binding.UHM_ENOCONV and info["iterations"] == 1 and info["converged"] == 0
+    res = np.linalg.norm(b - uniform.uh_mvp(vars(op), x)) / np.linalg.norm(b)
+    assert abs(res - info["rel_residual"]) <= 1e-10 and res < 1.0
+
+
+def test_gmres_batch_equals_alone(torch_dev):
+    """Each right-hand side has its own Krylov space: solving it alone or in a batch gives
+    the same iterate (same products, same reductions per column)."""
+    cloud, op = operator(n=3000, seed=3, leaf=64)
+    b = inputs.make_rhs(cloud.n, 3, seed=34)
+    for inner in (None, "c64"):
+        xb, _, _ = _solve(torch_dev, op, b, 1e-8, inner)
+        for j in range(3):
+            xa, _, _ = _solve(torch_dev, op, b[:, j:j + 1], 1e-8, inner)
+            assert np.array_equal(xa[:, 0], xb[:, j]), (inner, j)
