@@ -53,7 +53,9 @@ enum {
 typedef enum {
   UHM_C128 = 0,      /* complex128 storage and arithmetic; vectors complex128 */
   UHM_C64 = 1,       /* complex64 storage, FP32 accumulation; vectors complex64 */
-  UHM_BF16PAIR = 2   /* (re, im) bfloat16 pairs, FP32 accumulation; vectors complex64 */
+  UHM_BF16PAIR = 2,  /* (re, im) bfloat16 pairs, FP32 accumulation; vectors complex64 */
+  UHM_C128_MULTI = 3 /* complex128 storage and arithmetic laid out for many right-hand sides
+                        (FP64 MFMA, up to 64 per pass); vectors complex128 */
 } uhm_storage;
 
 typedef struct uhm_op uhm_op; /* opaque; owned by the library until uhm_free */
@@ -156,7 +158,7 @@ int uhm_upload_h(const uhm_host_hmatrix* h, uhm_storage storage, void* hip_strea
  * Y = A X  (w = A v of Algorithms 5 and 6, section 4.4; Y is overwritten).
  * X: device pointer, n x nrhs column-major, leading dimension ldx >= n, user order.
  * Y: device pointer, n x nrhs column-major, leading dimension ldy >= n; must not overlap X.
- * Element type: complex128 for UHM_C128 operators, complex64 otherwise.
+ * Element type: complex128 for UHM_C128 and UHM_C128_MULTI operators, complex64 otherwise.
  * Asynchronous on `hip_stream`.  nrhs == 0 is a no-op.  Errors: UHM_EINVAL (null
  * pointer, nrhs < 0, ld < n), UHM_ENOMEM (workspace growth failed), UHM_EHIP.
  */
@@ -187,7 +189,7 @@ typedef struct {
  * Solve A X = B by restarted GMRES(m) (textbook GMRES with classical Gram-Schmidt
  * applied twice, FP64 Krylov vectors, Givens least-squares), for nrhs right-hand sides
  * at once, each with its own Krylov space.  X starts at zero and is overwritten.
- *   op:    the operator A, complex128 storage (the true-residual operator).
+ *   op:    the operator A, UHM_C128 or UHM_C128_MULTI storage (the true-residual operator).
  *   inner: NULL for plain GMRES on op; otherwise an operator of the same matrix in
  *          complex64 or bf16-pair storage, and the solve is mixed-precision iterative
  *          refinement: r = B - A X with op (FP64), an inner GMRES(m) solves

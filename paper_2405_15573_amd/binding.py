@@ -15,7 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libuhm.so")
 
 UHM_OK, UHM_EINVAL, UHM_ENOMEM, UHM_EHIP, UHM_ENOCONV, UHM_ENOTSUP = 0, -1, -2, -3, -4, -5
-STORAGE = {"c128": 0, "c64": 1, "bf16pair": 2}
+STORAGE = {"c128": 0, "c64": 1, "bf16pair": 2, "c128multi": 3}
+C128_FORMS = ("c128", "c128multi")
 
 P = ctypes.c_void_p
 I64 = ctypes.c_int64
@@ -139,7 +140,7 @@ class DeviceOperator:
     def matvec(self, x, y=None, stream=None):
         """y = A x for a torch tensor x (n,) or (n, r) on the device; returns y."""
         import torch
-        want = torch.complex128 if self.storage == "c128" else torch.complex64
+        want = torch.complex128 if self.storage in C128_FORMS else torch.complex64
         if x.dtype != want or not x.is_cuda:
             raise ValueError(f"x must be a {want} device tensor")
         vec = x.dim() == 1
@@ -280,7 +281,7 @@ def solve_gmres(op: DeviceOperator, b, tol: float, inner: DeviceOperator | None 
     """Solve A X = B with GMRES(restart) (inner=None) or GMRES-IR with the low-precision
     operator `inner`.  b: complex128 device tensor (n,) or (n, r).  Returns (x, info dict, code)."""
     import torch
-    if op.storage != "c128":
+    if op.storage not in C128_FORMS:
         raise ValueError("the residual operator must be complex128")
     vec = b.dim() == 1
     b2 = b.reshape(op.n, 1) if vec else b

@@ -531,7 +531,7 @@ const char* uhm_last_error(void) { return g_err.c_str(); }
 int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream, uhm_op** out) {
   if (!h || !out) return fail(UHM_EINVAL, "null argument");
   *out = nullptr;
-  if (storage != UHM_C128 && storage != UHM_C64 && storage != UHM_BF16PAIR)
+  if (storage != UHM_C128 && storage != UHM_C64 && storage != UHM_BF16PAIR && storage != UHM_C128_MULTI)
     return fail(UHM_EINVAL, "unknown storage precision");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   TreeInfo T;
@@ -965,7 +965,7 @@ int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int
   if (ldx < op->n || ldy < op->n) return fail(UHM_EINVAL, "leading dimension smaller than n");
   const char* xb = static_cast<const char*>(X);
   const char* yb = static_cast<const char*>(Y);
-  const size_t es = op->storage == UHM_C128 ? sizeof(cd) : sizeof(float2);
+  const size_t es = (op->storage == UHM_C128 || op->storage == UHM_C128_MULTI) ? sizeof(cd) : sizeof(float2);
   if (xb < yb + (size_t)((nrhs - 1) * ldy + op->n) * es && yb < xb + (size_t)((nrhs - 1) * ldx + op->n) * es)
     return fail(UHM_EINVAL, "X and Y overlap");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);

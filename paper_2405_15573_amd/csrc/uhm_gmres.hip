@@ -252,7 +252,7 @@ int alloc_work(Work& W, int64_t n, int r, int m, bool lowp) {
 int apply(uhm_op* A, Work& W, const cd* x, cd* y, hipStream_t s) {
   const auto t0 = Clock::now();
   int rc;
-  if (A->storage == UHM_C128) {
+  if (A->storage == UHM_C128 || A->storage == UHM_C128_MULTI) {
     rc = uhm_matvec(A, x, W.n, y, W.n, W.r, s);
   } else {
     const int64_t nq = W.n * W.r;
@@ -418,8 +418,9 @@ using namespace uhm_detail;
 extern "C" int uhm_solve_gmres(uhm_op* op, uhm_op* inner, const void* B, int64_t ldb, void* X, int64_t ldx, int32_t nrhs,
                                double tol, const uhm_gmres_opts* opts, uhm_gmres_info* info, void* hip_stream) {
   if (!op || !B || !X) return fail(UHM_EINVAL, "null argument");
-  if (op->storage != UHM_C128 || op->kind != 0) return fail(UHM_EINVAL, "the residual operator must be a complex128 UH-matrix");
-  if (inner && (inner->storage == UHM_C128 || inner->n != op->n))
+  if ((op->storage != UHM_C128 && op->storage != UHM_C128_MULTI) || op->kind != 0)
+    return fail(UHM_EINVAL, "the residual operator must be a complex128 UH-matrix");
+  if (inner && (inner->storage == UHM_C128 || inner->storage == UHM_C128_MULTI || inner->n != op->n))
     return fail(UHM_EINVAL, "the inner operator must be a low-precision form of the same size");
   if (nrhs < 1 || ldb < op->n || ldx < op->n || !(tol > 0.0)) return fail(UHM_EINVAL, "bad nrhs, leading dimension or tol");
   uhm_gmres_opts o{50, 2000, 30, 1e-4};

@@ -1,6 +1,6 @@
-// Low-precision storage forms of the uniform H-matrix product: complex64 (FP32 MFMA) and
-// (re, im) bfloat16 pairs (BF16 MFMA), FP32 accumulation, 1 to 64 right-hand sides per
-// pass.  The three stages of Algorithm 6 (section 4.4) become batched complex GEMMs:
+// Many-right-hand-side forms of the uniform H-matrix product on MFMA: complex64 storage
+// (FP32 MFMA), (re, im) bfloat16 pairs (BF16 MFMA), both with FP32 accumulation, and
+// complex128 storage (FP64 MFMA), 1 to 64 right-hand sides per pass.  The three stages of Algorithm 6 (section 4.4) become batched complex GEMMs:
 //
 //   forward   P_lambda = F_lambda^* X_lambda   (C_lambda x r; K = leaf rows)
 //   coupling  Y^_tau   = [S_b ...] X^cat       (l_tau x r;    K = sum_sigma l_sigma)
@@ -18,7 +18,8 @@
 // MFMA lane layouts (checked on gfx950):
 //   v_mfma_f32_16x16x4_f32:  A lane l = A[l%16][l/16], B lane l = B[l/16][l%16]
 //   v_mfma_f32_16x16x32_bf16: A lane l = A[l%16][8(l/16)+t], B lane l = B[8(l/16)+t][l%16]
-//   both: accumulator register v of lane l = C[4(l/16)+v][l%16].
+//   both: accumulator register v of lane l = C[4(l/16)+v][l%16];
+//   v_mfma_f64_16x16x4_f64: A, B as the f32 form, register v of lane l = C[l/16 + 4v][l%16].
 // The k index inside one instruction may be any permutation shared by A and B; here lane
 // group g = l/16 owns the k-values g*KPL .. g*KPL+KPL-1 of the k-block.
 #include "uhm_internal.h"
@@ -31,37 +32,85 @@ namespace uhm_detail {
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 using cf = float2;
 
 constexpr int kLpWaves = 4;
-constexpr int kLpZ = 64;          // k-rows of the B operand staged in LDS per round
-constexpr int kLpCoupK = 1024;    // coupling tile width in columns (multiple of kLpZ)
-constexpr int kLpRmax = 64;       // right-hand sides per pass
+constexpr int kLpCoupK = 1024;      // coupling tile width in columns
+constexpr int kLpRmax = 64;         // right-hand sides per pass
 constexpr int32_t kZero = INT_MIN;  // gather-map entry for a zero (padding) column
+constexpr int kRS = kLpRmax + 4;    // LDS row stride of a vector operand (elements)
 
-template <int ST>
-struct Frag;
-template <>
-struct Frag<UHM_C64> {
-  static constexpr int KB = 16, KPL = 4;
-};
-template <>
-struct Frag<UHM_BF16PAIR> {
-  static constexpr int KB = 32, KPL = 8;
-};
-
-// LDS image of the B operand for one round of kLpZ k-rows and R <= 64 columns.
-constexpr int kRS = kLpRmax + 4;   // complex64 row stride (keeps lane groups on other banks)
-constexpr int kZT = kLpZ + 8;      // bf16 plane row stride (per column j)
+// ---- LDS images of the B operand for one round of RZ k-rows and R <= 64 columns
+template <int RZ>
 struct LdsF32 {
-  cf z[kLpZ * kRS];
+  cf z[RZ * kRS];
 };
+template <int RZ>
+struct LdsF64 {
+  cd z[RZ * kRS];
+};
+constexpr int kZT = 64 + 8;  // bf16 plane row stride (per column j)
 struct LdsBf16 {
   __bf16 re_hi[kLpRmax * kZT], re_lo[kLpRmax * kZT], im_hi[kLpRmax * kZT], im_lo[kLpRmax * kZT];
 };
 
-__device__ __forceinline__ void lds_put(LdsF32& L, int k, int j, cf v) { L.z[k * kRS + j] = v; }
+// ---- one lane's A chunk of a k-block: KPL complex values of its row
+struct ChunkF32 {
+  v4f re, im;
+};
+struct ChunkBf16 {
+  v8bf re, im;
+};
+struct ChunkF64 {
+  v4d re, im;
+};
+
+// Storage traits.  CH: 16-byte words per lane chunk; RZ: k-rows per LDS round;
+// V: vector element; ACC: accumulator register tile; rows of an accumulator register:
+// C64/BF16 lane (g, i) register v holds row 4g + v, C128 holds row g + 4v.
+template <int ST>
+struct Tr;
+template <>
+struct Tr<UHM_C64> {
+  static constexpr int KB = 16, KPL = 4, CH = 2, RZ = 64;
+  using V = cf;
+  using ACC = v4f;
+  using LDS = LdsF32<RZ>;
+  using CHUNK = ChunkF32;
+  __device__ static int row(int g, int v) { return 4 * g + v; }
+};
+template <>
+struct Tr<UHM_BF16PAIR> {
+  static constexpr int KB = 32, KPL = 8, CH = 2, RZ = 64;
+  using V = cf;
+  using ACC = v4f;
+  using LDS = LdsBf16;
+  using CHUNK = ChunkBf16;
+  __device__ static int row(int g, int v) { return 4 * g + v; }
+};
+template <>
+struct Tr<UHM_C128_MULTI> {
+  static constexpr int KB = 16, KPL = 4, CH = 4, RZ = 32;
+  using V = cd;
+  using ACC = v4d;
+  using LDS = LdsF64<RZ>;
+  using CHUNK = ChunkF64;
+  __device__ static int row(int g, int v) { return g + 4 * v; }
+};
+
+template <class V>
+__device__ __forceinline__ V vzero();
+template <>
+__device__ __forceinline__ cf vzero<cf>() { return make_float2(0.f, 0.f); }
+template <>
+__device__ __forceinline__ cd vzero<cd>() { return make_double2(0.0, 0.0); }
+
+template <int RZ>
+__device__ __forceinline__ void lds_put(LdsF32<RZ>& L, int k, int j, cf v) { L.z[k * kRS + j] = v; }
+template <int RZ>
+__device__ __forceinline__ void lds_put(LdsF64<RZ>& L, int k, int j, cd v) { L.z[k * kRS + j] = v; }
 __device__ __forceinline__ void lds_put(LdsBf16& L, int k, int j, cf v) {
   const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
   L.re_hi[j * kZT + k] = rh;
@@ -70,23 +119,14 @@ __device__ __forceinline__ void lds_put(LdsBf16& L, int k, int j, cf v) {
   L.im_lo[j * kZT + k] = (__bf16)(v.y - (float)ih);
 }
 
-// One lane's A chunk of a k-block: KPL complex values of its row.
-struct ChunkF32 {
-  v4f re, im;
-};
-struct ChunkBf16 {
-  v8bf re, im;
-};
-
 __device__ __forceinline__ void load_chunk(const uint4* p, bool act, ChunkF32& c) {
+  uint4 a = make_uint4(0, 0, 0, 0), b = a;
   if (act) {
-    const uint4 a = p[0], b = p[1];
-    c.re = v4f{__uint_as_float(a.x), __uint_as_float(a.y), __uint_as_float(a.z), __uint_as_float(a.w)};
-    c.im = v4f{__uint_as_float(b.x), __uint_as_float(b.y), __uint_as_float(b.z), __uint_as_float(b.w)};
-  } else {
-    c.re = v4f{0.f, 0.f, 0.f, 0.f};
-    c.im = c.re;
+    a = p[0];
+    b = p[1];
   }
+  c.re = __builtin_bit_cast(v4f, a);
+  c.im = __builtin_bit_cast(v4f, b);
 }
 __device__ __forceinline__ void load_chunk(const uint4* p, bool act, ChunkBf16& c) {
   uint4 a = make_uint4(0, 0, 0, 0), b = a;
@@ -97,10 +137,24 @@ __device__ __forceinline__ void load_chunk(const uint4* p, bool act, ChunkBf16& 
   c.re = __builtin_bit_cast(v8bf, a);
   c.im = __builtin_bit_cast(v8bf, b);
 }
+__device__ __forceinline__ void load_chunk(const uint4* p, bool act, ChunkF64& c) {
+  uint4 a0 = make_uint4(0, 0, 0, 0), a1 = a0, b0 = a0, b1 = a0;
+  if (act) {
+    a0 = p[0];
+    a1 = p[1];
+    b0 = p[2];
+    b1 = p[3];
+  }
+  const double2 r0 = __builtin_bit_cast(double2, a0), r1 = __builtin_bit_cast(double2, a1);
+  const double2 i0 = __builtin_bit_cast(double2, b0), i1 = __builtin_bit_cast(double2, b1);
+  c.re = v4d{r0.x, r0.y, r1.x, r1.y};
+  c.im = v4d{i0.x, i0.y, i1.x, i1.y};
+}
 
-// acc_r/acc_i[nt] += A_chunk (16 rows x one k-block) * B (k-block rows of the LDS round).
-template <int NT>
-__device__ __forceinline__ void mma_block(const ChunkF32& a, const LdsF32& L, int kk0, int g, int i, v4f* cr, v4f* ci) {
+// acc_r/acc_i[nt] += A_chunk (16 rows x one k-block) * B (k-block rows kk0.. of the LDS round).
+template <int NT, int RZ>
+__device__ __forceinline__ void mma_block(const ChunkF32& a, const LdsF32<RZ>& L, int kk0, int g, int i, v4f* cr,
+                                          v4f* ci) {
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int k = kk0 + g * 4 + t;
@@ -116,7 +170,25 @@ __device__ __forceinline__ void mma_block(const ChunkF32& a, const LdsF32& L, in
   }
 }
 
-template <int NT>
+template <int NT, int RZ>
+__device__ __forceinline__ void mma_block(const ChunkF64& a, const LdsF64<RZ>& L, int kk0, int g, int i, v4d* cr,
+                                          v4d* ci) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int k = kk0 + g * 4 + t;
+    const double ar = a.re[t], ai = a.im[t], nai = -a.im[t];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const cd b = L.z[k * kRS + nt * 16 + i];
+      cr[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.x, cr[nt], 0, 0, 0);
+      cr[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, b.y, cr[nt], 0, 0, 0);
+      ci[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.y, ci[nt], 0, 0, 0);
+      ci[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b.x, ci[nt], 0, 0, 0);
+    }
+  }
+}
+
+template <int NT, int RZ>
 __device__ __forceinline__ void mma_block(const ChunkBf16& a, const LdsBf16& L, int kk0, int g, int i, v4f* cr,
                                           v4f* ci) {
   uint4 neg = __builtin_bit_cast(uint4, a.im);
@@ -143,38 +215,41 @@ __device__ __forceinline__ void mma_block(const ChunkBf16& a, const LdsBf16& L, 
   }
 }
 
-template <int ST>
-using LdsOf = typename std::conditional<ST == UHM_C64, LdsF32, LdsBf16>::type;
-template <int ST>
-using ChunkOf = typename std::conditional<ST == UHM_C64, ChunkF32, ChunkBf16>::type;
-
-// Store the 16 x (16 NT) accumulator tile: row r = 4g + v (< hm), column j = 16 nt + i (< R).
-template <int NT>
-__device__ __forceinline__ void store_tile(cf* out, int64_t row0, int hm, int R, int g, int i, const v4f* cr,
-                                           const v4f* ci) {
+// Store the 16 x (16 NT) accumulator tile; register v of lane (g, i) holds row Tr::row(g, v).
+template <int ST, int NT>
+__device__ __forceinline__ void store_tile(typename Tr<ST>::V* out, int64_t row0, int hm, int R, int g, int i,
+                                           const typename Tr<ST>::ACC* cr, const typename Tr<ST>::ACC* ci) {
+  using V = typename Tr<ST>::V;
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int r = 4 * g + v;
-      if (r < hm) out[(row0 + r) * R + nt * 16 + i] = make_float2(cr[nt][v], ci[nt][v]);
+      const int r = Tr<ST>::row(g, v);
+      if (r < hm) {
+        V o;
+        o.x = cr[nt][v];
+        o.y = ci[nt][v];
+        out[(row0 + r) * R + nt * 16 + i] = o;
+      }
     }
 }
 
 // ---------------------------------------------------------------- kernels
 
 // Xc[pos][j] = x[perm[pos] + j ldx] (cluster order, row-major, R columns, zero beyond r).
-__global__ __launch_bounds__(256) void k_lp_gather(const cf* __restrict__ x, int64_t ldx, int r, int R,
-                                                   const int32_t* __restrict__ perm, int64_t n, cf* __restrict__ Xc) {
+template <class V>
+__global__ __launch_bounds__(256) void k_lp_gather(const V* __restrict__ x, int64_t ldx, int r, int R,
+                                                   const int32_t* __restrict__ perm, int64_t n, V* __restrict__ Xc) {
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= n * R) return;
   const int64_t pos = q / R;
   const int j = (int)(q - pos * R);
-  Xc[q] = j < r ? x[perm[pos] + (int64_t)j * ldx] : make_float2(0.f, 0.f);
+  Xc[q] = j < r ? x[perm[pos] + (int64_t)j * ldx] : vzero<V>();
 }
 
-__global__ __launch_bounds__(256) void k_lp_scatter(const cf* __restrict__ Yc, int r, int R, const int32_t* __restrict__ perm,
-                                                    int64_t n, cf* __restrict__ y, int64_t ldy) {
+template <class V>
+__global__ __launch_bounds__(256) void k_lp_scatter(const V* __restrict__ Yc, int r, int R, const int32_t* __restrict__ perm,
+                                                    int64_t n, V* __restrict__ y, int64_t ldy) {
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= n * (int64_t)r) return;
   const int j = (int)(q / n);
@@ -187,45 +262,79 @@ template <int ST, int NT>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lp_forward(
     const uint4* __restrict__ F, const int64_t* __restrict__ f_off, const int32_t* __restrict__ f_M,
     const int32_t* __restrict__ f_nkb, const int32_t* __restrict__ leaf_pos, const int32_t* __restrict__ leaf_n,
-    const int64_t* __restrict__ poff, const cf* __restrict__ Xc, int R, cf* __restrict__ p) {
-  using F_ = Frag<ST>;
-  __shared__ LdsOf<ST> L;
+    const int64_t* __restrict__ poff, const typename Tr<ST>::V* __restrict__ Xc, int R,
+    typename Tr<ST>::V* __restrict__ p) {
+  using T_ = Tr<ST>;
+  using V = typename T_::V;
+  __shared__ typename T_::LDS L;
   const int leaf = blockIdx.x;
   const int M = f_M[leaf];
   if (M == 0) return;
   const int n = leaf_n[leaf], nkb = f_nkb[leaf];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, i = lane & 15;
-  const int K = nkb * F_::KB;  // <= 64
-  for (int q = t; q < K * R; q += 64 * kLpWaves) {
-    const int k = q / R, j = q - k * R;
-    lds_put(L, k, j, k < n ? Xc[(int64_t)(leaf_pos[leaf] + k) * R + j] : make_float2(0.f, 0.f));
-  }
-  __syncthreads();
   const uint4* base = F + f_off[leaf];
   const int nmt = (M + 15) >> 4;
-  for (int mt = w; mt < nmt; mt += kLpWaves) {
-    const int hm = min(16, M - 16 * mt);
-    const uint4* tile = base + (int64_t)mt * nkb * 8 * 16;
-    v4f cr[NT], ci[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int kb = 0; kb < nkb; ++kb) {
-      ChunkOf<ST> a;
-      load_chunk(tile + (int64_t)kb * 8 * hm + 2 * (g * hm + i), i < hm, a);
-      mma_block<NT>(a, L, kb * F_::KB, g, i, cr, ci);
+  constexpr int KBR = T_::RZ / T_::KB;  // k-blocks per LDS round
+  if (nkb <= KBR) {
+    // the whole leaf (<= RZ rows) fits one round: stage once, sweep all m-tiles
+    for (int q = t; q < nkb * T_::KB * R; q += 64 * kLpWaves) {
+      const int k = q / R, j = q - k * R;
+      lds_put(L, k, j, k < n ? Xc[(int64_t)(leaf_pos[leaf] + k) * R + j] : vzero<V>());
     }
-    store_tile<NT>(p, poff[leaf] + 16 * mt, hm, R, g, i, cr, ci);
+    __syncthreads();
+    for (int mt = w; mt < nmt; mt += kLpWaves) {
+      const int hm = min(16, M - 16 * mt);
+      const uint4* tile = base + (int64_t)mt * nkb * T_::CH * 64;
+      typename T_::ACC cr[NT], ci[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = typename T_::ACC{0, 0, 0, 0};
+      for (int kb = 0; kb < nkb; ++kb) {
+        typename T_::CHUNK a;
+        load_chunk(tile + (int64_t)kb * T_::CH * 4 * hm + T_::CH * (g * hm + i), i < hm, a);
+        mma_block<NT, T_::RZ>(a, L, kb * T_::KB, g, i, cr, ci);
+      }
+      store_tile<ST, NT>(p, poff[leaf] + 16 * mt, hm, R, g, i, cr, ci);
+    }
+  } else {
+    // leaf rows in several rounds: each wave keeps its m-tiles' accumulators across rounds
+    // by sweeping m-tiles in the outer loop and restaging per m-tile group of 4
+    for (int mt0 = 0; mt0 < nmt; mt0 += kLpWaves) {
+      const int mt = mt0 + w;
+      const int hm = min(16, M - 16 * mt);
+      const uint4* tile = base + (int64_t)mt * nkb * T_::CH * 64;
+      typename T_::ACC cr[NT], ci[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = typename T_::ACC{0, 0, 0, 0};
+      for (int kb = 0; kb < nkb; kb += KBR) {
+        const int nk = min(KBR, nkb - kb) * T_::KB;
+        __syncthreads();
+        for (int q = t; q < nk * R; q += 64 * kLpWaves) {
+          const int k = q / R, j = q - k * R;
+          const int row = kb * T_::KB + k;
+          lds_put(L, k, j, row < n ? Xc[(int64_t)(leaf_pos[leaf] + row) * R + j] : vzero<V>());
+        }
+        __syncthreads();
+        if (mt < nmt)
+          for (int b = 0; b < nk / T_::KB; ++b) {
+            typename T_::CHUNK a;
+            load_chunk(tile + (int64_t)(kb + b) * T_::CH * 4 * hm + T_::CH * (g * hm + i), i < hm, a);
+            mma_block<NT, T_::RZ>(a, L, b * T_::KB, g, i, cr, ci);
+          }
+      }
+      if (mt < nmt) store_tile<ST, NT>(p, poff[leaf] + 16 * mt, hm, R, g, i, cr, ci);
+    }
   }
 }
 
 // xh[e][j] = sum over the leaves of the segment of p[poff[leaf] + col + e - start][j].
-__global__ __launch_bounds__(256) void k_lp_reduce_segments(const cf* __restrict__ p, int R, const int64_t* __restrict__ poff,
+template <class V>
+__global__ __launch_bounds__(256) void k_lp_reduce_segments(const V* __restrict__ p, int R, const int64_t* __restrict__ poff,
                                                             const int32_t* __restrict__ out_seg,
                                                             const int64_t* __restrict__ seg_start,
                                                             const int32_t* __restrict__ seg_leaf0,
                                                             const int32_t* __restrict__ seg_nleaf,
                                                             const int32_t* __restrict__ seg_col, int64_t nout,
-                                                            cf* __restrict__ xh) {
+                                                            V* __restrict__ xh) {
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= nout * R) return;
   const int64_t e = q / R;
@@ -233,13 +342,13 @@ __global__ __launch_bounds__(256) void k_lp_reduce_segments(const cf* __restrict
   const int s = out_seg[e];
   const int col = seg_col[s] + (int)(e - seg_start[s]);
   const int l0 = seg_leaf0[s], nl = seg_nleaf[s];
-  float re = 0.f, im = 0.f;
+  V acc = vzero<V>();
   for (int qq = 0; qq < nl; ++qq) {
-    const cf v = p[(poff[l0 + qq] + col) * R + j];
-    re += v.x;
-    im += v.y;
+    const V v = p[(poff[l0 + qq] + col) * R + j];
+    acc.x += v.x;
+    acc.y += v.y;
   }
-  xh[q] = make_float2(re, im);
+  xh[q] = acc;
 }
 
 struct LpCoupTile {
@@ -256,46 +365,48 @@ template <int ST, int NT>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lp_coupling(const uint4* __restrict__ S,
                                                                const LpCoupTile* __restrict__ tiles,
                                                                const int32_t* __restrict__ colsrc,
-                                                               const cf* __restrict__ xh, int R,
-                                                               cf* __restrict__ part) {
-  using F_ = Frag<ST>;
-  __shared__ LdsOf<ST> L;
+                                                               const typename Tr<ST>::V* __restrict__ xh, int R,
+                                                               typename Tr<ST>::V* __restrict__ part) {
+  using T_ = Tr<ST>;
+  using V = typename T_::V;
+  __shared__ typename T_::LDS L;
   const LpCoupTile T = tiles[blockIdx.x];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, i = lane & 15;
   const int nmt = (T.h + 15) >> 4;
   const int hm = min(16, T.h - 16 * w);
-  const uint4* tile = S + T.base + (int64_t)w * T.nkb_all * 8 * 16;
-  v4f cr[NT], ci[NT];
+  const uint4* tile = S + T.base + (int64_t)w * T.nkb_all * T_::CH * 64;
+  typename T_::ACC cr[NT], ci[NT];
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = v4f{0.f, 0.f, 0.f, 0.f};
-  constexpr int KBR = kLpZ / F_::KB;  // k-blocks per LDS round
+  for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = typename T_::ACC{0, 0, 0, 0};
+  constexpr int KBR = T_::RZ / T_::KB;
   for (int kb = 0; kb < T.nkb; kb += KBR) {
-    const int nk = min(KBR, T.nkb - kb) * F_::KB;
-    const int64_t c0 = T.csrc + (int64_t)(T.kb0 + kb) * F_::KB;
+    const int nk = min(KBR, T.nkb - kb) * T_::KB;
+    const int64_t c0 = T.csrc + (int64_t)(T.kb0 + kb) * T_::KB;
     __syncthreads();
     for (int q = t; q < nk * R; q += 64 * kLpWaves) {
       const int k = q / R, j = q - k * R;
       const int32_t src = colsrc[c0 + k];
-      lds_put(L, k, j, src >= 0 ? xh[(int64_t)src * R + j] : make_float2(0.f, 0.f));
+      lds_put(L, k, j, src >= 0 ? xh[(int64_t)src * R + j] : vzero<V>());
     }
     __syncthreads();
     if (w < nmt) {
-      for (int b = 0; b < nk / F_::KB; ++b) {
-        ChunkOf<ST> a;
-        load_chunk(tile + (int64_t)(T.kb0 + kb + b) * 8 * hm + 2 * (g * hm + i), i < hm, a);
-        mma_block<NT>(a, L, b * F_::KB, g, i, cr, ci);
+      for (int b = 0; b < nk / T_::KB; ++b) {
+        typename T_::CHUNK a;
+        load_chunk(tile + (int64_t)(T.kb0 + kb + b) * T_::CH * 4 * hm + T_::CH * (g * hm + i), i < hm, a);
+        mma_block<NT, T_::RZ>(a, L, b * T_::KB, g, i, cr, ci);
       }
     }
   }
-  if (w < nmt) store_tile<NT>(part, (int64_t)blockIdx.x * 64 + 16 * w, hm, R, g, i, cr, ci);
+  if (w < nmt) store_tile<ST, NT>(part, (int64_t)blockIdx.x * 64 + 16 * w, hm, R, g, i, cr, ci);
 }
 
-__global__ __launch_bounds__(256) void k_lp_reduce_coupling(const cf* __restrict__ part, int R,
+template <class V>
+__global__ __launch_bounds__(256) void k_lp_reduce_coupling(const V* __restrict__ part, int R,
                                                             const int32_t* __restrict__ yh_grp,
                                                             const int64_t* __restrict__ grp_start,
                                                             const int32_t* __restrict__ grp_t0,
                                                             const int32_t* __restrict__ grp_nt, int64_t nout,
-                                                            cf* __restrict__ yh) {
+                                                            V* __restrict__ yh) {
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= nout * R) return;
   const int64_t e = q / R;
@@ -303,13 +414,13 @@ __global__ __launch_bounds__(256) void k_lp_reduce_coupling(const cf* __restrict
   const int gi = yh_grp[e];
   const int r = (int)(e - grp_start[gi]);
   const int t0 = grp_t0[gi], nt = grp_nt[gi];
-  float re = 0.f, im = 0.f;
+  V acc = vzero<V>();
   for (int tt = 0; tt < nt; ++tt) {
-    const cf v = part[((int64_t)(t0 + tt) * 64 + r) * R + j];
-    re += v.x;
-    im += v.y;
+    const V v = part[((int64_t)(t0 + tt) * 64 + r) * R + j];
+    acc.x += v.x;
+    acc.y += v.y;
   }
-  yh[q] = make_float2(re, im);
+  yh[q] = acc;
 }
 
 // Y_lambda = B_lambda Z_lambda per leaf; Z gathered from yh (index >= 0), from the
@@ -318,28 +429,29 @@ template <int ST, int NT>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lp_backward(
     const uint4* __restrict__ B, const int64_t* __restrict__ b_off, const int32_t* __restrict__ b_nkb,
     const int64_t* __restrict__ zoff, const int32_t* __restrict__ zmap, const int32_t* __restrict__ leaf_pos,
-    const int32_t* __restrict__ leaf_n, const cf* __restrict__ yh, const cf* __restrict__ Xc, int R,
-    cf* __restrict__ Yc) {
-  using F_ = Frag<ST>;
-  __shared__ LdsOf<ST> L;
+    const int32_t* __restrict__ leaf_n, const typename Tr<ST>::V* __restrict__ yh,
+    const typename Tr<ST>::V* __restrict__ Xc, int R, typename Tr<ST>::V* __restrict__ Yc) {
+  using T_ = Tr<ST>;
+  using V = typename T_::V;
+  __shared__ typename T_::LDS L;
   const int leaf = blockIdx.x;
   const int n = leaf_n[leaf], nkb = b_nkb[leaf];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, i = lane & 15;
   const int nmt = (n + 15) >> 4;
   const int hm = min(16, n - 16 * w);
-  const uint4* tile = B + b_off[leaf] + (int64_t)w * nkb * 8 * 16;
+  const uint4* tile = B + b_off[leaf] + (int64_t)w * nkb * T_::CH * 64;
   const int32_t* zm = zmap + zoff[leaf];
-  v4f cr[NT], ci[NT];
+  typename T_::ACC cr[NT], ci[NT];
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = v4f{0.f, 0.f, 0.f, 0.f};
-  constexpr int KBR = kLpZ / F_::KB;
+  for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = typename T_::ACC{0, 0, 0, 0};
+  constexpr int KBR = T_::RZ / T_::KB;
   for (int kb = 0; kb < nkb; kb += KBR) {
-    const int nk = min(KBR, nkb - kb) * F_::KB;
+    const int nk = min(KBR, nkb - kb) * T_::KB;
     __syncthreads();
     for (int q = t; q < nk * R; q += 64 * kLpWaves) {
       const int k = q / R, j = q - k * R;
-      const int32_t m = zm[kb * F_::KB + k];
-      cf v = make_float2(0.f, 0.f);
+      const int32_t m = zm[kb * T_::KB + k];
+      V v = vzero<V>();
       if (m >= 0)
         v = yh[(int64_t)m * R + j];
       else if (m != kZero)
@@ -348,14 +460,14 @@ __global__ __launch_bounds__(64 * kLpWaves) void k_lp_backward(
     }
     __syncthreads();
     if (w < nmt) {
-      for (int b = 0; b < nk / F_::KB; ++b) {
-        ChunkOf<ST> a;
-        load_chunk(tile + (int64_t)(kb + b) * 8 * hm + 2 * (g * hm + i), i < hm, a);
-        mma_block<NT>(a, L, b * F_::KB, g, i, cr, ci);
+      for (int b = 0; b < nk / T_::KB; ++b) {
+        typename T_::CHUNK a;
+        load_chunk(tile + (int64_t)(kb + b) * T_::CH * 4 * hm + T_::CH * (g * hm + i), i < hm, a);
+        mma_block<NT, T_::RZ>(a, L, b * T_::KB, g, i, cr, ci);
       }
     }
   }
-  if (w < nmt) store_tile<NT>(Yc, (int64_t)leaf_pos[leaf] + 16 * w, hm, R, g, i, cr, ci);
+  if (w < nmt) store_tile<ST, NT>(Yc, (int64_t)leaf_pos[leaf] + 16 * w, hm, R, g, i, cr, ci);
 }
 
 }  // namespace
@@ -373,7 +485,7 @@ struct LowpOp {
   int32_t nctiles = 0;
   // workspace, sized for R columns
   int wsR = 0;
-  DevArray<cf> Xc, Yc, p, xh, part, yh;
+  DevArray<unsigned char> Xc, Yc, p, xh, part, yh;  // vector element: 8 or 16 bytes
 };
 
 void lowp_delete(LowpOp* lp) { delete lp; }
@@ -390,16 +502,16 @@ uint16_t to_bf16(float f) {
 // Pack an M x Kp panel (Kp a multiple of KB) given by get(m, k) into fragment-major chunks.
 template <int ST, class Get>
 int pack_panel(StagerT<uint4>& st, int32_t M, int32_t nkb, Get get) {
-  constexpr int KB = Frag<ST>::KB, KPL = Frag<ST>::KPL;
+  constexpr int KB = Tr<ST>::KB, KPL = Tr<ST>::KPL, CH = Tr<ST>::CH;
   std::complex<double> v[KPL];
   for (int32_t mt = 0; 16 * mt < M; ++mt) {
     const int32_t hm = std::min(16, M - 16 * mt);
     for (int32_t kb = 0; kb < nkb; ++kb) {
-      uint4* dst = st.span((int64_t)8 * hm);
+      uint4* dst = st.span((int64_t)CH * 4 * hm);
       for (int g = 0; g < 4; ++g)
         for (int32_t i = 0; i < hm; ++i) {
           for (int t = 0; t < KPL; ++t) v[t] = get(16 * mt + i, kb * KB + g * KPL + t);
-          uint4* c = dst + 2 * (g * hm + i);
+          uint4* c = dst + CH * (g * hm + i);
           if (ST == UHM_C64) {
             float re[4], im[4];
             for (int t = 0; t < 4; ++t) {
@@ -408,7 +520,7 @@ int pack_panel(StagerT<uint4>& st, int32_t M, int32_t nkb, Get get) {
             }
             std::memcpy(&c[0], re, 16);
             std::memcpy(&c[1], im, 16);
-          } else {
+          } else if (ST == UHM_BF16PAIR) {
             uint16_t re[8], im[8];
             for (int t = 0; t < 8; ++t) {
               re[t] = to_bf16((float)v[t].real());
@@ -416,6 +528,14 @@ int pack_panel(StagerT<uint4>& st, int32_t M, int32_t nkb, Get get) {
             }
             std::memcpy(&c[0], re, 16);
             std::memcpy(&c[1], im, 16);
+          } else {
+            double re[4], im[4];
+            for (int t = 0; t < 4; ++t) {
+              re[t] = v[t].real();
+              im[t] = v[t].imag();
+            }
+            std::memcpy(&c[0], re, 32);
+            std::memcpy(&c[2], im, 32);
           }
         }
     }
@@ -423,7 +543,10 @@ int pack_panel(StagerT<uint4>& st, int32_t M, int32_t nkb, Get get) {
   return st.err;
 }
 
-int64_t panel_chunks(int32_t M, int32_t nkb) { return (int64_t)8 * M * nkb; }  // uint4 units
+template <int ST>
+int64_t panel_chunks(int32_t M, int32_t nkb) {  // uint4 units
+  return (int64_t)Tr<ST>::CH * 4 * M * nkb;
+}
 
 using C = std::complex<double>;
 
@@ -436,7 +559,7 @@ struct SegLp {
 
 template <int ST>
 int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, uhm_op* op, LowpOp* lp) {
-  constexpr int KB = Frag<ST>::KB;
+  constexpr int KB = Tr<ST>::KB;
   const int32_t nc = h->nclusters;
   const int32_t nl = (int32_t)T.leaves.size();
   int rc;
@@ -463,7 +586,7 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
     f_nkb[i] = (int32_t)((h->size[T.leaves[i]] + KB - 1) / KB);
     f_off[i] = ftot;
     poff[i] = prow;
-    ftot += panel_chunks(Cn, f_nkb[i]);
+    ftot += panel_chunks<ST>(Cn, f_nkb[i]);
     prow += Cn;
   }
   if ((rc = lp->F.alloc(ftot))) return rc;
@@ -549,7 +672,7 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
         tiles.push_back({stot, csrc, hh, nkb, kb0, std::min(KBT, nkb - kb0)});
       grp_nt.push_back((int32_t)tiles.size() - grp_t0.back());
       jobs.push_back({t, r0, hh, stot, csrc, nkb});
-      stot += panel_chunks(hh, nkb);
+      stot += panel_chunks<ST>(hh, nkb);
     }
   }
   if ((rc = lp->S.alloc(stot))) return rc;
@@ -573,7 +696,7 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
     if ((rc = st.finish())) return rc;
   }
   for (const LpCoupTile& Tt : tiles) {
-    if (Tt.h < 1 || Tt.h > 64 || Tt.base < 0 || Tt.base + panel_chunks(Tt.h, Tt.nkb_all) > stot ||
+    if (Tt.h < 1 || Tt.h > 64 || Tt.base < 0 || Tt.base + panel_chunks<ST>(Tt.h, Tt.nkb_all) > stot ||
         Tt.kb0 < 0 || Tt.nkb < 1 || Tt.kb0 + Tt.nkb > Tt.nkb_all || Tt.csrc + (int64_t)Tt.nkb_all * KB > (int64_t)colsrc.size())
       return fail(UHM_EINVAL, "layout: coupling tile");
   }
@@ -600,7 +723,7 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
     }
     b_nkb[i] = (int32_t)((K + KB - 1) / KB);
     b_off[i] = btot;
-    btot += panel_chunks((int32_t)h->size[T.leaves[i]], b_nkb[i]);
+    btot += panel_chunks<ST>((int32_t)h->size[T.leaves[i]], b_nkb[i]);
   }
   if ((rc = lp->B.alloc(btot))) return rc;
   {
@@ -646,7 +769,7 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
   I.kind = 0;
   I.storage = ST;
   I.nleaves = nl;
-  I.elem_bytes = ST == UHM_C64 ? 8 : 4;
+  I.elem_bytes = ST == UHM_C64 ? 8 : (ST == UHM_BF16PAIR ? 4 : 16);
   I.nadm = h->nadm;
   I.nden = h->nden;
   I.elems_forward = I.elems_backward = I.elems_coupling = I.elems_near = 0;
@@ -662,53 +785,62 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
 }
 
 template <int ST, int NT>
-void launch_all(uhm_op* op, LowpOp* lp, const cf* x, int64_t ldx, cf* y, int64_t ldy, int r, int R, hipStream_t s) {
+void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, int64_t ldy, int r, int R, hipStream_t s) {
+  using V = typename Tr<ST>::V;
+  const V* x = static_cast<const V*>(xv);
+  V* y = static_cast<V*>(yv);
+  V* Xc = reinterpret_cast<V*>(lp->Xc.p);
+  V* Yc = reinterpret_cast<V*>(lp->Yc.p);
+  V* p = reinterpret_cast<V*>(lp->p.p);
+  V* xh = reinterpret_cast<V*>(lp->xh.p);
+  V* part = reinterpret_cast<V*>(lp->part.p);
+  V* yh = reinterpret_cast<V*>(lp->yh.p);
   const int nl = op->nleaves;
   const int64_t n = op->n;
   {
     ScopedTiming tm(op, s, K_LP_GATHER);
-    hipLaunchKernelGGL(k_lp_gather, dim3((unsigned)((n * R + 255) / 256)), dim3(256), 0, s, x, ldx, r, R, op->perm.p, n,
-                       lp->Xc.p);
+    hipLaunchKernelGGL(k_lp_gather<V>, dim3((unsigned)((n * R + 255) / 256)), dim3(256), 0, s, x, ldx, r, R,
+                       op->perm.p, n, Xc);
   }
   if (lp->nxh > 0) {
     {
       ScopedTiming tm(op, s, K_LP_FORWARD);
       hipLaunchKernelGGL((k_lp_forward<ST, NT>), dim3(nl), dim3(64 * kLpWaves), 0, s, lp->F.p, lp->f_off.p, lp->f_M.p,
-                         lp->f_nkb.p, op->leaf_pos.p, op->leaf_n.p, lp->poff.p, lp->Xc.p, R, lp->p.p);
+                         lp->f_nkb.p, op->leaf_pos.p, op->leaf_n.p, lp->poff.p, Xc, R, p);
     }
     {
       ScopedTiming tm(op, s, K_LP_REDUCE_FWD);
-      hipLaunchKernelGGL(k_lp_reduce_segments, dim3((unsigned)((lp->nxh * R + 255) / 256)), dim3(256), 0, s, lp->p.p, R,
+      hipLaunchKernelGGL(k_lp_reduce_segments<V>, dim3((unsigned)((lp->nxh * R + 255) / 256)), dim3(256), 0, s, p, R,
                          lp->poff.p, lp->out_seg.p, lp->seg_start.p, lp->seg_leaf0.p, lp->seg_nleaf.p, lp->seg_col.p,
-                         lp->nxh, lp->xh.p);
+                         lp->nxh, xh);
     }
   }
   if (lp->nctiles > 0) {
     {
       ScopedTiming tm(op, s, K_LP_COUPLING);
       hipLaunchKernelGGL((k_lp_coupling<ST, NT>), dim3(lp->nctiles), dim3(64 * kLpWaves), 0, s, lp->S.p, lp->ctiles.p,
-                         lp->colsrc.p, lp->xh.p, R, lp->part.p);
+                         lp->colsrc.p, xh, R, part);
     }
     {
       ScopedTiming tm(op, s, K_LP_REDUCE_COUP);
-      hipLaunchKernelGGL(k_lp_reduce_coupling, dim3((unsigned)((lp->nyh * R + 255) / 256)), dim3(256), 0, s, lp->part.p,
-                         R, lp->yh_grp.p, lp->grp_start.p, lp->grp_t0.p, lp->grp_nt.p, lp->nyh, lp->yh.p);
+      hipLaunchKernelGGL(k_lp_reduce_coupling<V>, dim3((unsigned)((lp->nyh * R + 255) / 256)), dim3(256), 0, s, part, R,
+                         lp->yh_grp.p, lp->grp_start.p, lp->grp_t0.p, lp->grp_nt.p, lp->nyh, yh);
     }
   }
   {
     ScopedTiming tm(op, s, K_LP_BACKWARD);
     hipLaunchKernelGGL((k_lp_backward<ST, NT>), dim3(nl), dim3(64 * kLpWaves), 0, s, lp->B.p, lp->b_off.p, lp->b_nkb.p,
-                       lp->zoff.p, lp->zmap.p, op->leaf_pos.p, op->leaf_n.p, lp->yh.p, lp->Xc.p, R, lp->Yc.p);
+                       lp->zoff.p, lp->zmap.p, op->leaf_pos.p, op->leaf_n.p, yh, Xc, R, Yc);
   }
   {
     ScopedTiming tm(op, s, K_LP_SCATTER);
-    hipLaunchKernelGGL(k_lp_scatter, dim3((unsigned)((n * r + 255) / 256)), dim3(256), 0, s, lp->Yc.p, r, R, op->perm.p,
-                       n, y, ldy);
+    hipLaunchKernelGGL(k_lp_scatter<V>, dim3((unsigned)((n * r + 255) / 256)), dim3(256), 0, s, Yc, r, R, op->perm.p, n,
+                       y, ldy);
   }
 }
 
 template <int ST>
-void launch_nt(uhm_op* op, LowpOp* lp, const cf* x, int64_t ldx, cf* y, int64_t ldy, int r, int R, hipStream_t s) {
+void launch_nt(uhm_op* op, LowpOp* lp, const void* x, int64_t ldx, void* y, int64_t ldy, int r, int R, hipStream_t s) {
   switch (R / 16) {
     case 1: launch_all<ST, 1>(op, lp, x, ldx, y, ldy, r, R, s); break;
     case 2: launch_all<ST, 2>(op, lp, x, ldx, y, ldy, r, R, s); break;
@@ -719,11 +851,13 @@ void launch_nt(uhm_op* op, LowpOp* lp, const cf* x, int64_t ldx, cf* y, int64_t 
 
 int grow(LowpOp* lp, int64_t n, int R) {
   if (lp->wsR >= R) return UHM_OK;
+  const int64_t e = lp->storage == UHM_C128_MULTI ? 16 : 8;
   int rc;
-  if ((rc = lp->Xc.alloc(n * R)) || (rc = lp->Yc.alloc(n * R)) || (rc = lp->p.alloc(std::max<int64_t>(1, lp->p_rows * R))) ||
-      (rc = lp->xh.alloc(std::max<int64_t>(1, lp->nxh * R))) ||
-      (rc = lp->part.alloc(std::max<int64_t>(1, (int64_t)lp->nctiles * 64 * R))) ||
-      (rc = lp->yh.alloc(std::max<int64_t>(1, lp->nyh * R)))) {
+  if ((rc = lp->Xc.alloc(e * n * R)) || (rc = lp->Yc.alloc(e * n * R)) ||
+      (rc = lp->p.alloc(e * std::max<int64_t>(1, lp->p_rows * R))) ||
+      (rc = lp->xh.alloc(e * std::max<int64_t>(1, lp->nxh * R))) ||
+      (rc = lp->part.alloc(e * std::max<int64_t>(1, (int64_t)lp->nctiles * 64 * R))) ||
+      (rc = lp->yh.alloc(e * std::max<int64_t>(1, lp->nyh * R)))) {
     lp->wsR = 0;
     return rc;
   }
@@ -737,9 +871,17 @@ int lowp_upload(const uhm_host_operator* h, uhm_storage storage, hipStream_t s, 
   std::unique_ptr<LowpOp> lp(new (std::nothrow) LowpOp);
   if (!lp) return fail(UHM_ENOMEM, "host allocation");
   lp->storage = storage;
-  lp->KB = storage == UHM_C64 ? Frag<UHM_C64>::KB : Frag<UHM_BF16PAIR>::KB;
-  const int rc = storage == UHM_C64 ? lowp_upload_t<UHM_C64>(h, s, T, op, lp.get())
-                                    : lowp_upload_t<UHM_BF16PAIR>(h, s, T, op, lp.get());
+  int rc;
+  if (storage == UHM_C64) {
+    lp->KB = Tr<UHM_C64>::KB;
+    rc = lowp_upload_t<UHM_C64>(h, s, T, op, lp.get());
+  } else if (storage == UHM_BF16PAIR) {
+    lp->KB = Tr<UHM_BF16PAIR>::KB;
+    rc = lowp_upload_t<UHM_BF16PAIR>(h, s, T, op, lp.get());
+  } else {
+    lp->KB = Tr<UHM_C128_MULTI>::KB;
+    rc = lowp_upload_t<UHM_C128_MULTI>(h, s, T, op, lp.get());
+  }
   if (rc) return rc;
   op->lp = lp.release();
   return UHM_OK;
@@ -748,20 +890,25 @@ int lowp_upload(const uhm_host_operator* h, uhm_storage storage, hipStream_t s, 
 int lowp_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs, hipStream_t s) {
   LowpOp* lp = op->lp;
   if (!lp) return fail(UHM_EINVAL, "operator has no low-precision form");
-  const cf* x = static_cast<const cf*>(X);
-  cf* y = static_cast<cf*>(Y);
+  const int64_t e = lp->storage == UHM_C128_MULTI ? 16 : 8;
+  const char* x = static_cast<const char*>(X);
+  char* y = static_cast<char*>(Y);
   for (int32_t c0 = 0; c0 < nrhs; c0 += kLpRmax) {
     const int r = std::min(kLpRmax, nrhs - c0);
     const int R = 16 * ((r + 15) / 16);
     int rc = grow(lp, op->n, std::max(R, lp->wsR));
     if (rc) return rc;
+    const void* xc = x + e * c0 * ldx;
+    void* yc = y + e * c0 * ldy;
     if (lp->storage == UHM_C64)
-      launch_nt<UHM_C64>(op, lp, x + (int64_t)c0 * ldx, ldx, y + (int64_t)c0 * ldy, ldy, r, R, s);
+      launch_nt<UHM_C64>(op, lp, xc, ldx, yc, ldy, r, R, s);
+    else if (lp->storage == UHM_BF16PAIR)
+      launch_nt<UHM_BF16PAIR>(op, lp, xc, ldx, yc, ldy, r, R, s);
     else
-      launch_nt<UHM_BF16PAIR>(op, lp, x + (int64_t)c0 * ldx, ldx, y + (int64_t)c0 * ldy, ldy, r, R, s);
+      launch_nt<UHM_C128_MULTI>(op, lp, xc, ldx, yc, ldy, r, R, s);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(UHM_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  const hipError_t he = hipGetLastError();
+  if (he != hipSuccess) return fail(UHM_EHIP, std::string("kernel launch: ") + hipGetErrorString(he));
   return UHM_OK;
 }
 

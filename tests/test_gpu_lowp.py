@@ -93,3 +93,23 @@ def test_lowp_dense_only(torch_dev):
         y = _run(torch_dev, dop, x)
         ref_r = uniform.uh_mvp(precision.round_operator(vars(op), storage), x)
         assert _col_rel(y, ref_r).max() <= 2e-5
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 16, 17, 64, 70])
+def test_c128multi_parity(torch_dev, nrhs):
+    """complex128 storage in the many-RHS layout (FP64 MFMA): the FP64 bar, 1e-12 per column."""
+    from paper_2405_15573_amd import binding
+    torch = torch_dev
+    print(f"case c128multi nrhs={nrhs}", flush=True)
+    for surface, n, seed, leaf in (("sphere", 3000, 3, 64), ("cube", 1300, 5, 32)):
+        cloud, op = operator(surface=surface, n=n, seed=seed, leaf=leaf)
+        dop = binding.upload(op, storage="c128multi")
+        x = inputs.make_rhs(cloud.n, nrhs, seed=50 + nrhs)
+        ld = cloud.n + 7
+        buf = torch.zeros((nrhs, ld), dtype=torch.complex128, device="cuda")
+        buf[:, :cloud.n] = torch.from_numpy(np.ascontiguousarray(x.T)).to("cuda")
+        ybuf = torch.zeros((nrhs, ld), dtype=torch.complex128, device="cuda")
+        dop.matvec(buf.t()[:cloud.n], ybuf.t()[:cloud.n])
+        torch.cuda.synchronize()
+        y = ybuf.t()[:cloud.n].cpu().numpy()
+        assert _col_rel(y, uniform.uh_mvp(vars(op), x)).max() <= 1e-12
