@@ -65,6 +65,168 @@ def time_products(torch, dop, x, y, steps, warmup, stream):
     return (t1 - t0) / steps, {k: (v[0] / max(1, v[1]), v[1]) for k, v in kt.items() if v[1] > 0}
 
 
+def run_gmres_cases(torch, binding, op, n, r, tol, maxit, stream, seed):
+    """Plain FP64 GMRES(50) against GMRES-IR with complex64 and bf16-pair inner products."""
+    import numpy as np
+
+    from paper_2405_15573_amd import inputs
+    out = {}
+    Bn = inputs.make_rhs(n, r, seed=seed + 11)
+    Bd = torch.from_numpy(np.ascontiguousarray(Bn.T)).to("cuda").t()
+    dmulti = binding.upload(op, storage="c128multi", stream=stream)
+    for name, inner_st in (("fp64", None), ("ir_c64", "c64"), ("ir_bf16pair", "bf16pair")):
+        inner = binding.upload(op, storage=inner_st, stream=stream) if inner_st else None
+        torch.cuda.synchronize()
+        t0g = time.perf_counter()
+        X, ginfo, rc = binding.solve_gmres(dmulti, Bd, tol, inner=inner, restart=50, max_iterations=maxit,
+                                           stream=stream, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0g
+        out[name] = dict(ginfo, wall_s=wall, nrhs=r, tol=tol, iteration_cap=maxit,
+                         status="converged" if rc == 0 else "iteration cap")
+        log(f"GMRES N={n} {name}: {wall:.2f} s, {ginfo['iterations']} it, {ginfo['refinements']} ref, "
+            f"res {ginfo['rel_residual']:.2e}, products {ginfo['seconds_products']:.2f} s, "
+            f"arnoldi {ginfo['seconds_arnoldi']:.2f} s")
+        if inner is not None:
+            inner.free()
+        del X
+    if out["fp64"]["status"] == "converged":
+        for k in ("ir_c64", "ir_bf16pair"):
+            if out[k]["status"] == "converged":
+                out[k]["speedup_vs_fp64"] = out["fp64"]["wall_s"] / out[k]["wall_s"]
+    dmulti.free()
+    return out
+
+
+def mixed_population(count, lo, hi, seed):
+    """Seeded operator population: N log-uniform in [lo, hi], surfaces cycling
+    sphere -> ellipsoid -> cube."""
+    from paper_2405_15573_amd import inputs
+    sizes = inputs.log_uniform_sizes(count, lo, hi, seed)
+    surf = ("sphere", "ellipsoid", "cube")
+    return [(surf[k % 3], int(sizes[k])) for k in range(count)]
+
+
+def run_batched(args):
+    """Many operators of uneven size (complex64, 1-16 RHS each) in shared stage launches,
+    tuned and captured in a hipGraph, against one operator at a time."""
+    import numpy as np
+    import torch
+
+    from paper_2405_15573_amd import binding, builder, inputs
+    pop = mixed_population(args.nops, 4096, args.max_n, args.seed)
+    rng = np.random.default_rng([args.seed, 4])
+    stream = torch.cuda.Stream()
+    ops, hosts, xs, ys, bytes_total, flops_total, rsum = [], [], [], [], 0, 0.0, 0
+    t0 = time.perf_counter()
+    for k, (surf, n) in enumerate(pop):
+        cloud = inputs.make_cloud(surf, n, seed=args.seed + k)
+        h = builder.build_operator(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6)
+        d = binding.upload(h, storage="c64", stream=stream)
+        r = int(rng.integers(1, 17))
+        inf = d.info()
+        M = inf["elems_forward"] + inf["elems_coupling"] + inf["elems_backward"] + inf["elems_near"]
+        bytes_total += 8 * M + 8 * r * 2 * cloud.n
+        flops_total += 8.0 * r * M
+        rsum += r
+        x = inputs.make_rhs(cloud.n, r, seed=args.seed + 100 + k).astype(np.complex64)
+        xs.append(torch.from_numpy(np.ascontiguousarray(x.T)).to("cuda").t())
+        ys.append(torch.empty((r, cloud.n), dtype=torch.complex64, device="cuda").t())
+        ops.append(d)
+        hosts.append((surf, cloud.n, r))
+        log(f"  op {k}: {surf} N={cloud.n} r={r} built {h.timings['total']:.1f}s")
+        del h
+    log(f"population built in {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+
+    def timed(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    def one_at_a_time():
+        for d, x, y in zip(ops, xs, ys):
+            d.matvec(x, y, stream=stream)
+
+    t_seq = timed(one_at_a_time, args.steps)
+    ref = [y.clone() for y in ys]
+    batch = binding.Batch(ops, xs, ys, stream=stream)
+    t_untuned = timed(lambda: batch.run(stream=stream), args.steps)
+    choice = batch.tune(stream=stream)
+    t_tuned = timed(lambda: batch.run(stream=stream), args.steps)
+    batch.capture(stream)
+    t_graph = timed(lambda: batch.run(stream=stream), args.steps)
+    err = max(float((torch.linalg.norm(y - r_) / torch.linalg.norm(r_)).item()) for y, r_ in zip(ys, ref))
+    line = {
+        "metric": "batched uniform-H MVPs: right-hand-side products per second, complex64, shared launches",
+        "value": rsum / (t_graph * 1e-3), "unit": "RHS-products/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 3, "ms_per_step": t_graph, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.nops} operators, N log-uniform in [4096, {args.max_n}], sphere/ellipsoid/cube, "
+                               "1-16 RHS each, complex64 storage", "operators": hosts},
+        "ms_one_operator_at_a_time": t_seq, "ms_batched_untuned": t_untuned, "ms_batched_tuned": t_tuned,
+        "ms_batched_graph": t_graph, "speedup_vs_one_at_a_time": t_seq / t_graph, "tuned_schedule": choice,
+        "gbs": bytes_total / (t_graph * 1e-3) / 1e9, "tflops": flops_total / (t_graph * 1e-3) / 1e12,
+        "max_rel_diff_vs_one_at_a_time": err,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_serving(args):
+    """Poisson arrivals of GMRES-IR solve requests over resident operators."""
+    import numpy as np
+    import torch
+
+    from paper_2405_15573_amd import builder, inputs
+    from paper_2405_15573_amd.serving import Request, Server
+    pop = mixed_population(16, 4096, args.max_n, args.seed + 1)
+    hosts = []
+    t0 = time.perf_counter()
+    for k, (surf, n) in enumerate(pop):
+        cloud = inputs.make_cloud(surf, n, seed=args.seed + k)
+        hosts.append(builder.build_operator(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6))
+        log(f"  op {k}: {surf} N={cloud.n} built {hosts[-1].timings['total']:.1f}s")
+    log(f"population built in {time.perf_counter() - t0:.1f} s")
+    srv = Server(hosts, low_storage="c64", max_iterations=1500)
+    results = {}
+    for rate in [float(v) for v in args.rates.split(",")]:
+        rng = np.random.default_rng([args.seed, 5, int(rate)])
+        t = np.cumsum(rng.exponential(1.0 / rate, size=args.requests))
+        reqs = []
+        for i in range(args.requests):
+            op = int(rng.integers(0, len(hosts)))
+            r = int(rng.integers(1, 9))
+            tol = 1e-6 if rng.random() < 0.5 else 1e-8
+            b = inputs.make_rhs(hosts[op].n, r, seed=int(rate) * 100000 + i)
+            reqs.append(Request(rid=i, op=op, b=torch.from_numpy(np.ascontiguousarray(b.T)).to("cuda").t(), tol=tol,
+                                arrival=float(t[i])))
+        log(f"rate {rate}/s: {args.requests} requests")
+        done = srv.serve(reqs, log=log)
+        results[str(int(rate))] = Server.report(done)
+        log(f"  {results[str(int(rate))]}")
+        del reqs, done
+    worst = max(results.values(), key=lambda v: v.get("p99_s", 0.0))
+    line = {
+        "metric": "p99 GMRES solve latency (served, continuous batching)", "value": worst.get("p99_s"),
+        "unit": "s", "n_gpus": 1, "steps": args.requests, "warmup": 0, "ms_per_step": None,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"16 resident operators, N log-uniform in [4096, {args.max_n}], GMRES-IR "
+                               f"(complex64 inner, FP64 residual), Poisson arrivals {args.rates}/s, "
+                               f"{args.requests} requests per rate, 1-8 RHS, tol 1e-6 or 1e-8",
+                   "operators": [(p[0], int(h.n)) for p, h in zip(pop, hosts)]},
+        "per_rate": results,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +240,19 @@ def main():
     ap.add_argument("--no-h", action="store_true")
     ap.add_argument("--no-lowp", action="store_true", help="skip the complex64 / bf16-pair multi-RHS forms")
     ap.add_argument("--lowp-rhs", type=int, default=64)
+    ap.add_argument("--no-gmres", action="store_true", help="skip the time-to-solution comparison")
+    ap.add_argument("--gmres-rhs", type=int, default=64)
+    ap.add_argument("--gmres-tol", type=float, default=1e-8)
+    ap.add_argument("--gmres-maxit", type=int, default=200)
+    ap.add_argument("--gmres-small-n", type=int, default=16384,
+                    help="size of the sphere at which the time-to-tolerance comparison runs to convergence")
+    ap.add_argument("--mode", choices=("headline", "batched", "serving"), default="headline",
+                    help="headline: the FP64 workload and its side measurements; batched: many operators in "
+                         "shared launches; serving: Poisson arrivals of GMRES solves")
+    ap.add_argument("--nops", type=int, default=32)
+    ap.add_argument("--rates", type=str, default="50,100,200,400")
+    ap.add_argument("--requests", type=int, default=200, help="requests per arrival rate (serving)")
+    ap.add_argument("--max-n", type=int, default=65536, help="largest operator of the batched / serving mixes")
     ap.add_argument("--parity-leaves", type=int, default=6)
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_sphere262k_c128.json"),
                     help="JSON file with counter-derived HBM bytes per launch (used only if it was taken on the "
@@ -100,6 +275,10 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     binding.load_library()
+    if args.mode == "batched":
+        return run_batched(args)
+    if args.mode == "serving":
+        return run_serving(args)
 
     if args.copy_calibration:
         a = torch.empty(1 << 26, dtype=torch.complex128, device="cuda")  # 1 GiB
@@ -191,6 +370,18 @@ def main():
             dl.free()
         del Xd, Yd
 
+    gm = None
+    if not args.no_gmres:
+        gm = {"full_size": run_gmres_cases(torch, binding, op, cloud.n, args.gmres_rhs, args.gmres_tol,
+                                           args.gmres_maxit, stream, args.seed)}
+        cs = inputs.make_cloud("sphere", args.gmres_small_n, seed=args.seed)
+        log(f"building the N={cs.n} sphere for the time-to-tolerance comparison")
+        ops_small = builder.build_operator(cs, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6)
+        gm["to_tolerance"] = run_gmres_cases(torch, binding, ops_small, cs.n, args.gmres_rhs, args.gmres_tol,
+                                             4000, stream, args.seed)
+        gm["to_tolerance"]["n"] = cs.n
+        gm["full_size"]["n"] = cloud.n
+
     cpu = None
     if not args.no_cpu:
         ncores = uniform.max_threads()
@@ -244,6 +435,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "precision_forms": lowp,
+        "gmres": gm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -207,6 +207,75 @@ typedef struct {
 int uhm_solve_gmres(uhm_op* op, uhm_op* inner, const void* B, int64_t ldb, void* X, int64_t ldx, int32_t nrhs,
                     double tol, const uhm_gmres_opts* opts, uhm_gmres_info* info, void* hip_stream);
 
+/*
+ * Batched products.  A batch binds a fixed set of products Y_k = A_k X_k (k < nops) over
+ * operators uploaded in one many-RHS storage form (UHM_C64, UHM_BF16PAIR or
+ * UHM_C128_MULTI); X_k, Y_k are device arrays (n_k x nrhs_k, column-major, leading
+ * dimensions ldx[k], ldy[k] >= n_k, 1 <= nrhs_k <= 64) that stay bound to the batch.
+ * uhm_batch_run executes all of them stage by stage: each stage of the product is one
+ * kernel launch over the work of every operator (work lists of (operator, leaf / tile)),
+ * so many small operators fill the GPU together.  Each operator's reductions keep their
+ * own fixed order, so a product's result does not depend on the rest of the batch.
+ * The batch owns its workspace; the operators' own workspace is not used, and the
+ * operators must outlive the batch.
+ *   uhm_batch_tune    times the candidate schedules (coupling tile width 256/512/1024/2048
+ *                     columns x work order: operator-major, largest-first, round-robin
+ *                     over cost buckets) on the device and keeps the fastest; the choice is
+ *                     cached for batches with the same signature (sizes, ranks, nrhs) in
+ *                     this process.  Outputs may be NULL.  Synchronous.
+ *   uhm_batch_capture captures the launches of one run into a hipGraph on `hip_stream`
+ *                     (not the NULL stream); later runs replay the graph.
+ *   uhm_batch_run     asynchronous on `hip_stream`; runs that overlap on different streams
+ *                     race on the batch's workspace.
+ * Errors: UHM_EINVAL (mixed or single-RHS storage, nrhs out of range, bad pointers),
+ * UHM_ENOMEM, UHM_EHIP.  This is not a construct of the paper: it batches the products of
+ * Algorithm 6 (section 4.4) of many operators.
+ */
+typedef struct uhm_batch uhm_batch;
+int uhm_batch_create(uhm_op* const* ops, int32_t nops, const void* const* X, const int64_t* ldx, void* const* Y,
+                     const int64_t* ldy, const int32_t* nrhs, void* hip_stream, uhm_batch** out);
+int uhm_batch_run(uhm_batch* b, void* hip_stream);
+int uhm_batch_tune(uhm_batch* b, void* hip_stream, int32_t* tile_width, int32_t* order, double* best_ms);
+int uhm_batch_capture(uhm_batch* b, void* hip_stream);
+void uhm_batch_free(uhm_batch* b);
+
+/*
+ * Resumable (reverse-communication) form of uhm_solve_gmres, for callers that batch the
+ * products of many solves (a serving loop).  The solve owns its Krylov workspace and stops
+ * whenever it needs a product:
+ *   uhm_krylov_next    returns UHM_KRYLOV_PRODUCT_HIGH (the caller writes A*in to out with
+ *                      the FP64 operator), UHM_KRYLOV_PRODUCT_LOW (the product with the
+ *                      low-precision operator; in/out are still complex128, the caller
+ *                      converts), or UHM_KRYLOV_DONE.  in/out: n x nrhs complex128 device
+ *                      arrays, leading dimension n, owned by the solve.
+ *   uhm_krylov_advance after the product is in out: runs the FP64 Arnoldi / refinement work
+ *                      on the solve's stream and prepares the next request.  Synchronous.
+ *   uhm_krylov_result  after DONE: X (ldx >= n, may be NULL) receives the solution, *info
+ *                      (may be NULL) the counts; returns UHM_OK or UHM_ENOCONV.
+ * mixed = 0: plain GMRES(m) with FP64 products; mixed = 1: GMRES-IR as uhm_solve_gmres
+ * with an inner operator.  B is copied at creation.  Errors as uhm_solve_gmres.
+ */
+enum { UHM_KRYLOV_DONE = 0, UHM_KRYLOV_PRODUCT_HIGH = 1, UHM_KRYLOV_PRODUCT_LOW = 2 };
+typedef struct uhm_krylov uhm_krylov;
+int uhm_krylov_create(int64_t n, int32_t nrhs, const void* B, int64_t ldb, double tol, int32_t mixed,
+                      const uhm_gmres_opts* opts, void* hip_stream, uhm_krylov** out);
+int uhm_krylov_next(uhm_krylov* k, const void** in, void** out);
+int uhm_krylov_advance(uhm_krylov* k);
+int uhm_krylov_result(uhm_krylov* k, void* X, int64_t ldx, uhm_gmres_info* info);
+void uhm_krylov_free(uhm_krylov* k);
+
+/*
+ * One step of many solves at once (continuous batching): every solve with a pending
+ * request gets its product, grouped by (operator, precision) into multi-column products of
+ * up to 64 columns (complex64 conversion for the low-precision ones), then every solve
+ * advances.  high[k] / low[k] are solve k's FP64 and low-precision operators (low may be
+ * NULL when no solve is mixed).  The operators' staging buffers grow as needed.  A solve's
+ * columns are products of its own Krylov vectors only, and each product column does not
+ * depend on the others, so a solve's iterates are the same alone or in any mix.
+ * Returns the number of solves still running, or a negative error code.
+ */
+int uhm_krylov_step(uhm_krylov* const* ks, uhm_op* const* high, uhm_op* const* low, int32_t count, void* hip_stream);
+
 /* Fill *info for an uploaded operator.  Errors: UHM_EINVAL. */
 int uhm_op_info_get(const uhm_op* op, uhm_op_info* info);
 

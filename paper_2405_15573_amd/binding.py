@@ -54,7 +54,12 @@ class GmresInfo(ctypes.Structure):
                 ("seconds_products", ctypes.c_double), ("seconds_arnoldi", ctypes.c_double)]
 
 
-EXPORTS = ("uhm_upload", "uhm_upload_h", "uhm_matvec", "uhm_solve_gmres", "uhm_op_info_get", "uhm_set_timing",
+KRYLOV_DONE, KRYLOV_PRODUCT_HIGH, KRYLOV_PRODUCT_LOW = 0, 1, 2
+
+EXPORTS = ("uhm_upload", "uhm_upload_h", "uhm_matvec", "uhm_solve_gmres", "uhm_krylov_create", "uhm_krylov_next",
+           "uhm_krylov_advance", "uhm_krylov_result", "uhm_krylov_free", "uhm_krylov_step",
+           "uhm_batch_create", "uhm_batch_run",
+           "uhm_batch_tune", "uhm_batch_capture", "uhm_batch_free", "uhm_op_info_get", "uhm_set_timing",
            "uhm_kernel_times", "uhm_free", "uhm_strerror", "uhm_last_error", "uhm_version")
 
 _LIB = None
@@ -77,6 +82,30 @@ def load_library(path: str = LIB_PATH):
     lib.uhm_solve_gmres.argtypes = [P, P, P, I64, P, I64, I32, ctypes.c_double, ctypes.POINTER(GmresOpts),
                                     ctypes.POINTER(GmresInfo), P]
     lib.uhm_solve_gmres.restype = ctypes.c_int
+    lib.uhm_krylov_create.argtypes = [I64, I32, P, I64, ctypes.c_double, I32, ctypes.POINTER(GmresOpts), P,
+                                      ctypes.POINTER(P)]
+    lib.uhm_krylov_create.restype = ctypes.c_int
+    lib.uhm_krylov_next.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P)]
+    lib.uhm_krylov_next.restype = ctypes.c_int
+    lib.uhm_krylov_advance.argtypes = [P]
+    lib.uhm_krylov_advance.restype = ctypes.c_int
+    lib.uhm_krylov_result.argtypes = [P, P, I64, ctypes.POINTER(GmresInfo)]
+    lib.uhm_krylov_result.restype = ctypes.c_int
+    lib.uhm_krylov_free.argtypes = [P]
+    lib.uhm_krylov_free.restype = None
+    lib.uhm_krylov_step.argtypes = [ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), I32, P]
+    lib.uhm_krylov_step.restype = ctypes.c_int
+    lib.uhm_batch_create.argtypes = [ctypes.POINTER(P), I32, ctypes.POINTER(P), ctypes.POINTER(I64), ctypes.POINTER(P),
+                                     ctypes.POINTER(I64), ctypes.POINTER(I32), P, ctypes.POINTER(P)]
+    lib.uhm_batch_create.restype = ctypes.c_int
+    lib.uhm_batch_run.argtypes = [P, P]
+    lib.uhm_batch_run.restype = ctypes.c_int
+    lib.uhm_batch_tune.argtypes = [P, P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double)]
+    lib.uhm_batch_tune.restype = ctypes.c_int
+    lib.uhm_batch_capture.argtypes = [P, P]
+    lib.uhm_batch_capture.restype = ctypes.c_int
+    lib.uhm_batch_free.argtypes = [P]
+    lib.uhm_batch_free.restype = None
     lib.uhm_op_info_get.argtypes = [P, ctypes.POINTER(OpInfo)]
     lib.uhm_op_info_get.restype = ctypes.c_int
     lib.uhm_set_timing.argtypes = [P, ctypes.c_int]
@@ -307,3 +336,129 @@ def solve_gmres(op: DeviceOperator, b, tol: float, inner: DeviceOperator | None 
         raise UhmError(rc, "uhm_solve_gmres")
     out = x if x is not None else (x2.reshape(op.n) if vec else x2)
     return out, info, rc
+
+
+class Batch:
+    """A bound set of products Y_k = A_k X_k run stage by stage in shared launches.
+
+    xs, ys: column-major device tensors (n_k, r_k) (or (n_k,)) of the operators' dtype;
+    they stay bound to the batch (keep them alive)."""
+
+    def __init__(self, ops, xs, ys, stream=None):
+        import torch
+        k = len(ops)
+        self._keep = (list(ops), list(xs), list(ys))
+        oph = (P * k)(*[o.handle for o in ops])
+        xp, yp = (P * k)(), (P * k)()
+        ldx, ldy, nr = (I64 * k)(), (I64 * k)(), (I32 * k)()
+        for i, (o, x, y) in enumerate(zip(ops, xs, ys)):
+            want = torch.complex128 if o.storage in C128_FORMS else torch.complex64
+            x2 = x.reshape(o.n, 1) if x.dim() == 1 else x
+            y2 = y.reshape(o.n, 1) if y.dim() == 1 else y
+            if x2.dtype != want or y2.dtype != want or x2.stride(0) != 1 or y2.stride(0) != 1:
+                raise ValueError("batch vectors must be column-major tensors of the operator's dtype")
+            xp[i] = x2.data_ptr()
+            yp[i] = y2.data_ptr()
+            ldx[i] = x2.stride(1) if x2.shape[1] > 1 else o.n
+            ldy[i] = y2.stride(1) if y2.shape[1] > 1 else o.n
+            nr[i] = x2.shape[1]
+        out = P()
+        sh, _ = _stream_handle(stream)
+        _check(load_library().uhm_batch_create(oph, k, xp, ldx, yp, ldy, nr, sh, ctypes.byref(out)), "uhm_batch_create")
+        self._h = out
+
+    def run(self, stream=None):
+        sh, _ = _stream_handle(stream)
+        _check(load_library().uhm_batch_run(self._h, sh), "uhm_batch_run")
+
+    def tune(self, stream=None):
+        w, o, ms = I32(), I32(), ctypes.c_double()
+        sh, _ = _stream_handle(stream)
+        _check(load_library().uhm_batch_tune(self._h, sh, ctypes.byref(w), ctypes.byref(o), ctypes.byref(ms)),
+               "uhm_batch_tune")
+        return {"tile_width": w.value, "order": o.value, "best_ms": ms.value}
+
+    def capture(self, stream):
+        sh, _ = _stream_handle(stream)
+        _check(load_library().uhm_batch_capture(self._h, sh), "uhm_batch_capture")
+
+    def free(self):
+        if getattr(self, "_h", None):
+            load_library().uhm_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Krylov:
+    """A resumable GMRES / GMRES-IR solve of A X = B (reverse communication).
+
+    The products are performed by the caller: alone through `product`, or for many solves
+    at once through `krylov_step`."""
+
+    def __init__(self, b, tol: float, mixed: bool, restart: int = 50, max_iterations: int = 2000,
+                 max_refinements: int = 30, inner_tol: float = 1e-4, stream=None):
+        import torch
+        b2 = b.reshape(-1, 1) if b.dim() == 1 else b
+        if b2.dtype != torch.complex128:
+            raise ValueError("b must be complex128")
+        if b2.stride(0) != 1:
+            b2 = b2.t().contiguous().t()
+        self.n, self.r = b2.shape
+        ldb = b2.stride(1) if self.r > 1 else self.n
+        o = GmresOpts(restart, max_iterations, max_refinements, inner_tol)
+        out = P()
+        sh, _ = _stream_handle(stream)
+        _check(load_library().uhm_krylov_create(self.n, self.r, ctypes.c_void_p(b2.data_ptr()), ldb, float(tol),
+                                                int(bool(mixed)), ctypes.byref(o), sh, ctypes.byref(out)),
+               "uhm_krylov_create")
+        self._h = out
+        self.mixed = bool(mixed)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def pending(self) -> int:
+        return load_library().uhm_krylov_next(self._h, None, None)
+
+    def result(self, x=None):
+        """Returns (x, info, code); x: (n, r) complex128 tensor (allocated if None)."""
+        import torch
+        if x is None:
+            x = torch.empty((self.r, self.n), dtype=torch.complex128, device="cuda").t()
+        ldx = x.stride(1) if self.r > 1 else self.n
+        inf = GmresInfo()
+        rc = load_library().uhm_krylov_result(self._h, ctypes.c_void_p(x.data_ptr()), ldx, ctypes.byref(inf))
+        if rc not in (UHM_OK, UHM_ENOCONV):
+            raise UhmError(rc, "uhm_krylov_result")
+        return x, {name: getattr(inf, name) for name, _ in GmresInfo._fields_}, rc
+
+    def free(self):
+        if getattr(self, "_h", None):
+            load_library().uhm_krylov_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def krylov_step(solves, highs, lows=None, stream=None) -> int:
+    """Advance many solves by one product each (grouped per operator).  Returns the number
+    still running."""
+    k = len(solves)
+    hs = (P * k)(*[s.handle for s in solves])
+    hi = (P * k)(*[o.handle for o in highs])
+    lo = (P * k)(*[(o.handle if o is not None else None) for o in lows]) if lows is not None else None
+    sh, _ = _stream_handle(stream)
+    rc = load_library().uhm_krylov_step(hs, hi, lo, k, sh)
+    if rc < 0:
+        raise UhmError(rc, "uhm_krylov_step")
+    return rc

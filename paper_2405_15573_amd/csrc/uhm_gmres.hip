@@ -19,6 +19,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <map>
 
 namespace uhm_detail {
 namespace {
@@ -221,6 +222,26 @@ __global__ __launch_bounds__(kGB) void k_g_add(const cd* __restrict__ d, int64_t
 
 unsigned nblk(int64_t q) { return (unsigned)((q + kGB - 1) / kGB); }
 
+// dst (ldd) columns [0, r) <- src (lds) columns, converting complex128 -> complex64
+__global__ __launch_bounds__(kGB) void k_g_pack32(const cd* __restrict__ src, int64_t lds, int64_t n, int r,
+                                                  cf* __restrict__ dst, int64_t ldd) {
+  const int64_t q = (int64_t)blockIdx.x * kGB + threadIdx.x;
+  if (q >= n * r) return;
+  const int c = (int)(q / n);
+  const int64_t row = q - (int64_t)c * n;
+  const cd v = src[(int64_t)c * lds + row];
+  dst[(int64_t)c * ldd + row] = make_float2((float)v.x, (float)v.y);
+}
+__global__ __launch_bounds__(kGB) void k_g_unpack32(const cf* __restrict__ src, int64_t lds, int64_t n, int r,
+                                                    cd* __restrict__ dst, int64_t ldd) {
+  const int64_t q = (int64_t)blockIdx.x * kGB + threadIdx.x;
+  if (q >= n * r) return;
+  const int c = (int)(q / n);
+  const int64_t row = q - (int64_t)c * n;
+  const cf v = src[(int64_t)c * lds + row];
+  dst[(int64_t)c * ldd + row] = make_double2((double)v.x, (double)v.y);
+}
+
 using C = std::complex<double>;
 using Clock = std::chrono::steady_clock;
 
@@ -248,24 +269,6 @@ int alloc_work(Work& W, int64_t n, int r, int m, bool lowp) {
   return UHM_OK;
 }
 
-// y = A x for contiguous n x r FP64 arrays, with A in any storage.
-int apply(uhm_op* A, Work& W, const cd* x, cd* y, hipStream_t s) {
-  const auto t0 = Clock::now();
-  int rc;
-  if (A->storage == UHM_C128 || A->storage == UHM_C128_MULTI) {
-    rc = uhm_matvec(A, x, W.n, y, W.n, W.r, s);
-  } else {
-    const int64_t nq = W.n * W.r;
-    hipLaunchKernelGGL(k_g_to32, dim3(nblk(nq)), dim3(kGB), 0, s, x, nq, W.x32.p);
-    rc = uhm_matvec(A, W.x32.p, W.n, W.y32.p, W.n, W.r, s);
-    if (rc == UHM_OK) hipLaunchKernelGGL(k_g_to64, dim3(nblk(nq)), dim3(kGB), 0, s, W.y32.p, nq, y);
-  }
-  if (rc) return rc;
-  UHM_HIP(hipStreamSynchronize(s));
-  W.t_prod += std::chrono::duration<double>(Clock::now() - t0).count();
-  return UHM_OK;
-}
-
 // Column norms of a contiguous n x r array.
 int norms(Work& W, const cd* a, std::vector<double>& out, hipStream_t s) {
   hipLaunchKernelGGL(k_g_sqnorm, dim3(W.nch, W.r), dim3(kGB), 0, s, a, W.n, W.nch, W.nrm.p);
@@ -276,137 +279,239 @@ int norms(Work& W, const cd* a, std::vector<double>& out, hipStream_t s) {
   return UHM_OK;
 }
 
-// Restarted GMRES(m) for A d = rhs (contiguous n x r), from d = 0 (W.d), until
-// ||rhs - A d_c|| <= rtol_c (per column) or `budget` Krylov iterations in total.
-int gmres_cycles(uhm_op* A, Work& W, const cd* rhs, const std::vector<double>& rtol, int budget, int& iters,
-                 int& restarts, std::vector<char>& done, hipStream_t s) {
-  const int r = W.r, m = W.m;
-  const int64_t n = W.n, vstride = n * r;
+}  // namespace
+}  // namespace uhm_detail
+
+// ------------------------------------------------------------------ resumable solve
+// The solve is a state machine that stops whenever it needs a product.  The caller reads
+// the request (vector, output buffer, precision), computes the product any way it likes
+// (alone, or batched with the requests of other solves) and calls advance.
+
+struct uhm_krylov {
+  using cd = uhm_detail::cd;
+  template <class T>
+  using DevArray = uhm_detail::DevArray<T>;
+  uhm_detail::Work W;
+  int64_t n = 0;
+  int r = 0;
+  double tol = 0.0;
+  uhm_gmres_opts o{};
+  bool mixed = false;
+  hipStream_t s = nullptr;
+  DevArray<cd> Bc, xacc, res, rhs;
+  // request
+  int req = UHM_KRYLOV_DONE;  // UHM_KRYLOV_PRODUCT_HIGH / _LOW / DONE
+  const void* req_in = nullptr;
+  void* req_out = nullptr;
+  // bookkeeping
+  enum Phase { ITER, CYCLE_END, INNER_FINAL_X, OUTER, FINISHED } phase = FINISHED;
+  std::vector<double> bn, rn, rtol, beta, hn, sc;
+  std::vector<std::complex<double>> H, g, cs, sn;
+  std::vector<cd> hh, hp;
+  std::vector<int> jc;
+  std::vector<char> active, done;
+  int j = 0;
+  int iters = 0, restarts = 0, refinements = 0, cycles = 0;
+  double t_arn = 0.0;
+  int status = UHM_OK;
+};
+
+namespace uhm_detail {
+namespace {
+
+// t = current inner residual; start a cycle, or finish the inner solve.
+int cycle_start(uhm_krylov* K) {
+  Work& W = K->W;
+  const int r = K->r, m = K->o.restart;
+  const int64_t n = K->n;
+  hipStream_t s = K->s;
   int rc;
-  UHM_HIP(hipMemsetAsync(W.d.p, 0, sizeof(cd) * (size_t)(n * r), s));
-  UHM_HIP(hipMemcpyAsync(W.t.p, rhs, sizeof(cd) * (size_t)(n * r), hipMemcpyDeviceToDevice, s));
-  bool first = true;
-  std::vector<double> beta;
-  std::vector<C> H((size_t)(m + 1) * m * r), g((size_t)(m + 1) * r), cs((size_t)m * r), sn((size_t)m * r);
-  std::vector<cd> hh((size_t)(m + 1) * r), hp;
-  std::vector<int> jc(r);
-  std::vector<double> sc(r), hn(r);
-  while (true) {
-    if ((rc = norms(W, W.t.p, beta, s))) return rc;
-    bool all = true;
-    for (int c = 0; c < r; ++c) {
-      done[c] = beta[c] <= rtol[c];
-      all = all && done[c];
+  if ((rc = norms(W, W.t.p, K->beta, s))) return rc;
+  bool all = true;
+  for (int c = 0; c < r; ++c) {
+    K->done[c] = K->beta[c] <= K->rtol[c];
+    all = all && K->done[c];
+  }
+  if (all || K->iters >= K->o.max_iterations) {
+    // inner solve finished: d is in W.d
+    if (K->mixed) {
+      hipLaunchKernelGGL(k_g_add, dim3(nblk(n * r)), dim3(kGB), 0, s, W.d.p, n, r, K->xacc.p, n, 0);
+      K->phase = uhm_krylov::OUTER;
+      K->req = UHM_KRYLOV_PRODUCT_HIGH;
+      K->req_in = K->xacc.p;
+      K->req_out = W.w.p;
+    } else {
+      K->phase = uhm_krylov::INNER_FINAL_X;
+      K->req = UHM_KRYLOV_PRODUCT_HIGH;
+      K->req_in = W.d.p;
+      K->req_out = W.w.p;
     }
-    if (all || iters >= budget) return UHM_OK;
-    if (!first) ++restarts;
-    first = false;
-    for (int c = 0; c < r; ++c) sc[c] = beta[c] > 0.0 ? 1.0 / beta[c] : 0.0;
-    UHM_HIP(hipMemcpyAsync(W.nrm_out.p, sc.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_g_scale, dim3(nblk(n * r)), dim3(kGB), 0, s, W.t.p, W.nrm_out.p, n, r, W.V.p);
-    std::fill(g.begin(), g.end(), C(0.0));
-    std::vector<char> active(r);
-    for (int c = 0; c < r; ++c) {
-      g[(size_t)c * (m + 1)] = C(beta[c]);
-      jc[c] = 0;
-      active[c] = !done[c];
-    }
-    int j = 0;
-    for (; j < m && iters < budget; ++j) {
-      if ((rc = apply(A, W, W.V.p + (int64_t)j * vstride, W.w.p, s))) return rc;
-      ++iters;
-      const auto ta = Clock::now();
-      hp.resize((size_t)(j + 1) * r);
-      for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(k_g_dots, dim3(W.nch, r), dim3(kGB), 0, s, W.V.p, vstride, j + 1, W.w.p, n, r, W.nch,
-                           W.part.p);
-        hipLaunchKernelGGL(k_g_reduce, dim3(nblk((int64_t)(j + 1) * r)), dim3(kGB), 0, s, W.part.p, W.nch,
-                           (int64_t)(j + 1) * r, W.hbuf.p);
-        hipLaunchKernelGGL(k_g_update, dim3(W.nch, r), dim3(kGB), 0, s, W.V.p, vstride, j + 1, W.hbuf.p, W.w.p, n, r,
-                           W.nch, W.nrm.p);
-        UHM_HIP(hipMemcpyAsync(hp.data(), W.hbuf.p, sizeof(cd) * hp.size(), hipMemcpyDeviceToHost, s));
-        UHM_HIP(hipStreamSynchronize(s));
-        for (size_t q = 0; q < hp.size(); ++q) {
-          if (pass == 0) {
-            hh[q] = hp[q];
-          } else {
-            hh[q].x += hp[q].x;
-            hh[q].y += hp[q].y;
-          }
-        }
-      }
-      hipLaunchKernelGGL(k_g_norm, dim3((r + 63) / 64), dim3(64), 0, s, W.nrm.p, W.nch, r, W.nrm_out.p);
-      UHM_HIP(hipMemcpyAsync(hn.data(), W.nrm_out.p, sizeof(double) * r, hipMemcpyDeviceToHost, s));
-      UHM_HIP(hipStreamSynchronize(s));
-      bool all_done = true;
-      for (int c = 0; c < r; ++c) {
-        sc[c] = 0.0;
-        if (!active[c]) continue;
-        C* col = &H[((size_t)c * m + j) * (m + 1)];
-        for (int i = 0; i <= j; ++i) col[i] = C(hh[(size_t)i * r + c].x, hh[(size_t)i * r + c].y);
-        col[j + 1] = C(hn[c]);
-        sc[c] = hn[c] > 1e-300 ? 1.0 / hn[c] : 0.0;
-        for (int i = 0; i < j; ++i) {
-          const C a = col[i], b = col[i + 1];
-          const C ci = cs[(size_t)c * m + i], si = sn[(size_t)c * m + i];
-          col[i] = std::conj(ci) * a + std::conj(si) * b;
-          col[i + 1] = -si * a + ci * b;
-        }
-        const C a = col[j], b = col[j + 1];
-        const double den = std::sqrt(std::norm(a) + std::norm(b));
-        C cj(1.0), sj(0.0);
-        if (den > 0.0) {
-          cj = a / den;
-          sj = b / den;
-        }
-        cs[(size_t)c * m + j] = cj;
-        sn[(size_t)c * m + j] = sj;
-        col[j] = std::conj(cj) * a + std::conj(sj) * b;
-        col[j + 1] = C(0.0);
-        C* gc = &g[(size_t)c * (m + 1)];
-        const C gj = gc[j];
-        gc[j] = std::conj(cj) * gj;
-        gc[j + 1] = -sj * gj;
-        jc[c] = j + 1;
-        if (std::abs(gc[j + 1]) <= rtol[c] || hn[c] <= 1e-300) active[c] = 0;
-        all_done = all_done && !active[c];
-      }
-      UHM_HIP(hipMemcpyAsync(W.nrm_out.p, sc.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_g_scale, dim3(nblk(n * r)), dim3(kGB), 0, s, W.w.p, W.nrm_out.p, n, r,
-                         W.V.p + (int64_t)(j + 1) * vstride);
-      UHM_HIP(hipStreamSynchronize(s));
-      W.t_arn += std::chrono::duration<double>(Clock::now() - ta).count();
-      if (all_done) {
-        ++j;
-        break;
-      }
-    }
-    // y_c = R_c^{-1} g_c (back substitution), d += V y
-    const auto ta = Clock::now();
-    const int jm = j;
-    if (jm > 0) {
-      std::vector<cd> yv((size_t)jm * r, make_double2(0.0, 0.0));
-      for (int c = 0; c < r; ++c) {
-        const int k = jc[c];
-        const C* Hc = &H[(size_t)c * m * (m + 1)];
-        const C* gc = &g[(size_t)c * (m + 1)];
-        std::vector<C> y(k);
-        for (int i = k - 1; i >= 0; --i) {
-          C acc = gc[i];
-          for (int q = i + 1; q < k; ++q) acc -= Hc[(size_t)q * (m + 1) + i] * y[q];
-          const C dgl = Hc[(size_t)i * (m + 1) + i];
-          y[i] = std::abs(dgl) > 0.0 ? acc / dgl : C(0.0);
-        }
-        for (int i = 0; i < k; ++i) yv[(size_t)i * r + c] = make_double2(y[i].real(), y[i].imag());
-      }
-      UHM_HIP(hipMemcpyAsync(W.ybuf.p, yv.data(), sizeof(cd) * yv.size(), hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_g_combine, dim3(nblk(n * r)), dim3(kGB), 0, s, W.V.p, vstride, jm, W.ybuf.p, W.d.p, n, n, r);
-    }
+    return UHM_OK;
+  }
+  if (K->cycles++ > 0) ++K->restarts;
+  for (int c = 0; c < r; ++c) K->sc[c] = K->beta[c] > 0.0 ? 1.0 / K->beta[c] : 0.0;
+  UHM_HIP(hipMemcpyAsync(W.nrm_out.p, K->sc.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_g_scale, dim3(nblk(n * r)), dim3(kGB), 0, s, W.t.p, W.nrm_out.p, n, r, W.V.p);
+  std::fill(K->g.begin(), K->g.end(), C(0.0));
+  for (int c = 0; c < r; ++c) {
+    K->g[(size_t)c * (m + 1)] = C(K->beta[c]);
+    K->jc[c] = 0;
+    K->active[c] = !K->done[c];
+  }
+  K->j = 0;
+  K->phase = uhm_krylov::ITER;
+  K->req = K->mixed ? UHM_KRYLOV_PRODUCT_LOW : UHM_KRYLOV_PRODUCT_HIGH;
+  K->req_in = W.V.p;
+  K->req_out = W.w.p;
+  return UHM_OK;
+}
+
+// Start an inner solve of A d = rhs_src (contiguous) to the per-column tolerances in K->rtol.
+int inner_start(uhm_krylov* K, const cd* rhs_src) {
+  Work& W = K->W;
+  const int64_t nr = K->n * K->r;
+  UHM_HIP(hipMemcpyAsync(K->rhs.p, rhs_src, sizeof(cd) * (size_t)nr, hipMemcpyDeviceToDevice, K->s));
+  UHM_HIP(hipMemsetAsync(W.d.p, 0, sizeof(cd) * (size_t)nr, K->s));
+  UHM_HIP(hipMemcpyAsync(W.t.p, K->rhs.p, sizeof(cd) * (size_t)nr, hipMemcpyDeviceToDevice, K->s));
+  K->cycles = 0;
+  return cycle_start(K);
+}
+
+// One Arnoldi step after the product W.w = A V_j.
+int arnoldi_step(uhm_krylov* K) {
+  Work& W = K->W;
+  const int r = K->r, m = K->o.restart, j = K->j;
+  const int64_t n = K->n, vstride = n * r;
+  hipStream_t s = K->s;
+  ++K->iters;
+  K->hp.resize((size_t)(j + 1) * r);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_g_dots, dim3(W.nch, r), dim3(kGB), 0, s, W.V.p, vstride, j + 1, W.w.p, n, r, W.nch, W.part.p);
+    hipLaunchKernelGGL(k_g_reduce, dim3(nblk((int64_t)(j + 1) * r)), dim3(kGB), 0, s, W.part.p, W.nch,
+                       (int64_t)(j + 1) * r, W.hbuf.p);
+    hipLaunchKernelGGL(k_g_update, dim3(W.nch, r), dim3(kGB), 0, s, W.V.p, vstride, j + 1, W.hbuf.p, W.w.p, n, r, W.nch,
+                       W.nrm.p);
+    UHM_HIP(hipMemcpyAsync(K->hp.data(), W.hbuf.p, sizeof(cd) * K->hp.size(), hipMemcpyDeviceToHost, s));
     UHM_HIP(hipStreamSynchronize(s));
-    W.t_arn += std::chrono::duration<double>(Clock::now() - ta).count();
-    // residual for the next cycle: t = rhs - A d
-    if ((rc = apply(A, W, W.d.p, W.w.p, s))) return rc;
-    hipLaunchKernelGGL(k_g_sub, dim3(nblk(n * r)), dim3(kGB), 0, s, rhs, n, W.w.p, n, r, W.t.p);
+    for (size_t q = 0; q < K->hp.size(); ++q) {
+      if (pass == 0) {
+        K->hh[q] = K->hp[q];
+      } else {
+        K->hh[q].x += K->hp[q].x;
+        K->hh[q].y += K->hp[q].y;
+      }
+    }
+  }
+  hipLaunchKernelGGL(k_g_norm, dim3((r + 63) / 64), dim3(64), 0, s, W.nrm.p, W.nch, r, W.nrm_out.p);
+  UHM_HIP(hipMemcpyAsync(K->hn.data(), W.nrm_out.p, sizeof(double) * r, hipMemcpyDeviceToHost, s));
+  UHM_HIP(hipStreamSynchronize(s));
+  bool all_done = true;
+  for (int c = 0; c < r; ++c) {
+    K->sc[c] = 0.0;
+    if (!K->active[c]) continue;
+    C* col = &K->H[((size_t)c * m + j) * (m + 1)];
+    for (int i = 0; i <= j; ++i) col[i] = C(K->hh[(size_t)i * r + c].x, K->hh[(size_t)i * r + c].y);
+    col[j + 1] = C(K->hn[c]);
+    K->sc[c] = K->hn[c] > 1e-300 ? 1.0 / K->hn[c] : 0.0;
+    for (int i = 0; i < j; ++i) {
+      const C a = col[i], b = col[i + 1];
+      const C ci = K->cs[(size_t)c * m + i], si = K->sn[(size_t)c * m + i];
+      col[i] = std::conj(ci) * a + std::conj(si) * b;
+      col[i + 1] = -si * a + ci * b;
+    }
+    const C a = col[j], b = col[j + 1];
+    const double den = std::sqrt(std::norm(a) + std::norm(b));
+    C cj(1.0), sj(0.0);
+    if (den > 0.0) {
+      cj = a / den;
+      sj = b / den;
+    }
+    K->cs[(size_t)c * m + j] = cj;
+    K->sn[(size_t)c * m + j] = sj;
+    col[j] = std::conj(cj) * a + std::conj(sj) * b;
+    col[j + 1] = C(0.0);
+    C* gc = &K->g[(size_t)c * (m + 1)];
+    const C gj = gc[j];
+    gc[j] = std::conj(cj) * gj;
+    gc[j + 1] = -sj * gj;
+    K->jc[c] = j + 1;
+    if (std::abs(gc[j + 1]) <= K->rtol[c] || K->hn[c] <= 1e-300) K->active[c] = 0;
+    all_done = all_done && !K->active[c];
+  }
+  UHM_HIP(hipMemcpyAsync(W.nrm_out.p, K->sc.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_g_scale, dim3(nblk(n * r)), dim3(kGB), 0, s, W.w.p, W.nrm_out.p, n, r,
+                     W.V.p + (int64_t)(j + 1) * vstride);
+  K->j = j + 1;
+  if (!all_done && K->j < m && K->iters < K->o.max_iterations) {
+    K->req = K->mixed ? UHM_KRYLOV_PRODUCT_LOW : UHM_KRYLOV_PRODUCT_HIGH;
+    K->req_in = W.V.p + (int64_t)K->j * vstride;
+    K->req_out = W.w.p;
+    return UHM_OK;
+  }
+  // end of the cycle: y_c = R_c^{-1} g_c, d += V y, then the residual t = rhs - A d
+  const int jm = K->j;
+  std::vector<cd> yv((size_t)jm * r, make_double2(0.0, 0.0));
+  for (int c = 0; c < r; ++c) {
+    const int k = K->jc[c];
+    const C* Hc = &K->H[(size_t)c * m * (m + 1)];
+    const C* gc = &K->g[(size_t)c * (m + 1)];
+    std::vector<C> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+      C acc = gc[i];
+      for (int q = i + 1; q < k; ++q) acc -= Hc[(size_t)q * (m + 1) + i] * y[q];
+      const C dgl = Hc[(size_t)i * (m + 1) + i];
+      y[i] = std::abs(dgl) > 0.0 ? acc / dgl : C(0.0);
+    }
+    for (int i = 0; i < k; ++i) yv[(size_t)i * r + c] = make_double2(y[i].real(), y[i].imag());
+  }
+  UHM_HIP(hipMemcpyAsync(W.ybuf.p, yv.data(), sizeof(cd) * yv.size(), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_g_combine, dim3(nblk(n * r)), dim3(kGB), 0, s, W.V.p, vstride, jm, W.ybuf.p, W.d.p, n, n, r);
+  UHM_HIP(hipStreamSynchronize(s));
+  K->phase = uhm_krylov::CYCLE_END;
+  K->req = K->mixed ? UHM_KRYLOV_PRODUCT_LOW : UHM_KRYLOV_PRODUCT_HIGH;
+  K->req_in = W.d.p;
+  K->req_out = W.w.p;
+  return UHM_OK;
+}
+
+int advance(uhm_krylov* K) {
+  Work& W = K->W;
+  const int r = K->r;
+  const int64_t n = K->n;
+  hipStream_t s = K->s;
+  switch (K->phase) {
+    case uhm_krylov::ITER:
+      return arnoldi_step(K);
+    case uhm_krylov::CYCLE_END:
+      hipLaunchKernelGGL(k_g_sub, dim3(nblk(n * r)), dim3(kGB), 0, s, K->rhs.p, n, W.w.p, n, r, W.t.p);
+      return cycle_start(K);
+    case uhm_krylov::INNER_FINAL_X: {
+      // plain GMRES: x = d, true residual from the product
+      UHM_HIP(hipMemcpyAsync(K->xacc.p, W.d.p, sizeof(cd) * (size_t)(n * r), hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(k_g_sub, dim3(nblk(n * r)), dim3(kGB), 0, s, K->Bc.p, n, W.w.p, n, r, K->res.p);
+      int rc = norms(W, K->res.p, K->rn, s);
+      if (rc) return rc;
+      K->phase = uhm_krylov::FINISHED;
+      K->req = UHM_KRYLOV_DONE;
+      return UHM_OK;
+    }
+    case uhm_krylov::OUTER: {
+      hipLaunchKernelGGL(k_g_sub, dim3(nblk(n * r)), dim3(kGB), 0, s, K->Bc.p, n, W.w.p, n, r, K->res.p);
+      int rc = norms(W, K->res.p, K->rn, s);
+      if (rc) return rc;
+      ++K->refinements;
+      bool all = true;
+      for (int c = 0; c < r; ++c) all = all && K->rn[c] <= K->tol * K->bn[c];
+      if (all || K->refinements >= K->o.max_refinements || K->iters >= K->o.max_iterations) {
+        K->phase = uhm_krylov::FINISHED;
+        K->req = UHM_KRYLOV_DONE;
+        return UHM_OK;
+      }
+      for (int c = 0; c < r; ++c) K->rtol[c] = K->o.inner_tol * K->rn[c];
+      return inner_start(K, K->res.p);
+    }
+    default:
+      return fail(UHM_EINVAL, "the solve needs no product");
   }
 }
 
@@ -415,80 +520,240 @@ int gmres_cycles(uhm_op* A, Work& W, const cd* rhs, const std::vector<double>& r
 
 using namespace uhm_detail;
 
-extern "C" int uhm_solve_gmres(uhm_op* op, uhm_op* inner, const void* B, int64_t ldb, void* X, int64_t ldx, int32_t nrhs,
-                               double tol, const uhm_gmres_opts* opts, uhm_gmres_info* info, void* hip_stream) {
-  if (!op || !B || !X) return fail(UHM_EINVAL, "null argument");
-  if ((op->storage != UHM_C128 && op->storage != UHM_C128_MULTI) || op->kind != 0)
-    return fail(UHM_EINVAL, "the residual operator must be a complex128 UH-matrix");
-  if (inner && (inner->storage == UHM_C128 || inner->storage == UHM_C128_MULTI || inner->n != op->n))
-    return fail(UHM_EINVAL, "the inner operator must be a low-precision form of the same size");
-  if (nrhs < 1 || ldb < op->n || ldx < op->n || !(tol > 0.0)) return fail(UHM_EINVAL, "bad nrhs, leading dimension or tol");
+extern "C" {
+
+int uhm_krylov_create(int64_t n, int32_t nrhs, const void* B, int64_t ldb, double tol, int32_t mixed,
+                      const uhm_gmres_opts* opts, void* hip_stream, uhm_krylov** out) {
+  if (!out || !B) return fail(UHM_EINVAL, "null argument");
+  *out = nullptr;
+  if (n < 1 || nrhs < 1 || ldb < n || !(tol > 0.0)) return fail(UHM_EINVAL, "bad n, nrhs, leading dimension or tol");
   uhm_gmres_opts o{50, 2000, 30, 1e-4};
   if (opts) o = *opts;
   if (o.restart < 1 || o.max_iterations < 1 || o.max_refinements < 1 || !(o.inner_tol > 0.0) || o.inner_tol >= 1.0)
     return fail(UHM_EINVAL, "bad GMRES options");
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  const auto t0 = Clock::now();
-  const int64_t n = op->n;
-  const int r = nrhs;
-  Work W;
-  int rc = alloc_work(W, n, r, o.restart, inner != nullptr);
-  if (rc) return rc;
-  DevArray<cd> Bc, xacc, res;
-  if ((rc = Bc.alloc(n * r)) || (rc = res.alloc(n * r))) return rc;
-  hipLaunchKernelGGL(k_g_copy_strided, dim3(nblk(n * r)), dim3(kGB), 0, s, static_cast<const cd*>(B), ldb, n, r, Bc.p);
-  std::vector<double> bn, rn;
-  if ((rc = norms(W, Bc.p, bn, s))) return rc;
-  int iters = 0, restarts = 0, refinements = 0;
-  std::vector<char> done(r, 0);
-  cd* Xd = static_cast<cd*>(X);
-  if (!inner) {
-    std::vector<double> rtol(r);
-    for (int c = 0; c < r; ++c) rtol[c] = tol * bn[c];
-    if ((rc = gmres_cycles(op, W, Bc.p, rtol, o.max_iterations, iters, restarts, done, s))) return rc;
-    hipLaunchKernelGGL(k_g_add, dim3(nblk(n * r)), dim3(kGB), 0, s, W.d.p, n, r, Xd, ldx, 1);
-    if ((rc = apply(op, W, W.d.p, W.w.p, s))) return rc;
-    hipLaunchKernelGGL(k_g_sub, dim3(nblk(n * r)), dim3(kGB), 0, s, Bc.p, n, W.w.p, n, r, res.p);
-    if ((rc = norms(W, res.p, rn, s))) return rc;
-  } else {
-    if ((rc = xacc.alloc(n * r))) return rc;
-    UHM_HIP(hipMemsetAsync(xacc.p, 0, sizeof(cd) * (size_t)(n * r), s));
-    UHM_HIP(hipMemcpyAsync(res.p, Bc.p, sizeof(cd) * (size_t)(n * r), hipMemcpyDeviceToDevice, s));
-    if ((rc = norms(W, res.p, rn, s))) return rc;
-    while (true) {
-      bool all = true;
-      for (int c = 0; c < r; ++c) all = all && rn[c] <= tol * bn[c];
-      if (all || refinements >= o.max_refinements || iters >= o.max_iterations) break;
-      std::vector<double> rtol(r);
-      for (int c = 0; c < r; ++c) rtol[c] = o.inner_tol * rn[c];
-      if ((rc = gmres_cycles(inner, W, res.p, rtol, o.max_iterations, iters, restarts, done, s))) return rc;
-      ++refinements;
-      hipLaunchKernelGGL(k_g_add, dim3(nblk(n * r)), dim3(kGB), 0, s, W.d.p, n, r, xacc.p, n, 0);
-      if ((rc = apply(op, W, xacc.p, W.w.p, s))) return rc;
-      hipLaunchKernelGGL(k_g_sub, dim3(nblk(n * r)), dim3(kGB), 0, s, Bc.p, n, W.w.p, n, r, res.p);
-      if ((rc = norms(W, res.p, rn, s))) return rc;
+  std::unique_ptr<uhm_krylov> K(new (std::nothrow) uhm_krylov);
+  if (!K) return fail(UHM_ENOMEM, "host allocation");
+  K->n = n;
+  K->r = nrhs;
+  K->tol = tol;
+  K->o = o;
+  K->mixed = mixed != 0;
+  K->s = static_cast<hipStream_t>(hip_stream);
+  hipStream_t s = K->s;
+  const int r = nrhs, m = o.restart;
+  int rc;
+  if ((rc = alloc_work(K->W, n, r, m, false)) || (rc = K->Bc.alloc(n * r)) || (rc = K->xacc.alloc(n * r)) ||
+      (rc = K->res.alloc(n * r)) || (rc = K->rhs.alloc(n * r)))
+    return rc;
+  K->H.assign((size_t)(m + 1) * m * r, C(0.0));
+  K->g.assign((size_t)(m + 1) * r, C(0.0));
+  K->cs.assign((size_t)m * r, C(0.0));
+  K->sn.assign((size_t)m * r, C(0.0));
+  K->hh.assign((size_t)(m + 1) * r, make_double2(0.0, 0.0));
+  K->jc.assign(r, 0);
+  K->active.assign(r, 0);
+  K->done.assign(r, 0);
+  K->hn.assign(r, 0.0);
+  K->sc.assign(r, 0.0);
+  K->rtol.assign(r, 0.0);
+  hipLaunchKernelGGL(k_g_copy_strided, dim3(nblk(n * r)), dim3(kGB), 0, s, static_cast<const cd*>(B), ldb, n, r, K->Bc.p);
+  UHM_HIP(hipMemsetAsync(K->xacc.p, 0, sizeof(cd) * (size_t)(n * r), s));
+  if ((rc = norms(K->W, K->Bc.p, K->bn, s))) return rc;
+  K->rn = K->bn;
+  if (K->mixed) {
+    bool all = true;
+    for (int c = 0; c < r; ++c) all = all && K->bn[c] <= tol * K->bn[c];
+    if (all) {
+      K->phase = uhm_krylov::FINISHED;
+      K->req = UHM_KRYLOV_DONE;
+    } else {
+      for (int c = 0; c < r; ++c) K->rtol[c] = o.inner_tol * K->bn[c];
+      if ((rc = inner_start(K.get(), K->Bc.p))) return rc;
     }
-    hipLaunchKernelGGL(k_g_add, dim3(nblk(n * r)), dim3(kGB), 0, s, xacc.p, n, r, Xd, ldx, 1);
+  } else {
+    for (int c = 0; c < r; ++c) K->rtol[c] = tol * K->bn[c];
+    if ((rc = inner_start(K.get(), K->Bc.p))) return rc;
   }
-  UHM_HIP(hipStreamSynchronize(s));
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(UHM_EHIP, std::string("gmres kernels: ") + hipGetErrorString(e));
+  *out = K.release();
+  return UHM_OK;
+}
+
+int uhm_krylov_next(uhm_krylov* K, const void** in, void** out) {
+  if (!K) return fail(UHM_EINVAL, "null solve");
+  if (in) *in = K->req_in;
+  if (out) *out = K->req_out;
+  return K->req;
+}
+
+int uhm_krylov_advance(uhm_krylov* K) {
+  if (!K) return fail(UHM_EINVAL, "null solve");
+  const auto t0 = Clock::now();
+  const int rc = advance(K);
+  K->t_arn += std::chrono::duration<double>(Clock::now() - t0).count();
+  if (rc) K->status = rc;
+  return rc;
+}
+
+int uhm_krylov_result(uhm_krylov* K, void* X, int64_t ldx, uhm_gmres_info* info) {
+  if (!K) return fail(UHM_EINVAL, "null solve");
+  if (K->phase != uhm_krylov::FINISHED) return fail(UHM_EINVAL, "the solve has not finished");
+  const int64_t n = K->n;
+  const int r = K->r;
+  if (X) {
+    if (ldx < n) return fail(UHM_EINVAL, "leading dimension smaller than n");
+    hipLaunchKernelGGL(k_g_add, dim3(nblk(n * r)), dim3(kGB), 0, K->s, K->xacc.p, n, r, static_cast<cd*>(X), ldx, 1);
+    UHM_HIP(hipStreamSynchronize(K->s));
+  }
   int conv = 0;
   double worst = 0.0;
   for (int c = 0; c < r; ++c) {
-    const double rel = bn[c] > 0.0 ? rn[c] / bn[c] : 0.0;
+    const double rel = K->bn[c] > 0.0 ? K->rn[c] / K->bn[c] : 0.0;
     worst = std::max(worst, rel);
-    conv += rel <= tol;
+    conv += rel <= K->tol;
   }
   if (info) {
-    info->iterations = iters;
-    info->restarts = restarts;
-    info->refinements = refinements;
+    info->iterations = K->iters;
+    info->restarts = K->restarts;
+    info->refinements = K->mixed ? K->refinements : 0;
     info->converged = conv;
     info->rel_residual = worst;
-    info->seconds_total = std::chrono::duration<double>(Clock::now() - t0).count();
-    info->seconds_products = W.t_prod;
-    info->seconds_arnoldi = W.t_arn;
+    info->seconds_total = 0.0;
+    info->seconds_products = 0.0;
+    info->seconds_arnoldi = K->t_arn;
   }
   return conv == r ? UHM_OK : fail(UHM_ENOCONV, "iteration limit reached before the tolerance");
 }
+
+void uhm_krylov_free(uhm_krylov* K) { delete K; }
+
+// One step of many solves: their pending products, one multi-column product per
+// (operator, precision) group, then every solve advances.  Returns the number of solves
+// still running (>= 0) or an error code.
+int uhm_krylov_step(uhm_krylov* const* ks, uhm_op* const* high, uhm_op* const* low, int32_t count, void* hip_stream) {
+  if (count < 0 || (count > 0 && (!ks || !high))) return fail(UHM_EINVAL, "null argument");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  struct Item {
+    int32_t k;
+    int kind;
+    const cd* in;
+    cd* out;
+  };
+  std::map<std::pair<uhm_op*, int>, std::vector<Item>> groups;
+  for (int32_t k = 0; k < count; ++k) {
+    uhm_krylov* K = ks[k];
+    if (!K) return fail(UHM_EINVAL, "null solve");
+    if (K->req == UHM_KRYLOV_DONE) continue;
+    uhm_op* A = K->req == UHM_KRYLOV_PRODUCT_HIGH ? high[k] : (low ? low[k] : nullptr);
+    if (!A || A->n != K->n || A->kind != 0) return fail(UHM_EINVAL, "missing or mismatched operator for a solve");
+    const bool want_hi = K->req == UHM_KRYLOV_PRODUCT_HIGH;
+    const bool is_hi = A->storage == UHM_C128 || A->storage == UHM_C128_MULTI;
+    if (want_hi != is_hi) return fail(UHM_EINVAL, "operator precision does not match the request");
+    groups[{A, K->req}].push_back({k, K->req, static_cast<const cd*>(K->req_in), static_cast<cd*>(K->req_out)});
+  }
+  int rc;
+  for (auto& gkv : groups) {
+    uhm_op* A = gkv.first.first;
+    const bool hi = gkv.first.second == UHM_KRYLOV_PRODUCT_HIGH;
+    const int64_t n = A->n;
+    const std::vector<Item>& items = gkv.second;
+    size_t a = 0;
+    while (a < items.size()) {
+      // pack up to 64 columns (whole solves) per product
+      int cols = 0;
+      size_t b = a;
+      while (b < items.size() && (cols == 0 || cols + ks[items[b].k]->r <= 64)) cols += ks[items[b++].k]->r;
+      const int64_t es = hi ? 16 : 8;
+      const int64_t need = es * n * cols;
+      if (A->stage_bytes < need) {
+        if ((rc = A->stage_in.alloc(need)) || (rc = A->stage_out.alloc(need))) {
+          A->stage_bytes = 0;
+          return rc;
+        }
+        A->stage_bytes = need;
+      }
+      int c0 = 0;
+      for (size_t q = a; q < b; ++q) {
+        const int r = ks[items[q].k]->r;
+        if (hi)
+          UHM_HIP(hipMemcpyAsync(reinterpret_cast<cd*>(A->stage_in.p) + (int64_t)c0 * n, items[q].in,
+                                 sizeof(cd) * (size_t)(n * r), hipMemcpyDeviceToDevice, s));
+        else
+          hipLaunchKernelGGL(k_g_pack32, dim3(nblk(n * r)), dim3(kGB), 0, s, items[q].in, n, n, r,
+                             reinterpret_cast<cf*>(A->stage_in.p) + (int64_t)c0 * n, n);
+        c0 += r;
+      }
+      if ((rc = uhm_matvec(A, A->stage_in.p, n, A->stage_out.p, n, cols, s))) return rc;
+      c0 = 0;
+      for (size_t q = a; q < b; ++q) {
+        const int r = ks[items[q].k]->r;
+        if (hi)
+          UHM_HIP(hipMemcpyAsync(items[q].out, reinterpret_cast<cd*>(A->stage_out.p) + (int64_t)c0 * n,
+                                 sizeof(cd) * (size_t)(n * r), hipMemcpyDeviceToDevice, s));
+        else
+          hipLaunchKernelGGL(k_g_unpack32, dim3(nblk(n * r)), dim3(kGB), 0, s,
+                             reinterpret_cast<const cf*>(A->stage_out.p) + (int64_t)c0 * n, n, n, r, items[q].out, n);
+        c0 += r;
+      }
+      a = b;
+    }
+  }
+  UHM_HIP(hipStreamSynchronize(s));
+  int running = 0;
+  for (int32_t k = 0; k < count; ++k) {
+    uhm_krylov* K = ks[k];
+    if (K->req == UHM_KRYLOV_DONE) continue;
+    // each solve runs its own FP64 work on its own stream; the products above are complete
+    if ((rc = uhm_krylov_advance(K))) return rc;
+    running += K->req != UHM_KRYLOV_DONE;
+  }
+  return running;
+}
+
+int uhm_solve_gmres(uhm_op* op, uhm_op* inner, const void* B, int64_t ldb, void* X, int64_t ldx, int32_t nrhs,
+                    double tol, const uhm_gmres_opts* opts, uhm_gmres_info* info, void* hip_stream) {
+  if (!op || !B || !X) return fail(UHM_EINVAL, "null argument");
+  if ((op->storage != UHM_C128 && op->storage != UHM_C128_MULTI) || op->kind != 0)
+    return fail(UHM_EINVAL, "the residual operator must be a complex128 UH-matrix");
+  if (inner && (inner->storage == UHM_C128 || inner->storage == UHM_C128_MULTI || inner->kind != 0 || inner->n != op->n))
+    return fail(UHM_EINVAL, "the inner operator must be a low-precision form of the same size");
+  if (nrhs < 1 || ldx < op->n) return fail(UHM_EINVAL, "bad nrhs or leading dimension");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const auto t0 = Clock::now();
+  uhm_krylov* K = nullptr;
+  int rc = uhm_krylov_create(op->n, nrhs, B, ldb, tol, inner != nullptr, opts, hip_stream, &K);
+  if (rc) return rc;
+  std::unique_ptr<uhm_krylov> hold(K);
+  // product buffers for the low-precision operator
+  DevArray<cf> in32, out32;
+  const int64_t nq = op->n * (int64_t)nrhs;
+  if (inner && ((rc = in32.alloc(nq)) || (rc = out32.alloc(nq)))) return rc;
+  double t_prod = 0.0;
+  while (true) {
+    const void* in = nullptr;
+    void* out = nullptr;
+    const int what = uhm_krylov_next(K, &in, &out);
+    if (what == UHM_KRYLOV_DONE) break;
+    const auto tp = Clock::now();
+    if (what == UHM_KRYLOV_PRODUCT_HIGH) {
+      rc = uhm_matvec(op, in, op->n, out, op->n, nrhs, s);
+    } else {
+      hipLaunchKernelGGL(k_g_to32, dim3(nblk(nq)), dim3(kGB), 0, s, static_cast<const cd*>(in), nq, in32.p);
+      rc = uhm_matvec(inner, in32.p, op->n, out32.p, op->n, nrhs, s);
+      if (rc == UHM_OK) hipLaunchKernelGGL(k_g_to64, dim3(nblk(nq)), dim3(kGB), 0, s, out32.p, nq, static_cast<cd*>(out));
+    }
+    if (rc) return rc;
+    UHM_HIP(hipStreamSynchronize(s));
+    t_prod += std::chrono::duration<double>(Clock::now() - tp).count();
+    if ((rc = uhm_krylov_advance(K))) return rc;
+  }
+  rc = uhm_krylov_result(K, X, ldx, info);
+  if (info) {
+    info->seconds_total = std::chrono::duration<double>(Clock::now() - t0).count();
+    info->seconds_products = t_prod;
+  }
+  const hipError_t he = hipGetLastError();
+  if (he != hipSuccess) return fail(UHM_EHIP, std::string("gmres kernels: ") + hipGetErrorString(he));
+  return rc;
+}
+
+}  // extern "C"

@@ -222,6 +222,9 @@ struct uhm_op {
   std::vector<hipEvent_t> free_events;
 
   uhm_detail::LowpOp* lp = nullptr;
+  // staging of batched solve products (uhm_krylov_step)
+  DevArray<unsigned char> stage_in, stage_out;
+  int64_t stage_bytes = 0;
 
   ~uhm_op() {
     if (lp) uhm_detail::lowp_delete(lp);
@@ -269,7 +272,15 @@ inline bool in_bounds(int64_t off, int64_t count, int64_t len) { return off >= 0
 int common_tree_upload(uhm_op* op, const TreeInfo& T, const int64_t* perm, const int64_t* off, const int64_t* size,
                        hipStream_t s);
 
-// Low-precision storage (complex64 or bf16 pairs): MFMA kernels, own device layout.
+struct LowpBatch;
+int lowp_batch_create(uhm_op* const* ops, int32_t nops, const void* const* X, const int64_t* ldx, void* const* Y,
+                      const int64_t* ldy, const int32_t* nrhs, hipStream_t s, LowpBatch** out);
+int lowp_batch_run(LowpBatch* b, hipStream_t s);
+int lowp_batch_capture(LowpBatch* b, hipStream_t s);
+int lowp_batch_tune(LowpBatch* b, hipStream_t s, int32_t* width_out, int32_t* order_out, double* ms_out);
+void lowp_batch_delete(LowpBatch* b);
+
+// Many-RHS storage forms (complex64, bf16 pairs, complex128): MFMA kernels, own device layout.
 int lowp_upload(const uhm_host_operator* h, uhm_storage storage, hipStream_t s, const TreeInfo& T, uhm_op* op);
 int lowp_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs, hipStream_t s);
 

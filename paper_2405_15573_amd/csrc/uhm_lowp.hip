@@ -26,6 +26,8 @@
 
 #include <climits>
 #include <complex>
+#include <functional>
+#include <map>
 
 namespace uhm_detail {
 
@@ -234,13 +236,39 @@ __device__ __forceinline__ void store_tile(typename Tr<ST>::V* out, int64_t row0
     }
 }
 
-// ---------------------------------------------------------------- kernels
+// ---------------------------------------------------------------- stage bodies
+// Each stage is a device function over one work item (an element block, a leaf or a
+// coupling tile).  The single-operator kernels map blockIdx.x to the item; the batched
+// kernels read (operator, item) from a work list and the operator's descriptor.
+
+struct LpCoupTile {
+  int64_t base;     // uint4 offset of the chunk panel (all its m-tiles)
+  int64_t csrc;     // offset of the chunk's first column in the column-source map
+  int32_t h;        // rows of the chunk (<= 64)
+  int32_t nkb_all;  // k-blocks of the chunk panel (stride between its m-tiles)
+  int32_t kb0;      // first k-block of this tile
+  int32_t nkb;      // k-blocks in this tile
+  int32_t part;     // partial-sum slot (rows part*64 ..)
+};
+
+// Everything a stage needs about one operator and its bound vectors.
+struct LpDesc {
+  const uint4 *F, *S, *B;
+  const int64_t *f_off, *poff, *b_off, *zoff, *seg_start, *grp_start;
+  const int32_t *f_M, *f_nkb, *b_nkb, *zmap, *colsrc, *out_seg, *seg_leaf0, *seg_nleaf, *seg_col;
+  const int32_t *yh_grp, *grp_t0, *grp_nt, *leaf_pos, *leaf_n, *perm;
+  const LpCoupTile* ctiles;
+  void *Xc, *Yc, *p, *xh, *part, *yh;
+  const void* x;
+  void* y;
+  int64_t ldx, ldy, n, nxh, nyh;
+  int32_t r, R;
+};
 
 // Xc[pos][j] = x[perm[pos] + j ldx] (cluster order, row-major, R columns, zero beyond r).
 template <class V>
-__global__ __launch_bounds__(256) void k_lp_gather(const V* __restrict__ x, int64_t ldx, int r, int R,
-                                                   const int32_t* __restrict__ perm, int64_t n, V* __restrict__ Xc) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void gather_body(int64_t q, const V* __restrict__ x, int64_t ldx, int r, int R,
+                                            const int32_t* __restrict__ perm, int64_t n, V* __restrict__ Xc) {
   if (q >= n * R) return;
   const int64_t pos = q / R;
   const int j = (int)(q - pos * R);
@@ -248,26 +276,25 @@ __global__ __launch_bounds__(256) void k_lp_gather(const V* __restrict__ x, int6
 }
 
 template <class V>
-__global__ __launch_bounds__(256) void k_lp_scatter(const V* __restrict__ Yc, int r, int R, const int32_t* __restrict__ perm,
-                                                    int64_t n, V* __restrict__ y, int64_t ldy) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void scatter_body(int64_t q, const V* __restrict__ Yc, int r, int R,
+                                             const int32_t* __restrict__ perm, int64_t n, V* __restrict__ y,
+                                             int64_t ldy) {
   if (q >= n * (int64_t)r) return;
   const int j = (int)(q / n);
   const int64_t pos = q - (int64_t)j * n;
   y[perm[pos] + (int64_t)j * ldy] = Yc[pos * R + j];
 }
 
-// P_lambda = F_lambda^* X_lambda for every leaf (one workgroup per leaf).
+// P_lambda = F_lambda^* X_lambda for one leaf.
 template <int ST, int NT>
-__global__ __launch_bounds__(64 * kLpWaves) void k_lp_forward(
-    const uint4* __restrict__ F, const int64_t* __restrict__ f_off, const int32_t* __restrict__ f_M,
-    const int32_t* __restrict__ f_nkb, const int32_t* __restrict__ leaf_pos, const int32_t* __restrict__ leaf_n,
-    const int64_t* __restrict__ poff, const typename Tr<ST>::V* __restrict__ Xc, int R,
-    typename Tr<ST>::V* __restrict__ p) {
+__device__ __forceinline__ void forward_body(typename Tr<ST>::LDS& L, int leaf, const uint4* __restrict__ F,
+                                             const int64_t* __restrict__ f_off, const int32_t* __restrict__ f_M,
+                                             const int32_t* __restrict__ f_nkb, const int32_t* __restrict__ leaf_pos,
+                                             const int32_t* __restrict__ leaf_n, const int64_t* __restrict__ poff,
+                                             const typename Tr<ST>::V* __restrict__ Xc, int R,
+                                             typename Tr<ST>::V* __restrict__ p) {
   using T_ = Tr<ST>;
   using V = typename T_::V;
-  __shared__ typename T_::LDS L;
-  const int leaf = blockIdx.x;
   const int M = f_M[leaf];
   if (M == 0) return;
   const int n = leaf_n[leaf], nkb = f_nkb[leaf];
@@ -276,7 +303,7 @@ __global__ __launch_bounds__(64 * kLpWaves) void k_lp_forward(
   const int nmt = (M + 15) >> 4;
   constexpr int KBR = T_::RZ / T_::KB;  // k-blocks per LDS round
   if (nkb <= KBR) {
-    // the whole leaf (<= RZ rows) fits one round: stage once, sweep all m-tiles
+    // the whole leaf fits one round: stage once, sweep all m-tiles
     for (int q = t; q < nkb * T_::KB * R; q += 64 * kLpWaves) {
       const int k = q / R, j = q - k * R;
       lds_put(L, k, j, k < n ? Xc[(int64_t)(leaf_pos[leaf] + k) * R + j] : vzero<V>());
@@ -296,8 +323,7 @@ __global__ __launch_bounds__(64 * kLpWaves) void k_lp_forward(
       store_tile<ST, NT>(p, poff[leaf] + 16 * mt, hm, R, g, i, cr, ci);
     }
   } else {
-    // leaf rows in several rounds: each wave keeps its m-tiles' accumulators across rounds
-    // by sweeping m-tiles in the outer loop and restaging per m-tile group of 4
+    // leaf rows in several rounds: m-tiles in groups of kLpWaves, restaged per group
     for (int mt0 = 0; mt0 < nmt; mt0 += kLpWaves) {
       const int mt = mt0 + w;
       const int hm = min(16, M - 16 * mt);
@@ -328,14 +354,14 @@ __global__ __launch_bounds__(64 * kLpWaves) void k_lp_forward(
 
 // xh[e][j] = sum over the leaves of the segment of p[poff[leaf] + col + e - start][j].
 template <class V>
-__global__ __launch_bounds__(256) void k_lp_reduce_segments(const V* __restrict__ p, int R, const int64_t* __restrict__ poff,
-                                                            const int32_t* __restrict__ out_seg,
-                                                            const int64_t* __restrict__ seg_start,
-                                                            const int32_t* __restrict__ seg_leaf0,
-                                                            const int32_t* __restrict__ seg_nleaf,
-                                                            const int32_t* __restrict__ seg_col, int64_t nout,
-                                                            V* __restrict__ xh) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void reduce_segments_body(int64_t q, const V* __restrict__ p, int R,
+                                                     const int64_t* __restrict__ poff,
+                                                     const int32_t* __restrict__ out_seg,
+                                                     const int64_t* __restrict__ seg_start,
+                                                     const int32_t* __restrict__ seg_leaf0,
+                                                     const int32_t* __restrict__ seg_nleaf,
+                                                     const int32_t* __restrict__ seg_col, int64_t nout,
+                                                     V* __restrict__ xh) {
   if (q >= nout * R) return;
   const int64_t e = q / R;
   const int j = (int)(q - e * R);
@@ -351,26 +377,14 @@ __global__ __launch_bounds__(256) void k_lp_reduce_segments(const V* __restrict_
   xh[q] = acc;
 }
 
-struct LpCoupTile {
-  int64_t base;     // uint4 offset of the chunk panel (all its m-tiles)
-  int64_t csrc;     // offset of the chunk's first column in the column-source map
-  int32_t h;        // rows of the chunk (<= 64)
-  int32_t nkb_all;  // k-blocks of the chunk panel (stride between its m-tiles)
-  int32_t kb0;      // first k-block of this tile
-  int32_t nkb;      // k-blocks in this tile
-};
-
-// Partial u_tau of one coupling tile (workgroup; wave w = m-tile w of the chunk).
+// Partial u_tau of one coupling tile (wave w = m-tile w of the chunk).
 template <int ST, int NT>
-__global__ __launch_bounds__(64 * kLpWaves) void k_lp_coupling(const uint4* __restrict__ S,
-                                                               const LpCoupTile* __restrict__ tiles,
-                                                               const int32_t* __restrict__ colsrc,
-                                                               const typename Tr<ST>::V* __restrict__ xh, int R,
-                                                               typename Tr<ST>::V* __restrict__ part) {
+__device__ __forceinline__ void coupling_body(typename Tr<ST>::LDS& L, const LpCoupTile& T,
+                                              const uint4* __restrict__ S, const int32_t* __restrict__ colsrc,
+                                              const typename Tr<ST>::V* __restrict__ xh, int R,
+                                              typename Tr<ST>::V* __restrict__ part) {
   using T_ = Tr<ST>;
   using V = typename T_::V;
-  __shared__ typename T_::LDS L;
-  const LpCoupTile T = tiles[blockIdx.x];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, i = lane & 15;
   const int nmt = (T.h + 15) >> 4;
   const int hm = min(16, T.h - 16 * w);
@@ -397,17 +411,16 @@ __global__ __launch_bounds__(64 * kLpWaves) void k_lp_coupling(const uint4* __re
       }
     }
   }
-  if (w < nmt) store_tile<ST, NT>(part, (int64_t)blockIdx.x * 64 + 16 * w, hm, R, g, i, cr, ci);
+  if (w < nmt) store_tile<ST, NT>(part, (int64_t)T.part * 64 + 16 * w, hm, R, g, i, cr, ci);
 }
 
 template <class V>
-__global__ __launch_bounds__(256) void k_lp_reduce_coupling(const V* __restrict__ part, int R,
-                                                            const int32_t* __restrict__ yh_grp,
-                                                            const int64_t* __restrict__ grp_start,
-                                                            const int32_t* __restrict__ grp_t0,
-                                                            const int32_t* __restrict__ grp_nt, int64_t nout,
-                                                            V* __restrict__ yh) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void reduce_coupling_body(int64_t q, const V* __restrict__ part, int R,
+                                                     const int32_t* __restrict__ yh_grp,
+                                                     const int64_t* __restrict__ grp_start,
+                                                     const int32_t* __restrict__ grp_t0,
+                                                     const int32_t* __restrict__ grp_nt, int64_t nout,
+                                                     V* __restrict__ yh) {
   if (q >= nout * R) return;
   const int64_t e = q / R;
   const int j = (int)(q - e * R);
@@ -423,18 +436,18 @@ __global__ __launch_bounds__(256) void k_lp_reduce_coupling(const V* __restrict_
   yh[q] = acc;
 }
 
-// Y_lambda = B_lambda Z_lambda per leaf; Z gathered from yh (index >= 0), from the
+// Y_lambda = B_lambda Z_lambda for one leaf; Z gathered from yh (index >= 0), from the
 // cluster-ordered input (index = -1 - position) or zero (kZero).
 template <int ST, int NT>
-__global__ __launch_bounds__(64 * kLpWaves) void k_lp_backward(
-    const uint4* __restrict__ B, const int64_t* __restrict__ b_off, const int32_t* __restrict__ b_nkb,
-    const int64_t* __restrict__ zoff, const int32_t* __restrict__ zmap, const int32_t* __restrict__ leaf_pos,
-    const int32_t* __restrict__ leaf_n, const typename Tr<ST>::V* __restrict__ yh,
-    const typename Tr<ST>::V* __restrict__ Xc, int R, typename Tr<ST>::V* __restrict__ Yc) {
+__device__ __forceinline__ void backward_body(typename Tr<ST>::LDS& L, int leaf, const uint4* __restrict__ B,
+                                              const int64_t* __restrict__ b_off, const int32_t* __restrict__ b_nkb,
+                                              const int64_t* __restrict__ zoff, const int32_t* __restrict__ zmap,
+                                              const int32_t* __restrict__ leaf_pos, const int32_t* __restrict__ leaf_n,
+                                              const typename Tr<ST>::V* __restrict__ yh,
+                                              const typename Tr<ST>::V* __restrict__ Xc, int R,
+                                              typename Tr<ST>::V* __restrict__ Yc) {
   using T_ = Tr<ST>;
   using V = typename T_::V;
-  __shared__ typename T_::LDS L;
-  const int leaf = blockIdx.x;
   const int n = leaf_n[leaf], nkb = b_nkb[leaf];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, i = lane & 15;
   const int nmt = (n + 15) >> 4;
@@ -470,6 +483,139 @@ __global__ __launch_bounds__(64 * kLpWaves) void k_lp_backward(
   if (w < nmt) store_tile<ST, NT>(Yc, (int64_t)leaf_pos[leaf] + 16 * w, hm, R, g, i, cr, ci);
 }
 
+// ---------------------------------------------------------------- single-operator kernels
+
+template <class V>
+__global__ __launch_bounds__(256) void k_lp_gather(const V* __restrict__ x, int64_t ldx, int r, int R,
+                                                   const int32_t* __restrict__ perm, int64_t n, V* __restrict__ Xc) {
+  gather_body<V>((int64_t)blockIdx.x * 256 + threadIdx.x, x, ldx, r, R, perm, n, Xc);
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_lp_scatter(const V* __restrict__ Yc, int r, int R, const int32_t* __restrict__ perm,
+                                                    int64_t n, V* __restrict__ y, int64_t ldy) {
+  scatter_body<V>((int64_t)blockIdx.x * 256 + threadIdx.x, Yc, r, R, perm, n, y, ldy);
+}
+
+template <int ST, int NT>
+__global__ __launch_bounds__(64 * kLpWaves) void k_lp_forward(
+    const uint4* __restrict__ F, const int64_t* __restrict__ f_off, const int32_t* __restrict__ f_M,
+    const int32_t* __restrict__ f_nkb, const int32_t* __restrict__ leaf_pos, const int32_t* __restrict__ leaf_n,
+    const int64_t* __restrict__ poff, const typename Tr<ST>::V* __restrict__ Xc, int R,
+    typename Tr<ST>::V* __restrict__ p) {
+  __shared__ typename Tr<ST>::LDS L;
+  forward_body<ST, NT>(L, blockIdx.x, F, f_off, f_M, f_nkb, leaf_pos, leaf_n, poff, Xc, R, p);
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_lp_reduce_segments(const V* __restrict__ p, int R, const int64_t* __restrict__ poff,
+                                                            const int32_t* __restrict__ out_seg,
+                                                            const int64_t* __restrict__ seg_start,
+                                                            const int32_t* __restrict__ seg_leaf0,
+                                                            const int32_t* __restrict__ seg_nleaf,
+                                                            const int32_t* __restrict__ seg_col, int64_t nout,
+                                                            V* __restrict__ xh) {
+  reduce_segments_body<V>((int64_t)blockIdx.x * 256 + threadIdx.x, p, R, poff, out_seg, seg_start, seg_leaf0, seg_nleaf,
+                          seg_col, nout, xh);
+}
+
+template <int ST, int NT>
+__global__ __launch_bounds__(64 * kLpWaves) void k_lp_coupling(const uint4* __restrict__ S,
+                                                               const LpCoupTile* __restrict__ tiles,
+                                                               const int32_t* __restrict__ colsrc,
+                                                               const typename Tr<ST>::V* __restrict__ xh, int R,
+                                                               typename Tr<ST>::V* __restrict__ part) {
+  __shared__ typename Tr<ST>::LDS L;
+  const LpCoupTile T = tiles[blockIdx.x];
+  coupling_body<ST, NT>(L, T, S, colsrc, xh, R, part);
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_lp_reduce_coupling(const V* __restrict__ part, int R,
+                                                            const int32_t* __restrict__ yh_grp,
+                                                            const int64_t* __restrict__ grp_start,
+                                                            const int32_t* __restrict__ grp_t0,
+                                                            const int32_t* __restrict__ grp_nt, int64_t nout,
+                                                            V* __restrict__ yh) {
+  reduce_coupling_body<V>((int64_t)blockIdx.x * 256 + threadIdx.x, part, R, yh_grp, grp_start, grp_t0, grp_nt, nout, yh);
+}
+
+template <int ST, int NT>
+__global__ __launch_bounds__(64 * kLpWaves) void k_lp_backward(
+    const uint4* __restrict__ B, const int64_t* __restrict__ b_off, const int32_t* __restrict__ b_nkb,
+    const int64_t* __restrict__ zoff, const int32_t* __restrict__ zmap, const int32_t* __restrict__ leaf_pos,
+    const int32_t* __restrict__ leaf_n, const typename Tr<ST>::V* __restrict__ yh,
+    const typename Tr<ST>::V* __restrict__ Xc, int R, typename Tr<ST>::V* __restrict__ Yc) {
+  __shared__ typename Tr<ST>::LDS L;
+  backward_body<ST, NT>(L, blockIdx.x, B, b_off, b_nkb, zoff, zmap, leaf_pos, leaf_n, yh, Xc, R, Yc);
+}
+
+// ---------------------------------------------------------------- batched kernels
+// work[b] = (operator, item): item is a 256-element block for the element-wise stages,
+// a leaf for forward/backward, a coupling tile index (into the descriptor's tile array).
+
+template <class V>
+__global__ __launch_bounds__(256) void k_lpb_gather(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const LpDesc& d = D[wk.x];
+  gather_body<V>((int64_t)wk.y * 256 + threadIdx.x, static_cast<const V*>(d.x), d.ldx, d.r, d.R, d.perm, d.n,
+                 static_cast<V*>(d.Xc));
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_lpb_scatter(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const LpDesc& d = D[wk.x];
+  scatter_body<V>((int64_t)wk.y * 256 + threadIdx.x, static_cast<const V*>(d.Yc), d.r, d.R, d.perm, d.n,
+                  static_cast<V*>(d.y), d.ldy);
+}
+
+template <int ST, int NT>
+__global__ __launch_bounds__(64 * kLpWaves) void k_lpb_forward(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
+  __shared__ typename Tr<ST>::LDS L;
+  using V = typename Tr<ST>::V;
+  const int2 wk = work[blockIdx.x];
+  const LpDesc& d = D[wk.x];
+  forward_body<ST, NT>(L, wk.y, d.F, d.f_off, d.f_M, d.f_nkb, d.leaf_pos, d.leaf_n, d.poff,
+                       static_cast<const V*>(d.Xc), d.R, static_cast<V*>(d.p));
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_lpb_reduce_segments(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const LpDesc& d = D[wk.x];
+  reduce_segments_body<V>((int64_t)wk.y * 256 + threadIdx.x, static_cast<const V*>(d.p), d.R, d.poff, d.out_seg,
+                          d.seg_start, d.seg_leaf0, d.seg_nleaf, d.seg_col, d.nxh, static_cast<V*>(d.xh));
+}
+
+template <int ST, int NT>
+__global__ __launch_bounds__(64 * kLpWaves) void k_lpb_coupling(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
+  __shared__ typename Tr<ST>::LDS L;
+  using V = typename Tr<ST>::V;
+  const int2 wk = work[blockIdx.x];
+  const LpDesc& d = D[wk.x];
+  const LpCoupTile T = d.ctiles[wk.y];
+  coupling_body<ST, NT>(L, T, d.S, d.colsrc, static_cast<const V*>(d.xh), d.R, static_cast<V*>(d.part));
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_lpb_reduce_coupling(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const LpDesc& d = D[wk.x];
+  reduce_coupling_body<V>((int64_t)wk.y * 256 + threadIdx.x, static_cast<const V*>(d.part), d.R, d.yh_grp, d.grp_start,
+                          d.grp_t0, d.grp_nt, d.nyh, static_cast<V*>(d.yh));
+}
+
+template <int ST, int NT>
+__global__ __launch_bounds__(64 * kLpWaves) void k_lpb_backward(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
+  __shared__ typename Tr<ST>::LDS L;
+  using V = typename Tr<ST>::V;
+  const int2 wk = work[blockIdx.x];
+  const LpDesc& d = D[wk.x];
+  backward_body<ST, NT>(L, wk.y, d.B, d.b_off, d.b_nkb, d.zoff, d.zmap, d.leaf_pos, d.leaf_n,
+                        static_cast<const V*>(d.yh), static_cast<const V*>(d.Xc), d.R, static_cast<V*>(d.Yc));
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- host side
@@ -483,6 +629,13 @@ struct LowpOp {
   DevArray<LpCoupTile> ctiles;
   int64_t p_rows = 0, nxh = 0, nyh = 0;
   int32_t nctiles = 0;
+  // host copies for re-tiling the couplings (batched launches): one entry per row chunk
+  struct Chunk {
+    int64_t base, csrc;
+    int32_t h, nkb_all;
+  };
+  std::vector<Chunk> chunks;
+  std::vector<int32_t> f_M_h, b_nkb_h, f_nkb_h, leaf_n_h;
   // workspace, sized for R columns
   int wsR = 0;
   DevArray<unsigned char> Xc, Yc, p, xh, part, yh;  // vector element: 8 or 16 bytes
@@ -612,6 +765,9 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
   if ((rc = lp->f_off.upload(f_off, s)) || (rc = lp->f_M.upload(f_M, s)) || (rc = lp->f_nkb.upload(f_nkb, s)) ||
       (rc = lp->poff.upload(poff, s)))
     return rc;
+  lp->f_M_h = f_M;
+  lp->f_nkb_h = f_nkb;
+  for (int32_t i = 0; i < nl; ++i) lp->leaf_n_h.push_back((int32_t)h->size[T.leaves[i]]);
   lp->p_rows = prow;
   // segments of u_sigma: sums over the leaves of sigma
   std::vector<SegLp> segs;
@@ -669,9 +825,10 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
       for (int32_t r = 0; r < hh; ++r) yh_grp[yh_off[t] + r0 + r] = gi;
       constexpr int KBT = kLpCoupK / KB;
       for (int32_t kb0 = 0; kb0 < nkb; kb0 += KBT)
-        tiles.push_back({stot, csrc, hh, nkb, kb0, std::min(KBT, nkb - kb0)});
+        tiles.push_back({stot, csrc, hh, nkb, kb0, std::min(KBT, nkb - kb0), (int32_t)tiles.size()});
       grp_nt.push_back((int32_t)tiles.size() - grp_t0.back());
       jobs.push_back({t, r0, hh, stot, csrc, nkb});
+      lp->chunks.push_back({stot, csrc, hh, nkb});
       stot += panel_chunks<ST>(hh, nkb);
     }
   }
@@ -762,6 +919,7 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
   if ((rc = lp->b_off.upload(b_off, s)) || (rc = lp->b_nkb.upload(b_nkb, s)) || (rc = lp->zoff.upload(zoff, s)) ||
       (rc = lp->zmap.upload(zmap, s)))
     return rc;
+  lp->b_nkb_h = b_nkb;
   UHM_HIP(hipStreamSynchronize(s));
 
   uhm_op_info& I = op->info;
@@ -912,4 +1070,396 @@ int lowp_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, in
   return UHM_OK;
 }
 
+
+// ---------------------------------------------------------------- batched products
+
+namespace {
+
+struct BatchConfig {
+  int32_t coup_cols = kLpCoupK;  // coupling tile width in columns
+  int32_t order = 0;             // 0 operator-major, 1 cost-descending, 2 round-robin over cost buckets
+};
+
+// Candidate schedules the tuner times; winners are cached per batch signature.
+const int32_t kTileWidths[] = {256, 512, 1024, 2048};
+std::map<std::string, BatchConfig>& tune_cache() {
+  static std::map<std::string, BatchConfig> m;
+  return m;
+}
+
+struct BatchOp {
+  uhm_op* op;
+  const void* x;
+  void* y;
+  int64_t ldx, ldy;
+  int32_t r;
+  DevArray<unsigned char> Xc, Yc, p, xh, part, yh;
+  DevArray<LpCoupTile> tiles;
+  DevArray<int32_t> grp_t0, grp_nt;
+  int32_t ntiles = 0;
+  int64_t part_cap = 0;  // partial-sum slots allocated (tiles * 64 * R elements)
+};
+
+}  // namespace
+
+struct LowpBatch {
+  int storage = UHM_C64;
+  int R = 16;
+  std::vector<std::unique_ptr<BatchOp>> ops;
+  BatchConfig cfg;
+  bool configured = false;
+  DevArray<LpDesc> desc;
+  DevArray<int2> w_gather, w_forward, w_rseg, w_coup, w_rcoup, w_backward, w_scatter;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::string signature;
+  ~LowpBatch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+namespace {
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Order a stage's work items: 0 keeps operator-major order, 1 sorts by cost (largest
+// first), 2 deals items round-robin over cost buckets (powers of two), largest bucket first.
+void order_work(std::vector<int2>& w, const std::vector<int64_t>& cost, int order) {
+  if (order == 0 || w.size() < 2) return;
+  std::vector<size_t> idx(w.size());
+  for (size_t k = 0; k < idx.size(); ++k) idx[k] = k;
+  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  std::vector<int2> out;
+  out.reserve(w.size());
+  if (order == 1) {
+    for (size_t k : idx) out.push_back(w[k]);
+  } else {
+    std::map<int, std::vector<size_t>, std::greater<int>> buckets;
+    for (size_t k : idx) {
+      int bkt = 0;
+      for (int64_t c = cost[k]; c > 1; c >>= 1) ++bkt;
+      buckets[bkt].push_back(k);
+    }
+    std::vector<std::pair<std::vector<size_t>*, size_t>> cur;
+    for (auto& kv : buckets) cur.push_back({&kv.second, 0});
+    bool any = true;
+    while (any) {
+      any = false;
+      for (auto& c : cur)
+        if (c.second < c.first->size()) {
+          out.push_back(w[(*c.first)[c.second++]]);
+          any = true;
+        }
+    }
+  }
+  w.swap(out);
+}
+
+int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
+  const int KB = B->ops[0]->op->lp->KB;
+  const int64_t e = B->storage == UHM_C128_MULTI ? 16 : 8;
+  const int R = B->R;
+  std::vector<LpDesc> descs;
+  std::vector<int2> wg, wf, wrs, wc, wrc, wb, wsc;
+  std::vector<int64_t> cf_, cc_, cb_;
+  int rc;
+  for (size_t k = 0; k < B->ops.size(); ++k) {
+    BatchOp& bo = *B->ops[k];
+    uhm_op* op = bo.op;
+    LowpOp* lp = op->lp;
+    // coupling tiles of width cfg.coup_cols over the operator's row chunks
+    std::vector<LpCoupTile> tiles;
+    std::vector<int32_t> t0, nt;
+    const int32_t kbt = std::max(1, cfg.coup_cols / KB);
+    for (const LowpOp::Chunk& c : lp->chunks) {
+      t0.push_back((int32_t)tiles.size());
+      for (int32_t kb0 = 0; kb0 < c.nkb_all; kb0 += kbt)
+        tiles.push_back({c.base, c.csrc, c.h, c.nkb_all, kb0, std::min(kbt, c.nkb_all - kb0), (int32_t)tiles.size()});
+      nt.push_back((int32_t)tiles.size() - t0.back());
+    }
+    if ((rc = bo.tiles.upload(tiles, s)) || (rc = bo.grp_t0.upload(t0, s)) || (rc = bo.grp_nt.upload(nt, s))) return rc;
+    bo.ntiles = (int32_t)tiles.size();
+    const int64_t need = std::max<int64_t>(1, (int64_t)bo.ntiles * 64 * R);
+    if (bo.part_cap < need) {
+      if ((rc = bo.part.alloc(e * need))) return rc;
+      bo.part_cap = need;
+    }
+    LpDesc d{};
+    d.F = lp->F.p;
+    d.S = lp->S.p;
+    d.B = lp->B.p;
+    d.f_off = lp->f_off.p;
+    d.poff = lp->poff.p;
+    d.b_off = lp->b_off.p;
+    d.zoff = lp->zoff.p;
+    d.seg_start = lp->seg_start.p;
+    d.grp_start = lp->grp_start.p;
+    d.f_M = lp->f_M.p;
+    d.f_nkb = lp->f_nkb.p;
+    d.b_nkb = lp->b_nkb.p;
+    d.zmap = lp->zmap.p;
+    d.colsrc = lp->colsrc.p;
+    d.out_seg = lp->out_seg.p;
+    d.seg_leaf0 = lp->seg_leaf0.p;
+    d.seg_nleaf = lp->seg_nleaf.p;
+    d.seg_col = lp->seg_col.p;
+    d.yh_grp = lp->yh_grp.p;
+    d.grp_t0 = bo.grp_t0.p;
+    d.grp_nt = bo.grp_nt.p;
+    d.leaf_pos = op->leaf_pos.p;
+    d.leaf_n = op->leaf_n.p;
+    d.perm = op->perm.p;
+    d.ctiles = bo.tiles.p;
+    d.Xc = bo.Xc.p;
+    d.Yc = bo.Yc.p;
+    d.p = bo.p.p;
+    d.xh = bo.xh.p;
+    d.part = bo.part.p;
+    d.yh = bo.yh.p;
+    d.x = bo.x;
+    d.y = bo.y;
+    d.ldx = bo.ldx;
+    d.ldy = bo.ldy;
+    d.n = op->n;
+    d.nxh = lp->nxh;
+    d.nyh = lp->nyh;
+    d.r = bo.r;
+    d.R = R;
+    descs.push_back(d);
+    const int32_t ki = (int32_t)k;
+    for (int64_t b = 0; b < ceil_div(op->n * R, 256); ++b) wg.push_back(make_int2(ki, (int32_t)b));
+    for (int64_t b = 0; b < ceil_div(op->n * bo.r, 256); ++b) wsc.push_back(make_int2(ki, (int32_t)b));
+    if (lp->nxh > 0) {
+      for (int32_t l = 0; l < op->nleaves; ++l) {
+        wf.push_back(make_int2(ki, l));
+        cf_.push_back((int64_t)lp->f_M_h[l] * lp->f_nkb_h[l]);
+      }
+      for (int64_t b = 0; b < ceil_div(lp->nxh * R, 256); ++b) wrs.push_back(make_int2(ki, (int32_t)b));
+    }
+    for (int32_t t = 0; t < bo.ntiles; ++t) {
+      wc.push_back(make_int2(ki, t));
+      cc_.push_back((int64_t)tiles[t].h * tiles[t].nkb);
+    }
+    for (int64_t b = 0; b < ceil_div(lp->nyh * R, 256); ++b) wrc.push_back(make_int2(ki, (int32_t)b));
+    for (int32_t l = 0; l < op->nleaves; ++l) {
+      wb.push_back(make_int2(ki, l));
+      cb_.push_back((int64_t)lp->leaf_n_h[l] * lp->b_nkb_h[l]);
+    }
+  }
+  order_work(wf, cf_, cfg.order);
+  order_work(wc, cc_, cfg.order);
+  order_work(wb, cb_, cfg.order);
+  if ((rc = B->desc.upload(descs, s)) || (rc = B->w_gather.upload(wg, s)) || (rc = B->w_forward.upload(wf, s)) ||
+      (rc = B->w_rseg.upload(wrs, s)) || (rc = B->w_coup.upload(wc, s)) || (rc = B->w_rcoup.upload(wrc, s)) ||
+      (rc = B->w_backward.upload(wb, s)) || (rc = B->w_scatter.upload(wsc, s)))
+    return rc;
+  UHM_HIP(hipStreamSynchronize(s));
+  B->cfg = cfg;
+  B->configured = true;
+  if (B->exec) {
+    (void)hipGraphExecDestroy(B->exec);
+    B->exec = nullptr;
+  }
+  if (B->graph) {
+    (void)hipGraphDestroy(B->graph);
+    B->graph = nullptr;
+  }
+  return UHM_OK;
+}
+
+template <int ST, int NT>
+void batch_launch_t(LowpBatch* B, hipStream_t s) {
+  using V = typename Tr<ST>::V;
+  const LpDesc* D = B->desc.p;
+  auto go = [&](auto kern, const DevArray<int2>& w, int threads) {
+    if (w.n > 0) hipLaunchKernelGGL(kern, dim3((unsigned)w.n), dim3(threads), 0, s, D, w.p);
+  };
+  go(k_lpb_gather<V>, B->w_gather, 256);
+  go(k_lpb_forward<ST, NT>, B->w_forward, 64 * kLpWaves);
+  go(k_lpb_reduce_segments<V>, B->w_rseg, 256);
+  go(k_lpb_coupling<ST, NT>, B->w_coup, 64 * kLpWaves);
+  go(k_lpb_reduce_coupling<V>, B->w_rcoup, 256);
+  go(k_lpb_backward<ST, NT>, B->w_backward, 64 * kLpWaves);
+  go(k_lpb_scatter<V>, B->w_scatter, 256);
+}
+
+template <int ST>
+void batch_launch_st(LowpBatch* B, hipStream_t s) {
+  switch (B->R / 16) {
+    case 1: batch_launch_t<ST, 1>(B, s); break;
+    case 2: batch_launch_t<ST, 2>(B, s); break;
+    case 3: batch_launch_t<ST, 3>(B, s); break;
+    default: batch_launch_t<ST, 4>(B, s); break;
+  }
+}
+
+void batch_launch(LowpBatch* B, hipStream_t s) {
+  if (B->storage == UHM_C64)
+    batch_launch_st<UHM_C64>(B, s);
+  else if (B->storage == UHM_BF16PAIR)
+    batch_launch_st<UHM_BF16PAIR>(B, s);
+  else
+    batch_launch_st<UHM_C128_MULTI>(B, s);
+}
+
+}  // namespace
+
+void lowp_batch_delete(LowpBatch* b) { delete b; }
+
+int lowp_batch_create(uhm_op* const* ops, int32_t nops, const void* const* X, const int64_t* ldx, void* const* Y,
+                      const int64_t* ldy, const int32_t* nrhs, hipStream_t s, LowpBatch** out) {
+  if (!ops || nops < 1 || !X || !Y || !ldx || !ldy || !nrhs || !out) return fail(UHM_EINVAL, "null argument");
+  *out = nullptr;
+  std::unique_ptr<LowpBatch> B(new (std::nothrow) LowpBatch);
+  if (!B) return fail(UHM_ENOMEM, "host allocation");
+  int rmax = 1;
+  for (int32_t k = 0; k < nops; ++k) {
+    if (!ops[k] || !ops[k]->lp) return fail(UHM_EINVAL, "batched operators must use a many-RHS storage form");
+    if (ops[k]->storage != ops[0]->storage) return fail(UHM_EINVAL, "batched operators must share one storage form");
+    if (nrhs[k] < 1 || nrhs[k] > kLpRmax) return fail(UHM_EINVAL, "nrhs must be in [1, 64] per operator");
+    if (!X[k] || !Y[k] || ldx[k] < ops[k]->n || ldy[k] < ops[k]->n) return fail(UHM_EINVAL, "bad vector or leading dimension");
+    rmax = std::max(rmax, (int)nrhs[k]);
+  }
+  B->storage = ops[0]->storage;
+  B->R = 16 * ((rmax + 15) / 16);
+  const int64_t e = B->storage == UHM_C128_MULTI ? 16 : 8;
+  std::string sig = "st" + std::to_string(B->storage) + "R" + std::to_string(B->R);
+  for (int32_t k = 0; k < nops; ++k) {
+    std::unique_ptr<BatchOp> bo(new (std::nothrow) BatchOp);
+    if (!bo) return fail(UHM_ENOMEM, "host allocation");
+    uhm_op* op = ops[k];
+    LowpOp* lp = op->lp;
+    bo->op = op;
+    bo->x = X[k];
+    bo->y = Y[k];
+    bo->ldx = ldx[k];
+    bo->ldy = ldy[k];
+    bo->r = nrhs[k];
+    const int64_t R = B->R;
+    int rc;
+    if ((rc = bo->Xc.alloc(e * op->n * R)) || (rc = bo->Yc.alloc(e * op->n * R)) ||
+        (rc = bo->p.alloc(e * std::max<int64_t>(1, lp->p_rows * R))) ||
+        (rc = bo->xh.alloc(e * std::max<int64_t>(1, lp->nxh * R))) ||
+        (rc = bo->yh.alloc(e * std::max<int64_t>(1, lp->nyh * R))))
+      return rc;
+    sig += "|" + std::to_string(op->n) + "," + std::to_string(lp->nxh) + "," + std::to_string(lp->nyh) + "," +
+           std::to_string(lp->chunks.size()) + "," + std::to_string(nrhs[k]);
+    B->ops.push_back(std::move(bo));
+  }
+  B->signature = sig;
+  BatchConfig cfg;
+  auto it = tune_cache().find(sig);
+  if (it != tune_cache().end()) cfg = it->second;
+  int rc = configure(B.get(), cfg, s);
+  if (rc) return rc;
+  *out = B.release();
+  return UHM_OK;
+}
+
+int lowp_batch_run(LowpBatch* B, hipStream_t s) {
+  if (B->exec) {
+    UHM_HIP(hipGraphLaunch(B->exec, s));
+  } else {
+    batch_launch(B, s);
+  }
+  const hipError_t he = hipGetLastError();
+  if (he != hipSuccess) return fail(UHM_EHIP, std::string("batched launch: ") + hipGetErrorString(he));
+  return UHM_OK;
+}
+
+int lowp_batch_capture(LowpBatch* B, hipStream_t s) {
+  if (!s) return fail(UHM_EINVAL, "graph capture needs a non-default stream");
+  if (B->exec) return UHM_OK;
+  UHM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  batch_launch(B, s);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (e != hipSuccess) return fail(UHM_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  B->graph = g;
+  UHM_HIP(hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0));
+  return UHM_OK;
+}
+
+// Time every candidate schedule (width x order) on the device and keep the fastest; the
+// winner is cached for batches of the same signature in this process.
+int lowp_batch_tune(LowpBatch* B, hipStream_t s, int32_t* width_out, int32_t* order_out, double* ms_out) {
+  auto it = tune_cache().find(B->signature);
+  BatchConfig best;
+  double best_ms = -1.0;
+  if (it != tune_cache().end()) {
+    best = it->second;
+  } else {
+    hipEvent_t a, b;
+    UHM_HIP(hipEventCreate(&a));
+    UHM_HIP(hipEventCreate(&b));
+    for (int32_t wdt : kTileWidths)
+      for (int32_t ord = 0; ord < 3; ++ord) {
+        BatchConfig c;
+        c.coup_cols = wdt;
+        c.order = ord;
+        int rc = configure(B, c, s);
+        if (rc) {
+          (void)hipEventDestroy(a);
+          (void)hipEventDestroy(b);
+          return rc;
+        }
+        batch_launch(B, s);  // warm
+        UHM_HIP(hipEventRecord(a, s));
+        for (int rep = 0; rep < 3; ++rep) batch_launch(B, s);
+        UHM_HIP(hipEventRecord(b, s));
+        UHM_HIP(hipEventSynchronize(b));
+        float ms = 0.f;
+        UHM_HIP(hipEventElapsedTime(&ms, a, b));
+        ms /= 3.f;
+        if (best_ms < 0.0 || ms < best_ms) {
+          best_ms = ms;
+          best = c;
+        }
+      }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    tune_cache()[B->signature] = best;
+  }
+  int rc = configure(B, best, s);
+  if (rc) return rc;
+  if (width_out) *width_out = best.coup_cols;
+  if (order_out) *order_out = best.order;
+  if (ms_out) *ms_out = best_ms;
+  return UHM_OK;
+}
+
 }  // namespace uhm_detail
+
+using namespace uhm_detail;
+
+extern "C" {
+
+int uhm_batch_create(uhm_op* const* ops, int32_t nops, const void* const* X, const int64_t* ldx, void* const* Y,
+                     const int64_t* ldy, const int32_t* nrhs, void* hip_stream, uhm_batch** out) {
+  if (!out) return fail(UHM_EINVAL, "null argument");
+  LowpBatch* b = nullptr;
+  const int rc = lowp_batch_create(ops, nops, X, ldx, Y, ldy, nrhs, static_cast<hipStream_t>(hip_stream), &b);
+  *out = reinterpret_cast<uhm_batch*>(b);
+  return rc;
+}
+
+int uhm_batch_run(uhm_batch* b, void* hip_stream) {
+  if (!b) return fail(UHM_EINVAL, "null batch");
+  return lowp_batch_run(reinterpret_cast<LowpBatch*>(b), static_cast<hipStream_t>(hip_stream));
+}
+
+int uhm_batch_tune(uhm_batch* b, void* hip_stream, int32_t* tile_width, int32_t* order, double* best_ms) {
+  if (!b) return fail(UHM_EINVAL, "null batch");
+  return lowp_batch_tune(reinterpret_cast<LowpBatch*>(b), static_cast<hipStream_t>(hip_stream), tile_width, order,
+                         best_ms);
+}
+
+int uhm_batch_capture(uhm_batch* b, void* hip_stream) {
+  if (!b) return fail(UHM_EINVAL, "null batch");
+  return lowp_batch_capture(reinterpret_cast<LowpBatch*>(b), static_cast<hipStream_t>(hip_stream));
+}
+
+void uhm_batch_free(uhm_batch* b) { lowp_batch_delete(reinterpret_cast<LowpBatch*>(b)); }
+
+}  // extern "C"
