@@ -285,6 +285,77 @@ __device__ __forceinline__ void scatter_body(int64_t q, const V* __restrict__ Yc
   y[perm[pos] + (int64_t)j * ldy] = Yc[pos * R + j];
 }
 
+// One LDS round covers up to KBR k-blocks.  Its memory requests are issued in batches so a
+// round waits on about two memory latencies, not one per element and per k-block: the
+// gather indices of the B operand, then the A chunks of all its k-blocks, then the B values.
+// Every load of a batch is issued unconditionally from an address that is always in bounds
+// (out-of-range slots re-read a valid one) and results are masked where they are used, so
+// no load waits on a branch and the waits count only the batch they need.
+template <int ST, int NT>
+struct Round {
+  using T_ = Tr<ST>;
+  static constexpr int KBR = T_::RZ / T_::KB;                   // k-blocks per round
+  static constexpr int PQ = T_::RZ * 16 * NT / (64 * kLpWaves);  // B elements per thread
+  typename T_::CHUNK a[KBR];
+  typename T_::V v[PQ];
+  int32_t id[PQ];
+  bool ok[PQ];
+};
+
+// A chunks of k-blocks kb .. kb+nkr-1 (nkr >= 1) of an m-tile with hm >= 1 valid rows.
+// Lanes of rows i >= hm re-read row 0 and slots b >= nkr re-read k-block kb: those values
+// only reach accumulator rows that are never stored, or no MFMA at all.
+template <int ST, int NT>
+__device__ __forceinline__ void round_issue_a(Round<ST, NT>& Q, const uint4* tile, int kb, int nkr, int hm, int g,
+                                              int i) {
+  using T_ = Tr<ST>;
+  const int ii = i < hm ? i : 0;
+#pragma unroll
+  for (int b = 0; b < Round<ST, NT>::KBR; ++b) {
+    const int kbb = kb + (b < nkr ? b : 0);
+    load_chunk(tile + (int64_t)kbb * T_::CH * 4 * hm + T_::CH * (g * hm + ii), true, Q.a[b]);
+  }
+}
+
+// Raw gather indices of the round's B elements; element q is (k, j) = (q / R, q % R),
+// R = 16 NT, and q >= nk R re-reads k = nk - 1.
+template <int ST, int NT, class Idx>
+__device__ __forceinline__ void round_indices(Round<ST, NT>& Q, int nk, Idx idx) {
+  constexpr int R = 16 * NT;
+#pragma unroll
+  for (int u = 0; u < Round<ST, NT>::PQ; ++u) {
+    const int q = threadIdx.x + u * 64 * kLpWaves;
+    Q.id[u] = idx(min(q / R, nk - 1));
+  }
+}
+// B values: src(index, j, ok) returns the element's address when ok, else any valid address.
+template <int ST, int NT, class Src>
+__device__ __forceinline__ void round_values(Round<ST, NT>& Q, int nk, Src src) {
+  constexpr int R = 16 * NT;
+#pragma unroll
+  for (int u = 0; u < Round<ST, NT>::PQ; ++u) {
+    const int q = threadIdx.x + u * 64 * kLpWaves;
+    Q.ok[u] = q < nk * R && Q.id[u] != kZero;
+    Q.v[u] = *src(Q.id[u], q % R, Q.ok[u]);
+  }
+}
+template <int ST, int NT>
+__device__ __forceinline__ void round_commit(typename Tr<ST>::LDS& L, const Round<ST, NT>& Q, int nk) {
+  constexpr int R = 16 * NT;
+#pragma unroll
+  for (int u = 0; u < Round<ST, NT>::PQ; ++u) {
+    const int q = threadIdx.x + u * 64 * kLpWaves;
+    if (q < nk * R) lds_put(L, q / R, q % R, Q.ok[u] ? Q.v[u] : vzero<typename Tr<ST>::V>());
+  }
+}
+template <int ST, int NT>
+__device__ __forceinline__ void round_mma(const Round<ST, NT>& Q, const typename Tr<ST>::LDS& L, int nkr, int g, int i,
+                                          typename Tr<ST>::ACC* cr, typename Tr<ST>::ACC* ci) {
+#pragma unroll
+  for (int b = 0; b < Round<ST, NT>::KBR; ++b)
+    if (b < nkr) mma_block<NT, Tr<ST>::RZ>(Q.a[b], L, b * Tr<ST>::KB, g, i, cr, ci);
+}
+
 // P_lambda = F_lambda^* X_lambda for one leaf.
 template <int ST, int NT>
 __device__ __forceinline__ void forward_body(typename Tr<ST>::LDS& L, int leaf, const uint4* __restrict__ F,
@@ -294,58 +365,61 @@ __device__ __forceinline__ void forward_body(typename Tr<ST>::LDS& L, int leaf, 
                                              const typename Tr<ST>::V* __restrict__ Xc, int R,
                                              typename Tr<ST>::V* __restrict__ p) {
   using T_ = Tr<ST>;
-  using V = typename T_::V;
+  using Q_ = Round<ST, NT>;
   const int M = f_M[leaf];
   if (M == 0) return;
   const int n = leaf_n[leaf], nkb = f_nkb[leaf];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, i = lane & 15;
   const uint4* base = F + f_off[leaf];
   const int nmt = (M + 15) >> 4;
-  constexpr int KBR = T_::RZ / T_::KB;  // k-blocks per LDS round
+  const typename T_::V* xl = Xc + (int64_t)leaf_pos[leaf] * R;
+  constexpr int KBR = Q_::KBR;
+  // rows k < n of the leaf; padding rows read row 0 and are masked
+  auto src = [&](int32_t k, int j, bool ok) { return xl + (ok ? (int64_t)k * R + j : 0); };
+  auto row = [&](int k0) { return [=](int k) { return k0 + k < n ? k0 + k : kZero; }; };
   if (nkb <= KBR) {
-    // the whole leaf fits one round: stage once, sweep all m-tiles
-    for (int q = t; q < nkb * T_::KB * R; q += 64 * kLpWaves) {
-      const int k = q / R, j = q - k * R;
-      lds_put(L, k, j, k < n ? Xc[(int64_t)(leaf_pos[leaf] + k) * R + j] : vzero<V>());
-    }
+    // the whole leaf fits one round: stage once, then sweep the m-tiles with the next
+    // m-tile's A chunks in flight while the current one multiplies
+    Q_ Q, Qn;
+    int mt = w;
+    round_indices<ST, NT>(Q, nkb * T_::KB, row(0));
+    const int m0 = mt < nmt ? mt : 0;
+    round_issue_a<ST, NT>(Q, base + (int64_t)m0 * nkb * T_::CH * 64, 0, nkb, min(16, M - 16 * m0), g, i);
+    round_values<ST, NT>(Q, nkb * T_::KB, src);
+    round_commit<ST, NT>(L, Q, nkb * T_::KB);
     __syncthreads();
-    for (int mt = w; mt < nmt; mt += kLpWaves) {
+    for (; mt < nmt; mt += kLpWaves) {
       const int hm = min(16, M - 16 * mt);
-      const uint4* tile = base + (int64_t)mt * nkb * T_::CH * 64;
+      const int mn = mt + kLpWaves < nmt ? mt + kLpWaves : mt;
+      round_issue_a<ST, NT>(Qn, base + (int64_t)mn * nkb * T_::CH * 64, 0, nkb, min(16, M - 16 * mn), g, i);
       typename T_::ACC cr[NT], ci[NT];
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = typename T_::ACC{0, 0, 0, 0};
-      for (int kb = 0; kb < nkb; ++kb) {
-        typename T_::CHUNK a;
-        load_chunk(tile + (int64_t)kb * T_::CH * 4 * hm + T_::CH * (g * hm + i), i < hm, a);
-        mma_block<NT, T_::RZ>(a, L, kb * T_::KB, g, i, cr, ci);
-      }
+      round_mma<ST, NT>(Q, L, nkb, g, i, cr, ci);
       store_tile<ST, NT>(p, poff[leaf] + 16 * mt, hm, R, g, i, cr, ci);
+#pragma unroll
+      for (int b = 0; b < KBR; ++b) Q.a[b] = Qn.a[b];
     }
   } else {
     // leaf rows in several rounds: m-tiles in groups of kLpWaves, restaged per group
+    Q_ Q;
     for (int mt0 = 0; mt0 < nmt; mt0 += kLpWaves) {
       const int mt = mt0 + w;
-      const int hm = min(16, M - 16 * mt);
-      const uint4* tile = base + (int64_t)mt * nkb * T_::CH * 64;
+      const int ma = mt < nmt ? mt : 0;
+      const int hm = min(16, M - 16 * ma);
+      const uint4* tile = base + (int64_t)ma * nkb * T_::CH * 64;
       typename T_::ACC cr[NT], ci[NT];
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = typename T_::ACC{0, 0, 0, 0};
       for (int kb = 0; kb < nkb; kb += KBR) {
-        const int nk = min(KBR, nkb - kb) * T_::KB;
+        const int nkr = min(KBR, nkb - kb), nk = nkr * T_::KB;
+        round_indices<ST, NT>(Q, nk, row(kb * T_::KB));
+        round_issue_a<ST, NT>(Q, tile, kb, nkr, hm, g, i);
+        round_values<ST, NT>(Q, nk, src);
         __syncthreads();
-        for (int q = t; q < nk * R; q += 64 * kLpWaves) {
-          const int k = q / R, j = q - k * R;
-          const int row = kb * T_::KB + k;
-          lds_put(L, k, j, row < n ? Xc[(int64_t)(leaf_pos[leaf] + row) * R + j] : vzero<V>());
-        }
+        round_commit<ST, NT>(L, Q, nk);
         __syncthreads();
-        if (mt < nmt)
-          for (int b = 0; b < nk / T_::KB; ++b) {
-            typename T_::CHUNK a;
-            load_chunk(tile + (int64_t)(kb + b) * T_::CH * 4 * hm + T_::CH * (g * hm + i), i < hm, a);
-            mma_block<NT, T_::RZ>(a, L, b * T_::KB, g, i, cr, ci);
-          }
+        if (mt < nmt) round_mma<ST, NT>(Q, L, nkr, g, i, cr, ci);
       }
       if (mt < nmt) store_tile<ST, NT>(p, poff[leaf] + 16 * mt, hm, R, g, i, cr, ci);
     }
@@ -384,32 +458,33 @@ __device__ __forceinline__ void coupling_body(typename Tr<ST>::LDS& L, const LpC
                                               const typename Tr<ST>::V* __restrict__ xh, int R,
                                               typename Tr<ST>::V* __restrict__ part) {
   using T_ = Tr<ST>;
-  using V = typename T_::V;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, i = lane & 15;
   const int nmt = (T.h + 15) >> 4;
   const int hm = min(16, T.h - 16 * w);
-  const uint4* tile = S + T.base + (int64_t)w * T.nkb_all * T_::CH * 64;
   typename T_::ACC cr[NT], ci[NT];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = typename T_::ACC{0, 0, 0, 0};
-  constexpr int KBR = T_::RZ / T_::KB;
+  using Q_ = Round<ST, NT>;
+  constexpr int KBR = Q_::KBR;
+  // waves without an m-tile re-read m-tile 0 and skip the MFMAs
+  const int hma = w < nmt ? hm : min(16, T.h);
+  const uint4* tila = S + T.base + (int64_t)(w < nmt ? w : 0) * T.nkb_all * T_::CH * 64;
+  // column c of the chunk reads xh row colsrc[c] (< 0: zero); masked slots read row 0
+  auto src = [&](int32_t sc, int j, bool ok) { return xh + (ok ? (int64_t)sc * R + j : 0); };
+  Q_ Q;
   for (int kb = 0; kb < T.nkb; kb += KBR) {
-    const int nk = min(KBR, T.nkb - kb) * T_::KB;
-    const int64_t c0 = T.csrc + (int64_t)(T.kb0 + kb) * T_::KB;
+    const int nkr = min(KBR, T.nkb - kb), nk = nkr * T_::KB;
+    const int32_t* cs = colsrc + T.csrc + (int64_t)(T.kb0 + kb) * T_::KB;
+    round_indices<ST, NT>(Q, nk, [&](int k) {
+      const int32_t sc = cs[k];
+      return sc >= 0 ? sc : kZero;
+    });
+    round_issue_a<ST, NT>(Q, tila, T.kb0 + kb, nkr, hma, g, i);
+    round_values<ST, NT>(Q, nk, src);
     __syncthreads();
-    for (int q = t; q < nk * R; q += 64 * kLpWaves) {
-      const int k = q / R, j = q - k * R;
-      const int32_t src = colsrc[c0 + k];
-      lds_put(L, k, j, src >= 0 ? xh[(int64_t)src * R + j] : vzero<V>());
-    }
+    round_commit<ST, NT>(L, Q, nk);
     __syncthreads();
-    if (w < nmt) {
-      for (int b = 0; b < nk / T_::KB; ++b) {
-        typename T_::CHUNK a;
-        load_chunk(tile + (int64_t)(T.kb0 + kb + b) * T_::CH * 4 * hm + T_::CH * (g * hm + i), i < hm, a);
-        mma_block<NT, T_::RZ>(a, L, b * T_::KB, g, i, cr, ci);
-      }
-    }
+    if (w < nmt) round_mma<ST, NT>(Q, L, nkr, g, i, cr, ci);
   }
   if (w < nmt) store_tile<ST, NT>(part, (int64_t)T.part * 64 + 16 * w, hm, R, g, i, cr, ci);
 }
@@ -447,38 +522,33 @@ __device__ __forceinline__ void backward_body(typename Tr<ST>::LDS& L, int leaf,
                                               const typename Tr<ST>::V* __restrict__ Xc, int R,
                                               typename Tr<ST>::V* __restrict__ Yc) {
   using T_ = Tr<ST>;
-  using V = typename T_::V;
   const int n = leaf_n[leaf], nkb = b_nkb[leaf];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, i = lane & 15;
   const int nmt = (n + 15) >> 4;
   const int hm = min(16, n - 16 * w);
-  const uint4* tile = B + b_off[leaf] + (int64_t)w * nkb * T_::CH * 64;
   const int32_t* zm = zmap + zoff[leaf];
   typename T_::ACC cr[NT], ci[NT];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = typename T_::ACC{0, 0, 0, 0};
-  constexpr int KBR = T_::RZ / T_::KB;
+  using Q_ = Round<ST, NT>;
+  constexpr int KBR = Q_::KBR;
+  const int hma = w < nmt ? hm : min(16, n);
+  const uint4* tila = B + b_off[leaf] + (int64_t)(w < nmt ? w : 0) * nkb * T_::CH * 64;
+  // map entry m >= 0: yh row m; m < 0 (not kZero): row -1 - m of the cluster-ordered input
+  auto src = [&](int32_t m, int j, bool ok) {
+    return ok ? (m >= 0 ? yh + (int64_t)m * R + j : Xc + (int64_t)(-1 - m) * R + j) : Xc;
+  };
+  Q_ Q;
   for (int kb = 0; kb < nkb; kb += KBR) {
-    const int nk = min(KBR, nkb - kb) * T_::KB;
+    const int nkr = min(KBR, nkb - kb), nk = nkr * T_::KB;
+    const int32_t* zk = zm + kb * T_::KB;
+    round_indices<ST, NT>(Q, nk, [&](int k) { return zk[k]; });
+    round_issue_a<ST, NT>(Q, tila, kb, nkr, hma, g, i);
+    round_values<ST, NT>(Q, nk, src);
     __syncthreads();
-    for (int q = t; q < nk * R; q += 64 * kLpWaves) {
-      const int k = q / R, j = q - k * R;
-      const int32_t m = zm[kb * T_::KB + k];
-      V v = vzero<V>();
-      if (m >= 0)
-        v = yh[(int64_t)m * R + j];
-      else if (m != kZero)
-        v = Xc[(int64_t)(-1 - m) * R + j];
-      lds_put(L, k, j, v);
-    }
+    round_commit<ST, NT>(L, Q, nk);
     __syncthreads();
-    if (w < nmt) {
-      for (int b = 0; b < nk / T_::KB; ++b) {
-        typename T_::CHUNK a;
-        load_chunk(tile + (int64_t)(kb + b) * T_::CH * 4 * hm + T_::CH * (g * hm + i), i < hm, a);
-        mma_block<NT, T_::RZ>(a, L, b * T_::KB, g, i, cr, ci);
-      }
-    }
+    if (w < nmt) round_mma<ST, NT>(Q, L, nkr, g, i, cr, ci);
   }
   if (w < nmt) store_tile<ST, NT>(Yc, (int64_t)leaf_pos[leaf] + 16 * w, hm, R, g, i, cr, ci);
 }
