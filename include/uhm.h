@@ -183,12 +183,15 @@ typedef struct {
   double seconds_total;     /* wall clock of the solve (synchronized) */
   double seconds_products;  /* of which spent in operator products */
   double seconds_arnoldi;   /* of which spent in the orthogonalisation and updates */
+  int64_t second_passes;    /* column-steps that needed the second Gram-Schmidt pass */
 } uhm_gmres_info;
 
 /*
- * Solve A X = B by restarted GMRES(m) (textbook GMRES with classical Gram-Schmidt
- * applied twice, FP64 Krylov vectors, Givens least-squares), for nrhs right-hand sides
- * at once, each with its own Krylov space.  X starts at zero and is overwritten.
+ * Solve A X = B by restarted GMRES(m) (textbook GMRES with classical Gram-Schmidt,
+ * repeated once for a column whose norm drops below 1/sqrt(2) of its value in the first
+ * pass (Daniel, Gragg, Kaufman and Stewart), FP64 Krylov vectors, Givens least-squares),
+ * for nrhs right-hand sides at once, each with its own Krylov space.  X starts at zero
+ * and is overwritten.
  *   op:    the operator A, UHM_C128 or UHM_C128_MULTI storage (the true-residual operator).
  *   inner: NULL for plain GMRES on op; otherwise an operator of the same matrix in
  *          complex64 or bf16-pair storage, and the solve is mixed-precision iterative

@@ -51,7 +51,8 @@ class GmresOpts(ctypes.Structure):
 class GmresInfo(ctypes.Structure):
     _fields_ = [("iterations", I32), ("restarts", I32), ("refinements", I32), ("converged", I32),
                 ("rel_residual", ctypes.c_double), ("seconds_total", ctypes.c_double),
-                ("seconds_products", ctypes.c_double), ("seconds_arnoldi", ctypes.c_double)]
+                ("seconds_products", ctypes.c_double), ("seconds_arnoldi", ctypes.c_double),
+                ("second_passes", I64)]
 
 
 KRYLOV_DONE, KRYLOV_PRODUCT_HIGH, KRYLOV_PRODUCT_LOW = 0, 1, 2

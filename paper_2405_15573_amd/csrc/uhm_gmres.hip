@@ -3,12 +3,16 @@
 // Every right-hand side has its own Krylov space; all of them advance in lockstep so that
 // each Arnoldi step is one batched product with the operator (uhm_matvec over nrhs
 // columns) plus batched FP64 kernels:
-//   dots     h_i = V_i^* w for i <= j (classical Gram-Schmidt), per column,
+//   dots     h_i = V_i^* w for i <= j (classical Gram-Schmidt), per column, with ||w||^2,
 //   update   w -= sum_i V_i h_i, with the partial sums of ||w||^2,
-//   scale    V_{j+1} = w / ||w||,
-// and Gram-Schmidt is applied twice.  The reductions are two-pass over fixed row chunks
-// (deterministic).  The (m+1) x m Hessenberg matrices, the Givens rotations and the small
-// triangular solves are done on the host in FP64 from the few numbers each step produces.
+//   scale    V_{j+1} = w / ||w||.
+// Classical Gram-Schmidt is repeated once for the columns whose norm fell below 1/sqrt(2)
+// of its value before the projection (the reorthogonalisation criterion of Daniel, Gragg,
+// Kaufman and Stewart, 1976); the other columns skip the second pass.  Partial sums are
+// per wavefront over fixed row ranges and are reduced in a fixed order (deterministic).
+// The (m+1) x m Hessenberg matrices, the Givens rotations and the small triangular solves
+// are done on the host in FP64 from the few numbers each step produces, after one
+// synchronisation per step.
 //
 // With an inner operator (complex64 or bf16 pairs) the solve is iterative refinement: the
 // residual r = b - A x is formed with the FP64 operator, an inner GMRES(m) whose products
@@ -52,75 +56,167 @@ __device__ __forceinline__ void block_sum2(double re, double im, double* sh, dou
     }
 }
 
-// part[((i * r) + c) * nch + ch] = sum over the chunk's rows of conj(V_i[row, c]) w[row, c]
-__global__ __launch_bounds__(kGB) void k_g_dots(const cd* __restrict__ V, int64_t vstride, int nvec,
-                                                const cd* __restrict__ w, int64_t n, int r, int nch,
-                                                cd* __restrict__ part) {
-  __shared__ double sh[2 * kGB / 64];
-  const int ch = blockIdx.x, c = blockIdx.y;
-  const int64_t r0 = (int64_t)ch * kGRows;
-  const int64_t r1 = min(n, r0 + kGRows);
-  constexpr int PER = kGRows / kGB;
-  cd wv[PER];
+// ---- Arnoldi kernels: one wavefront per kAWRows rows of one column, kAPer rows per lane
+constexpr int kAWRows = 512;
+constexpr int kAPer = kAWRows / 64;
+
+// part[(i r + c) nsub + sb] = sum over the rows of wave sb of conj(V_i[row, c]) w[row, c];
+// w2[c nsub + sb] = the same rows' sum of |w|^2 (when w2 is given).  Columns with
+// need[c] == 0 are skipped (when need is given).
+__global__ __launch_bounds__(kGB) void k_a_dots(const cd* __restrict__ V, int64_t vstride, int nvec,
+                                                const cd* __restrict__ w, int64_t n, int r, int nsub,
+                                                const int* __restrict__ need, cd* __restrict__ part,
+                                                double* __restrict__ w2) {
+  const int sb = blockIdx.x * (kGB / 64) + (threadIdx.x >> 6), c = blockIdx.y, lane = threadIdx.x & 63;
+  if (sb >= nsub || (need && !need[c])) return;
+  const int64_t r0 = (int64_t)sb * kAWRows;
+  const cd* wc = w + (int64_t)c * n;
+  cd wv[kAPer];
+  double s2 = 0.0;
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int64_t row = r0 + threadIdx.x + (int64_t)q * kGB;
-    wv[q] = row < r1 ? w[(int64_t)c * n + row] : make_double2(0.0, 0.0);
+  for (int q = 0; q < kAPer; ++q) {
+    const int64_t row = r0 + q * 64 + lane;
+    wv[q] = row < n ? wc[row] : make_double2(0.0, 0.0);
+    s2 = fma(wv[q].x, wv[q].x, fma(wv[q].y, wv[q].y, s2));
   }
-  for (int i = 0; i < nvec; ++i) {
-    const cd* vi = V + (int64_t)i * vstride + (int64_t)c * n;
-    double re = 0.0, im = 0.0;
+  if (w2) {
+    s2 = warp_sum(s2);
+    if (lane == 0) w2[(int64_t)c * nsub + sb] = s2;
+  }
+  const int64_t lim = n - r0 - lane;  // rows q * 64 < lim are in range
+  int i = 0;
+  for (; i + 1 < nvec; i += 2) {
+    const cd* va = V + (int64_t)i * vstride + (int64_t)c * n + r0 + lane;
+    const cd* vb = va + vstride;
+    cd a[kAPer], b[kAPer];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int64_t row = r0 + threadIdx.x + (int64_t)q * kGB;
-      if (row < r1) {
-        const cd v = vi[row];
-        re = fma(v.x, wv[q].x, fma(v.y, wv[q].y, re));
-        im = fma(v.x, wv[q].y, fma(-v.y, wv[q].x, im));
-      }
+    for (int q = 0; q < kAPer; ++q) {
+      const bool ok = q * 64 < lim;
+      a[q] = ok ? va[q * 64] : make_double2(0.0, 0.0);
+      b[q] = ok ? vb[q * 64] : make_double2(0.0, 0.0);
     }
-    double sr, si;
-    block_sum2(re, im, sh, sr, si);
-    if (threadIdx.x == 0) part[((int64_t)i * r + c) * nch + ch] = make_double2(sr, si);
+    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+#pragma unroll
+    for (int q = 0; q < kAPer; ++q) {
+      ar = fma(a[q].x, wv[q].x, fma(a[q].y, wv[q].y, ar));
+      ai = fma(a[q].x, wv[q].y, fma(-a[q].y, wv[q].x, ai));
+      br = fma(b[q].x, wv[q].x, fma(b[q].y, wv[q].y, br));
+      bi = fma(b[q].x, wv[q].y, fma(-b[q].y, wv[q].x, bi));
+    }
+    ar = warp_sum(ar);
+    ai = warp_sum(ai);
+    br = warp_sum(br);
+    bi = warp_sum(bi);
+    if (lane == 0) {
+      part[((int64_t)i * r + c) * nsub + sb] = make_double2(ar, ai);
+      part[((int64_t)(i + 1) * r + c) * nsub + sb] = make_double2(br, bi);
+    }
+  }
+  if (i < nvec) {
+    const cd* va = V + (int64_t)i * vstride + (int64_t)c * n + r0 + lane;
+    double ar = 0.0, ai = 0.0;
+#pragma unroll
+    for (int q = 0; q < kAPer; ++q) {
+      const cd a = q * 64 < lim ? va[q * 64] : make_double2(0.0, 0.0);
+      ar = fma(a.x, wv[q].x, fma(a.y, wv[q].y, ar));
+      ai = fma(a.x, wv[q].y, fma(-a.y, wv[q].x, ai));
+    }
+    ar = warp_sum(ar);
+    ai = warp_sum(ai);
+    if (lane == 0) part[((int64_t)i * r + c) * nsub + sb] = make_double2(ar, ai);
   }
 }
 
-// out[q] = sum_ch part[q * nch + ch]
-__global__ __launch_bounds__(kGB) void k_g_reduce(const cd* __restrict__ part, int nch, int64_t nq, cd* __restrict__ out) {
+// out[q] = sum_sb part[q nsub + sb], q = i r + c; zero for columns with need[c] == 0.
+__global__ __launch_bounds__(kGB) void k_a_reduce(const cd* __restrict__ part, int nsub, int64_t nq, int r,
+                                                  const int* __restrict__ need, cd* __restrict__ out) {
   const int64_t q = (int64_t)blockIdx.x * kGB + threadIdx.x;
   if (q >= nq) return;
   double re = 0.0, im = 0.0;
-  for (int ch = 0; ch < nch; ++ch) {
-    const cd v = part[q * nch + ch];
-    re += v.x;
-    im += v.y;
-  }
+  if (!need || need[q % r])
+    for (int sb = 0; sb < nsub; ++sb) {
+      const cd v = part[q * nsub + sb];
+      re += v.x;
+      im += v.y;
+    }
   out[q] = make_double2(re, im);
 }
 
-// w[:, c] -= sum_i V_i[:, c] h[i * r + c]; nrm[c * nch + ch] = partial ||w_new||^2
-__global__ __launch_bounds__(kGB) void k_g_update(const cd* __restrict__ V, int64_t vstride, int nvec,
+// w[:, c] -= sum_i V_i[:, c] h[i r + c]; w2[c nsub + sb] = partial ||w_new||^2.
+__global__ __launch_bounds__(kGB) void k_a_update(const cd* __restrict__ V, int64_t vstride, int nvec,
                                                   const cd* __restrict__ h, cd* __restrict__ w, int64_t n, int r,
-                                                  int nch, double* __restrict__ nrm) {
-  __shared__ double sh[2 * kGB / 64];
-  const int ch = blockIdx.x, c = blockIdx.y;
-  const int64_t r0 = (int64_t)ch * kGRows;
-  const int64_t r1 = min(n, r0 + kGRows);
-  double acc = 0.0;
-  for (int64_t row = r0 + threadIdx.x; row < r1; row += kGB) {
-    cd a = w[(int64_t)c * n + row];
-    for (int i = 0; i < nvec; ++i) {
-      const cd v = V[(int64_t)i * vstride + (int64_t)c * n + row];
-      const cd hi = h[(int64_t)i * r + c];
-      a.x -= v.x * hi.x - v.y * hi.y;
-      a.y -= v.x * hi.y + v.y * hi.x;
+                                                  int nsub, const int* __restrict__ need, double* __restrict__ w2) {
+  const int sb = blockIdx.x * (kGB / 64) + (threadIdx.x >> 6), c = blockIdx.y, lane = threadIdx.x & 63;
+  if (sb >= nsub || (need && !need[c])) return;
+  const int64_t r0 = (int64_t)sb * kAWRows;
+  const int64_t lim = n - r0 - lane;
+  cd* wc = w + (int64_t)c * n + r0 + lane;
+  cd wv[kAPer];
+#pragma unroll
+  for (int q = 0; q < kAPer; ++q) wv[q] = q * 64 < lim ? wc[q * 64] : make_double2(0.0, 0.0);
+  int i = 0;
+  for (; i + 1 < nvec; i += 2) {
+    const cd* va = V + (int64_t)i * vstride + (int64_t)c * n + r0 + lane;
+    const cd* vb = va + vstride;
+    const cd ha = h[(int64_t)i * r + c], hb = h[(int64_t)(i + 1) * r + c];
+    cd a[kAPer], b[kAPer];
+#pragma unroll
+    for (int q = 0; q < kAPer; ++q) {
+      const bool ok = q * 64 < lim;
+      a[q] = ok ? va[q * 64] : make_double2(0.0, 0.0);
+      b[q] = ok ? vb[q * 64] : make_double2(0.0, 0.0);
     }
-    w[(int64_t)c * n + row] = a;
-    acc += a.x * a.x + a.y * a.y;
+#pragma unroll
+    for (int q = 0; q < kAPer; ++q) {
+      wv[q].x -= a[q].x * ha.x - a[q].y * ha.y;
+      wv[q].y -= a[q].x * ha.y + a[q].y * ha.x;
+      wv[q].x -= b[q].x * hb.x - b[q].y * hb.y;
+      wv[q].y -= b[q].x * hb.y + b[q].y * hb.x;
+    }
   }
-  double s, dummy;
-  block_sum2(acc, 0.0, sh, s, dummy);
-  if (threadIdx.x == 0) nrm[(int64_t)c * nch + ch] = s;
+  if (i < nvec) {
+    const cd* va = V + (int64_t)i * vstride + (int64_t)c * n + r0 + lane;
+    const cd ha = h[(int64_t)i * r + c];
+#pragma unroll
+    for (int q = 0; q < kAPer; ++q) {
+      const cd a = q * 64 < lim ? va[q * 64] : make_double2(0.0, 0.0);
+      wv[q].x -= a.x * ha.x - a.y * ha.y;
+      wv[q].y -= a.x * ha.y + a.y * ha.x;
+    }
+  }
+  double s2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < kAPer; ++q)
+    if (q * 64 < lim) {
+      wc[q * 64] = wv[q];
+      s2 = fma(wv[q].x, wv[q].x, fma(wv[q].y, wv[q].y, s2));
+    }
+  s2 = warp_sum(s2);
+  if (lane == 0) w2[(int64_t)c * nsub + sb] = s2;
+}
+
+// need[c] = (||w after the projection||^2 < ||w before||^2 / 2)
+__global__ void k_a_decide(const double* __restrict__ w0, const double* __restrict__ w1, int nsub, int r,
+                           int* __restrict__ need) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= r) return;
+  double s0 = 0.0, s1 = 0.0;
+  for (int sb = 0; sb < nsub; ++sb) {
+    s0 += w0[(int64_t)c * nsub + sb];
+    s1 += w1[(int64_t)c * nsub + sb];
+  }
+  need[c] = s1 < 0.5 * s0;
+}
+
+// out[c] = (||w||, need[c]) with ||w|| from the last pass the column ran
+__global__ void k_a_final(const double* __restrict__ w1, const double* __restrict__ w2, const int* __restrict__ need,
+                          int nsub, int r, cd* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= r) return;
+  const double* src = need[c] ? w2 : w1;
+  double s = 0.0;
+  for (int sb = 0; sb < nsub; ++sb) s += src[(int64_t)c * nsub + sb];
+  out[c] = make_double2(sqrt(s), (double)need[c]);
 }
 
 // nrm_out[c] = sqrt(sum_ch nrm[c * nch + ch])
@@ -245,12 +341,27 @@ __global__ __launch_bounds__(kGB) void k_g_unpack32(const cf* __restrict__ src, 
 using C = std::complex<double>;
 using Clock = std::chrono::steady_clock;
 
+// Pinned host memory for the per-step device-to-host copies.
+struct PinnedHost {
+  cd* p = nullptr;
+  int alloc(int64_t count) {
+    UHM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), sizeof(cd) * (size_t)count, hipHostMallocDefault));
+    return UHM_OK;
+  }
+  ~PinnedHost() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
 struct Work {
   int64_t n = 0;
-  int r = 0, m = 0, nch = 0;
+  int r = 0, m = 0, nch = 0, nsub = 0;
   DevArray<cd> V, w, t, d, part, hbuf, ybuf;
   DevArray<double> nrm, nrm_out;
+  DevArray<int> need;
   DevArray<cf> x32, y32;
+  PinnedHost hx;  // h of both passes and the final norms of one step
+  int64_t reorth = 0;  // columns that needed the second Gram-Schmidt pass
   double t_prod = 0.0, t_arn = 0.0;
 };
 
@@ -259,11 +370,14 @@ int alloc_work(Work& W, int64_t n, int r, int m, bool lowp) {
   W.r = r;
   W.m = m;
   W.nch = (int)((n + kGRows - 1) / kGRows);
+  W.nsub = (int)((n + kAWRows - 1) / kAWRows);
+  const int64_t hsz = 2 * (int64_t)(m + 1) * r + r;
   int rc;
   if ((rc = W.V.alloc((int64_t)(m + 1) * n * r)) || (rc = W.w.alloc(n * r)) || (rc = W.t.alloc(n * r)) ||
-      (rc = W.d.alloc(n * r)) || (rc = W.part.alloc((int64_t)(m + 1) * r * W.nch)) ||
-      (rc = W.hbuf.alloc((int64_t)(m + 1) * r)) || (rc = W.ybuf.alloc((int64_t)(m + 1) * r)) ||
-      (rc = W.nrm.alloc((int64_t)r * W.nch)) || (rc = W.nrm_out.alloc(r)))
+      (rc = W.d.alloc(n * r)) || (rc = W.part.alloc((int64_t)(m + 1) * r * std::max(W.nch, W.nsub))) ||
+      (rc = W.hbuf.alloc(hsz)) || (rc = W.ybuf.alloc((int64_t)(m + 1) * r)) ||
+      (rc = W.nrm.alloc(3 * (int64_t)r * std::max(W.nch, W.nsub))) || (rc = W.nrm_out.alloc(r)) ||
+      (rc = W.need.alloc(r)) || (rc = W.hx.alloc(hsz)))
     return rc;
   if (lowp && ((rc = W.x32.alloc(n * r)) || (rc = W.y32.alloc(n * r)))) return rc;
   return UHM_OK;
@@ -307,7 +421,7 @@ struct uhm_krylov {
   enum Phase { ITER, CYCLE_END, INNER_FINAL_X, OUTER, FINISHED } phase = FINISHED;
   std::vector<double> bn, rn, rtol, beta, hn, sc;
   std::vector<std::complex<double>> H, g, cs, sn;
-  std::vector<cd> hh, hp;
+  std::vector<cd> hh;
   std::vector<int> jc;
   std::vector<char> active, done;
   int j = 0;
@@ -384,27 +498,34 @@ int arnoldi_step(uhm_krylov* K) {
   const int64_t n = K->n, vstride = n * r;
   hipStream_t s = K->s;
   ++K->iters;
-  K->hp.resize((size_t)(j + 1) * r);
-  for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(k_g_dots, dim3(W.nch, r), dim3(kGB), 0, s, W.V.p, vstride, j + 1, W.w.p, n, r, W.nch, W.part.p);
-    hipLaunchKernelGGL(k_g_reduce, dim3(nblk((int64_t)(j + 1) * r)), dim3(kGB), 0, s, W.part.p, W.nch,
-                       (int64_t)(j + 1) * r, W.hbuf.p);
-    hipLaunchKernelGGL(k_g_update, dim3(W.nch, r), dim3(kGB), 0, s, W.V.p, vstride, j + 1, W.hbuf.p, W.w.p, n, r, W.nch,
-                       W.nrm.p);
-    UHM_HIP(hipMemcpyAsync(K->hp.data(), W.hbuf.p, sizeof(cd) * K->hp.size(), hipMemcpyDeviceToHost, s));
-    UHM_HIP(hipStreamSynchronize(s));
-    for (size_t q = 0; q < K->hp.size(); ++q) {
-      if (pass == 0) {
-        K->hh[q] = K->hp[q];
-      } else {
-        K->hh[q].x += K->hp[q].x;
-        K->hh[q].y += K->hp[q].y;
-      }
-    }
-  }
-  hipLaunchKernelGGL(k_g_norm, dim3((r + 63) / 64), dim3(64), 0, s, W.nrm.p, W.nch, r, W.nrm_out.p);
-  UHM_HIP(hipMemcpyAsync(K->hn.data(), W.nrm_out.p, sizeof(double) * r, hipMemcpyDeviceToHost, s));
+  const int ns = W.nsub;
+  const dim3 gw((unsigned)((ns + kGB / 64 - 1) / (kGB / 64)), (unsigned)r);
+  const int64_t nq = (int64_t)(j + 1) * r, hoff = (int64_t)(m + 1) * r;
+  cd *h1 = W.hbuf.p, *h2 = W.hbuf.p + hoff, *tail = W.hbuf.p + 2 * hoff;
+  double *n0 = W.nrm.p, *n1 = n0 + (int64_t)r * ns, *n2 = n1 + (int64_t)r * ns;
+  // first classical Gram-Schmidt pass, all columns
+  hipLaunchKernelGGL(k_a_dots, gw, dim3(kGB), 0, s, W.V.p, vstride, j + 1, W.w.p, n, r, ns, nullptr, W.part.p, n0);
+  hipLaunchKernelGGL(k_a_reduce, dim3(nblk(nq)), dim3(kGB), 0, s, W.part.p, ns, nq, r, nullptr, h1);
+  hipLaunchKernelGGL(k_a_update, gw, dim3(kGB), 0, s, W.V.p, vstride, j + 1, h1, W.w.p, n, r, ns, nullptr, n1);
+  hipLaunchKernelGGL(k_a_decide, dim3((r + 63) / 64), dim3(64), 0, s, n0, n1, ns, r, W.need.p);
+  // second pass for the columns that need it
+  hipLaunchKernelGGL(k_a_dots, gw, dim3(kGB), 0, s, W.V.p, vstride, j + 1, W.w.p, n, r, ns, W.need.p, W.part.p,
+                     nullptr);
+  hipLaunchKernelGGL(k_a_reduce, dim3(nblk(nq)), dim3(kGB), 0, s, W.part.p, ns, nq, r, W.need.p, h2);
+  hipLaunchKernelGGL(k_a_update, gw, dim3(kGB), 0, s, W.V.p, vstride, j + 1, h2, W.w.p, n, r, ns, W.need.p, n2);
+  hipLaunchKernelGGL(k_a_final, dim3((r + 63) / 64), dim3(64), 0, s, n1, n2, W.need.p, ns, r, tail);
+  UHM_HIP(hipMemcpyAsync(W.hx.p, h1, sizeof(cd) * (size_t)nq, hipMemcpyDeviceToHost, s));
+  UHM_HIP(hipMemcpyAsync(W.hx.p + hoff, h2, sizeof(cd) * (size_t)nq, hipMemcpyDeviceToHost, s));
+  UHM_HIP(hipMemcpyAsync(W.hx.p + 2 * hoff, tail, sizeof(cd) * (size_t)r, hipMemcpyDeviceToHost, s));
   UHM_HIP(hipStreamSynchronize(s));
+  for (int64_t q = 0; q < nq; ++q) {
+    K->hh[q].x = W.hx.p[q].x + W.hx.p[hoff + q].x;
+    K->hh[q].y = W.hx.p[q].y + W.hx.p[hoff + q].y;
+  }
+  for (int c = 0; c < r; ++c) {
+    K->hn[c] = W.hx.p[2 * hoff + c].x;
+    W.reorth += W.hx.p[2 * hoff + c].y != 0.0;
+  }
   bool all_done = true;
   for (int c = 0; c < r; ++c) {
     K->sc[c] = 0.0;
@@ -620,6 +741,7 @@ int uhm_krylov_result(uhm_krylov* K, void* X, int64_t ldx, uhm_gmres_info* info)
     info->seconds_total = 0.0;
     info->seconds_products = 0.0;
     info->seconds_arnoldi = K->t_arn;
+    info->second_passes = K->W.reorth;
   }
   return conv == r ? UHM_OK : fail(UHM_ENOCONV, "iteration limit reached before the tolerance");
 }

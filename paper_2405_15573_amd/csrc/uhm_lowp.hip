@@ -42,21 +42,27 @@ constexpr int kLpWaves = 4;
 constexpr int kLpCoupK = 1024;      // coupling tile width in columns
 constexpr int kLpRmax = 64;         // right-hand sides per pass
 constexpr int32_t kZero = INT_MIN;  // gather-map entry for a zero (padding) column
-constexpr int kRS = kLpRmax + 4;    // LDS row stride of a vector operand (elements)
 
-// ---- LDS images of the B operand for one round of RZ k-rows and R <= 64 columns
-template <int RZ>
+// ---- LDS images of the B operand for one round of RZ k-rows and R = 16 NT columns, sized
+// for R so that passes with few right-hand sides leave room for more resident workgroups
+template <int RZ, int NT>
 struct LdsF32 {
-  cf z[RZ * kRS];
+  static constexpr int S = 16 * NT + 4;  // row stride (elements)
+  cf z[RZ * S];
 };
-template <int RZ>
+template <int RZ, int NT>
 struct LdsF64 {
-  cd z[RZ * kRS];
+  static constexpr int S = 16 * NT + 4;
+  cd z[RZ * S];
 };
-constexpr int kZT = 64 + 8;  // bf16 plane row stride (per column j)
+template <int RZ, int NT>
 struct LdsBf16 {
-  __bf16 re_hi[kLpRmax * kZT], re_lo[kLpRmax * kZT], im_hi[kLpRmax * kZT], im_lo[kLpRmax * kZT];
+  static constexpr int ZT = RZ + 8;  // plane row stride (per column j)
+  __bf16 re_hi[16 * NT * ZT], re_lo[16 * NT * ZT], im_hi[16 * NT * ZT], im_lo[16 * NT * ZT];
 };
+
+// k-rows per LDS round: the storage's base round rz, for R = 16 nt columns
+constexpr int round_rows(int rz, int nt) { return rz; }
 
 // ---- one lane's A chunk of a k-block: KPL complex values of its row
 struct ChunkF32 {
@@ -79,7 +85,8 @@ struct Tr<UHM_C64> {
   static constexpr int KB = 16, KPL = 4, CH = 2, RZ = 64;
   using V = cf;
   using ACC = v4f;
-  using LDS = LdsF32<RZ>;
+  template <int NT>
+  using LDS = LdsF32<round_rows(RZ, NT), NT>;
   using CHUNK = ChunkF32;
   __device__ static int row(int g, int v) { return 4 * g + v; }
 };
@@ -88,7 +95,8 @@ struct Tr<UHM_BF16PAIR> {
   static constexpr int KB = 32, KPL = 8, CH = 2, RZ = 64;
   using V = cf;
   using ACC = v4f;
-  using LDS = LdsBf16;
+  template <int NT>
+  using LDS = LdsBf16<round_rows(RZ, NT), NT>;
   using CHUNK = ChunkBf16;
   __device__ static int row(int g, int v) { return 4 * g + v; }
 };
@@ -97,7 +105,8 @@ struct Tr<UHM_C128_MULTI> {
   static constexpr int KB = 16, KPL = 4, CH = 4, RZ = 32;
   using V = cd;
   using ACC = v4d;
-  using LDS = LdsF64<RZ>;
+  template <int NT>
+  using LDS = LdsF64<round_rows(RZ, NT), NT>;
   using CHUNK = ChunkF64;
   __device__ static int row(int g, int v) { return g + 4 * v; }
 };
@@ -109,16 +118,20 @@ __device__ __forceinline__ cf vzero<cf>() { return make_float2(0.f, 0.f); }
 template <>
 __device__ __forceinline__ cd vzero<cd>() { return make_double2(0.0, 0.0); }
 
-template <int RZ>
-__device__ __forceinline__ void lds_put(LdsF32<RZ>& L, int k, int j, cf v) { L.z[k * kRS + j] = v; }
-template <int RZ>
-__device__ __forceinline__ void lds_put(LdsF64<RZ>& L, int k, int j, cd v) { L.z[k * kRS + j] = v; }
-__device__ __forceinline__ void lds_put(LdsBf16& L, int k, int j, cf v) {
+template <int ST, int NT>
+using LdsOf = typename Tr<ST>::template LDS<NT>;
+
+template <int RZ, int NT>
+__device__ __forceinline__ void lds_put(LdsF32<RZ, NT>& L, int k, int j, cf v) { L.z[k * L.S + j] = v; }
+template <int RZ, int NT>
+__device__ __forceinline__ void lds_put(LdsF64<RZ, NT>& L, int k, int j, cd v) { L.z[k * L.S + j] = v; }
+template <int RZ, int NT>
+__device__ __forceinline__ void lds_put(LdsBf16<RZ, NT>& L, int k, int j, cf v) {
   const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
-  L.re_hi[j * kZT + k] = rh;
-  L.re_lo[j * kZT + k] = (__bf16)(v.x - (float)rh);
-  L.im_hi[j * kZT + k] = ih;
-  L.im_lo[j * kZT + k] = (__bf16)(v.y - (float)ih);
+  L.re_hi[j * L.ZT + k] = rh;
+  L.re_lo[j * L.ZT + k] = (__bf16)(v.x - (float)rh);
+  L.im_hi[j * L.ZT + k] = ih;
+  L.im_lo[j * L.ZT + k] = (__bf16)(v.y - (float)ih);
 }
 
 __device__ __forceinline__ void load_chunk(const uint4* p, bool act, ChunkF32& c) {
@@ -155,7 +168,7 @@ __device__ __forceinline__ void load_chunk(const uint4* p, bool act, ChunkF64& c
 
 // acc_r/acc_i[nt] += A_chunk (16 rows x one k-block) * B (k-block rows kk0.. of the LDS round).
 template <int NT, int RZ>
-__device__ __forceinline__ void mma_block(const ChunkF32& a, const LdsF32<RZ>& L, int kk0, int g, int i, v4f* cr,
+__device__ __forceinline__ void mma_block(const ChunkF32& a, const LdsF32<RZ, NT>& L, int kk0, int g, int i, v4f* cr,
                                           v4f* ci) {
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -163,7 +176,7 @@ __device__ __forceinline__ void mma_block(const ChunkF32& a, const LdsF32<RZ>& L
     const float ar = a.re[t], ai = a.im[t], nai = -a.im[t];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const cf b = L.z[k * kRS + nt * 16 + i];
+      const cf b = L.z[k * L.S + nt * 16 + i];
       cr[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b.x, cr[nt], 0, 0, 0);
       cr[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai, b.y, cr[nt], 0, 0, 0);
       ci[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b.y, ci[nt], 0, 0, 0);
@@ -173,7 +186,7 @@ __device__ __forceinline__ void mma_block(const ChunkF32& a, const LdsF32<RZ>& L
 }
 
 template <int NT, int RZ>
-__device__ __forceinline__ void mma_block(const ChunkF64& a, const LdsF64<RZ>& L, int kk0, int g, int i, v4d* cr,
+__device__ __forceinline__ void mma_block(const ChunkF64& a, const LdsF64<RZ, NT>& L, int kk0, int g, int i, v4d* cr,
                                           v4d* ci) {
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -181,7 +194,7 @@ __device__ __forceinline__ void mma_block(const ChunkF64& a, const LdsF64<RZ>& L
     const double ar = a.re[t], ai = a.im[t], nai = -a.im[t];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const cd b = L.z[k * kRS + nt * 16 + i];
+      const cd b = L.z[k * L.S + nt * 16 + i];
       cr[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.x, cr[nt], 0, 0, 0);
       cr[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, b.y, cr[nt], 0, 0, 0);
       ci[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.y, ci[nt], 0, 0, 0);
@@ -191,7 +204,7 @@ __device__ __forceinline__ void mma_block(const ChunkF64& a, const LdsF64<RZ>& L
 }
 
 template <int NT, int RZ>
-__device__ __forceinline__ void mma_block(const ChunkBf16& a, const LdsBf16& L, int kk0, int g, int i, v4f* cr,
+__device__ __forceinline__ void mma_block(const ChunkBf16& a, const LdsBf16<RZ, NT>& L, int kk0, int g, int i, v4f* cr,
                                           v4f* ci) {
   uint4 neg = __builtin_bit_cast(uint4, a.im);
   neg.x ^= 0x80008000u;
@@ -201,7 +214,7 @@ __device__ __forceinline__ void mma_block(const ChunkBf16& a, const LdsBf16& L, 
   const v8bf nai = __builtin_bit_cast(v8bf, neg);
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
-    const int o = (nt * 16 + i) * kZT + kk0 + g * 8;
+    const int o = (nt * 16 + i) * L.ZT + kk0 + g * 8;
     const v8bf brh = *reinterpret_cast<const v8bf*>(&L.re_hi[o]);
     const v8bf brl = *reinterpret_cast<const v8bf*>(&L.re_lo[o]);
     const v8bf bih = *reinterpret_cast<const v8bf*>(&L.im_hi[o]);
@@ -294,8 +307,9 @@ __device__ __forceinline__ void scatter_body(int64_t q, const V* __restrict__ Yc
 template <int ST, int NT>
 struct Round {
   using T_ = Tr<ST>;
-  static constexpr int KBR = T_::RZ / T_::KB;                   // k-blocks per round
-  static constexpr int PQ = T_::RZ * 16 * NT / (64 * kLpWaves);  // B elements per thread
+  static constexpr int RZN = round_rows(T_::RZ, NT);
+  static constexpr int KBR = RZN / T_::KB;                    // k-blocks per round
+  static constexpr int PQ = RZN * 16 * NT / (64 * kLpWaves);  // B elements per thread
   typename T_::CHUNK a[KBR];
   typename T_::V v[PQ];
   int32_t id[PQ];
@@ -340,7 +354,7 @@ __device__ __forceinline__ void round_values(Round<ST, NT>& Q, int nk, Src src) 
   }
 }
 template <int ST, int NT>
-__device__ __forceinline__ void round_commit(typename Tr<ST>::LDS& L, const Round<ST, NT>& Q, int nk) {
+__device__ __forceinline__ void round_commit(LdsOf<ST, NT>& L, const Round<ST, NT>& Q, int nk) {
   constexpr int R = 16 * NT;
 #pragma unroll
   for (int u = 0; u < Round<ST, NT>::PQ; ++u) {
@@ -349,16 +363,16 @@ __device__ __forceinline__ void round_commit(typename Tr<ST>::LDS& L, const Roun
   }
 }
 template <int ST, int NT>
-__device__ __forceinline__ void round_mma(const Round<ST, NT>& Q, const typename Tr<ST>::LDS& L, int nkr, int g, int i,
+__device__ __forceinline__ void round_mma(const Round<ST, NT>& Q, const LdsOf<ST, NT>& L, int nkr, int g, int i,
                                           typename Tr<ST>::ACC* cr, typename Tr<ST>::ACC* ci) {
 #pragma unroll
   for (int b = 0; b < Round<ST, NT>::KBR; ++b)
-    if (b < nkr) mma_block<NT, Tr<ST>::RZ>(Q.a[b], L, b * Tr<ST>::KB, g, i, cr, ci);
+    if (b < nkr) mma_block<NT, Round<ST, NT>::RZN>(Q.a[b], L, b * Tr<ST>::KB, g, i, cr, ci);
 }
 
 // P_lambda = F_lambda^* X_lambda for one leaf.
 template <int ST, int NT>
-__device__ __forceinline__ void forward_body(typename Tr<ST>::LDS& L, int leaf, const uint4* __restrict__ F,
+__device__ __forceinline__ void forward_body(LdsOf<ST, NT>& L, int leaf, const uint4* __restrict__ F,
                                              const int64_t* __restrict__ f_off, const int32_t* __restrict__ f_M,
                                              const int32_t* __restrict__ f_nkb, const int32_t* __restrict__ leaf_pos,
                                              const int32_t* __restrict__ leaf_n, const int64_t* __restrict__ poff,
@@ -453,7 +467,7 @@ __device__ __forceinline__ void reduce_segments_body(int64_t q, const V* __restr
 
 // Partial u_tau of one coupling tile (wave w = m-tile w of the chunk).
 template <int ST, int NT>
-__device__ __forceinline__ void coupling_body(typename Tr<ST>::LDS& L, const LpCoupTile& T,
+__device__ __forceinline__ void coupling_body(LdsOf<ST, NT>& L, const LpCoupTile& T,
                                               const uint4* __restrict__ S, const int32_t* __restrict__ colsrc,
                                               const typename Tr<ST>::V* __restrict__ xh, int R,
                                               typename Tr<ST>::V* __restrict__ part) {
@@ -514,7 +528,7 @@ __device__ __forceinline__ void reduce_coupling_body(int64_t q, const V* __restr
 // Y_lambda = B_lambda Z_lambda for one leaf; Z gathered from yh (index >= 0), from the
 // cluster-ordered input (index = -1 - position) or zero (kZero).
 template <int ST, int NT>
-__device__ __forceinline__ void backward_body(typename Tr<ST>::LDS& L, int leaf, const uint4* __restrict__ B,
+__device__ __forceinline__ void backward_body(LdsOf<ST, NT>& L, int leaf, const uint4* __restrict__ B,
                                               const int64_t* __restrict__ b_off, const int32_t* __restrict__ b_nkb,
                                               const int64_t* __restrict__ zoff, const int32_t* __restrict__ zmap,
                                               const int32_t* __restrict__ leaf_pos, const int32_t* __restrict__ leaf_n,
@@ -573,7 +587,7 @@ __global__ __launch_bounds__(64 * kLpWaves) void k_lp_forward(
     const int32_t* __restrict__ f_nkb, const int32_t* __restrict__ leaf_pos, const int32_t* __restrict__ leaf_n,
     const int64_t* __restrict__ poff, const typename Tr<ST>::V* __restrict__ Xc, int R,
     typename Tr<ST>::V* __restrict__ p) {
-  __shared__ typename Tr<ST>::LDS L;
+  __shared__ LdsOf<ST, NT> L;
   forward_body<ST, NT>(L, blockIdx.x, F, f_off, f_M, f_nkb, leaf_pos, leaf_n, poff, Xc, R, p);
 }
 
@@ -595,7 +609,7 @@ __global__ __launch_bounds__(64 * kLpWaves) void k_lp_coupling(const uint4* __re
                                                                const int32_t* __restrict__ colsrc,
                                                                const typename Tr<ST>::V* __restrict__ xh, int R,
                                                                typename Tr<ST>::V* __restrict__ part) {
-  __shared__ typename Tr<ST>::LDS L;
+  __shared__ LdsOf<ST, NT> L;
   const LpCoupTile T = tiles[blockIdx.x];
   coupling_body<ST, NT>(L, T, S, colsrc, xh, R, part);
 }
@@ -616,7 +630,7 @@ __global__ __launch_bounds__(64 * kLpWaves) void k_lp_backward(
     const int64_t* __restrict__ zoff, const int32_t* __restrict__ zmap, const int32_t* __restrict__ leaf_pos,
     const int32_t* __restrict__ leaf_n, const typename Tr<ST>::V* __restrict__ yh,
     const typename Tr<ST>::V* __restrict__ Xc, int R, typename Tr<ST>::V* __restrict__ Yc) {
-  __shared__ typename Tr<ST>::LDS L;
+  __shared__ LdsOf<ST, NT> L;
   backward_body<ST, NT>(L, blockIdx.x, B, b_off, b_nkb, zoff, zmap, leaf_pos, leaf_n, yh, Xc, R, Yc);
 }
 
@@ -642,7 +656,7 @@ __global__ __launch_bounds__(256) void k_lpb_scatter(const LpDesc* __restrict__ 
 
 template <int ST, int NT>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lpb_forward(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
-  __shared__ typename Tr<ST>::LDS L;
+  __shared__ LdsOf<ST, NT> L;
   using V = typename Tr<ST>::V;
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];
@@ -660,7 +674,7 @@ __global__ __launch_bounds__(256) void k_lpb_reduce_segments(const LpDesc* __res
 
 template <int ST, int NT>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lpb_coupling(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
-  __shared__ typename Tr<ST>::LDS L;
+  __shared__ LdsOf<ST, NT> L;
   using V = typename Tr<ST>::V;
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];
@@ -678,7 +692,7 @@ __global__ __launch_bounds__(256) void k_lpb_reduce_coupling(const LpDesc* __res
 
 template <int ST, int NT>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lpb_backward(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
-  __shared__ typename Tr<ST>::LDS L;
+  __shared__ LdsOf<ST, NT> L;
   using V = typename Tr<ST>::V;
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];

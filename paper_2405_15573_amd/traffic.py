@@ -28,9 +28,11 @@ def kernel_source_sha256() -> str:
 
 
 def _short(name: str) -> str:
-    base = name.split("(")[0]
-    base = base.replace("(anonymous namespace)::", "")
-    return base
+    """'void (anonymous namespace)::k_backward<1>(double2 const*, ...)' -> 'k_backward<1>'."""
+    base = name.replace("(anonymous namespace)::", "").replace("uhm_detail::", "")
+    if base.startswith("void "):
+        base = base[5:]
+    return base.split("(")[0].strip()
 
 
 def per_kernel(path: str, counter: str) -> dict:

@@ -1,0 +1,37 @@
+"""Host logic of the HBM-traffic summary: kernel-name parsing and copy calibration."""
+import csv
+
+from paper_2405_15573_amd import traffic
+
+
+def _write(path, counter, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for i, (name, v) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Kernel_Name": name, "Counter_Name": counter, "Counter_Value": v})
+
+
+def test_short_names():
+    assert traffic._short("void (anonymous namespace)::k_backward<1>(HIP_vector_type<double, 2u> const*, int)") \
+        == "k_backward<1>"
+    assert traffic._short("void uhm_detail::(anonymous namespace)::k_coupling(double const*)") == "k_coupling"
+    assert traffic._short("__amd_rocclr_copyBuffer") == "__amd_rocclr_copyBuffer"
+
+
+def test_summary_scales_by_the_copy(tmp_path):
+    gib_kib = float(1 << 20)
+    # the counters read the 1 GiB copy as 0.5 GiB fetched and 2 GiB written: scales 2 and 1/2
+    fetch = [("__amd_rocclr_copyBuffer", gib_kib / 2), ("void (anonymous namespace)::k_coupling(int)", 1000.0),
+             ("void (anonymous namespace)::k_coupling(int)", 3000.0)]
+    write = [("__amd_rocclr_copyBuffer", 2 * gib_kib), ("void (anonymous namespace)::k_coupling(int)", 400.0),
+             ("void (anonymous namespace)::k_coupling(int)", 400.0)]
+    fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
+    _write(fp, "FETCH_SIZE", fetch)
+    _write(wp, "WRITE_SIZE", write)
+    s = traffic.summarize(str(fp), str(wp))
+    k = s["kernels"]["k_coupling"]
+    assert k["dispatches"] == 2
+    assert abs(k["fetch_bytes"] - 2000.0 * 1024 * 2) < 1e-6
+    assert abs(k["write_bytes"] - 400.0 * 1024 / 2) < 1e-6
+    assert "__amd_rocclr_copyBuffer" not in s["kernels"]
