@@ -65,6 +65,30 @@ def time_products(torch, dop, x, y, steps, warmup, stream):
     return (t1 - t0) / steps, {k: (v[0] / max(1, v[1]), v[1]) for k, v in kt.items() if v[1] > 0}
 
 
+def stream_context(torch):
+    """Rates plain torch kernels reach on this GPU: a 2 GiB device copy (read + write) and a
+    2 GiB sum (read).  Context for the roofline fraction, which stays against the 8 TB/s
+    peak."""
+    a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    out = {}
+    for name, fn, nbytes in (("copy", lambda: b.copy_(a), 2 * a.numel() * 8),
+                             ("sum", lambda: a.sum(), a.numel() * 8)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"torch_{name}_gbs"] = nbytes / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_gmres_cases(torch, binding, op, n, r, tol, maxit, stream, seed):
     """Plain FP64 GMRES(50) against GMRES-IR with complex64 and bf16-pair inner products."""
     import numpy as np
@@ -313,6 +337,9 @@ def main():
     ab = algorithmic_bytes(info, cloud.n)
     log(f"UH MVP {t_uh * 1e3:.3f} ms; kernels " + json.dumps({k: round(v[0], 4) for k, v in k_uh.items()}))
 
+    ctx = stream_context(torch)
+    log(f"plain torch kernels: {json.dumps(ctx)}")
+
     # sampled parity at full size against the oracle (block-wise definition, restricted rows)
     from oracle import uniform
     leaves = np.nonzero(np.bincount(op.parent[op.parent >= 0], minlength=op.nclusters) == 0)[0]
@@ -434,6 +461,7 @@ def main():
         "operator": {k: st[k] for k in ("nadm", "nden", "c_sp", "l_max", "k_max", "bytes_uh_c128", "bytes_h_c128")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "hbm_context": ctx,
         "precision_forms": lowp,
         "gmres": gm,
         "cpu_baseline": cpu,
