@@ -28,6 +28,7 @@
 #include <complex>
 #include <functional>
 #include <map>
+#include <type_traits>
 
 namespace uhm_detail {
 
@@ -75,6 +76,33 @@ struct ChunkF64 {
   v4d re, im;
 };
 
+// ---- accumulators of a wave's 16 x 16 NT output tile
+// Three-product form (complex64, complex128): p = sum ar br, q = sum ai bi,
+// s = sum (ar + ai)(br + bi); Re = p - q, Im = s - p - q (Gauss's trick: three real
+// products per complex multiply-add instead of four).
+template <class A, int NT>
+struct Acc3 {
+  A p[NT], q[NT], s[NT];
+  __device__ void zero() {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) p[nt] = q[nt] = s[nt] = A{0, 0, 0, 0};
+  }
+  __device__ auto re(int nt, int v) const { return p[nt][v] - q[nt][v]; }
+  __device__ auto im(int nt, int v) const { return s[nt][v] - p[nt][v] - q[nt][v]; }
+};
+// Four-product form (bf16 pairs, where ar + ai would be rounded to bf16 again, and
+// complex128 with many columns, where a third accumulator costs occupancy).
+template <class A, int NT>
+struct Acc2 {
+  A r[NT], i[NT];
+  __device__ void zero() {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) r[nt] = i[nt] = A{0, 0, 0, 0};
+  }
+  __device__ auto re(int nt, int v) const { return r[nt][v]; }
+  __device__ auto im(int nt, int v) const { return i[nt][v]; }
+};
+
 // Storage traits.  CH: 16-byte words per lane chunk; RZ: k-rows per LDS round;
 // V: vector element; ACC: accumulator register tile; rows of an accumulator register:
 // C64/BF16 lane (g, i) register v holds row 4g + v, C128 holds row g + 4v.
@@ -86,6 +114,8 @@ struct Tr<UHM_C64> {
   using V = cf;
   using ACC = v4f;
   template <int NT>
+  using ACCS = Acc3<v4f, NT>;
+  template <int NT>
   using LDS = LdsF32<round_rows(RZ, NT), NT>;
   using CHUNK = ChunkF32;
   __device__ static int row(int g, int v) { return 4 * g + v; }
@@ -96,6 +126,8 @@ struct Tr<UHM_BF16PAIR> {
   using V = cf;
   using ACC = v4f;
   template <int NT>
+  using ACCS = Acc2<v4f, NT>;
+  template <int NT>
   using LDS = LdsBf16<round_rows(RZ, NT), NT>;
   using CHUNK = ChunkBf16;
   __device__ static int row(int g, int v) { return 4 * g + v; }
@@ -105,6 +137,9 @@ struct Tr<UHM_C128_MULTI> {
   static constexpr int KB = 16, KPL = 4, CH = 4, RZ = 32;
   using V = cd;
   using ACC = v4d;
+  // three accumulators per column tile would leave one wave per SIMD at NT >= 3
+  template <int NT>
+  using ACCS = std::conditional_t<(NT <= 2), Acc3<v4d, NT>, Acc2<v4d, NT>>;
   template <int NT>
   using LDS = LdsF64<round_rows(RZ, NT), NT>;
   using CHUNK = ChunkF64;
@@ -166,28 +201,44 @@ __device__ __forceinline__ void load_chunk(const uint4* p, bool act, ChunkF64& c
   c.im = v4d{i0.x, i0.y, i1.x, i1.y};
 }
 
-// acc_r/acc_i[nt] += A_chunk (16 rows x one k-block) * B (k-block rows kk0.. of the LDS round).
+// acc += A_chunk (16 rows x one k-block) * B (k-block rows kk0.. of the LDS round).
 template <int NT, int RZ>
-__device__ __forceinline__ void mma_block(const ChunkF32& a, const LdsF32<RZ, NT>& L, int kk0, int g, int i, v4f* cr,
-                                          v4f* ci) {
+__device__ __forceinline__ void mma_block(const ChunkF32& a, const LdsF32<RZ, NT>& L, int kk0, int g, int i,
+                                          Acc3<v4f, NT>& c) {
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int k = kk0 + g * 4 + t;
-    const float ar = a.re[t], ai = a.im[t], nai = -a.im[t];
+    const float ar = a.re[t], ai = a.im[t], as = ar + ai;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const cf b = L.z[k * L.S + nt * 16 + i];
-      cr[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b.x, cr[nt], 0, 0, 0);
-      cr[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai, b.y, cr[nt], 0, 0, 0);
-      ci[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b.y, ci[nt], 0, 0, 0);
-      ci[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, b.x, ci[nt], 0, 0, 0);
+      c.p[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b.x, c.p[nt], 0, 0, 0);
+      c.q[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, b.y, c.q[nt], 0, 0, 0);
+      c.s[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, b.x + b.y, c.s[nt], 0, 0, 0);
     }
   }
 }
 
 template <int NT, int RZ>
-__device__ __forceinline__ void mma_block(const ChunkF64& a, const LdsF64<RZ, NT>& L, int kk0, int g, int i, v4d* cr,
-                                          v4d* ci) {
+__device__ __forceinline__ void mma_block(const ChunkF64& a, const LdsF64<RZ, NT>& L, int kk0, int g, int i,
+                                          Acc3<v4d, NT>& c) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int k = kk0 + g * 4 + t;
+    const double ar = a.re[t], ai = a.im[t], as = ar + ai;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const cd b = L.z[k * L.S + nt * 16 + i];
+      c.p[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.x, c.p[nt], 0, 0, 0);
+      c.q[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b.y, c.q[nt], 0, 0, 0);
+      c.s[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, b.x + b.y, c.s[nt], 0, 0, 0);
+    }
+  }
+}
+
+template <int NT, int RZ>
+__device__ __forceinline__ void mma_block(const ChunkF64& a, const LdsF64<RZ, NT>& L, int kk0, int g, int i,
+                                          Acc2<v4d, NT>& c) {
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int k = kk0 + g * 4 + t;
@@ -195,17 +246,17 @@ __device__ __forceinline__ void mma_block(const ChunkF64& a, const LdsF64<RZ, NT
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const cd b = L.z[k * L.S + nt * 16 + i];
-      cr[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.x, cr[nt], 0, 0, 0);
-      cr[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, b.y, cr[nt], 0, 0, 0);
-      ci[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.y, ci[nt], 0, 0, 0);
-      ci[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b.x, ci[nt], 0, 0, 0);
+      c.r[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.x, c.r[nt], 0, 0, 0);
+      c.r[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, b.y, c.r[nt], 0, 0, 0);
+      c.i[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.y, c.i[nt], 0, 0, 0);
+      c.i[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b.x, c.i[nt], 0, 0, 0);
     }
   }
 }
 
 template <int NT, int RZ>
-__device__ __forceinline__ void mma_block(const ChunkBf16& a, const LdsBf16<RZ, NT>& L, int kk0, int g, int i, v4f* cr,
-                                          v4f* ci) {
+__device__ __forceinline__ void mma_block(const ChunkBf16& a, const LdsBf16<RZ, NT>& L, int kk0, int g, int i,
+                                          Acc2<v4f, NT>& c) {
   uint4 neg = __builtin_bit_cast(uint4, a.im);
   neg.x ^= 0x80008000u;
   neg.y ^= 0x80008000u;
@@ -219,21 +270,21 @@ __device__ __forceinline__ void mma_block(const ChunkBf16& a, const LdsBf16<RZ, 
     const v8bf brl = *reinterpret_cast<const v8bf*>(&L.re_lo[o]);
     const v8bf bih = *reinterpret_cast<const v8bf*>(&L.im_hi[o]);
     const v8bf bil = *reinterpret_cast<const v8bf*>(&L.im_lo[o]);
-    cr[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.re, brh, cr[nt], 0, 0, 0);
-    cr[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.re, brl, cr[nt], 0, 0, 0);
-    cr[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nai, bih, cr[nt], 0, 0, 0);
-    cr[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nai, bil, cr[nt], 0, 0, 0);
-    ci[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.re, bih, ci[nt], 0, 0, 0);
-    ci[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.re, bil, ci[nt], 0, 0, 0);
-    ci[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.im, brh, ci[nt], 0, 0, 0);
-    ci[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.im, brl, ci[nt], 0, 0, 0);
+    c.r[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.re, brh, c.r[nt], 0, 0, 0);
+    c.r[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.re, brl, c.r[nt], 0, 0, 0);
+    c.r[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nai, bih, c.r[nt], 0, 0, 0);
+    c.r[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nai, bil, c.r[nt], 0, 0, 0);
+    c.i[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.re, bih, c.i[nt], 0, 0, 0);
+    c.i[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.re, bil, c.i[nt], 0, 0, 0);
+    c.i[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.im, brh, c.i[nt], 0, 0, 0);
+    c.i[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.im, brl, c.i[nt], 0, 0, 0);
   }
 }
 
 // Store the 16 x (16 NT) accumulator tile; register v of lane (g, i) holds row Tr::row(g, v).
 template <int ST, int NT>
 __device__ __forceinline__ void store_tile(typename Tr<ST>::V* out, int64_t row0, int hm, int R, int g, int i,
-                                           const typename Tr<ST>::ACC* cr, const typename Tr<ST>::ACC* ci) {
+                                           const typename Tr<ST>::template ACCS<NT>& c) {
   using V = typename Tr<ST>::V;
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt)
@@ -242,8 +293,8 @@ __device__ __forceinline__ void store_tile(typename Tr<ST>::V* out, int64_t row0
       const int r = Tr<ST>::row(g, v);
       if (r < hm) {
         V o;
-        o.x = cr[nt][v];
-        o.y = ci[nt][v];
+        o.x = c.re(nt, v);
+        o.y = c.im(nt, v);
         out[(row0 + r) * R + nt * 16 + i] = o;
       }
     }
@@ -364,10 +415,10 @@ __device__ __forceinline__ void round_commit(LdsOf<ST, NT>& L, const Round<ST, N
 }
 template <int ST, int NT>
 __device__ __forceinline__ void round_mma(const Round<ST, NT>& Q, const LdsOf<ST, NT>& L, int nkr, int g, int i,
-                                          typename Tr<ST>::ACC* cr, typename Tr<ST>::ACC* ci) {
+                                          typename Tr<ST>::template ACCS<NT>& c) {
 #pragma unroll
   for (int b = 0; b < Round<ST, NT>::KBR; ++b)
-    if (b < nkr) mma_block<NT, Round<ST, NT>::RZN>(Q.a[b], L, b * Tr<ST>::KB, g, i, cr, ci);
+    if (b < nkr) mma_block<NT, Round<ST, NT>::RZN>(Q.a[b], L, b * Tr<ST>::KB, g, i, c);
 }
 
 // P_lambda = F_lambda^* X_lambda for one leaf.
@@ -406,11 +457,10 @@ __device__ __forceinline__ void forward_body(LdsOf<ST, NT>& L, int leaf, const u
       const int hm = min(16, M - 16 * mt);
       const int mn = mt + kLpWaves < nmt ? mt + kLpWaves : mt;
       round_issue_a<ST, NT>(Qn, base + (int64_t)mn * nkb * T_::CH * 64, 0, nkb, min(16, M - 16 * mn), g, i);
-      typename T_::ACC cr[NT], ci[NT];
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = typename T_::ACC{0, 0, 0, 0};
-      round_mma<ST, NT>(Q, L, nkb, g, i, cr, ci);
-      store_tile<ST, NT>(p, poff[leaf] + 16 * mt, hm, R, g, i, cr, ci);
+      typename T_::template ACCS<NT> acc;
+      acc.zero();
+      round_mma<ST, NT>(Q, L, nkb, g, i, acc);
+      store_tile<ST, NT>(p, poff[leaf] + 16 * mt, hm, R, g, i, acc);
 #pragma unroll
       for (int b = 0; b < KBR; ++b) Q.a[b] = Qn.a[b];
     }
@@ -422,9 +472,8 @@ __device__ __forceinline__ void forward_body(LdsOf<ST, NT>& L, int leaf, const u
       const int ma = mt < nmt ? mt : 0;
       const int hm = min(16, M - 16 * ma);
       const uint4* tile = base + (int64_t)ma * nkb * T_::CH * 64;
-      typename T_::ACC cr[NT], ci[NT];
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = typename T_::ACC{0, 0, 0, 0};
+      typename T_::template ACCS<NT> acc;
+      acc.zero();
       for (int kb = 0; kb < nkb; kb += KBR) {
         const int nkr = min(KBR, nkb - kb), nk = nkr * T_::KB;
         round_indices<ST, NT>(Q, nk, row(kb * T_::KB));
@@ -433,9 +482,9 @@ __device__ __forceinline__ void forward_body(LdsOf<ST, NT>& L, int leaf, const u
         __syncthreads();
         round_commit<ST, NT>(L, Q, nk);
         __syncthreads();
-        if (mt < nmt) round_mma<ST, NT>(Q, L, nkr, g, i, cr, ci);
+        if (mt < nmt) round_mma<ST, NT>(Q, L, nkr, g, i, acc);
       }
-      if (mt < nmt) store_tile<ST, NT>(p, poff[leaf] + 16 * mt, hm, R, g, i, cr, ci);
+      if (mt < nmt) store_tile<ST, NT>(p, poff[leaf] + 16 * mt, hm, R, g, i, acc);
     }
   }
 }
@@ -475,9 +524,8 @@ __device__ __forceinline__ void coupling_body(LdsOf<ST, NT>& L, const LpCoupTile
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, i = lane & 15;
   const int nmt = (T.h + 15) >> 4;
   const int hm = min(16, T.h - 16 * w);
-  typename T_::ACC cr[NT], ci[NT];
-#pragma unroll
-  for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = typename T_::ACC{0, 0, 0, 0};
+  typename T_::template ACCS<NT> acc;
+  acc.zero();
   using Q_ = Round<ST, NT>;
   constexpr int KBR = Q_::KBR;
   // waves without an m-tile re-read m-tile 0 and skip the MFMAs
@@ -498,9 +546,9 @@ __device__ __forceinline__ void coupling_body(LdsOf<ST, NT>& L, const LpCoupTile
     __syncthreads();
     round_commit<ST, NT>(L, Q, nk);
     __syncthreads();
-    if (w < nmt) round_mma<ST, NT>(Q, L, nkr, g, i, cr, ci);
+    if (w < nmt) round_mma<ST, NT>(Q, L, nkr, g, i, acc);
   }
-  if (w < nmt) store_tile<ST, NT>(part, (int64_t)T.part * 64 + 16 * w, hm, R, g, i, cr, ci);
+  if (w < nmt) store_tile<ST, NT>(part, (int64_t)T.part * 64 + 16 * w, hm, R, g, i, acc);
 }
 
 template <class V>
@@ -541,9 +589,8 @@ __device__ __forceinline__ void backward_body(LdsOf<ST, NT>& L, int leaf, const 
   const int nmt = (n + 15) >> 4;
   const int hm = min(16, n - 16 * w);
   const int32_t* zm = zmap + zoff[leaf];
-  typename T_::ACC cr[NT], ci[NT];
-#pragma unroll
-  for (int nt = 0; nt < NT; ++nt) cr[nt] = ci[nt] = typename T_::ACC{0, 0, 0, 0};
+  typename T_::template ACCS<NT> acc;
+  acc.zero();
   using Q_ = Round<ST, NT>;
   constexpr int KBR = Q_::KBR;
   const int hma = w < nmt ? hm : min(16, n);
@@ -562,9 +609,9 @@ __device__ __forceinline__ void backward_body(LdsOf<ST, NT>& L, int leaf, const 
     __syncthreads();
     round_commit<ST, NT>(L, Q, nk);
     __syncthreads();
-    if (w < nmt) round_mma<ST, NT>(Q, L, nkr, g, i, cr, ci);
+    if (w < nmt) round_mma<ST, NT>(Q, L, nkr, g, i, acc);
   }
-  if (w < nmt) store_tile<ST, NT>(Yc, (int64_t)leaf_pos[leaf] + 16 * w, hm, R, g, i, cr, ci);
+  if (w < nmt) store_tile<ST, NT>(Yc, (int64_t)leaf_pos[leaf] + 16 * w, hm, R, g, i, acc);
 }
 
 // ---------------------------------------------------------------- single-operator kernels
