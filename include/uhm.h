@@ -271,10 +271,14 @@ void uhm_krylov_free(uhm_krylov* k);
  * One step of many solves at once (continuous batching): every solve with a pending
  * request gets its product, grouped by (operator, precision) into multi-column products of
  * up to 64 columns (complex64 conversion for the low-precision ones), then every solve
- * advances.  high[k] / low[k] are solve k's FP64 and low-precision operators (low may be
- * NULL when no solve is mixed).  The operators' staging buffers grow as needed.  A solve's
- * columns are products of its own Krylov vectors only, and each product column does not
- * depend on the others, so a solve's iterates are the same alone or in any mix.
+ * advances.  The Arnoldi steps of all solves run as one launch per kernel over all of
+ * them, followed by one synchronisation of `hip_stream`.  high[k] / low[k] are solve k's
+ * FP64 and low-precision operators (low may be NULL when no solve is mixed).  The
+ * operators' staging buffers grow as needed.  Products and Arnoldi kernels run on
+ * `hip_stream`; solves created on other streams are synchronised first.  Steps from
+ * several host threads are serialised on a process-wide lock around the Arnoldi launches.
+ * A solve's columns are products of its own Krylov vectors only, and every reduction is
+ * per column in a fixed order, so a solve's iterates are the same alone or in any mix.
  * Returns the number of solves still running, or a negative error code.
  */
 int uhm_krylov_step(uhm_krylov* const* ks, uhm_op* const* high, uhm_op* const* low, int32_t count, void* hip_stream);

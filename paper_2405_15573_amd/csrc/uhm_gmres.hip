@@ -20,7 +20,10 @@
 // reduces it by inner_tol, and x += d.
 #include "uhm_internal.h"
 
+#include <algorithm>
 #include <chrono>
+#include <cstring>
+#include <mutex>
 #include <cmath>
 #include <complex>
 #include <map>
@@ -63,11 +66,11 @@ constexpr int kAPer = kAWRows / 64;
 // part[(i r + c) nsub + sb] = sum over the rows of wave sb of conj(V_i[row, c]) w[row, c];
 // w2[c nsub + sb] = the same rows' sum of |w|^2 (when w2 is given).  Columns with
 // need[c] == 0 are skipped (when need is given).
-__global__ __launch_bounds__(kGB) void k_a_dots(const cd* __restrict__ V, int64_t vstride, int nvec,
-                                                const cd* __restrict__ w, int64_t n, int r, int nsub,
-                                                const int* __restrict__ need, cd* __restrict__ part,
-                                                double* __restrict__ w2) {
-  const int sb = blockIdx.x * (kGB / 64) + (threadIdx.x >> 6), c = blockIdx.y, lane = threadIdx.x & 63;
+__device__ __forceinline__ void a_dots_body(int sb, int c, const cd* __restrict__ V, int64_t vstride, int nvec,
+                                            const cd* __restrict__ w, int64_t n, int r, int nsub,
+                                            const int* __restrict__ need, cd* __restrict__ part,
+                                            double* __restrict__ w2) {
+  const int lane = threadIdx.x & 63;
   if (sb >= nsub || (need && !need[c])) return;
   const int64_t r0 = (int64_t)sb * kAWRows;
   const cd* wc = w + (int64_t)c * n;
@@ -127,10 +130,16 @@ __global__ __launch_bounds__(kGB) void k_a_dots(const cd* __restrict__ V, int64_
   }
 }
 
+__global__ __launch_bounds__(kGB) void k_a_dots(const cd* __restrict__ V, int64_t vstride, int nvec,
+                                                const cd* __restrict__ w, int64_t n, int r, int nsub,
+                                                const int* __restrict__ need, cd* __restrict__ part,
+                                                double* __restrict__ w2) {
+  a_dots_body(blockIdx.x * (kGB / 64) + (threadIdx.x >> 6), blockIdx.y, V, vstride, nvec, w, n, r, nsub, need, part, w2);
+}
+
 // out[q] = sum_sb part[q nsub + sb], q = i r + c; zero for columns with need[c] == 0.
-__global__ __launch_bounds__(kGB) void k_a_reduce(const cd* __restrict__ part, int nsub, int64_t nq, int r,
-                                                  const int* __restrict__ need, cd* __restrict__ out) {
-  const int64_t q = (int64_t)blockIdx.x * kGB + threadIdx.x;
+__device__ __forceinline__ void a_reduce_body(int64_t q, const cd* __restrict__ part, int nsub, int64_t nq, int r,
+                                              const int* __restrict__ need, cd* __restrict__ out) {
   if (q >= nq) return;
   double re = 0.0, im = 0.0;
   if (!need || need[q % r])
@@ -141,12 +150,16 @@ __global__ __launch_bounds__(kGB) void k_a_reduce(const cd* __restrict__ part, i
     }
   out[q] = make_double2(re, im);
 }
+__global__ __launch_bounds__(kGB) void k_a_reduce(const cd* __restrict__ part, int nsub, int64_t nq, int r,
+                                                  const int* __restrict__ need, cd* __restrict__ out) {
+  a_reduce_body((int64_t)blockIdx.x * kGB + threadIdx.x, part, nsub, nq, r, need, out);
+}
 
 // w[:, c] -= sum_i V_i[:, c] h[i r + c]; w2[c nsub + sb] = partial ||w_new||^2.
-__global__ __launch_bounds__(kGB) void k_a_update(const cd* __restrict__ V, int64_t vstride, int nvec,
-                                                  const cd* __restrict__ h, cd* __restrict__ w, int64_t n, int r,
-                                                  int nsub, const int* __restrict__ need, double* __restrict__ w2) {
-  const int sb = blockIdx.x * (kGB / 64) + (threadIdx.x >> 6), c = blockIdx.y, lane = threadIdx.x & 63;
+__device__ __forceinline__ void a_update_body(int sb, int c, const cd* __restrict__ V, int64_t vstride, int nvec,
+                                              const cd* __restrict__ h, cd* __restrict__ w, int64_t n, int r,
+                                              int nsub, const int* __restrict__ need, double* __restrict__ w2) {
+  const int lane = threadIdx.x & 63;
   if (sb >= nsub || (need && !need[c])) return;
   const int64_t r0 = (int64_t)sb * kAWRows;
   const int64_t lim = n - r0 - lane;
@@ -194,11 +207,15 @@ __global__ __launch_bounds__(kGB) void k_a_update(const cd* __restrict__ V, int6
   s2 = warp_sum(s2);
   if (lane == 0) w2[(int64_t)c * nsub + sb] = s2;
 }
+__global__ __launch_bounds__(kGB) void k_a_update(const cd* __restrict__ V, int64_t vstride, int nvec,
+                                                  const cd* __restrict__ h, cd* __restrict__ w, int64_t n, int r,
+                                                  int nsub, const int* __restrict__ need, double* __restrict__ w2) {
+  a_update_body(blockIdx.x * (kGB / 64) + (threadIdx.x >> 6), blockIdx.y, V, vstride, nvec, h, w, n, r, nsub, need, w2);
+}
 
 // need[c] = (||w after the projection||^2 < ||w before||^2 / 2)
-__global__ void k_a_decide(const double* __restrict__ w0, const double* __restrict__ w1, int nsub, int r,
-                           int* __restrict__ need) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void a_decide_body(int c, const double* __restrict__ w0, const double* __restrict__ w1,
+                                              int nsub, int r, int* __restrict__ need) {
   if (c >= r) return;
   double s0 = 0.0, s1 = 0.0;
   for (int sb = 0; sb < nsub; ++sb) {
@@ -207,16 +224,72 @@ __global__ void k_a_decide(const double* __restrict__ w0, const double* __restri
   }
   need[c] = s1 < 0.5 * s0;
 }
+__global__ void k_a_decide(const double* __restrict__ w0, const double* __restrict__ w1, int nsub, int r,
+                           int* __restrict__ need) {
+  a_decide_body(blockIdx.x * blockDim.x + threadIdx.x, w0, w1, nsub, r, need);
+}
 
 // out[c] = (||w||, need[c]) with ||w|| from the last pass the column ran
-__global__ void k_a_final(const double* __restrict__ w1, const double* __restrict__ w2, const int* __restrict__ need,
-                          int nsub, int r, cd* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void a_final_body(int c, const double* __restrict__ w1, const double* __restrict__ w2,
+                                             const int* __restrict__ need, int nsub, int r, cd* __restrict__ out) {
   if (c >= r) return;
   const double* src = need[c] ? w2 : w1;
   double s = 0.0;
   for (int sb = 0; sb < nsub; ++sb) s += src[(int64_t)c * nsub + sb];
   out[c] = make_double2(sqrt(s), (double)need[c]);
+}
+__global__ void k_a_final(const double* __restrict__ w1, const double* __restrict__ w2, const int* __restrict__ need,
+                          int nsub, int r, cd* __restrict__ out) {
+  a_final_body(blockIdx.x * blockDim.x + threadIdx.x, w1, w2, need, nsub, r, out);
+}
+
+// ---- the same Arnoldi step for many solves in one launch per kernel
+// One solve's buffers: h1 = hbuf, h2 = hbuf + hoff, tail = hbuf + 2 hoff; partial norms
+// n0 = nrm, n1 = nrm + r nsub, n2 = nrm + 2 r nsub.
+struct ArnDesc {
+  const cd* V;
+  cd *w, *part, *hbuf;
+  double* nrm;
+  int* need;
+  int64_t n, vstride, hoff;
+  int32_t r, nvec, nsub, pad;
+};
+
+// work item of the row kernels: (solve, column, block of kGB/64 row ranges)
+__global__ __launch_bounds__(kGB) void k_ab_dots(const ArnDesc* __restrict__ D, const int4* __restrict__ work, int pass) {
+  const int4 wk = work[blockIdx.x];
+  const ArnDesc& d = D[wk.x];
+  const int sb = wk.z * (kGB / 64) + (threadIdx.x >> 6);
+  a_dots_body(sb, wk.y, d.V, d.vstride, d.nvec, d.w, d.n, d.r, d.nsub, pass ? d.need : nullptr, d.part,
+              pass ? nullptr : d.nrm);
+}
+__global__ __launch_bounds__(kGB) void k_ab_update(const ArnDesc* __restrict__ D, const int4* __restrict__ work, int pass) {
+  const int4 wk = work[blockIdx.x];
+  const ArnDesc& d = D[wk.x];
+  const int sb = wk.z * (kGB / 64) + (threadIdx.x >> 6);
+  const int64_t rn = (int64_t)d.r * d.nsub;
+  a_update_body(sb, wk.y, d.V, d.vstride, d.nvec, d.hbuf + (pass ? d.hoff : 0), d.w, d.n, d.r, d.nsub,
+                pass ? d.need : nullptr, d.nrm + (pass ? 2 : 1) * rn);
+}
+// work item: (solve, block of kGB entries of h)
+__global__ __launch_bounds__(kGB) void k_ab_reduce(const ArnDesc* __restrict__ D, const int2* __restrict__ work, int pass) {
+  const int2 wk = work[blockIdx.x];
+  const ArnDesc& d = D[wk.x];
+  a_reduce_body((int64_t)wk.y * kGB + threadIdx.x, d.part, d.nsub, (int64_t)d.nvec * d.r, d.r, pass ? d.need : nullptr,
+                d.hbuf + (pass ? d.hoff : 0));
+}
+// work item: (solve, block of 64 columns)
+__global__ __launch_bounds__(64) void k_ab_decide(const ArnDesc* __restrict__ D, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const ArnDesc& d = D[wk.x];
+  const int64_t rn = (int64_t)d.r * d.nsub;
+  a_decide_body(wk.y * 64 + threadIdx.x, d.nrm, d.nrm + rn, d.nsub, d.r, d.need);
+}
+__global__ __launch_bounds__(64) void k_ab_final(const ArnDesc* __restrict__ D, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const ArnDesc& d = D[wk.x];
+  const int64_t rn = (int64_t)d.r * d.nsub;
+  a_final_body(wk.y * 64 + threadIdx.x, d.nrm + rn, d.nrm + 2 * rn, d.need, d.nsub, d.r, d.hbuf + 2 * d.hoff);
 }
 
 // nrm_out[c] = sqrt(sum_ch nrm[c * nch + ch])
@@ -236,6 +309,16 @@ __global__ __launch_bounds__(kGB) void k_g_scale(const cd* __restrict__ src, con
   const double s = scale[q / n];
   const cd v = src[q];
   dst[q] = make_double2(v.x * s, v.y * s);
+}
+
+// dst[:, c] = src[:, c] * scale[c].x
+__global__ __launch_bounds__(kGB) void k_g_scale2(const cd* __restrict__ src, const cd* __restrict__ scale, int64_t n,
+                                                  int r, cd* __restrict__ dst) {
+  const int64_t q = (int64_t)blockIdx.x * kGB + threadIdx.x;
+  if (q >= n * r) return;
+  const double sc = scale[q / n].x;
+  const cd v = src[q];
+  dst[q] = make_double2(v.x * sc, v.y * sc);
 }
 
 // x[:, c] += sum_i V_i[:, c] y[i * r + c]
@@ -360,7 +443,9 @@ struct Work {
   DevArray<double> nrm, nrm_out;
   DevArray<int> need;
   DevArray<cf> x32, y32;
-  PinnedHost hx;  // h of both passes and the final norms of one step
+  PinnedHost hx;   // h of both passes and the final norms of one step
+  PinnedHost scp;  // the step's scale factors 1 / ||w|| (in .x), copied to `scale`
+  DevArray<cd> scale;
   int64_t reorth = 0;  // columns that needed the second Gram-Schmidt pass
   double t_prod = 0.0, t_arn = 0.0;
 };
@@ -377,7 +462,7 @@ int alloc_work(Work& W, int64_t n, int r, int m, bool lowp) {
       (rc = W.d.alloc(n * r)) || (rc = W.part.alloc((int64_t)(m + 1) * r * std::max(W.nch, W.nsub))) ||
       (rc = W.hbuf.alloc(hsz)) || (rc = W.ybuf.alloc((int64_t)(m + 1) * r)) ||
       (rc = W.nrm.alloc(3 * (int64_t)r * std::max(W.nch, W.nsub))) || (rc = W.nrm_out.alloc(r)) ||
-      (rc = W.need.alloc(r)) || (rc = W.hx.alloc(hsz)))
+      (rc = W.need.alloc(r)) || (rc = W.hx.alloc(hsz)) || (rc = W.scp.alloc(r)) || (rc = W.scale.alloc(r)))
     return rc;
   if (lowp && ((rc = W.x32.alloc(n * r)) || (rc = W.y32.alloc(n * r)))) return rc;
   return UHM_OK;
@@ -491,13 +576,15 @@ int inner_start(uhm_krylov* K, const cd* rhs_src) {
   return cycle_start(K);
 }
 
-// One Arnoldi step after the product W.w = A V_j.
-int arnoldi_step(uhm_krylov* K) {
+// One Arnoldi step after the product W.w = A V_j, in two halves: arnoldi_issue enqueues
+// the orthogonalisation and the copies of h and the norms to pinned host memory;
+// arnoldi_finish runs after the stream has synchronised.  Many solves can issue their
+// halves first and share one synchronisation.
+int arnoldi_issue(uhm_krylov* K) {
   Work& W = K->W;
   const int r = K->r, m = K->o.restart, j = K->j;
   const int64_t n = K->n, vstride = n * r;
   hipStream_t s = K->s;
-  ++K->iters;
   const int ns = W.nsub;
   const dim3 gw((unsigned)((ns + kGB / 64 - 1) / (kGB / 64)), (unsigned)r);
   const int64_t nq = (int64_t)(j + 1) * r, hoff = (int64_t)(m + 1) * r;
@@ -517,7 +604,16 @@ int arnoldi_step(uhm_krylov* K) {
   UHM_HIP(hipMemcpyAsync(W.hx.p, h1, sizeof(cd) * (size_t)nq, hipMemcpyDeviceToHost, s));
   UHM_HIP(hipMemcpyAsync(W.hx.p + hoff, h2, sizeof(cd) * (size_t)nq, hipMemcpyDeviceToHost, s));
   UHM_HIP(hipMemcpyAsync(W.hx.p + 2 * hoff, tail, sizeof(cd) * (size_t)r, hipMemcpyDeviceToHost, s));
-  UHM_HIP(hipStreamSynchronize(s));
+  return UHM_OK;
+}
+
+int arnoldi_finish(uhm_krylov* K) {
+  Work& W = K->W;
+  const int r = K->r, m = K->o.restart, j = K->j;
+  const int64_t n = K->n, vstride = n * r;
+  const int64_t nq = (int64_t)(j + 1) * r, hoff = (int64_t)(m + 1) * r;
+  hipStream_t s = K->s;
+  ++K->iters;
   for (int64_t q = 0; q < nq; ++q) {
     K->hh[q].x = W.hx.p[q].x + W.hx.p[hoff + q].x;
     K->hh[q].y = W.hx.p[q].y + W.hx.p[hoff + q].y;
@@ -559,8 +655,9 @@ int arnoldi_step(uhm_krylov* K) {
     if (std::abs(gc[j + 1]) <= K->rtol[c] || K->hn[c] <= 1e-300) K->active[c] = 0;
     all_done = all_done && !K->active[c];
   }
-  UHM_HIP(hipMemcpyAsync(W.nrm_out.p, K->sc.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_g_scale, dim3(nblk(n * r)), dim3(kGB), 0, s, W.w.p, W.nrm_out.p, n, r,
+  for (int c = 0; c < r; ++c) W.scp.p[c] = make_double2(K->sc[c], 0.0);
+  UHM_HIP(hipMemcpyAsync(W.scale.p, W.scp.p, sizeof(cd) * r, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_g_scale2, dim3(nblk(n * r)), dim3(kGB), 0, s, W.w.p, W.scale.p, n, r,
                      W.V.p + (int64_t)(j + 1) * vstride);
   K->j = j + 1;
   if (!all_done && K->j < m && K->iters < K->o.max_iterations) {
@@ -593,6 +690,96 @@ int arnoldi_step(uhm_krylov* K) {
   K->req_in = W.d.p;
   K->req_out = W.w.p;
   return UHM_OK;
+}
+
+// Process-wide scratch of the batched Arnoldi launches: device descriptors and work lists,
+// staged through pinned host memory (grow-only, never released; one step at a time).
+struct StepScratch {
+  std::mutex mu;
+  unsigned char* dev = nullptr;
+  unsigned char* host = nullptr;
+  size_t cap = 0;
+};
+StepScratch& step_scratch() {
+  static StepScratch* ss = new StepScratch;
+  return *ss;
+}
+
+size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
+
+// arnoldi_issue for many solves: each kernel is launched once over the work of all of them
+// on stream s, then each solve's h and norms are copied to its pinned host buffer.  The
+// caller holds the scratch lock until s has synchronised.
+int arnoldi_issue_many(const std::vector<uhm_krylov*>& iter, hipStream_t s, StepScratch& ss) {
+  std::vector<ArnDesc> D;
+  std::vector<int4> wrow;
+  std::vector<int2> wred, wcol;
+  for (size_t k = 0; k < iter.size(); ++k) {
+    uhm_krylov* K = iter[k];
+    Work& W = K->W;
+    const int r = K->r, m = K->o.restart, j = K->j;
+    ArnDesc d{};
+    d.V = W.V.p;
+    d.w = W.w.p;
+    d.part = W.part.p;
+    d.hbuf = W.hbuf.p;
+    d.nrm = W.nrm.p;
+    d.need = W.need.p;
+    d.n = K->n;
+    d.vstride = K->n * r;
+    d.hoff = (int64_t)(m + 1) * r;
+    d.r = r;
+    d.nvec = j + 1;
+    d.nsub = W.nsub;
+    D.push_back(d);
+    const int ki = (int)k;
+    for (int c = 0; c < r; ++c)
+      for (int zb = 0; zb < (W.nsub + kGB / 64 - 1) / (kGB / 64); ++zb) wrow.push_back(make_int4(ki, c, zb, 0));
+    for (int64_t qb = 0; qb < ((int64_t)(j + 1) * r + kGB - 1) / kGB; ++qb) wred.push_back(make_int2(ki, (int)qb));
+    for (int cb = 0; cb < (r + 63) / 64; ++cb) wcol.push_back(make_int2(ki, cb));
+  }
+  const size_t o_d = 0, o_row = align16(sizeof(ArnDesc) * D.size()), o_red = o_row + align16(sizeof(int4) * wrow.size()),
+               o_col = o_red + align16(sizeof(int2) * wred.size()), tot = o_col + align16(sizeof(int2) * wcol.size());
+  if (tot > ss.cap) {
+    if (ss.dev) (void)hipFree(ss.dev);
+    if (ss.host) (void)hipHostFree(ss.host);
+    ss.dev = ss.host = nullptr;
+    ss.cap = 0;
+    const size_t cap = std::max(tot, 2 * ss.cap + (1 << 16));
+    UHM_HIP(hipMalloc(reinterpret_cast<void**>(&ss.dev), cap));
+    UHM_HIP(hipHostMalloc(reinterpret_cast<void**>(&ss.host), cap, hipHostMallocDefault));
+    ss.cap = cap;
+  }
+  std::memcpy(ss.host + o_d, D.data(), sizeof(ArnDesc) * D.size());
+  std::memcpy(ss.host + o_row, wrow.data(), sizeof(int4) * wrow.size());
+  std::memcpy(ss.host + o_red, wred.data(), sizeof(int2) * wred.size());
+  std::memcpy(ss.host + o_col, wcol.data(), sizeof(int2) * wcol.size());
+  UHM_HIP(hipMemcpyAsync(ss.dev, ss.host, tot, hipMemcpyHostToDevice, s));
+  const ArnDesc* dD = reinterpret_cast<const ArnDesc*>(ss.dev + o_d);
+  const int4* dRow = reinterpret_cast<const int4*>(ss.dev + o_row);
+  const int2* dRed = reinterpret_cast<const int2*>(ss.dev + o_red);
+  const int2* dCol = reinterpret_cast<const int2*>(ss.dev + o_col);
+  const unsigned nrow = (unsigned)wrow.size(), nred = (unsigned)wred.size(), ncol = (unsigned)wcol.size();
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_ab_dots, dim3(nrow), dim3(kGB), 0, s, dD, dRow, pass);
+    hipLaunchKernelGGL(k_ab_reduce, dim3(nred), dim3(kGB), 0, s, dD, dRed, pass);
+    hipLaunchKernelGGL(k_ab_update, dim3(nrow), dim3(kGB), 0, s, dD, dRow, pass);
+    if (pass == 0) hipLaunchKernelGGL(k_ab_decide, dim3(ncol), dim3(64), 0, s, dD, dCol);
+  }
+  hipLaunchKernelGGL(k_ab_final, dim3(ncol), dim3(64), 0, s, dD, dCol);
+  for (uhm_krylov* K : iter) {
+    Work& W = K->W;
+    const int64_t hsz = 2 * (int64_t)(K->o.restart + 1) * K->r + K->r;
+    UHM_HIP(hipMemcpyAsync(W.hx.p, W.hbuf.p, sizeof(cd) * (size_t)hsz, hipMemcpyDeviceToHost, s));
+  }
+  return UHM_OK;
+}
+
+int arnoldi_step(uhm_krylov* K) {
+  int rc = arnoldi_issue(K);
+  if (rc) return rc;
+  UHM_HIP(hipStreamSynchronize(K->s));
+  return arnoldi_finish(K);
 }
 
 int advance(uhm_krylov* K) {
@@ -773,6 +960,15 @@ int uhm_krylov_step(uhm_krylov* const* ks, uhm_op* const* high, uhm_op* const* l
     groups[{A, K->req}].push_back({k, K->req, static_cast<const cd*>(K->req_in), static_cast<cd*>(K->req_out)});
   }
   int rc;
+  // products run on s: work a solve queued earlier on its own stream must be complete
+  bool all_on_s = true;
+  std::vector<hipStream_t> other;
+  for (int32_t k = 0; k < count; ++k)
+    if (ks[k]->s != s) {
+      all_on_s = false;
+      if (std::find(other.begin(), other.end(), ks[k]->s) == other.end()) other.push_back(ks[k]->s);
+    }
+  for (hipStream_t o : other) UHM_HIP(hipStreamSynchronize(o));
   for (auto& gkv : groups) {
     uhm_op* A = gkv.first.first;
     const bool hi = gkv.first.second == UHM_KRYLOV_PRODUCT_HIGH;
@@ -819,13 +1015,33 @@ int uhm_krylov_step(uhm_krylov* const* ks, uhm_op* const* high, uhm_op* const* l
       a = b;
     }
   }
-  UHM_HIP(hipStreamSynchronize(s));
+  if (!all_on_s) UHM_HIP(hipStreamSynchronize(s));
+  // Arnoldi steps of all solves: one launch per kernel over all of them on s, one
+  // synchronisation, then the host halves.  Other phases advance one by one.
+  std::vector<uhm_krylov*> iter;
+  for (int32_t k = 0; k < count; ++k) {
+    uhm_krylov* K = ks[k];
+    if (K->req != UHM_KRYLOV_DONE && K->phase == uhm_krylov::ITER) iter.push_back(K);
+  }
+  if (!iter.empty()) {
+    StepScratch& ss = step_scratch();
+    std::lock_guard<std::mutex> lock(ss.mu);
+    const auto t0 = Clock::now();
+    if ((rc = arnoldi_issue_many(iter, s, ss))) return rc;
+    UHM_HIP(hipStreamSynchronize(s));
+    const double dt = std::chrono::duration<double>(Clock::now() - t0).count() / (double)iter.size();
+    for (uhm_krylov* K : iter) K->t_arn += dt;
+  }
+  for (uhm_krylov* K : iter) {
+    const auto t0 = Clock::now();
+    if ((rc = arnoldi_finish(K))) return K->status = rc;
+    K->t_arn += std::chrono::duration<double>(Clock::now() - t0).count();
+  }
   int running = 0;
   for (int32_t k = 0; k < count; ++k) {
     uhm_krylov* K = ks[k];
     if (K->req == UHM_KRYLOV_DONE) continue;
-    // each solve runs its own FP64 work on its own stream; the products above are complete
-    if ((rc = uhm_krylov_advance(K))) return rc;
+    if (std::find(iter.begin(), iter.end(), K) == iter.end() && (rc = uhm_krylov_advance(K))) return rc;
     running += K->req != UHM_KRYLOV_DONE;
   }
   return running;

@@ -57,7 +57,12 @@ struct DevArray {
   ~DevArray() {
     if (p) (void)hipFree(p);
   }
+  // (Re)allocates; the previous contents are released.
   int alloc(int64_t count) {
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+    }
     n = count;
     if (count == 0) return UHM_OK;
     hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)count);

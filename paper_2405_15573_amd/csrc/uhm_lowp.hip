@@ -41,6 +41,7 @@ using cf = float2;
 
 constexpr int kLpWaves = 4;
 constexpr int kLpCoupK = 1024;      // coupling tile width in columns
+constexpr int kFwdGroupRows = 256;  // rows of the largest forward panels
 constexpr int kLpRmax = 64;         // right-hand sides per pass
 constexpr int32_t kZero = INT_MIN;  // gather-map entry for a zero (padding) column
 
@@ -103,14 +104,15 @@ struct Acc2 {
   __device__ auto im(int nt, int v) const { return i[nt][v]; }
 };
 
-// Storage traits.  CH: 16-byte words per lane chunk; RZ: k-rows per LDS round;
+// Storage traits.  CH: 16-byte words per lane chunk; RZ: k-rows per LDS round; KP: k-rows
+// of one column that a thread stages together (one packed LDS store per plane);
 // V: vector element; ACC: accumulator register tile; rows of an accumulator register:
 // C64/BF16 lane (g, i) register v holds row 4g + v, C128 holds row g + 4v.
 template <int ST>
 struct Tr;
 template <>
 struct Tr<UHM_C64> {
-  static constexpr int KB = 16, KPL = 4, CH = 2, RZ = 64;
+  static constexpr int KB = 16, KPL = 4, CH = 2, RZ = 64, KP = 1;
   using V = cf;
   using ACC = v4f;
   template <int NT>
@@ -122,7 +124,7 @@ struct Tr<UHM_C64> {
 };
 template <>
 struct Tr<UHM_BF16PAIR> {
-  static constexpr int KB = 32, KPL = 8, CH = 2, RZ = 64;
+  static constexpr int KB = 32, KPL = 8, CH = 2, RZ = 64, KP = 4;
   using V = cf;
   using ACC = v4f;
   template <int NT>
@@ -134,7 +136,7 @@ struct Tr<UHM_BF16PAIR> {
 };
 template <>
 struct Tr<UHM_C128_MULTI> {
-  static constexpr int KB = 16, KPL = 4, CH = 4, RZ = 32;
+  static constexpr int KB = 16, KPL = 4, CH = 4, RZ = 32, KP = 1;
   using V = cd;
   using ACC = v4d;
   // three accumulators per column tile would leave one wave per SIMD at NT >= 3
@@ -167,6 +169,28 @@ __device__ __forceinline__ void lds_put(LdsBf16<RZ, NT>& L, int k, int j, cf v) 
   L.re_lo[j * L.ZT + k] = (__bf16)(v.x - (float)rh);
   L.im_hi[j * L.ZT + k] = ih;
   L.im_lo[j * L.ZT + k] = (__bf16)(v.y - (float)ih);
+}
+// Rows k0 .. k0 + 3 (k0 a multiple of 4) of column j: one 8-byte store per plane.
+template <int RZ, int NT>
+__device__ __forceinline__ void lds_put4(LdsBf16<RZ, NT>& L, int k0, int j, const cf* v) {
+  uint16_t rh[4], rl[4], ih[4], il[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const __bf16 a = (__bf16)v[t].x, c = (__bf16)v[t].y;
+    const __bf16 al = (__bf16)(v[t].x - (float)a), cl = (__bf16)(v[t].y - (float)c);
+    rh[t] = __builtin_bit_cast(uint16_t, a);
+    rl[t] = __builtin_bit_cast(uint16_t, al);
+    ih[t] = __builtin_bit_cast(uint16_t, c);
+    il[t] = __builtin_bit_cast(uint16_t, cl);
+  }
+  auto pack = [](const uint16_t* h) {
+    return make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+  };
+  const int o = j * L.ZT + k0;
+  *reinterpret_cast<uint2*>(&L.re_hi[o]) = pack(rh);
+  *reinterpret_cast<uint2*>(&L.re_lo[o]) = pack(rl);
+  *reinterpret_cast<uint2*>(&L.im_hi[o]) = pack(ih);
+  *reinterpret_cast<uint2*>(&L.im_lo[o]) = pack(il);
 }
 
 __device__ __forceinline__ void load_chunk(const uint4* p, bool act, ChunkF32& c) {
@@ -319,7 +343,7 @@ struct LpCoupTile {
 struct LpDesc {
   const uint4 *F, *S, *B;
   const int64_t *f_off, *poff, *b_off, *zoff, *seg_start, *grp_start;
-  const int32_t *f_M, *f_nkb, *b_nkb, *zmap, *colsrc, *out_seg, *seg_leaf0, *seg_nleaf, *seg_col;
+  const int32_t *f_M, *f_nkb, *f_pos, *f_n, *b_nkb, *zmap, *colsrc, *out_seg, *seg_pan0, *seg_npan, *seg_col;
   const int32_t *yh_grp, *grp_t0, *grp_nt, *leaf_pos, *leaf_n, *perm;
   const LpCoupTile* ctiles;
   void *Xc, *Yc, *p, *xh, *part, *yh;
@@ -361,6 +385,7 @@ struct Round {
   static constexpr int RZN = round_rows(T_::RZ, NT);
   static constexpr int KBR = RZN / T_::KB;                    // k-blocks per round
   static constexpr int PQ = RZN * 16 * NT / (64 * kLpWaves);  // B elements per thread
+  static_assert(PQ % T_::KP == 0, "slots come in whole groups of KP rows");
   typename T_::CHUNK a[KBR];
   typename T_::V v[PQ];
   int32_t id[PQ];
@@ -382,35 +407,56 @@ __device__ __forceinline__ void round_issue_a(Round<ST, NT>& Q, const uint4* til
   }
 }
 
-// Raw gather indices of the round's B elements; element q is (k, j) = (q / R, q % R),
-// R = 16 NT, and q >= nk R re-reads k = nk - 1.
+// Element (k, j) of the round that slot u of this thread stages: slots come in groups of
+// KP consecutive k of one column; group g of thread t is q = t + g 256 with
+// k = KP (q / R) + u % KP, j = q % R (R = 16 NT), so a wave's loads of one k are contiguous.
+template <int ST, int NT>
+__device__ __forceinline__ void slot_kj(int u, int& k, int& j) {
+  constexpr int R = 16 * NT, KP = Tr<ST>::KP;
+  const int q = threadIdx.x + (u / KP) * 64 * kLpWaves;
+  k = KP * (q / R) + u % KP;
+  j = q % R;
+}
+
+// Raw gather indices of the round's B elements; slots with k >= nk re-read k = nk - 1.
 template <int ST, int NT, class Idx>
 __device__ __forceinline__ void round_indices(Round<ST, NT>& Q, int nk, Idx idx) {
-  constexpr int R = 16 * NT;
 #pragma unroll
   for (int u = 0; u < Round<ST, NT>::PQ; ++u) {
-    const int q = threadIdx.x + u * 64 * kLpWaves;
-    Q.id[u] = idx(min(q / R, nk - 1));
+    int k, j;
+    slot_kj<ST, NT>(u, k, j);
+    Q.id[u] = idx(min(k, nk - 1));
   }
 }
 // B values: src(index, j, ok) returns the element's address when ok, else any valid address.
 template <int ST, int NT, class Src>
 __device__ __forceinline__ void round_values(Round<ST, NT>& Q, int nk, Src src) {
-  constexpr int R = 16 * NT;
 #pragma unroll
   for (int u = 0; u < Round<ST, NT>::PQ; ++u) {
-    const int q = threadIdx.x + u * 64 * kLpWaves;
-    Q.ok[u] = q < nk * R && Q.id[u] != kZero;
-    Q.v[u] = *src(Q.id[u], q % R, Q.ok[u]);
+    int k, j;
+    slot_kj<ST, NT>(u, k, j);
+    Q.ok[u] = k < nk && Q.id[u] != kZero;
+    Q.v[u] = *src(Q.id[u], j, Q.ok[u]);
   }
 }
 template <int ST, int NT>
 __device__ __forceinline__ void round_commit(LdsOf<ST, NT>& L, const Round<ST, NT>& Q, int nk) {
-  constexpr int R = 16 * NT;
+  using V = typename Tr<ST>::V;
+  constexpr int KP = Tr<ST>::KP;
 #pragma unroll
-  for (int u = 0; u < Round<ST, NT>::PQ; ++u) {
-    const int q = threadIdx.x + u * 64 * kLpWaves;
-    if (q < nk * R) lds_put(L, q / R, q % R, Q.ok[u] ? Q.v[u] : vzero<typename Tr<ST>::V>());
+  for (int u = 0; u < Round<ST, NT>::PQ; u += KP) {
+    int k, j;
+    slot_kj<ST, NT>(u, k, j);  // k is a multiple of KP and nk of KB, so the group is whole
+    if (k < nk) {
+      if constexpr (KP == 1) {
+        lds_put(L, k, j, Q.ok[u] ? Q.v[u] : vzero<V>());
+      } else {
+        V w[KP];
+#pragma unroll
+        for (int t = 0; t < KP; ++t) w[t] = Q.ok[u + t] ? Q.v[u + t] : vzero<V>();
+        lds_put4(L, k, j, w);
+      }
+    }
   }
 }
 template <int ST, int NT>
@@ -421,23 +467,23 @@ __device__ __forceinline__ void round_mma(const Round<ST, NT>& Q, const LdsOf<ST
     if (b < nkr) mma_block<NT, Round<ST, NT>::RZN>(Q.a[b], L, b * Tr<ST>::KB, g, i, c);
 }
 
-// P_lambda = F_lambda^* X_lambda for one leaf.
+// P = F^* X for one forward panel (rows pan_pos .. pan_pos + pan_n - 1 of the cluster order).
 template <int ST, int NT>
-__device__ __forceinline__ void forward_body(LdsOf<ST, NT>& L, int leaf, const uint4* __restrict__ F,
+__device__ __forceinline__ void forward_body(LdsOf<ST, NT>& L, int pan, const uint4* __restrict__ F,
                                              const int64_t* __restrict__ f_off, const int32_t* __restrict__ f_M,
-                                             const int32_t* __restrict__ f_nkb, const int32_t* __restrict__ leaf_pos,
-                                             const int32_t* __restrict__ leaf_n, const int64_t* __restrict__ poff,
+                                             const int32_t* __restrict__ f_nkb, const int32_t* __restrict__ pan_pos,
+                                             const int32_t* __restrict__ pan_n, const int64_t* __restrict__ poff,
                                              const typename Tr<ST>::V* __restrict__ Xc, int R,
                                              typename Tr<ST>::V* __restrict__ p) {
   using T_ = Tr<ST>;
   using Q_ = Round<ST, NT>;
-  const int M = f_M[leaf];
+  const int M = f_M[pan];
   if (M == 0) return;
-  const int n = leaf_n[leaf], nkb = f_nkb[leaf];
+  const int n = pan_n[pan], nkb = f_nkb[pan];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, i = lane & 15;
-  const uint4* base = F + f_off[leaf];
+  const uint4* base = F + f_off[pan];
   const int nmt = (M + 15) >> 4;
-  const typename T_::V* xl = Xc + (int64_t)leaf_pos[leaf] * R;
+  const typename T_::V* xl = Xc + (int64_t)pan_pos[pan] * R;
   constexpr int KBR = Q_::KBR;
   // rows k < n of the leaf; padding rows read row 0 and are masked
   auto src = [&](int32_t k, int j, bool ok) { return xl + (ok ? (int64_t)k * R + j : 0); };
@@ -460,7 +506,7 @@ __device__ __forceinline__ void forward_body(LdsOf<ST, NT>& L, int leaf, const u
       typename T_::template ACCS<NT> acc;
       acc.zero();
       round_mma<ST, NT>(Q, L, nkb, g, i, acc);
-      store_tile<ST, NT>(p, poff[leaf] + 16 * mt, hm, R, g, i, acc);
+      store_tile<ST, NT>(p, poff[pan] + 16 * mt, hm, R, g, i, acc);
 #pragma unroll
       for (int b = 0; b < KBR; ++b) Q.a[b] = Qn.a[b];
     }
@@ -484,19 +530,19 @@ __device__ __forceinline__ void forward_body(LdsOf<ST, NT>& L, int leaf, const u
         __syncthreads();
         if (mt < nmt) round_mma<ST, NT>(Q, L, nkr, g, i, acc);
       }
-      if (mt < nmt) store_tile<ST, NT>(p, poff[leaf] + 16 * mt, hm, R, g, i, acc);
+      if (mt < nmt) store_tile<ST, NT>(p, poff[pan] + 16 * mt, hm, R, g, i, acc);
     }
   }
 }
 
-// xh[e][j] = sum over the leaves of the segment of p[poff[leaf] + col + e - start][j].
+// xh[e][j] = sum over the panels of the segment of p[poff[panel] + col + e - start][j].
 template <class V>
 __device__ __forceinline__ void reduce_segments_body(int64_t q, const V* __restrict__ p, int R,
                                                      const int64_t* __restrict__ poff,
                                                      const int32_t* __restrict__ out_seg,
                                                      const int64_t* __restrict__ seg_start,
-                                                     const int32_t* __restrict__ seg_leaf0,
-                                                     const int32_t* __restrict__ seg_nleaf,
+                                                     const int32_t* __restrict__ seg_pan0,
+                                                     const int32_t* __restrict__ seg_npan,
                                                      const int32_t* __restrict__ seg_col, int64_t nout,
                                                      V* __restrict__ xh) {
   if (q >= nout * R) return;
@@ -504,7 +550,7 @@ __device__ __forceinline__ void reduce_segments_body(int64_t q, const V* __restr
   const int j = (int)(q - e * R);
   const int s = out_seg[e];
   const int col = seg_col[s] + (int)(e - seg_start[s]);
-  const int l0 = seg_leaf0[s], nl = seg_nleaf[s];
+  const int l0 = seg_pan0[s], nl = seg_npan[s];
   V acc = vzero<V>();
   for (int qq = 0; qq < nl; ++qq) {
     const V v = p[(poff[l0 + qq] + col) * R + j];
@@ -631,22 +677,22 @@ __global__ __launch_bounds__(256) void k_lp_scatter(const V* __restrict__ Yc, in
 template <int ST, int NT>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lp_forward(
     const uint4* __restrict__ F, const int64_t* __restrict__ f_off, const int32_t* __restrict__ f_M,
-    const int32_t* __restrict__ f_nkb, const int32_t* __restrict__ leaf_pos, const int32_t* __restrict__ leaf_n,
+    const int32_t* __restrict__ f_nkb, const int32_t* __restrict__ f_pos, const int32_t* __restrict__ f_n,
     const int64_t* __restrict__ poff, const typename Tr<ST>::V* __restrict__ Xc, int R,
     typename Tr<ST>::V* __restrict__ p) {
   __shared__ LdsOf<ST, NT> L;
-  forward_body<ST, NT>(L, blockIdx.x, F, f_off, f_M, f_nkb, leaf_pos, leaf_n, poff, Xc, R, p);
+  forward_body<ST, NT>(L, blockIdx.x, F, f_off, f_M, f_nkb, f_pos, f_n, poff, Xc, R, p);
 }
 
 template <class V>
 __global__ __launch_bounds__(256) void k_lp_reduce_segments(const V* __restrict__ p, int R, const int64_t* __restrict__ poff,
                                                             const int32_t* __restrict__ out_seg,
                                                             const int64_t* __restrict__ seg_start,
-                                                            const int32_t* __restrict__ seg_leaf0,
-                                                            const int32_t* __restrict__ seg_nleaf,
+                                                            const int32_t* __restrict__ seg_pan0,
+                                                            const int32_t* __restrict__ seg_npan,
                                                             const int32_t* __restrict__ seg_col, int64_t nout,
                                                             V* __restrict__ xh) {
-  reduce_segments_body<V>((int64_t)blockIdx.x * 256 + threadIdx.x, p, R, poff, out_seg, seg_start, seg_leaf0, seg_nleaf,
+  reduce_segments_body<V>((int64_t)blockIdx.x * 256 + threadIdx.x, p, R, poff, out_seg, seg_start, seg_pan0, seg_npan,
                           seg_col, nout, xh);
 }
 
@@ -707,7 +753,7 @@ __global__ __launch_bounds__(64 * kLpWaves) void k_lpb_forward(const LpDesc* __r
   using V = typename Tr<ST>::V;
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];
-  forward_body<ST, NT>(L, wk.y, d.F, d.f_off, d.f_M, d.f_nkb, d.leaf_pos, d.leaf_n, d.poff,
+  forward_body<ST, NT>(L, wk.y, d.F, d.f_off, d.f_M, d.f_nkb, d.f_pos, d.f_n, d.poff,
                        static_cast<const V*>(d.Xc), d.R, static_cast<V*>(d.p));
 }
 
@@ -716,7 +762,7 @@ __global__ __launch_bounds__(256) void k_lpb_reduce_segments(const LpDesc* __res
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];
   reduce_segments_body<V>((int64_t)wk.y * 256 + threadIdx.x, static_cast<const V*>(d.p), d.R, d.poff, d.out_seg,
-                          d.seg_start, d.seg_leaf0, d.seg_nleaf, d.seg_col, d.nxh, static_cast<V*>(d.xh));
+                          d.seg_start, d.seg_pan0, d.seg_npan, d.seg_col, d.nxh, static_cast<V*>(d.xh));
 }
 
 template <int ST, int NT>
@@ -756,7 +802,9 @@ struct LowpOp {
   int KB = 16;
   DevArray<uint4> F, S, B;
   DevArray<int64_t> f_off, poff, b_off, zoff, seg_start, grp_start;
-  DevArray<int32_t> f_M, f_nkb, b_nkb, zmap, colsrc, out_seg, seg_leaf0, seg_nleaf, seg_col, yh_grp, grp_t0, grp_nt;
+  DevArray<int32_t> f_M, f_nkb, f_pos, f_n, b_nkb, zmap, colsrc, out_seg, seg_pan0, seg_npan, seg_col, yh_grp, grp_t0,
+      grp_nt;
+  int32_t npan = 0;  // forward panels
   DevArray<LpCoupTile> ctiles;
   int64_t p_rows = 0, nxh = 0, nyh = 0;
   int32_t nctiles = 0;
@@ -836,11 +884,6 @@ using C = std::complex<double>;
 
 inline C cget(const double* a, int64_t idx) { return C(a[2 * idx], a[2 * idx + 1]); }
 
-struct SegLp {
-  int64_t start;
-  int32_t len, leaf0, nleaf, col;
-};
-
 template <int ST>
 int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, uhm_op* op, LowpOp* lp) {
   constexpr int KB = Tr<ST>::KB;
@@ -855,38 +898,73 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
   }
   if (nxh > INT32_MAX / kLpRmax || nyh > INT32_MAX / kLpRmax) return fail(UHM_ENOTSUP, "rank space too large");
 
-  // ---- forward panels: A = F_lambda^* (C_lambda x roundup(n_lambda, KB))
-  std::vector<int64_t> f_off(nl), poff(nl);
-  std::vector<int32_t> f_M(nl), f_nkb(nl), seg_col_of(nc, -1);
-  int64_t ftot = 0, prow = 0;
+  // ---- forward panels.  Groups are the largest clusters of at most kFwdGroupRows rows;
+  // they partition the index set.  The panel of a group g holds its rows of V_sigma for
+  // every sigma containing g (root first); the panel of a leaf holds its rows of V_sigma for
+  // the sigma strictly inside its group.  x_sigma is the sum of sigma's segment over the
+  // panels that hold it, and the segment starts at the same column in each of them.  Group
+  // panels cut the per-panel partial sums of the upper levels by up to kFwdGroupRows / leaf.
+  std::vector<int32_t> gtop(nl);  // per leaf: index in anc of its group cluster
   for (int32_t i = 0; i < nl; ++i) {
+    const std::vector<int32_t>& A = T.anc[i];
+    int32_t q = (int32_t)A.size() - 1;
+    while (q > 0 && h->size[A[q - 1]] <= kFwdGroupRows) --q;
+    gtop[i] = q;
+  }
+  struct Pan {
+    int32_t cl, leaf, a0, a1;  // rows of cluster cl; columns of anc[leaf][a0 .. a1)
+  };
+  std::vector<Pan> pans;
+  for (int32_t i = 0; i < nl; ++i)  // group panels, in position order
+    if (i == 0 || T.anc[i][gtop[i]] != T.anc[i - 1][gtop[i - 1]]) pans.push_back({T.anc[i][gtop[i]], i, 0, gtop[i] + 1});
+  for (int32_t i = 0; i < nl; ++i)  // leaf panels: clusters strictly inside the group
+    pans.push_back({T.leaves[i], i, gtop[i] + 1, (int32_t)T.anc[i].size()});
+  std::vector<int64_t> f_off, poff;
+  std::vector<int32_t> f_M, f_nkb, f_pos, f_n, seg_col_of(nc, -1), seg_pan0(nc, -1), seg_npan(nc, 0);
+  int64_t ftot = 0, prow = 0;
+  std::vector<Pan> kept;
+  for (const Pan& P : pans) {
     int32_t Cn = 0;
-    for (int32_t a : T.anc[i])
-      if (h->rank_col[a] > 0) {
-        if (seg_col_of[a] < 0) seg_col_of[a] = Cn;
-        Cn += h->rank_col[a];
-      }
-    f_M[i] = Cn;
-    f_nkb[i] = (int32_t)((h->size[T.leaves[i]] + KB - 1) / KB);
-    f_off[i] = ftot;
-    poff[i] = prow;
-    ftot += panel_chunks<ST>(Cn, f_nkb[i]);
+    for (int32_t q = P.a0; q < P.a1; ++q) Cn += std::max(0, h->rank_col[T.anc[P.leaf][q]]);
+    if (Cn == 0) continue;
+    const int32_t pi = (int32_t)kept.size();
+    Cn = 0;
+    for (int32_t q = P.a0; q < P.a1; ++q) {
+      const int32_t a = T.anc[P.leaf][q];
+      if (h->rank_col[a] <= 0) continue;
+      if (seg_col_of[a] < 0) seg_col_of[a] = Cn;
+      if (seg_col_of[a] != Cn) return fail(UHM_EINVAL, "layout: forward segment column differs between panels");
+      if (seg_pan0[a] < 0) seg_pan0[a] = pi;
+      if (seg_pan0[a] + seg_npan[a] != pi) return fail(UHM_EINVAL, "layout: forward panels of a cluster not contiguous");
+      ++seg_npan[a];
+      Cn += h->rank_col[a];
+    }
+    kept.push_back(P);
+    f_M.push_back(Cn);
+    f_n.push_back((int32_t)h->size[P.cl]);
+    f_pos.push_back((int32_t)h->off[P.cl]);
+    f_nkb.push_back((int32_t)((h->size[P.cl] + KB - 1) / KB));
+    f_off.push_back(ftot);
+    poff.push_back(prow);
+    ftot += panel_chunks<ST>(Cn, f_nkb.back());
     prow += Cn;
   }
+  const int32_t npan = (int32_t)kept.size();
   if ((rc = lp->F.alloc(ftot))) return rc;
   if (ftot > 0) {
     StagerT<uint4> st;
     if ((rc = st.init(lp->F.p, ftot, s))) return rc;
-    std::vector<const double*> colp;  // per panel column: start of the leaf's rows in that basis column
-    for (int32_t i = 0; i < nl && !st.err; ++i) {
-      const int32_t lf = T.leaves[i];
-      const int64_t n = h->size[lf];
+    std::vector<const double*> colp;  // per panel column: start of the panel's rows in that basis column
+    for (int32_t pi = 0; pi < npan && !st.err; ++pi) {
+      const Pan& P = kept[pi];
+      const int64_t n = h->size[P.cl];
       colp.clear();
-      for (int32_t a : T.anc[i])
-        if (h->rank_col[a] > 0)
-          for (int32_t j = 0; j < h->rank_col[a]; ++j)
-            colp.push_back(h->V + 2 * (h->V_off[a] + (int64_t)j * h->size[a] + (h->off[lf] - h->off[a])));
-      if ((rc = pack_panel<ST>(st, f_M[i], f_nkb[i], [&](int32_t m, int32_t k) -> C {
+      for (int32_t q = P.a0; q < P.a1; ++q) {
+        const int32_t a = T.anc[P.leaf][q];
+        for (int32_t j = 0; j < h->rank_col[a]; ++j)
+          colp.push_back(h->V + 2 * (h->V_off[a] + (int64_t)j * h->size[a] + (h->off[P.cl] - h->off[a])));
+      }
+      if ((rc = pack_panel<ST>(st, f_M[pi], f_nkb[pi], [&](int32_t m, int32_t k) -> C {
              return k < n ? std::conj(cget(colp[m], k)) : C(0.0, 0.0);
            })))
         return rc;
@@ -894,32 +972,31 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
     if ((rc = st.finish())) return rc;
   }
   if ((rc = lp->f_off.upload(f_off, s)) || (rc = lp->f_M.upload(f_M, s)) || (rc = lp->f_nkb.upload(f_nkb, s)) ||
-      (rc = lp->poff.upload(poff, s)))
+      (rc = lp->f_pos.upload(f_pos, s)) || (rc = lp->f_n.upload(f_n, s)) || (rc = lp->poff.upload(poff, s)))
     return rc;
+  lp->npan = npan;
   lp->f_M_h = f_M;
   lp->f_nkb_h = f_nkb;
   for (int32_t i = 0; i < nl; ++i) lp->leaf_n_h.push_back((int32_t)h->size[T.leaves[i]]);
   lp->p_rows = prow;
-  // segments of u_sigma: sums over the leaves of sigma
-  std::vector<SegLp> segs;
-  for (int32_t c = 0; c < nc; ++c)
-    if (h->rank_col[c] > 0) segs.push_back({xh_off[c], h->rank_col[c], T.leaf_first[c], T.leaf_cnt[c], seg_col_of[c]});
+  // segments of x_sigma: sums over the panels that hold sigma
   {
-    std::vector<int32_t> out_seg(nxh), l0(segs.size()), nlv(segs.size()), col(segs.size());
-    std::vector<int64_t> start(segs.size());
-    for (size_t k = 0; k < segs.size(); ++k) {
-      const SegLp& sg = segs[k];
-      if (sg.leaf0 < 0 || sg.nleaf < 1 || sg.leaf0 + sg.nleaf > nl) return fail(UHM_EINVAL, "layout: segment");
-      for (int32_t q = 0; q < sg.nleaf; ++q)
-        if (sg.col < 0 || sg.col + sg.len > f_M[sg.leaf0 + q]) return fail(UHM_EINVAL, "layout: segment column");
-      for (int32_t j = 0; j < sg.len; ++j) out_seg[sg.start + j] = (int32_t)k;
-      start[k] = sg.start;
-      l0[k] = sg.leaf0;
-      nlv[k] = sg.nleaf;
-      col[k] = sg.col;
+    std::vector<int32_t> out_seg(nxh), p0, np, col;
+    std::vector<int64_t> start;
+    for (int32_t c = 0; c < nc; ++c) {
+      if (h->rank_col[c] <= 0) continue;
+      if (seg_pan0[c] < 0 || seg_npan[c] < 1 || seg_pan0[c] + seg_npan[c] > npan) return fail(UHM_EINVAL, "layout: segment");
+      for (int32_t q = 0; q < seg_npan[c]; ++q)
+        if (seg_col_of[c] < 0 || seg_col_of[c] + h->rank_col[c] > f_M[seg_pan0[c] + q])
+          return fail(UHM_EINVAL, "layout: segment column");
+      for (int32_t j = 0; j < h->rank_col[c]; ++j) out_seg[xh_off[c] + j] = (int32_t)start.size();
+      start.push_back(xh_off[c]);
+      p0.push_back(seg_pan0[c]);
+      np.push_back(seg_npan[c]);
+      col.push_back(seg_col_of[c]);
     }
     if ((rc = lp->out_seg.upload(out_seg, s)) || (rc = lp->seg_start.upload(start, s)) ||
-        (rc = lp->seg_leaf0.upload(l0, s)) || (rc = lp->seg_nleaf.upload(nlv, s)) || (rc = lp->seg_col.upload(col, s)))
+        (rc = lp->seg_pan0.upload(p0, s)) || (rc = lp->seg_npan.upload(np, s)) || (rc = lp->seg_col.upload(col, s)))
       return rc;
   }
   lp->nxh = nxh;
@@ -1094,13 +1171,13 @@ void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, i
   if (lp->nxh > 0) {
     {
       ScopedTiming tm(op, s, K_LP_FORWARD);
-      hipLaunchKernelGGL((k_lp_forward<ST, NT>), dim3(nl), dim3(64 * kLpWaves), 0, s, lp->F.p, lp->f_off.p, lp->f_M.p,
-                         lp->f_nkb.p, op->leaf_pos.p, op->leaf_n.p, lp->poff.p, Xc, R, p);
+      hipLaunchKernelGGL((k_lp_forward<ST, NT>), dim3(lp->npan), dim3(64 * kLpWaves), 0, s, lp->F.p, lp->f_off.p, lp->f_M.p,
+                         lp->f_nkb.p, lp->f_pos.p, lp->f_n.p, lp->poff.p, Xc, R, p);
     }
     {
       ScopedTiming tm(op, s, K_LP_REDUCE_FWD);
       hipLaunchKernelGGL(k_lp_reduce_segments<V>, dim3((unsigned)((lp->nxh * R + 255) / 256)), dim3(256), 0, s, p, R,
-                         lp->poff.p, lp->out_seg.p, lp->seg_start.p, lp->seg_leaf0.p, lp->seg_nleaf.p, lp->seg_col.p,
+                         lp->poff.p, lp->out_seg.p, lp->seg_start.p, lp->seg_pan0.p, lp->seg_npan.p, lp->seg_col.p,
                          lp->nxh, xh);
     }
   }
@@ -1332,8 +1409,10 @@ int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
     d.zmap = lp->zmap.p;
     d.colsrc = lp->colsrc.p;
     d.out_seg = lp->out_seg.p;
-    d.seg_leaf0 = lp->seg_leaf0.p;
-    d.seg_nleaf = lp->seg_nleaf.p;
+    d.seg_pan0 = lp->seg_pan0.p;
+    d.seg_npan = lp->seg_npan.p;
+    d.f_pos = lp->f_pos.p;
+    d.f_n = lp->f_n.p;
     d.seg_col = lp->seg_col.p;
     d.yh_grp = lp->yh_grp.p;
     d.grp_t0 = bo.grp_t0.p;
@@ -1362,7 +1441,7 @@ int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
     for (int64_t b = 0; b < ceil_div(op->n * R, 256); ++b) wg.push_back(make_int2(ki, (int32_t)b));
     for (int64_t b = 0; b < ceil_div(op->n * bo.r, 256); ++b) wsc.push_back(make_int2(ki, (int32_t)b));
     if (lp->nxh > 0) {
-      for (int32_t l = 0; l < op->nleaves; ++l) {
+      for (int32_t l = 0; l < lp->npan; ++l) {
         wf.push_back(make_int2(ki, l));
         cf_.push_back((int64_t)lp->f_M_h[l] * lp->f_nkb_h[l]);
       }
