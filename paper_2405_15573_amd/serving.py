@@ -164,6 +164,7 @@ class Server:
         if not len(fin):
             return {"completed": 0}
         span = max(q.finish for q in fin) - min(q.arrival for q in reqs)
+        conv = np.array([q.finish - q.arrival for q in fin if q.code == 0])
         return {
             "completed": len(fin),
             "converged": int(sum(1 for q in fin if q.code == 0)),
@@ -174,6 +175,9 @@ class Server:
             "mean_wait_s": float(np.mean([q.start - q.arrival for q in fin])),
             "mean_iterations": float(np.mean([q.info.get("iterations", 0) for q in fin])),
             "max_rel_residual": float(max(q.info.get("rel_residual", 0.0) for q in fin)),
+            # the same latencies over the solves that reached their tolerance
+            "p50_converged_s": float(np.percentile(conv, 50)) if conv.size else None,
+            "p99_converged_s": float(np.percentile(conv, 99)) if conv.size else None,
         }
 
     def free(self):
