@@ -270,7 +270,8 @@ void uhm_krylov_free(uhm_krylov* k);
 /*
  * One step of many solves at once (continuous batching): every solve with a pending
  * request gets its product, grouped by (operator, precision) into multi-column products of
- * up to 64 columns (complex64 conversion for the low-precision ones), then every solve
+ * up to 64 columns that read and write the solves' vectors in place through column
+ * pointers (with complex64 conversion for the low-precision operators), then every solve
  * advances.  The Arnoldi steps of all solves run as one launch per kernel over all of
  * them, followed by one synchronisation of `hip_stream`.  high[k] / low[k] are solve k's
  * FP64 and low-precision operators (low may be NULL when no solve is mixed).  The

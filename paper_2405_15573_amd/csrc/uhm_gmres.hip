@@ -248,10 +248,11 @@ __global__ void k_a_final(const double* __restrict__ w1, const double* __restric
 // n0 = nrm, n1 = nrm + r nsub, n2 = nrm + 2 r nsub.
 struct ArnDesc {
   const cd* V;
-  cd *w, *part, *hbuf;
+  cd *w, *part, *hbuf, *vnext;  // vnext: V_{j+1}
   double* nrm;
   int* need;
-  int64_t n, vstride, hoff;
+  int64_t n, vstride, hoff, hsz;  // hsz: entries of hbuf copied back to the host
+  int64_t goff, soff;             // offsets of the solve's h in the gather area, of its scales
   int32_t r, nvec, nsub, pad;
 };
 
@@ -278,6 +279,26 @@ __global__ __launch_bounds__(kGB) void k_ab_reduce(const ArnDesc* __restrict__ D
   a_reduce_body((int64_t)wk.y * kGB + threadIdx.x, d.part, d.nsub, (int64_t)d.nvec * d.r, d.r, pass ? d.need : nullptr,
                 d.hbuf + (pass ? d.hoff : 0));
 }
+// gather[d.goff + e] = d.hbuf[e], e < d.hsz; work item: (solve, block of kGB entries)
+__global__ __launch_bounds__(kGB) void k_ab_gather(const ArnDesc* __restrict__ D, const int2* __restrict__ work,
+                                                   cd* __restrict__ gather) {
+  const int2 wk = work[blockIdx.x];
+  const ArnDesc& d = D[wk.x];
+  const int64_t e = (int64_t)wk.y * kGB + threadIdx.x;
+  if (e < d.hsz) gather[d.goff + e] = d.hbuf[e];
+}
+// d.vnext[:, c] = d.w[:, c] * scale[d.soff + c].x; work item: (solve, block of kGB elements)
+__global__ __launch_bounds__(kGB) void k_ab_scale(const ArnDesc* __restrict__ D, const int2* __restrict__ work,
+                                                  const cd* __restrict__ scale) {
+  const int2 wk = work[blockIdx.x];
+  const ArnDesc& d = D[wk.x];
+  const int64_t q = (int64_t)wk.y * kGB + threadIdx.x;
+  if (q >= d.n * d.r) return;
+  const double sc = scale[d.soff + q / d.n].x;
+  const cd v = d.w[q];
+  d.vnext[q] = make_double2(v.x * sc, v.y * sc);
+}
+
 // work item: (solve, block of 64 columns)
 __global__ __launch_bounds__(64) void k_ab_decide(const ArnDesc* __restrict__ D, const int2* __restrict__ work) {
   const int2 wk = work[blockIdx.x];
@@ -400,26 +421,6 @@ __global__ __launch_bounds__(kGB) void k_g_add(const cd* __restrict__ d, int64_t
 }
 
 unsigned nblk(int64_t q) { return (unsigned)((q + kGB - 1) / kGB); }
-
-// dst (ldd) columns [0, r) <- src (lds) columns, converting complex128 -> complex64
-__global__ __launch_bounds__(kGB) void k_g_pack32(const cd* __restrict__ src, int64_t lds, int64_t n, int r,
-                                                  cf* __restrict__ dst, int64_t ldd) {
-  const int64_t q = (int64_t)blockIdx.x * kGB + threadIdx.x;
-  if (q >= n * r) return;
-  const int c = (int)(q / n);
-  const int64_t row = q - (int64_t)c * n;
-  const cd v = src[(int64_t)c * lds + row];
-  dst[(int64_t)c * ldd + row] = make_float2((float)v.x, (float)v.y);
-}
-__global__ __launch_bounds__(kGB) void k_g_unpack32(const cf* __restrict__ src, int64_t lds, int64_t n, int r,
-                                                    cd* __restrict__ dst, int64_t ldd) {
-  const int64_t q = (int64_t)blockIdx.x * kGB + threadIdx.x;
-  if (q >= n * r) return;
-  const int c = (int)(q / n);
-  const int64_t row = q - (int64_t)c * n;
-  const cf v = src[(int64_t)c * lds + row];
-  dst[(int64_t)c * ldd + row] = make_double2((double)v.x, (double)v.y);
-}
 
 using C = std::complex<double>;
 using Clock = std::chrono::steady_clock;
@@ -607,20 +608,21 @@ int arnoldi_issue(uhm_krylov* K) {
   return UHM_OK;
 }
 
-int arnoldi_finish(uhm_krylov* K) {
+// Host half of an Arnoldi step: h and the norms (at hx: h1, h2 at hx + hoff, norms at
+// hx + 2 hoff) update the Hessenberg matrices, the Givens rotations and K->sc = 1/||w||.
+// Returns whether every column has stopped.
+bool arnoldi_host(uhm_krylov* K, const cd* hx) {
   Work& W = K->W;
   const int r = K->r, m = K->o.restart, j = K->j;
-  const int64_t n = K->n, vstride = n * r;
   const int64_t nq = (int64_t)(j + 1) * r, hoff = (int64_t)(m + 1) * r;
-  hipStream_t s = K->s;
   ++K->iters;
   for (int64_t q = 0; q < nq; ++q) {
-    K->hh[q].x = W.hx.p[q].x + W.hx.p[hoff + q].x;
-    K->hh[q].y = W.hx.p[q].y + W.hx.p[hoff + q].y;
+    K->hh[q].x = hx[q].x + hx[hoff + q].x;
+    K->hh[q].y = hx[q].y + hx[hoff + q].y;
   }
   for (int c = 0; c < r; ++c) {
-    K->hn[c] = W.hx.p[2 * hoff + c].x;
-    W.reorth += W.hx.p[2 * hoff + c].y != 0.0;
+    K->hn[c] = hx[2 * hoff + c].x;
+    W.reorth += hx[2 * hoff + c].y != 0.0;
   }
   bool all_done = true;
   for (int c = 0; c < r; ++c) {
@@ -655,10 +657,15 @@ int arnoldi_finish(uhm_krylov* K) {
     if (std::abs(gc[j + 1]) <= K->rtol[c] || K->hn[c] <= 1e-300) K->active[c] = 0;
     all_done = all_done && !K->active[c];
   }
-  for (int c = 0; c < r; ++c) W.scp.p[c] = make_double2(K->sc[c], 0.0);
-  UHM_HIP(hipMemcpyAsync(W.scale.p, W.scp.p, sizeof(cd) * r, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_g_scale2, dim3(nblk(n * r)), dim3(kGB), 0, s, W.w.p, W.scale.p, n, r,
-                     W.V.p + (int64_t)(j + 1) * vstride);
+  return all_done;
+}
+
+// After V_{j+1} = w / ||w|| has been enqueued: the next request, or the end of the cycle.
+int arnoldi_next(uhm_krylov* K, bool all_done) {
+  Work& W = K->W;
+  const int r = K->r, m = K->o.restart, j = K->j;
+  const int64_t n = K->n, vstride = n * r;
+  hipStream_t s = K->s;
   K->j = j + 1;
   if (!all_done && K->j < m && K->iters < K->o.max_iterations) {
     K->req = K->mixed ? UHM_KRYLOV_PRODUCT_LOW : UHM_KRYLOV_PRODUCT_HIGH;
@@ -699,6 +706,12 @@ struct StepScratch {
   unsigned char* dev = nullptr;
   unsigned char* host = nullptr;
   size_t cap = 0;
+  // column pointers of the step's products; pev marks when their upload has been read
+  const cd** pdev = nullptr;
+  const cd** phost = nullptr;
+  size_t pcap = 0;
+  hipEvent_t pev = nullptr;
+  bool pev_recorded = false;
 };
 StepScratch& step_scratch() {
   static StepScratch* ss = new StepScratch;
@@ -707,13 +720,20 @@ StepScratch& step_scratch() {
 
 size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
+// Offsets of one batched step in the scratch buffers (bytes).
+struct ManyLayout {
+  size_t o_d, o_row, o_red, o_col, o_gw, o_sw, o_g, o_s, tot;
+  unsigned nrow, nred, ncol, ngw, nsw;
+};
+
 // arnoldi_issue for many solves: each kernel is launched once over the work of all of them
-// on stream s, then each solve's h and norms are copied to its pinned host buffer.  The
-// caller holds the scratch lock until s has synchronised.
-int arnoldi_issue_many(const std::vector<uhm_krylov*>& iter, hipStream_t s, StepScratch& ss) {
+// on stream s; the solves' h and norms are gathered into one area and copied to pinned
+// host memory in one transfer.  The caller holds the scratch lock until the step is done.
+int arnoldi_issue_many(const std::vector<uhm_krylov*>& iter, hipStream_t s, StepScratch& ss, ManyLayout& Lo) {
   std::vector<ArnDesc> D;
   std::vector<int4> wrow;
-  std::vector<int2> wred, wcol;
+  std::vector<int2> wred, wcol, wg, wsc;
+  int64_t goff = 0, soff = 0;
   for (size_t k = 0; k < iter.size(); ++k) {
     uhm_krylov* K = iter[k];
     Work& W = K->W;
@@ -723,11 +743,15 @@ int arnoldi_issue_many(const std::vector<uhm_krylov*>& iter, hipStream_t s, Step
     d.w = W.w.p;
     d.part = W.part.p;
     d.hbuf = W.hbuf.p;
+    d.vnext = W.V.p + (int64_t)(j + 1) * K->n * r;
     d.nrm = W.nrm.p;
     d.need = W.need.p;
     d.n = K->n;
     d.vstride = K->n * r;
     d.hoff = (int64_t)(m + 1) * r;
+    d.hsz = 2 * d.hoff + r;
+    d.goff = goff;
+    d.soff = soff;
     d.r = r;
     d.nvec = j + 1;
     d.nsub = W.nsub;
@@ -737,41 +761,82 @@ int arnoldi_issue_many(const std::vector<uhm_krylov*>& iter, hipStream_t s, Step
       for (int zb = 0; zb < (W.nsub + kGB / 64 - 1) / (kGB / 64); ++zb) wrow.push_back(make_int4(ki, c, zb, 0));
     for (int64_t qb = 0; qb < ((int64_t)(j + 1) * r + kGB - 1) / kGB; ++qb) wred.push_back(make_int2(ki, (int)qb));
     for (int cb = 0; cb < (r + 63) / 64; ++cb) wcol.push_back(make_int2(ki, cb));
+    for (int64_t gb = 0; gb < (d.hsz + kGB - 1) / kGB; ++gb) wg.push_back(make_int2(ki, (int)gb));
+    for (int64_t sb = 0; sb < (K->n * r + kGB - 1) / kGB; ++sb) wsc.push_back(make_int2(ki, (int)sb));
+    goff += d.hsz;
+    soff += r;
   }
-  const size_t o_d = 0, o_row = align16(sizeof(ArnDesc) * D.size()), o_red = o_row + align16(sizeof(int4) * wrow.size()),
-               o_col = o_red + align16(sizeof(int2) * wred.size()), tot = o_col + align16(sizeof(int2) * wcol.size());
-  if (tot > ss.cap) {
+  Lo.o_d = 0;
+  Lo.o_row = align16(sizeof(ArnDesc) * D.size());
+  Lo.o_red = Lo.o_row + align16(sizeof(int4) * wrow.size());
+  Lo.o_col = Lo.o_red + align16(sizeof(int2) * wred.size());
+  Lo.o_gw = Lo.o_col + align16(sizeof(int2) * wcol.size());
+  Lo.o_sw = Lo.o_gw + align16(sizeof(int2) * wg.size());
+  Lo.o_g = Lo.o_sw + align16(sizeof(int2) * wsc.size());  // gathered h, device -> host
+  Lo.o_s = Lo.o_g + align16(sizeof(cd) * (size_t)goff);     // scales, host -> device
+  Lo.tot = Lo.o_s + align16(sizeof(cd) * (size_t)soff);
+  Lo.nrow = (unsigned)wrow.size();
+  Lo.nred = (unsigned)wred.size();
+  Lo.ncol = (unsigned)wcol.size();
+  Lo.ngw = (unsigned)wg.size();
+  Lo.nsw = (unsigned)wsc.size();
+  if (Lo.tot > ss.cap) {
     if (ss.dev) (void)hipFree(ss.dev);
     if (ss.host) (void)hipHostFree(ss.host);
     ss.dev = ss.host = nullptr;
+    const size_t cap = std::max(Lo.tot, 2 * ss.cap + (1 << 16));
     ss.cap = 0;
-    const size_t cap = std::max(tot, 2 * ss.cap + (1 << 16));
     UHM_HIP(hipMalloc(reinterpret_cast<void**>(&ss.dev), cap));
     UHM_HIP(hipHostMalloc(reinterpret_cast<void**>(&ss.host), cap, hipHostMallocDefault));
     ss.cap = cap;
   }
-  std::memcpy(ss.host + o_d, D.data(), sizeof(ArnDesc) * D.size());
-  std::memcpy(ss.host + o_row, wrow.data(), sizeof(int4) * wrow.size());
-  std::memcpy(ss.host + o_red, wred.data(), sizeof(int2) * wred.size());
-  std::memcpy(ss.host + o_col, wcol.data(), sizeof(int2) * wcol.size());
-  UHM_HIP(hipMemcpyAsync(ss.dev, ss.host, tot, hipMemcpyHostToDevice, s));
-  const ArnDesc* dD = reinterpret_cast<const ArnDesc*>(ss.dev + o_d);
-  const int4* dRow = reinterpret_cast<const int4*>(ss.dev + o_row);
-  const int2* dRed = reinterpret_cast<const int2*>(ss.dev + o_red);
-  const int2* dCol = reinterpret_cast<const int2*>(ss.dev + o_col);
-  const unsigned nrow = (unsigned)wrow.size(), nred = (unsigned)wred.size(), ncol = (unsigned)wcol.size();
+  std::memcpy(ss.host + Lo.o_d, D.data(), sizeof(ArnDesc) * D.size());
+  std::memcpy(ss.host + Lo.o_row, wrow.data(), sizeof(int4) * wrow.size());
+  std::memcpy(ss.host + Lo.o_red, wred.data(), sizeof(int2) * wred.size());
+  std::memcpy(ss.host + Lo.o_col, wcol.data(), sizeof(int2) * wcol.size());
+  std::memcpy(ss.host + Lo.o_gw, wg.data(), sizeof(int2) * wg.size());
+  std::memcpy(ss.host + Lo.o_sw, wsc.data(), sizeof(int2) * wsc.size());
+  UHM_HIP(hipMemcpyAsync(ss.dev, ss.host, Lo.o_g, hipMemcpyHostToDevice, s));
+  const ArnDesc* dD = reinterpret_cast<const ArnDesc*>(ss.dev + Lo.o_d);
+  const int4* dRow = reinterpret_cast<const int4*>(ss.dev + Lo.o_row);
+  const int2* dRed = reinterpret_cast<const int2*>(ss.dev + Lo.o_red);
+  const int2* dCol = reinterpret_cast<const int2*>(ss.dev + Lo.o_col);
   for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(k_ab_dots, dim3(nrow), dim3(kGB), 0, s, dD, dRow, pass);
-    hipLaunchKernelGGL(k_ab_reduce, dim3(nred), dim3(kGB), 0, s, dD, dRed, pass);
-    hipLaunchKernelGGL(k_ab_update, dim3(nrow), dim3(kGB), 0, s, dD, dRow, pass);
-    if (pass == 0) hipLaunchKernelGGL(k_ab_decide, dim3(ncol), dim3(64), 0, s, dD, dCol);
+    hipLaunchKernelGGL(k_ab_dots, dim3(Lo.nrow), dim3(kGB), 0, s, dD, dRow, pass);
+    hipLaunchKernelGGL(k_ab_reduce, dim3(Lo.nred), dim3(kGB), 0, s, dD, dRed, pass);
+    hipLaunchKernelGGL(k_ab_update, dim3(Lo.nrow), dim3(kGB), 0, s, dD, dRow, pass);
+    if (pass == 0) hipLaunchKernelGGL(k_ab_decide, dim3(Lo.ncol), dim3(64), 0, s, dD, dCol);
   }
-  hipLaunchKernelGGL(k_ab_final, dim3(ncol), dim3(64), 0, s, dD, dCol);
-  for (uhm_krylov* K : iter) {
-    Work& W = K->W;
-    const int64_t hsz = 2 * (int64_t)(K->o.restart + 1) * K->r + K->r;
-    UHM_HIP(hipMemcpyAsync(W.hx.p, W.hbuf.p, sizeof(cd) * (size_t)hsz, hipMemcpyDeviceToHost, s));
+  hipLaunchKernelGGL(k_ab_final, dim3(Lo.ncol), dim3(64), 0, s, dD, dCol);
+  hipLaunchKernelGGL(k_ab_gather, dim3(Lo.ngw), dim3(kGB), 0, s, dD, reinterpret_cast<const int2*>(ss.dev + Lo.o_gw),
+                     reinterpret_cast<cd*>(ss.dev + Lo.o_g));
+  UHM_HIP(hipMemcpyAsync(ss.host + Lo.o_g, ss.dev + Lo.o_g, Lo.o_s - Lo.o_g, hipMemcpyDeviceToHost, s));
+  return UHM_OK;
+}
+
+// Host halves of many solves after the gathered h has arrived, then one upload of all the
+// scale factors and one launch that forms every V_{j+1}.
+int arnoldi_finish_many(const std::vector<uhm_krylov*>& iter, hipStream_t s, StepScratch& ss, const ManyLayout& Lo) {
+  const cd* g = reinterpret_cast<const cd*>(ss.host + Lo.o_g);
+  cd* sc = reinterpret_cast<cd*>(ss.host + Lo.o_s);
+  std::vector<char> done(iter.size());
+  int64_t goff = 0, soff = 0;
+  for (size_t k = 0; k < iter.size(); ++k) {
+    uhm_krylov* K = iter[k];
+    done[k] = arnoldi_host(K, g + goff);
+    for (int c = 0; c < K->r; ++c) sc[soff + c] = make_double2(K->sc[c], 0.0);
+    goff += 2 * (int64_t)(K->o.restart + 1) * K->r + K->r;
+    soff += K->r;
   }
+  UHM_HIP(hipMemcpyAsync(ss.dev + Lo.o_s, ss.host + Lo.o_s, Lo.tot - Lo.o_s, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_ab_scale, dim3(Lo.nsw), dim3(kGB), 0, s, reinterpret_cast<const ArnDesc*>(ss.dev + Lo.o_d),
+                     reinterpret_cast<const int2*>(ss.dev + Lo.o_sw), reinterpret_cast<const cd*>(ss.dev + Lo.o_s));
+  for (size_t k = 0; k < iter.size(); ++k) {
+    int rc = arnoldi_next(iter[k], done[k] != 0);
+    if (rc) return iter[k]->status = rc;
+  }
+  // the pinned scale area is reused by the next step: the upload must be complete
+  UHM_HIP(hipStreamSynchronize(s));
   return UHM_OK;
 }
 
@@ -779,7 +844,14 @@ int arnoldi_step(uhm_krylov* K) {
   int rc = arnoldi_issue(K);
   if (rc) return rc;
   UHM_HIP(hipStreamSynchronize(K->s));
-  return arnoldi_finish(K);
+  Work& W = K->W;
+  const int r = K->r;
+  const bool all_done = arnoldi_host(K, W.hx.p);
+  for (int c = 0; c < r; ++c) W.scp.p[c] = make_double2(K->sc[c], 0.0);
+  UHM_HIP(hipMemcpyAsync(W.scale.p, W.scp.p, sizeof(cd) * r, hipMemcpyHostToDevice, K->s));
+  hipLaunchKernelGGL(k_g_scale2, dim3(nblk(K->n * r)), dim3(kGB), 0, K->s, W.w.p, W.scale.p, K->n, r,
+                     W.V.p + (int64_t)(K->j + 1) * K->n * r);
+  return arnoldi_next(K, all_done);
 }
 
 int advance(uhm_krylov* K) {
@@ -969,50 +1041,89 @@ int uhm_krylov_step(uhm_krylov* const* ks, uhm_op* const* high, uhm_op* const* l
       if (std::find(other.begin(), other.end(), ks[k]->s) == other.end()) other.push_back(ks[k]->s);
     }
   for (hipStream_t o : other) UHM_HIP(hipStreamSynchronize(o));
+  StepScratch& ss = step_scratch();
+  std::lock_guard<std::mutex> lock(ss.mu);
+  // products of up to 64 columns (whole solves) per operator and precision
+  struct Chunk {
+    uhm_op* A;
+    bool hi;
+    const Item* items;
+    size_t cnt;
+    int cols;
+    size_t poff;  // first x pointer in the step's pointer array (y pointers follow the x ones)
+  };
+  std::vector<Chunk> chunks;
+  size_t nptr = 0;
   for (auto& gkv : groups) {
-    uhm_op* A = gkv.first.first;
-    const bool hi = gkv.first.second == UHM_KRYLOV_PRODUCT_HIGH;
-    const int64_t n = A->n;
     const std::vector<Item>& items = gkv.second;
     size_t a = 0;
     while (a < items.size()) {
-      // pack up to 64 columns (whole solves) per product
       int cols = 0;
       size_t b = a;
       while (b < items.size() && (cols == 0 || cols + ks[items[b].k]->r <= 64)) cols += ks[items[b++].k]->r;
-      const int64_t es = hi ? 16 : 8;
-      const int64_t need = es * n * cols;
-      if (A->stage_bytes < need) {
-        if ((rc = A->stage_in.alloc(need)) || (rc = A->stage_out.alloc(need))) {
-          A->stage_bytes = 0;
-          return rc;
-        }
-        A->stage_bytes = need;
-      }
-      int c0 = 0;
-      for (size_t q = a; q < b; ++q) {
-        const int r = ks[items[q].k]->r;
-        if (hi)
-          UHM_HIP(hipMemcpyAsync(reinterpret_cast<cd*>(A->stage_in.p) + (int64_t)c0 * n, items[q].in,
-                                 sizeof(cd) * (size_t)(n * r), hipMemcpyDeviceToDevice, s));
-        else
-          hipLaunchKernelGGL(k_g_pack32, dim3(nblk(n * r)), dim3(kGB), 0, s, items[q].in, n, n, r,
-                             reinterpret_cast<cf*>(A->stage_in.p) + (int64_t)c0 * n, n);
-        c0 += r;
-      }
-      if ((rc = uhm_matvec(A, A->stage_in.p, n, A->stage_out.p, n, cols, s))) return rc;
-      c0 = 0;
-      for (size_t q = a; q < b; ++q) {
-        const int r = ks[items[q].k]->r;
-        if (hi)
-          UHM_HIP(hipMemcpyAsync(items[q].out, reinterpret_cast<cd*>(A->stage_out.p) + (int64_t)c0 * n,
-                                 sizeof(cd) * (size_t)(n * r), hipMemcpyDeviceToDevice, s));
-        else
-          hipLaunchKernelGGL(k_g_unpack32, dim3(nblk(n * r)), dim3(kGB), 0, s,
-                             reinterpret_cast<const cf*>(A->stage_out.p) + (int64_t)c0 * n, n, n, r, items[q].out, n);
-        c0 += r;
-      }
+      Chunk c{gkv.first.first, gkv.first.second == UHM_KRYLOV_PRODUCT_HIGH, &items[a], b - a, cols, nptr};
+      if (c.A->lp) nptr += 2 * (size_t)cols;
+      chunks.push_back(c);
       a = b;
+    }
+  }
+  // many-RHS operators read and write the solves' vectors through column pointers
+  if (nptr > 0) {
+    if (ss.pev_recorded) UHM_HIP(hipEventSynchronize(ss.pev));
+    if (!ss.pev) UHM_HIP(hipEventCreateWithFlags(&ss.pev, hipEventDisableTiming));
+    if (nptr > ss.pcap) {
+      if (ss.pdev) (void)hipFree(ss.pdev);
+      if (ss.phost) (void)hipHostFree(ss.phost);
+      ss.pdev = ss.phost = nullptr;
+      const size_t cap = std::max(nptr, 2 * ss.pcap + 1024);
+      ss.pcap = 0;
+      UHM_HIP(hipMalloc(reinterpret_cast<void**>(&ss.pdev), sizeof(cd*) * cap));
+      UHM_HIP(hipHostMalloc(reinterpret_cast<void**>(&ss.phost), sizeof(cd*) * cap, hipHostMallocDefault));
+      ss.pcap = cap;
+    }
+    for (const Chunk& c : chunks) {
+      if (!c.A->lp) continue;
+      size_t q = c.poff;
+      for (size_t t = 0; t < c.cnt; ++t)
+        for (int j = 0; j < ks[c.items[t].k]->r; ++j) ss.phost[q++] = c.items[t].in + (int64_t)j * c.A->n;
+      for (size_t t = 0; t < c.cnt; ++t)
+        for (int j = 0; j < ks[c.items[t].k]->r; ++j) ss.phost[q++] = c.items[t].out + (int64_t)j * c.A->n;
+    }
+    UHM_HIP(hipMemcpyAsync(ss.pdev, ss.phost, sizeof(cd*) * nptr, hipMemcpyHostToDevice, s));
+    UHM_HIP(hipEventRecord(ss.pev, s));
+    ss.pev_recorded = true;
+  }
+  for (const Chunk& c : chunks) {
+    uhm_op* A = c.A;
+    const int64_t n = A->n;
+    if (A->lp) {
+      if ((rc = lowp_matvec_cols(A, ss.pdev + c.poff, const_cast<cd* const*>(ss.pdev + c.poff + c.cols), c.cols, s)))
+        return rc;
+      continue;
+    }
+    // single-RHS storage: pack the columns, multiply, unpack
+    const int64_t need = 16 * n * c.cols;
+    if (A->stage_bytes < need) {
+      if ((rc = A->stage_in.alloc(need)) || (rc = A->stage_out.alloc(need))) {
+        A->stage_bytes = 0;
+        return rc;
+      }
+      A->stage_bytes = need;
+    }
+    int c0 = 0;
+    for (size_t t = 0; t < c.cnt; ++t) {
+      const int r = ks[c.items[t].k]->r;
+      UHM_HIP(hipMemcpyAsync(reinterpret_cast<cd*>(A->stage_in.p) + (int64_t)c0 * n, c.items[t].in,
+                             sizeof(cd) * (size_t)(n * r), hipMemcpyDeviceToDevice, s));
+      c0 += r;
+    }
+    if ((rc = uhm_matvec(A, A->stage_in.p, n, A->stage_out.p, n, c.cols, s))) return rc;
+    c0 = 0;
+    for (size_t t = 0; t < c.cnt; ++t) {
+      const int r = ks[c.items[t].k]->r;
+      UHM_HIP(hipMemcpyAsync(c.items[t].out, reinterpret_cast<cd*>(A->stage_out.p) + (int64_t)c0 * n,
+                             sizeof(cd) * (size_t)(n * r), hipMemcpyDeviceToDevice, s));
+      c0 += r;
     }
   }
   if (!all_on_s) UHM_HIP(hipStreamSynchronize(s));
@@ -1024,18 +1135,13 @@ int uhm_krylov_step(uhm_krylov* const* ks, uhm_op* const* high, uhm_op* const* l
     if (K->req != UHM_KRYLOV_DONE && K->phase == uhm_krylov::ITER) iter.push_back(K);
   }
   if (!iter.empty()) {
-    StepScratch& ss = step_scratch();
-    std::lock_guard<std::mutex> lock(ss.mu);
     const auto t0 = Clock::now();
-    if ((rc = arnoldi_issue_many(iter, s, ss))) return rc;
+    ManyLayout Lo{};
+    if ((rc = arnoldi_issue_many(iter, s, ss, Lo))) return rc;
     UHM_HIP(hipStreamSynchronize(s));
+    if ((rc = arnoldi_finish_many(iter, s, ss, Lo))) return rc;
     const double dt = std::chrono::duration<double>(Clock::now() - t0).count() / (double)iter.size();
     for (uhm_krylov* K : iter) K->t_arn += dt;
-  }
-  for (uhm_krylov* K : iter) {
-    const auto t0 = Clock::now();
-    if ((rc = arnoldi_finish(K))) return K->status = rc;
-    K->t_arn += std::chrono::duration<double>(Clock::now() - t0).count();
   }
   int running = 0;
   for (int32_t k = 0; k < count; ++k) {

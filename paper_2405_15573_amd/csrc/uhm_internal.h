@@ -288,5 +288,7 @@ void lowp_batch_delete(LowpBatch* b);
 // Many-RHS storage forms (complex64, bf16 pairs, complex128): MFMA kernels, own device layout.
 int lowp_upload(const uhm_host_operator* h, uhm_storage storage, hipStream_t s, const TreeInfo& T, uhm_op* op);
 int lowp_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs, hipStream_t s);
+// Y = A X for 1..64 columns given as device arrays of complex128 column pointers (user order).
+int lowp_matvec_cols(uhm_op* op, const cd* const* xcol, cd* const* ycol, int32_t ncols, hipStream_t s);
 
 }  // namespace uhm_detail

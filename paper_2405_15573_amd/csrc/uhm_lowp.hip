@@ -674,6 +674,38 @@ __global__ __launch_bounds__(256) void k_lp_scatter(const V* __restrict__ Yc, in
   scatter_body<V>((int64_t)blockIdx.x * 256 + threadIdx.x, Yc, r, R, perm, n, y, ldy);
 }
 
+// Column-pointer forms of the gather and the scatter: column j of the input and the output
+// are complex128 vectors xcol[j], ycol[j] in user order (converted to and from the storage's
+// vector element), so the columns of many solves need no packing.
+template <class V>
+__device__ __forceinline__ V from_c128(cd a);
+template <>
+__device__ __forceinline__ cf from_c128<cf>(cd a) { return make_float2((float)a.x, (float)a.y); }
+template <>
+__device__ __forceinline__ cd from_c128<cd>(cd a) { return a; }
+
+template <class V>
+__global__ __launch_bounds__(256) void k_lp_gather_cols(const cd* const* __restrict__ xcol, int r, int R,
+                                                        const int32_t* __restrict__ perm, int64_t n, V* __restrict__ Xc) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= n * R) return;
+  const int64_t pos = q / R;
+  const int j = (int)(q - pos * R);
+  Xc[q] = j < r ? from_c128<V>(xcol[j][perm[pos]]) : vzero<V>();
+}
+
+template <class V>
+__global__ __launch_bounds__(256) void k_lp_scatter_cols(const V* __restrict__ Yc, int r, int R,
+                                                         const int32_t* __restrict__ perm, int64_t n,
+                                                         cd* const* __restrict__ ycol) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= n * (int64_t)r) return;
+  const int j = (int)(q / n);
+  const int64_t pos = q - (int64_t)j * n;
+  const V v = Yc[pos * R + j];
+  ycol[j][perm[pos]] = make_double2((double)v.x, (double)v.y);
+}
+
 template <int ST, int NT>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lp_forward(
     const uint4* __restrict__ F, const int64_t* __restrict__ f_off, const int32_t* __restrict__ f_M,
@@ -1151,7 +1183,8 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
 }
 
 template <int ST, int NT>
-void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, int64_t ldy, int r, int R, hipStream_t s) {
+void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, int64_t ldy, int r, int R, hipStream_t s,
+                const cd* const* xcol = nullptr, cd* const* ycol = nullptr) {
   using V = typename Tr<ST>::V;
   const V* x = static_cast<const V*>(xv);
   V* y = static_cast<V*>(yv);
@@ -1165,8 +1198,12 @@ void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, i
   const int64_t n = op->n;
   {
     ScopedTiming tm(op, s, K_LP_GATHER);
-    hipLaunchKernelGGL(k_lp_gather<V>, dim3((unsigned)((n * R + 255) / 256)), dim3(256), 0, s, x, ldx, r, R,
-                       op->perm.p, n, Xc);
+    if (xcol)
+      hipLaunchKernelGGL(k_lp_gather_cols<V>, dim3((unsigned)((n * R + 255) / 256)), dim3(256), 0, s, xcol, r, R,
+                         op->perm.p, n, Xc);
+    else
+      hipLaunchKernelGGL(k_lp_gather<V>, dim3((unsigned)((n * R + 255) / 256)), dim3(256), 0, s, x, ldx, r, R,
+                         op->perm.p, n, Xc);
   }
   if (lp->nxh > 0) {
     {
@@ -1200,18 +1237,23 @@ void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, i
   }
   {
     ScopedTiming tm(op, s, K_LP_SCATTER);
-    hipLaunchKernelGGL(k_lp_scatter<V>, dim3((unsigned)((n * r + 255) / 256)), dim3(256), 0, s, Yc, r, R, op->perm.p, n,
-                       y, ldy);
+    if (ycol)
+      hipLaunchKernelGGL(k_lp_scatter_cols<V>, dim3((unsigned)((n * r + 255) / 256)), dim3(256), 0, s, Yc, r, R,
+                         op->perm.p, n, ycol);
+    else
+      hipLaunchKernelGGL(k_lp_scatter<V>, dim3((unsigned)((n * r + 255) / 256)), dim3(256), 0, s, Yc, r, R, op->perm.p,
+                         n, y, ldy);
   }
 }
 
 template <int ST>
-void launch_nt(uhm_op* op, LowpOp* lp, const void* x, int64_t ldx, void* y, int64_t ldy, int r, int R, hipStream_t s) {
+void launch_nt(uhm_op* op, LowpOp* lp, const void* x, int64_t ldx, void* y, int64_t ldy, int r, int R, hipStream_t s,
+               const cd* const* xcol = nullptr, cd* const* ycol = nullptr) {
   switch (R / 16) {
-    case 1: launch_all<ST, 1>(op, lp, x, ldx, y, ldy, r, R, s); break;
-    case 2: launch_all<ST, 2>(op, lp, x, ldx, y, ldy, r, R, s); break;
-    case 3: launch_all<ST, 3>(op, lp, x, ldx, y, ldy, r, R, s); break;
-    default: launch_all<ST, 4>(op, lp, x, ldx, y, ldy, r, R, s); break;
+    case 1: launch_all<ST, 1>(op, lp, x, ldx, y, ldy, r, R, s, xcol, ycol); break;
+    case 2: launch_all<ST, 2>(op, lp, x, ldx, y, ldy, r, R, s, xcol, ycol); break;
+    case 3: launch_all<ST, 3>(op, lp, x, ldx, y, ldy, r, R, s, xcol, ycol); break;
+    default: launch_all<ST, 4>(op, lp, x, ldx, y, ldy, r, R, s, xcol, ycol); break;
   }
 }
 
@@ -1278,6 +1320,23 @@ int lowp_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, in
   return UHM_OK;
 }
 
+int lowp_matvec_cols(uhm_op* op, const cd* const* xcol, cd* const* ycol, int32_t ncols, hipStream_t s) {
+  LowpOp* lp = op->lp;
+  if (!lp) return fail(UHM_EINVAL, "operator has no many-RHS form");
+  if (ncols < 1 || ncols > kLpRmax || !xcol || !ycol) return fail(UHM_EINVAL, "bad column pointer arrays");
+  const int R = 16 * ((ncols + 15) / 16);
+  int rc = grow(lp, op->n, std::max(R, lp->wsR));
+  if (rc) return rc;
+  if (lp->storage == UHM_C64)
+    launch_nt<UHM_C64>(op, lp, nullptr, 0, nullptr, 0, ncols, R, s, xcol, ycol);
+  else if (lp->storage == UHM_BF16PAIR)
+    launch_nt<UHM_BF16PAIR>(op, lp, nullptr, 0, nullptr, 0, ncols, R, s, xcol, ycol);
+  else
+    launch_nt<UHM_C128_MULTI>(op, lp, nullptr, 0, nullptr, 0, ncols, R, s, xcol, ycol);
+  const hipError_t he = hipGetLastError();
+  if (he != hipSuccess) return fail(UHM_EHIP, std::string("kernel launch: ") + hipGetErrorString(he));
+  return UHM_OK;
+}
 
 // ---------------------------------------------------------------- batched products
 
