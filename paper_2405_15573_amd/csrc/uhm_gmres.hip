@@ -27,6 +27,7 @@
 #include <cmath>
 #include <complex>
 #include <map>
+#include <tuple>
 
 namespace uhm_detail {
 namespace {
@@ -1093,14 +1094,31 @@ int uhm_krylov_step(uhm_krylov* const* ks, uhm_op* const* high, uhm_op* const* l
     UHM_HIP(hipEventRecord(ss.pev, s));
     ss.pev_recorded = true;
   }
+  // many-RHS products in shared stage launches: one call per (storage, column blocks,
+  // chunk number of the operator), every operator at most once per call
+  {
+    std::map<std::tuple<int, int, int>, std::vector<const Chunk*>> sets;
+    std::map<uhm_op*, int> seen;
+    for (const Chunk& c : chunks)
+      if (c.A->lp) sets[{c.A->storage, (c.cols + 15) / 16, seen[c.A]++}].push_back(&c);
+    for (auto& kv : sets) {
+      std::vector<uhm_op*> ops;
+      std::vector<const cd* const*> xc;
+      std::vector<cd* const*> yc;
+      std::vector<int32_t> nc;
+      for (const Chunk* c : kv.second) {
+        ops.push_back(c->A);
+        xc.push_back(ss.pdev + c->poff);
+        yc.push_back(const_cast<cd* const*>(ss.pdev + c->poff + c->cols));
+        nc.push_back(c->cols);
+      }
+      if ((rc = lowp_step_products(ops.data(), xc.data(), yc.data(), nc.data(), (int32_t)ops.size(), s))) return rc;
+    }
+  }
   for (const Chunk& c : chunks) {
     uhm_op* A = c.A;
     const int64_t n = A->n;
-    if (A->lp) {
-      if ((rc = lowp_matvec_cols(A, ss.pdev + c.poff, const_cast<cd* const*>(ss.pdev + c.poff + c.cols), c.cols, s)))
-        return rc;
-      continue;
-    }
+    if (A->lp) continue;
     // single-RHS storage: pack the columns, multiply, unpack
     const int64_t need = 16 * n * c.cols;
     if (A->stage_bytes < need) {

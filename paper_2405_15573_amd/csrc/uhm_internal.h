@@ -288,7 +288,11 @@ void lowp_batch_delete(LowpBatch* b);
 // Many-RHS storage forms (complex64, bf16 pairs, complex128): MFMA kernels, own device layout.
 int lowp_upload(const uhm_host_operator* h, uhm_storage storage, hipStream_t s, const TreeInfo& T, uhm_op* op);
 int lowp_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs, hipStream_t s);
-// Y = A X for 1..64 columns given as device arrays of complex128 column pointers (user order).
-int lowp_matvec_cols(uhm_op* op, const cd* const* xcol, cd* const* ycol, int32_t ncols, hipStream_t s);
+// Products Y_k = A_k X_k of several distinct operators of one many-RHS storage form in
+// shared stage launches.  Columns are complex128 vectors in user order, given per operator
+// as device arrays of ncols[k] (1..64) pointers xcol[k], ycol[k].  Calls must not overlap
+// (shared staging).
+int lowp_step_products(uhm_op* const* ops, const cd* const* const* xcol, cd* const* const* ycol, const int32_t* ncols,
+                       int32_t nops, hipStream_t s);
 
 }  // namespace uhm_detail

@@ -28,7 +28,7 @@
 #include <complex>
 #include <functional>
 #include <map>
-#include <type_traits>
+#include <cstring>
 
 namespace uhm_detail {
 
@@ -92,7 +92,7 @@ struct Acc3 {
   __device__ auto im(int nt, int v) const { return s[nt][v] - p[nt][v] - q[nt][v]; }
 };
 // Four-product form (bf16 pairs, where ar + ai would be rounded to bf16 again, and
-// complex128 with many columns, where a third accumulator costs occupancy).
+// complex128, where a third accumulator costs occupancy at many columns).
 template <class A, int NT>
 struct Acc2 {
   A r[NT], i[NT];
@@ -139,9 +139,11 @@ struct Tr<UHM_C128_MULTI> {
   static constexpr int KB = 16, KPL = 4, CH = 4, RZ = 32, KP = 1;
   using V = cd;
   using ACC = v4d;
-  // three accumulators per column tile would leave one wave per SIMD at NT >= 3
+  // four products at every NT: three accumulators per column tile would leave one wave per
+  // SIMD at NT >= 3, and one scheme for all NT keeps a column's rounding independent of
+  // how many columns share its pass
   template <int NT>
-  using ACCS = std::conditional_t<(NT <= 2), Acc3<v4d, NT>, Acc2<v4d, NT>>;
+  using ACCS = Acc2<v4d, NT>;
   template <int NT>
   using LDS = LdsF64<round_rows(RZ, NT), NT>;
   using CHUNK = ChunkF64;
@@ -245,23 +247,6 @@ __device__ __forceinline__ void mma_block(const ChunkF32& a, const LdsF32<RZ, NT
 
 template <int NT, int RZ>
 __device__ __forceinline__ void mma_block(const ChunkF64& a, const LdsF64<RZ, NT>& L, int kk0, int g, int i,
-                                          Acc3<v4d, NT>& c) {
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int k = kk0 + g * 4 + t;
-    const double ar = a.re[t], ai = a.im[t], as = ar + ai;
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const cd b = L.z[k * L.S + nt * 16 + i];
-      c.p[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.x, c.p[nt], 0, 0, 0);
-      c.q[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b.y, c.q[nt], 0, 0, 0);
-      c.s[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, b.x + b.y, c.s[nt], 0, 0, 0);
-    }
-  }
-}
-
-template <int NT, int RZ>
-__device__ __forceinline__ void mma_block(const ChunkF64& a, const LdsF64<RZ, NT>& L, int kk0, int g, int i,
                                           Acc2<v4d, NT>& c) {
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -349,6 +334,8 @@ struct LpDesc {
   void *Xc, *Yc, *p, *xh, *part, *yh;
   const void* x;
   void* y;
+  const cd* const* xcol;  // when set: column j of x / y is the complex128 vector xcol[j] / ycol[j]
+  cd* const* ycol;
   int64_t ldx, ldy, n, nxh, nyh;
   int32_t r, R;
 };
@@ -674,9 +661,7 @@ __global__ __launch_bounds__(256) void k_lp_scatter(const V* __restrict__ Yc, in
   scatter_body<V>((int64_t)blockIdx.x * 256 + threadIdx.x, Yc, r, R, perm, n, y, ldy);
 }
 
-// Column-pointer forms of the gather and the scatter: column j of the input and the output
-// are complex128 vectors xcol[j], ycol[j] in user order (converted to and from the storage's
-// vector element), so the columns of many solves need no packing.
+// complex128 -> the storage's vector element, for inputs given as complex128 columns
 template <class V>
 __device__ __forceinline__ V from_c128(cd a);
 template <>
@@ -684,27 +669,6 @@ __device__ __forceinline__ cf from_c128<cf>(cd a) { return make_float2((float)a.
 template <>
 __device__ __forceinline__ cd from_c128<cd>(cd a) { return a; }
 
-template <class V>
-__global__ __launch_bounds__(256) void k_lp_gather_cols(const cd* const* __restrict__ xcol, int r, int R,
-                                                        const int32_t* __restrict__ perm, int64_t n, V* __restrict__ Xc) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (q >= n * R) return;
-  const int64_t pos = q / R;
-  const int j = (int)(q - pos * R);
-  Xc[q] = j < r ? from_c128<V>(xcol[j][perm[pos]]) : vzero<V>();
-}
-
-template <class V>
-__global__ __launch_bounds__(256) void k_lp_scatter_cols(const V* __restrict__ Yc, int r, int R,
-                                                         const int32_t* __restrict__ perm, int64_t n,
-                                                         cd* const* __restrict__ ycol) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (q >= n * (int64_t)r) return;
-  const int j = (int)(q / n);
-  const int64_t pos = q - (int64_t)j * n;
-  const V v = Yc[pos * R + j];
-  ycol[j][perm[pos]] = make_double2((double)v.x, (double)v.y);
-}
 
 template <int ST, int NT>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lp_forward(
@@ -767,6 +731,14 @@ template <class V>
 __global__ __launch_bounds__(256) void k_lpb_gather(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];
+  if (d.xcol) {
+    const int64_t q = (int64_t)wk.y * 256 + threadIdx.x;
+    if (q >= d.n * d.R) return;
+    const int64_t pos = q / d.R;
+    const int j = (int)(q - pos * d.R);
+    static_cast<V*>(d.Xc)[q] = j < d.r ? from_c128<V>(d.xcol[j][d.perm[pos]]) : vzero<V>();
+    return;
+  }
   gather_body<V>((int64_t)wk.y * 256 + threadIdx.x, static_cast<const V*>(d.x), d.ldx, d.r, d.R, d.perm, d.n,
                  static_cast<V*>(d.Xc));
 }
@@ -775,6 +747,15 @@ template <class V>
 __global__ __launch_bounds__(256) void k_lpb_scatter(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];
+  if (d.ycol) {
+    const int64_t q = (int64_t)wk.y * 256 + threadIdx.x;
+    if (q >= d.n * (int64_t)d.r) return;
+    const int j = (int)(q / d.n);
+    const int64_t pos = q - (int64_t)j * d.n;
+    const V v = static_cast<const V*>(d.Yc)[pos * d.R + j];
+    d.ycol[j][d.perm[pos]] = make_double2((double)v.x, (double)v.y);
+    return;
+  }
   scatter_body<V>((int64_t)wk.y * 256 + threadIdx.x, static_cast<const V*>(d.Yc), d.r, d.R, d.perm, d.n,
                   static_cast<V*>(d.y), d.ldy);
 }
@@ -1183,8 +1164,7 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
 }
 
 template <int ST, int NT>
-void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, int64_t ldy, int r, int R, hipStream_t s,
-                const cd* const* xcol = nullptr, cd* const* ycol = nullptr) {
+void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, int64_t ldy, int r, int R, hipStream_t s) {
   using V = typename Tr<ST>::V;
   const V* x = static_cast<const V*>(xv);
   V* y = static_cast<V*>(yv);
@@ -1198,12 +1178,8 @@ void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, i
   const int64_t n = op->n;
   {
     ScopedTiming tm(op, s, K_LP_GATHER);
-    if (xcol)
-      hipLaunchKernelGGL(k_lp_gather_cols<V>, dim3((unsigned)((n * R + 255) / 256)), dim3(256), 0, s, xcol, r, R,
-                         op->perm.p, n, Xc);
-    else
-      hipLaunchKernelGGL(k_lp_gather<V>, dim3((unsigned)((n * R + 255) / 256)), dim3(256), 0, s, x, ldx, r, R,
-                         op->perm.p, n, Xc);
+    hipLaunchKernelGGL(k_lp_gather<V>, dim3((unsigned)((n * R + 255) / 256)), dim3(256), 0, s, x, ldx, r, R,
+                       op->perm.p, n, Xc);
   }
   if (lp->nxh > 0) {
     {
@@ -1237,23 +1213,18 @@ void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, i
   }
   {
     ScopedTiming tm(op, s, K_LP_SCATTER);
-    if (ycol)
-      hipLaunchKernelGGL(k_lp_scatter_cols<V>, dim3((unsigned)((n * r + 255) / 256)), dim3(256), 0, s, Yc, r, R,
-                         op->perm.p, n, ycol);
-    else
-      hipLaunchKernelGGL(k_lp_scatter<V>, dim3((unsigned)((n * r + 255) / 256)), dim3(256), 0, s, Yc, r, R, op->perm.p,
-                         n, y, ldy);
+    hipLaunchKernelGGL(k_lp_scatter<V>, dim3((unsigned)((n * r + 255) / 256)), dim3(256), 0, s, Yc, r, R, op->perm.p, n,
+                       y, ldy);
   }
 }
 
 template <int ST>
-void launch_nt(uhm_op* op, LowpOp* lp, const void* x, int64_t ldx, void* y, int64_t ldy, int r, int R, hipStream_t s,
-               const cd* const* xcol = nullptr, cd* const* ycol = nullptr) {
+void launch_nt(uhm_op* op, LowpOp* lp, const void* x, int64_t ldx, void* y, int64_t ldy, int r, int R, hipStream_t s) {
   switch (R / 16) {
-    case 1: launch_all<ST, 1>(op, lp, x, ldx, y, ldy, r, R, s, xcol, ycol); break;
-    case 2: launch_all<ST, 2>(op, lp, x, ldx, y, ldy, r, R, s, xcol, ycol); break;
-    case 3: launch_all<ST, 3>(op, lp, x, ldx, y, ldy, r, R, s, xcol, ycol); break;
-    default: launch_all<ST, 4>(op, lp, x, ldx, y, ldy, r, R, s, xcol, ycol); break;
+    case 1: launch_all<ST, 1>(op, lp, x, ldx, y, ldy, r, R, s); break;
+    case 2: launch_all<ST, 2>(op, lp, x, ldx, y, ldy, r, R, s); break;
+    case 3: launch_all<ST, 3>(op, lp, x, ldx, y, ldy, r, R, s); break;
+    default: launch_all<ST, 4>(op, lp, x, ldx, y, ldy, r, R, s); break;
   }
 }
 
@@ -1315,24 +1286,6 @@ int lowp_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, in
     else
       launch_nt<UHM_C128_MULTI>(op, lp, xc, ldx, yc, ldy, r, R, s);
   }
-  const hipError_t he = hipGetLastError();
-  if (he != hipSuccess) return fail(UHM_EHIP, std::string("kernel launch: ") + hipGetErrorString(he));
-  return UHM_OK;
-}
-
-int lowp_matvec_cols(uhm_op* op, const cd* const* xcol, cd* const* ycol, int32_t ncols, hipStream_t s) {
-  LowpOp* lp = op->lp;
-  if (!lp) return fail(UHM_EINVAL, "operator has no many-RHS form");
-  if (ncols < 1 || ncols > kLpRmax || !xcol || !ycol) return fail(UHM_EINVAL, "bad column pointer arrays");
-  const int R = 16 * ((ncols + 15) / 16);
-  int rc = grow(lp, op->n, std::max(R, lp->wsR));
-  if (rc) return rc;
-  if (lp->storage == UHM_C64)
-    launch_nt<UHM_C64>(op, lp, nullptr, 0, nullptr, 0, ncols, R, s, xcol, ycol);
-  else if (lp->storage == UHM_BF16PAIR)
-    launch_nt<UHM_BF16PAIR>(op, lp, nullptr, 0, nullptr, 0, ncols, R, s, xcol, ycol);
-  else
-    launch_nt<UHM_C128_MULTI>(op, lp, nullptr, 0, nullptr, 0, ncols, R, s, xcol, ycol);
   const hipError_t he = hipGetLastError();
   if (he != hipSuccess) return fail(UHM_EHIP, std::string("kernel launch: ") + hipGetErrorString(he));
   return UHM_OK;
@@ -1423,6 +1376,40 @@ void order_work(std::vector<int2>& w, const std::vector<int64_t>& cost, int orde
   w.swap(out);
 }
 
+// The operator's part of a batch descriptor: its panels, maps and tables.
+LpDesc desc_of(uhm_op* op) {
+  const LowpOp* lp = op->lp;
+  LpDesc d{};
+  d.F = lp->F.p;
+  d.S = lp->S.p;
+  d.B = lp->B.p;
+  d.f_off = lp->f_off.p;
+  d.poff = lp->poff.p;
+  d.b_off = lp->b_off.p;
+  d.zoff = lp->zoff.p;
+  d.seg_start = lp->seg_start.p;
+  d.grp_start = lp->grp_start.p;
+  d.f_M = lp->f_M.p;
+  d.f_nkb = lp->f_nkb.p;
+  d.b_nkb = lp->b_nkb.p;
+  d.zmap = lp->zmap.p;
+  d.colsrc = lp->colsrc.p;
+  d.out_seg = lp->out_seg.p;
+  d.seg_pan0 = lp->seg_pan0.p;
+  d.seg_npan = lp->seg_npan.p;
+  d.f_pos = lp->f_pos.p;
+  d.f_n = lp->f_n.p;
+  d.seg_col = lp->seg_col.p;
+  d.yh_grp = lp->yh_grp.p;
+  d.leaf_pos = op->leaf_pos.p;
+  d.leaf_n = op->leaf_n.p;
+  d.perm = op->perm.p;
+  d.n = op->n;
+  d.nxh = lp->nxh;
+  d.nyh = lp->nyh;
+  return d;
+}
+
 int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
   const int KB = B->ops[0]->op->lp->KB;
   const int64_t e = B->storage == UHM_C128_MULTI ? 16 : 8;
@@ -1452,33 +1439,9 @@ int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
       if ((rc = bo.part.alloc(e * need))) return rc;
       bo.part_cap = need;
     }
-    LpDesc d{};
-    d.F = lp->F.p;
-    d.S = lp->S.p;
-    d.B = lp->B.p;
-    d.f_off = lp->f_off.p;
-    d.poff = lp->poff.p;
-    d.b_off = lp->b_off.p;
-    d.zoff = lp->zoff.p;
-    d.seg_start = lp->seg_start.p;
-    d.grp_start = lp->grp_start.p;
-    d.f_M = lp->f_M.p;
-    d.f_nkb = lp->f_nkb.p;
-    d.b_nkb = lp->b_nkb.p;
-    d.zmap = lp->zmap.p;
-    d.colsrc = lp->colsrc.p;
-    d.out_seg = lp->out_seg.p;
-    d.seg_pan0 = lp->seg_pan0.p;
-    d.seg_npan = lp->seg_npan.p;
-    d.f_pos = lp->f_pos.p;
-    d.f_n = lp->f_n.p;
-    d.seg_col = lp->seg_col.p;
-    d.yh_grp = lp->yh_grp.p;
+    LpDesc d = desc_of(op);
     d.grp_t0 = bo.grp_t0.p;
     d.grp_nt = bo.grp_nt.p;
-    d.leaf_pos = op->leaf_pos.p;
-    d.leaf_n = op->leaf_n.p;
-    d.perm = op->perm.p;
     d.ctiles = bo.tiles.p;
     d.Xc = bo.Xc.p;
     d.Yc = bo.Yc.p;
@@ -1490,9 +1453,6 @@ int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
     d.y = bo.y;
     d.ldx = bo.ldx;
     d.ldy = bo.ldy;
-    d.n = op->n;
-    d.nxh = lp->nxh;
-    d.nyh = lp->nyh;
     d.r = bo.r;
     d.R = R;
     descs.push_back(d);
@@ -1575,6 +1535,137 @@ void batch_launch(LowpBatch* B, hipStream_t s) {
 }  // namespace
 
 void lowp_batch_delete(LowpBatch* b) { delete b; }
+
+// ---------------------------------------------------------------- products of a solver step
+namespace {
+
+// Pinned staging of the step products' descriptors and work lists (grow-only, never
+// released); ev marks when the last upload from it has been read.
+struct StepProducts {
+  unsigned char* dev = nullptr;
+  unsigned char* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool recorded = false;
+};
+StepProducts& step_products() {
+  static StepProducts* sp = new StepProducts;
+  return *sp;
+}
+
+template <int ST, int NT>
+void step_launch(const LpDesc* D, const int2* const* w, const unsigned* cnt, hipStream_t s) {
+  using V = typename Tr<ST>::V;
+  auto go = [&](auto kern, int st, int threads) {
+    if (cnt[st] > 0) hipLaunchKernelGGL(kern, dim3(cnt[st]), dim3(threads), 0, s, D, w[st]);
+  };
+  go(k_lpb_gather<V>, 0, 256);
+  go(k_lpb_forward<ST, NT>, 1, 64 * kLpWaves);
+  go(k_lpb_reduce_segments<V>, 2, 256);
+  go(k_lpb_coupling<ST, NT>, 3, 64 * kLpWaves);
+  go(k_lpb_reduce_coupling<V>, 4, 256);
+  go(k_lpb_backward<ST, NT>, 5, 64 * kLpWaves);
+  go(k_lpb_scatter<V>, 6, 256);
+}
+
+template <int ST>
+void step_launch_st(int NT, const LpDesc* D, const int2* const* w, const unsigned* cnt, hipStream_t s) {
+  switch (NT) {
+    case 1: step_launch<ST, 1>(D, w, cnt, s); break;
+    case 2: step_launch<ST, 2>(D, w, cnt, s); break;
+    case 3: step_launch<ST, 3>(D, w, cnt, s); break;
+    default: step_launch<ST, 4>(D, w, cnt, s); break;
+  }
+}
+
+}  // namespace
+
+int lowp_step_products(uhm_op* const* ops, const cd* const* const* xcol, cd* const* const* ycol, const int32_t* ncols,
+                       int32_t nops, hipStream_t s) {
+  if (nops < 1 || !ops || !xcol || !ycol || !ncols) return fail(UHM_EINVAL, "null argument");
+  const int storage = ops[0]->lp ? ops[0]->lp->storage : -1;
+  int maxc = 0;
+  for (int32_t k = 0; k < nops; ++k) {
+    if (!ops[k]->lp || ops[k]->lp->storage != storage) return fail(UHM_EINVAL, "step products need one many-RHS form");
+    if (ncols[k] < 1 || ncols[k] > kLpRmax) return fail(UHM_EINVAL, "1 to 64 columns per operator");
+    for (int32_t q = 0; q < k; ++q)
+      if (ops[q] == ops[k]) return fail(UHM_EINVAL, "an operator appears twice in one step product");
+    maxc = std::max(maxc, (int)ncols[k]);
+  }
+  const int R = 16 * ((maxc + 15) / 16);
+  std::vector<LpDesc> descs;
+  std::vector<int2> w[7];
+  int rc;
+  for (int32_t k = 0; k < nops; ++k) {
+    uhm_op* op = ops[k];
+    LowpOp* lp = op->lp;
+    if ((rc = grow(lp, op->n, std::max(R, lp->wsR)))) return rc;
+    LpDesc d = desc_of(op);
+    d.ctiles = lp->ctiles.p;
+    d.grp_t0 = lp->grp_t0.p;
+    d.grp_nt = lp->grp_nt.p;
+    d.Xc = lp->Xc.p;
+    d.Yc = lp->Yc.p;
+    d.p = lp->p.p;
+    d.xh = lp->xh.p;
+    d.part = lp->part.p;
+    d.yh = lp->yh.p;
+    d.xcol = xcol[k];
+    d.ycol = ycol[k];
+    d.r = ncols[k];
+    d.R = R;
+    descs.push_back(d);
+    const int32_t ki = k;
+    for (int64_t b = 0; b < ceil_div(op->n * R, 256); ++b) w[0].push_back(make_int2(ki, (int32_t)b));
+    if (lp->nxh > 0) {
+      for (int32_t pn = 0; pn < lp->npan; ++pn) w[1].push_back(make_int2(ki, pn));
+      for (int64_t b = 0; b < ceil_div(lp->nxh * R, 256); ++b) w[2].push_back(make_int2(ki, (int32_t)b));
+    }
+    for (int32_t t = 0; t < lp->nctiles; ++t) w[3].push_back(make_int2(ki, t));
+    if (lp->nctiles > 0)
+      for (int64_t b = 0; b < ceil_div(lp->nyh * R, 256); ++b) w[4].push_back(make_int2(ki, (int32_t)b));
+    for (int32_t l = 0; l < op->nleaves; ++l) w[5].push_back(make_int2(ki, l));
+    for (int64_t b = 0; b < ceil_div(op->n * (int64_t)ncols[k], 256); ++b) w[6].push_back(make_int2(ki, (int32_t)b));
+  }
+  size_t off[8];
+  off[0] = (sizeof(LpDesc) * descs.size() + 15) & ~size_t(15);
+  for (int st = 0; st < 7; ++st) off[st + 1] = off[st] + ((sizeof(int2) * w[st].size() + 15) & ~size_t(15));
+  const size_t tot = off[7];
+  StepProducts& sp = step_products();
+  if (sp.recorded) UHM_HIP(hipEventSynchronize(sp.ev));
+  if (!sp.ev) UHM_HIP(hipEventCreateWithFlags(&sp.ev, hipEventDisableTiming));
+  if (tot > sp.cap) {
+    if (sp.dev) (void)hipFree(sp.dev);
+    if (sp.host) (void)hipHostFree(sp.host);
+    sp.dev = sp.host = nullptr;
+    const size_t cap = std::max(tot, 2 * sp.cap + (1 << 16));
+    sp.cap = 0;
+    UHM_HIP(hipMalloc(reinterpret_cast<void**>(&sp.dev), cap));
+    UHM_HIP(hipHostMalloc(reinterpret_cast<void**>(&sp.host), cap, hipHostMallocDefault));
+    sp.cap = cap;
+  }
+  std::memcpy(sp.host, descs.data(), sizeof(LpDesc) * descs.size());
+  const int2* dw[7];
+  unsigned cnt[7];
+  for (int st = 0; st < 7; ++st) {
+    std::memcpy(sp.host + off[st], w[st].data(), sizeof(int2) * w[st].size());
+    dw[st] = reinterpret_cast<const int2*>(sp.dev + off[st]);
+    cnt[st] = (unsigned)w[st].size();
+  }
+  UHM_HIP(hipMemcpyAsync(sp.dev, sp.host, tot, hipMemcpyHostToDevice, s));
+  UHM_HIP(hipEventRecord(sp.ev, s));
+  sp.recorded = true;
+  const LpDesc* D = reinterpret_cast<const LpDesc*>(sp.dev);
+  if (storage == UHM_C64)
+    step_launch_st<UHM_C64>(R / 16, D, dw, cnt, s);
+  else if (storage == UHM_BF16PAIR)
+    step_launch_st<UHM_BF16PAIR>(R / 16, D, dw, cnt, s);
+  else
+    step_launch_st<UHM_C128_MULTI>(R / 16, D, dw, cnt, s);
+  const hipError_t he = hipGetLastError();
+  if (he != hipSuccess) return fail(UHM_EHIP, std::string("kernel launch: ") + hipGetErrorString(he));
+  return UHM_OK;
+}
 
 int lowp_batch_create(uhm_op* const* ops, int32_t nops, const void* const* X, const int64_t* ldx, void* const* Y,
                       const int64_t* ldy, const int32_t* nrhs, hipStream_t s, LowpBatch** out) {

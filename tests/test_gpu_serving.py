@@ -75,3 +75,19 @@ def test_small_budget_queues_and_admits_on_free(server_env):
     assert starts[1] >= fins[0] and starts[2] >= fins[1]
     assert srv.admission.used == 0 and srv.admission.active == 0
     srv.free()
+
+
+def test_wide_mix_equals_alone(server_env):
+    """58 columns on one operator share each product (four column blocks) while the solves
+    alone use one or two; a column's arithmetic must not depend on that."""
+    torch, host = server_env
+    from paper_2405_15573_amd.serving import Request, Server
+    spec = [(0, 8, 1e-8, 0.0), (0, 30, 1e-6, 0.0), (0, 20, 1e-6, 0.0), (1, 2, 1e-8, 0.0)]
+    srv = Server(host, low_storage="c64", keep_solutions=True)
+    mix = srv.serve(_requests(torch, host, spec))
+    assert all(q.code == 0 for q in mix)
+    for q in (mix[0], mix[3]):
+        alone = srv.serve([Request(rid=q.rid, op=q.op, b=q.b, tol=q.tol, arrival=0.0)])[0]
+        assert torch.equal(alone.x, q.x), q.rid
+        assert alone.info["iterations"] == q.info["iterations"]
+    srv.free()
