@@ -157,6 +157,14 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   return x * q + min(x, r) + k;
 }
 
+// Streaming loads of operator data: each element is read once per product, so the loads
+// carry the nontemporal hint and do not displace the reused vectors from the caches.
+typedef double v2d_stream __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cd stream_load(const cd* p) {
+  const v2d_stream v = __builtin_nontemporal_load(reinterpret_cast<const v2d_stream*>(p));
+  return make_double2(v.x, v.y);
+}
+
 template <int FORM>
 __global__ __launch_bounds__(64 * kFwdWaves) void k_forward(
     const cd* __restrict__ F, const int64_t* __restrict__ fwd_off, const int32_t* __restrict__ fwd_cols,
@@ -183,7 +191,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_forward(
     for (; i + 8 <= n; i += 8) {
       cd v[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = q[(i + k) * wj];
+      for (int k = 0; k < 8; ++k) v[k] = stream_load(&q[(i + k) * wj]);
 #pragma unroll
       for (int k = 0; k < 8; k += 2) {
         const cd x0 = xs[i + k], x1 = xs[i + k + 1];
@@ -194,7 +202,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_forward(
       }
     }
     for (; i < n; ++i) {
-      const cd v = q[i * wj], xv = xs[i];
+      const cd v = stream_load(&q[i * wj]), xv = xs[i];
       re0 = fma(v.x, xv.x, fma(v.y, xv.y, re0));
       im0 = fma(v.x, xv.y, fma(-v.y, xv.x, im0));
     }
@@ -263,7 +271,7 @@ __global__ __launch_bounds__(64 * kCoupWaves) void k_coupling(
     for (; q + 8 <= cnt; q += 8) {
       cd sv[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) sv[k] = col[(int64_t)(q + k) * h];
+      for (int k = 0; k < 8; ++k) sv[k] = stream_load(&col[(int64_t)(q + k) * h]);
 #pragma unroll
       for (int k = 0; k < 8; k += 2) {
         const cd x0 = xv[q + k], x1 = xv[q + k + 1];
@@ -274,7 +282,7 @@ __global__ __launch_bounds__(64 * kCoupWaves) void k_coupling(
       }
     }
     for (; q < cnt; ++q) {
-      const cd s0 = col[(int64_t)q * h], x0 = xv[q];
+      const cd s0 = stream_load(&col[(int64_t)q * h]), x0 = xv[q];
       re0 = fma(s0.x, x0.x, fma(-s0.y, x0.y, re0));
       im0 = fma(s0.x, x0.y, fma(s0.y, x0.x, im0));
     }
@@ -337,7 +345,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_backward(
       for (; c + 8 <= e; c += 8, col += 8 * n) {
         cd bv[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) bv[k] = col[k * n];
+        for (int k = 0; k < 8; ++k) bv[k] = stream_load(&col[k * n]);
 #pragma unroll
         for (int k = 0; k < 8; k += 2) {
           const cd z0 = zs[c + k], z1 = zs[c + k + 1];
@@ -348,7 +356,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_backward(
         }
       }
       for (; c < e; ++c, col += n) {
-        const cd b0 = col[0], z0 = zs[c];
+        const cd b0 = stream_load(col), z0 = zs[c];
         re0 = fma(b0.x, z0.x, fma(-b0.y, z0.y, re0));
         im0 = fma(b0.x, z0.y, fma(b0.y, z0.x, im0));
       }
