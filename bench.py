@@ -344,11 +344,12 @@ def main():
         a = torch.empty(1 << 26, dtype=torch.complex128, device="cuda")  # 1 GiB
         a.fill_(1.0)
         b = torch.empty_like(a)
-        for _ in range(3):
+        from paper_2405_15573_amd import traffic as trmod
+        for _ in range(trmod.CALIBRATION_COPIES):
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-        log("copy calibration: 3 copies of 1 GiB")
+        log(f"copy calibration: {trmod.CALIBRATION_COPIES} copies of 1 GiB")
 
     t0 = time.perf_counter()
     cloud = inputs.make_cloud("sphere", args.n, seed=args.seed)

@@ -17,7 +17,8 @@ import os
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-COPY_BYTES = 1 << 30
+COPY_BYTES = 1 << 30        # bytes read and written by each calibration copy
+CALIBRATION_COPIES = 3      # bench.py --copy-calibration runs this many before anything else
 
 
 def kernel_source_sha256() -> str:
@@ -35,27 +36,35 @@ def _short(name: str) -> str:
     return base.split("(")[0].strip()
 
 
+def _rows(path: str, counter: str):
+    with open(path) as f:
+        rows = [r for r in csv.DictReader(f) if r.get("Counter_Name") == counter]
+    return sorted(rows, key=lambda r: int(r.get("Dispatch_Id", 0)))
+
+
 def per_kernel(path: str, counter: str) -> dict:
     vals = defaultdict(list)
-    with open(path) as f:
-        for row in csv.DictReader(f):
-            if row.get("Counter_Name") != counter:
-                continue
-            vals[_short(row["Kernel_Name"])].append(float(row["Counter_Value"]))
+    for row in _rows(path, counter):
+        vals[_short(row["Kernel_Name"])].append(float(row["Counter_Value"]))
     return vals
+
+
+def calibration_kib(path: str, counter: str) -> float:
+    """Counter reading (KiB) of the calibration copies: the first CALIBRATION_COPIES device
+    copies of more than 64 MiB in dispatch order, which the program runs before anything
+    else."""
+    big = [float(r["Counter_Value"]) for r in _rows(path, counter)
+           if "copy" in r["Kernel_Name"].lower() and float(r["Counter_Value"]) > 65536.0]
+    if len(big) < CALIBRATION_COPIES:
+        raise RuntimeError("calibration copies not found")
+    return sum(big[:CALIBRATION_COPIES]) / CALIBRATION_COPIES
 
 
 def summarize(fetch_csv: str, write_csv: str) -> dict:
     fetch = per_kernel(fetch_csv, "FETCH_SIZE")
     write = per_kernel(write_csv, "WRITE_SIZE")
-    copy_f = [v for k, lst in fetch.items() if "copy" in k.lower() or "elementwise" in k.lower() for v in lst]
-    copy_w = [v for k, lst in write.items() if "copy" in k.lower() or "elementwise" in k.lower() for v in lst]
-    if not copy_f or not copy_w:
-        raise RuntimeError("no copy kernel found for calibration")
-    # the largest copy dispatches are the 1 GiB calibration copies
-    cf = sorted(copy_f)[-1] * 1024.0
-    cw = sorted(copy_w)[-1] * 1024.0
-    sf, sw = COPY_BYTES / cf, COPY_BYTES / cw
+    sf = COPY_BYTES / (calibration_kib(fetch_csv, "FETCH_SIZE") * 1024.0)
+    sw = COPY_BYTES / (calibration_kib(write_csv, "WRITE_SIZE") * 1024.0)
     out = {}
     for k in set(fetch) | set(write):
         if not k.startswith("k_"):

@@ -21,17 +21,30 @@ def test_short_names():
 
 def test_summary_scales_by_the_copy(tmp_path):
     gib_kib = float(1 << 20)
-    # the counters read the 1 GiB copy as 0.5 GiB fetched and 2 GiB written: scales 2 and 1/2
-    fetch = [("__amd_rocclr_copyBuffer", gib_kib / 2), ("void (anonymous namespace)::k_coupling(int)", 1000.0),
-             ("void (anonymous namespace)::k_coupling(int)", 3000.0)]
-    write = [("__amd_rocclr_copyBuffer", 2 * gib_kib), ("void (anonymous namespace)::k_coupling(int)", 400.0),
-             ("void (anonymous namespace)::k_coupling(int)", 400.0)]
+    cal = traffic.CALIBRATION_COPIES
+    # the counters read each 1 GiB calibration copy as 0.5 GiB fetched and 2 GiB written
+    # (scales 2 and 1/2); later, larger copies of the same program must not be taken for it
+    fetch = [("__amd_rocclr_copyBuffer", gib_kib / 2)] * cal + [
+        ("__amd_rocclr_copyBuffer", 8.0), ("void (anonymous namespace)::k_coupling(int)", 1000.0),
+        ("void (anonymous namespace)::k_coupling(int)", 3000.0), ("__amd_rocclr_copyBuffer", 4 * gib_kib)]
+    write = [("__amd_rocclr_copyBuffer", 2 * gib_kib)] * cal + [
+        ("__amd_rocclr_copyBuffer", 8.0), ("void (anonymous namespace)::k_coupling(int)", 400.0),
+        ("void (anonymous namespace)::k_coupling(int)", 400.0), ("__amd_rocclr_copyBuffer", 16 * gib_kib)]
     fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
     _write(fp, "FETCH_SIZE", fetch)
     _write(wp, "WRITE_SIZE", write)
     s = traffic.summarize(str(fp), str(wp))
+    assert abs(s["copy_fetch_scale"] - 2.0) < 1e-12 and abs(s["copy_write_scale"] - 0.5) < 1e-12
     k = s["kernels"]["k_coupling"]
     assert k["dispatches"] == 2
     assert abs(k["fetch_bytes"] - 2000.0 * 1024 * 2) < 1e-6
     assert abs(k["write_bytes"] - 400.0 * 1024 / 2) < 1e-6
     assert "__amd_rocclr_copyBuffer" not in s["kernels"]
+
+
+def test_missing_calibration_is_an_error(tmp_path):
+    import pytest
+    fp = tmp_path / "f.csv"
+    _write(fp, "FETCH_SIZE", [("void (anonymous namespace)::k_coupling(int)", 1000.0)])
+    with pytest.raises(RuntimeError):
+        traffic.summarize(str(fp), str(fp))
