@@ -13,6 +13,9 @@ uh_mvp_rows   the same sum restricted to a set of rows (for operators too large 
               uh_mvp to finish quickly; the rows are computed one block at a time).
 h_mvp         y = sum_{b in P+} X_b Y_b^* x|_sigma + sum_{b in P-} A|_b x|_sigma
                                                                     (Definition 2.3)
+expand_symmetric
+              the general image that a symmetric-storage image stands for (Remark 4.4):
+              every stored off-diagonal block also gives its mirror, as a transpose.
 alg6, alg5    the C implementations of Algorithms 6 and 5 (section 4.4), through ctypes.
 optimal_row_basis
               Algorithm 1: the leading left singular vectors of the explicit
@@ -113,6 +116,56 @@ def h_mvp(op: Mapping, x: np.ndarray) -> np.ndarray:
         Db = _colmajor(op["D"], int(op["D_off"][b]), int(op["size"][t]), int(op["size"][s]))
         y[_rows_of(op, t)] += Db @ x2[_rows_of(op, s)]
     return y.reshape(np.shape(x))
+
+
+def expand_symmetric(op: Mapping) -> dict:
+    """The general UH image that a symmetric-storage image stands for (Remark 4.4).
+
+    A symmetric-storage image has one cluster set with one basis per cluster and lists one
+    block of each mirrored pair tau x sigma / sigma x tau (diagonal dense blocks once).
+    With V_sigma = conj(U_sigma) the transpose of a stored admissible block is
+    (U_tau S_b V_sigma^*)^T = conj(V_sigma) S_b^T U_tau^T = U_sigma S_b^T V_tau^*, so its mirror
+    has coupling S_b^T; the mirror of a stored dense block tau x sigma, tau != sigma, is
+    (A|_b)^T.  The V, V_off and rank_col entries of the input are not read.  Returns the
+    stored blocks followed by their mirrors, with new flat S and D arrays,
+    rank_col = rank_row, V = conj(U) and V_off = U_off (the H-form entries are dropped)."""
+    out = {k: v for k, v in op.items() if k not in ("adm_rank", "X_off", "Y_off", "X", "Y")}
+    rank, size = np.asarray(op["rank_row"]), np.asarray(op["size"])
+    out["rank_col"] = rank.copy()
+    out["V"] = np.conj(op["U"])
+    out["V_off"] = np.asarray(op["U_off"]).copy()
+    ar, ac = np.asarray(op["adm_row"]), np.asarray(op["adm_col"])
+    if np.any(ar == ac):
+        raise ValueError("a cluster is admissible with itself")
+    rows, cols, blocks = [], [], []
+    for b in range(ar.size):
+        t, s = int(ar[b]), int(ac[b])
+        Sb = _colmajor(op["S"], int(op["S_off"][b]), int(rank[t]), int(rank[s]))
+        rows.append(t), cols.append(s), blocks.append(Sb)
+    for b in range(ar.size):
+        rows.append(int(ac[b])), cols.append(int(ar[b])), blocks.append(blocks[b].T)
+    out["adm_row"], out["adm_col"] = np.array(rows, np.int32), np.array(cols, np.int32)
+    out["S_off"], out["S"] = _pack(blocks)
+    dr, dc = np.asarray(op["den_row"]), np.asarray(op["den_col"])
+    rows, cols, blocks = [], [], []
+    for b in range(dr.size):
+        t, s = int(dr[b]), int(dc[b])
+        rows.append(t), cols.append(s)
+        blocks.append(_colmajor(op["D"], int(op["D_off"][b]), int(size[t]), int(size[s])))
+    for b in range(dr.size):
+        if dr[b] != dc[b]:
+            rows.append(int(dc[b])), cols.append(int(dr[b])), blocks.append(blocks[b].T)
+    out["den_row"], out["den_col"] = np.array(rows, np.int32), np.array(cols, np.int32)
+    out["D_off"], out["D"] = _pack(blocks)
+    return out
+
+
+def _pack(blocks):
+    offs = np.zeros(len(blocks), np.int64)
+    if blocks:
+        offs[1:] = np.cumsum([m.size for m in blocks])[:-1]
+    flat = np.concatenate([m.ravel(order="F") for m in blocks]) if blocks else np.zeros(0, np.complex128)
+    return offs, flat
 
 
 def assemble_uh(op: Mapping) -> np.ndarray:

@@ -493,6 +493,25 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
         sv_dropped=sv_dropped, sv_tail=sv_tail, timings=tim)
 
 
+def symmetric_image(op: HostOperator) -> dict:
+    """The symmetric-storage image of an operator (Remark 4.4, as in section 6.1): one block
+    of each mirrored pair, the one whose row cluster has the smaller index, and every
+    diagonal dense block.  The flat arrays are shared with ``op`` (the blocks left out are
+    simply not listed); V_sigma = conj(U_sigma) and the mirrors are implied, so an upload
+    with symmetric storage reads only U, the listed couplings and the listed dense blocks."""
+    d = {k: getattr(op, k) for k in ("n", "perm", "off", "size", "level", "parent", "rank_row", "rank_col",
+                                     "U_off", "V_off", "U", "V", "S", "D", "kappa", "h", "leaf", "eta",
+                                     "eps_aca", "eps_comp", "depth")}
+    ka = op.adm_row < op.adm_col
+    kd = op.den_row <= op.den_col
+    d.update(adm_row=op.adm_row[ka], adm_col=op.adm_col[ka], S_off=op.S_off[ka],
+             den_row=op.den_row[kd], den_col=op.den_col[kd], D_off=op.D_off[kd])
+    rs = op.rank_row.astype(np.int64)
+    d["elems_S_stored"] = int(np.sum(rs[d["adm_row"]] * rs[d["adm_col"]]))
+    d["elems_D_stored"] = int(np.sum(op.size[d["den_row"]] * op.size[d["den_col"]]))
+    return d
+
+
 def save_operator(op: HostOperator, path: str) -> None:
     arrays = {k: v for k, v in op.__dict__.items() if isinstance(v, np.ndarray)}
     scalars = {k: v for k, v in op.__dict__.items() if isinstance(v, (int, float)) and not isinstance(v, bool)}
