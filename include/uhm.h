@@ -54,8 +54,15 @@ typedef enum {
   UHM_C128 = 0,      /* complex128 storage and arithmetic; vectors complex128 */
   UHM_C64 = 1,       /* complex64 storage, FP32 accumulation; vectors complex64 */
   UHM_BF16PAIR = 2,  /* (re, im) bfloat16 pairs, FP32 accumulation; vectors complex64 */
-  UHM_C128_MULTI = 3 /* complex128 storage and arithmetic laid out for many right-hand sides
-                        (FP64 MFMA, up to 64 per pass); vectors complex128 */
+  UHM_C128_MULTI = 3, /* complex128 storage and arithmetic laid out for many right-hand sides
+                         (FP64 MFMA, up to 64 per pass); vectors complex128 */
+  UHM_C128_SYM = 4    /* complex128, symmetric storage (Remark 4.4): for a complex-symmetric
+                         A = A^T on one cluster tree.  The image lists one block of each mirrored
+                         pair tau x sigma / sigma x tau (diagonal dense blocks once); the mirror
+                         of a stored admissible block is U_sigma S_b^T U_tau^T and that of a
+                         stored dense block A|_b^T, with V_c = conj(U_c) implied: V, V_off and
+                         rank_col are not read.  Each stored element is read once per product
+                         and applied both ways.  uhm_upload only; vectors complex128 */
 } uhm_storage;
 
 typedef struct uhm_op uhm_op; /* opaque; owned by the library until uhm_free */
@@ -136,6 +143,9 @@ typedef struct {
   int64_t elems_near;        /* sum_b n_tau n_sigma over P- */
   int64_t rank_space;        /* sum l_sigma (UH) or sum k_b (H): length of the rank-space vectors */
   int64_t device_bytes;      /* device memory held by the operator, workspace excluded */
+  int64_t partial_coupling;  /* UHM_C128_SYM: partial sums the transposed coupling products write per
+                                right-hand side (complex elements); 0 for the other forms */
+  int64_t partial_near;      /* UHM_C128_SYM: the same for the transposed dense blocks */
 } uhm_op_info;
 
 /*
@@ -192,7 +202,7 @@ typedef struct {
  * pass (Daniel, Gragg, Kaufman and Stewart), FP64 Krylov vectors, Givens least-squares),
  * for nrhs right-hand sides at once, each with its own Krylov space.  X starts at zero
  * and is overwritten.
- *   op:    the operator A, UHM_C128 or UHM_C128_MULTI storage (the true-residual operator).
+ *   op:    the operator A, UHM_C128, UHM_C128_MULTI or UHM_C128_SYM storage (the true-residual operator).
  *   inner: NULL for plain GMRES on op; otherwise an operator of the same matrix in
  *          complex64 or bf16-pair storage, and the solve is mixed-precision iterative
  *          refinement: r = B - A X with op (FP64), an inner GMRES(m) solves

@@ -15,8 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libuhm.so")
 
 UHM_OK, UHM_EINVAL, UHM_ENOMEM, UHM_EHIP, UHM_ENOCONV, UHM_ENOTSUP = 0, -1, -2, -3, -4, -5
-STORAGE = {"c128": 0, "c64": 1, "bf16pair": 2, "c128multi": 3}
-C128_FORMS = ("c128", "c128multi")
+STORAGE = {"c128": 0, "c64": 1, "bf16pair": 2, "c128multi": 3, "c128sym": 4}
+C128_FORMS = ("c128", "c128multi", "c128sym")
 
 P = ctypes.c_void_p
 I64 = ctypes.c_int64
@@ -41,7 +41,8 @@ class HostHMatrix(ctypes.Structure):
 class OpInfo(ctypes.Structure):
     _fields_ = [("n", I64), ("kind", I32), ("storage", I32), ("nleaves", I32), ("elem_bytes", I32),
                 ("nadm", I64), ("nden", I64), ("elems_forward", I64), ("elems_coupling", I64),
-                ("elems_backward", I64), ("elems_near", I64), ("rank_space", I64), ("device_bytes", I64)]
+                ("elems_backward", I64), ("elems_near", I64), ("rank_space", I64), ("device_bytes", I64),
+                ("partial_coupling", I64), ("partial_near", I64)]
 
 
 class GmresOpts(ctypes.Structure):
@@ -201,7 +202,7 @@ class DeviceOperator:
         _check(load_library().uhm_set_timing(self._h, int(bool(enabled))), "uhm_set_timing")
 
     def kernel_times(self) -> dict:
-        cap = 16
+        cap = 32
         names = (ctypes.c_char_p * cap)()
         ms = (ctypes.c_double * cap)()
         cnt = (I64 * cap)()

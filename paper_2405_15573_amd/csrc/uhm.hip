@@ -35,7 +35,7 @@ thread_local std::string g_err;
 const char* const kKernelNames[K_COUNT] = {
     "k_forward", "k_reduce_segments", "k_coupling", "k_reduce_coupling", "k_backward",
     "k_lp_gather", "k_lp_forward", "k_lp_reduce_segments", "k_lp_coupling", "k_lp_reduce_coupling",
-    "k_lp_backward", "k_lp_scatter"};
+    "k_lp_backward", "k_lp_scatter", "k_coupling_sym", "k_reduce_sym", "k_backward_sym", "k_finish_sym"};
 
 int check_tree(int64_t n, const int64_t* perm, int32_t nc, const int64_t* off, const int64_t* size,
                const int32_t* parent, TreeInfo& T) {
@@ -374,6 +374,249 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_backward(
   }
 }
 
+// ------------------------------------------------------------------ symmetric storage
+//
+// Remark 4.4: rows and columns share one cluster set, V_sigma = conj(U_sigma), and only one
+// block b = tau x sigma of each mirrored pair is stored; its mirror is applied as
+// U_sigma S_b^T U_tau^T (admissible) or A|_b^T (dense).  Each stored element is read once
+// and used twice: for the direct product (one lane per row, as above) and for the
+// transposed one, whose column sums run across the 64 lanes of the wave.
+
+__device__ __forceinline__ cd cmul(cd a, cd b) {
+  return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+
+// x + y after swapping lanes 32-63 of x with lanes 0-31 of y (v_permlane32_swap): lanes
+// 0-31 get x_L + x_{L+32}, lanes 32-63 get y_{L-32} + y_L.
+__device__ __forceinline__ double swap32_add(double x, double y) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+// The same with the odd 16-lane rows of x and the even rows of y (v_permlane16_swap):
+// rows 0 and 2 get x_L + x_{L+16}, rows 1 and 3 get y_{L-16} + y_L.
+__device__ __forceinline__ double swap16_add(double x, double y) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+// A DPP lane move within 16-lane rows (CTRL: 0x11n = from lane L - n, 0x12n = from lane
+// (L + n) mod 16 of the row); lanes whose source lies outside the row get 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Column sums of eight columns at once, all 64 lanes taking part.  p[k] is this lane's
+// term of column k.  Three exchange steps halve the number of values per lane (lanes
+// 0-31 keep columns 0-3 and 32-63 columns 4-7, then the 16-lane rows, then the 8-lane
+// halves of a row), each adding the partner lane's terms of the kept columns; three
+// shifted adds then sum the eight lanes that hold one column.  On return, lane L with
+// (L & 7) == 7 holds the sum of column L >> 3.  Lane moves only (no LDS); the order of the
+// additions is fixed, so the sums do not change from run to run.
+__device__ __forceinline__ cd wave_colsum8(const cd (&p)[8], int lane) {
+  cd q[4], r[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) q[i] = make_double2(swap32_add(p[i].x, p[i + 4].x), swap32_add(p[i].y, p[i + 4].y));
+#pragma unroll
+  for (int i = 0; i < 2; ++i) r[i] = make_double2(swap16_add(q[i].x, q[i + 2].x), swap16_add(q[i].y, q[i + 2].y));
+  const bool b3 = lane & 8;
+  const cd keep = b3 ? r[1] : r[0], send = b3 ? r[0] : r[1];
+  cd v = make_double2(keep.x + dpp_move<0x128>(send.x), keep.y + dpp_move<0x128>(send.y));  // row_ror:8 = lane ^ 8
+  v = make_double2(v.x + dpp_move<0x111>(v.x), v.y + dpp_move<0x111>(v.y));                // row_shr:1
+  v = make_double2(v.x + dpp_move<0x112>(v.x), v.y + dpp_move<0x112>(v.y));                // row_shr:2
+  return make_double2(v.x + dpp_move<0x114>(v.x), v.y + dpp_move<0x114>(v.y));             // row_shr:4
+}
+
+// Direct:     part[tile][r]     = sum_c S_chunk[r, c] xh[csrc[c]]   (S_b u_sigma)
+// Transposed: tpart[t_base + c] = sum_r S_chunk[r, c] xh[x_row + r] (S_b^T u_tau, this chunk's rows)
+__global__ __launch_bounds__(64 * kCoupWaves) void k_coupling_sym(
+    const cd* __restrict__ S, const SymTile* __restrict__ tiles, int32_t ntiles, const int32_t* __restrict__ csrc,
+    const cd* __restrict__ xh, cd* __restrict__ part, cd* __restrict__ tpart) {
+  const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * kCoupWaves + (threadIdx.x >> 6));
+  if (tile >= ntiles) return;
+  const int lane = threadIdx.x & 63;
+  const SymTile T = tiles[tile];
+  const int h = T.h;
+  const bool act = lane < h;
+  // lanes past the chunk read row 0 and weigh it by zero
+  const cd xt = act ? xh[T.x_row + lane] : make_double2(0.0, 0.0);
+  const cd* col = S + T.s_base + (act ? lane : 0);
+  const int32_t* cs = csrc + T.c_base;
+  cd* tp = tpart + T.t_base;
+  double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+  const int nc = T.ncols;
+  // groups of 8 columns, the next group's loads issued before this group's arithmetic;
+  // the last group may run past the tile: the S array and the column-source table carry
+  // slack for it, and the extra columns get a zero weight
+  cd sv[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sv[k] = stream_load(&col[(int64_t)k * h]);
+  for (int q = 0; q < nc; q += 8) {
+    const int rem = nc - q;
+    cd xv[8], nx[8];
+    if (q + 8 < nc) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) nx[k] = stream_load(&col[(int64_t)(q + 8 + k) * h]);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const cd v = xh[cs[q + k]];
+      xv[k] = k < rem ? v : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+      re0 = fma(sv[k].x, xv[k].x, fma(-sv[k].y, xv[k].y, re0));
+      im0 = fma(sv[k].x, xv[k].y, fma(sv[k].y, xv[k].x, im0));
+      re1 = fma(sv[k + 1].x, xv[k + 1].x, fma(-sv[k + 1].y, xv[k + 1].y, re1));
+      im1 = fma(sv[k + 1].x, xv[k + 1].y, fma(sv[k + 1].y, xv[k + 1].x, im1));
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sv[k] = cmul(sv[k], xt);
+    const cd t = wave_colsum8(sv, lane);
+    if ((lane & 7) == 7 && (lane >> 3) < rem) tp[q + (lane >> 3)] = t;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sv[k] = nx[k];
+  }
+  if (act) part[(int64_t)tile * kRowChunk + lane] = make_double2(re0 + re1, im0 + im1);
+}
+
+// yh[e] = (direct tiles of e's row chunk, in column order) + (transposed partials of the
+// mirrored blocks, in table order).
+__global__ __launch_bounds__(256) void k_reduce_sym(
+    const cd* __restrict__ part, const cd* __restrict__ tpart, const int32_t* __restrict__ yh_grp,
+    const int64_t* __restrict__ grp_start, const int32_t* __restrict__ grp_t0, const int32_t* __restrict__ grp_nt,
+    const int32_t* __restrict__ grp_s0, const int32_t* __restrict__ grp_ns, const int64_t* __restrict__ tsrc,
+    int64_t nout, cd* __restrict__ yh) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nout) return;
+  const int g = yh_grp[e];
+  const int r = (int)(e - grp_start[g]);
+  const int t0 = grp_t0[g], nt = grp_nt[g], s0 = grp_s0[g], ns = grp_ns[g];
+  double re = 0.0, im = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    const cd v = part[(int64_t)(t0 + t) * kRowChunk + r];
+    re += v.x;
+    im += v.y;
+  }
+  int k = 0;
+  for (; k + 4 <= ns; k += 4) {
+    cd v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = tpart[tsrc[s0 + k + j] + r];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      re += v[j].x;
+      im += v[j].y;
+    }
+  }
+  for (; k < ns; ++k) {
+    const cd v = tpart[tsrc[s0 + k] + r];
+    re += v.x;
+    im += v.y;
+  }
+  yh[e] = make_double2(re, im);
+}
+
+// As k_backward, and for the panel columns c >= tcol (stored off-diagonal dense blocks
+// A|_b, b = lambda' x sigma with lambda inside lambda') also the column sums
+// td[td_off + c - tcol] = sum_i B[i, c] v_i over the leaf's rows i: lambda's share of
+// (A|_b^T v|_lambda').
+__global__ __launch_bounds__(64 * kBwdWaves) void k_backward_sym(
+    const cd* __restrict__ B, const int64_t* __restrict__ bwd_off, const int32_t* __restrict__ bwd_cols,
+    const int32_t* __restrict__ bwd_tcol, const int64_t* __restrict__ td_off, const int64_t* __restrict__ zoff,
+    const int32_t* __restrict__ zmap, const int32_t* __restrict__ leaf_pos, const int32_t* __restrict__ leaf_n,
+    const int32_t* __restrict__ perm, const cd* __restrict__ yh, const cd* __restrict__ x, cd* __restrict__ y,
+    cd* __restrict__ td, int nleaves) {
+  const int leaf = xcd_remap(blockIdx.x, nleaves);
+  const int K = bwd_cols[leaf], n = leaf_n[leaf], tc = bwd_tcol[leaf];
+  __shared__ cd zs[kBwdChunk];
+  __shared__ cd red[kBwdWaves][kLeafMax];
+  // the wave index is uniform over the wave: the column loop then branches on scalars
+  const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const cd* Bl = B + bwd_off[leaf];
+  const int32_t* zm = zmap + zoff[leaf];
+  cd* tdl = td + td_off[leaf];
+  const bool act = lane < n;
+  const cd xr = act ? x[perm[leaf_pos[leaf] + lane]] : make_double2(0.0, 0.0);
+  double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+  for (int c0 = 0; c0 < K; c0 += kBwdChunk) {
+    const int cn = min(kBwdChunk, K - c0);
+    __syncthreads();
+    // z of this chunk, then zeros up to the next multiple of 8 columns
+    for (int c = t; c < ((cn + 7) & ~7); c += 64 * kBwdWaves) {
+      if (c < cn) {
+        const int m = zm[c0 + c];
+        zs[c] = m >= 0 ? yh[m] : x[-1 - m];
+      } else {
+        zs[c] = make_double2(0.0, 0.0);
+      }
+    }
+    __syncthreads();
+    // groups of 8 columns dealt round-robin to the waves; the last group of the chunk
+    // may run past it (into the next chunk, or the slack after the last panel), where
+    // the zero z entries take the extra columns out of the direct product
+    for (int c = 8 * w; c < cn; c += 8 * kBwdWaves) {
+      const cd* col = Bl + (int64_t)(c0 + c) * n + (act ? lane : 0);
+      cd bv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) bv[k] = stream_load(&col[k * n]);
+#pragma unroll
+      for (int k = 0; k < 8; k += 2) {
+        const cd z0 = zs[c + k], z1 = zs[c + k + 1];
+        re0 = fma(bv[k].x, z0.x, fma(-bv[k].y, z0.y, re0));
+        im0 = fma(bv[k].x, z0.y, fma(bv[k].y, z0.x, im0));
+        re1 = fma(bv[k + 1].x, z1.x, fma(-bv[k + 1].y, z1.y, re1));
+        im1 = fma(bv[k + 1].x, z1.y, fma(bv[k + 1].y, z1.x, im1));
+      }
+      const int g = c0 + c;  // panel column of bv[0]
+      if (g + 8 > tc) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const cd xk = g + k >= tc ? xr : make_double2(0.0, 0.0);
+          bv[k] = cmul(bv[k], xk);
+        }
+        const cd s = wave_colsum8(bv, lane);
+        const int kk = lane >> 3;
+        if ((lane & 7) == 7 && c + kk < cn && g + kk >= tc) tdl[g + kk - tc] = s;
+      }
+    }
+  }
+  red[w][lane] = make_double2(re0 + re1, im0 + im1);
+  __syncthreads();
+  if (w == 0 && act) {
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q < kBwdWaves; ++q) {
+      sr += red[q][lane].x;
+      si += red[q][lane].y;
+    }
+    y[perm[leaf_pos[leaf] + lane]] = make_double2(sr, si);
+  }
+}
+
+// w|_mu += sum of the transposed dense partials addressed to leaf mu, in table order.
+__global__ __launch_bounds__(64) void k_finish_sym(
+    const int32_t* __restrict__ fin_off, const int32_t* __restrict__ fin_cnt, const int64_t* __restrict__ fsrc,
+    const int32_t* __restrict__ leaf_pos, const int32_t* __restrict__ leaf_n, const int32_t* __restrict__ perm,
+    const cd* __restrict__ td, cd* __restrict__ y) {
+  const int leaf = blockIdx.x, lane = threadIdx.x;
+  const int cnt = fin_cnt[leaf];
+  if (cnt == 0 || lane >= leaf_n[leaf]) return;
+  const int64_t* src = fsrc + fin_off[leaf];
+  const int idx = perm[leaf_pos[leaf] + lane];
+  cd acc = y[idx];
+  for (int k = 0; k < cnt; ++k) {
+    const cd v = td[src[k] + lane];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  y[idx] = acc;
+}
+
 // ------------------------------------------------------------------ host structures
 
 // A column source of a forward or backward panel: `len` columns of a column-major
@@ -385,6 +628,7 @@ struct PanelSeg {
   int32_t len;
   int32_t zbase;  // backward: rank-space index of the first column, or -1 for dense
   const int64_t* dense_cols;  // backward dense: perm + off[sigma]
+  bool conj = false;          // forward: store the complex conjugate
 };
 
 // Forward panel of one leaf: tile-major, tiles of 64 columns, each row-major.
@@ -400,7 +644,10 @@ int stage_forward_leaf(Stager& st, const std::vector<PanelSeg>& segs, int32_t C,
     for (int32_t c = 0; c < wj; ++c) {
       const PanelSeg& sg = segs[cmap[j0 + c].first];
       const cd* colp = sg.src + (int64_t)cmap[j0 + c].second * sg.nrows + sg.row0;
-      for (int32_t i = 0; i < n; ++i) tile[(int64_t)i * wj + c] = colp[i];
+      if (sg.conj)
+        for (int32_t i = 0; i < n; ++i) tile[(int64_t)i * wj + c] = make_double2(colp[i].x, -colp[i].y);
+      else
+        for (int32_t i = 0; i < n; ++i) tile[(int64_t)i * wj + c] = colp[i];
     }
   }
   return st.err;
@@ -442,6 +689,65 @@ int upload_segments(uhm_op* op, const std::vector<SegDesc>& segs, int64_t nout, 
   return UHM_OK;
 }
 
+struct FwdLayout {
+  int64_t ftot = 0, ptot = 0;
+  std::vector<int64_t> fwd_off, poff;
+  std::vector<int32_t> fwd_cols;
+  std::vector<SegDesc> segs;
+};
+
+// Forward panels of the bases W_c (size[c] x rank[c] at W + W_off[c], conjugated on the
+// way if `conj`) of every cluster with rank[c] > 0, and the segment tables that add the
+// per-leaf partial sums into u_c = W_c^* v|_c at xh_off[c].
+int build_forward(uhm_op* op, const TreeInfo& T, const int64_t* off, const int64_t* size, const int32_t* rank,
+                  const cd* W, const int64_t* W_off, bool conj, const std::vector<int64_t>& xh_off, int64_t nxh,
+                  hipStream_t s, FwdLayout& L) {
+  const int32_t nl = (int32_t)T.leaves.size(), nc = T.nc;
+  L.fwd_off.assign(nl, 0);
+  L.poff.assign(nl, 0);
+  L.fwd_cols.assign(nl, 0);
+  std::vector<int32_t> seg_col_of(nc, -1);  // column of cluster c's segment in its leaves' panels
+  int64_t ftot = 0, ptot = 0;
+  for (int32_t i = 0; i < nl; ++i) {
+    int32_t C = 0;
+    for (int32_t a : T.anc[i])
+      if (rank[a] > 0) {
+        if (seg_col_of[a] < 0) seg_col_of[a] = C;
+        C += rank[a];
+      }
+    L.fwd_cols[i] = C;
+    L.fwd_off[i] = ftot;
+    L.poff[i] = ptot;
+    ftot += (int64_t)C * size[T.leaves[i]];
+    ptot += C;
+  }
+  int rc;
+  if ((rc = op->F.alloc(ftot))) return rc;
+  {
+    Stager st;
+    if ((rc = st.init(op->F.p, ftot, s))) return rc;
+    std::vector<PanelSeg> segs;
+    for (int32_t i = 0; i < nl && !st.err; ++i) {
+      const int32_t lf = T.leaves[i];
+      segs.clear();
+      for (int32_t a : T.anc[i])
+        if (rank[a] > 0) segs.push_back({W + W_off[a], size[a], off[lf] - off[a], rank[a], -1, nullptr, conj});
+      if ((rc = stage_forward_leaf(st, segs, L.fwd_cols[i], (int32_t)size[lf]))) return rc;
+    }
+    if ((rc = st.finish())) return rc;
+  }
+  if ((rc = op->fwd_off.upload(L.fwd_off, s)) || (rc = op->fwd_cols.upload(L.fwd_cols, s)) ||
+      (rc = op->poff.upload(L.poff, s)))
+    return rc;
+  op->p_len = ptot;
+  L.ftot = ftot;
+  L.ptot = ptot;
+  L.segs.clear();
+  for (int32_t c = 0; c < nc; ++c)
+    if (rank[c] > 0) L.segs.push_back({xh_off[c], rank[c], T.leaf_first[c], T.leaf_cnt[c], seg_col_of[c]});
+  return upload_segments(op, L.segs, nxh, s);
+}
+
 
 int grow_workspace(uhm_op* op) {
   // single-RHS workspace; columns are processed one at a time
@@ -452,6 +758,10 @@ int grow_workspace(uhm_op* op) {
     if (op->ws_part.n < (int64_t)op->nctiles * kRowChunk && (rc = op->ws_part.alloc((int64_t)op->nctiles * kRowChunk)))
       return rc;
     if (op->ws_yh.n < op->nyh && (rc = op->ws_yh.alloc(op->nyh))) return rc;
+  }
+  if (op->sym) {
+    if (op->ws_tpart.n < op->ttot && (rc = op->ws_tpart.alloc(op->ttot))) return rc;
+    if (op->ws_td.n < op->tdtot && (rc = op->ws_td.alloc(op->tdtot))) return rc;
   }
   return UHM_OK;
 }
@@ -516,6 +826,327 @@ int check_coupling(const std::vector<CoupTile>& tiles, const std::vector<int2>& 
   return UHM_OK;
 }
 
+
+// Elements of zeros after the symmetric form's couplings and backward panels: a group of
+// 8 columns that starts inside a tile (or panel range) may read 7 columns past its end.
+constexpr int64_t kSymSlack = 8 * kLeafMax;
+static_assert(kRowChunk <= kLeafMax, "slack covers 8 coupling columns too");
+
+// Index checks of the symmetric-storage tables, against the sizes of the arrays the
+// kernels touch (the couplings and panels have kSymSlack elements after stot and btot).
+int check_sym(const std::vector<SymTile>& tiles, int64_t stot, int64_t ttot, const std::vector<int32_t>& csrc,
+              int64_t nrs, const std::vector<int64_t>& grp_start, const std::vector<int32_t>& grp_t0,
+              const std::vector<int32_t>& grp_nt, const std::vector<int32_t>& grp_s0,
+              const std::vector<int32_t>& grp_ns, const std::vector<int64_t>& tsrc, const std::vector<int32_t>& leaf_n,
+              const std::vector<int32_t>& bwd_cols, const std::vector<int32_t>& bwd_tcol,
+              const std::vector<int64_t>& td_off, int64_t tdtot, const std::vector<int32_t>& fin_off,
+              const std::vector<int32_t>& fin_cnt, const std::vector<int64_t>& fsrc) {
+  for (const SymTile& T : tiles) {
+    if (T.h < 1 || T.h > kRowChunk || T.ncols < 1 || T.s_base < 0 || T.s_base + (int64_t)T.ncols * T.h > stot ||
+        T.t_base < 0 || T.t_base + T.ncols > ttot || T.c_base < 0 ||
+        (int64_t)T.c_base + T.ncols + 7 > (int64_t)csrc.size() ||
+        T.x_row < 0 || (int64_t)T.x_row + T.h > nrs)
+      return fail(UHM_EINVAL, "layout: symmetric coupling tile");
+  }
+  for (int32_t c : csrc)
+    if (c < 0 || c >= nrs) return fail(UHM_EINVAL, "layout: symmetric column source");
+  const size_t ng = grp_start.size();
+  std::vector<int32_t> gh(ng, 0);
+  for (size_t g = 0; g < ng; ++g) {
+    const int64_t end = g + 1 < ng ? grp_start[g + 1] : nrs;
+    gh[g] = (int32_t)(end - grp_start[g]);
+    if (grp_start[g] < 0 || gh[g] < 1 || gh[g] > kRowChunk || grp_nt[g] < 0 || grp_t0[g] < 0 ||
+        (size_t)grp_t0[g] + grp_nt[g] > tiles.size() || grp_ns[g] < 0 || grp_s0[g] < 0 ||
+        (size_t)grp_s0[g] + grp_ns[g] > tsrc.size())
+      return fail(UHM_EINVAL, "layout: symmetric group");
+    for (int32_t t = 0; t < grp_nt[g]; ++t)
+      if (tiles[grp_t0[g] + t].h < gh[g]) return fail(UHM_EINVAL, "layout: symmetric group rows");
+    for (int32_t k = 0; k < grp_ns[g]; ++k)
+      if (tsrc[grp_s0[g] + k] < 0 || tsrc[grp_s0[g] + k] + gh[g] > ttot)
+        return fail(UHM_EINVAL, "layout: symmetric transposed source");
+  }
+  const size_t nl = leaf_n.size();
+  for (size_t i = 0; i < nl; ++i) {
+    if (bwd_tcol[i] < 0 || bwd_tcol[i] > bwd_cols[i] || td_off[i] < 0 ||
+        td_off[i] + (bwd_cols[i] - bwd_tcol[i]) > tdtot)
+      return fail(UHM_EINVAL, "layout: symmetric near field");
+    if (fin_cnt[i] < 0 || fin_off[i] < 0 || (size_t)fin_off[i] + fin_cnt[i] > fsrc.size())
+      return fail(UHM_EINVAL, "layout: symmetric finish table");
+    for (int32_t k = 0; k < fin_cnt[i]; ++k)
+      if (fsrc[fin_off[i] + k] < 0 || fsrc[fin_off[i] + k] + leaf_n[i] > tdtot)
+        return fail(UHM_EINVAL, "layout: symmetric finish source");
+  }
+  return UHM_OK;
+}
+
+// Upload of the symmetric storage form (Remark 4.4).  The image lists one block of each
+// mirrored pair; U is the one cluster basis (V_c = conj(U_c) is implied and V, V_off and
+// rank_col are not read).
+int upload_sym(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, uhm_op* op) {
+  const int32_t nc = h->nclusters;
+  if (!h->rank_row || !h->U_off) return fail(UHM_EINVAL, "null basis arrays");
+  if ((h->nadm > 0 && (!h->adm_row || !h->adm_col || !h->S_off || !h->S)) ||
+      (h->nden > 0 && (!h->den_row || !h->den_col || !h->D_off || !h->D)) || h->nadm < 0 || h->nden < 0)
+    return fail(UHM_EINVAL, "null block arrays");
+  const int32_t* rank = h->rank_row;
+  for (int32_t c = 0; c < nc; ++c) {
+    if (rank[c] < 0 || rank[c] > h->size[c]) return fail(UHM_EINVAL, "cluster rank out of range");
+    if (rank[c] > 0 && (!h->U || !in_bounds(h->U_off[c], h->size[c] * rank[c], h->U_len)))
+      return fail(UHM_EINVAL, "U_off out of bounds");
+  }
+  std::vector<std::pair<int32_t, int32_t>> pairs;
+  for (int64_t b = 0; b < h->nadm; ++b) {
+    const int32_t t = h->adm_row[b], sg = h->adm_col[b];
+    if (t < 0 || t >= nc || sg < 0 || sg >= nc) return fail(UHM_EINVAL, "admissible block cluster out of range");
+    if (t == sg) return fail(UHM_EINVAL, "symmetric storage: a diagonal admissible block");
+    if (rank[t] < 1 || rank[sg] < 1) return fail(UHM_EINVAL, "admissible block without bases");
+    if (!in_bounds(h->S_off[b], (int64_t)rank[t] * rank[sg], h->S_len)) return fail(UHM_EINVAL, "S_off out of bounds");
+    pairs.push_back({std::min(t, sg), std::max(t, sg)});
+  }
+  std::sort(pairs.begin(), pairs.end());
+  if (std::adjacent_find(pairs.begin(), pairs.end()) != pairs.end())
+    return fail(UHM_EINVAL, "symmetric storage: a block and its mirror (or a block twice) are both listed");
+  pairs.clear();
+  for (int64_t b = 0; b < h->nden; ++b) {
+    const int32_t t = h->den_row[b], sg = h->den_col[b];
+    if (t < 0 || t >= nc || sg < 0 || sg >= nc) return fail(UHM_EINVAL, "dense block cluster out of range");
+    if (!in_bounds(h->D_off[b], h->size[t] * h->size[sg], h->D_len)) return fail(UHM_EINVAL, "D_off out of bounds");
+    pairs.push_back({std::min(t, sg), std::max(t, sg)});
+  }
+  std::sort(pairs.begin(), pairs.end());
+  if (std::adjacent_find(pairs.begin(), pairs.end()) != pairs.end())
+    return fail(UHM_EINVAL, "symmetric storage: a dense block and its mirror (or a block twice) are both listed");
+
+  const int32_t nl = op->nleaves;
+  const cd* U = reinterpret_cast<const cd*>(h->U);
+  const cd* Sh = reinterpret_cast<const cd*>(h->S);
+  const cd* D = reinterpret_cast<const cd*>(h->D);
+  int rc;
+
+  // ---- one rank-space vector: u_c (forward) and its coupling result share offsets
+  std::vector<int64_t> rs_off(nc, -1);
+  int64_t nrs = 0;
+  for (int32_t c = 0; c < nc; ++c)
+    if (rank[c] > 0) { rs_off[c] = nrs; nrs += rank[c]; }
+  if (nrs > INT32_MAX) return fail(UHM_ENOTSUP, "rank space too large");
+
+  // ---- forward: u_c = conj(U_c)^* v|_c = U_c^T v|_c
+  FwdLayout FL;
+  if ((rc = build_forward(op, T, h->off, h->size, rank, U, h->U_off, true, rs_off, nrs, s, FL))) return rc;
+
+  // ---- couplings of the stored blocks, by row cluster, in row chunks
+  std::vector<std::vector<int64_t>> rowblk(nc), colblk(nc);
+  for (int64_t b = 0; b < h->nadm; ++b) {
+    rowblk[h->adm_row[b]].push_back(b);
+    colblk[h->adm_col[b]].push_back(b);
+  }
+  std::vector<int32_t> colstart(h->nadm, 0);                    // first column of b in [S_b1 S_b2 ...]
+  std::vector<std::vector<int64_t>> chunk_tp(nc);               // transposed-partial base per row chunk
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> chunk_tiles(nc);  // (first tile, count) per chunk
+  std::vector<SymTile> tiles;
+  std::vector<int32_t> csrc;
+  int64_t stot = 0, ttot = 0;
+  for (int32_t t = 0; t < nc; ++t) {
+    if (rowblk[t].empty()) continue;
+    const int32_t lt = rank[t];
+    int64_t K = 0;
+    for (int64_t b : rowblk[t]) {
+      colstart[b] = (int32_t)K;
+      K += rank[h->adm_col[b]];
+    }
+    if (K > INT32_MAX || (int64_t)csrc.size() + K > INT32_MAX) return fail(UHM_ENOTSUP, "coupling row too wide");
+    const int32_t cs0 = (int32_t)csrc.size();
+    for (int64_t b : rowblk[t])
+      for (int32_t j = 0; j < rank[h->adm_col[b]]; ++j) csrc.push_back((int32_t)(rs_off[h->adm_col[b]] + j));
+    for (int32_t r0 = 0; r0 < lt; r0 += kRowChunk) {
+      const int32_t hh = std::min(kRowChunk, lt - r0);
+      chunk_tp[t].push_back(ttot);
+      const int32_t t0 = (int32_t)tiles.size();
+      for (int64_t c0 = 0; c0 < K; c0 += kCoupCols) {
+        const int32_t ncol = (int32_t)std::min<int64_t>(kCoupCols, K - c0);
+        tiles.push_back({stot + c0 * hh, ttot + c0, cs0 + (int32_t)c0, hh, ncol, (int32_t)(rs_off[t] + r0)});
+      }
+      chunk_tiles[t].push_back({t0, (int32_t)tiles.size() - t0});
+      stot += K * hh;
+      ttot += K;
+    }
+  }
+  if (tiles.size() > (size_t)INT32_MAX / kRowChunk) return fail(UHM_ENOTSUP, "too many coupling tiles");
+  // result groups: every cluster with a basis, in row chunks; direct tiles of its own
+  // stored blocks, then the transposed partials of the blocks stored on the mirror side
+  std::vector<int64_t> grp_start, tsrc;
+  std::vector<int32_t> grp_t0, grp_nt, grp_s0, grp_ns, yh_grp(nrs);
+  for (int32_t c = 0; c < nc; ++c) {
+    if (rank[c] < 1) continue;
+    for (int32_t r0 = 0, ci = 0; r0 < rank[c]; r0 += kRowChunk, ++ci) {
+      const int32_t hh = std::min(kRowChunk, rank[c] - r0);
+      const int32_t g = (int32_t)grp_start.size();
+      grp_start.push_back(rs_off[c] + r0);
+      if (!rowblk[c].empty()) {
+        grp_t0.push_back(chunk_tiles[c][ci].first);
+        grp_nt.push_back(chunk_tiles[c][ci].second);
+      } else {
+        grp_t0.push_back(0);
+        grp_nt.push_back(0);
+      }
+      if (tsrc.size() > (size_t)INT32_MAX) return fail(UHM_ENOTSUP, "transposed source table too large");
+      grp_s0.push_back((int32_t)tsrc.size());
+      for (int64_t b : colblk[c])
+        for (int64_t base : chunk_tp[h->adm_row[b]]) tsrc.push_back(base + colstart[b] + r0);
+      if (tsrc.size() - grp_s0.back() > (size_t)INT32_MAX) return fail(UHM_ENOTSUP, "transposed source table too large");
+      grp_ns.push_back((int32_t)(tsrc.size() - grp_s0.back()));
+      for (int32_t r = 0; r < hh; ++r) yh_grp[rs_off[c] + r0 + r] = g;
+    }
+  }
+  // slack after the couplings, the backward panels and the column-source table: the
+  // last 8-column group of a tile or panel range may read up to 7 columns past its end
+  if (!tiles.empty()) csrc.insert(csrc.end(), 8, 0);
+  if ((rc = op->S.alloc(stot + kSymSlack))) return rc;
+  UHM_HIP(hipMemsetAsync(op->S.p + stot, 0, sizeof(cd) * kSymSlack, s));
+  if (stot > 0) {
+    Stager st;
+    if ((rc = st.init(op->S.p, stot, s))) return rc;
+    for (int32_t t = 0; t < nc && !st.err; ++t) {
+      if (rowblk[t].empty()) continue;
+      const int32_t lt = rank[t];
+      for (int32_t r0 = 0; r0 < lt; r0 += kRowChunk) {
+        const int32_t hh = std::min(kRowChunk, lt - r0);
+        for (int64_t b : rowblk[t]) {
+          const int32_t ls = rank[h->adm_col[b]];
+          const cd* Sb = Sh + h->S_off[b];
+          for (int32_t j = 0; j < ls; ++j) {
+            cd* dst = st.span(hh);
+            std::memcpy(static_cast<void*>(dst), Sb + (int64_t)j * lt + r0, sizeof(cd) * (size_t)hh);
+          }
+        }
+      }
+    }
+    if ((rc = st.finish())) return rc;
+  }
+
+  // ---- backward panels: ancestor bases, diagonal dense blocks, then the stored
+  // off-diagonal dense blocks (also applied transposed)
+  std::vector<std::vector<int64_t>> dendiag(nc), denoff(nc);
+  for (int64_t b = 0; b < h->nden; ++b)
+    (h->den_row[b] == h->den_col[b] ? dendiag : denoff)[h->den_row[b]].push_back(b);
+  std::vector<int64_t> bwd_off(nl), zoff(nl), td_off(nl);
+  std::vector<int32_t> bwd_cols(nl), bwd_tcol(nl), leaf_n(nl);
+  int64_t btot = 0, ztot = 0, tdtot = 0;
+  for (int32_t i = 0; i < nl; ++i) {
+    int64_t K = 0;
+    for (int32_t a : T.anc[i]) {
+      K += rank[a];
+      for (int64_t b : dendiag[a]) K += h->size[h->den_col[b]];
+    }
+    const int64_t tc = K;
+    for (int32_t a : T.anc[i])
+      for (int64_t b : denoff[a]) K += h->size[h->den_col[b]];
+    if (K > INT32_MAX) return fail(UHM_ENOTSUP, "backward panel too wide");
+    leaf_n[i] = (int32_t)h->size[T.leaves[i]];
+    bwd_cols[i] = (int32_t)K;
+    bwd_tcol[i] = (int32_t)tc;
+    bwd_off[i] = btot;
+    zoff[i] = ztot;
+    td_off[i] = tdtot;
+    btot += K * leaf_n[i];
+    ztot += K;
+    tdtot += K - tc;
+  }
+  std::vector<int32_t> zmap(ztot);
+  std::vector<std::vector<int64_t>> fin(nl);  // per output leaf: transposed partials to add
+  if ((rc = op->B.alloc(btot + kSymSlack))) return rc;
+  UHM_HIP(hipMemsetAsync(op->B.p + btot, 0, sizeof(cd) * kSymSlack, s));
+  {
+    Stager st;
+    if ((rc = st.init(op->B.p, btot, s))) return rc;
+    std::vector<PanelSeg> segs;
+    for (int32_t i = 0; i < nl && !st.err; ++i) {
+      const int32_t lf = T.leaves[i];
+      segs.clear();
+      int64_t z = zoff[i];
+      auto dense = [&](int64_t b, int32_t a) {
+        const int32_t sg = h->den_col[b];
+        segs.push_back({D + h->D_off[b], h->size[a], h->off[lf] - h->off[a], (int32_t)h->size[sg], -1, nullptr});
+        for (int64_t j = 0; j < h->size[sg]; ++j) zmap[z++] = (int32_t)(-1 - h->perm[h->off[sg] + j]);
+      };
+      for (int32_t a : T.anc[i])
+        if (rank[a] > 0) {
+          segs.push_back({U + h->U_off[a], h->size[a], h->off[lf] - h->off[a], rank[a], 0, nullptr});
+          for (int32_t j = 0; j < rank[a]; ++j) zmap[z++] = (int32_t)(rs_off[a] + j);
+        }
+      for (int32_t a : T.anc[i])
+        for (int64_t b : dendiag[a]) dense(b, a);
+      for (int32_t a : T.anc[i])
+        for (int64_t b : denoff[a]) {
+          // column j of this block in leaf i's panel adds to row off[sg] + j; leaf mu of sg
+          // reads its rows from td_off[i] + (panel column - tcol) + off[mu] - off[sg]
+          const int32_t sg = h->den_col[b];
+          const int64_t base = td_off[i] + (z - zoff[i]) - bwd_tcol[i];
+          for (int32_t q = 0; q < T.leaf_cnt[sg]; ++q) {
+            const int32_t mu = T.leaf_first[sg] + q;
+            fin[mu].push_back(base + h->off[T.leaves[mu]] - h->off[sg]);
+          }
+          dense(b, a);
+        }
+      if ((rc = stage_backward_leaf(st, segs, (int32_t)h->size[lf]))) return rc;
+    }
+    if ((rc = st.finish())) return rc;
+  }
+  std::vector<int32_t> fin_off(nl), fin_cnt(nl);
+  std::vector<int64_t> fsrc;
+  for (int32_t i = 0; i < nl; ++i) {
+    if (fsrc.size() + fin[i].size() > (size_t)INT32_MAX) return fail(UHM_ENOTSUP, "finish table too large");
+    fin_off[i] = (int32_t)fsrc.size();
+    fin_cnt[i] = (int32_t)fin[i].size();
+    fsrc.insert(fsrc.end(), fin[i].begin(), fin[i].end());
+  }
+  {
+    LayoutView L{h->n, nl, FL.ftot, FL.ptot, btot, ztot, nrs, nrs, &leaf_n, &FL.fwd_off, &FL.fwd_cols, &FL.poff,
+                 &FL.segs, &bwd_off, &bwd_cols, &zoff, &zmap};
+    if ((rc = check_layout(L))) return rc;
+    if ((rc = check_sym(tiles, stot, ttot, csrc, nrs, grp_start, grp_t0, grp_nt, grp_s0, grp_ns, tsrc, leaf_n,
+                        bwd_cols, bwd_tcol, td_off, tdtot, fin_off, fin_cnt, fsrc)))
+      return rc;
+  }
+  if ((rc = op->stiles.upload(tiles, s)) || (rc = op->csrc.upload(csrc, s)) || (rc = op->yh_grp.upload(yh_grp, s)) ||
+      (rc = op->grp_start.upload(grp_start, s)) || (rc = op->grp_t0.upload(grp_t0, s)) ||
+      (rc = op->grp_nt.upload(grp_nt, s)) || (rc = op->grp_s0.upload(grp_s0, s)) ||
+      (rc = op->grp_ns.upload(grp_ns, s)) || (rc = op->tsrc.upload(tsrc, s)) ||
+      (rc = op->bwd_off.upload(bwd_off, s)) || (rc = op->bwd_cols.upload(bwd_cols, s)) ||
+      (rc = op->bwd_tcol.upload(bwd_tcol, s)) || (rc = op->td_off.upload(td_off, s)) ||
+      (rc = op->zoff.upload(zoff, s)) || (rc = op->zmap.upload(zmap, s)) || (rc = op->fin_off.upload(fin_off, s)) ||
+      (rc = op->fin_cnt.upload(fin_cnt, s)) || (rc = op->fsrc.upload(fsrc, s)))
+    return rc;
+  UHM_HIP(hipStreamSynchronize(s));
+  op->sym = true;
+  op->nctiles = (int32_t)tiles.size();
+  op->nyh = nrs;
+  op->ttot = ttot;
+  op->tdtot = tdtot;
+
+  uhm_op_info& I = op->info;
+  I.n = h->n;
+  I.kind = 0;
+  I.storage = UHM_C128_SYM;
+  I.nleaves = nl;
+  I.elem_bytes = 16;
+  I.nadm = h->nadm;
+  I.nden = h->nden;
+  I.elems_forward = I.elems_backward = 0;
+  for (int32_t c = 0; c < nc; ++c) I.elems_forward += h->size[c] * rank[c];
+  I.elems_backward = I.elems_forward;
+  I.elems_coupling = stot;
+  I.elems_near = 0;
+  for (int64_t b = 0; b < h->nden; ++b) I.elems_near += h->size[h->den_row[b]] * h->size[h->den_col[b]];
+  I.rank_space = nrs;
+  I.partial_coupling = ttot;
+  I.partial_near = tdtot;
+  I.device_bytes = (int64_t)(op->F.bytes() + op->S.bytes() + op->B.bytes() + op->zmap.bytes() + op->perm.bytes() +
+                             op->stiles.bytes() + op->csrc.bytes() + op->tsrc.bytes() + op->fsrc.bytes() +
+                             op->out_seg.bytes() + op->yh_grp.bytes());
+  return UHM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -539,13 +1170,24 @@ const char* uhm_last_error(void) { return g_err.c_str(); }
 int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream, uhm_op** out) {
   if (!h || !out) return fail(UHM_EINVAL, "null argument");
   *out = nullptr;
-  if (storage != UHM_C128 && storage != UHM_C64 && storage != UHM_BF16PAIR && storage != UHM_C128_MULTI)
+  if (storage != UHM_C128 && storage != UHM_C64 && storage != UHM_BF16PAIR && storage != UHM_C128_MULTI &&
+      storage != UHM_C128_SYM)
     return fail(UHM_EINVAL, "unknown storage precision");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   TreeInfo T;
   int rc = check_tree(h->n, h->perm, h->nclusters, h->off, h->size, h->parent, T);
   if (rc) return rc;
   const int32_t nc = h->nclusters;
+  if (storage == UHM_C128_SYM) {
+    std::unique_ptr<uhm_op> op(new (std::nothrow) uhm_op);
+    if (!op) return fail(UHM_ENOMEM, "host allocation");
+    op->kind = 0;
+    op->storage = storage;
+    if ((rc = common_tree_upload(op.get(), T, h->perm, h->off, h->size, s))) return rc;
+    if ((rc = upload_sym(h, s, T, op.get()))) return rc;
+    *out = op.release();
+    return UHM_OK;
+  }
   if (!h->rank_row || !h->rank_col || !h->U_off || !h->V_off) return fail(UHM_EINVAL, "null basis arrays");
   if ((h->nadm > 0 && (!h->adm_row || !h->adm_col || !h->S_off || !h->S)) ||
       (h->nden > 0 && (!h->den_row || !h->den_col || !h->D_off || !h->D)) || h->nadm < 0 || h->nden < 0)
@@ -596,48 +1238,8 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
   if (nxh > INT32_MAX || nyh > INT32_MAX) return fail(UHM_ENOTSUP, "rank space too large");
 
   // ---- forward panels
-  std::vector<int64_t> fwd_off(nl), poff(nl);
-  std::vector<int32_t> fwd_cols(nl);
-  std::vector<int32_t> seg_col_of(nc, -1);  // column of cluster sigma's segment in its leaves' panels
-  int64_t ftot = 0, ptot = 0;
-  for (int32_t i = 0; i < nl; ++i) {
-    int32_t C = 0;
-    for (int32_t a : T.anc[i])
-      if (h->rank_col[a] > 0) {
-        if (seg_col_of[a] < 0) seg_col_of[a] = C;
-        C += h->rank_col[a];
-      }
-    fwd_cols[i] = C;
-    fwd_off[i] = ftot;
-    poff[i] = ptot;
-    ftot += (int64_t)C * h->size[T.leaves[i]];
-    ptot += C;
-  }
-  if ((rc = op->F.alloc(ftot))) return rc;
-  {
-    Stager st;
-    if ((rc = st.init(op->F.p, ftot, s))) return rc;
-    std::vector<PanelSeg> segs;
-    for (int32_t i = 0; i < nl && !st.err; ++i) {
-      const int32_t lf = T.leaves[i];
-      segs.clear();
-      for (int32_t a : T.anc[i])
-        if (h->rank_col[a] > 0)
-          segs.push_back({V + h->V_off[a], h->size[a], h->off[lf] - h->off[a], h->rank_col[a], -1, nullptr});
-      if ((rc = stage_forward_leaf(st, segs, fwd_cols[i], (int32_t)h->size[lf]))) return rc;
-    }
-    if ((rc = st.finish())) return rc;
-  }
-  if ((rc = op->fwd_off.upload(fwd_off, s)) || (rc = op->fwd_cols.upload(fwd_cols, s)) ||
-      (rc = op->poff.upload(poff, s)))
-    return rc;
-  op->p_len = ptot;
-  {
-    std::vector<SegDesc> segs;
-    for (int32_t c = 0; c < nc; ++c)
-      if (h->rank_col[c] > 0) segs.push_back({xh_off[c], h->rank_col[c], T.leaf_first[c], T.leaf_cnt[c], seg_col_of[c]});
-    if ((rc = upload_segments(op.get(), segs, nxh, s))) return rc;
-  }
+  FwdLayout FL;
+  if ((rc = build_forward(op.get(), T, h->off, h->size, h->rank_col, V, h->V_off, false, xh_off, nxh, s, FL))) return rc;
 
   // ---- couplings, grouped by row cluster, in row chunks
   std::vector<std::vector<int64_t>> rowblk(nc);
@@ -759,10 +1361,7 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
   {
     std::vector<int32_t> leaf_n(nl);
     for (int32_t i = 0; i < nl; ++i) leaf_n[i] = (int32_t)h->size[T.leaves[i]];
-    std::vector<SegDesc> segs;
-    for (int32_t c = 0; c < nc; ++c)
-      if (h->rank_col[c] > 0) segs.push_back({xh_off[c], h->rank_col[c], T.leaf_first[c], T.leaf_cnt[c], seg_col_of[c]});
-    LayoutView L{h->n, nl, ftot, ptot, btot, ztot, nyh, nxh, &leaf_n, &fwd_off, &fwd_cols, &poff, &segs,
+    LayoutView L{h->n, nl, FL.ftot, FL.ptot, btot, ztot, nyh, nxh, &leaf_n, &FL.fwd_off, &FL.fwd_cols, &FL.poff, &FL.segs,
                  &bwd_off, &bwd_cols, &zoff, &zmap};
     if ((rc = check_layout(L))) return rc;
     if ((rc = check_coupling(tiles, cblk, stot, nxh, grp_t0, grp_nt, grp_start, nyh))) return rc;
@@ -973,7 +1572,8 @@ int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int
   if (ldx < op->n || ldy < op->n) return fail(UHM_EINVAL, "leading dimension smaller than n");
   const char* xb = static_cast<const char*>(X);
   const char* yb = static_cast<const char*>(Y);
-  const size_t es = (op->storage == UHM_C128 || op->storage == UHM_C128_MULTI) ? sizeof(cd) : sizeof(float2);
+  const size_t es =
+      (op->storage == UHM_C128 || op->storage == UHM_C128_MULTI || op->storage == UHM_C128_SYM) ? sizeof(cd) : sizeof(float2);
   if (xb < yb + (size_t)((nrhs - 1) * ldy + op->n) * es && yb < xb + (size_t)((nrhs - 1) * ldx + op->n) * es)
     return fail(UHM_EINVAL, "X and Y overlap");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -998,6 +1598,35 @@ int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int
       }
     }
     const cd* zsrc = op->ws_xh.p;
+    if (op->sym) {
+      if (op->nyh > 0) {
+        if (op->nctiles > 0) {
+          ScopedTiming tm(op, s, K_SYM_COUPLING);
+          hipLaunchKernelGGL(k_coupling_sym, dim3((unsigned)((op->nctiles + kCoupWaves - 1) / kCoupWaves)),
+                             dim3(64 * kCoupWaves), 0, s, op->S.p, op->stiles.p, op->nctiles, op->csrc.p,
+                             op->ws_xh.p, op->ws_part.p, op->ws_tpart.p);
+        }
+        {
+          ScopedTiming tm(op, s, K_SYM_REDUCE);
+          hipLaunchKernelGGL(k_reduce_sym, dim3((unsigned)((op->nyh + 255) / 256)), dim3(256), 0, s, op->ws_part.p,
+                             op->ws_tpart.p, op->yh_grp.p, op->grp_start.p, op->grp_t0.p, op->grp_nt.p, op->grp_s0.p,
+                             op->grp_ns.p, op->tsrc.p, op->nyh, op->ws_yh.p);
+        }
+        zsrc = op->ws_yh.p;
+      }
+      {
+        ScopedTiming tm(op, s, K_SYM_BACKWARD);
+        hipLaunchKernelGGL(k_backward_sym, dim3(nl), dim3(64 * kBwdWaves), 0, s, op->B.p, op->bwd_off.p,
+                           op->bwd_cols.p, op->bwd_tcol.p, op->td_off.p, op->zoff.p, op->zmap.p, op->leaf_pos.p,
+                           op->leaf_n.p, op->perm.p, zsrc, x, y, op->ws_td.p, nl);
+      }
+      if (op->tdtot > 0) {
+        ScopedTiming tm(op, s, K_SYM_FINISH);
+        hipLaunchKernelGGL(k_finish_sym, dim3(nl), dim3(64), 0, s, op->fin_off.p, op->fin_cnt.p, op->fsrc.p,
+                           op->leaf_pos.p, op->leaf_n.p, op->perm.p, op->ws_td.p, y);
+      }
+      continue;
+    }
     if (op->kind == 0 && op->nctiles > 0) {
       {
         ScopedTiming tm(op, s, K_COUPLING);

@@ -50,6 +50,18 @@ struct CoupTile {
   int32_t first_col;  // column within that block
 };
 
+// Coupling tile of the symmetric storage form: a column range of one row chunk of
+// [S_b1 S_b2 ...] (stored blocks of one row cluster), read once for S_b u_sigma and for
+// S_b^T u_tau.
+struct SymTile {
+  int64_t s_base;  // element offset of the tile's first column
+  int64_t t_base;  // transposed-partial index of the tile's first column
+  int32_t c_base;  // index into the column-source table of the tile's first column
+  int32_t h;       // rows in the chunk (<= 64)
+  int32_t ncols;   // columns in the tile
+  int32_t x_row;   // rank-space index of the chunk's first row
+};
+
 template <class T>
 struct DevArray {
   T* p = nullptr;
@@ -218,8 +230,15 @@ struct uhm_op {
   DevArray<cd> B;
   DevArray<int64_t> bwd_off, zoff;
   DevArray<int32_t> bwd_cols, zmap;
+  // symmetric storage (Remark 4.4): stored blocks applied as S_b and S_b^T, dense blocks
+  // as A|_b and A|_b^T; the transposed products go through partial buffers
+  bool sym = false;
+  DevArray<uhm_detail::SymTile> stiles;
+  DevArray<int32_t> csrc, grp_s0, grp_ns, bwd_tcol, fin_off, fin_cnt;
+  DevArray<int64_t> tsrc, td_off, fsrc;
+  int64_t ttot = 0, tdtot = 0;
   // workspace
-  DevArray<cd> ws_p, ws_xh, ws_part, ws_yh;
+  DevArray<cd> ws_p, ws_xh, ws_part, ws_yh, ws_tpart, ws_td;
   // timing
   bool timing = false;
   std::vector<Timer> timers;
@@ -246,6 +265,7 @@ namespace uhm_detail {
 enum {
   K_FORWARD = 0, K_REDUCE_FWD, K_COUPLING, K_REDUCE_COUP, K_BACKWARD,
   K_LP_GATHER, K_LP_FORWARD, K_LP_REDUCE_FWD, K_LP_COUPLING, K_LP_REDUCE_COUP, K_LP_BACKWARD, K_LP_SCATTER,
+  K_SYM_COUPLING, K_SYM_REDUCE, K_SYM_BACKWARD, K_SYM_FINISH,
   K_COUNT
 };
 extern const char* const kKernelNames[K_COUNT];

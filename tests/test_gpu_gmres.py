@@ -104,3 +104,24 @@ def test_gmres_with_multi_rhs_fp64_operator(torch_dev):
         x = x.cpu().numpy()
         res = np.linalg.norm(b - uniform.uh_mvp(vars(op), x), axis=0) / np.linalg.norm(b, axis=0)
         assert rc == 0 and res.max() <= 1e-8 * 1.01
+
+
+def test_gmres_with_symmetric_storage_operator(torch_dev):
+    """The symmetric-storage FP64 operator (Remark 4.4) as the residual operator of plain
+    GMRES and of the refinement; residuals checked with the oracle's expanded operator."""
+    from paper_2405_15573_amd import binding, builder
+    torch = torch_dev
+    print("case gmres symmetric storage", flush=True)
+    cloud, op = operator(n=3000, seed=3, leaf=64)
+    sym = builder.symmetric_image(op)
+    ex = uniform.expand_symmetric(sym)
+    b = inputs.make_rhs(cloud.n, 3, seed=36)
+    dop = binding.upload(sym, storage="c128sym")
+    inner = binding.upload(op, storage="c64")
+    bt = torch.from_numpy(np.ascontiguousarray(b.T)).to("cuda").t()
+    for inn in (None, inner):
+        x, info, rc = binding.solve_gmres(dop, bt, 1e-8, inner=inn)
+        torch.cuda.synchronize()
+        x = x.cpu().numpy()
+        res = np.linalg.norm(b - uniform.uh_mvp(ex, x), axis=0) / np.linalg.norm(b, axis=0)
+        assert rc == 0 and info["converged"] == 3 and res.max() <= 1e-8 * 1.01
