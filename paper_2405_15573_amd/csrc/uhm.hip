@@ -382,6 +382,9 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_backward(
 // and used twice: for the direct product (one lane per row, as above) and for the
 // transposed one, whose column sums run across the 64 lanes of the wave.
 
+constexpr int kSymBwdWaves = 4;
+constexpr int kSymBwdChunk = 512;  // z entries staged in LDS per round
+
 __device__ __forceinline__ cd cmul(cd a, cd b) {
   return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
 }
@@ -447,7 +450,11 @@ __global__ __launch_bounds__(64 * kCoupWaves) void k_coupling_sym(
   const cd xt = act ? xh[T.x_row + lane] : make_double2(0.0, 0.0);
   const cd* col = S + T.s_base + (act ? lane : 0);
   const int32_t* cs = csrc + T.c_base;
-  cd* tp = tpart + T.t_base;
+  // the column sums are collected in LDS and written out once per tile, in full lines:
+  // small scattered writes in the middle of the operator stream cost far more than
+  // their bytes
+  __shared__ cd tbuf[kCoupWaves][kCoupCols];
+  cd* tb = tbuf[threadIdx.x >> 6];
   double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
   const int nc = T.ncols;
   // groups of 8 columns, the next group's loads issued before this group's arithmetic;
@@ -478,11 +485,18 @@ __global__ __launch_bounds__(64 * kCoupWaves) void k_coupling_sym(
 #pragma unroll
     for (int k = 0; k < 8; ++k) sv[k] = cmul(sv[k], xt);
     const cd t = wave_colsum8(sv, lane);
-    if ((lane & 7) == 7 && (lane >> 3) < rem) tp[q + (lane >> 3)] = t;
+    if ((lane & 7) == 7 && (lane >> 3) < rem) tb[q + (lane >> 3)] = t;
 #pragma unroll
     for (int k = 0; k < 8; ++k) sv[k] = nx[k];
   }
   if (act) part[(int64_t)tile * kRowChunk + lane] = make_double2(re0 + re1, im0 + im1);
+  // LDS operations of one wave complete in order; the barrier keeps the compiler from
+  // moving the reads above the writes of other lanes
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  cd* tp = tpart + T.t_base;
+  for (int c = lane; c < nc; c += 64) tp[c] = tb[c];
 }
 
 // yh[e] = (direct tiles of e's row chunk, in column order) + (transposed partials of the
@@ -526,7 +540,7 @@ __global__ __launch_bounds__(256) void k_reduce_sym(
 // A|_b, b = lambda' x sigma with lambda inside lambda') also the column sums
 // td[td_off + c - tcol] = sum_i B[i, c] v_i over the leaf's rows i: lambda's share of
 // (A|_b^T v|_lambda').
-__global__ __launch_bounds__(64 * kBwdWaves) void k_backward_sym(
+__global__ __launch_bounds__(64 * kSymBwdWaves) void k_backward_sym(
     const cd* __restrict__ B, const int64_t* __restrict__ bwd_off, const int32_t* __restrict__ bwd_cols,
     const int32_t* __restrict__ bwd_tcol, const int64_t* __restrict__ td_off, const int64_t* __restrict__ zoff,
     const int32_t* __restrict__ zmap, const int32_t* __restrict__ leaf_pos, const int32_t* __restrict__ leaf_n,
@@ -534,8 +548,9 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_backward_sym(
     cd* __restrict__ td, int nleaves) {
   const int leaf = xcd_remap(blockIdx.x, nleaves);
   const int K = bwd_cols[leaf], n = leaf_n[leaf], tc = bwd_tcol[leaf];
-  __shared__ cd zs[kBwdChunk];
-  __shared__ cd red[kBwdWaves][kLeafMax];
+  __shared__ cd zs[kSymBwdChunk];
+  __shared__ cd tdb[kSymBwdChunk];  // column sums of the chunk, written out in full lines
+  __shared__ cd red[kSymBwdWaves][kLeafMax];
   // the wave index is uniform over the wave: the column loop then branches on scalars
   const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
   const cd* Bl = B + bwd_off[leaf];
@@ -544,11 +559,11 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_backward_sym(
   const bool act = lane < n;
   const cd xr = act ? x[perm[leaf_pos[leaf] + lane]] : make_double2(0.0, 0.0);
   double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
-  for (int c0 = 0; c0 < K; c0 += kBwdChunk) {
-    const int cn = min(kBwdChunk, K - c0);
+  for (int c0 = 0; c0 < K; c0 += kSymBwdChunk) {
+    const int cn = min(kSymBwdChunk, K - c0);
     __syncthreads();
     // z of this chunk, then zeros up to the next multiple of 8 columns
-    for (int c = t; c < ((cn + 7) & ~7); c += 64 * kBwdWaves) {
+    for (int c = t; c < ((cn + 7) & ~7); c += 64 * kSymBwdWaves) {
       if (c < cn) {
         const int m = zm[c0 + c];
         zs[c] = m >= 0 ? yh[m] : x[-1 - m];
@@ -560,7 +575,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_backward_sym(
     // groups of 8 columns dealt round-robin to the waves; the last group of the chunk
     // may run past it (into the next chunk, or the slack after the last panel), where
     // the zero z entries take the extra columns out of the direct product
-    for (int c = 8 * w; c < cn; c += 8 * kBwdWaves) {
+    for (int c = 8 * w; c < cn; c += 8 * kSymBwdWaves) {
       const cd* col = Bl + (int64_t)(c0 + c) * n + (act ? lane : 0);
       cd bv[8];
 #pragma unroll
@@ -582,15 +597,19 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_backward_sym(
         }
         const cd s = wave_colsum8(bv, lane);
         const int kk = lane >> 3;
-        if ((lane & 7) == 7 && c + kk < cn && g + kk >= tc) tdl[g + kk - tc] = s;
+        if ((lane & 7) == 7 && c + kk < cn && g + kk >= tc) tdb[c + kk] = s;
       }
+    }
+    if (c0 + cn > tc) {  // uniform over the workgroup
+      __syncthreads();
+      for (int c = max(c0, tc) - c0 + t; c < cn; c += 64 * kSymBwdWaves) tdl[c0 + c - tc] = tdb[c];
     }
   }
   red[w][lane] = make_double2(re0 + re1, im0 + im1);
   __syncthreads();
   if (w == 0 && act) {
     double sr = 0.0, si = 0.0;
-    for (int q = 0; q < kBwdWaves; ++q) {
+    for (int q = 0; q < kSymBwdWaves; ++q) {
       sr += red[q][lane].x;
       si += red[q][lane].y;
     }
@@ -1616,7 +1635,7 @@ int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int
       }
       {
         ScopedTiming tm(op, s, K_SYM_BACKWARD);
-        hipLaunchKernelGGL(k_backward_sym, dim3(nl), dim3(64 * kBwdWaves), 0, s, op->B.p, op->bwd_off.p,
+        hipLaunchKernelGGL(k_backward_sym, dim3(nl), dim3(64 * kSymBwdWaves), 0, s, op->B.p, op->bwd_off.p,
                            op->bwd_cols.p, op->bwd_tcol.p, op->td_off.p, op->zoff.p, op->zmap.p, op->leaf_pos.p,
                            op->leaf_n.p, op->perm.p, zsrc, x, y, op->ws_td.p, nl);
       }
