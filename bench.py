@@ -40,7 +40,7 @@ def algorithmic_bytes(info: dict, n: int, nrhs: int = 1) -> dict:
     f = 16 if info["storage"] == 0 else 8
     rs = info["rank_space"]
     out = {
-        "k_forward": e * info["elems_forward"] + f * nrhs * (n + rs),
+        "k_forward_tiles": e * info["elems_forward"] + f * nrhs * (n + rs),
         "k_backward": e * (info["elems_backward"] + info["elems_near"]) + f * nrhs * (2 * n),
     }
     if info["storage"] == SYM_STORAGE:

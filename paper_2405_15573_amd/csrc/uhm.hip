@@ -33,7 +33,7 @@ namespace uhm_detail {
 thread_local std::string g_err;
 
 const char* const kKernelNames[K_COUNT] = {
-    "k_forward", "k_reduce_segments", "k_coupling", "k_reduce_coupling", "k_backward",
+    "k_forward_tiles", "k_reduce_segments", "k_coupling", "k_reduce_coupling", "k_backward",
     "k_lp_gather", "k_lp_forward", "k_lp_reduce_segments", "k_lp_coupling", "k_lp_reduce_coupling",
     "k_lp_backward", "k_lp_scatter", "k_coupling_sym", "k_reduce_sym", "k_backward_sym", "k_finish_sym"};
 
@@ -165,49 +165,46 @@ __device__ __forceinline__ cd stream_load(const cd* p) {
   return make_double2(v.x, v.y);
 }
 
+// Forward transform: one wave per 64-column tile of a leaf's panel (tiles listed leaf by
+// leaf), lane c accumulating conj(F[i,c]) x_i over the leaf's rows i.  The leaf's x values
+// are uniform over the wave and come through scalar loads.
 template <int FORM>
-__global__ __launch_bounds__(64 * kFwdWaves) void k_forward(
-    const cd* __restrict__ F, const int64_t* __restrict__ fwd_off, const int32_t* __restrict__ fwd_cols,
-    const int32_t* __restrict__ leaf_pos, const int32_t* __restrict__ leaf_n, const int32_t* __restrict__ perm,
-    const cd* __restrict__ x, const int64_t* __restrict__ poff, cd* __restrict__ p, int nleaves) {
-  const int leaf = xcd_remap(blockIdx.x, nleaves);
-  const int C = fwd_cols[leaf];
-  if (C == 0) return;
-  __shared__ cd xs[kLeafMax];
+__global__ __launch_bounds__(64 * kFwdWaves) void k_forward_tiles(
+    const cd* __restrict__ F, const int2* __restrict__ ftiles, int32_t ntiles, const int64_t* __restrict__ fwd_off,
+    const int32_t* __restrict__ fwd_cols, const int32_t* __restrict__ leaf_pos, const int32_t* __restrict__ leaf_n,
+    const int32_t* __restrict__ perm, const cd* __restrict__ x, const int64_t* __restrict__ poff, cd* __restrict__ p) {
+  const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * kFwdWaves + (threadIdx.x >> 6));
+  if (tile >= ntiles) return;
+  const int lane = threadIdx.x & 63;
+  const int2 lt = ftiles[tile];
+  const int leaf = lt.x, j = lt.y;
   const int n = leaf_n[leaf];
-  const int t = threadIdx.x;
-  if (t < n) xs[t] = x[perm[leaf_pos[leaf] + t]];
-  __syncthreads();
-  const int lane = t & 63, w = t >> 6;
-  const cd* base = F + fwd_off[leaf];
-  cd* pl = p + poff[leaf];
-  const int ntile = (C + kTile - 1) / kTile;
-  for (int j = w; j < ntile; j += kFwdWaves) {
-    const int wj = min(kTile, C - kTile * j);
-    if (lane >= wj) continue;
-    const cd* q = base + (int64_t)kTile * j * n + lane;
-    double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
-    int i = 0;
-    for (; i + 8 <= n; i += 8) {
-      cd v[8];
+  const int wj = min(kTile, fwd_cols[leaf] - kTile * j);
+  if (lane >= wj) return;
+  const cd* q = F + fwd_off[leaf] + (int64_t)kTile * j * n + lane;
+  const int32_t* px = perm + leaf_pos[leaf];
+  double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+  int i = 0;
+  for (; i + 8 <= n; i += 8) {
+    cd v[8], xv[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = stream_load(&q[(i + k) * wj]);
+    for (int k = 0; k < 8; ++k) v[k] = stream_load(&q[(i + k) * wj]);
 #pragma unroll
-      for (int k = 0; k < 8; k += 2) {
-        const cd x0 = xs[i + k], x1 = xs[i + k + 1];
-        re0 = fma(v[k].x, x0.x, fma(v[k].y, x0.y, re0));
-        im0 = fma(v[k].x, x0.y, fma(-v[k].y, x0.x, im0));
-        re1 = fma(v[k + 1].x, x1.x, fma(v[k + 1].y, x1.y, re1));
-        im1 = fma(v[k + 1].x, x1.y, fma(-v[k + 1].y, x1.x, im1));
-      }
+    for (int k = 0; k < 8; ++k) xv[k] = x[px[i + k]];
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+      re0 = fma(v[k].x, xv[k].x, fma(v[k].y, xv[k].y, re0));
+      im0 = fma(v[k].x, xv[k].y, fma(-v[k].y, xv[k].x, im0));
+      re1 = fma(v[k + 1].x, xv[k + 1].x, fma(v[k + 1].y, xv[k + 1].y, re1));
+      im1 = fma(v[k + 1].x, xv[k + 1].y, fma(-v[k + 1].y, xv[k + 1].x, im1));
     }
-    for (; i < n; ++i) {
-      const cd v = stream_load(&q[i * wj]), xv = xs[i];
-      re0 = fma(v.x, xv.x, fma(v.y, xv.y, re0));
-      im0 = fma(v.x, xv.y, fma(-v.y, xv.x, im0));
-    }
-    pl[kTile * j + lane] = make_double2(re0 + re1, im0 + im1);
   }
+  for (; i < n; ++i) {
+    const cd v = stream_load(&q[i * wj]), xv = x[px[i]];
+    re0 = fma(v.x, xv.x, fma(v.y, xv.y, re0));
+    im0 = fma(v.x, xv.y, fma(-v.y, xv.x, im0));
+  }
+  p[poff[leaf] + kTile * j + lane] = make_double2(re0 + re1, im0 + im1);
 }
 
 // out[e] = sum over the leaves of segment seg(e) of p[leaf][col(seg) + e - start(seg)],
@@ -708,6 +705,16 @@ int upload_segments(uhm_op* op, const std::vector<SegDesc>& segs, int64_t nout, 
   return UHM_OK;
 }
 
+// (leaf, tile) list of the 64-column tiles of the forward panels, leaf by leaf.
+int upload_fwd_tiles(uhm_op* op, const std::vector<int32_t>& fwd_cols, hipStream_t s) {
+  std::vector<int2> t;
+  for (size_t i = 0; i < fwd_cols.size(); ++i)
+    for (int32_t j = 0; j * kTile < fwd_cols[i]; ++j) t.push_back(make_int2((int)i, j));
+  if (t.size() > (size_t)INT32_MAX) return fail(UHM_ENOTSUP, "too many forward tiles");
+  op->nftiles = (int32_t)t.size();
+  return op->ftiles.upload(t, s);
+}
+
 struct FwdLayout {
   int64_t ftot = 0, ptot = 0;
   std::vector<int64_t> fwd_off, poff;
@@ -756,7 +763,7 @@ int build_forward(uhm_op* op, const TreeInfo& T, const int64_t* off, const int64
     if ((rc = st.finish())) return rc;
   }
   if ((rc = op->fwd_off.upload(L.fwd_off, s)) || (rc = op->fwd_cols.upload(L.fwd_cols, s)) ||
-      (rc = op->poff.upload(L.poff, s)))
+      (rc = op->poff.upload(L.poff, s)) || (rc = upload_fwd_tiles(op, L.fwd_cols, s)))
     return rc;
   op->p_len = ptot;
   L.ftot = ftot;
@@ -1490,6 +1497,7 @@ int uhm_upload_h(const uhm_host_hmatrix* h, uhm_storage storage, void* hip_strea
     if ((rc = st.finish())) return rc;
   }
   if ((rc = op->fwd_off.upload(fwd_off, s)) || (rc = op->fwd_cols.upload(fwd_cols, s)) ||
+      (rc = upload_fwd_tiles(op.get(), fwd_cols, s)) ||
       (rc = op->poff.upload(poff, s)))
     return rc;
   op->p_len = ptot;
@@ -1606,8 +1614,10 @@ int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int
     if (op->nxh > 0) {
       {
         ScopedTiming tm(op, s, K_FORWARD);
-        hipLaunchKernelGGL(op->kind == 0 ? k_forward<0> : k_forward<1>, dim3(nl), dim3(64 * kFwdWaves), 0, s, op->F.p, op->fwd_off.p, op->fwd_cols.p,
-                           op->leaf_pos.p, op->leaf_n.p, op->perm.p, x, op->poff.p, op->ws_p.p, nl);
+        hipLaunchKernelGGL(op->kind == 0 ? k_forward_tiles<0> : k_forward_tiles<1>,
+                           dim3((unsigned)((op->nftiles + kFwdWaves - 1) / kFwdWaves)), dim3(64 * kFwdWaves), 0, s,
+                           op->F.p, op->ftiles.p, op->nftiles, op->fwd_off.p, op->fwd_cols.p, op->leaf_pos.p,
+                           op->leaf_n.p, op->perm.p, x, op->poff.p, op->ws_p.p);
       }
       {
         ScopedTiming tm(op, s, K_REDUCE_FWD);

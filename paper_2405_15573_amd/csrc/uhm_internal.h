@@ -213,6 +213,8 @@ struct uhm_op {
   DevArray<cd> F;
   DevArray<int64_t> fwd_off, poff;
   DevArray<int32_t> fwd_cols;
+  DevArray<int2> ftiles;  // (leaf, tile) of every 64-column tile of the forward panels
+  int32_t nftiles = 0;
   int64_t p_len = 0;
   // segments of the rank-space vector (u_sigma per cluster, or Y_b^* v per block)
   DevArray<int32_t> out_seg, seg_leaf0, seg_nleaf, seg_col;
