@@ -16,6 +16,9 @@ h_mvp         y = sum_{b in P+} X_b Y_b^* x|_sigma + sum_{b in P-} A|_b x|_sigma
 expand_symmetric
               the general image that a symmetric-storage image stands for (Remark 4.4):
               every stored off-diagonal block also gives its mirror, as a transpose.
+assemble_factored
+              the general image with every coupling formed from its factors,
+              S_b = S_{X,b} S_{Y,b}^* (section 4.2).
 alg6, alg5    the C implementations of Algorithms 6 and 5 (section 4.4), through ctypes.
 optimal_row_basis
               Algorithm 1: the leading left singular vectors of the explicit
@@ -157,6 +160,23 @@ def expand_symmetric(op: Mapping) -> dict:
             rows.append(int(dc[b])), cols.append(int(dr[b])), blocks.append(blocks[b].T)
     out["den_row"], out["den_col"] = np.array(rows, np.int32), np.array(cols, np.int32)
     out["D_off"], out["D"] = _pack(blocks)
+    return out
+
+
+def assemble_factored(op: Mapping) -> dict:
+    """The general UH image whose couplings are the products of their stored factors,
+    S_b = S_{X,b} S_{Y,b}^* (section 4.2), S_{X,b} (l_tau x k_b) at SX_off[b] and S_{Y,b}
+    (l_sigma x k_b) at SY_off[b], k_b = adm_rank[b].  The S and S_off entries of the input
+    are not read."""
+    out = dict(op)
+    rr, rc, k = np.asarray(op["rank_row"]), np.asarray(op["rank_col"]), np.asarray(op["adm_rank"])
+    blocks = []
+    for b in range(np.asarray(op["adm_row"]).size):
+        lt, ls, kb = int(rr[op["adm_row"][b]]), int(rc[op["adm_col"][b]]), int(k[b])
+        sx = _colmajor(op["SX"], int(op["SX_off"][b]), lt, kb)
+        sy = _colmajor(op["SY"], int(op["SY_off"][b]), ls, kb)
+        blocks.append(sx @ sy.conj().T)
+    out["S_off"], out["S"] = _pack(blocks)
     return out
 
 

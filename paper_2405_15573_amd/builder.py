@@ -214,6 +214,10 @@ class HostOperator:
     eps_aca: float
     eps_comp: float
     depth: int
+    SX_off: np.ndarray = field(default=None)       # factored couplings S_b = S_{X,b} S_{Y,b}^*:
+    SY_off: np.ndarray = field(default=None)       # S_{X,b} l_tau x k_b at SX_off[b],
+    SX: np.ndarray = field(default=None)           # S_{Y,b} l_sigma x k_b at SY_off[b]
+    SY: np.ndarray = field(default=None)
     sv_dropped: np.ndarray = field(default=None)   # per cluster: sigma_{l+1}(X_tau) (0 if none)
     sv_tail: np.ndarray = field(default=None)      # per cluster: sqrt(sum_{i>l} sigma_i^2)
     timings: dict = field(default_factory=dict)
@@ -433,13 +437,24 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
     sizes = rank[adm[:, 0]].astype(np.int64) * rank[adm[:, 1]].astype(np.int64)
     S_off[1:] = np.cumsum(sizes)[:-1]
     S = np.empty(int(sizes.sum()), np.complex128)
-    adm_rank = np.zeros(nadm, np.int32)
+    adm_rank = np.array([fac_s[(min(int(t), int(s)), max(int(t), int(s)))].size for t, s in adm], np.int32) \
+        if nadm else np.zeros(0, np.int32)
+    # factored couplings S_b = S_{X,b} S_{Y,b}^* (section 4.2): S_{X,b} = U_tau^* U_b (l_tau x k_b),
+    # S_{Y,b} = V_sigma^* V_b (l_sigma x k_b), with V_b's scale folded into S_{X,b}
+    xsz = rank[adm[:, 0]].astype(np.int64) * adm_rank
+    ysz = rank[adm[:, 1]].astype(np.int64) * adm_rank
+    SX_off = np.concatenate([[0], np.cumsum(xsz)[:-1]]).astype(np.int64)[:nadm]
+    SY_off = np.concatenate([[0], np.cumsum(ysz)[:-1]]).astype(np.int64)[:nadm]
+    SX = np.empty(int(xsz.sum()), np.complex128)
+    SY = np.empty(int(ysz.sum()), np.complex128)
     for b in range(nadm):
         t, s = int(adm[b, 0]), int(adm[b, 1])
         sb = fac_s[(min(t, s), max(t, s))]
-        Sb = (Lmat[(t, s)] / sb[None, :]) @ Lmat[(s, t)].T
-        S[S_off[b]:S_off[b] + sizes[b]] = Sb.ravel(order="F")
-        adm_rank[b] = sb.size
+        Xf = Lmat[(t, s)] / sb[None, :]
+        Yf = np.conj(Lmat[(s, t)])
+        S[S_off[b]:S_off[b] + sizes[b]] = (Xf @ Lmat[(s, t)].T).ravel(order="F")
+        SX[SX_off[b]:SX_off[b] + xsz[b]] = Xf.ravel(order="F")
+        SY[SY_off[b]:SY_off[b] + ysz[b]] = Yf.ravel(order="F")
     tim["couplings"] = time.perf_counter() - t3
     if verbose:
         print(f"  couplings {tim['couplings']:.1f} s", file=sys.stderr, flush=True)
@@ -490,6 +505,7 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
         adm_rank=adm_rank, X_off=X_off, Y_off=Y_off, X=Xh, Y=Yh,
         den_row=den[:, 0].astype(np.int32), den_col=den[:, 1].astype(np.int32), D_off=D_off, D=D,
         kappa=kappa, h=cloud.h, leaf=leaf, eta=eta, eps_aca=eps_aca, eps_comp=eps_comp, depth=tree.depth,
+        SX_off=SX_off, SY_off=SY_off, SX=SX, SY=SY,
         sv_dropped=sv_dropped, sv_tail=sv_tail, timings=tim)
 
 

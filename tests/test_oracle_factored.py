@@ -1,0 +1,59 @@
+"""Pins of the factored-coupling oracle (uniform.assemble_factored, section 4.2; no GPU).
+
+S_b = S_{X,b} S_{Y,b}^* must be the optimal coefficient matrix U_tau^* (X_b Y_b^*) V_sigma of
+the block's H-matrix factors (section 4.1), which the builder stores separately; the
+factored operator must meet the dense kernel matrix within the compression tolerance; and a
+missing conjugate on the second factor is rejected.
+"""
+import numpy as np
+import pytest
+
+from conftest import operator, rel
+from oracle import kernel, uniform
+from paper_2405_15573_amd import inputs
+
+EPS = 1e-6
+
+
+def _colmajor(flat, start, rows, cols):
+    return flat[start:start + rows * cols].reshape(cols, rows).T
+
+
+def test_factors_give_the_optimal_coefficients(small_op):
+    _, op = small_op
+    fa = uniform.assemble_factored(vars(op))
+    rng = np.random.default_rng(5)
+    for b in rng.choice(op.nadm, size=min(60, op.nadm), replace=False):
+        t, s, k = int(op.adm_row[b]), int(op.adm_col[b]), int(op.adm_rank[b])
+        lt, ls = int(op.rank_row[t]), int(op.rank_col[s])
+        U = _colmajor(op.U, int(op.U_off[t]), int(op.size[t]), lt)
+        V = _colmajor(op.V, int(op.V_off[s]), int(op.size[s]), ls)
+        X = _colmajor(op.X, int(op.X_off[b]), int(op.size[t]), k)
+        Y = _colmajor(op.Y, int(op.Y_off[b]), int(op.size[s]), k)
+        want = U.conj().T @ (X @ Y.conj().T) @ V
+        got = _colmajor(fa["S"], int(fa["S_off"][b]), lt, ls)
+        assert np.linalg.norm(got - want) <= 1e-13 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("surface,n,seed,leaf", [("sphere", 2048, 0, 32), ("cube", 1300, 5, 32)])
+def test_factored_operator_against_dense(surface, n, seed, leaf):
+    cloud, op = operator(surface=surface, n=n, seed=seed, leaf=leaf)
+    fa = uniform.assemble_factored(vars(op))
+    x = inputs.make_rhs(cloud.n, 2, seed=seed + 50)
+    a = kernel.dense_matrix(cloud.points, cloud.kappa, 1.0 / (2.0 * cloud.h))
+    y = uniform.uh_mvp(fa, x)
+    norm_a = np.linalg.norm(a, 2)
+    for j in range(2):
+        assert np.linalg.norm(y[:, j] - a @ x[:, j]) <= 10 * EPS * norm_a * np.linalg.norm(x[:, j])
+    # and the stored assembled couplings to rounding
+    assert rel(y, uniform.uh_mvp(vars(op), x)) < 1e-13
+
+
+def test_missing_conjugate_is_rejected(small_op):
+    cloud, op = small_op
+    bad = dict(vars(op))
+    bad["SY"] = np.conj(op.SY)
+    x = inputs.make_rhs(cloud.n, 1, seed=51)
+    a = kernel.dense_matrix(cloud.points, cloud.kappa, 1.0 / (2.0 * cloud.h))
+    y = uniform.uh_mvp(uniform.assemble_factored(bad), x)
+    assert np.linalg.norm(y[:, 0] - a @ x[:, 0]) > 10 * EPS * np.linalg.norm(a, 2) * np.linalg.norm(x[:, 0])
