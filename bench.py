@@ -51,13 +51,17 @@ def algorithmic_bytes(info: dict, n: int, nrhs: int = 1) -> dict:
         out["total"] = (e * (info["elems_forward"] + info["elems_coupling"] + info["elems_backward"]
                              + info["elems_near"]) + f * nrhs * (2 * n + 4 * rs + 2 * tc + 2 * tn))
         return out
+    ci = info.get("elems_coupling_in", 0)
     if info["kind"] == 0:
         out["k_coupling"] = e * info["elems_coupling"] + f * nrhs * 2 * rs
         out["k_backward"] += f * nrhs * rs
+        if ci:  # factored couplings: first step S_Y^* u, then S_X (and the assembled S_b) in k_coupling
+            out["k_factor_in"] = e * ci + f * nrhs * 2 * rs
     else:
         out["k_backward"] += f * nrhs * rs
-    out["total"] = (e * (info["elems_forward"] + info["elems_coupling"] + info["elems_backward"] + info["elems_near"])
-                    + f * nrhs * (2 * n + 2 * rs + (2 * rs if info["kind"] == 0 else 0)))
+    out["total"] = (e * (info["elems_forward"] + info["elems_coupling"] + ci + info["elems_backward"]
+                         + info["elems_near"])
+                    + f * nrhs * (2 * n + 2 * rs + (2 * rs if info["kind"] == 0 else 0) + (2 * rs if ci else 0)))
     return out
 
 
@@ -302,6 +306,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-h", action="store_true")
     ap.add_argument("--no-sym", action="store_true", help="skip the symmetric storage form")
+    ap.add_argument("--no-factored", action="store_true", help="skip the factored-coupling form")
     ap.add_argument("--no-lowp", action="store_true", help="skip the complex64 / bf16-pair multi-RHS forms")
     ap.add_argument("--lowp-rhs", type=int, default=64)
     ap.add_argument("--no-gmres", action="store_true", help="skip the time-to-solution comparison")
@@ -428,6 +433,29 @@ def main():
         dsym.free()
         del ys
 
+    # factored couplings (section 4.2) in general storage, where they store fewer elements
+    fact = None
+    if not args.no_factored:
+        tf = time.perf_counter()
+        dfa = binding.upload(op, "c128fact", stream=stream)
+        log(f"factored upload {time.perf_counter() - tf:.1f} s")
+        finfo = dfa.info()
+        yf = torch.empty_like(x)
+        t_fa, k_fa = time_products(torch, dfa, x, yf, args.steps, args.warmup, stream)
+        y_fa = yf.cpu().numpy()
+        abf = algorithmic_bytes(finfo, cloud.n)
+        tp = time.perf_counter()
+        ref_f, users_f = uniform.uh_mvp_rows(uniform.assemble_factored(vars(op)), x_np, pos)
+        par_f = float(np.linalg.norm(y_fa[users_f] - ref_f[:, 0]) / np.linalg.norm(ref_f[:, 0]))
+        log(f"factored sampled parity {par_f:.3e} in {time.perf_counter() - tp:.1f} s")
+        fact = {"ms_per_mvp": t_fa * 1e3, "mvps_per_s": 1.0 / t_fa, "gbs": abf["total"] / t_fa / 1e9,
+                "bytes": abf["total"], "bytes_per_kernel": abf, "vs_general_speedup": t_uh / t_fa,
+                "kernels_ms": {k: v[0] for k, v in k_fa.items()}, "parity_sampled_rel_err": par_f,
+                "elems_coupling": finfo["elems_coupling"], "elems_coupling_in": finfo["elems_coupling_in"]}
+        log(f"factored UH MVP {t_fa * 1e3:.3f} ms; kernels " + json.dumps({k: round(v[0], 4) for k, v in k_fa.items()}))
+        dfa.free()
+        del yf
+
     res_h = None
     if not args.no_h:
         t2 = time.perf_counter()
@@ -543,6 +571,7 @@ def main():
         "kernels_ms": {k: v[0] for k, v in k_hd.items()},
         "general_storage": general,
         "symmetric": sym,
+        "general_factored": fact,
         "h_mvp": res_h,
         "uh_speedup_over_h": (res_h["ms_per_mvp"] / (t_uh * 1e3)) if res_h else None,
         "uh_symmetric_speedup_over_h": (res_h["ms_per_mvp"] / (t_sy * 1e3)) if (res_h and sym) else None,

@@ -56,13 +56,18 @@ typedef enum {
   UHM_BF16PAIR = 2,  /* (re, im) bfloat16 pairs, FP32 accumulation; vectors complex64 */
   UHM_C128_MULTI = 3, /* complex128 storage and arithmetic laid out for many right-hand sides
                          (FP64 MFMA, up to 64 per pass); vectors complex128 */
-  UHM_C128_SYM = 4    /* complex128, symmetric storage (Remark 4.4): for a complex-symmetric
+  UHM_C128_SYM = 4,   /* complex128, symmetric storage (Remark 4.4): for a complex-symmetric
                          A = A^T on one cluster tree.  The image lists one block of each mirrored
                          pair tau x sigma / sigma x tau (diagonal dense blocks once); the mirror
                          of a stored admissible block is U_sigma S_b^T U_tau^T and that of a
                          stored dense block A|_b^T, with V_c = conj(U_c) implied: V, V_off and
                          rank_col are not read.  Each stored element is read once per product
                          and applied both ways.  uhm_upload only; vectors complex128 */
+  UHM_C128_FACTORED = 5 /* complex128 with factored couplings (section 4.2):
+                         S_b = S_{X,b} S_{Y,b}^*, applied in two steps (S_{Y,b}^* u_sigma, then
+                         S_{X,b} times that) for every block where k_b (l_tau + l_sigma) <
+                         l_tau l_sigma, assembled S_b elsewhere.  The image must carry adm_rank,
+                         SX and SY.  uhm_upload only; vectors complex128 */
 } uhm_storage;
 
 typedef struct uhm_op uhm_op; /* opaque; owned by the library until uhm_free */
@@ -100,6 +105,14 @@ typedef struct {
   const int32_t* den_col;    /* [nden] */
   const int64_t* D_off;      /* [nden] */
   const double* D; int64_t D_len;
+  /* Factored couplings, read only with UHM_C128_FACTORED (NULL otherwise): block b has
+   * k_b = adm_rank[b] >= 1, S_{X,b} (rank_row[adm_row[b]] x k_b) at SX + 2*SX_off[b] and
+   * S_{Y,b} (rank_col[adm_col[b]] x k_b) at SY + 2*SY_off[b]. */
+  const int32_t* adm_rank;   /* [nadm] */
+  const int64_t* SX_off;     /* [nadm] */
+  const int64_t* SY_off;     /* [nadm] */
+  const double* SX; int64_t SX_len;
+  const double* SY; int64_t SY_len;
 } uhm_host_operator;
 
 /*
@@ -146,6 +159,9 @@ typedef struct {
   int64_t partial_coupling;  /* UHM_C128_SYM: partial sums the transposed coupling products write per
                                 right-hand side (complex elements); 0 for the other forms */
   int64_t partial_near;      /* UHM_C128_SYM: the same for the transposed dense blocks */
+  int64_t elems_coupling_in; /* UHM_C128_FACTORED: elements of the S_{Y,b} factors, read by the
+                                first coupling step (elems_coupling counts the assembled S_b
+                                and the S_{X,b} factors); 0 for the other forms */
 } uhm_op_info;
 
 /*
@@ -202,7 +218,7 @@ typedef struct {
  * pass (Daniel, Gragg, Kaufman and Stewart), FP64 Krylov vectors, Givens least-squares),
  * for nrhs right-hand sides at once, each with its own Krylov space.  X starts at zero
  * and is overwritten.
- *   op:    the operator A, UHM_C128, UHM_C128_MULTI or UHM_C128_SYM storage (the true-residual operator).
+ *   op:    the operator A in a complex128 storage form (the true-residual operator).
  *   inner: NULL for plain GMRES on op; otherwise an operator of the same matrix in
  *          complex64 or bf16-pair storage, and the solve is mixed-precision iterative
  *          refinement: r = B - A X with op (FP64), an inner GMRES(m) solves

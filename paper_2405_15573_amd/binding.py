@@ -15,8 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libuhm.so")
 
 UHM_OK, UHM_EINVAL, UHM_ENOMEM, UHM_EHIP, UHM_ENOCONV, UHM_ENOTSUP = 0, -1, -2, -3, -4, -5
-STORAGE = {"c128": 0, "c64": 1, "bf16pair": 2, "c128multi": 3, "c128sym": 4}
-C128_FORMS = ("c128", "c128multi", "c128sym")
+STORAGE = {"c128": 0, "c64": 1, "bf16pair": 2, "c128multi": 3, "c128sym": 4, "c128fact": 5}
+C128_FORMS = ("c128", "c128multi", "c128sym", "c128fact")
 
 P = ctypes.c_void_p
 I64 = ctypes.c_int64
@@ -28,7 +28,8 @@ class HostOperator(ctypes.Structure):
                 ("rank_row", P), ("rank_col", P), ("U_off", P), ("V_off", P),
                 ("U", P), ("U_len", I64), ("V", P), ("V_len", I64),
                 ("nadm", I64), ("adm_row", P), ("adm_col", P), ("S_off", P), ("S", P), ("S_len", I64),
-                ("nden", I64), ("den_row", P), ("den_col", P), ("D_off", P), ("D", P), ("D_len", I64)]
+                ("nden", I64), ("den_row", P), ("den_col", P), ("D_off", P), ("D", P), ("D_len", I64),
+                ("adm_rank", P), ("SX_off", P), ("SY_off", P), ("SX", P), ("SX_len", I64), ("SY", P), ("SY_len", I64)]
 
 
 class HostHMatrix(ctypes.Structure):
@@ -42,7 +43,7 @@ class OpInfo(ctypes.Structure):
     _fields_ = [("n", I64), ("kind", I32), ("storage", I32), ("nleaves", I32), ("elem_bytes", I32),
                 ("nadm", I64), ("nden", I64), ("elems_forward", I64), ("elems_coupling", I64),
                 ("elems_backward", I64), ("elems_near", I64), ("rank_space", I64), ("device_bytes", I64),
-                ("partial_coupling", I64), ("partial_near", I64)]
+                ("partial_coupling", I64), ("partial_near", I64), ("elems_coupling_in", I64)]
 
 
 class GmresOpts(ctypes.Structure):
@@ -261,6 +262,14 @@ def upload(op, storage: str = "c128", stream=None) -> DeviceOperator:
     h.D_off = a("D_off", np.int64)
     h.D = a("D", np.complex128)
     h.D_len = keep["D"].size
+    if storage == "c128fact":
+        h.adm_rank = a("adm_rank", np.int32)
+        h.SX_off = a("SX_off", np.int64)
+        h.SY_off = a("SY_off", np.int64)
+        h.SX = a("SX", np.complex128)
+        h.SX_len = keep["SX"].size
+        h.SY = a("SY", np.complex128)
+        h.SY_len = keep["SY"].size
     out = P()
     sh, _ = _stream_handle(stream)
     _check(load_library().uhm_upload(ctypes.byref(h), STORAGE[storage], sh, ctypes.byref(out)), "uhm_upload")

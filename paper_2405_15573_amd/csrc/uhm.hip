@@ -35,7 +35,8 @@ thread_local std::string g_err;
 const char* const kKernelNames[K_COUNT] = {
     "k_forward_tiles", "k_reduce_segments", "k_coupling", "k_reduce_coupling", "k_backward",
     "k_lp_gather", "k_lp_forward", "k_lp_reduce_segments", "k_lp_coupling", "k_lp_reduce_coupling",
-    "k_lp_backward", "k_lp_scatter", "k_coupling_sym", "k_reduce_sym", "k_backward_sym", "k_finish_sym"};
+    "k_lp_backward", "k_lp_scatter", "k_coupling_sym", "k_reduce_sym", "k_backward_sym", "k_finish_sym",
+    "k_factor_in"};
 
 int check_tree(int64_t n, const int64_t* perm, int32_t nc, const int64_t* off, const int64_t* size,
                const int32_t* parent, TreeInfo& T) {
@@ -289,6 +290,46 @@ __global__ __launch_bounds__(64 * kCoupWaves) void k_coupling(
     j = 0;
   }
   if (act) part[(int64_t)tile * kRowChunk + lane] = make_double2(re0 + re1, im0 + im1);
+}
+
+// First step of the factored couplings: out[t_out + c] = sum_r conj(FY[r, c]) u[x_row + r]
+// over the l_sigma rows of one tile, one lane per column (t_b = S_{Y,b}^* u_sigma); u_sigma
+// is uniform over the wave and comes through scalar loads.  u and out are the two disjoint
+// parts of the coupling source vector ([0, nxh) and [nxh, nsrc)).
+__global__ __launch_bounds__(64 * kCoupWaves) void k_factor_in(const cd* __restrict__ FY,
+                                                               const FacTile* __restrict__ ftl, int32_t ntiles,
+                                                               const cd* __restrict__ u_all,
+                                                               cd* __restrict__ out) {
+  const int tile = __builtin_amdgcn_readfirstlane(blockIdx.x * kCoupWaves + (threadIdx.x >> 6));
+  if (tile >= ntiles) return;
+  const int lane = threadIdx.x & 63;
+  const FacTile T = ftl[tile];
+  if (lane >= T.wj) return;
+  const cd* q = FY + T.f_base + lane;
+  const cd* u = u_all + T.x_row;
+  const int wj = T.wj, n = T.rows;
+  double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+  int i = 0;
+  for (; i + 8 <= n; i += 8) {
+    cd v[8], uv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = stream_load(&q[(int64_t)(i + k) * wj]);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) uv[k] = u[i + k];
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+      re0 = fma(v[k].x, uv[k].x, fma(v[k].y, uv[k].y, re0));
+      im0 = fma(v[k].x, uv[k].y, fma(-v[k].y, uv[k].x, im0));
+      re1 = fma(v[k + 1].x, uv[k + 1].x, fma(v[k + 1].y, uv[k + 1].y, re1));
+      im1 = fma(v[k + 1].x, uv[k + 1].y, fma(-v[k + 1].y, uv[k + 1].x, im1));
+    }
+  }
+  for (; i < n; ++i) {
+    const cd v = stream_load(&q[(int64_t)i * wj]), uv = u[i];
+    re0 = fma(v.x, uv.x, fma(v.y, uv.y, re0));
+    im0 = fma(v.x, uv.y, fma(-v.y, uv.x, im0));
+  }
+  out[T.t_out + lane] = make_double2(re0 + re1, im0 + im1);
 }
 
 // yh[e] = sum_{t in tiles of e's chunk} part[t][r(e)], tiles in column order.
@@ -779,7 +820,8 @@ int grow_workspace(uhm_op* op) {
   // single-RHS workspace; columns are processed one at a time
   int rc;
   if (op->ws_p.n < op->p_len && (rc = op->ws_p.alloc(op->p_len))) return rc;
-  if (op->ws_xh.n < op->nxh && (rc = op->ws_xh.alloc(op->nxh))) return rc;
+  const int64_t nsrc = std::max(op->nxh, op->nsrc);
+  if (op->ws_xh.n < nsrc && (rc = op->ws_xh.alloc(nsrc))) return rc;
   if (op->kind == 0) {
     if (op->ws_part.n < (int64_t)op->nctiles * kRowChunk && (rc = op->ws_part.alloc((int64_t)op->nctiles * kRowChunk)))
       return rc;
@@ -1197,7 +1239,7 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
   if (!h || !out) return fail(UHM_EINVAL, "null argument");
   *out = nullptr;
   if (storage != UHM_C128 && storage != UHM_C64 && storage != UHM_BF16PAIR && storage != UHM_C128_MULTI &&
-      storage != UHM_C128_SYM)
+      storage != UHM_C128_SYM && storage != UHM_C128_FACTORED)
     return fail(UHM_EINVAL, "unknown storage precision");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   TreeInfo T;
@@ -1238,12 +1280,25 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
     if (t < 0 || t >= nc || sg < 0 || sg >= nc) return fail(UHM_EINVAL, "dense block cluster out of range");
     if (!in_bounds(h->D_off[b], h->size[t] * h->size[sg], h->D_len)) return fail(UHM_EINVAL, "D_off out of bounds");
   }
+  // factored couplings: which blocks take the two-step form (fewer stored elements)
+  const bool factored = storage == UHM_C128_FACTORED;
+  std::vector<char> fac(h->nadm, 0);
+  if (factored) {
+    if (h->nadm > 0 && (!h->adm_rank || !h->SX_off || !h->SY_off || !h->SX || !h->SY))
+      return fail(UHM_EINVAL, "factored storage needs adm_rank, SX and SY");
+    for (int64_t b = 0; b < h->nadm; ++b) {
+      const int64_t lt = h->rank_row[h->adm_row[b]], ls = h->rank_col[h->adm_col[b]], k = h->adm_rank[b];
+      if (k < 1 || !in_bounds(h->SX_off[b], lt * k, h->SX_len) || !in_bounds(h->SY_off[b], ls * k, h->SY_len))
+        return fail(UHM_EINVAL, "factored coupling out of bounds");
+      fac[b] = k * (lt + ls) < lt * ls;
+    }
+  }
   std::unique_ptr<uhm_op> op(new (std::nothrow) uhm_op);
   if (!op) return fail(UHM_ENOMEM, "host allocation");
   op->kind = 0;
   op->storage = storage;
   if ((rc = common_tree_upload(op.get(), T, h->perm, h->off, h->size, s))) return rc;
-  if (storage != UHM_C128) {
+  if (storage != UHM_C128 && storage != UHM_C128_FACTORED) {
     if ((rc = lowp_upload(h, storage, s, T, op.get()))) return rc;
     *out = op.release();
     return UHM_OK;
@@ -1267,9 +1322,61 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
   FwdLayout FL;
   if ((rc = build_forward(op.get(), T, h->off, h->size, h->rank_col, V, h->V_off, false, xh_off, nxh, s, FL))) return rc;
 
-  // ---- couplings, grouped by row cluster, in row chunks
+  // ---- factored couplings, first step: t_b = S_{Y,b}^* u_sigma, stored in the coupling source
+  // vector after u, block by block within each column cluster
+  std::vector<int64_t> t_off(h->nadm, -1);
+  std::vector<std::vector<int64_t>> colfac(nc);
+  for (int64_t b = 0; b < h->nadm; ++b)
+    if (fac[b]) colfac[h->adm_col[b]].push_back(b);
+  int64_t nsrc = nxh;
+  for (int32_t c = 0; c < nc; ++c)
+    for (int64_t b : colfac[c]) {
+      t_off[b] = nsrc;
+      nsrc += h->adm_rank[b];
+    }
+  if (nsrc > INT32_MAX) return fail(UHM_ENOTSUP, "coupling source vector too long");
+  std::vector<FacTile> ftl;
+  int64_t fytot = 0;
+  for (int32_t c = 0; c < nc; ++c) {
+    int64_t Kf = 0;
+    for (int64_t b : colfac[c]) Kf += h->adm_rank[b];
+    for (int64_t c0 = 0; c0 < Kf; c0 += kTile) {
+      const int32_t wj = (int32_t)std::min<int64_t>(kTile, Kf - c0);
+      ftl.push_back({fytot, h->rank_col[c], wj, (int32_t)xh_off[c], (int32_t)(t_off[colfac[c][0]] + c0)});
+      fytot += (int64_t)wj * h->rank_col[c];
+    }
+  }
+  if (ftl.size() > (size_t)INT32_MAX) return fail(UHM_ENOTSUP, "too many factor tiles");
+  if ((rc = op->FY.alloc(fytot))) return rc;
+  if (fytot > 0) {
+    const cd* SY = reinterpret_cast<const cd*>(h->SY);
+    Stager st;
+    if ((rc = st.init(op->FY.p, fytot, s))) return rc;
+    std::vector<const cd*> colp;
+    for (int32_t c = 0; c < nc && !st.err; ++c) {
+      if (colfac[c].empty()) continue;
+      const int32_t ls = h->rank_col[c];
+      colp.clear();  // start of every panel column, in the order of the t_b
+      for (int64_t b : colfac[c])
+        for (int32_t j = 0; j < h->adm_rank[b]; ++j) colp.push_back(SY + h->SY_off[b] + (int64_t)j * ls);
+      for (size_t c0 = 0; c0 < colp.size(); c0 += kTile) {
+        const int32_t wj = (int32_t)std::min<size_t>(kTile, colp.size() - c0);
+        cd* tile = st.span((int64_t)wj * ls);
+        for (int32_t r = 0; r < ls; ++r)
+          for (int32_t q = 0; q < wj; ++q) tile[(int64_t)r * wj + q] = colp[c0 + q][r];
+      }
+    }
+    if ((rc = st.finish())) return rc;
+  }
+  if ((rc = op->factiles.upload(ftl, s))) return rc;
+  op->nfactiles = (int32_t)ftl.size();
+  op->nsrc = nsrc;
+
+  // ---- couplings, grouped by row cluster, in row chunks: [S_b1 S_b2 ...] with a factored
+  // block's S_{X,b} in place of its S_b
   std::vector<std::vector<int64_t>> rowblk(nc);
   for (int64_t b = 0; b < h->nadm; ++b) rowblk[h->adm_row[b]].push_back(b);
+  auto width = [&](int64_t b) { return fac[b] ? h->adm_rank[b] : h->rank_col[h->adm_col[b]]; };
   std::vector<CoupTile> tiles;
   std::vector<int2> cblk;
   std::vector<int32_t> grp_t0, grp_nt, yh_grp(nyh);
@@ -1280,9 +1387,10 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
     std::sort(rowblk[t].begin(), rowblk[t].end());
     const int32_t lt = h->rank_row[t];
     int64_t K = 0;
-    for (int64_t b : rowblk[t]) K += h->rank_col[h->adm_col[b]];
+    for (int64_t b : rowblk[t]) K += width(b);
     const int32_t blk0 = (int32_t)cblk.size();
-    for (int64_t b : rowblk[t]) cblk.push_back(make_int2(h->rank_col[h->adm_col[b]], (int32_t)xh_off[h->adm_col[b]]));
+    for (int64_t b : rowblk[t])
+      cblk.push_back(make_int2(width(b), (int32_t)(fac[b] ? t_off[b] : xh_off[h->adm_col[b]])));
     for (int32_t r0 = 0; r0 < lt; r0 += kRowChunk) {
       const int32_t hh = std::min(kRowChunk, lt - r0);
       const int32_t g = (int32_t)grp_start.size();
@@ -1318,8 +1426,8 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
       for (int32_t r0 = 0; r0 < lt; r0 += kRowChunk) {
         const int32_t hh = std::min(kRowChunk, lt - r0);
         for (int64_t b : rowblk[t]) {
-          const int32_t ls = h->rank_col[h->adm_col[b]];
-          const cd* Sb = Sh + h->S_off[b];
+          const int32_t ls = (int32_t)width(b);
+          const cd* Sb = fac[b] ? reinterpret_cast<const cd*>(h->SX) + h->SX_off[b] : Sh + h->S_off[b];
           for (int32_t j = 0; j < ls; ++j) {
             cd* dst = st.span(hh);
             std::memcpy(static_cast<void*>(dst), Sb + (int64_t)j * lt + r0, sizeof(cd) * (size_t)hh);
@@ -1390,7 +1498,11 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
     LayoutView L{h->n, nl, FL.ftot, FL.ptot, btot, ztot, nyh, nxh, &leaf_n, &FL.fwd_off, &FL.fwd_cols, &FL.poff, &FL.segs,
                  &bwd_off, &bwd_cols, &zoff, &zmap};
     if ((rc = check_layout(L))) return rc;
-    if ((rc = check_coupling(tiles, cblk, stot, nxh, grp_t0, grp_nt, grp_start, nyh))) return rc;
+    if ((rc = check_coupling(tiles, cblk, stot, nsrc, grp_t0, grp_nt, grp_start, nyh))) return rc;
+    for (const FacTile& F : ftl)
+      if (F.rows < 1 || F.wj < 1 || F.wj > kTile || F.f_base < 0 || F.f_base + (int64_t)F.rows * F.wj > fytot ||
+          F.x_row < 0 || (int64_t)F.x_row + F.rows > nxh || F.t_out < nxh || (int64_t)F.t_out + F.wj > nsrc)
+        return fail(UHM_EINVAL, "layout: factor tile");
   }
 
   uhm_op_info& I = op->info;
@@ -1407,11 +1519,13 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
     I.elems_backward += h->size[c] * h->rank_row[c];
   }
   I.elems_coupling = stot;
+  I.elems_coupling_in = fytot;
   I.elems_near = 0;
   for (int64_t b = 0; b < h->nden; ++b) I.elems_near += h->size[h->den_row[b]] * h->size[h->den_col[b]];
   I.rank_space = nxh;
   I.device_bytes = (int64_t)(op->F.bytes() + op->S.bytes() + op->B.bytes() + op->zmap.bytes() + op->perm.bytes() +
-                             op->ctiles.bytes() + op->cblk.bytes() + op->out_seg.bytes() + op->yh_grp.bytes());
+                             op->ctiles.bytes() + op->cblk.bytes() + op->out_seg.bytes() + op->yh_grp.bytes() +
+                             op->FY.bytes() + op->factiles.bytes());
   *out = op.release();
   return UHM_OK;
 }
@@ -1599,8 +1713,7 @@ int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int
   if (ldx < op->n || ldy < op->n) return fail(UHM_EINVAL, "leading dimension smaller than n");
   const char* xb = static_cast<const char*>(X);
   const char* yb = static_cast<const char*>(Y);
-  const size_t es =
-      (op->storage == UHM_C128 || op->storage == UHM_C128_MULTI || op->storage == UHM_C128_SYM) ? sizeof(cd) : sizeof(float2);
+  const size_t es = is_c128(op->storage) ? sizeof(cd) : sizeof(float2);
   if (xb < yb + (size_t)((nrhs - 1) * ldy + op->n) * es && yb < xb + (size_t)((nrhs - 1) * ldx + op->n) * es)
     return fail(UHM_EINVAL, "X and Y overlap");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -1625,6 +1738,12 @@ int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int
                            op->poff.p, op->out_seg.p, op->seg_start.p, op->seg_leaf0.p, op->seg_nleaf.p, op->seg_col.p,
                            op->nxh, op->ws_xh.p);
       }
+    }
+    if (op->nfactiles > 0) {
+      ScopedTiming tm(op, s, K_FACTOR_IN);
+      hipLaunchKernelGGL(k_factor_in, dim3((unsigned)((op->nfactiles + kCoupWaves - 1) / kCoupWaves)),
+                         dim3(64 * kCoupWaves), 0, s, op->FY.p, op->factiles.p, op->nfactiles, op->ws_xh.p,
+                         op->ws_xh.p);
     }
     const cd* zsrc = op->ws_xh.p;
     if (op->sym) {

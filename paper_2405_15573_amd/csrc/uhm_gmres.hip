@@ -1028,7 +1028,7 @@ int uhm_krylov_step(uhm_krylov* const* ks, uhm_op* const* high, uhm_op* const* l
     uhm_op* A = K->req == UHM_KRYLOV_PRODUCT_HIGH ? high[k] : (low ? low[k] : nullptr);
     if (!A || A->n != K->n || A->kind != 0) return fail(UHM_EINVAL, "missing or mismatched operator for a solve");
     const bool want_hi = K->req == UHM_KRYLOV_PRODUCT_HIGH;
-    const bool is_hi = A->storage == UHM_C128 || A->storage == UHM_C128_MULTI || A->storage == UHM_C128_SYM;
+    const bool is_hi = is_c128(A->storage);
     if (want_hi != is_hi) return fail(UHM_EINVAL, "operator precision does not match the request");
     groups[{A, K->req}].push_back({k, K->req, static_cast<const cd*>(K->req_in), static_cast<cd*>(K->req_out)});
   }
@@ -1174,10 +1174,9 @@ int uhm_krylov_step(uhm_krylov* const* ks, uhm_op* const* high, uhm_op* const* l
 int uhm_solve_gmres(uhm_op* op, uhm_op* inner, const void* B, int64_t ldb, void* X, int64_t ldx, int32_t nrhs,
                     double tol, const uhm_gmres_opts* opts, uhm_gmres_info* info, void* hip_stream) {
   if (!op || !B || !X) return fail(UHM_EINVAL, "null argument");
-  if ((op->storage != UHM_C128 && op->storage != UHM_C128_MULTI && op->storage != UHM_C128_SYM) || op->kind != 0)
+  if (!is_c128(op->storage) || op->kind != 0)
     return fail(UHM_EINVAL, "the residual operator must be a complex128 UH-matrix");
-  if (inner && (inner->storage == UHM_C128 || inner->storage == UHM_C128_MULTI || inner->storage == UHM_C128_SYM ||
-                inner->kind != 0 || inner->n != op->n))
+  if (inner && (is_c128(inner->storage) || inner->kind != 0 || inner->n != op->n))
     return fail(UHM_EINVAL, "the inner operator must be a low-precision form of the same size");
   if (nrhs < 1 || ldx < op->n) return fail(UHM_EINVAL, "bad nrhs or leading dimension");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);

@@ -62,6 +62,16 @@ struct SymTile {
   int32_t x_row;   // rank-space index of the chunk's first row
 };
 
+// A tile of the first step of factored couplings: wj (<= 64) columns of the panel
+// [S_{Y,b1} S_{Y,b2} ...] of one column cluster sigma (l_sigma rows, row-major tile).
+struct FacTile {
+  int64_t f_base;  // element offset of the tile
+  int32_t rows;    // l_sigma
+  int32_t wj;      // columns in the tile
+  int32_t x_row;   // rank-space index of u_sigma
+  int32_t t_out;   // index of the tile's first result in the coupling source vector
+};
+
 template <class T>
 struct DevArray {
   T* p = nullptr;
@@ -228,6 +238,11 @@ struct uhm_op {
   DevArray<int64_t> grp_start;
   int32_t nctiles = 0;
   int64_t nyh = 0;
+  // factored couplings: first step t_b = S_{Y,b}^* u_sigma into the source vector after u
+  DevArray<cd> FY;
+  DevArray<uhm_detail::FacTile> factiles;
+  int32_t nfactiles = 0;
+  int64_t nsrc = 0;  // length of the coupling source vector (u, then the t_b)
   // backward panels
   DevArray<cd> B;
   DevArray<int64_t> bwd_off, zoff;
@@ -267,7 +282,7 @@ namespace uhm_detail {
 enum {
   K_FORWARD = 0, K_REDUCE_FWD, K_COUPLING, K_REDUCE_COUP, K_BACKWARD,
   K_LP_GATHER, K_LP_FORWARD, K_LP_REDUCE_FWD, K_LP_COUPLING, K_LP_REDUCE_COUP, K_LP_BACKWARD, K_LP_SCATTER,
-  K_SYM_COUPLING, K_SYM_REDUCE, K_SYM_BACKWARD, K_SYM_FINISH,
+  K_SYM_COUPLING, K_SYM_REDUCE, K_SYM_BACKWARD, K_SYM_FINISH, K_FACTOR_IN,
   K_COUNT
 };
 extern const char* const kKernelNames[K_COUNT];
@@ -295,6 +310,11 @@ struct ScopedTiming {
 };
 
 inline bool in_bounds(int64_t off, int64_t count, int64_t len) { return off >= 0 && count >= 0 && off + count <= len; }
+
+// Storage forms whose vectors and arithmetic are complex128.
+inline bool is_c128(int storage) {
+  return storage == UHM_C128 || storage == UHM_C128_MULTI || storage == UHM_C128_SYM || storage == UHM_C128_FACTORED;
+}
 
 int common_tree_upload(uhm_op* op, const TreeInfo& T, const int64_t* perm, const int64_t* off, const int64_t* size,
                        hipStream_t s);

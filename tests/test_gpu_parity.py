@@ -185,3 +185,25 @@ def test_symmetric_storage_deterministic_and_rejects_mirrors(torch_dev):
     # the general image lists both blocks of every mirrored pair: not a symmetric image
     with pytest.raises(binding.UhmError):
         binding.upload(op, "c128sym")
+
+
+@pytest.mark.parametrize("surface,n,seed,leaf", CASES + [("sphere", 60, 0, 32), ("sphere", 1, 0, 2)])
+def test_factored_couplings_parity(torch_dev, surface, n, seed, leaf):
+    """Factored couplings (two-step S_{X,b} (S_{Y,b}^* u_sigma) where that stores fewer
+    elements) against the oracle's product with S_b = S_{X,b} S_{Y,b}^* for every block."""
+    from paper_2405_15573_amd import binding
+    print(f"case factored {surface} n={n} seed={seed} leaf={leaf}", flush=True)
+    cloud, op = operator(surface=surface, n=n, seed=seed, leaf=leaf)
+    dop = binding.upload(op, "c128fact")
+    x = inputs.make_rhs(cloud.n, 2, seed=seed + 9)
+    y = _run(torch_dev, dop, x)
+    ref = uniform.uh_mvp(uniform.assemble_factored(vars(op)), x)
+    assert max(_cols_rel(y, ref)) <= TOL
+    info = dop.info()
+    assert info["storage"] == 5
+    if op.nadm:
+        lt = op.rank_row[op.adm_row].astype(np.int64)
+        ls = op.rank_col[op.adm_col].astype(np.int64)
+        k = op.adm_rank.astype(np.int64)
+        assert info["elems_coupling"] + info["elems_coupling_in"] == int(np.minimum(lt * ls, k * (lt + ls)).sum())
+        assert info["elems_coupling_in"] == int((ls * k)[k * (lt + ls) < lt * ls].sum())
