@@ -207,3 +207,37 @@ def test_factored_couplings_parity(torch_dev, surface, n, seed, leaf):
         k = op.adm_rank.astype(np.int64)
         assert info["elems_coupling"] + info["elems_coupling_in"] == int(np.minimum(lt * ls, k * (lt + ls)).sum())
         assert info["elems_coupling_in"] == int((ls * k)[k * (lt + ls) < lt * ls].sum())
+
+
+@pytest.mark.parametrize("form", ["c128sym", "c128fact"])
+def test_symmetric_and_factored_multi_rhs_and_leading_dimension(torch_dev, form):
+    from paper_2405_15573_amd import binding, builder
+    torch = torch_dev
+    print(f"case {form} multi-rhs ld", flush=True)
+    cloud, op = operator(n=3000, seed=3, leaf=64)
+    if form == "c128sym":
+        img = builder.symmetric_image(op)
+        ref_op = uniform.expand_symmetric(img)
+    else:
+        img = op
+        ref_op = uniform.assemble_factored(vars(op))
+    dop = binding.upload(img, form)
+    n, r, ld = cloud.n, 3, cloud.n + 5
+    x = inputs.make_rhs(n, r, seed=22)
+    xbuf = torch.zeros((r, ld), dtype=torch.complex128, device="cuda")
+    xbuf[:, :n] = torch.from_numpy(np.ascontiguousarray(x.T)).to("cuda")
+    ybuf = torch.full((r, ld + 3), 7.0 + 0j, dtype=torch.complex128, device="cuda")
+    dop.matvec(xbuf.t()[:n], ybuf.t()[:n])
+    torch.cuda.synchronize()
+    assert max(_cols_rel(ybuf.t()[:n].cpu().numpy(), uniform.uh_mvp(ref_op, x))) <= TOL
+    assert torch.all(ybuf.t()[n:] == 7.0 + 0j).item()
+
+
+def test_factored_upload_needs_the_factors(torch_dev):
+    from paper_2405_15573_amd import binding
+    cloud, op = operator()
+    bad = dict(vars(op))
+    bad["SX_off"] = op.SX_off.copy()
+    bad["SX_off"][-1] = op.SX.size  # factor runs past the end of SX
+    with pytest.raises(binding.UhmError):
+        binding.upload(bad, "c128fact")
