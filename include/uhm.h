@@ -63,11 +63,14 @@ typedef enum {
                          stored dense block A|_b^T, with V_c = conj(U_c) implied: V, V_off and
                          rank_col are not read.  Each stored element is read once per product
                          and applied both ways.  uhm_upload only; vectors complex128 */
-  UHM_C128_FACTORED = 5 /* complex128 with factored couplings (section 4.2):
+  UHM_C128_FACTORED = 5, /* complex128 with factored couplings (section 4.2):
                          S_b = S_{X,b} S_{Y,b}^*, applied in two steps (S_{Y,b}^* u_sigma, then
                          S_{X,b} times that) for every block where k_b (l_tau + l_sigma) <
                          l_tau l_sigma, assembled S_b elsewhere.  The image must carry adm_rank,
                          SX and SY.  uhm_upload only; vectors complex128 */
+  UHM_C64_FACTORED = 6,     /* UHM_C64 with factored couplings where they store fewer elements
+                               (the same rule); the image must carry adm_rank, SX and SY */
+  UHM_BF16PAIR_FACTORED = 7 /* UHM_BF16PAIR with factored couplings, likewise */
 } uhm_storage;
 
 typedef struct uhm_op uhm_op; /* opaque; owned by the library until uhm_free */

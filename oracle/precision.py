@@ -9,7 +9,7 @@ from the rounding of its storage.
 """
 import numpy as np
 
-ROUNDED_KEYS = ("U", "V", "S", "D")
+ROUNDED_KEYS = ("U", "V", "S", "D", "SX", "SY")
 
 
 def to_f32(a: np.ndarray) -> np.ndarray:
@@ -28,9 +28,11 @@ def to_bf16_pair(a: np.ndarray) -> np.ndarray:
 
 
 def round_operator(op, storage: str) -> dict:
-    """A copy of the operator mapping with U, V, S and D rounded to the storage format."""
+    """A copy of the operator mapping with U, V, S, D and the coupling factors SX, SY (when
+    present) rounded to the storage format."""
     f = {"c64": to_f32, "bf16pair": to_bf16_pair}[storage]
     out = dict(op)
     for k in ROUNDED_KEYS:
-        out[k] = f(np.asarray(op[k]))
+        if op.get(k) is not None:
+            out[k] = f(np.asarray(op[k]))
     return out

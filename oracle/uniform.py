@@ -163,16 +163,21 @@ def expand_symmetric(op: Mapping) -> dict:
     return out
 
 
-def assemble_factored(op: Mapping) -> dict:
+def assemble_factored(op: Mapping, which: str = "all") -> dict:
     """The general UH image whose couplings are the products of their stored factors,
     S_b = S_{X,b} S_{Y,b}^* (section 4.2), S_{X,b} (l_tau x k_b) at SX_off[b] and S_{Y,b}
-    (l_sigma x k_b) at SY_off[b], k_b = adm_rank[b].  The S and S_off entries of the input
-    are not read."""
+    (l_sigma x k_b) at SY_off[b], k_b = adm_rank[b].  which="all" forms every coupling from
+    its factors; which="smaller" only those of the blocks whose factors hold fewer elements,
+    k_b (l_tau + l_sigma) < l_tau l_sigma, and keeps the stored S_b of the others (the
+    operator a per-block choice of the two forms stands for)."""
     out = dict(op)
     rr, rc, k = np.asarray(op["rank_row"]), np.asarray(op["rank_col"]), np.asarray(op["adm_rank"])
     blocks = []
     for b in range(np.asarray(op["adm_row"]).size):
         lt, ls, kb = int(rr[op["adm_row"][b]]), int(rc[op["adm_col"][b]]), int(k[b])
+        if which == "smaller" and not kb * (lt + ls) < lt * ls:
+            blocks.append(_colmajor(op["S"], int(op["S_off"][b]), lt, ls))
+            continue
         sx = _colmajor(op["SX"], int(op["SX_off"][b]), lt, kb)
         sy = _colmajor(op["SY"], int(op["SY_off"][b]), ls, kb)
         blocks.append(sx @ sy.conj().T)

@@ -15,7 +15,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libuhm.so")
 
 UHM_OK, UHM_EINVAL, UHM_ENOMEM, UHM_EHIP, UHM_ENOCONV, UHM_ENOTSUP = 0, -1, -2, -3, -4, -5
-STORAGE = {"c128": 0, "c64": 1, "bf16pair": 2, "c128multi": 3, "c128sym": 4, "c128fact": 5}
+STORAGE = {"c128": 0, "c64": 1, "bf16pair": 2, "c128multi": 3, "c128sym": 4, "c128fact": 5, "c64fact": 6,
+           "bf16pairfact": 7}
+FACTORED_FORMS = ("c128fact", "c64fact", "bf16pairfact")
 C128_FORMS = ("c128", "c128multi", "c128sym", "c128fact")
 
 P = ctypes.c_void_p
@@ -262,7 +264,7 @@ def upload(op, storage: str = "c128", stream=None) -> DeviceOperator:
     h.D_off = a("D_off", np.int64)
     h.D = a("D", np.complex128)
     h.D_len = keep["D"].size
-    if storage == "c128fact":
+    if storage in FACTORED_FORMS:
         h.adm_rank = a("adm_rank", np.int32)
         h.SX_off = a("SX_off", np.int64)
         h.SY_off = a("SY_off", np.int64)

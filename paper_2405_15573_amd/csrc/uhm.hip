@@ -36,7 +36,7 @@ const char* const kKernelNames[K_COUNT] = {
     "k_forward_tiles", "k_reduce_segments", "k_coupling", "k_reduce_coupling", "k_backward",
     "k_lp_gather", "k_lp_forward", "k_lp_reduce_segments", "k_lp_coupling", "k_lp_reduce_coupling",
     "k_lp_backward", "k_lp_scatter", "k_coupling_sym", "k_reduce_sym", "k_backward_sym", "k_finish_sym",
-    "k_factor_in"};
+    "k_factor_in", "k_lp_factor_in", "k_lp_reduce_factor"};
 
 int check_tree(int64_t n, const int64_t* perm, int32_t nc, const int64_t* off, const int64_t* size,
                const int32_t* parent, TreeInfo& T) {
@@ -1239,7 +1239,8 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
   if (!h || !out) return fail(UHM_EINVAL, "null argument");
   *out = nullptr;
   if (storage != UHM_C128 && storage != UHM_C64 && storage != UHM_BF16PAIR && storage != UHM_C128_MULTI &&
-      storage != UHM_C128_SYM && storage != UHM_C128_FACTORED)
+      storage != UHM_C128_SYM && storage != UHM_C128_FACTORED && storage != UHM_C64_FACTORED &&
+      storage != UHM_BF16PAIR_FACTORED)
     return fail(UHM_EINVAL, "unknown storage precision");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   TreeInfo T;
@@ -1281,7 +1282,8 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
     if (!in_bounds(h->D_off[b], h->size[t] * h->size[sg], h->D_len)) return fail(UHM_EINVAL, "D_off out of bounds");
   }
   // factored couplings: which blocks take the two-step form (fewer stored elements)
-  const bool factored = storage == UHM_C128_FACTORED;
+  const bool factored =
+      storage == UHM_C128_FACTORED || storage == UHM_C64_FACTORED || storage == UHM_BF16PAIR_FACTORED;
   std::vector<char> fac(h->nadm, 0);
   if (factored) {
     if (h->nadm > 0 && (!h->adm_rank || !h->SX_off || !h->SY_off || !h->SX || !h->SY))

@@ -827,6 +827,16 @@ struct LowpOp {
     int32_t h, nkb_all;
   };
   std::vector<Chunk> chunks;
+  // factored couplings (section 4.2): a first coupling pass whose rows are the t_b =
+  // S_{Y,b}^* u_sigma of the factored blocks, grouped by column cluster sigma; its results
+  // go to rows nxh .. nxh + ntf of the xh buffer, where the main pass reads them
+  DevArray<uint4> ST;
+  DevArray<int64_t> tgrp_start;
+  DevArray<int32_t> tcolsrc, tyh_grp, tgrp_t0, tgrp_nt;
+  DevArray<LpCoupTile> tctiles;
+  int32_t ntctiles = 0;
+  int64_t ntf = 0;
+  std::vector<Chunk> tchunks;
   std::vector<int32_t> f_M_h, b_nkb_h, f_nkb_h, leaf_n_h;
   // workspace, sized for R columns
   int wsR = 0;
@@ -898,7 +908,7 @@ using C = std::complex<double>;
 inline C cget(const double* a, int64_t idx) { return C(a[2 * idx], a[2 * idx + 1]); }
 
 template <int ST>
-int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, uhm_op* op, LowpOp* lp) {
+int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, uhm_op* op, LowpOp* lp, bool fact) {
   constexpr int KB = Tr<ST>::KB;
   const int32_t nc = h->nclusters;
   const int32_t nl = (int32_t)T.leaves.size();
@@ -1014,9 +1024,101 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
   }
   lp->nxh = nxh;
 
-  // ---- couplings: row chunks of 64 rows, K padded to KB, tiles of kLpCoupK columns
+  // ---- factored couplings: blocks with k_b (l_tau + l_sigma) < l_tau l_sigma keep their
+  // factors; t_b = S_{Y,b}^* u_sigma is row t_off[b] .. of the t part of the xh buffer
+  std::vector<char> fac(h->nadm, 0);
+  std::vector<int64_t> t_off(h->nadm, -1);
+  std::vector<std::vector<int64_t>> colfac(nc);
+  int64_t ntf = 0;
+  if (fact)
+    for (int64_t b = 0; b < h->nadm; ++b) {
+      const int64_t lt = h->rank_row[h->adm_row[b]], ls = h->rank_col[h->adm_col[b]], k = h->adm_rank[b];
+      fac[b] = k * (lt + ls) < lt * ls;
+      if (fac[b]) colfac[h->adm_col[b]].push_back(b);
+    }
+  for (int32_t c = 0; c < nc; ++c)
+    for (int64_t b : colfac[c]) {
+      t_off[b] = ntf;
+      ntf += h->adm_rank[b];
+    }
+  if (nxh + ntf > INT32_MAX / kLpRmax) return fail(UHM_ENOTSUP, "rank space too large");
+  {
+    // first pass: for each column cluster sigma with factored blocks, the rows are the
+    // columns of [S_{Y,b1} S_{Y,b2} ...] (conjugated), the columns are u_sigma
+    std::vector<LpCoupTile> tt;
+    std::vector<int32_t> tcs, tg0, tgn, tyg(ntf);
+    std::vector<int64_t> tgs;
+    struct TJob {
+      int64_t m0, base;
+      int32_t sg, hh, nkb;
+    };
+    std::vector<TJob> tj;
+    int64_t tot = 0;
+    constexpr int KBT = kLpCoupK / KB;
+    for (int32_t c = 0; c < nc; ++c) {
+      if (colfac[c].empty()) continue;
+      const int32_t ls = h->rank_col[c];
+      const int32_t nkb = (ls + KB - 1) / KB;
+      const int64_t csrc = (int64_t)tcs.size();
+      for (int32_t j = 0; j < ls; ++j) tcs.push_back((int32_t)(xh_off[c] + j));
+      while ((int64_t)tcs.size() < csrc + (int64_t)nkb * KB) tcs.push_back(-1);
+      int64_t M = 0;
+      for (int64_t b : colfac[c]) M += h->adm_rank[b];
+      const int64_t m0 = t_off[colfac[c][0]];
+      for (int64_t r0 = 0; r0 < M; r0 += 64) {
+        const int32_t hh = (int32_t)std::min<int64_t>(64, M - r0);
+        const int32_t gi = (int32_t)tgs.size();
+        tgs.push_back(m0 + r0);
+        tg0.push_back((int32_t)tt.size());
+        for (int32_t r = 0; r < hh; ++r) tyg[m0 + r0 + r] = gi;
+        for (int32_t kb0 = 0; kb0 < nkb; kb0 += KBT)
+          tt.push_back({tot, csrc, hh, nkb, kb0, std::min(KBT, nkb - kb0), (int32_t)tt.size()});
+        tgn.push_back((int32_t)tt.size() - tg0.back());
+        tj.push_back({m0 + r0, tot, c, hh, nkb});
+        lp->tchunks.push_back({tot, csrc, hh, nkb});
+        tot += panel_chunks<ST>(hh, nkb);
+      }
+    }
+    if ((rc = lp->ST.alloc(tot))) return rc;
+    if (tot > 0) {
+      std::vector<const double*> trow(ntf);  // t row -> start of its S_{Y,b} column
+      for (int32_t c = 0; c < nc; ++c)
+        for (int64_t b : colfac[c])
+          for (int32_t j = 0; j < h->adm_rank[b]; ++j)
+            trow[t_off[b] + j] = h->SY + 2 * (h->SY_off[b] + (int64_t)j * h->rank_col[c]);
+      StagerT<uint4> st;
+      if ((rc = st.init(lp->ST.p, tot, s))) return rc;
+      for (const TJob& J : tj) {
+        if (st.err) break;
+        const int32_t ls = h->rank_col[J.sg];
+        if ((rc = pack_panel<ST>(st, J.hh, J.nkb, [&](int32_t m, int32_t k) -> C {
+               return k < ls ? std::conj(cget(trow[J.m0 + m], k)) : C(0.0, 0.0);
+             })))
+          return rc;
+      }
+      if ((rc = st.finish())) return rc;
+    }
+    for (const LpCoupTile& Tt : tt)
+      if (Tt.h < 1 || Tt.h > 64 || Tt.base < 0 || Tt.base + panel_chunks<ST>(Tt.h, Tt.nkb_all) > tot || Tt.kb0 < 0 ||
+          Tt.nkb < 1 || Tt.kb0 + Tt.nkb > Tt.nkb_all || Tt.csrc + (int64_t)Tt.nkb_all * KB > (int64_t)tcs.size())
+        return fail(UHM_EINVAL, "layout: factor tile");
+    for (int32_t v : tcs)
+      if (v >= nxh) return fail(UHM_EINVAL, "layout: factor column source");
+    for (size_t g = 0; g < tgs.size(); ++g)
+      if (tgs[g] < 0 || tgs[g] + tt[tg0[g]].h > ntf || tgn[g] < 1 || (size_t)tg0[g] + tgn[g] > tt.size())
+        return fail(UHM_EINVAL, "layout: factor group");
+    if ((rc = lp->tctiles.upload(tt, s)) || (rc = lp->tcolsrc.upload(tcs, s)) || (rc = lp->tyh_grp.upload(tyg, s)) ||
+        (rc = lp->tgrp_start.upload(tgs, s)) || (rc = lp->tgrp_t0.upload(tg0, s)) || (rc = lp->tgrp_nt.upload(tgn, s)))
+      return rc;
+    lp->ntctiles = (int32_t)tt.size();
+    lp->ntf = ntf;
+  }
+
+  // ---- couplings: row chunks of 64 rows, K padded to KB, tiles of kLpCoupK columns; a
+  // factored block contributes S_{X,b} (columns reading t_b) in place of S_b (reading u_sigma)
   std::vector<std::vector<int64_t>> rowblk(nc);
   for (int64_t b = 0; b < h->nadm; ++b) rowblk[h->adm_row[b]].push_back(b);
+  auto width = [&](int64_t b) -> int32_t { return fac[b] ? h->adm_rank[b] : h->rank_col[h->adm_col[b]]; };
   std::vector<LpCoupTile> tiles;
   std::vector<int32_t> colsrc, grp_t0, grp_nt, yh_grp(nyh);
   std::vector<int64_t> grp_start;
@@ -1032,11 +1134,12 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
     std::sort(rowblk[t].begin(), rowblk[t].end());
     const int32_t lt = h->rank_row[t];
     int64_t K = 0;
-    for (int64_t b : rowblk[t]) K += h->rank_col[h->adm_col[b]];
+    for (int64_t b : rowblk[t]) K += width(b);
     const int32_t nkb = (int32_t)((K + KB - 1) / KB);
     const int64_t csrc = (int64_t)colsrc.size();
     for (int64_t b : rowblk[t])
-      for (int32_t j = 0; j < h->rank_col[h->adm_col[b]]; ++j) colsrc.push_back((int32_t)(xh_off[h->adm_col[b]] + j));
+      for (int32_t j = 0; j < width(b); ++j)
+        colsrc.push_back((int32_t)(fac[b] ? nxh + t_off[b] + j : xh_off[h->adm_col[b]] + j));
     while ((int64_t)colsrc.size() < csrc + (int64_t)nkb * KB) colsrc.push_back(-1);
     for (int32_t r0 = 0; r0 < lt; r0 += 64) {
       const int32_t hh = std::min(64, lt - r0);
@@ -1063,8 +1166,10 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
       const int32_t lt = h->rank_row[J.tau];
       colp.clear();
       for (int64_t b : rowblk[J.tau])
-        for (int32_t j = 0; j < h->rank_col[h->adm_col[b]]; ++j)
-          colp.push_back({h->S + 2 * (h->S_off[b] + (int64_t)j * lt + J.r0), lt});
+        for (int32_t j = 0; j < width(b); ++j)
+          colp.push_back({fac[b] ? h->SX + 2 * (h->SX_off[b] + (int64_t)j * lt + J.r0)
+                                 : h->S + 2 * (h->S_off[b] + (int64_t)j * lt + J.r0),
+                          lt});
       const int64_t K = (int64_t)colp.size();
       if ((rc = pack_panel<ST>(st, J.h, J.nkb, [&](int32_t m, int32_t k) -> C {
              return k < K ? cget(colp[k].first, m) : C(0.0, 0.0);
@@ -1079,7 +1184,7 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
       return fail(UHM_EINVAL, "layout: coupling tile");
   }
   for (int32_t v : colsrc)
-    if (v >= nxh) return fail(UHM_EINVAL, "layout: coupling column source");
+    if (v >= nxh + ntf) return fail(UHM_EINVAL, "layout: coupling column source");
   if ((rc = lp->ctiles.upload(tiles, s)) || (rc = lp->colsrc.upload(colsrc, s)) || (rc = lp->yh_grp.upload(yh_grp, s)) ||
       (rc = lp->grp_start.upload(grp_start, s)) || (rc = lp->grp_t0.upload(grp_t0, s)) ||
       (rc = lp->grp_nt.upload(grp_nt, s)))
@@ -1146,7 +1251,7 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
   uhm_op_info& I = op->info;
   I.n = h->n;
   I.kind = 0;
-  I.storage = ST;
+  I.storage = op->storage;
   I.nleaves = nl;
   I.elem_bytes = ST == UHM_C64 ? 8 : (ST == UHM_BF16PAIR ? 4 : 16);
   I.nadm = h->nadm;
@@ -1156,10 +1261,16 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
     I.elems_forward += h->size[c] * h->rank_col[c];
     I.elems_backward += h->size[c] * h->rank_row[c];
   }
-  for (int64_t b = 0; b < h->nadm; ++b) I.elems_coupling += (int64_t)h->rank_row[h->adm_row[b]] * h->rank_col[h->adm_col[b]];
+  I.elems_coupling_in = 0;
+  for (int64_t b = 0; b < h->nadm; ++b) {
+    const int64_t lt = h->rank_row[h->adm_row[b]], ls = h->rank_col[h->adm_col[b]];
+    I.elems_coupling += fac[b] ? lt * h->adm_rank[b] : lt * ls;
+    if (fac[b]) I.elems_coupling_in += ls * h->adm_rank[b];
+  }
   for (int64_t b = 0; b < h->nden; ++b) I.elems_near += h->size[h->den_row[b]] * h->size[h->den_col[b]];
   I.rank_space = nxh;
-  I.device_bytes = (int64_t)(lp->F.bytes() + lp->S.bytes() + lp->B.bytes() + lp->zmap.bytes() + lp->colsrc.bytes());
+  I.device_bytes = (int64_t)(lp->F.bytes() + lp->S.bytes() + lp->B.bytes() + lp->zmap.bytes() + lp->colsrc.bytes() +
+                             lp->ST.bytes() + lp->tcolsrc.bytes());
   return UHM_OK;
 }
 
@@ -1192,6 +1303,18 @@ void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, i
       hipLaunchKernelGGL(k_lp_reduce_segments<V>, dim3((unsigned)((lp->nxh * R + 255) / 256)), dim3(256), 0, s, p, R,
                          lp->poff.p, lp->out_seg.p, lp->seg_start.p, lp->seg_pan0.p, lp->seg_npan.p, lp->seg_col.p,
                          lp->nxh, xh);
+    }
+  }
+  if (lp->ntctiles > 0) {
+    {
+      ScopedTiming tm(op, s, K_LP_FACTOR_IN);
+      hipLaunchKernelGGL((k_lp_coupling<ST, NT>), dim3(lp->ntctiles), dim3(64 * kLpWaves), 0, s, lp->ST.p, lp->tctiles.p,
+                         lp->tcolsrc.p, xh, R, part);
+    }
+    {
+      ScopedTiming tm(op, s, K_LP_REDUCE_FACTOR);
+      hipLaunchKernelGGL(k_lp_reduce_coupling<V>, dim3((unsigned)((lp->ntf * R + 255) / 256)), dim3(256), 0, s, part, R,
+                         lp->tyh_grp.p, lp->tgrp_start.p, lp->tgrp_t0.p, lp->tgrp_nt.p, lp->ntf, xh + lp->nxh * R);
     }
   }
   if (lp->nctiles > 0) {
@@ -1234,8 +1357,8 @@ int grow(LowpOp* lp, int64_t n, int R) {
   int rc;
   if ((rc = lp->Xc.alloc(e * n * R)) || (rc = lp->Yc.alloc(e * n * R)) ||
       (rc = lp->p.alloc(e * std::max<int64_t>(1, lp->p_rows * R))) ||
-      (rc = lp->xh.alloc(e * std::max<int64_t>(1, lp->nxh * R))) ||
-      (rc = lp->part.alloc(e * std::max<int64_t>(1, (int64_t)lp->nctiles * 64 * R))) ||
+      (rc = lp->xh.alloc(e * std::max<int64_t>(1, (lp->nxh + lp->ntf) * R))) ||
+      (rc = lp->part.alloc(e * std::max<int64_t>(1, (int64_t)std::max(lp->nctiles, lp->ntctiles) * 64 * R))) ||
       (rc = lp->yh.alloc(e * std::max<int64_t>(1, lp->nyh * R)))) {
     lp->wsR = 0;
     return rc;
@@ -1249,17 +1372,20 @@ int grow(LowpOp* lp, int64_t n, int R) {
 int lowp_upload(const uhm_host_operator* h, uhm_storage storage, hipStream_t s, const TreeInfo& T, uhm_op* op) {
   std::unique_ptr<LowpOp> lp(new (std::nothrow) LowpOp);
   if (!lp) return fail(UHM_ENOMEM, "host allocation");
-  lp->storage = storage;
+  // the factored forms run the kernels of their base form
+  const bool fact = storage == UHM_C64_FACTORED || storage == UHM_BF16PAIR_FACTORED;
+  const int base = storage == UHM_C64_FACTORED ? UHM_C64 : storage == UHM_BF16PAIR_FACTORED ? UHM_BF16PAIR : storage;
+  lp->storage = base;
   int rc;
-  if (storage == UHM_C64) {
+  if (base == UHM_C64) {
     lp->KB = Tr<UHM_C64>::KB;
-    rc = lowp_upload_t<UHM_C64>(h, s, T, op, lp.get());
-  } else if (storage == UHM_BF16PAIR) {
+    rc = lowp_upload_t<UHM_C64>(h, s, T, op, lp.get(), fact);
+  } else if (base == UHM_BF16PAIR) {
     lp->KB = Tr<UHM_BF16PAIR>::KB;
-    rc = lowp_upload_t<UHM_BF16PAIR>(h, s, T, op, lp.get());
+    rc = lowp_upload_t<UHM_BF16PAIR>(h, s, T, op, lp.get(), fact);
   } else {
     lp->KB = Tr<UHM_C128_MULTI>::KB;
-    rc = lowp_upload_t<UHM_C128_MULTI>(h, s, T, op, lp.get());
+    rc = lowp_upload_t<UHM_C128_MULTI>(h, s, T, op, lp.get(), fact);
   }
   if (rc) return rc;
   op->lp = lp.release();
@@ -1314,9 +1440,9 @@ struct BatchOp {
   int64_t ldx, ldy;
   int32_t r;
   DevArray<unsigned char> Xc, Yc, p, xh, part, yh;
-  DevArray<LpCoupTile> tiles;
-  DevArray<int32_t> grp_t0, grp_nt;
-  int32_t ntiles = 0;
+  DevArray<LpCoupTile> tiles, ftiles;  // ftiles: first pass of factored couplings
+  DevArray<int32_t> grp_t0, grp_nt, fgrp_t0, fgrp_nt;
+  int32_t ntiles = 0, nftiles = 0;
   int64_t part_cap = 0;  // partial-sum slots allocated (tiles * 64 * R elements)
 };
 
@@ -1329,7 +1455,7 @@ struct LowpBatch {
   BatchConfig cfg;
   bool configured = false;
   DevArray<LpDesc> desc;
-  DevArray<int2> w_gather, w_forward, w_rseg, w_coup, w_rcoup, w_backward, w_scatter;
+  DevArray<int2> w_gather, w_forward, w_rseg, w_fcoup, w_frcoup, w_coup, w_rcoup, w_backward, w_scatter;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::string signature;
@@ -1410,13 +1536,31 @@ LpDesc desc_of(uhm_op* op) {
   return d;
 }
 
+// The descriptor of an operator's first factored-coupling pass, from the descriptor d of its
+// main passes: the coupling stage reads the t-rows panel and writes into rows nxh .. of xh.
+LpDesc factor_desc(const LowpOp* lp, const LpDesc& d, const LpCoupTile* tiles, const int32_t* t0, const int32_t* nt,
+                   int64_t ebytes) {
+  LpDesc f = d;
+  f.S = lp->ST.p;
+  f.colsrc = lp->tcolsrc.p;
+  f.ctiles = tiles;
+  f.grp_t0 = t0;
+  f.grp_nt = nt;
+  f.grp_start = lp->tgrp_start.p;
+  f.yh_grp = lp->tyh_grp.p;
+  f.nyh = lp->ntf;
+  f.yh = static_cast<unsigned char*>(d.xh) + ebytes * lp->nxh * d.R;
+  return f;
+}
+
 int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
   const int KB = B->ops[0]->op->lp->KB;
   const int64_t e = B->storage == UHM_C128_MULTI ? 16 : 8;
   const int R = B->R;
-  std::vector<LpDesc> descs;
-  std::vector<int2> wg, wf, wrs, wc, wrc, wb, wsc;
-  std::vector<int64_t> cf_, cc_, cb_;
+  std::vector<LpDesc> descs, fdescs;
+  std::vector<int2> wg, wf, wrs, wfc, wfrc, wc, wrc, wb, wsc;
+  std::vector<int64_t> cf_, cfc_, cc_, cb_;
+  const int32_t nops = (int32_t)B->ops.size();
   int rc;
   for (size_t k = 0; k < B->ops.size(); ++k) {
     BatchOp& bo = *B->ops[k];
@@ -1434,7 +1578,19 @@ int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
     }
     if ((rc = bo.tiles.upload(tiles, s)) || (rc = bo.grp_t0.upload(t0, s)) || (rc = bo.grp_nt.upload(nt, s))) return rc;
     bo.ntiles = (int32_t)tiles.size();
-    const int64_t need = std::max<int64_t>(1, (int64_t)bo.ntiles * 64 * R);
+    // the same tiling of the first pass of factored couplings
+    std::vector<LpCoupTile> ftiles;
+    std::vector<int32_t> ft0, fnt;
+    for (const LowpOp::Chunk& c : lp->tchunks) {
+      ft0.push_back((int32_t)ftiles.size());
+      for (int32_t kb0 = 0; kb0 < c.nkb_all; kb0 += kbt)
+        ftiles.push_back({c.base, c.csrc, c.h, c.nkb_all, kb0, std::min(kbt, c.nkb_all - kb0), (int32_t)ftiles.size()});
+      fnt.push_back((int32_t)ftiles.size() - ft0.back());
+    }
+    if ((rc = bo.ftiles.upload(ftiles, s)) || (rc = bo.fgrp_t0.upload(ft0, s)) || (rc = bo.fgrp_nt.upload(fnt, s)))
+      return rc;
+    bo.nftiles = (int32_t)ftiles.size();
+    const int64_t need = std::max<int64_t>(1, (int64_t)std::max(bo.ntiles, bo.nftiles) * 64 * R);
     if (bo.part_cap < need) {
       if ((rc = bo.part.alloc(e * need))) return rc;
       bo.part_cap = need;
@@ -1475,12 +1631,24 @@ int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
       wb.push_back(make_int2(ki, l));
       cb_.push_back((int64_t)lp->leaf_n_h[l] * lp->b_nkb_h[l]);
     }
+    if (bo.nftiles > 0) {
+      const int32_t fi = nops + (int32_t)fdescs.size();
+      fdescs.push_back(factor_desc(lp, d, bo.ftiles.p, bo.fgrp_t0.p, bo.fgrp_nt.p, e));
+      for (int32_t t = 0; t < bo.nftiles; ++t) {
+        wfc.push_back(make_int2(fi, t));
+        cfc_.push_back((int64_t)ftiles[t].h * ftiles[t].nkb);
+      }
+      for (int64_t b = 0; b < ceil_div(lp->ntf * R, 256); ++b) wfrc.push_back(make_int2(fi, (int32_t)b));
+    }
   }
+  descs.insert(descs.end(), fdescs.begin(), fdescs.end());
   order_work(wf, cf_, cfg.order);
+  order_work(wfc, cfc_, cfg.order);
   order_work(wc, cc_, cfg.order);
   order_work(wb, cb_, cfg.order);
   if ((rc = B->desc.upload(descs, s)) || (rc = B->w_gather.upload(wg, s)) || (rc = B->w_forward.upload(wf, s)) ||
-      (rc = B->w_rseg.upload(wrs, s)) || (rc = B->w_coup.upload(wc, s)) || (rc = B->w_rcoup.upload(wrc, s)) ||
+      (rc = B->w_rseg.upload(wrs, s)) || (rc = B->w_fcoup.upload(wfc, s)) || (rc = B->w_frcoup.upload(wfrc, s)) ||
+      (rc = B->w_coup.upload(wc, s)) || (rc = B->w_rcoup.upload(wrc, s)) ||
       (rc = B->w_backward.upload(wb, s)) || (rc = B->w_scatter.upload(wsc, s)))
     return rc;
   UHM_HIP(hipStreamSynchronize(s));
@@ -1507,6 +1675,8 @@ void batch_launch_t(LowpBatch* B, hipStream_t s) {
   go(k_lpb_gather<V>, B->w_gather, 256);
   go(k_lpb_forward<ST, NT>, B->w_forward, 64 * kLpWaves);
   go(k_lpb_reduce_segments<V>, B->w_rseg, 256);
+  go(k_lpb_coupling<ST, NT>, B->w_fcoup, 64 * kLpWaves);  // factored couplings, first pass
+  go(k_lpb_reduce_coupling<V>, B->w_frcoup, 256);
   go(k_lpb_coupling<ST, NT>, B->w_coup, 64 * kLpWaves);
   go(k_lpb_reduce_coupling<V>, B->w_rcoup, 256);
   go(k_lpb_backward<ST, NT>, B->w_backward, 64 * kLpWaves);
@@ -1562,6 +1732,8 @@ void step_launch(const LpDesc* D, const int2* const* w, const unsigned* cnt, hip
   go(k_lpb_gather<V>, 0, 256);
   go(k_lpb_forward<ST, NT>, 1, 64 * kLpWaves);
   go(k_lpb_reduce_segments<V>, 2, 256);
+  go(k_lpb_coupling<ST, NT>, 7, 64 * kLpWaves);  // factored couplings, first pass
+  go(k_lpb_reduce_coupling<V>, 8, 256);
   go(k_lpb_coupling<ST, NT>, 3, 64 * kLpWaves);
   go(k_lpb_reduce_coupling<V>, 4, 256);
   go(k_lpb_backward<ST, NT>, 5, 64 * kLpWaves);
@@ -1593,8 +1765,9 @@ int lowp_step_products(uhm_op* const* ops, const cd* const* const* xcol, cd* con
     maxc = std::max(maxc, (int)ncols[k]);
   }
   const int R = 16 * ((maxc + 15) / 16);
-  std::vector<LpDesc> descs;
-  std::vector<int2> w[7];
+  const int64_t e = storage == UHM_C128_MULTI ? 16 : 8;
+  std::vector<LpDesc> descs, fdescs;
+  std::vector<int2> w[9];  // stages 7, 8: the first pass of factored couplings (run after stage 2)
   int rc;
   for (int32_t k = 0; k < nops; ++k) {
     uhm_op* op = ops[k];
@@ -1626,11 +1799,18 @@ int lowp_step_products(uhm_op* const* ops, const cd* const* const* xcol, cd* con
       for (int64_t b = 0; b < ceil_div(lp->nyh * R, 256); ++b) w[4].push_back(make_int2(ki, (int32_t)b));
     for (int32_t l = 0; l < op->nleaves; ++l) w[5].push_back(make_int2(ki, l));
     for (int64_t b = 0; b < ceil_div(op->n * (int64_t)ncols[k], 256); ++b) w[6].push_back(make_int2(ki, (int32_t)b));
+    if (lp->ntctiles > 0) {
+      const int32_t fi = nops + (int32_t)fdescs.size();
+      fdescs.push_back(factor_desc(lp, d, lp->tctiles.p, lp->tgrp_t0.p, lp->tgrp_nt.p, e));
+      for (int32_t t = 0; t < lp->ntctiles; ++t) w[7].push_back(make_int2(fi, t));
+      for (int64_t b = 0; b < ceil_div(lp->ntf * R, 256); ++b) w[8].push_back(make_int2(fi, (int32_t)b));
+    }
   }
-  size_t off[8];
+  descs.insert(descs.end(), fdescs.begin(), fdescs.end());
+  size_t off[10];
   off[0] = (sizeof(LpDesc) * descs.size() + 15) & ~size_t(15);
-  for (int st = 0; st < 7; ++st) off[st + 1] = off[st] + ((sizeof(int2) * w[st].size() + 15) & ~size_t(15));
-  const size_t tot = off[7];
+  for (int st = 0; st < 9; ++st) off[st + 1] = off[st] + ((sizeof(int2) * w[st].size() + 15) & ~size_t(15));
+  const size_t tot = off[9];
   StepProducts& sp = step_products();
   if (sp.recorded) UHM_HIP(hipEventSynchronize(sp.ev));
   if (!sp.ev) UHM_HIP(hipEventCreateWithFlags(&sp.ev, hipEventDisableTiming));
@@ -1645,9 +1825,9 @@ int lowp_step_products(uhm_op* const* ops, const cd* const* const* xcol, cd* con
     sp.cap = cap;
   }
   std::memcpy(sp.host, descs.data(), sizeof(LpDesc) * descs.size());
-  const int2* dw[7];
-  unsigned cnt[7];
-  for (int st = 0; st < 7; ++st) {
+  const int2* dw[9];
+  unsigned cnt[9];
+  for (int st = 0; st < 9; ++st) {
     std::memcpy(sp.host + off[st], w[st].data(), sizeof(int2) * w[st].size());
     dw[st] = reinterpret_cast<const int2*>(sp.dev + off[st]);
     cnt[st] = (unsigned)w[st].size();
@@ -1681,7 +1861,7 @@ int lowp_batch_create(uhm_op* const* ops, int32_t nops, const void* const* X, co
     if (!X[k] || !Y[k] || ldx[k] < ops[k]->n || ldy[k] < ops[k]->n) return fail(UHM_EINVAL, "bad vector or leading dimension");
     rmax = std::max(rmax, (int)nrhs[k]);
   }
-  B->storage = ops[0]->storage;
+  B->storage = ops[0]->lp->storage;  // the kernels of the base form (factored forms included)
   B->R = 16 * ((rmax + 15) / 16);
   const int64_t e = B->storage == UHM_C128_MULTI ? 16 : 8;
   std::string sig = "st" + std::to_string(B->storage) + "R" + std::to_string(B->R);
@@ -1700,11 +1880,11 @@ int lowp_batch_create(uhm_op* const* ops, int32_t nops, const void* const* X, co
     int rc;
     if ((rc = bo->Xc.alloc(e * op->n * R)) || (rc = bo->Yc.alloc(e * op->n * R)) ||
         (rc = bo->p.alloc(e * std::max<int64_t>(1, lp->p_rows * R))) ||
-        (rc = bo->xh.alloc(e * std::max<int64_t>(1, lp->nxh * R))) ||
+        (rc = bo->xh.alloc(e * std::max<int64_t>(1, (lp->nxh + lp->ntf) * R))) ||
         (rc = bo->yh.alloc(e * std::max<int64_t>(1, lp->nyh * R))))
       return rc;
     sig += "|" + std::to_string(op->n) + "," + std::to_string(lp->nxh) + "," + std::to_string(lp->nyh) + "," +
-           std::to_string(lp->chunks.size()) + "," + std::to_string(nrhs[k]);
+           std::to_string(lp->chunks.size()) + "," + std::to_string(lp->tchunks.size()) + "," + std::to_string(nrhs[k]);
     B->ops.push_back(std::move(bo));
   }
   B->signature = sig;

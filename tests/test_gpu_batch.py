@@ -45,7 +45,7 @@ def _setup(torch, storage, rhs):
     return ops, dops, xs, ys, xn
 
 
-@pytest.mark.parametrize("storage", ["c64", "bf16pair", "c128multi"])
+@pytest.mark.parametrize("storage", ["c64", "bf16pair", "c128multi", "c64fact"])
 def test_batch_equals_individual_products(torch_dev, storage):
     from paper_2405_15573_amd import binding
     torch = torch_dev
@@ -62,6 +62,9 @@ def test_batch_equals_individual_products(torch_dev, storage):
         if storage == "c128multi":
             ref = uniform.uh_mvp(vars(op), xn[k])
             tol = 1e-12
+        elif storage.endswith("fact"):
+            ref = uniform.uh_mvp(uniform.assemble_factored(precision.round_operator(vars(op), storage[:-4]), "smaller"), xn[k])
+            tol = 2e-5
         else:
             ref = uniform.uh_mvp(precision.round_operator(vars(op), storage), xn[k])
             tol = 2e-5

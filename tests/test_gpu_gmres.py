@@ -34,7 +34,7 @@ def _solve(torch, op, b, tol, inner_storage=None, **kw):
     return x.cpu().numpy(), info, rc
 
 
-@pytest.mark.parametrize("inner", [None, "c64", "bf16pair"])
+@pytest.mark.parametrize("inner", [None, "c64", "bf16pair", "c64fact", "bf16pairfact"])
 def test_gmres_solves_against_dense_solution(torch_dev, inner):
     print(f"case gmres inner={inner}", flush=True)
     cloud, op = operator()

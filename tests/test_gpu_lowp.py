@@ -113,3 +113,33 @@ def test_c128multi_parity(torch_dev, nrhs):
         torch.cuda.synchronize()
         y = ybuf.t()[:cloud.n].cpu().numpy()
         assert _col_rel(y, uniform.uh_mvp(vars(op), x)).max() <= 1e-12
+
+
+@pytest.mark.parametrize("storage", ["c64fact", "bf16pairfact"])
+@pytest.mark.parametrize("surface,n,seed,leaf,nrhs", [("sphere", 2048, 0, 32, 1), ("sphere", 3000, 3, 64, 17),
+                                                      ("cube", 1300, 5, 32, 64), ("ellipsoid", 1500, 4, 32, 3)])
+def test_lowp_factored_couplings(torch_dev, storage, surface, n, seed, leaf, nrhs):
+    """Factored couplings on the matrix cores: a first coupling pass forms S_{Y,b}^* u_sigma,
+    the main pass applies S_{X,b}.  Reference: the FP64 definition with S_b = S_{X,b} S_{Y,b}^*
+    formed from the factors rounded to the storage format where the factors are stored, and
+    the rounded S_b elsewhere (the two roundings differ by the storage precision)."""
+    from paper_2405_15573_amd import binding
+    base = storage[:-4]
+    print(f"case {storage} {surface} n={n} nrhs={nrhs}", flush=True)
+    cloud, op = operator(surface=surface, n=n, seed=seed, leaf=leaf)
+    dop = binding.upload(op, storage=storage)
+    x = inputs.make_rhs(cloud.n, nrhs, seed=seed + 60).astype(np.complex64).astype(np.complex128)
+    y = _run(torch_dev, dop, x, ld_pad=3)
+    ref_r = uniform.uh_mvp(uniform.assemble_factored(precision.round_operator(vars(op), base), "smaller"), x)
+    ref = uniform.uh_mvp(vars(op), x)
+    e_arith = _col_rel(y, ref_r).max()
+    e_full = _col_rel(y, ref).max()
+    print(f"  arithmetic err {e_arith:.2e}  vs FP64 operator {e_full:.2e}", flush=True)
+    assert e_arith <= 2e-5
+    assert e_full <= (1e-5 if base == "c64" else 2e-2)
+    info = dop.info()
+    assert info["storage"] == binding.STORAGE[storage]
+    lt = op.rank_row[op.adm_row].astype(np.int64)
+    ls = op.rank_col[op.adm_col].astype(np.int64)
+    k = op.adm_rank.astype(np.int64)
+    assert info["elems_coupling"] + info["elems_coupling_in"] == int(np.minimum(lt * ls, k * (lt + ls)).sum())

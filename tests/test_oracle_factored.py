@@ -57,3 +57,20 @@ def test_missing_conjugate_is_rejected(small_op):
     a = kernel.dense_matrix(cloud.points, cloud.kappa, 1.0 / (2.0 * cloud.h))
     y = uniform.uh_mvp(uniform.assemble_factored(bad), x)
     assert np.linalg.norm(y[:, 0] - a @ x[:, 0]) > 10 * EPS * np.linalg.norm(a, 2) * np.linalg.norm(x[:, 0])
+
+
+def test_per_block_choice_keeps_the_stored_couplings(small_op):
+    """which="smaller" forms S_b from the factors exactly where they hold fewer elements."""
+    _, op = small_op
+    fa = uniform.assemble_factored(vars(op), "smaller")
+    full = uniform.assemble_factored(vars(op))
+    lt = op.rank_row[op.adm_row].astype(np.int64)
+    ls = op.rank_col[op.adm_col].astype(np.int64)
+    k = op.adm_rank.astype(np.int64)
+    for b in range(op.nadm):
+        m = int(lt[b] * ls[b])
+        got = fa["S"][fa["S_off"][b]:fa["S_off"][b] + m]
+        if k[b] * (lt[b] + ls[b]) < lt[b] * ls[b]:
+            assert np.array_equal(got, full["S"][full["S_off"][b]:full["S_off"][b] + m])
+        else:
+            assert np.array_equal(got, op.S[op.S_off[b]:op.S_off[b] + m])
