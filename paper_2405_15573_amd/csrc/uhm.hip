@@ -36,7 +36,7 @@ const char* const kKernelNames[K_COUNT] = {
     "k_forward_tiles", "k_reduce_segments", "k_coupling", "k_reduce_coupling", "k_backward",
     "k_lp_gather", "k_lp_forward", "k_lp_reduce_segments", "k_lp_coupling", "k_lp_reduce_coupling",
     "k_lp_backward", "k_lp_scatter", "k_coupling_sym", "k_reduce_sym", "k_backward_sym", "k_finish_sym",
-    "k_factor_in", "k_lp_factor_in", "k_lp_reduce_factor"};
+    "k_factor_in", "k_lp_factor_in"};
 
 int check_tree(int64_t n, const int64_t* perm, int32_t nc, const int64_t* off, const int64_t* size,
                const int32_t* parent, TreeInfo& T) {

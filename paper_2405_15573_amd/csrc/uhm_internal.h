@@ -282,7 +282,7 @@ namespace uhm_detail {
 enum {
   K_FORWARD = 0, K_REDUCE_FWD, K_COUPLING, K_REDUCE_COUP, K_BACKWARD,
   K_LP_GATHER, K_LP_FORWARD, K_LP_REDUCE_FWD, K_LP_COUPLING, K_LP_REDUCE_COUP, K_LP_BACKWARD, K_LP_SCATTER,
-  K_SYM_COUPLING, K_SYM_REDUCE, K_SYM_BACKWARD, K_SYM_FINISH, K_FACTOR_IN, K_LP_FACTOR_IN, K_LP_REDUCE_FACTOR,
+  K_SYM_COUPLING, K_SYM_REDUCE, K_SYM_BACKWARD, K_SYM_FINISH, K_FACTOR_IN, K_LP_FACTOR_IN,
   K_COUNT
 };
 extern const char* const kKernelNames[K_COUNT];

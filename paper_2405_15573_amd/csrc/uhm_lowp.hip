@@ -825,14 +825,15 @@ struct LowpOp {
   struct Chunk {
     int64_t base, csrc;
     int32_t h, nkb_all;
+    int32_t slot = -1;  // factor pass: 64-row slot of the output rows
   };
   std::vector<Chunk> chunks;
   // factored couplings (section 4.2): a first coupling pass whose rows are the t_b =
-  // S_{Y,b}^* u_sigma of the factored blocks, grouped by column cluster sigma; its results
-  // go to rows nxh .. nxh + ntf of the xh buffer, where the main pass reads them
+  // S_{Y,b}^* u_sigma of the factored blocks, grouped by column cluster sigma; one tile per
+  // 64-row chunk (K = l_sigma), written straight to rows nxh .. nxh + ntf of the xh buffer
+  // (each cluster's rows start on a multiple of 64), where the main pass reads them
   DevArray<uint4> ST;
-  DevArray<int64_t> tgrp_start;
-  DevArray<int32_t> tcolsrc, tyh_grp, tgrp_t0, tgrp_nt;
+  DevArray<int32_t> tcolsrc;
   DevArray<LpCoupTile> tctiles;
   int32_t ntctiles = 0;
   int64_t ntf = 0;
@@ -1036,25 +1037,26 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
       fac[b] = k * (lt + ls) < lt * ls;
       if (fac[b]) colfac[h->adm_col[b]].push_back(b);
     }
-  for (int32_t c = 0; c < nc; ++c)
+  for (int32_t c = 0; c < nc; ++c) {
+    if (colfac[c].empty()) continue;
+    ntf = (ntf + 63) & ~int64_t(63);  // the factor pass writes whole 64-row slots
     for (int64_t b : colfac[c]) {
       t_off[b] = ntf;
       ntf += h->adm_rank[b];
     }
+  }
   if (nxh + ntf > INT32_MAX / kLpRmax) return fail(UHM_ENOTSUP, "rank space too large");
   {
     // first pass: for each column cluster sigma with factored blocks, the rows are the
     // columns of [S_{Y,b1} S_{Y,b2} ...] (conjugated), the columns are u_sigma
     std::vector<LpCoupTile> tt;
-    std::vector<int32_t> tcs, tg0, tgn, tyg(ntf);
-    std::vector<int64_t> tgs;
+    std::vector<int32_t> tcs;
     struct TJob {
       int64_t m0, base;
       int32_t sg, hh, nkb;
     };
     std::vector<TJob> tj;
     int64_t tot = 0;
-    constexpr int KBT = kLpCoupK / KB;
     for (int32_t c = 0; c < nc; ++c) {
       if (colfac[c].empty()) continue;
       const int32_t ls = h->rank_col[c];
@@ -1067,21 +1069,16 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
       const int64_t m0 = t_off[colfac[c][0]];
       for (int64_t r0 = 0; r0 < M; r0 += 64) {
         const int32_t hh = (int32_t)std::min<int64_t>(64, M - r0);
-        const int32_t gi = (int32_t)tgs.size();
-        tgs.push_back(m0 + r0);
-        tg0.push_back((int32_t)tt.size());
-        for (int32_t r = 0; r < hh; ++r) tyg[m0 + r0 + r] = gi;
-        for (int32_t kb0 = 0; kb0 < nkb; kb0 += KBT)
-          tt.push_back({tot, csrc, hh, nkb, kb0, std::min(KBT, nkb - kb0), (int32_t)tt.size()});
-        tgn.push_back((int32_t)tt.size() - tg0.back());
+        const int32_t slot = (int32_t)((m0 + r0) / 64);
+        tt.push_back({tot, csrc, hh, nkb, 0, nkb, slot});
         tj.push_back({m0 + r0, tot, c, hh, nkb});
-        lp->tchunks.push_back({tot, csrc, hh, nkb});
+        lp->tchunks.push_back({tot, csrc, hh, nkb, slot});
         tot += panel_chunks<ST>(hh, nkb);
       }
     }
     if ((rc = lp->ST.alloc(tot))) return rc;
     if (tot > 0) {
-      std::vector<const double*> trow(ntf);  // t row -> start of its S_{Y,b} column
+      std::vector<const double*> trow(ntf, nullptr);  // t row -> start of its S_{Y,b} column
       for (int32_t c = 0; c < nc; ++c)
         for (int64_t b : colfac[c])
           for (int32_t j = 0; j < h->adm_rank[b]; ++j)
@@ -1104,12 +1101,9 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
         return fail(UHM_EINVAL, "layout: factor tile");
     for (int32_t v : tcs)
       if (v >= nxh) return fail(UHM_EINVAL, "layout: factor column source");
-    for (size_t g = 0; g < tgs.size(); ++g)
-      if (tgs[g] < 0 || tgs[g] + tt[tg0[g]].h > ntf || tgn[g] < 1 || (size_t)tg0[g] + tgn[g] > tt.size())
-        return fail(UHM_EINVAL, "layout: factor group");
-    if ((rc = lp->tctiles.upload(tt, s)) || (rc = lp->tcolsrc.upload(tcs, s)) || (rc = lp->tyh_grp.upload(tyg, s)) ||
-        (rc = lp->tgrp_start.upload(tgs, s)) || (rc = lp->tgrp_t0.upload(tg0, s)) || (rc = lp->tgrp_nt.upload(tgn, s)))
-      return rc;
+    for (const LpCoupTile& Tt : tt)
+      if (Tt.part < 0 || (int64_t)Tt.part * 64 + Tt.h > ntf) return fail(UHM_EINVAL, "layout: factor rows");
+    if ((rc = lp->tctiles.upload(tt, s)) || (rc = lp->tcolsrc.upload(tcs, s))) return rc;
     lp->ntctiles = (int32_t)tt.size();
     lp->ntf = ntf;
   }
@@ -1306,16 +1300,10 @@ void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, i
     }
   }
   if (lp->ntctiles > 0) {
-    {
-      ScopedTiming tm(op, s, K_LP_FACTOR_IN);
-      hipLaunchKernelGGL((k_lp_coupling<ST, NT>), dim3(lp->ntctiles), dim3(64 * kLpWaves), 0, s, lp->ST.p, lp->tctiles.p,
-                         lp->tcolsrc.p, xh, R, part);
-    }
-    {
-      ScopedTiming tm(op, s, K_LP_REDUCE_FACTOR);
-      hipLaunchKernelGGL(k_lp_reduce_coupling<V>, dim3((unsigned)((lp->ntf * R + 255) / 256)), dim3(256), 0, s, part, R,
-                         lp->tyh_grp.p, lp->tgrp_start.p, lp->tgrp_t0.p, lp->tgrp_nt.p, lp->ntf, xh + lp->nxh * R);
-    }
+    // t_b rows go straight to their slots after the nxh rows of u (one tile per slot)
+    ScopedTiming tm(op, s, K_LP_FACTOR_IN);
+    hipLaunchKernelGGL((k_lp_coupling<ST, NT>), dim3(lp->ntctiles), dim3(64 * kLpWaves), 0, s, lp->ST.p, lp->tctiles.p,
+                       lp->tcolsrc.p, xh, R, xh + lp->nxh * R);
   }
   if (lp->nctiles > 0) {
     {
@@ -1440,9 +1428,9 @@ struct BatchOp {
   int64_t ldx, ldy;
   int32_t r;
   DevArray<unsigned char> Xc, Yc, p, xh, part, yh;
-  DevArray<LpCoupTile> tiles, ftiles;  // ftiles: first pass of factored couplings
-  DevArray<int32_t> grp_t0, grp_nt, fgrp_t0, fgrp_nt;
-  int32_t ntiles = 0, nftiles = 0;
+  DevArray<LpCoupTile> tiles;
+  DevArray<int32_t> grp_t0, grp_nt;
+  int32_t ntiles = 0;
   int64_t part_cap = 0;  // partial-sum slots allocated (tiles * 64 * R elements)
 };
 
@@ -1455,7 +1443,7 @@ struct LowpBatch {
   BatchConfig cfg;
   bool configured = false;
   DevArray<LpDesc> desc;
-  DevArray<int2> w_gather, w_forward, w_rseg, w_fcoup, w_frcoup, w_coup, w_rcoup, w_backward, w_scatter;
+  DevArray<int2> w_gather, w_forward, w_rseg, w_fcoup, w_coup, w_rcoup, w_backward, w_scatter;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::string signature;
@@ -1536,20 +1524,15 @@ LpDesc desc_of(uhm_op* op) {
   return d;
 }
 
-// The descriptor of an operator's first factored-coupling pass, from the descriptor d of its
-// main passes: the coupling stage reads the t-rows panel and writes into rows nxh .. of xh.
-LpDesc factor_desc(const LowpOp* lp, const LpDesc& d, const LpCoupTile* tiles, const int32_t* t0, const int32_t* nt,
-                   int64_t ebytes) {
+// The descriptor of an operator's factored-coupling first pass, from the descriptor d of its
+// main passes: the coupling stage reads the t-rows panel and writes its tiles (one per
+// 64-row slot) straight into rows nxh .. of xh.
+LpDesc factor_desc(const LowpOp* lp, const LpDesc& d, int64_t ebytes) {
   LpDesc f = d;
   f.S = lp->ST.p;
   f.colsrc = lp->tcolsrc.p;
-  f.ctiles = tiles;
-  f.grp_t0 = t0;
-  f.grp_nt = nt;
-  f.grp_start = lp->tgrp_start.p;
-  f.yh_grp = lp->tyh_grp.p;
-  f.nyh = lp->ntf;
-  f.yh = static_cast<unsigned char*>(d.xh) + ebytes * lp->nxh * d.R;
+  f.ctiles = lp->tctiles.p;
+  f.part = static_cast<unsigned char*>(d.xh) + ebytes * lp->nxh * d.R;
   return f;
 }
 
@@ -1558,7 +1541,7 @@ int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
   const int64_t e = B->storage == UHM_C128_MULTI ? 16 : 8;
   const int R = B->R;
   std::vector<LpDesc> descs, fdescs;
-  std::vector<int2> wg, wf, wrs, wfc, wfrc, wc, wrc, wb, wsc;
+  std::vector<int2> wg, wf, wrs, wfc, wc, wrc, wb, wsc;
   std::vector<int64_t> cf_, cfc_, cc_, cb_;
   const int32_t nops = (int32_t)B->ops.size();
   int rc;
@@ -1578,19 +1561,7 @@ int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
     }
     if ((rc = bo.tiles.upload(tiles, s)) || (rc = bo.grp_t0.upload(t0, s)) || (rc = bo.grp_nt.upload(nt, s))) return rc;
     bo.ntiles = (int32_t)tiles.size();
-    // the same tiling of the first pass of factored couplings
-    std::vector<LpCoupTile> ftiles;
-    std::vector<int32_t> ft0, fnt;
-    for (const LowpOp::Chunk& c : lp->tchunks) {
-      ft0.push_back((int32_t)ftiles.size());
-      for (int32_t kb0 = 0; kb0 < c.nkb_all; kb0 += kbt)
-        ftiles.push_back({c.base, c.csrc, c.h, c.nkb_all, kb0, std::min(kbt, c.nkb_all - kb0), (int32_t)ftiles.size()});
-      fnt.push_back((int32_t)ftiles.size() - ft0.back());
-    }
-    if ((rc = bo.ftiles.upload(ftiles, s)) || (rc = bo.fgrp_t0.upload(ft0, s)) || (rc = bo.fgrp_nt.upload(fnt, s)))
-      return rc;
-    bo.nftiles = (int32_t)ftiles.size();
-    const int64_t need = std::max<int64_t>(1, (int64_t)std::max(bo.ntiles, bo.nftiles) * 64 * R);
+    const int64_t need = std::max<int64_t>(1, (int64_t)bo.ntiles * 64 * R);
     if (bo.part_cap < need) {
       if ((rc = bo.part.alloc(e * need))) return rc;
       bo.part_cap = need;
@@ -1631,14 +1602,13 @@ int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
       wb.push_back(make_int2(ki, l));
       cb_.push_back((int64_t)lp->leaf_n_h[l] * lp->b_nkb_h[l]);
     }
-    if (bo.nftiles > 0) {
+    if (lp->ntctiles > 0) {  // the factor pass keeps the upload's tiling (one tile per output slot)
       const int32_t fi = nops + (int32_t)fdescs.size();
-      fdescs.push_back(factor_desc(lp, d, bo.ftiles.p, bo.fgrp_t0.p, bo.fgrp_nt.p, e));
-      for (int32_t t = 0; t < bo.nftiles; ++t) {
-        wfc.push_back(make_int2(fi, t));
-        cfc_.push_back((int64_t)ftiles[t].h * ftiles[t].nkb);
+      fdescs.push_back(factor_desc(lp, d, e));
+      for (size_t t = 0; t < lp->tchunks.size(); ++t) {
+        wfc.push_back(make_int2(fi, (int32_t)t));
+        cfc_.push_back((int64_t)lp->tchunks[t].h * lp->tchunks[t].nkb_all);
       }
-      for (int64_t b = 0; b < ceil_div(lp->ntf * R, 256); ++b) wfrc.push_back(make_int2(fi, (int32_t)b));
     }
   }
   descs.insert(descs.end(), fdescs.begin(), fdescs.end());
@@ -1647,7 +1617,7 @@ int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
   order_work(wc, cc_, cfg.order);
   order_work(wb, cb_, cfg.order);
   if ((rc = B->desc.upload(descs, s)) || (rc = B->w_gather.upload(wg, s)) || (rc = B->w_forward.upload(wf, s)) ||
-      (rc = B->w_rseg.upload(wrs, s)) || (rc = B->w_fcoup.upload(wfc, s)) || (rc = B->w_frcoup.upload(wfrc, s)) ||
+      (rc = B->w_rseg.upload(wrs, s)) || (rc = B->w_fcoup.upload(wfc, s)) ||
       (rc = B->w_coup.upload(wc, s)) || (rc = B->w_rcoup.upload(wrc, s)) ||
       (rc = B->w_backward.upload(wb, s)) || (rc = B->w_scatter.upload(wsc, s)))
     return rc;
@@ -1676,7 +1646,6 @@ void batch_launch_t(LowpBatch* B, hipStream_t s) {
   go(k_lpb_forward<ST, NT>, B->w_forward, 64 * kLpWaves);
   go(k_lpb_reduce_segments<V>, B->w_rseg, 256);
   go(k_lpb_coupling<ST, NT>, B->w_fcoup, 64 * kLpWaves);  // factored couplings, first pass
-  go(k_lpb_reduce_coupling<V>, B->w_frcoup, 256);
   go(k_lpb_coupling<ST, NT>, B->w_coup, 64 * kLpWaves);
   go(k_lpb_reduce_coupling<V>, B->w_rcoup, 256);
   go(k_lpb_backward<ST, NT>, B->w_backward, 64 * kLpWaves);
@@ -1733,7 +1702,6 @@ void step_launch(const LpDesc* D, const int2* const* w, const unsigned* cnt, hip
   go(k_lpb_forward<ST, NT>, 1, 64 * kLpWaves);
   go(k_lpb_reduce_segments<V>, 2, 256);
   go(k_lpb_coupling<ST, NT>, 7, 64 * kLpWaves);  // factored couplings, first pass
-  go(k_lpb_reduce_coupling<V>, 8, 256);
   go(k_lpb_coupling<ST, NT>, 3, 64 * kLpWaves);
   go(k_lpb_reduce_coupling<V>, 4, 256);
   go(k_lpb_backward<ST, NT>, 5, 64 * kLpWaves);
@@ -1767,7 +1735,7 @@ int lowp_step_products(uhm_op* const* ops, const cd* const* const* xcol, cd* con
   const int R = 16 * ((maxc + 15) / 16);
   const int64_t e = storage == UHM_C128_MULTI ? 16 : 8;
   std::vector<LpDesc> descs, fdescs;
-  std::vector<int2> w[9];  // stages 7, 8: the first pass of factored couplings (run after stage 2)
+  std::vector<int2> w[8];  // stage 7: the first pass of factored couplings (run after stage 2)
   int rc;
   for (int32_t k = 0; k < nops; ++k) {
     uhm_op* op = ops[k];
@@ -1801,16 +1769,15 @@ int lowp_step_products(uhm_op* const* ops, const cd* const* const* xcol, cd* con
     for (int64_t b = 0; b < ceil_div(op->n * (int64_t)ncols[k], 256); ++b) w[6].push_back(make_int2(ki, (int32_t)b));
     if (lp->ntctiles > 0) {
       const int32_t fi = nops + (int32_t)fdescs.size();
-      fdescs.push_back(factor_desc(lp, d, lp->tctiles.p, lp->tgrp_t0.p, lp->tgrp_nt.p, e));
+      fdescs.push_back(factor_desc(lp, d, e));
       for (int32_t t = 0; t < lp->ntctiles; ++t) w[7].push_back(make_int2(fi, t));
-      for (int64_t b = 0; b < ceil_div(lp->ntf * R, 256); ++b) w[8].push_back(make_int2(fi, (int32_t)b));
     }
   }
   descs.insert(descs.end(), fdescs.begin(), fdescs.end());
-  size_t off[10];
+  size_t off[9];
   off[0] = (sizeof(LpDesc) * descs.size() + 15) & ~size_t(15);
-  for (int st = 0; st < 9; ++st) off[st + 1] = off[st] + ((sizeof(int2) * w[st].size() + 15) & ~size_t(15));
-  const size_t tot = off[9];
+  for (int st = 0; st < 8; ++st) off[st + 1] = off[st] + ((sizeof(int2) * w[st].size() + 15) & ~size_t(15));
+  const size_t tot = off[8];
   StepProducts& sp = step_products();
   if (sp.recorded) UHM_HIP(hipEventSynchronize(sp.ev));
   if (!sp.ev) UHM_HIP(hipEventCreateWithFlags(&sp.ev, hipEventDisableTiming));
@@ -1825,9 +1792,9 @@ int lowp_step_products(uhm_op* const* ops, const cd* const* const* xcol, cd* con
     sp.cap = cap;
   }
   std::memcpy(sp.host, descs.data(), sizeof(LpDesc) * descs.size());
-  const int2* dw[9];
-  unsigned cnt[9];
-  for (int st = 0; st < 9; ++st) {
+  const int2* dw[8];
+  unsigned cnt[8];
+  for (int st = 0; st < 8; ++st) {
     std::memcpy(sp.host + off[st], w[st].data(), sizeof(int2) * w[st].size());
     dw[st] = reinterpret_cast<const int2*>(sp.dev + off[st]);
     cnt[st] = (unsigned)w[st].size();
