@@ -420,8 +420,8 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_backward(
 // and used twice: for the direct product (one lane per row, as above) and for the
 // transposed one, whose column sums run across the 64 lanes of the wave.
 
-constexpr int kSymBwdWaves = 4;
-constexpr int kSymBwdChunk = 512;  // z entries staged in LDS per round
+constexpr int kSymBwdWaves = 8;
+constexpr int kSymBwdChunk = 1024;  // z entries staged in LDS per round
 
 __device__ __forceinline__ cd cmul(cd a, cd b) {
   return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
