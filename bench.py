@@ -263,7 +263,7 @@ def run_serving(args):
         hosts.append(builder.build_operator(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6))
         log(f"  op {k}: {surf} N={cloud.n} built {hosts[-1].timings['total']:.1f}s")
     log(f"population built in {time.perf_counter() - t0:.1f} s")
-    srv = Server(hosts, low_storage="c64", inner_tol=1e-3, max_iterations=4000)
+    srv = Server(hosts, low_storage=args.serve_storage, inner_tol=1e-3, max_iterations=4000)
     results = {}
     for rate in [float(v) for v in args.rates.split(",")]:
         rng = np.random.default_rng([args.seed, 5, int(rate)])
@@ -287,7 +287,7 @@ def run_serving(args):
         "unit": "s", "n_gpus": 1, "steps": args.requests, "warmup": 0, "ms_per_step": None,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"16 resident operators (sphere, cube), N log-uniform in [4096, {args.serve_max_n}], GMRES-IR "
-                               f"(complex64 inner, FP64 residual), Poisson arrivals {args.rates}/s, "
+                               f"({args.serve_storage} inner, FP64 residual), Poisson arrivals {args.rates}/s, "
                                f"{args.requests} requests per rate, 1-8 RHS, tol 1e-6 or 1e-8",
                    "operators": [(p[0], int(h.n)) for p, h in zip(pop, hosts)]},
         "per_rate": results,
@@ -329,6 +329,8 @@ def main():
     ap.add_argument("--serve-max-n", type=int, default=16384,
                     help="largest operator of the serving mix (GMRES(50) on larger operators of these clouds "
                          "needs thousands of iterations)")
+    ap.add_argument("--serve-storage", choices=("c64", "c64fact", "bf16pair", "bf16pairfact"), default="c64fact",
+                    help="storage of the inner (low-precision) operators of the serving loop")
     ap.add_argument("--parity-leaves", type=int, default=6)
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_sphere262k_c128.json"),
                     help="JSON file with counter-derived HBM bytes per launch (used only if it was taken on the "
