@@ -163,10 +163,11 @@ def run_batched(args):
     for k, (surf, n) in enumerate(pop):
         cloud = inputs.make_cloud(surf, n, seed=args.seed + k)
         h = builder.build_operator(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6)
-        d = binding.upload(h, storage="c64", stream=stream)
+        d = binding.upload(h, storage=args.batch_storage, stream=stream)
         r = int(rng.integers(1, 17))
         inf = d.info()
-        M = inf["elems_forward"] + inf["elems_coupling"] + inf["elems_backward"] + inf["elems_near"]
+        M = (inf["elems_forward"] + inf["elems_coupling"] + inf["elems_coupling_in"] + inf["elems_backward"]
+             + inf["elems_near"])
         bytes_total += 8 * M + 8 * r * 2 * cloud.n
         flops_total += 8.0 * r * M
         rsum += r
@@ -207,12 +208,12 @@ def run_batched(args):
     t_graph = timed(lambda: batch.run(stream=stream), args.steps)
     err = max(float((torch.linalg.norm(y - r_) / torch.linalg.norm(r_)).item()) for y, r_ in zip(ys, ref))
     line = {
-        "metric": "batched uniform-H MVPs: right-hand-side products per second, complex64, shared launches",
+        "metric": f"batched uniform-H MVPs: right-hand-side products per second, {args.batch_storage}, shared launches",
         "value": rsum / (t_graph * 1e-3), "unit": "RHS-products/s", "n_gpus": 1, "steps": args.steps,
         "warmup": 3, "ms_per_step": t_graph, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.nops} operators, N log-uniform in [4096, {args.max_n}], sphere/ellipsoid/cube, "
-                               "1-16 RHS each, complex64 storage", "operators": hosts},
+                               f"1-16 RHS each, {args.batch_storage} storage", "operators": hosts},
         "ms_one_operator_at_a_time": t_seq, "ms_batched_untuned": t_untuned, "ms_batched_tuned": t_tuned,
         "ms_batched_graph": t_graph, "speedup_vs_one_at_a_time": t_seq / t_graph, "tuned_schedule": choice,
         "gbs": bytes_total / (t_graph * 1e-3) / 1e9, "tflops": flops_total / (t_graph * 1e-3) / 1e12,
@@ -329,6 +330,8 @@ def main():
     ap.add_argument("--serve-max-n", type=int, default=16384,
                     help="largest operator of the serving mix (GMRES(50) on larger operators of these clouds "
                          "needs thousands of iterations)")
+    ap.add_argument("--batch-storage", choices=("c64", "c64fact", "bf16pair", "bf16pairfact"), default="c64fact",
+                    help="storage of the operators of the batched mode")
     ap.add_argument("--serve-storage", choices=("c64", "c64fact", "bf16pair", "bf16pairfact"), default="c64fact",
                     help="storage of the inner (low-precision) operators of the serving loop")
     ap.add_argument("--parity-leaves", type=int, default=6)
