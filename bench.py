@@ -32,12 +32,13 @@ def log(*a):
 
 
 SYM_STORAGE = 4  # symmetric storage form (one block per mirrored pair)
+C128_STORAGES = (0, 3, 4, 5)  # storage forms with complex128 vectors
 
 
 def algorithmic_bytes(info: dict, n: int, nrhs: int = 1) -> dict:
     """Bytes each kernel must move per product: stored operator elements once, vectors once."""
     e = info["elem_bytes"]
-    f = 16 if info["storage"] == 0 else 8
+    f = 16 if info["storage"] in C128_STORAGES else 8  # vector element: complex128 or complex64
     rs = info["rank_space"]
     out = {
         "k_forward_tiles": e * info["elems_forward"] + f * nrhs * (n + rs),

@@ -1,0 +1,35 @@
+"""Host logic of bench.py: algorithmic bytes per kernel for each storage form (no GPU)."""
+import bench
+
+
+def _info(**kw):
+    base = dict(n=1000, kind=0, storage=0, elem_bytes=16, elems_forward=100, elems_coupling=200,
+                elems_backward=300, elems_near=400, rank_space=10, partial_coupling=0, partial_near=0,
+                elems_coupling_in=0)
+    base.update(kw)
+    return base
+
+
+def test_general_form():
+    ab = bench.algorithmic_bytes(_info(), 1000)
+    assert ab["k_forward_tiles"] == 16 * 100 + 16 * (1000 + 10)
+    assert ab["k_coupling"] == 16 * 200 + 16 * 20
+    assert ab["k_backward"] == 16 * 700 + 16 * (2000 + 10)
+    assert ab["total"] == 16 * 1000 + 16 * (2000 + 40)
+
+
+def test_symmetric_form_counts_the_partial_sums():
+    ab = bench.algorithmic_bytes(_info(storage=4, partial_coupling=50, partial_near=30), 1000)
+    assert ab["k_coupling_sym"] == 16 * 200 + 16 * (20 + 50)
+    assert ab["k_backward_sym"] == 16 * 700 + 16 * (2000 + 10 + 30)
+    assert "k_coupling" not in ab and "k_backward" not in ab
+    assert ab["total"] == 16 * 1000 + 16 * (2000 + 40 + 100 + 60)
+
+
+def test_factored_form_counts_both_factors():
+    ab = bench.algorithmic_bytes(_info(storage=5, elems_coupling_in=80), 1000)
+    assert ab["k_factor_in"] == 16 * 80 + 16 * 20
+    assert ab["total"] == 16 * 1080 + 16 * (2000 + 60)
+    # complex64 vectors for the low-precision forms
+    ab = bench.algorithmic_bytes(_info(storage=6, elem_bytes=8, elems_coupling_in=80), 1000)
+    assert ab["k_forward_tiles"] == 8 * 100 + 8 * 1010
