@@ -40,10 +40,12 @@ def _requests(torch, host, spec):
 SPEC = [(0, 2, 1e-8, 0.0), (1, 1, 1e-6, 0.0), (2, 3, 1e-8, 0.001), (0, 1, 1e-6, 0.002), (1, 4, 1e-8, 0.003)]
 
 
-def test_mix_equals_alone_and_converges(server_env):
+@pytest.mark.parametrize("low", ["c64", "c64fact"])
+def test_mix_equals_alone_and_converges(server_env, low):
     torch, host = server_env
     from paper_2405_15573_amd.serving import Server
-    srv = Server(host, low_storage="c64", keep_solutions=True)
+    print(f"case serving mix, inner {low}", flush=True)
+    srv = Server(host, low_storage=low, keep_solutions=True)
     mix = srv.serve(_requests(torch, host, SPEC))
     rep = Server.report(mix)
     print(f"  mix report {rep}", flush=True)
