@@ -584,6 +584,39 @@ __device__ __forceinline__ void coupling_body(LdsOf<ST, NT>& L, const LpCoupTile
   if (w < nmt) store_tile<ST, NT>(part, (int64_t)T.part * 64 + 16 * w, hm, R, g, i, acc);
 }
 
+// Factor pass over all t rows of one column cluster sigma whose K = l_sigma fits one LDS
+// round: the gathered u_sigma is staged once and each wave multiplies it by its m-tiles in
+// turn, storing rows part * 64 + 16 mt .. of `out`.
+template <int ST, int NT>
+__device__ __forceinline__ void factor_body(LdsOf<ST, NT>& L, const LpCoupTile& T, const uint4* __restrict__ S,
+                                            const int32_t* __restrict__ colsrc,
+                                            const typename Tr<ST>::V* __restrict__ xh, int R,
+                                            typename Tr<ST>::V* __restrict__ out) {
+  using T_ = Tr<ST>;
+  using Q_ = Round<ST, NT>;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, i = lane & 15;
+  const int nmt = (T.h + 15) >> 4;
+  const int nkr = T.nkb_all, nk = nkr * T_::KB;  // nkr <= KBR, checked at upload
+  auto src = [&](int32_t sc, int j, bool ok) { return xh + (ok ? (int64_t)sc * R + j : 0); };
+  const int32_t* cs = colsrc + T.csrc;
+  Q_ Q;
+  round_indices<ST, NT>(Q, nk, [&](int k) {
+    const int32_t sc = cs[k];
+    return sc >= 0 ? sc : kZero;
+  });
+  round_values<ST, NT>(Q, nk, src);
+  round_commit<ST, NT>(L, Q, nk);
+  __syncthreads();
+  for (int mt = w; mt < nmt; mt += kLpWaves) {
+    const int hm = min(16, T.h - 16 * mt);
+    round_issue_a<ST, NT>(Q, S + T.base + (int64_t)mt * T.nkb_all * T_::CH * 64, 0, nkr, hm, g, i);
+    typename T_::template ACCS<NT> acc;
+    acc.zero();
+    round_mma<ST, NT>(Q, L, nkr, g, i, acc);
+    store_tile<ST, NT>(out, (int64_t)T.part * 64 + 16 * mt, hm, R, g, i, acc);
+  }
+}
+
 template <class V>
 __device__ __forceinline__ void reduce_coupling_body(int64_t q, const V* __restrict__ part, int R,
                                                      const int32_t* __restrict__ yh_grp,
@@ -703,6 +736,17 @@ __global__ __launch_bounds__(64 * kLpWaves) void k_lp_coupling(const uint4* __re
   coupling_body<ST, NT>(L, T, S, colsrc, xh, R, part);
 }
 
+template <int ST, int NT>
+__global__ __launch_bounds__(64 * kLpWaves) void k_lp_factor(const uint4* __restrict__ S,
+                                                             const LpCoupTile* __restrict__ tiles,
+                                                             const int32_t* __restrict__ colsrc,
+                                                             const typename Tr<ST>::V* __restrict__ xh, int R,
+                                                             typename Tr<ST>::V* __restrict__ out) {
+  __shared__ LdsOf<ST, NT> L;
+  const LpCoupTile T = tiles[blockIdx.x];
+  factor_body<ST, NT>(L, T, S, colsrc, xh, R, out);
+}
+
 template <class V>
 __global__ __launch_bounds__(256) void k_lp_reduce_coupling(const V* __restrict__ part, int R,
                                                             const int32_t* __restrict__ yh_grp,
@@ -788,6 +832,16 @@ __global__ __launch_bounds__(64 * kLpWaves) void k_lpb_coupling(const LpDesc* __
   coupling_body<ST, NT>(L, T, d.S, d.colsrc, static_cast<const V*>(d.xh), d.R, static_cast<V*>(d.part));
 }
 
+template <int ST, int NT>
+__global__ __launch_bounds__(64 * kLpWaves) void k_lpb_factor(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
+  __shared__ LdsOf<ST, NT> L;
+  using V = typename Tr<ST>::V;
+  const int2 wk = work[blockIdx.x];
+  const LpDesc& d = D[wk.x];
+  const LpCoupTile T = d.ctiles[wk.y];
+  factor_body<ST, NT>(L, T, d.S, d.colsrc, static_cast<const V*>(d.xh), d.R, static_cast<V*>(d.part));
+}
+
 template <class V>
 __global__ __launch_bounds__(256) void k_lpb_reduce_coupling(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
   const int2 wk = work[blockIdx.x];
@@ -834,8 +888,9 @@ struct LowpOp {
   // (each cluster's rows start on a multiple of 64), where the main pass reads them
   DevArray<uint4> ST;
   DevArray<int32_t> tcolsrc;
-  DevArray<LpCoupTile> tctiles;
-  int32_t ntctiles = 0;
+  DevArray<LpCoupTile> tctiles;  // clusters with l_sigma beyond one LDS round: 64-row chunks
+  DevArray<LpCoupTile> tftiles;  // the others: one tile with all the cluster's t rows
+  int32_t ntctiles = 0, ntftiles = 0;
   int64_t ntf = 0;
   std::vector<Chunk> tchunks;
   std::vector<int32_t> f_M_h, b_nkb_h, f_nkb_h, leaf_n_h;
@@ -1049,8 +1104,9 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
   {
     // first pass: for each column cluster sigma with factored blocks, the rows are the
     // columns of [S_{Y,b1} S_{Y,b2} ...] (conjugated), the columns are u_sigma
-    std::vector<LpCoupTile> tt;
+    std::vector<LpCoupTile> tt, tf;
     std::vector<int32_t> tcs;
+    constexpr int KBR1 = Tr<ST>::RZ / KB;  // k-blocks of one LDS round
     struct TJob {
       int64_t m0, base;
       int32_t sg, hh, nkb;
@@ -1067,6 +1123,12 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
       int64_t M = 0;
       for (int64_t b : colfac[c]) M += h->adm_rank[b];
       const int64_t m0 = t_off[colfac[c][0]];
+      if (nkb <= KBR1 && M <= INT32_MAX / 64) {  // u_sigma staged once for all its t rows
+        tf.push_back({tot, csrc, (int32_t)M, nkb, 0, nkb, (int32_t)(m0 / 64)});
+        tj.push_back({m0, tot, c, (int32_t)M, nkb});
+        tot += panel_chunks<ST>((int32_t)M, nkb);
+        continue;
+      }
       for (int64_t r0 = 0; r0 < M; r0 += 64) {
         const int32_t hh = (int32_t)std::min<int64_t>(64, M - r0);
         const int32_t slot = (int32_t)((m0 + r0) / 64);
@@ -1099,11 +1161,18 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
       if (Tt.h < 1 || Tt.h > 64 || Tt.base < 0 || Tt.base + panel_chunks<ST>(Tt.h, Tt.nkb_all) > tot || Tt.kb0 < 0 ||
           Tt.nkb < 1 || Tt.kb0 + Tt.nkb > Tt.nkb_all || Tt.csrc + (int64_t)Tt.nkb_all * KB > (int64_t)tcs.size())
         return fail(UHM_EINVAL, "layout: factor tile");
+    for (const LpCoupTile& Tt : tf)
+      if (Tt.h < 1 || Tt.base < 0 || Tt.base + panel_chunks<ST>(Tt.h, Tt.nkb_all) > tot || Tt.nkb_all < 1 ||
+          Tt.nkb_all > KBR1 || Tt.csrc + (int64_t)Tt.nkb_all * KB > (int64_t)tcs.size() || Tt.part < 0 ||
+          (int64_t)Tt.part * 64 + Tt.h > ntf)
+        return fail(UHM_EINVAL, "layout: factor tile");
     for (int32_t v : tcs)
       if (v >= nxh) return fail(UHM_EINVAL, "layout: factor column source");
     for (const LpCoupTile& Tt : tt)
       if (Tt.part < 0 || (int64_t)Tt.part * 64 + Tt.h > ntf) return fail(UHM_EINVAL, "layout: factor rows");
-    if ((rc = lp->tctiles.upload(tt, s)) || (rc = lp->tcolsrc.upload(tcs, s))) return rc;
+    if ((rc = lp->tctiles.upload(tt, s)) || (rc = lp->tftiles.upload(tf, s)) || (rc = lp->tcolsrc.upload(tcs, s)))
+      return rc;
+    lp->ntftiles = (int32_t)tf.size();
     lp->ntctiles = (int32_t)tt.size();
     lp->ntf = ntf;
   }
@@ -1299,8 +1368,13 @@ void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, i
                          lp->nxh, xh);
     }
   }
+  // factored couplings, first pass: t_b rows go straight to their slots after the nxh rows of u
+  if (lp->ntftiles > 0) {
+    ScopedTiming tm(op, s, K_LP_FACTOR_IN);
+    hipLaunchKernelGGL((k_lp_factor<ST, NT>), dim3(lp->ntftiles), dim3(64 * kLpWaves), 0, s, lp->ST.p, lp->tftiles.p,
+                       lp->tcolsrc.p, xh, R, xh + lp->nxh * R);
+  }
   if (lp->ntctiles > 0) {
-    // t_b rows go straight to their slots after the nxh rows of u (one tile per slot)
     ScopedTiming tm(op, s, K_LP_FACTOR_IN);
     hipLaunchKernelGGL((k_lp_coupling<ST, NT>), dim3(lp->ntctiles), dim3(64 * kLpWaves), 0, s, lp->ST.p, lp->tctiles.p,
                        lp->tcolsrc.p, xh, R, xh + lp->nxh * R);
@@ -1443,7 +1517,7 @@ struct LowpBatch {
   BatchConfig cfg;
   bool configured = false;
   DevArray<LpDesc> desc;
-  DevArray<int2> w_gather, w_forward, w_rseg, w_fcoup, w_coup, w_rcoup, w_backward, w_scatter;
+  DevArray<int2> w_gather, w_forward, w_rseg, w_ffac, w_fcoup, w_coup, w_rcoup, w_backward, w_scatter;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::string signature;
@@ -1527,11 +1601,11 @@ LpDesc desc_of(uhm_op* op) {
 // The descriptor of an operator's factored-coupling first pass, from the descriptor d of its
 // main passes: the coupling stage reads the t-rows panel and writes its tiles (one per
 // 64-row slot) straight into rows nxh .. of xh.
-LpDesc factor_desc(const LowpOp* lp, const LpDesc& d, int64_t ebytes) {
+LpDesc factor_desc(const LowpOp* lp, const LpDesc& d, const LpCoupTile* tiles, int64_t ebytes) {
   LpDesc f = d;
   f.S = lp->ST.p;
   f.colsrc = lp->tcolsrc.p;
-  f.ctiles = lp->tctiles.p;
+  f.ctiles = tiles;
   f.part = static_cast<unsigned char*>(d.xh) + ebytes * lp->nxh * d.R;
   return f;
 }
@@ -1541,7 +1615,7 @@ int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
   const int64_t e = B->storage == UHM_C128_MULTI ? 16 : 8;
   const int R = B->R;
   std::vector<LpDesc> descs, fdescs;
-  std::vector<int2> wg, wf, wrs, wfc, wc, wrc, wb, wsc;
+  std::vector<int2> wg, wf, wrs, wff, wfc, wc, wrc, wb, wsc;
   std::vector<int64_t> cf_, cfc_, cc_, cb_;
   const int32_t nops = (int32_t)B->ops.size();
   int rc;
@@ -1604,11 +1678,16 @@ int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
     }
     if (lp->ntctiles > 0) {  // the factor pass keeps the upload's tiling (one tile per output slot)
       const int32_t fi = nops + (int32_t)fdescs.size();
-      fdescs.push_back(factor_desc(lp, d, e));
+      fdescs.push_back(factor_desc(lp, d, lp->tctiles.p, e));
       for (size_t t = 0; t < lp->tchunks.size(); ++t) {
         wfc.push_back(make_int2(fi, (int32_t)t));
         cfc_.push_back((int64_t)lp->tchunks[t].h * lp->tchunks[t].nkb_all);
       }
+    }
+    if (lp->ntftiles > 0) {
+      const int32_t fi = nops + (int32_t)fdescs.size();
+      fdescs.push_back(factor_desc(lp, d, lp->tftiles.p, e));
+      for (int32_t t = 0; t < lp->ntftiles; ++t) wff.push_back(make_int2(fi, t));
     }
   }
   descs.insert(descs.end(), fdescs.begin(), fdescs.end());
@@ -1617,7 +1696,7 @@ int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
   order_work(wc, cc_, cfg.order);
   order_work(wb, cb_, cfg.order);
   if ((rc = B->desc.upload(descs, s)) || (rc = B->w_gather.upload(wg, s)) || (rc = B->w_forward.upload(wf, s)) ||
-      (rc = B->w_rseg.upload(wrs, s)) || (rc = B->w_fcoup.upload(wfc, s)) ||
+      (rc = B->w_rseg.upload(wrs, s)) || (rc = B->w_ffac.upload(wff, s)) || (rc = B->w_fcoup.upload(wfc, s)) ||
       (rc = B->w_coup.upload(wc, s)) || (rc = B->w_rcoup.upload(wrc, s)) ||
       (rc = B->w_backward.upload(wb, s)) || (rc = B->w_scatter.upload(wsc, s)))
     return rc;
@@ -1645,7 +1724,8 @@ void batch_launch_t(LowpBatch* B, hipStream_t s) {
   go(k_lpb_gather<V>, B->w_gather, 256);
   go(k_lpb_forward<ST, NT>, B->w_forward, 64 * kLpWaves);
   go(k_lpb_reduce_segments<V>, B->w_rseg, 256);
-  go(k_lpb_coupling<ST, NT>, B->w_fcoup, 64 * kLpWaves);  // factored couplings, first pass
+  go(k_lpb_factor<ST, NT>, B->w_ffac, 64 * kLpWaves);  // factored couplings, first pass
+  go(k_lpb_coupling<ST, NT>, B->w_fcoup, 64 * kLpWaves);
   go(k_lpb_coupling<ST, NT>, B->w_coup, 64 * kLpWaves);
   go(k_lpb_reduce_coupling<V>, B->w_rcoup, 256);
   go(k_lpb_backward<ST, NT>, B->w_backward, 64 * kLpWaves);
@@ -1701,7 +1781,8 @@ void step_launch(const LpDesc* D, const int2* const* w, const unsigned* cnt, hip
   go(k_lpb_gather<V>, 0, 256);
   go(k_lpb_forward<ST, NT>, 1, 64 * kLpWaves);
   go(k_lpb_reduce_segments<V>, 2, 256);
-  go(k_lpb_coupling<ST, NT>, 7, 64 * kLpWaves);  // factored couplings, first pass
+  go(k_lpb_factor<ST, NT>, 8, 64 * kLpWaves);  // factored couplings, first pass
+  go(k_lpb_coupling<ST, NT>, 7, 64 * kLpWaves);
   go(k_lpb_coupling<ST, NT>, 3, 64 * kLpWaves);
   go(k_lpb_reduce_coupling<V>, 4, 256);
   go(k_lpb_backward<ST, NT>, 5, 64 * kLpWaves);
@@ -1735,7 +1816,7 @@ int lowp_step_products(uhm_op* const* ops, const cd* const* const* xcol, cd* con
   const int R = 16 * ((maxc + 15) / 16);
   const int64_t e = storage == UHM_C128_MULTI ? 16 : 8;
   std::vector<LpDesc> descs, fdescs;
-  std::vector<int2> w[8];  // stage 7: the first pass of factored couplings (run after stage 2)
+  std::vector<int2> w[9];  // stages 7, 8: the first pass of factored couplings (run after stage 2)
   int rc;
   for (int32_t k = 0; k < nops; ++k) {
     uhm_op* op = ops[k];
@@ -1769,15 +1850,20 @@ int lowp_step_products(uhm_op* const* ops, const cd* const* const* xcol, cd* con
     for (int64_t b = 0; b < ceil_div(op->n * (int64_t)ncols[k], 256); ++b) w[6].push_back(make_int2(ki, (int32_t)b));
     if (lp->ntctiles > 0) {
       const int32_t fi = nops + (int32_t)fdescs.size();
-      fdescs.push_back(factor_desc(lp, d, e));
+      fdescs.push_back(factor_desc(lp, d, lp->tctiles.p, e));
       for (int32_t t = 0; t < lp->ntctiles; ++t) w[7].push_back(make_int2(fi, t));
+    }
+    if (lp->ntftiles > 0) {
+      const int32_t fi = nops + (int32_t)fdescs.size();
+      fdescs.push_back(factor_desc(lp, d, lp->tftiles.p, e));
+      for (int32_t t = 0; t < lp->ntftiles; ++t) w[8].push_back(make_int2(fi, t));
     }
   }
   descs.insert(descs.end(), fdescs.begin(), fdescs.end());
-  size_t off[9];
+  size_t off[10];
   off[0] = (sizeof(LpDesc) * descs.size() + 15) & ~size_t(15);
-  for (int st = 0; st < 8; ++st) off[st + 1] = off[st] + ((sizeof(int2) * w[st].size() + 15) & ~size_t(15));
-  const size_t tot = off[8];
+  for (int st = 0; st < 9; ++st) off[st + 1] = off[st] + ((sizeof(int2) * w[st].size() + 15) & ~size_t(15));
+  const size_t tot = off[9];
   StepProducts& sp = step_products();
   if (sp.recorded) UHM_HIP(hipEventSynchronize(sp.ev));
   if (!sp.ev) UHM_HIP(hipEventCreateWithFlags(&sp.ev, hipEventDisableTiming));
@@ -1792,9 +1878,9 @@ int lowp_step_products(uhm_op* const* ops, const cd* const* const* xcol, cd* con
     sp.cap = cap;
   }
   std::memcpy(sp.host, descs.data(), sizeof(LpDesc) * descs.size());
-  const int2* dw[8];
-  unsigned cnt[8];
-  for (int st = 0; st < 8; ++st) {
+  const int2* dw[9];
+  unsigned cnt[9];
+  for (int st = 0; st < 9; ++st) {
     std::memcpy(sp.host + off[st], w[st].data(), sizeof(int2) * w[st].size());
     dw[st] = reinterpret_cast<const int2*>(sp.dev + off[st]);
     cnt[st] = (unsigned)w[st].size();
