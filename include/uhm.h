@@ -70,7 +70,8 @@ typedef enum {
                          SX and SY.  uhm_upload only; vectors complex128 */
   UHM_C64_FACTORED = 6,     /* UHM_C64 with factored couplings where they store fewer elements
                                (the same rule); the image must carry adm_rank, SX and SY */
-  UHM_BF16PAIR_FACTORED = 7 /* UHM_BF16PAIR with factored couplings, likewise */
+  UHM_BF16PAIR_FACTORED = 7, /* UHM_BF16PAIR with factored couplings, likewise */
+  UHM_C128_MULTI_FACTORED = 8 /* UHM_C128_MULTI with factored couplings, likewise */
 } uhm_storage;
 
 typedef struct uhm_op uhm_op; /* opaque; owned by the library until uhm_free */

@@ -16,9 +16,9 @@ LIB_PATH = os.path.join(_HERE, "libuhm.so")
 
 UHM_OK, UHM_EINVAL, UHM_ENOMEM, UHM_EHIP, UHM_ENOCONV, UHM_ENOTSUP = 0, -1, -2, -3, -4, -5
 STORAGE = {"c128": 0, "c64": 1, "bf16pair": 2, "c128multi": 3, "c128sym": 4, "c128fact": 5, "c64fact": 6,
-           "bf16pairfact": 7}
-FACTORED_FORMS = ("c128fact", "c64fact", "bf16pairfact")
-C128_FORMS = ("c128", "c128multi", "c128sym", "c128fact")
+           "bf16pairfact": 7, "c128multifact": 8}
+FACTORED_FORMS = ("c128fact", "c64fact", "bf16pairfact", "c128multifact")
+C128_FORMS = ("c128", "c128multi", "c128sym", "c128fact", "c128multifact")
 
 P = ctypes.c_void_p
 I64 = ctypes.c_int64

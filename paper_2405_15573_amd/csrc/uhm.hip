@@ -1240,7 +1240,7 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
   *out = nullptr;
   if (storage != UHM_C128 && storage != UHM_C64 && storage != UHM_BF16PAIR && storage != UHM_C128_MULTI &&
       storage != UHM_C128_SYM && storage != UHM_C128_FACTORED && storage != UHM_C64_FACTORED &&
-      storage != UHM_BF16PAIR_FACTORED)
+      storage != UHM_BF16PAIR_FACTORED && storage != UHM_C128_MULTI_FACTORED)
     return fail(UHM_EINVAL, "unknown storage precision");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   TreeInfo T;
@@ -1282,8 +1282,8 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
     if (!in_bounds(h->D_off[b], h->size[t] * h->size[sg], h->D_len)) return fail(UHM_EINVAL, "D_off out of bounds");
   }
   // factored couplings: which blocks take the two-step form (fewer stored elements)
-  const bool factored =
-      storage == UHM_C128_FACTORED || storage == UHM_C64_FACTORED || storage == UHM_BF16PAIR_FACTORED;
+  const bool factored = storage == UHM_C128_FACTORED || storage == UHM_C64_FACTORED ||
+                        storage == UHM_BF16PAIR_FACTORED || storage == UHM_C128_MULTI_FACTORED;
   std::vector<char> fac(h->nadm, 0);
   if (factored) {
     if (h->nadm > 0 && (!h->adm_rank || !h->SX_off || !h->SY_off || !h->SX || !h->SY))

@@ -313,7 +313,8 @@ inline bool in_bounds(int64_t off, int64_t count, int64_t len) { return off >= 0
 
 // Storage forms whose vectors and arithmetic are complex128.
 inline bool is_c128(int storage) {
-  return storage == UHM_C128 || storage == UHM_C128_MULTI || storage == UHM_C128_SYM || storage == UHM_C128_FACTORED;
+  return storage == UHM_C128 || storage == UHM_C128_MULTI || storage == UHM_C128_SYM || storage == UHM_C128_FACTORED ||
+         storage == UHM_C128_MULTI_FACTORED;
 }
 
 int common_tree_upload(uhm_op* op, const TreeInfo& T, const int64_t* perm, const int64_t* off, const int64_t* size,

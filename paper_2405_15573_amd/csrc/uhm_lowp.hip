@@ -1435,8 +1435,12 @@ int lowp_upload(const uhm_host_operator* h, uhm_storage storage, hipStream_t s, 
   std::unique_ptr<LowpOp> lp(new (std::nothrow) LowpOp);
   if (!lp) return fail(UHM_ENOMEM, "host allocation");
   // the factored forms run the kernels of their base form
-  const bool fact = storage == UHM_C64_FACTORED || storage == UHM_BF16PAIR_FACTORED;
-  const int base = storage == UHM_C64_FACTORED ? UHM_C64 : storage == UHM_BF16PAIR_FACTORED ? UHM_BF16PAIR : storage;
+  const bool fact =
+      storage == UHM_C64_FACTORED || storage == UHM_BF16PAIR_FACTORED || storage == UHM_C128_MULTI_FACTORED;
+  const int base = storage == UHM_C64_FACTORED        ? UHM_C64
+                   : storage == UHM_BF16PAIR_FACTORED  ? UHM_BF16PAIR
+                   : storage == UHM_C128_MULTI_FACTORED ? UHM_C128_MULTI
+                                                        : storage;
   lp->storage = base;
   int rc;
   if (base == UHM_C64) {

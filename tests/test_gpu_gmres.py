@@ -89,13 +89,16 @@ def test_gmres_batch_equals_alone(torch_dev):
             assert np.array_equal(xa[:, 0], xb[:, j]), (inner, j)
 
 
-def test_gmres_with_multi_rhs_fp64_operator(torch_dev):
-    """The FP64 operator in its many-RHS layout drives both plain GMRES and the refinement."""
+@pytest.mark.parametrize("storage", ["c128multi", "c128multifact"])
+def test_gmres_with_multi_rhs_fp64_operator(torch_dev, storage):
+    """The FP64 operator in its many-RHS layout (also with factored couplings) drives both
+    plain GMRES and the refinement."""
     from paper_2405_15573_amd import binding
     torch = torch_dev
+    print(f"case gmres residual operator {storage}", flush=True)
     cloud, op = operator(n=3000, seed=3, leaf=64)
     b = inputs.make_rhs(cloud.n, 5, seed=35)
-    dop = binding.upload(op, storage="c128multi")
+    dop = binding.upload(op, storage=storage)
     inner = binding.upload(op, storage="bf16pair")
     bt = torch.from_numpy(np.ascontiguousarray(b.T)).to("cuda").t()
     for inn in (None, inner):

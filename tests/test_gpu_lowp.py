@@ -95,15 +95,17 @@ def test_lowp_dense_only(torch_dev):
         assert _col_rel(y, ref_r).max() <= 2e-5
 
 
+@pytest.mark.parametrize("storage", ["c128multi", "c128multifact"])
 @pytest.mark.parametrize("nrhs", [1, 3, 16, 17, 64, 70])
-def test_c128multi_parity(torch_dev, nrhs):
-    """complex128 storage in the many-RHS layout (FP64 MFMA): the FP64 bar, 1e-12 per column."""
+def test_c128multi_parity(torch_dev, nrhs, storage):
+    """complex128 storage in the many-RHS layout (FP64 MFMA), also with factored couplings:
+    the FP64 bar, 1e-12 per column."""
     from paper_2405_15573_amd import binding
     torch = torch_dev
-    print(f"case c128multi nrhs={nrhs}", flush=True)
+    print(f"case {storage} nrhs={nrhs}", flush=True)
     for surface, n, seed, leaf in (("sphere", 3000, 3, 64), ("cube", 1300, 5, 32)):
         cloud, op = operator(surface=surface, n=n, seed=seed, leaf=leaf)
-        dop = binding.upload(op, storage="c128multi")
+        dop = binding.upload(op, storage=storage)
         x = inputs.make_rhs(cloud.n, nrhs, seed=50 + nrhs)
         ld = cloud.n + 7
         buf = torch.zeros((nrhs, ld), dtype=torch.complex128, device="cuda")
@@ -112,7 +114,8 @@ def test_c128multi_parity(torch_dev, nrhs):
         dop.matvec(buf.t()[:cloud.n], ybuf.t()[:cloud.n])
         torch.cuda.synchronize()
         y = ybuf.t()[:cloud.n].cpu().numpy()
-        assert _col_rel(y, uniform.uh_mvp(vars(op), x)).max() <= 1e-12
+        ref_op = uniform.assemble_factored(vars(op), "smaller") if storage.endswith("fact") else vars(op)
+        assert _col_rel(y, uniform.uh_mvp(ref_op, x)).max() <= 1e-12
 
 
 @pytest.mark.parametrize("storage", ["c64fact", "bf16pairfact"])
