@@ -11,7 +11,7 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP library)")
-    config.addinivalue_line("markers", "slow: long CPU test")
+    config.addinivalue_line("markers", "slow: long test (a CPU test, or a GPU test at the full workload size)")
 
 
 _CACHE = {}

@@ -1,0 +1,78 @@
+"""Parity at the full size of the headline workload (N = 262144 sphere, kappa*h = 0.6, leaf
+64, eta 1, tolerances 1e-6), in the launch configuration bench.py times, on sampled rows the
+oracle computes block by block (uniform.uh_mvp_rows): 384 rows of 6 random leaves.
+
+Bars: FP64 forms (general, symmetric and factored storage) 1e-12 relative on the sampled
+rows; complex64 and bf16-pair forms with 64 right-hand sides against the FP64 oracle 1e-5
+and 2e-2.  The operator build takes about two minutes on 16 host threads.
+"""
+import numpy as np
+import pytest
+
+from oracle import uniform
+from paper_2405_15573_amd import inputs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+N = 262144
+
+
+@pytest.fixture(scope="module")
+def full(request):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    from paper_2405_15573_amd import binding, builder
+    binding.load_library()
+    print(f"building the N={N} sphere operator", flush=True)
+    cloud = inputs.make_cloud("sphere", N, seed=0)
+    op = builder.build_operator(cloud, leaf=64, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, verbose=True)
+    leaves = np.nonzero(np.bincount(op.parent[op.parent >= 0], minlength=op.nclusters) == 0)[0]
+    pick = np.random.default_rng(12345).choice(leaves, size=6, replace=False)
+    pos = np.concatenate([np.arange(op.off[c], op.off[c] + op.size[c]) for c in pick])
+    return torch, cloud, op, pos
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.timeout(900)
+def test_fp64_forms_at_full_size(full):
+    from paper_2405_15573_amd import binding, builder
+    torch, cloud, op, pos = full
+    x = inputs.make_rhs(cloud.n, 1, seed=0)[:, 0]
+    xd = torch.from_numpy(x).to("cuda")
+    sym = builder.symmetric_image(op)
+    cases = [("c128", op, vars(op)), ("c128sym", sym, None), ("c128fact", op, None)]
+    for form, img, ref_img in cases:
+        print(f"case full-size {form}", flush=True)
+        dop = binding.upload(img, form)
+        y = dop.matvec(xd).cpu().numpy()
+        dop.free()
+        if form == "c128sym":
+            ref_img = uniform.expand_symmetric(sym)
+        elif form == "c128fact":
+            ref_img = uniform.assemble_factored(vars(op), "smaller")
+        ref, users = uniform.uh_mvp_rows(ref_img, x, pos)
+        err = _rel(y[users], ref[:, 0])
+        print(f"  sampled parity {err:.2e}", flush=True)
+        assert err <= 1e-12
+
+
+@pytest.mark.timeout(900)
+def test_precision_forms_at_full_size(full):
+    from paper_2405_15573_amd import binding
+    torch, cloud, op, pos = full
+    r = 64
+    x = inputs.make_rhs(cloud.n, r, seed=7).astype(np.complex64).astype(np.complex128)
+    ref, users = uniform.uh_mvp_rows(vars(op), x, pos)
+    xd = torch.from_numpy(np.ascontiguousarray(x.T.astype(np.complex64))).to("cuda").t()
+    for form, bar in (("c64", 1e-5), ("c64fact", 1e-5), ("bf16pair", 2e-2), ("bf16pairfact", 2e-2)):
+        print(f"case full-size {form} {r} RHS", flush=True)
+        dop = binding.upload(op, form)
+        y = dop.matvec(xd).cpu().numpy().astype(np.complex128)
+        dop.free()
+        err = max(_rel(y[users, j], ref[:, j]) for j in range(r))
+        print(f"  sampled error vs FP64 {err:.2e}", flush=True)
+        assert err <= bar
