@@ -1420,7 +1420,7 @@ int grow(LowpOp* lp, int64_t n, int R) {
   if ((rc = lp->Xc.alloc(e * n * R)) || (rc = lp->Yc.alloc(e * n * R)) ||
       (rc = lp->p.alloc(e * std::max<int64_t>(1, lp->p_rows * R))) ||
       (rc = lp->xh.alloc(e * std::max<int64_t>(1, (lp->nxh + lp->ntf) * R))) ||
-      (rc = lp->part.alloc(e * std::max<int64_t>(1, (int64_t)std::max(lp->nctiles, lp->ntctiles) * 64 * R))) ||
+      (rc = lp->part.alloc(e * std::max<int64_t>(1, (int64_t)lp->nctiles * 64 * R))) ||
       (rc = lp->yh.alloc(e * std::max<int64_t>(1, lp->nyh * R)))) {
     lp->wsR = 0;
     return rc;
