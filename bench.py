@@ -265,6 +265,134 @@ def run_gmres_sizes(args):
     print(json.dumps(line), flush=True)
 
 
+def run_construct(args):
+    """Sampling the matrix on the GPU (ACA of every admissible block, uhm_aca, and the dense
+    near-field blocks, uhm_kernel_blocks) against the host builder's OpenMP C++ on the same
+    blocks: times, rank agreement, and sampled parity of the GPU factors with the oracle."""
+    import numpy as np
+    import torch
+
+    from oracle import aca as oaca
+    from paper_2405_15573_amd import binding, builder, inputs
+    cloud = inputs.make_cloud("sphere", args.n, seed=args.seed)
+    tree = builder.build_tree(cloud.points, args.leaf)
+    pts = np.ascontiguousarray(cloud.points[tree.perm])
+    diag = 1.0 / (2.0 * cloud.h)
+    adm, den = builder.build_block_tree(tree, 1.0)
+    low = adm[adm[:, 0] < adm[:, 1]]
+    levs = tree.level[low[:, 0]]
+    dev_pts = binding._points_on_device(pts)
+    lib = builder._native()
+    P = builder._ptr
+    eps, kcap = 1e-6, 1024
+    stream = torch.cuda.Stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # warm-up launch (module load)
+    binding.aca(dev_pts, cloud.kappa, diag, [0], [8], [64], [8], [4], eps, stream=stream)
+    torch.cuda.synchronize()
+    per_level, tot = {}, {"gpu_ms": 0.0, "host_s": 0.0, "entries": 0, "update_flops": 0, "blocks": 0,
+                          "rank_equal": 0, "reruns": 0}
+    sample = []
+    for lev in np.unique(levs):
+        blk = low[levs == lev]
+        ro, rs = tree.off[blk[:, 0]], tree.size[blk[:, 0]]
+        co, cs = tree.off[blk[:, 1]], tree.size[blk[:, 1]]
+        order = np.argsort(-(rs + cs), kind="stable")
+        ro, rs, co, cs = ro[order], rs[order], co[order], cs[order]
+        full = np.minimum(np.minimum(rs, cs), kcap)
+        rank = np.zeros(len(ro), np.int64)
+        todo, cap_now, ms = np.arange(len(ro)), 128, 0.0
+        first = None
+        while todo.size:
+            caps = np.minimum(full[todo], cap_now)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            res = binding.aca(dev_pts, cloud.kappa, diag, ro[todo], rs[todo], co[todo], cs[todo], caps, eps,
+                              stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1)
+            done = (res.status != 0) | (caps >= full[todo])
+            rank[todo[done]] = res.rank[done]
+            if first is None:
+                first = (res, todo.copy())
+            else:
+                tot["reruns"] += int(done.sum())
+            todo = todo[~done]
+            cap_now *= 4
+        kout = np.zeros(len(ro), np.int32)
+        t = time.perf_counter()
+        h = lib.uhmb_aca_run(P(pts), cloud.kappa, diag, len(ro), P(np.ascontiguousarray(ro)),
+                             P(np.ascontiguousarray(rs)), P(np.ascontiguousarray(co)), P(np.ascontiguousarray(cs)),
+                             eps, kcap, P(kout))
+        host_s = time.perf_counter() - t
+        lib.uhmb_aca_free(h)
+        entries = int(np.sum(rank * (rs + cs)))
+        flops = int(np.sum(8 * rank * (rank - 1) * (rs + cs)))  # residual updates + norm cross terms
+        eq = int(np.sum(rank == kout))
+        per_level[int(lev)] = {"blocks": len(ro), "rows": int(rs.max()), "k_max": int(rank.max()),
+                               "gpu_ms": round(ms, 3), "host_s": round(host_s, 3), "rank_equal_host": eq}
+        log(f"level {lev}: {len(ro)} blocks of {int(rs.max())}, k_max {int(rank.max())}: GPU {ms:.2f} ms, "
+            f"host {host_s:.2f} s, ranks equal {eq}/{len(ro)}")
+        for key, v in (("gpu_ms", ms), ("host_s", host_s), ("entries", entries), ("update_flops", flops),
+                       ("blocks", len(ro)), ("rank_equal", eq)):
+            tot[key] += v
+        # sampled parity with the oracle: two blocks of each level up to 1024 rows (first pass, full rank)
+        res, idx = first
+        if int(rs.max()) <= 1024:
+            for b in (0, len(idx) - 1):
+                if res.status[b] == 0:
+                    continue
+                j = int(idx[b])
+                u, v, pr, pc, conv = oaca.aca_kernel_block(pts, cloud.kappa, diag, int(ro[j]), int(rs[j]), int(co[j]),
+                                                           int(cs[j]), eps, int(res.cap[b]))
+                gu, gv, gpr, gpc = res.factors(b)
+                ok = (np.array_equal(gpr, pr) and np.array_equal(gpc, pc) and gu.shape == u.shape)
+                blk = oaca.kernel_block(pts, cloud.kappa, diag, np.arange(ro[j], ro[j] + rs[j]),
+                                        np.arange(co[j], co[j] + cs[j]))
+                err = float(np.linalg.norm(gu @ gv.T - u @ v.T) / np.linalg.norm(blk)) if ok else float("inf")
+                sample.append({"level": int(lev), "rows": int(rs[j]), "k": int(u.shape[1]), "pivots_equal": ok,
+                               "approx_rel_diff": err, "aca_rel_err": float(np.linalg.norm(gu @ gv.T - blk)
+                                                                             / np.linalg.norm(blk))})
+        del first, res
+    # dense near field
+    ro, rs, co, cs = tree.off[den[:, 0]], tree.size[den[:, 0]], tree.off[den[:, 1]], tree.size[den[:, 1]]
+    torch.cuda.synchronize()
+    e0.record(stream)
+    Dd, doff = binding.kernel_blocks(dev_pts, cloud.kappa, diag, ro, rs, co, cs, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dense_ms = e0.elapsed_time(e1)
+    Dh = np.empty(int(np.sum(rs * cs)), np.complex128)
+    t = time.perf_counter()
+    lib.uhmb_dense_blocks(P(pts), cloud.kappa, diag, len(ro), P(np.ascontiguousarray(ro)), P(np.ascontiguousarray(rs)),
+                          P(np.ascontiguousarray(co)), P(np.ascontiguousarray(cs)), P(np.ascontiguousarray(doff)), P(Dh))
+    dense_host_s = time.perf_counter() - t
+    dense_err = float(np.max(np.abs(Dd.cpu().numpy() - Dh)) / np.max(np.abs(Dh)))
+    del Dd, Dh
+    worst = max((sm["approx_rel_diff"] for sm in sample), default=None)
+    gpu_s = (tot["gpu_ms"] + dense_ms) / 1e3
+    host_s = tot["host_s"] + dense_host_s
+    line = {
+        "metric": "matrix sampling for construction: ACA of every admissible block + dense near field",
+        "value": round(gpu_s, 4), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(gpu_s * 1e3, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"sphere N={cloud.n}, leaf {args.leaf}, eta 1, ACA eps {eps}, kappa*h=0.6"},
+        "aca": {"gpu_ms": round(tot["gpu_ms"], 3), "host_s": round(tot["host_s"], 3),
+                "speedup": round(tot["host_s"] * 1e3 / tot["gpu_ms"], 1), "blocks": tot["blocks"],
+                "rank_equal_host": tot["rank_equal"], "reruns_at_larger_cap": tot["reruns"],
+                "entries_sampled": tot["entries"], "entries_per_s": round(tot["entries"] / (tot["gpu_ms"] / 1e3), 1),
+                "update_tflops": round(tot["update_flops"] / (tot["gpu_ms"] / 1e3) / 1e12, 3),
+                "per_level": per_level},
+        "dense": {"gpu_ms": round(dense_ms, 3), "host_s": round(dense_host_s, 3), "entries": int(np.sum(rs * cs)),
+                  "max_rel_diff_host": dense_err},
+        "host_threads": int(lib.uhmb_num_threads()),
+        "parity_sample": {"blocks": len(sample), "pivots_equal": all(sm["pivots_equal"] for sm in sample),
+                          "worst_approx_rel_diff": worst},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def run_serving(args):
     """Poisson arrivals of GMRES-IR solve requests over resident operators."""
     import numpy as np
@@ -335,10 +463,11 @@ def main():
     ap.add_argument("--gmres-maxit", type=int, default=200)
     ap.add_argument("--gmres-small-n", type=int, default=16384,
                     help="size of the sphere at which the time-to-tolerance comparison runs to convergence")
-    ap.add_argument("--mode", choices=("headline", "batched", "serving", "gmres"), default="headline",
+    ap.add_argument("--mode", choices=("headline", "batched", "serving", "gmres", "construct"), default="headline",
                     help="headline: the FP64 workload and its side measurements; batched: many operators in "
                          "shared launches; serving: Poisson arrivals of GMRES solves; gmres: time to tolerance "
-                         "of FP64 GMRES and GMRES-IR over sphere sizes")
+                         "of FP64 GMRES and GMRES-IR over sphere sizes; construct: ACA and near-field "
+                         "sampling on the GPU vs the host builder")
     ap.add_argument("--gmres-sizes", type=str, default="16384,32768,65536",
                     help="sphere sizes of --mode gmres")
     ap.add_argument("--gmres-cases", type=str, default="", help="gmres mode: comma list of cases to run")
@@ -383,6 +512,8 @@ def main():
         return run_serving(args)
     if args.mode == "gmres":
         return run_gmres_sizes(args)
+    if args.mode == "construct":
+        return run_construct(args)
 
     if args.copy_calibration:
         a = torch.empty(1 << 26, dtype=torch.complex128, device="cuda")  # 1 GiB

@@ -330,6 +330,67 @@ int uhm_kernel_times(uhm_op* op, const char** names, double* total_ms, int64_t* 
 /* Release every device allocation of the operator.  NULL is a no-op. */
 void uhm_free(uhm_op* op);
 
+/* ---------------------------------------------------------------------------------------
+ * Construction on the GPU: blocks of the kernel matrix and their adaptive cross
+ * approximation (section 2.3).
+ *
+ * The matrix is the point-kernel matrix of the Helmholtz single-layer kernel (section 6.1):
+ * A_ij = exp(i kappa r_ij) / (4 pi r_ij) with r_ij = |p_i - p_j|, and A_ij = diag where
+ * i = j or the two points coincide.  `points` is a DEVICE array of npoints x 3 doubles
+ * (row-major, x y z), in cluster order; blocks address rows and columns by position in it.
+ * Every pointer below is a device pointer except where stated; nothing is allocated, and
+ * the calls are asynchronous on `hip_stream`.  Each block descriptor is checked on the
+ * device: a descriptor whose sizes, positions or output ranges do not fit the given
+ * lengths is not processed and gets status -1.
+ */
+typedef struct uhm_block_desc {
+  int64_t row_off;  /* first row position, 0 <= row_off, row_off + rows <= npoints */
+  int64_t col_off;  /* first column position, likewise */
+  int32_t rows;     /* m >= 1 */
+  int32_t cols;     /* n >= 1 */
+  int32_t cap;      /* ACA: most terms kept, 1 <= cap <= max_cap; uhm_kernel_blocks: unused */
+  int32_t reserved; /* 0 */
+  int64_t a_off;    /* uhm_kernel_blocks: complex offset of the m x n block in D;
+                       uhm_aca: complex offset of u (m x cap) in U */
+  int64_t b_off;    /* uhm_aca: complex offset of v (n x cap) in V */
+  int64_t p_off;    /* uhm_aca: offset in piv of 2*cap int32 pivots (cap rows, then cap columns) */
+} uhm_block_desc;
+
+/*
+ * D[a_off + i + j*m] = A[row_off + i, col_off + j] (column-major, complex128) for every
+ * block; the dense near-field blocks of the operator (P-, Definition 2.2).  status[b] is 1
+ * for a block written, -1 for a rejected descriptor.  D_len counts complex elements.
+ * Errors: UHM_EINVAL (negative sizes, null pointers with nblocks > 0), UHM_EHIP.
+ */
+int uhm_kernel_blocks(const double* points, int64_t npoints, double kappa, double diag,
+                      const uhm_block_desc* blocks, int64_t nblocks, double* D, int64_t D_len,
+                      int32_t* status, void* hip_stream);
+
+/*
+ * ACA with partial pivoting (section 2.3; the variant of Bebendorf the paper cites) of each
+ * block A|_b = A[row_off : row_off+m, col_off : col_off+n], one wavefront per block:
+ *   start from row i_1 = 0; at step k take the residual row r = A[i_k, :] - sum_{l<k}
+ *   u_l[i_k] v_l, mark row i_k used, pick j_k maximising |r_j| (if r vanishes, retry with
+ *   the unused row of smallest index), set v_k = r / r[j_k] and u_k = A[:, j_k] -
+ *   sum_{l<k} v_l[j_k] u_l; stop once |u_k| |v_k| <= eps |sum_{l<=k} u_l v_l^T|_F (the
+ *   Frobenius norm updated term by term), else continue from the unused row maximising
+ *   |u_k[i]|; at most min(m, n, cap) terms.  Moduli are compared as re^2 + im^2 in FP64 and
+ *   the first index wins a tie.
+ * Outputs, per block: A|_b ~ sum_{l<k} u_l v_l^T with u_l = U[a_off + l*m : ... + m] and
+ * v_l = V[b_off + l*n : ... + n] (complex128, column-major, columns k..cap-1 undefined);
+ * piv[p_off + l] = i_l and piv[p_off + cap + l] = j_l (block-relative); rank[b] = k;
+ * status[b] = 1 when the stopping test ended the iteration, 2 when the block ran out of
+ * rows or reached min(m, n) terms, 0 when `cap` (< min(m, n)) stopped it first (call again
+ * with a larger cap), -1 for a rejected descriptor.
+ * max_rows (1..65536) and max_cap (1..1024) bound every block's rows and cap and size the
+ * local memory of the launch.  U_len, V_len count complex elements, piv_len int32 entries.
+ * Errors: UHM_EINVAL (bounds above, eps < 0 or not finite, null pointers), UHM_EHIP.
+ */
+int uhm_aca(const double* points, int64_t npoints, double kappa, double diag,
+            const uhm_block_desc* blocks, int64_t nblocks, int32_t max_rows, int32_t max_cap, double eps,
+            double* U, int64_t U_len, double* V, int64_t V_len, int32_t* piv, int64_t piv_len,
+            int32_t* rank, int32_t* status, void* hip_stream);
+
 const char* uhm_strerror(int code);
 const char* uhm_last_error(void);
 int uhm_version(void);

@@ -59,13 +59,25 @@ class GmresInfo(ctypes.Structure):
                 ("second_passes", I64)]
 
 
+class BlockDesc(ctypes.Structure):
+    _fields_ = [("row_off", I64), ("col_off", I64), ("rows", I32), ("cols", I32), ("cap", I32), ("reserved", I32),
+                ("a_off", I64), ("b_off", I64), ("p_off", I64)]
+
+
+# the same layout as a numpy record, to fill many descriptors at once
+BLOCK_DTYPE = np.dtype({"names": [f for f, _ in BlockDesc._fields_],
+                        "formats": [np.int64 if t is I64 else np.int32 for _, t in BlockDesc._fields_],
+                        "offsets": [getattr(BlockDesc, f).offset for f, _ in BlockDesc._fields_],
+                        "itemsize": ctypes.sizeof(BlockDesc)})
+
 KRYLOV_DONE, KRYLOV_PRODUCT_HIGH, KRYLOV_PRODUCT_LOW = 0, 1, 2
 
 EXPORTS = ("uhm_upload", "uhm_upload_h", "uhm_matvec", "uhm_solve_gmres", "uhm_krylov_create", "uhm_krylov_next",
            "uhm_krylov_advance", "uhm_krylov_result", "uhm_krylov_free", "uhm_krylov_step",
            "uhm_batch_create", "uhm_batch_run",
            "uhm_batch_tune", "uhm_batch_capture", "uhm_batch_free", "uhm_op_info_get", "uhm_set_timing",
-           "uhm_kernel_times", "uhm_free", "uhm_strerror", "uhm_last_error", "uhm_version")
+           "uhm_kernel_times", "uhm_free", "uhm_strerror", "uhm_last_error", "uhm_version",
+           "uhm_kernel_blocks", "uhm_aca")
 
 _LIB = None
 
@@ -125,6 +137,11 @@ def load_library(path: str = LIB_PATH):
     lib.uhm_last_error.argtypes = []
     lib.uhm_last_error.restype = ctypes.c_char_p
     lib.uhm_version.restype = ctypes.c_int
+    D = ctypes.c_double
+    lib.uhm_kernel_blocks.argtypes = [P, I64, D, D, P, I64, P, I64, P, P]
+    lib.uhm_kernel_blocks.restype = ctypes.c_int
+    lib.uhm_aca.argtypes = [P, I64, D, D, P, I64, I32, I32, D, P, I64, P, I64, P, I64, P, P, P]
+    lib.uhm_aca.restype = ctypes.c_int
     _LIB = lib
     return lib
 
@@ -475,3 +492,116 @@ def krylov_step(solves, highs, lows=None, stream=None) -> int:
     if rc < 0:
         raise UhmError(rc, "uhm_krylov_step")
     return rc
+
+
+# --------------------------------------------------------------------------- construction
+def _points_on_device(points):
+    import torch
+    if isinstance(points, torch.Tensor):
+        if points.device.type != "cuda" or points.dtype != torch.float64 or points.dim() != 2 \
+                or points.shape[1] != 3 or not points.is_contiguous():
+            raise ValueError("points must be a contiguous (n, 3) float64 tensor on the HIP device")
+        return points
+    a = np.ascontiguousarray(points, dtype=np.float64)
+    if a.ndim != 2 or a.shape[1] != 3:
+        raise ValueError("points must have shape (n, 3)")
+    return torch.from_numpy(a).to("cuda")
+
+
+def _descs(row_off, rows, col_off, cols, cap=None):
+    nb = len(rows)
+    d = np.zeros(nb, BLOCK_DTYPE)
+    d["row_off"], d["rows"], d["col_off"], d["cols"] = row_off, rows, col_off, cols
+    if cap is not None:
+        d["cap"] = cap
+    return d
+
+
+def _to_device(arr):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(arr).view(np.uint8)).to("cuda")
+
+
+def kernel_blocks(points, kappa: float, diag: float, row_off, rows, col_off, cols, stream=None):
+    """Dense blocks A[row_off:row_off+rows, col_off:col_off+cols] of the point-kernel matrix,
+    computed on the device (uhm_kernel_blocks).  Returns (D, offsets): D a flat complex128
+    device tensor holding block b column-major at offsets[b]."""
+    import torch
+    lib = load_library()
+    pts = _points_on_device(points)
+    rows = np.asarray(rows, np.int64)
+    cols = np.asarray(cols, np.int64)
+    d = _descs(row_off, rows, col_off, cols)
+    sz = rows * cols
+    d["a_off"] = np.concatenate([[0], np.cumsum(sz)[:-1]]) if len(sz) else []
+    total = int(sz.sum())
+    h, stream = _stream_handle(stream)
+    with torch.cuda.stream(stream):   # allocations, copies and the launch in one stream order
+        D = torch.empty(total, dtype=torch.complex128, device="cuda")
+        status = torch.empty(len(rows), dtype=torch.int32, device="cuda")
+        dd = _to_device(d)
+        _check(lib.uhm_kernel_blocks(ctypes.c_void_p(pts.data_ptr()), pts.shape[0], float(kappa), float(diag),
+                                     ctypes.c_void_p(dd.data_ptr()), len(rows), ctypes.c_void_p(D.data_ptr()), total,
+                                     ctypes.c_void_p(status.data_ptr()), h), "uhm_kernel_blocks")
+        st = status.cpu().numpy()
+    if (st != 1).any():
+        raise UhmError(UHM_EINVAL, f"uhm_kernel_blocks: {int((st != 1).sum())} descriptors rejected")
+    return D, d["a_off"].copy()
+
+
+class AcaResult:
+    """Device outputs of uhm_aca for a list of blocks: U, V (flat complex128 tensors), piv
+    (int32 tensor), the host arrays rank, status, and the per-block offsets u_off, v_off, p_off
+    and caps."""
+
+    def __init__(self, U, V, piv, rank, status, desc):
+        self.U, self.V, self.piv = U, V, piv
+        self.rank, self.status = rank, status
+        self.u_off, self.v_off, self.p_off = desc["a_off"].copy(), desc["b_off"].copy(), desc["p_off"].copy()
+        self.rows, self.cols, self.cap = (desc["rows"].astype(np.int64), desc["cols"].astype(np.int64),
+                                          desc["cap"].astype(np.int64))
+
+    def factors(self, b: int):
+        """(u (m x k), v (n x k), pivot rows, pivot columns) of block b, on the host."""
+        m, n, k, c = int(self.rows[b]), int(self.cols[b]), int(self.rank[b]), int(self.cap[b])
+        u = self.U[self.u_off[b]:self.u_off[b] + m * k].cpu().numpy().reshape(k, m).T
+        v = self.V[self.v_off[b]:self.v_off[b] + n * k].cpu().numpy().reshape(k, n).T
+        p = self.piv[self.p_off[b]:self.p_off[b] + 2 * c].cpu().numpy()
+        return u, v, p[:k].astype(np.int64), p[c:c + k].astype(np.int64)
+
+
+def aca(points, kappa: float, diag: float, row_off, rows, col_off, cols, cap, eps: float, stream=None) -> AcaResult:
+    """ACA with partial pivoting of every block on the device (uhm_aca), one wavefront per
+    block, in the order given.  cap: most terms per block (scalar or per block)."""
+    import torch
+    lib = load_library()
+    pts = _points_on_device(points)
+    rows = np.asarray(rows, np.int64)
+    cols = np.asarray(cols, np.int64)
+    nb = len(rows)
+    cap = np.broadcast_to(np.asarray(cap, np.int64), (nb,)).copy()
+    d = _descs(row_off, rows, col_off, cols, cap)
+    usz, vsz, psz = rows * cap, cols * cap, 2 * cap
+    d["a_off"] = np.concatenate([[0], np.cumsum(usz)[:-1]]) if nb else []
+    d["b_off"] = np.concatenate([[0], np.cumsum(vsz)[:-1]]) if nb else []
+    d["p_off"] = np.concatenate([[0], np.cumsum(psz)[:-1]]) if nb else []
+    h, stream = _stream_handle(stream)
+    max_rows = int(rows.max()) if nb else 1
+    max_cap = int(cap.max()) if nb else 1
+    with torch.cuda.stream(stream):   # allocations, copies and the launch in one stream order
+        U = torch.zeros(int(usz.sum()), dtype=torch.complex128, device="cuda")
+        V = torch.zeros(int(vsz.sum()), dtype=torch.complex128, device="cuda")
+        piv = torch.full((int(psz.sum()),), -1, dtype=torch.int32, device="cuda")
+        rank = torch.zeros(nb, dtype=torch.int32, device="cuda")
+        status = torch.zeros(nb, dtype=torch.int32, device="cuda")
+        dd = _to_device(d)
+        _check(lib.uhm_aca(ctypes.c_void_p(pts.data_ptr()), pts.shape[0], float(kappa), float(diag),
+                           ctypes.c_void_p(dd.data_ptr()), nb, max_rows, max_cap, float(eps),
+                           ctypes.c_void_p(U.data_ptr()), U.numel(), ctypes.c_void_p(V.data_ptr()), V.numel(),
+                           ctypes.c_void_p(piv.data_ptr()), piv.numel(), ctypes.c_void_p(rank.data_ptr()),
+                           ctypes.c_void_p(status.data_ptr()), h), "uhm_aca")
+        st = status.cpu().numpy()
+        rk = rank.cpu().numpy()
+    if (st < 0).any():
+        raise UhmError(UHM_EINVAL, f"uhm_aca: {int((st < 0).sum())} descriptors rejected")
+    return AcaResult(U, V, piv, rk, st, d)

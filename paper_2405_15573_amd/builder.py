@@ -281,11 +281,62 @@ def _pmap(fn, items):
             ctx.__exit__(None, None, None)
 
 
+def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_cap=128):
+    """ACA of one level's blocks on the GPU (uhm_aca).  Blocks whose first pass stopped at
+    its rank capacity run again with a four times larger one, up to kcap.  Returns the ranks
+    and, per (shape, pass) group, (block indices, X (cnt, m, kp), Y (cnt, n, kp)) with
+    A|_b ~ X Y^H and zero columns beyond each block's rank (the layout of uhmb_aca_copy)."""
+    from . import binding
+    nb = roff.shape[0]
+    kout = np.zeros(nb, np.int32)
+    groups = []
+    todo = np.arange(nb)
+    cap_now = first_cap
+    kernel_s = 0.0
+    while todo.size:
+        order = np.lexsort((csz[todo], rsz[todo]))
+        idx = todo[order]
+        full = np.minimum(np.minimum(rsz[idx], csz[idx]), kcap)
+        caps = np.minimum(full, cap_now)
+        tk = time.perf_counter()
+        res = binding.aca(dev_pts, kappa, diag, roff[idx], rsz[idx], coff[idx], csz[idx], caps, eps)
+        kernel_s += time.perf_counter() - tk
+        final = (res.status != 0) | (caps >= full)
+        kout[idx[final]] = res.rank[final]
+        shapes = np.stack([rsz[idx], csz[idx]], 1)
+        for (m, n) in np.unique(shapes, axis=0):
+            pos = np.nonzero((shapes[:, 0] == m) & (shapes[:, 1] == n))[0]   # contiguous in idx
+            c = int(caps[pos[0]])
+            keep = pos[final[pos]]
+            if keep.size == 0:
+                continue
+            kp = int(res.rank[keep].max())
+            a0, b0 = int(res.u_off[pos[0]]), int(res.v_off[pos[0]])
+            rel = keep - pos[0]
+            Ug = res.U[a0:a0 + pos.size * c * m].view(pos.size, c, m)[rel][:, :kp, :].cpu().numpy()
+            Vg = res.V[b0:b0 + pos.size * c * n].view(pos.size, c, n)[rel][:, :kp, :].cpu().numpy()
+            live = (np.arange(kp)[None, :] < res.rank[keep][:, None])[:, :, None]
+            X = np.ascontiguousarray(np.where(live, Ug, 0.0).transpose(0, 2, 1))
+            Y = np.ascontiguousarray(np.conj(np.where(live, Vg, 0.0)).transpose(0, 2, 1))
+            groups.append((idx[keep], int(m), int(n), X, Y))
+        todo = idx[~final]
+        cap_now *= 4
+        del res
+    return kout, groups, kernel_s
+
+
 def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca: float = 1e-6,
                    eps_comp: float = 1e-6, eps_rec: float | None = None, kcap: int = 1024,
-                   verbose: bool = False) -> HostOperator:
+                   verbose: bool = False, construct: str = "host") -> HostOperator:
     """Build the H form and the UH form of the point-kernel matrix A_ij = g(x_i, x_j),
-    A_ii = 1/(2h), for one seeded cloud."""
+    A_ii = 1/(2h), for one seeded cloud.
+
+    construct="gpu" samples the matrix on the GPU: ACA of the admissible blocks
+    (uhm_aca) and the dense near-field blocks (uhm_kernel_blocks); the recompression and
+    the uniform compression stay on the host.  construct="host" does everything on the
+    host (OpenMP C++ and LAPACK)."""
+    if construct not in ("host", "gpu"):
+        raise ValueError("construct must be 'host' or 'gpu'")
     lib = _native()
     if eps_rec is None:
         eps_rec = eps_aca / 10.0
@@ -301,13 +352,18 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
     off, size = tree.off, tree.size
 
     # ---- admissible blocks: ACA + recompression on one block of each mirrored pair
+    dev_pts = None
+    if construct == "gpu":
+        from . import binding
+        binding.load_library()
+        dev_pts = binding._points_on_device(pts)
     lower = adm[adm[:, 0] < adm[:, 1]]
     if np.any(adm[:, 0] == adm[:, 1]):
         raise RuntimeError("a cluster is admissible with itself")
     fac_U, fac_V, fac_s = {}, {}, {}   # keyed by (tau, sigma) with tau < sigma
     t1 = time.perf_counter()
     levels = tree.level[lower[:, 0]] if lower.shape[0] else np.zeros(0, np.int32)
-    t_aca = t_rec = 0.0
+    t_aca = t_rec = t_aca_kernel = 0.0
     for lev in np.unique(levels):
         blk = lower[levels == lev]
         nb = blk.shape[0]
@@ -317,19 +373,19 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
         csz = np.ascontiguousarray(size[blk[:, 1]])
         kout = np.zeros(nb, np.int32)
         ta = time.perf_counter()
-        handle = lib.uhmb_aca_run(_ptr(pts), kappa, diag, nb, _ptr(roff), _ptr(rsz), _ptr(coff), _ptr(csz),
-                                  eps_aca, kcap, _ptr(kout))
-        if not handle:
-            raise MemoryError("ACA batch allocation failed")
+        handle = None
+        if construct == "gpu":
+            kout, gpu_groups, ks = _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps_aca, kcap)
+            t_aca_kernel += ks
+        else:
+            handle = lib.uhmb_aca_run(_ptr(pts), kappa, diag, nb, _ptr(roff), _ptr(rsz), _ptr(coff), _ptr(csz),
+                                      eps_aca, kcap, _ptr(kout))
+            if not handle:
+                raise MemoryError("ACA batch allocation failed")
         t_aca += time.perf_counter() - ta
         tr = time.perf_counter()
-        def recompress(job):
-            part, m, n, kp = job
-            cnt = len(part)
-            X = np.empty((cnt, m, kp), np.complex128)
-            Y = np.empty((cnt, n, kp), np.complex128)
-            idx = np.ascontiguousarray(part, dtype=np.int64)
-            lib.uhmb_aca_copy(handle, cnt, _ptr(idx), int(m), int(n), kp, _ptr(X), _ptr(Y))
+
+        def recompress_xy(part, X, Y):
             QX, RX = np.linalg.qr(X)
             QY, RY = np.linalg.qr(Y)
             del X, Y
@@ -342,25 +398,47 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
                             QY[c] @ np.conj(Zh[c][:k, :]).T, sc[:k].copy()))
             return out
 
+        def recompress(job):
+            if handle is None:
+                return recompress_xy(*job)
+            part, m, n, kp = job
+            cnt = len(part)
+            X = np.empty((cnt, m, kp), np.complex128)
+            Y = np.empty((cnt, n, kp), np.complex128)
+            idx = np.ascontiguousarray(part, dtype=np.int64)
+            lib.uhmb_aca_copy(handle, cnt, _ptr(idx), int(m), int(n), kp, _ptr(X), _ptr(Y))
+            return recompress_xy(part, X, Y)
+
         try:
             jobs = []
-            shapes = np.stack([rsz, csz], 1)
-            for (m, n) in np.unique(shapes, axis=0):
-                sel = np.nonzero((rsz == m) & (csz == n))[0]
-                kp = int(kout[sel].max())
-                for part in _chunks(sel, 16 * (m + n) * kp * 4, parts=4 * _workers()):
-                    jobs.append((part, int(m), int(n), kp))
+            if handle is None:
+                for sel, m, n, X, Y in gpu_groups:
+                    kp = X.shape[2]
+                    step = max(1, len(list(_chunks(sel, 16 * (m + n) * kp * 4, parts=4 * _workers()))[0]))
+                    for a in range(0, len(sel), step):
+                        jobs.append((sel[a:a + step], X[a:a + step], Y[a:a + step]))
+                del gpu_groups
+            else:
+                shapes = np.stack([rsz, csz], 1)
+                for (m, n) in np.unique(shapes, axis=0):
+                    sel = np.nonzero((rsz == m) & (csz == n))[0]
+                    kp = int(kout[sel].max())
+                    for part in _chunks(sel, 16 * (m + n) * kp * 4, parts=4 * _workers()):
+                        jobs.append((part, int(m), int(n), kp))
             for res in _pmap(recompress, jobs):
                 for key, Ub, Vb, sb in res:
                     fac_U[key] = Ub
                     fac_V[key] = Vb
                     fac_s[key] = sb
         finally:
-            lib.uhmb_aca_free(handle)
+            if handle is not None:
+                lib.uhmb_aca_free(handle)
         t_rec += time.perf_counter() - tr
         if verbose:
             print(f"  level {lev}: {nb} ACA blocks, k_max {int(kout.max())}", file=sys.stderr, flush=True)
     tim["aca"] = t_aca
+    if construct == "gpu":
+        tim["aca_gpu_calls"] = t_aca_kernel
     tim["recompress"] = t_rec
     if verbose:
         print(f"  ACA {t_aca:.1f} s, recompression {t_rec:.1f} s", file=sys.stderr, flush=True)
@@ -488,7 +566,13 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
     dsz = size[den[:, 0]] * size[den[:, 1]]
     D_off = np.concatenate([[0], np.cumsum(dsz)[:-1]]).astype(np.int64) if nden else np.zeros(0, np.int64)
     D = np.empty(int(dsz.sum()), np.complex128)
-    if nden:
+    if nden and construct == "gpu":
+        Dd, doff = binding.kernel_blocks(dev_pts, kappa, diag, off[den[:, 0]], size[den[:, 0]], off[den[:, 1]],
+                                         size[den[:, 1]])
+        assert np.array_equal(doff, D_off)
+        D = Dd.cpu().numpy()
+        del Dd
+    elif nden:
         d_ro = np.ascontiguousarray(off[den[:, 0]])
         d_rs = np.ascontiguousarray(size[den[:, 0]])
         d_co = np.ascontiguousarray(off[den[:, 1]])

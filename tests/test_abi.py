@@ -30,7 +30,8 @@ def test_library_exports_every_declared_symbol():
 
 
 STRUCTS = (("uhm_host_operator", binding.HostOperator), ("uhm_host_hmatrix", binding.HostHMatrix),
-           ("uhm_op_info", binding.OpInfo), ("uhm_gmres_opts", binding.GmresOpts), ("uhm_gmres_info", binding.GmresInfo))
+           ("uhm_op_info", binding.OpInfo), ("uhm_gmres_opts", binding.GmresOpts), ("uhm_gmres_info", binding.GmresInfo),
+           ("uhm_block_desc", binding.BlockDesc))
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -53,3 +54,10 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(got[cname]) == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_block_record_matches_struct():
+    import ctypes
+    assert binding.BLOCK_DTYPE.itemsize == ctypes.sizeof(binding.BlockDesc)
+    for f, _ in binding.BlockDesc._fields_:
+        assert binding.BLOCK_DTYPE.fields[f][1] == getattr(binding.BlockDesc, f).offset

@@ -1,0 +1,156 @@
+"""GPU construction (uhm_kernel_blocks, uhm_aca) against the oracle (oracle/aca.py).
+
+* Kernel blocks: every entry within 1e-13 of the block's largest entry (both sides evaluate
+  the same closed form in FP64; the phase kappa*r carries a few ulps of r).
+* ACA: both sides take every pivot decision in FP64 on |z|^2, so the pivot rows and
+  columns and the ranks must agree exactly.  The factors themselves are compared through
+  each rank-one term u_l v_l^T and their sum: the entries of a late factor are residuals of
+  size |delta_l| (the l-th pivot) carrying rounding noise of size eps_mach |A|, so a factor
+  compared alone agrees only to eps_mach |A| / |delta_l| relative, while each term and the
+  sum agree to a small multiple of eps_mach |A|: 1e-12 of |A|_b|_F here (the oracle
+  run on entries perturbed by 2e-16 relative moves its factors by 2e-10 and its terms by 6e-15).  u v^T stays within
+  20 eps of the block (the approximation itself).  The one branch not reached here is a
+  residual row that vanishes exactly, which this kernel's entries never produce; the
+  oracle's pin covers it on the CPU.
+* The builder with construct="gpu" gives the operator of construct="host": the same ranks
+  and block structure, and the same product to 1e-9.
+"""
+import numpy as np
+import pytest
+
+from conftest import operator, rel
+from oracle import aca as oaca
+from oracle import uniform
+from paper_2405_15573_amd import builder, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    from paper_2405_15573_amd import binding
+    binding.load_library()
+    return torch
+
+
+def _geometry(surface, n, seed, leaf=64):
+    cloud = inputs.make_cloud(surface, n, seed=seed)
+    tree = builder.build_tree(cloud.points, leaf)
+    pts = np.ascontiguousarray(cloud.points[tree.perm])
+    adm, den = builder.build_block_tree(tree, 1.0)
+    return cloud, tree, pts, adm, den
+
+
+def test_kernel_blocks_parity(torch_dev):
+    from paper_2405_15573_amd import binding
+    cloud, tree, pts, adm, den = _geometry("ellipsoid", 3000, 5)
+    diag = 1.0 / (2.0 * cloud.h)
+    ro, rs = tree.off[den[:, 0]], tree.size[den[:, 0]]
+    co, cs = tree.off[den[:, 1]], tree.size[den[:, 1]]
+    # ragged extras: single row, single column, a diagonal-crossing block, the last point
+    extra = np.array([[0, 1, 5, 70], [17, 93, 1000, 1], [100, 130, 90, 111], [cloud.n - 1, 1, 0, cloud.n]])
+    ro = np.concatenate([ro, extra[:, 0]])
+    rs = np.concatenate([rs, extra[:, 1]])
+    co = np.concatenate([co, extra[:, 2]])
+    cs = np.concatenate([cs, extra[:, 3]])
+    print(f"case kernel_blocks: {len(ro)} blocks", flush=True)
+    D, offs = binding.kernel_blocks(pts, cloud.kappa, diag, ro, rs, co, cs)
+    D = D.cpu().numpy()
+    for b in list(range(0, len(ro), 7)) + list(range(len(ro) - 4, len(ro))):
+        m, n = int(rs[b]), int(cs[b])
+        ref = oaca.kernel_block(pts, cloud.kappa, diag, np.arange(ro[b], ro[b] + m), np.arange(co[b], co[b] + n))
+        got = D[offs[b]:offs[b] + m * n].reshape(n, m).T
+        assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref)), b
+        on_diag = (np.arange(ro[b], ro[b] + m)[:, None] == np.arange(co[b], co[b] + n)[None, :])
+        assert np.all(got[on_diag] == diag)
+
+
+def _compare(res, pts, kappa, diag, ro, rs, co, cs, caps, eps, which):
+    checked = 0
+    for b in which:
+        m, n = int(rs[b]), int(cs[b])
+        u, v, pr, pc, conv = oaca.aca_kernel_block(pts, kappa, diag, int(ro[b]), m, int(co[b]), n, eps, int(caps[b]))
+        gu, gv, gpr, gpc = res.factors(b)
+        assert res.rank[b] == u.shape[1], (b, res.rank[b], u.shape[1])
+        assert (res.status[b] > 0) == conv, (b, res.status[b], conv)
+        assert np.array_equal(gpr, pr) and np.array_equal(gpc, pc), b
+        blk = oaca.kernel_block(pts, kappa, diag, np.arange(ro[b], ro[b] + m), np.arange(co[b], co[b] + n))
+        scale = np.linalg.norm(blk)
+        for l in range(u.shape[1]):
+            assert np.linalg.norm(np.outer(gu[:, l], gv[:, l]) - np.outer(u[:, l], v[:, l])) <= 1e-12 * scale, (b, l)
+        assert np.linalg.norm(gu @ gv.T - u @ v.T) <= 1e-12 * scale, b
+        if conv and eps > 0:
+            assert rel(gu @ gv.T, blk) <= 20 * eps, b
+        checked += 1
+    return checked
+
+
+@pytest.mark.parametrize("surface,n,seed", [("ellipsoid", 6000, 3), ("cube", 3000, 1)])
+def test_aca_parity(torch_dev, surface, n, seed):
+    from paper_2405_15573_amd import binding
+    cloud, tree, pts, adm, den = _geometry(surface, n, seed)
+    diag = 1.0 / (2.0 * cloud.h)
+    low = adm[adm[:, 0] < adm[:, 1]]
+    ro, rs = tree.off[low[:, 0]], tree.size[low[:, 0]]
+    co, cs = tree.off[low[:, 1]], tree.size[low[:, 1]]
+    eps = 1e-6
+    caps = np.minimum(np.minimum(rs, cs), 1024)
+    order = np.argsort(-(rs + cs), kind="stable")   # large blocks first, as the builder launches
+    print(f"case aca {surface} n={cloud.n}: {len(ro)} blocks, largest {int(rs.max())}", flush=True)
+    res = binding.aca(pts, cloud.kappa, diag, ro[order], rs[order], co[order], cs[order], caps[order], eps)
+    assert np.all(res.status > 0)
+    big = [b for b in range(len(order)) if rs[order][b] >= 180]
+    which = big + list(range(len(big), len(order), 9))
+    got = _compare(res, pts, cloud.kappa, diag, ro[order], rs[order], co[order], cs[order], caps[order], eps, which)
+    print(f"  {got} blocks match the oracle (pivots, ranks, factors)", flush=True)
+
+
+def test_aca_cap_and_degenerate_shapes(torch_dev):
+    """A rank cap below the block's rank (status 0, same pivots as the oracle), single-row and
+    single-column blocks, eps = 0 (the term limit ends every block), and a block that holds
+    coincident positions (the diagonal value)."""
+    from paper_2405_15573_amd import binding
+    cloud, tree, pts, adm, den = _geometry("sphere", 3000, 2)
+    diag = 1.0 / (2.0 * cloud.h)
+    low = adm[adm[:, 0] < adm[:, 1]][:40]
+    ro = np.concatenate([tree.off[low[:, 0]], [0, 10, 500, 64]])
+    rs = np.concatenate([tree.size[low[:, 0]], [1, 130, 77, 40]])
+    co = np.concatenate([tree.off[low[:, 1]], [900, 2000, 2500, 64]])
+    cs = np.concatenate([tree.size[low[:, 1]], [150, 1, 65, 40]])
+    for eps, cap in ((1e-6, 4), (0.0, 12)):
+        caps = np.minimum(np.minimum(rs, cs), cap)
+        print(f"case aca cap={cap} eps={eps}", flush=True)
+        res = binding.aca(pts, cloud.kappa, diag, ro, rs, co, cs, caps, eps)
+        _compare(res, pts, cloud.kappa, diag, ro, rs, co, cs, caps, eps, range(len(ro)))
+        if eps == 0.0:
+            assert np.all(res.rank == caps)
+
+
+def test_aca_rejects_bad_descriptors(torch_dev):
+    from paper_2405_15573_amd import binding
+    cloud, tree, pts, adm, den = _geometry("sphere", 2048, 0)
+    with pytest.raises(binding.UhmError):
+        binding.aca(pts, cloud.kappa, 1.0, [cloud.n - 5], [10], [0], [10], [4], 1e-6)   # rows past the end
+    with pytest.raises(binding.UhmError):
+        binding.aca(pts, cloud.kappa, 1.0, [0], [10], [100], [10], [2000], 1e-6)        # cap above 1024
+    with pytest.raises(binding.UhmError):
+        binding.aca(pts, cloud.kappa, 1.0, [0], [10], [100], [10], [4], -1.0)           # eps < 0
+    with pytest.raises(binding.UhmError):
+        binding.kernel_blocks(pts, cloud.kappa, 1.0, [0], [10], [cloud.n], [1])         # column past the end
+
+
+@pytest.mark.parametrize("surface,n,seed,leaf", [("sphere", 2048, 0, 32), ("ellipsoid", 4000, 4, 64)])
+def test_builder_gpu_construction(torch_dev, surface, n, seed, leaf):
+    cloud = inputs.make_cloud(surface, n, seed=seed)
+    print(f"case builder construct=gpu {surface} n={cloud.n} leaf={leaf}", flush=True)
+    h = builder.build_operator(cloud, leaf=leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="host")
+    g = builder.build_operator(cloud, leaf=leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="gpu")
+    assert np.array_equal(h.adm_rank, g.adm_rank)
+    assert np.array_equal(h.rank_row, g.rank_row)
+    assert np.max(np.abs(g.D - h.D)) <= 1e-13 * np.max(np.abs(h.D))
+    x = inputs.make_rhs(cloud.n, 2, seed=seed + 1)
+    assert rel(uniform.uh_mvp(vars(g), x), uniform.uh_mvp(vars(h), x)) <= 1e-9
+    assert rel(uniform.h_mvp(vars(g), x), uniform.h_mvp(vars(h), x)) <= 1e-9
