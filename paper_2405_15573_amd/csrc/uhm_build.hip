@@ -8,14 +8,16 @@
 // k_kernel_blocks: one workgroup per dense block; consecutive lanes write consecutive
 // entries of a column (coalesced column-major stores).
 //
-// k_aca: one wavefront per block, barrier-light (the workgroup is that one wavefront).
-// Lane l owns rows l, l+64, ... and columns l, l+64, ... of its block: it evaluates those
-// entries, keeps their residual updates, writes them into u_k and v_k, and later reads back
-// only what it wrote itself.  The only values that cross lanes go through LDS or wave
-// reductions: the pivot row's entries u_l[i_k] and the pivot column's entries v_l[j_k]
-// (gathered by their owning lane into LDS), the used-row flags (a bitmask in LDS), and
-// the argmax and norm reductions (xor butterflies, so every lane holds bit-identical
-// results and takes the same branch).
+// k_aca: one workgroup of W wavefronts per block, W = 1..16 chosen per launch from the
+// largest block (about 8 rows per thread).  Thread t owns rows t, t+64W, ... and columns
+// t, t+64W, ... of its block: it evaluates those entries, keeps their residual updates,
+// writes them into u_k and v_k, and later reads back only what it wrote itself.  The only
+// values that cross threads go through LDS or reductions: the pivot row's entries u_l[i_k]
+// and the pivot column's entries v_l[j_k] (gathered by their owning thread into LDS), the
+// used-row flags (a bitmask in LDS), and the argmax and norm reductions (xor butterflies
+// within a wavefront, then the W wavefront results combined in order, so every thread
+// holds bit-identical results and takes the same branch).  Entries and factors do not
+// depend on W; only the summation order of the norms in the stopping test does.
 #include "uhm_internal.h"
 
 #include <climits>
@@ -86,14 +88,56 @@ __global__ __launch_bounds__(kDenseThreads) void k_kernel_blocks(
   }
 }
 
-__global__ __launch_bounds__(64) void k_aca(const double* __restrict__ pts, int64_t npts, double kappa, double diag,
-                                            const uhm_block_desc* __restrict__ blocks, int32_t max_rows,
-                                            int32_t max_cap, double eps, double2* U, int64_t U_len, double2* V,
-                                            int64_t V_len, int32_t* piv, int64_t piv_len, int32_t* __restrict__ rank_out,
-                                            int32_t* __restrict__ status_out) {
+// Combines one value per wavefront, in wavefront order, so that every thread of the block
+// holds the same result.  `slot` has W entries; a barrier separates the writes from the reads.
+template <int W>
+__device__ __forceinline__ double block_sum(double x, double* slot) {
+  x = wave_sum(x);
+  if (W == 1) return x;
+  if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = x;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll 1
+  for (int w = 0; w < W; ++w) s += slot[w];
+  return s;
+}
+
+template <int W>
+__device__ __forceinline__ Pick block_argmax(Pick a, Pick* slot) {
+  a = wave_argmax(a);
+  if (W == 1) return a;
+  if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = a;
+  __syncthreads();
+  Pick r = slot[0];
+#pragma unroll 1
+  for (int w = 1; w < W; ++w) {
+    const Pick b = slot[w];
+    if (b.mag > r.mag || (b.mag == r.mag && b.idx < r.idx)) r = b;
+  }
+  return r;
+}
+
+constexpr int kCrossGroup = 4;  // norm cross terms reduced 4 at a time
+
+// W wavefronts per block (64 W threads).  Thread t owns rows t, t + 64W, ... and columns
+// t, t + 64W, ... of its block; every value it reads back from U or V it wrote itself.
+// Everything that decides a branch (pivots, norms, the stopping test) is combined in a fixed
+// order and is bit-identical in all threads, so all threads take every branch together.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_aca(const double* __restrict__ pts, int64_t npts, double kappa,
+                                                double diag, const uhm_block_desc* __restrict__ blocks,
+                                                int32_t max_rows, int32_t max_cap, double eps, double2* U,
+                                                int64_t U_len, double2* V, int64_t V_len, int32_t* piv,
+                                                int64_t piv_len, int32_t* __restrict__ rank_out,
+                                                int32_t* __restrict__ status_out) {
+  constexpr int T = 64 * W;
   extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ Pick red_row[W], red_col[W];
+  __shared__ double red_nv[W], red_nu[W];
+  __shared__ int red_free[W];
+  __shared__ double red_cross[2][W][4 * kCrossGroup];
   const int64_t b = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
   const uhm_block_desc B = blocks[b];
   const int m = B.rows, n = B.cols, cap = B.cap;
   const bool ok = m >= 1 && n >= 1 && cap >= 1 && m <= max_rows && cap <= max_cap && B.row_off >= 0 &&
@@ -101,7 +145,7 @@ __global__ __launch_bounds__(64) void k_aca(const double* __restrict__ pts, int6
                   B.a_off + (int64_t)m * cap <= U_len && B.b_off >= 0 && B.b_off + (int64_t)n * cap <= V_len &&
                   B.p_off >= 0 && B.p_off + 2 * (int64_t)cap <= piv_len;
   if (!ok) {
-    if (lane == 0) {
+    if (tid == 0) {
       rank_out[b] = 0;
       status_out[b] = -1;
     }
@@ -111,7 +155,7 @@ __global__ __launch_bounds__(64) void k_aca(const double* __restrict__ pts, int6
   double2* vj = ui + max_cap;                     // v_l[j_k], l < k
   uint32_t* used = reinterpret_cast<uint32_t*>(vj + max_cap);
   const int nwords = (m + 31) >> 5;
-  for (int w = lane; w < nwords; w += 64) used[w] = 0u;
+  for (int w = tid; w < nwords; w += T) used[w] = 0u;
 
   double2* u = U + B.a_off;
   double2* v = V + B.b_off;
@@ -126,15 +170,15 @@ __global__ __launch_bounds__(64) void k_aca(const double* __restrict__ pts, int6
   __syncthreads();
 
   while (k < kmax) {
-    // u_l[i] for l < k, gathered by the lane that wrote row i
-    if (lane == (i & 63))
+    // u_l[i] for l < k, gathered by the thread that wrote row i
+    if (tid == i % T)
       for (int l = 0; l < k; ++l) ui[l] = u[(size_t)l * m + i];
     __syncthreads();
     // residual row i (unscaled) into v column k, and its largest entry
     const double* pi = P + 3 * (int64_t)i;
     double2* vk = v + (size_t)k * n;
     Pick best{-1.0, INT_MAX, 0.0, 0.0};
-    for (int j = lane; j < n; j += 64) {
+    for (int j = tid; j < n; j += T) {
       double2 a = kernel_entry(pi, Q + 3 * (int64_t)j, (int64_t)i == (int64_t)j + shift, kappa, diag);
       for (int l = 0; l < k; ++l) {
         const double2 w = ui[l];
@@ -146,13 +190,13 @@ __global__ __launch_bounds__(64) void k_aca(const double* __restrict__ pts, int6
       const double mg = a.x * a.x + a.y * a.y;
       if (mg > best.mag) best = Pick{mg, j, a.x, a.y};
     }
-    best = wave_argmax(best);
-    if (lane == 0) used[i >> 5] |= 1u << (i & 31);
-    __syncthreads();
+    if (tid == 0) used[i >> 5] |= 1u << (i & 31);
+    best = block_argmax<W>(best, red_row);
+    __syncthreads();  // the used flag of row i
     if (!(best.mag > 0.0)) {
       // the residual row vanishes: retry with the unused row of smallest index
       int nx = INT_MAX;
-      for (int w = lane; w < nwords; w += 64) {
+      for (int w = tid; w < nwords; w += T) {
         const uint32_t freebits = ~used[w] & (w == nwords - 1 && (m & 31) ? ((1u << (m & 31)) - 1u) : 0xffffffffu);
         if (freebits) {
           nx = (w << 5) + __builtin_ctz(freebits);
@@ -161,6 +205,12 @@ __global__ __launch_bounds__(64) void k_aca(const double* __restrict__ pts, int6
       }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) nx = min(nx, __shfl_xor(nx, o, 64));
+      if (W > 1) {
+        if ((tid & 63) == 0) red_free[tid >> 6] = nx;
+        __syncthreads();
+        for (int w = 0; w < W; ++w) nx = min(nx, red_free[w]);
+        __syncthreads();
+      }
       if (nx == INT_MAX) {
         status = 2;
         break;
@@ -172,23 +222,23 @@ __global__ __launch_bounds__(64) void k_aca(const double* __restrict__ pts, int6
     const double dd = best.re * best.re + best.im * best.im;
     const double ir = best.re / dd, ii = -best.im / dd;  // 1 / r[j_k]
     double nv = 0.0;
-    for (int j = lane; j < n; j += 64) {
+    for (int j = tid; j < n; j += T) {
       const double2 a = vk[j];
       const double2 z = make_double2(a.x * ir - a.y * ii, a.x * ii + a.y * ir);
       vk[j] = z;
       nv += z.x * z.x + z.y * z.y;
     }
-    nv = wave_sum(nv);
-    // v_l[j_k] for l < k, gathered by the lane that wrote column j_k
-    if (lane == (jp & 63))
+    // v_l[j_k] for l < k, gathered by the thread that wrote column j_k
+    if (tid == jp % T)
       for (int l = 0; l < k; ++l) vj[l] = v[(size_t)l * n + jp];
-    __syncthreads();
+    nv = block_sum<W>(nv, red_nv);
+    __syncthreads();  // vj
     // residual column j_k into u column k; |u_k|^2; next pivot among the unused rows
     const double* qj = Q + 3 * (int64_t)jp;
     double2* uk = u + (size_t)k * m;
     double nu = 0.0;
     Pick nxt{-1.0, INT_MAX, 0.0, 0.0};
-    for (int t = lane; t < m; t += 64) {
+    for (int t = tid; t < m; t += T) {
       double2 a = kernel_entry(P + 3 * (int64_t)t, qj, (int64_t)t == (int64_t)jp + shift, kappa, diag);
       for (int l = 0; l < k; ++l) {
         const double2 w = vj[l];
@@ -201,32 +251,61 @@ __global__ __launch_bounds__(64) void k_aca(const double* __restrict__ pts, int6
       nu += mg;
       if (!((used[t >> 5] >> (t & 31)) & 1u) && mg > nxt.mag) nxt = Pick{mg, t, 0.0, 0.0};
     }
-    nu = wave_sum(nu);
-    nxt = wave_argmax(nxt);
-    // |S_k|^2 = |S_{k-1}|^2 + 2 Re sum_{l<k} (u_l^* u_k)(v_l^* v_k) + |u_k|^2 |v_k|^2
+    nu = block_sum<W>(nu, red_nu);
+    nxt = block_argmax<W>(nxt, red_col);
+    // |S_k|^2 = |S_{k-1}|^2 + 2 Re sum_{l<k} (u_l^* u_k)(v_l^* v_k) + |u_k|^2 |v_k|^2,
+    // the inner products taken kCrossGroup at a time
     double cross = 0.0;
-    for (int l = 0; l < k; ++l) {
-      double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-      const double2* ul = u + (size_t)l * m;
-      const double2* vl = v + (size_t)l * n;
-      for (int t = lane; t < m; t += 64) {
-        const double2 x = ul[t], y = uk[t];
-        ar += x.x * y.x + x.y * y.y;
-        ai += x.x * y.y - x.y * y.x;
+    for (int l0 = 0, g = 0; l0 < k; l0 += kCrossGroup, ++g) {
+      const int cnt = min(kCrossGroup, k - l0);
+      double acc[4 * kCrossGroup];
+#pragma unroll
+      for (int q = 0; q < 4 * kCrossGroup; ++q) acc[q] = 0.0;
+      for (int t = tid; t < m; t += T) {
+        const double2 y = uk[t];
+#pragma unroll
+        for (int q = 0; q < kCrossGroup; ++q) {
+          if (q < cnt) {
+            const double2 x = u[(size_t)(l0 + q) * m + t];
+            acc[4 * q] += x.x * y.x + x.y * y.y;
+            acc[4 * q + 1] += x.x * y.y - x.y * y.x;
+          }
+        }
       }
-      for (int j = lane; j < n; j += 64) {
-        const double2 x = vl[j], y = vk[j];
-        br += x.x * y.x + x.y * y.y;
-        bi += x.x * y.y - x.y * y.x;
+      for (int j = tid; j < n; j += T) {
+        const double2 y = vk[j];
+#pragma unroll
+        for (int q = 0; q < kCrossGroup; ++q) {
+          if (q < cnt) {
+            const double2 x = v[(size_t)(l0 + q) * n + j];
+            acc[4 * q + 2] += x.x * y.x + x.y * y.y;
+            acc[4 * q + 3] += x.x * y.y - x.y * y.x;
+          }
+        }
       }
-      ar = wave_sum(ar);
-      ai = wave_sum(ai);
-      br = wave_sum(br);
-      bi = wave_sum(bi);
-      cross += ar * br - ai * bi;
+#pragma unroll
+      for (int q = 0; q < 4 * kCrossGroup; ++q) acc[q] = wave_sum(acc[q]);
+      if (W > 1) {
+        double* slot = red_cross[g & 1][0];
+        if ((tid & 63) == 0) {
+#pragma unroll
+          for (int q = 0; q < 4 * kCrossGroup; ++q) slot[(tid >> 6) * 4 * kCrossGroup + q] = acc[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4 * kCrossGroup; ++q) {
+          double s = 0.0;
+#pragma unroll 1
+          for (int w = 0; w < W; ++w) s += slot[w * 4 * kCrossGroup + q];
+          acc[q] = s;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kCrossGroup; ++q)
+        if (q < cnt) cross += acc[4 * q] * acc[4 * q + 2] - acc[4 * q + 1] * acc[4 * q + 3];
     }
     norm2 += 2.0 * cross + nu * nv;
-    if (lane == 0) {
+    if (tid == 0) {
       prow[k] = i;
       pcol[k] = jp;
     }
@@ -242,10 +321,18 @@ __global__ __launch_bounds__(64) void k_aca(const double* __restrict__ pts, int6
     i = nxt.idx;
   }
   if (status == -2) status = (kmax == min(m, n)) ? 2 : 0;
-  if (lane == 0) {
+  if (tid == 0) {
     rank_out[b] = k;
     status_out[b] = status;
   }
+}
+
+// Wavefronts per block for a launch: enough that each thread holds about 8 of the largest
+// block's rows, between 1 and 16.
+int aca_waves(int32_t max_rows) {
+  int w = 1;
+  while (w < 16 && 512 * w < max_rows) w *= 2;
+  return w;
 }
 
 }  // namespace
@@ -283,9 +370,24 @@ int uhm_aca(const double* points, int64_t npoints, double kappa, double diag, co
   if (nblocks > INT32_MAX) return fail(UHM_EINVAL, "uhm_aca: too many blocks for one launch");
   const size_t lds = 2 * sizeof(double2) * (size_t)max_cap + 4 * (size_t)((max_rows + 31) / 32);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  k_aca<<<dim3((unsigned)nblocks), dim3(64), lds, s>>>(points, npoints, kappa, diag, blocks, max_rows, max_cap, eps,
-                                                       reinterpret_cast<double2*>(U), U_len,
-                                                       reinterpret_cast<double2*>(V), V_len, piv, piv_len, rank, status);
+  const dim3 grid((unsigned)nblocks);
+  double2* Uc = reinterpret_cast<double2*>(U);
+  double2* Vc = reinterpret_cast<double2*>(V);
+  switch (aca_waves(max_rows)) {
+#define UHM_ACA_LAUNCH(WV)                                                                                     \
+  case WV:                                                                                                     \
+    k_aca<WV><<<grid, dim3(64 * WV), lds, s>>>(points, npoints, kappa, diag, blocks, max_rows, max_cap, eps, Uc, \
+                                               U_len, Vc, V_len, piv, piv_len, rank, status);                 \
+    break;
+    UHM_ACA_LAUNCH(1)
+    UHM_ACA_LAUNCH(2)
+    UHM_ACA_LAUNCH(4)
+    UHM_ACA_LAUNCH(8)
+    UHM_ACA_LAUNCH(16)
+#undef UHM_ACA_LAUNCH
+    default:
+      return fail(UHM_EINVAL, "uhm_aca: internal wave count");
+  }
   UHM_HIP(hipGetLastError());
   return UHM_OK;
 }

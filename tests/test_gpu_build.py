@@ -129,6 +129,27 @@ def test_aca_cap_and_degenerate_shapes(torch_dev):
             assert np.all(res.rank == caps)
 
 
+@pytest.mark.parametrize("m,n,waves", [(2100, 1500, 8), (4200, 700, 16), (1500, 2100, 4)])
+def test_aca_wide_workgroups(torch_dev, m, n, waves):
+    """Blocks large enough that one launch uses 4, 8 or 16 wavefronts per block (the count
+    follows the largest row count): two separated random boxes."""
+    from paper_2405_15573_amd import binding
+    rng = np.random.default_rng(m + n)
+    pts = np.concatenate([rng.uniform(-0.5, 0.5, size=(m, 3)) * [1.0, 0.6, 0.3],
+                          rng.uniform(-0.5, 0.5, size=(n, 3)) * [0.4, 1.0, 0.7] + [2.2, 0.3, -0.1]])
+    kappa, diag = 12.0, 3.0
+    w = 1
+    while w < 16 and 512 * w < m:
+        w *= 2
+    assert w == waves
+    print(f"case aca {m}x{n}, {waves} wavefronts per block", flush=True)
+    ro, rs, co, cs = np.array([0]), np.array([m]), np.array([m]), np.array([n])
+    res = binding.aca(pts, kappa, diag, ro, rs, co, cs, [min(m, n, 256)], 1e-6)
+    assert res.status[0] == 1
+    _compare(res, pts, kappa, diag, ro, rs, co, cs, [min(m, n, 256)], 1e-6, [0])
+    print(f"  rank {res.rank[0]}", flush=True)
+
+
 def test_aca_rejects_bad_descriptors(torch_dev):
     from paper_2405_15573_amd import binding
     cloud, tree, pts, adm, den = _geometry("sphere", 2048, 0)
