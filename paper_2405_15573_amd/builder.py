@@ -281,6 +281,88 @@ def _pmap(fn, items):
             ctx.__exit__(None, None, None)
 
 
+def _pack_factors(res, pos, rel, m, n):
+    """Factors of the blocks pos[rel] of one shape group of an ACA result (blocks pos are
+    contiguous, all m x n with one cap c): X (cnt, m, kp) = u and Y (cnt, n, kp) = conj(v),
+    zero beyond each block's rank, kp the group's largest rank.  Packed where the result
+    lives (the device) and copied to the host once."""
+    import torch
+    c = int(res.cap[pos[0]])
+    a0, b0 = int(res.u_off[pos[0]]), int(res.v_off[pos[0]])
+    rank = res.rank[pos[rel]]
+    kp = int(rank.max())
+    dev = res.U.device
+    sel = torch.from_numpy(np.ascontiguousarray(rel, dtype=np.int64)).to(dev)
+    Ud = res.U[a0:a0 + len(pos) * c * m].view(len(pos), c, m).index_select(0, sel)[:, :kp, :]
+    Vd = res.V[b0:b0 + len(pos) * c * n].view(len(pos), c, n).index_select(0, sel)[:, :kp, :]
+    live = (torch.arange(kp, device=dev)[None, :] < torch.from_numpy(rank.astype(np.int64)).to(dev)[:, None])[:, :, None]
+    zero = torch.zeros((), dtype=Ud.dtype, device=dev)
+    X = torch.where(live, Ud, zero).transpose(1, 2).contiguous().cpu().numpy()
+    Y = torch.conj_physical(torch.where(live, Vd, zero)).transpose(1, 2).contiguous().cpu().numpy()
+    return X, Y
+
+
+def _compress_gpu(Xb, ks, eps_comp, device="cuda"):
+    """Alg. 2's per-cluster step for a batch of row clusters of one size, with the large
+    products as batched GEMMs on the GPU and only small Hermitian eigenproblems on the host.
+
+    Xb (cnt, n, kp): the agglomerations X_tau = [U_b Sigma_b] (zero-padded columns); ks: the
+    true column counts.  The leading left singular subspace of X_tau comes from the
+    eigenvectors of the smaller Gram matrix: X X^* (n <= kp) gives it directly; otherwise
+    X^* X = W Lambda W^* gives Y = X W_l Lambda_l^{-1/2}, made orthonormal by one Cholesky
+    QR step.  The rank is l = #{sigma_i > eps sigma_1}, at most ks, with sigma_i^2 the
+    eigenvalues.  The coefficients are the projection L = Q^* X, and sigma_{l+1} and
+    sqrt(sum_{i>l} sigma_i^2) are taken from the residual X - Q L (its largest singular
+    value and its Frobenius norm).  Returns per cluster (l, Q (n x l), sigma_{l+1}, tail,
+    L (l x kp)).  `device` is where the products run (a torch device name)."""
+    import torch
+    cnt, n, kp = Xb.shape
+    Xd = torch.from_numpy(Xb).to(device)
+    XdH = Xd.transpose(1, 2).conj().contiguous()
+    ks = np.asarray(ks)
+
+    def ranks(lam):
+        sg = np.sqrt(np.maximum(lam[:, ::-1], 0.0))
+        ls = np.array([max(1, int(np.count_nonzero(sg[c] > eps_comp * sg[c, 0]))) if sg[c, 0] > 0 else 1
+                       for c in range(cnt)])
+        return np.minimum(ls, ks)
+
+    if n <= kp:
+        lam, W = np.linalg.eigh(torch.bmm(Xd, XdH).cpu().numpy())
+        ls = ranks(lam)
+        lmax = int(ls.max())
+        Q = np.ascontiguousarray(W[:, :, ::-1][:, :, :lmax] * (np.arange(lmax)[None, None, :] < ls[:, None, None]))
+        Qd = torch.from_numpy(Q).to(device)
+    else:
+        lam, W = np.linalg.eigh(torch.bmm(XdH, Xd).cpu().numpy())
+        ls = ranks(lam)
+        lmax = int(ls.max())
+        sg = np.sqrt(np.maximum(lam[:, ::-1][:, :lmax], 0.0))
+        live = np.arange(lmax)[None, :] < ls[:, None]
+        scale = np.where(live, 1.0 / np.where(live, sg, 1.0), 0.0)
+        Wl = np.ascontiguousarray(W[:, :, ::-1][:, :, :lmax] * scale[:, None, :])
+        Yd = torch.bmm(Xd, torch.from_numpy(Wl).to(device))
+        C = torch.bmm(Yd.transpose(1, 2).conj().contiguous(), Yd).cpu().numpy()
+        C[:, np.arange(lmax), np.arange(lmax)] = np.where(live, C[:, np.arange(lmax), np.arange(lmax)], 1.0)
+        Rinv = np.linalg.inv(np.conj(np.swapaxes(np.linalg.cholesky(C), 1, 2)))   # C = R^* R, R upper
+        Rinv = np.ascontiguousarray(Rinv * (live[:, :, None] & live[:, None, :]))
+        Qd = torch.bmm(Yd, torch.from_numpy(Rinv).to(device))
+        del Yd
+    Ld = torch.bmm(Qd.transpose(1, 2).conj().contiguous(), Xd)
+    Rd = Xd - torch.bmm(Qd, Ld)
+    del Xd, XdH
+    small = Rd.transpose(1, 2).conj().contiguous()
+    Gr = (torch.bmm(Rd, small) if n <= kp else torch.bmm(small, Rd)).cpu().numpy()
+    del Rd, small
+    lr = np.linalg.eigvalsh(Gr)
+    dropped = np.sqrt(np.maximum(lr[:, -1], 0.0))
+    tail = np.sqrt(np.maximum(np.trace(Gr, axis1=1, axis2=2).real, 0.0))
+    Q = Qd.cpu().numpy()
+    L = Ld.cpu().numpy()
+    return [(int(ls[c]), np.ascontiguousarray(Q[c][:, :ls[c]]), float(dropped[c]), float(tail[c]),
+             L[c][:ls[c], :]) for c in range(cnt)]
+
+
 def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_cap=128):
     """ACA of one level's blocks on the GPU (uhm_aca).  Blocks whose first pass stopped at
     its rank capacity run again with a four times larger one, up to kcap.  Returns the ranks
@@ -306,18 +388,10 @@ def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_
         shapes = np.stack([rsz[idx], csz[idx]], 1)
         for (m, n) in np.unique(shapes, axis=0):
             pos = np.nonzero((shapes[:, 0] == m) & (shapes[:, 1] == n))[0]   # contiguous in idx
-            c = int(caps[pos[0]])
             keep = pos[final[pos]]
             if keep.size == 0:
                 continue
-            kp = int(res.rank[keep].max())
-            a0, b0 = int(res.u_off[pos[0]]), int(res.v_off[pos[0]])
-            rel = keep - pos[0]
-            Ug = res.U[a0:a0 + pos.size * c * m].view(pos.size, c, m)[rel][:, :kp, :].cpu().numpy()
-            Vg = res.V[b0:b0 + pos.size * c * n].view(pos.size, c, n)[rel][:, :kp, :].cpu().numpy()
-            live = (np.arange(kp)[None, :] < res.rank[keep][:, None])[:, :, None]
-            X = np.ascontiguousarray(np.where(live, Ug, 0.0).transpose(0, 2, 1))
-            Y = np.ascontiguousarray(np.conj(np.where(live, Vg, 0.0)).transpose(0, 2, 1))
+            X, Y = _pack_factors(res, pos, keep - pos[0], int(m), int(n))
             groups.append((idx[keep], int(m), int(n), X, Y))
         todo = idx[~final]
         cap_now *= 4
@@ -327,16 +401,18 @@ def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_
 
 def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca: float = 1e-6,
                    eps_comp: float = 1e-6, eps_rec: float | None = None, kcap: int = 1024,
-                   verbose: bool = False, construct: str = "host") -> HostOperator:
+                   verbose: bool = False, construct: str = "host", compress_on: str = "host",
+                   compress_device: str = "cuda") -> HostOperator:
     """Build the H form and the UH form of the point-kernel matrix A_ij = g(x_i, x_j),
     A_ii = 1/(2h), for one seeded cloud.
 
     construct="gpu" samples the matrix on the GPU: ACA of the admissible blocks
     (uhm_aca) and the dense near-field blocks (uhm_kernel_blocks); the recompression and
     the uniform compression stay on the host.  construct="host" does everything on the
-    host (OpenMP C++ and LAPACK)."""
-    if construct not in ("host", "gpu"):
-        raise ValueError("construct must be 'host' or 'gpu'")
+    host (OpenMP C++ and LAPACK).  compress_on="gpu" runs the large products of the uniform
+    compression (Alg. 2) as batched GEMMs on the GPU (_compress_gpu)."""
+    if construct not in ("host", "gpu") or compress_on not in ("host", "gpu"):
+        raise ValueError("construct and compress_on must be 'host' or 'gpu'")
     lib = _native()
     if eps_rec is None:
         eps_rec = eps_aca / 10.0
@@ -464,7 +540,7 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
     for t in clusters:
         ks = sum(fac_s[(min(t, s), max(t, s))].size for s in row_blocks[t])
         groups.setdefault((int(size[t])), []).append((int(t), ks))
-    def compress(part):
+    def agglomerate(part):
         nt = int(size[part[0][0]])
         kp = max(k for _, k in part)
         Xb = np.zeros((len(part), nt, kp), np.complex128)
@@ -479,6 +555,10 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
                 cl.append((s, j, kb))
                 j += kb
             cols.append(cl)
+        return Xb, cols
+
+    def compress(part):
+        Xb, cols = agglomerate(part)
         Uh, sh, Vh = np.linalg.svd(Xb, full_matrices=False)
         del Xb
         out = []
@@ -492,11 +572,24 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
                         [(s, np.ascontiguousarray(SV[:, j:j + kb])) for s, j, kb in cols[c]]))
         return out
 
+    def compress_gpu(part):
+        Xb, cols = agglomerate(part)
+        out = []
+        for c, (l, Ut, dropped, tail, SV) in enumerate(_compress_gpu(Xb, [k for _, k in part], eps_comp,
+                                                                     compress_device)):
+            out.append((part[c][0], l, Ut, dropped, tail,
+                        [(s, np.ascontiguousarray(SV[:, j:j + kb])) for s, j, kb in cols[c]]))
+        return [out]
+
     jobs = []
     for nt, members in groups.items():
         kp_all = max(k for _, k in members)
-        jobs.extend(_chunks(members, 16 * nt * kp_all * 3, parts=2 * _workers()))
-    for res in _pmap(compress, jobs):
+        if compress_on == "gpu":
+            jobs.extend(_chunks(members, 16 * nt * kp_all * 4, budget=1 << 32))
+        else:
+            jobs.extend(_chunks(members, 16 * nt * kp_all * 3, parts=2 * _workers()))
+    results = [r for job in jobs for r in compress_gpu(job)] if compress_on == "gpu" else _pmap(compress, jobs)
+    for res in results:
         for t, l, Ut, dropped, tail, Ls in res:
             rank[t] = l
             Ubasis[t] = Ut

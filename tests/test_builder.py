@@ -129,3 +129,32 @@ def test_save_load_roundtrip(tmp_path, small_op):
     op2 = builder.load_operator(p)
     assert op2.n == op.n and op2.kappa == op.kappa
     assert np.array_equal(op2.S, op.S) and np.array_equal(op2.perm, op.perm)
+
+
+def test_pack_factors_layout():
+    """The packing of GPU ACA output for the recompression (builder._pack_factors), on CPU
+    tensors: X[c] = u (m x kp), Y[c] = conj(v) (n x kp), zero beyond each block's rank, for
+    the selected blocks of a contiguous shape group, whatever the unused columns hold."""
+    import torch
+    from types import SimpleNamespace
+    from paper_2405_15573_amd import builder
+    rng = np.random.default_rng(3)
+    nb, m, n, c = 5, 7, 4, 3
+    ranks = np.array([2, 3, 1, 3, 2])
+    U = rng.normal(size=(nb, c, m)) + 1j * rng.normal(size=(nb, c, m))   # column l of block b at [b, l]
+    V = rng.normal(size=(nb, c, n)) + 1j * rng.normal(size=(nb, c, n))
+    Uf = np.concatenate([np.full(5, 9.0 + 9j), U.ravel()])
+    Vf = np.concatenate([np.full(5, 9.0 + 9j), V.ravel()])
+    res = SimpleNamespace(U=torch.from_numpy(Uf), V=torch.from_numpy(Vf), rank=np.concatenate([[1], ranks]),
+                          cap=np.full(nb + 1, c), u_off=np.concatenate([[0], 5 + np.arange(nb) * c * m]),
+                          v_off=np.concatenate([[0], 5 + np.arange(nb) * c * n]))
+    pos = np.arange(1, nb + 1)
+    rel = np.array([0, 1, 3, 4])
+    X, Y = builder._pack_factors(res, pos, rel, m, n)
+    kp = 3
+    assert X.shape == (4, m, kp) and Y.shape == (4, n, kp)
+    for q, r in enumerate(rel):
+        k = ranks[r]
+        assert np.array_equal(X[q, :, :k], U[r, :k, :].T)
+        assert np.array_equal(Y[q, :, :k], np.conj(V[r, :k, :]).T)
+        assert np.all(X[q, :, k:] == 0) and np.all(Y[q, :, k:] == 0)
