@@ -490,6 +490,9 @@ def main():
                          "current kernel source)")
     ap.add_argument("--construct", choices=("gpu", "host"), default="gpu",
                     help="headline: sample the operator's blocks (ACA, near field) on the GPU or on the host")
+    ap.add_argument("--compress", choices=("gpu", "host"), default="host",
+                    help="headline: the uniform compression on the host (LAPACK SVDs) or with its large products "
+                         "on the GPU (Gram-matrix form)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (the calibration kernel for the byte counters)")
     args = ap.parse_args()
@@ -532,7 +535,7 @@ def main():
     cloud = inputs.make_cloud("sphere", args.n, seed=args.seed)
     log(f"building operator N={cloud.n} kappa={cloud.kappa:.3f} h={cloud.h:.5f}")
     op = builder.build_operator(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, verbose=True,
-                                construct=args.construct)
+                                construct=args.construct, compress_on=args.compress)
     st = op.stats()
     log(f"built in {time.perf_counter() - t0:.1f} s: {json.dumps(op.timings)}")
     log(json.dumps(st))
@@ -742,7 +745,7 @@ def main():
         "uh_symmetric_speedup_over_h": (res_h["ms_per_mvp"] / (t_sy * 1e3)) if (res_h and sym) else None,
         "parity_sampled_rel_err": par_hd,
         "operator": {k: st[k] for k in ("nadm", "nden", "c_sp", "l_max", "k_max", "bytes_uh_c128", "bytes_h_c128")},
-        "build": {"construct": args.construct, **{k: round(v, 3) for k, v in op.timings.items()}},
+        "build": {"construct": args.construct, "compress": args.compress, **{k: round(v, 3) for k, v in op.timings.items()}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "hbm_context": ctx,

@@ -281,6 +281,35 @@ def _pmap(fn, items):
             ctx.__exit__(None, None, None)
 
 
+def _to_host(t):
+    """A device tensor copied to the host through page-locked memory (a DMA at the bus rate
+    rather than a staged copy through pageable memory); the numpy array views that memory."""
+    import torch
+    if t.device.type == "cpu":
+        return t.numpy()
+    h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+    h.copy_(t)
+    return h.numpy()
+
+
+def _host_buffer(shape, dtype, pinned):
+    """A zeroed host array, page-locked when it is to be copied to the device."""
+    if not pinned:
+        return np.zeros(shape, dtype)
+    import torch
+    tdt = {np.dtype(np.complex128): torch.complex128, np.dtype(np.float64): torch.float64}[np.dtype(dtype)]
+    return torch.zeros(shape, dtype=tdt, pin_memory=True).numpy()
+
+
+def _eigh(G):
+    """np.linalg.eigh over a batch, split across the builder's threads."""
+    nw = min(_workers(), G.shape[0])
+    if nw <= 1:
+        return np.linalg.eigh(G)
+    parts = _pmap(np.linalg.eigh, np.array_split(G, nw))
+    return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
+
+
 def _pack_factors(res, pos, rel, m, n):
     """Factors of the blocks pos[rel] of one shape group of an ACA result (blocks pos are
     contiguous, all m x n with one cap c): X (cnt, m, kp) = u and Y (cnt, n, kp) = conj(v),
@@ -297,8 +326,8 @@ def _pack_factors(res, pos, rel, m, n):
     Vd = res.V[b0:b0 + len(pos) * c * n].view(len(pos), c, n).index_select(0, sel)[:, :kp, :]
     live = (torch.arange(kp, device=dev)[None, :] < torch.from_numpy(rank.astype(np.int64)).to(dev)[:, None])[:, :, None]
     zero = torch.zeros((), dtype=Ud.dtype, device=dev)
-    X = torch.where(live, Ud, zero).transpose(1, 2).contiguous().cpu().numpy()
-    Y = torch.conj_physical(torch.where(live, Vd, zero)).transpose(1, 2).contiguous().cpu().numpy()
+    X = _to_host(torch.where(live, Ud, zero).transpose(1, 2).contiguous())
+    Y = _to_host(torch.conj_physical(torch.where(live, Vd, zero)).transpose(1, 2).contiguous())
     return X, Y
 
 
@@ -328,13 +357,13 @@ def _compress_gpu(Xb, ks, eps_comp, device="cuda"):
         return np.minimum(ls, ks)
 
     if n <= kp:
-        lam, W = np.linalg.eigh(torch.bmm(Xd, XdH).cpu().numpy())
+        lam, W = _eigh(_to_host(torch.bmm(Xd, XdH)))
         ls = ranks(lam)
         lmax = int(ls.max())
         Q = np.ascontiguousarray(W[:, :, ::-1][:, :, :lmax] * (np.arange(lmax)[None, None, :] < ls[:, None, None]))
         Qd = torch.from_numpy(Q).to(device)
     else:
-        lam, W = np.linalg.eigh(torch.bmm(XdH, Xd).cpu().numpy())
+        lam, W = _eigh(_to_host(torch.bmm(XdH, Xd)))
         ls = ranks(lam)
         lmax = int(ls.max())
         sg = np.sqrt(np.maximum(lam[:, ::-1][:, :lmax], 0.0))
@@ -342,7 +371,7 @@ def _compress_gpu(Xb, ks, eps_comp, device="cuda"):
         scale = np.where(live, 1.0 / np.where(live, sg, 1.0), 0.0)
         Wl = np.ascontiguousarray(W[:, :, ::-1][:, :, :lmax] * scale[:, None, :])
         Yd = torch.bmm(Xd, torch.from_numpy(Wl).to(device))
-        C = torch.bmm(Yd.transpose(1, 2).conj().contiguous(), Yd).cpu().numpy()
+        C = _to_host(torch.bmm(Yd.transpose(1, 2).conj().contiguous(), Yd)).copy()
         C[:, np.arange(lmax), np.arange(lmax)] = np.where(live, C[:, np.arange(lmax), np.arange(lmax)], 1.0)
         Rinv = np.linalg.inv(np.conj(np.swapaxes(np.linalg.cholesky(C), 1, 2)))   # C = R^* R, R upper
         Rinv = np.ascontiguousarray(Rinv * (live[:, :, None] & live[:, None, :]))
@@ -352,13 +381,13 @@ def _compress_gpu(Xb, ks, eps_comp, device="cuda"):
     Rd = Xd - torch.bmm(Qd, Ld)
     del Xd, XdH
     small = Rd.transpose(1, 2).conj().contiguous()
-    Gr = (torch.bmm(Rd, small) if n <= kp else torch.bmm(small, Rd)).cpu().numpy()
+    Gr = _to_host(torch.bmm(Rd, small) if n <= kp else torch.bmm(small, Rd))
     del Rd, small
     lr = np.linalg.eigvalsh(Gr)
     dropped = np.sqrt(np.maximum(lr[:, -1], 0.0))
     tail = np.sqrt(np.maximum(np.trace(Gr, axis1=1, axis2=2).real, 0.0))
-    Q = Qd.cpu().numpy()
-    L = Ld.cpu().numpy()
+    Q = _to_host(Qd)
+    L = _to_host(Ld)
     return [(int(ls[c]), np.ascontiguousarray(Q[c][:, :ls[c]]), float(dropped[c]), float(tail[c]),
              L[c][:ls[c], :]) for c in range(cnt)]
 
@@ -540,10 +569,10 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
     for t in clusters:
         ks = sum(fac_s[(min(t, s), max(t, s))].size for s in row_blocks[t])
         groups.setdefault((int(size[t])), []).append((int(t), ks))
-    def agglomerate(part):
+    def agglomerate(part, pinned=False):
         nt = int(size[part[0][0]])
         kp = max(k for _, k in part)
-        Xb = np.zeros((len(part), nt, kp), np.complex128)
+        Xb = _host_buffer((len(part), nt, kp), np.complex128, pinned)
         cols = []
         for c, (t, _) in enumerate(part):
             j = 0
@@ -573,7 +602,7 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
         return out
 
     def compress_gpu(part):
-        Xb, cols = agglomerate(part)
+        Xb, cols = agglomerate(part, pinned=compress_device != "cpu")
         out = []
         for c, (l, Ut, dropped, tail, SV) in enumerate(_compress_gpu(Xb, [k for _, k in part], eps_comp,
                                                                      compress_device)):
@@ -663,7 +692,7 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
         Dd, doff = binding.kernel_blocks(dev_pts, kappa, diag, off[den[:, 0]], size[den[:, 0]], off[den[:, 1]],
                                          size[den[:, 1]])
         assert np.array_equal(doff, D_off)
-        D = Dd.cpu().numpy()
+        D = _to_host(Dd)
         del Dd
     elif nden:
         d_ro = np.ascontiguousarray(off[den[:, 0]])

@@ -14,6 +14,10 @@
   oracle's pin covers it on the CPU.
 * The builder with construct="gpu" gives the operator of construct="host": the same ranks
   and block structure, and the same product to 1e-9.
+* The Gram-matrix form of Alg. 2's per-cluster step (compress_on="gpu") meets the pins the
+  host builder meets (tests/test_builder.py): orthonormal bases, optimal couplings, Thm
+  5.1's bounds, and Alg. 1's ranks and optimal projection error; with the host builder's
+  ranks its product agrees with the host-built operator's to 1e-9.
 """
 import numpy as np
 import pytest
@@ -175,3 +179,21 @@ def test_builder_gpu_construction(torch_dev, surface, n, seed, leaf):
     x = inputs.make_rhs(cloud.n, 2, seed=seed + 1)
     assert rel(uniform.uh_mvp(vars(g), x), uniform.uh_mvp(vars(h), x)) <= 1e-9
     assert rel(uniform.h_mvp(vars(g), x), uniform.h_mvp(vars(h), x)) <= 1e-9
+
+
+@pytest.mark.parametrize("surface,n,leaf", [("sphere", 2048, 32), ("ellipsoid", 4000, 64), ("cube", 3000, 32)])
+def test_gpu_compression_meets_the_builder_pins(torch_dev, surface, n, leaf):
+    import test_builder as tb
+    cloud = inputs.make_cloud(surface, n, seed=0)
+    print(f"case compress_on=gpu {surface} n={cloud.n} leaf={leaf}", flush=True)
+    g = builder.build_operator(cloud, leaf=leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="gpu",
+                               compress_on="gpu")
+    h = builder.build_operator(cloud, leaf=leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="host")
+    for fn in (tb.test_orthogonal_bases_and_conjugate_symmetry, tb.test_couplings_are_optimal,
+               tb.test_theorem_5_1_and_frobenius_identity, tb.test_algorithm_1_and_2_give_the_same_basis):
+        fn((cloud, g))
+    x = inputs.make_rhs(cloud.n, 2, seed=1)
+    d = rel(uniform.uh_mvp(vars(g), x), uniform.uh_mvp(vars(h), x))
+    same = np.array_equal(g.rank_row, h.rank_row)
+    print(f"  ranks equal to the host's: {same}; product difference {d:.2e}", flush=True)
+    assert d <= (1e-9 if same else 1e-5)

@@ -5,7 +5,7 @@ oracle computes block by block (uniform.uh_mvp_rows): 384 rows of 6 random leave
 Bars: FP64 forms (general, symmetric and factored storage) 1e-12 relative on the sampled
 rows; complex64 and bf16-pair forms with 64 right-hand sides against the FP64 oracle 1e-5
 and 2e-2.  The operator is built as bench.py builds it, with the matrix sampled on the GPU
-(ACA and near field); the host part of the build takes about 100 s on 16 threads.  The
+(ACA and near field); the host part of the build takes about 90 s on 16 threads.  The
 operator itself is checked on the same rows against the dense kernel matrix: within
 10 eps |A x| (a stricter stand-in for the 10 eps |A|_2 |x| of the small-size pins, since
 |A x| <= |A|_2 |x|).
