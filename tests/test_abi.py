@@ -61,3 +61,37 @@ def test_block_record_matches_struct():
     assert binding.BLOCK_DTYPE.itemsize == ctypes.sizeof(binding.BlockDesc)
     for f, _ in binding.BlockDesc._fields_:
         assert binding.BLOCK_DTYPE.fields[f][1] == getattr(binding.BlockDesc, f).offset
+
+
+def test_construction_entry_points_validate_before_any_device_work():
+    """uhm_aca and uhm_kernel_blocks check their scalar arguments on the host and return
+    before touching the device, so these calls run without a GPU."""
+    import ctypes
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("libuhm.so is not built")
+    lib = binding.load_library()
+    null = ctypes.c_void_p(0)
+
+    def aca(nblocks=0, max_rows=64, max_cap=16, eps=1e-6, npoints=10, kappa=1.0):
+        return lib.uhm_aca(null, npoints, kappa, 1.0, null, nblocks, max_rows, max_cap, eps,
+                           null, 0, null, 0, null, 0, null, null, null)
+
+    assert aca() == binding.UHM_OK                       # nothing to do
+    assert aca(max_rows=0) == binding.UHM_EINVAL
+    assert aca(max_rows=65537) == binding.UHM_EINVAL
+    assert aca(max_cap=0) == binding.UHM_EINVAL
+    assert aca(max_cap=1025) == binding.UHM_EINVAL
+    assert aca(eps=-1.0) == binding.UHM_EINVAL
+    assert aca(eps=float("nan")) == binding.UHM_EINVAL
+    assert aca(kappa=float("inf")) == binding.UHM_EINVAL
+    assert aca(npoints=-1) == binding.UHM_EINVAL
+    assert aca(nblocks=3) == binding.UHM_EINVAL          # null pointers with blocks to do
+    assert b"null pointer" in lib.uhm_last_error()
+
+    def dense(nblocks=0, npoints=10, D_len=0):
+        return lib.uhm_kernel_blocks(null, npoints, 1.0, 1.0, null, nblocks, null, D_len, null, null)
+
+    assert dense() == binding.UHM_OK
+    assert dense(npoints=-5) == binding.UHM_EINVAL
+    assert dense(D_len=-1) == binding.UHM_EINVAL
+    assert dense(nblocks=2) == binding.UHM_EINVAL
