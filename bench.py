@@ -322,9 +322,8 @@ def run_construct(args):
             cap_now *= 4
         kout = np.zeros(len(ro), np.int32)
         t = time.perf_counter()
-        h = lib.uhmb_aca_run(P(pts), cloud.kappa, diag, len(ro), P(np.ascontiguousarray(ro)),
-                             P(np.ascontiguousarray(rs)), P(np.ascontiguousarray(co)), P(np.ascontiguousarray(cs)),
-                             eps, kcap, P(kout))
+        args_c = [np.ascontiguousarray(a, dtype=np.int64) for a in (ro, rs, co, cs)]   # alive during the call
+        h = lib.uhmb_aca_run(P(pts), cloud.kappa, diag, len(ro), *[P(a) for a in args_c], eps, kcap, P(kout))
         host_s = time.perf_counter() - t
         lib.uhmb_aca_free(h)
         entries = int(np.sum(rank * (rs + cs)))
@@ -365,8 +364,8 @@ def run_construct(args):
     dense_ms = e0.elapsed_time(e1)
     Dh = np.empty(int(np.sum(rs * cs)), np.complex128)
     t = time.perf_counter()
-    lib.uhmb_dense_blocks(P(pts), cloud.kappa, diag, len(ro), P(np.ascontiguousarray(ro)), P(np.ascontiguousarray(rs)),
-                          P(np.ascontiguousarray(co)), P(np.ascontiguousarray(cs)), P(np.ascontiguousarray(doff)), P(Dh))
+    args_c = [np.ascontiguousarray(a, dtype=np.int64) for a in (ro, rs, co, cs, doff)]   # alive during the call
+    lib.uhmb_dense_blocks(P(pts), cloud.kappa, diag, len(ro), *[P(a) for a in args_c], P(Dh))
     dense_host_s = time.perf_counter() - t
     dense_err = float(np.max(np.abs(Dd.cpu().numpy() - Dh)) / np.max(np.abs(Dh)))
     del Dd, Dh
@@ -389,6 +388,47 @@ def run_construct(args):
         "host_threads": int(lib.uhmb_num_threads()),
         "parity_sample": {"blocks": len(sample), "pivots_equal": all(sm["pivots_equal"] for sm in sample),
                           "worst_approx_rel_diff": worst},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_direct(args):
+    """Direct UH construction (Algs. 3-4 with per-block locks) against the two-phase builder
+    (H-matrix, then Alg. 2) on one cloud, on the host: times, the block factors held at once,
+    and agreement of the two operators on sampled rows (oracle, block by block)."""
+    import numpy as np
+
+    from oracle import uniform
+    from paper_2405_15573_amd import builder, inputs
+    cloud = inputs.make_cloud("sphere", args.n, seed=args.seed)
+    t = time.perf_counter()
+    two = builder.build_operator(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6)
+    t_two = time.perf_counter() - t
+    log(f"two-phase {t_two:.1f} s")
+    t = time.perf_counter()
+    direct = builder.build_uniform_direct(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6)
+    t_dir = time.perf_counter() - t
+    log(f"direct {t_dir:.1f} s: {json.dumps(direct.timings)}")
+    leaves = np.nonzero(np.bincount(two.parent[two.parent >= 0], minlength=two.nclusters) == 0)[0]
+    pick = np.random.default_rng(7).choice(leaves, size=4, replace=False)
+    pos = np.concatenate([np.arange(two.off[c], two.off[c] + two.size[c]) for c in pick])
+    x = inputs.make_rhs(cloud.n, 1, seed=args.seed)
+    a, _ = uniform.uh_mvp_rows(vars(two), x, pos)
+    b, _ = uniform.uh_mvp_rows(vars(direct), x, pos)
+    st = two.stats()
+    tm = direct.timings
+    line = {
+        "metric": "direct UH construction (Algs. 3-4, per-block locks) vs H-matrix then Alg. 2",
+        "value": round(t_dir, 2), "unit": "s", "n_gpus": 0, "steps": 1, "warmup": 0, "ms_per_step": round(t_dir * 1e3, 1),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"sphere N={cloud.n}, leaf {args.leaf}, eta 1, tolerances 1e-6, host threads "
+                               f"{tm['threads']}"},
+        "two_phase_s": round(t_two, 2), "direct_s": round(t_dir, 2),
+        "peak_factor_bytes": tm["peak_factor_bytes"], "total_factor_bytes": tm["total_factor_bytes"],
+        "uh_bytes": st["bytes_uh_c128"], "h_bytes": st["bytes_h_c128"], "lock_waits": tm["lock_waits"],
+        "ranks_equal": bool(np.array_equal(two.rank_row, direct.rank_row) and np.array_equal(two.adm_rank,
+                                                                                            direct.adm_rank)),
+        "sampled_rel_diff": float(np.linalg.norm(a - b) / np.linalg.norm(a)),
     }
     print(json.dumps(line), flush=True)
 
@@ -463,11 +503,13 @@ def main():
     ap.add_argument("--gmres-maxit", type=int, default=200)
     ap.add_argument("--gmres-small-n", type=int, default=16384,
                     help="size of the sphere at which the time-to-tolerance comparison runs to convergence")
-    ap.add_argument("--mode", choices=("headline", "batched", "serving", "gmres", "construct"), default="headline",
+    ap.add_argument("--mode", choices=("headline", "batched", "serving", "gmres", "construct", "direct"),
+                    default="headline",
                     help="headline: the FP64 workload and its side measurements; batched: many operators in "
                          "shared launches; serving: Poisson arrivals of GMRES solves; gmres: time to tolerance "
                          "of FP64 GMRES and GMRES-IR over sphere sizes; construct: ACA and near-field "
-                         "sampling on the GPU vs the host builder")
+                         "sampling on the GPU vs the host builder; direct: direct UH construction vs the "
+                         "two-phase builder (host only)")
     ap.add_argument("--gmres-sizes", type=str, default="16384,32768,65536",
                     help="sphere sizes of --mode gmres")
     ap.add_argument("--gmres-cases", type=str, default="", help="gmres mode: comma list of cases to run")
@@ -500,6 +542,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a design "
               "described in DESIGN.md and is not built", file=sys.stderr)
         sys.exit(2)
+
+    if args.mode == "direct":
+        return run_direct(args)
 
     import numpy as np
     import torch

@@ -68,6 +68,8 @@ def _native():
         lib.uhmb_aca_copy.restype = ctypes.c_int
         lib.uhmb_aca_free.argtypes = [P]
         lib.uhmb_aca_free.restype = None
+        lib.uhmb_aca_block.argtypes = [P, D, D, I64, I64, I64, I64, D, I32, P, P]
+        lib.uhmb_aca_block.restype = I32
         lib.uhmb_num_threads.argtypes = []
         lib.uhmb_num_threads.restype = ctypes.c_int
         _LIB = lib
@@ -713,6 +715,200 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
         kappa=kappa, h=cloud.h, leaf=leaf, eta=eta, eps_aca=eps_aca, eps_comp=eps_comp, depth=tree.depth,
         SX_off=SX_off, SY_off=SY_off, SX=SX, SY=SY,
         sv_dropped=sv_dropped, sv_tail=sv_tail, timings=tim)
+
+
+def build_uniform_direct(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca: float = 1e-6,
+                         eps_comp: float = 1e-6, eps_rec: float | None = None, kcap: int = 1024,
+                         threads: int | None = None) -> HostOperator:
+    """Direct construction of the UH form from matrix entries (Algs. 3-4, section 4.3), in
+    parallel with one lock per admissible block (section 4.4), in the symmetric form of
+    Remark 4.4: one set of clusters, one approximation per mirrored pair of blocks.
+
+    The clusters are processed from large to small.  Building cluster tau takes, for each
+    block tau x sigma, the block's recompressed factors U_b Sigma_b V_b^*, approximating the
+    block first (ACA + recompression, section 2.3) if no thread has yet; the block's lock
+    makes the second thread wait for the first.  Its columns U_b Sigma_b (or conj(V_b)
+    Sigma_b for the mirrored orientation) go into X_tau, and once both clusters of a block
+    have taken them the factors are dropped; only Sigma_b is kept, for the couplings.  The
+    SVD of X_tau gives U_tau and U_tau^* U_b Sigma_b as in build_operator, and the couplings
+    S_b = S_{X,b} S_{Y,b}^* are formed the same way.  The H form is never held whole, so the
+    returned operator carries no X and Y (adm_rank is set); timings["peak_factor_bytes"] is
+    the largest amount of block factors held at once and timings["total_factor_bytes"] what
+    the H form would hold."""
+    import threading
+    lib = _native()
+    if eps_rec is None:
+        eps_rec = eps_aca / 10.0
+    t0 = time.perf_counter()
+    tim = {}
+    tree = build_tree(cloud.points, leaf)
+    pts = np.ascontiguousarray(cloud.points[tree.perm])
+    diag = 1.0 / (2.0 * cloud.h)
+    kappa = cloud.kappa
+    adm, den = build_block_tree(tree, eta)
+    nc = tree.nclusters
+    off, size = tree.off, tree.size
+    if np.any(adm[:, 0] == adm[:, 1]):
+        raise RuntimeError("a cluster is admissible with itself")
+    lower = adm[adm[:, 0] < adm[:, 1]]
+    index = {(int(t), int(s)): b for b, (t, s) in enumerate(lower)}
+    row_blocks = {}
+    for t, s in adm:
+        row_blocks.setdefault(int(t), []).append(int(s))
+    order = sorted(row_blocks, key=lambda c: (-int(size[c]), c))
+    nlow = lower.shape[0]
+    locks = [threading.Lock() for _ in range(nlow)]
+    fac = [None] * nlow
+    sigma = [None] * nlow
+    uses = [2] * nlow
+    book = threading.Lock()
+    acct = {"live": 0, "peak": 0, "total": 0, "waits": 0}
+
+    def approximate(b):
+        t, s = int(lower[b, 0]), int(lower[b, 1])
+        m, n = int(size[t]), int(size[s])
+        full = min(m, n, kcap)
+        cap = min(full, 128)
+        while True:
+            X = np.empty((m, cap), np.complex128)
+            Y = np.empty((n, cap), np.complex128)
+            k = lib.uhmb_aca_block(_ptr(pts), kappa, diag, int(off[t]), m, int(off[s]), n, eps_aca, cap, _ptr(X), _ptr(Y))
+            if k < cap or cap >= full:
+                break
+            cap = min(full, 4 * cap)
+        QX, RX = np.linalg.qr(X[:, :k])
+        QY, RY = np.linalg.qr(Y[:, :k])
+        W, sv, Zh = np.linalg.svd(RX @ RY.conj().T)
+        r = max(1, int(np.count_nonzero(sv > eps_rec * sv[0]))) if sv.size and sv[0] > 0.0 else 1
+        return QX @ W[:, :r], sv[:r].copy(), QY @ Zh[:r, :].conj().T
+
+    def factors(b):
+        if not locks[b].acquire(blocking=False):
+            with book:
+                acct["waits"] += 1
+            locks[b].acquire()
+        try:
+            if fac[b] is None and sigma[b] is None:
+                Ub, sb, Vb = approximate(b)
+                fac[b], sigma[b] = (Ub, Vb), sb
+                nbytes = Ub.nbytes + Vb.nbytes
+                with book:
+                    acct["live"] += nbytes
+                    acct["total"] += nbytes
+                    acct["peak"] = max(acct["peak"], acct["live"])
+            return fac[b], sigma[b]
+        finally:
+            locks[b].release()
+
+    def release(b):
+        with book:
+            uses[b] -= 1
+            if uses[b] == 0:
+                acct["live"] -= fac[b][0].nbytes + fac[b][1].nbytes
+                fac[b] = None
+
+    def build_cluster(t):
+        cols, parts = [], []
+        for s in row_blocks[t]:
+            b = index[(min(t, s), max(t, s))]
+            (Ub, Vb), sb = factors(b)
+            parts.append(Ub * sb[None, :] if t < s else np.conj(Vb) * sb[None, :])
+            cols.append((s, sb.size))
+            release(b)
+        X = np.concatenate(parts, 1)
+        Uh, sv, Vh = np.linalg.svd(X, full_matrices=False)
+        l = max(1, int(np.count_nonzero(sv > eps_comp * sv[0]))) if sv[0] > 0 else 1
+        l = min(l, X.shape[1])
+        SV = sv[:l, None] * Vh[:l, :]
+        out, j = [], 0
+        for s, kb in cols:
+            out.append((s, np.ascontiguousarray(SV[:, j:j + kb])))
+            j += kb
+        return (t, l, np.ascontiguousarray(Uh[:, :l]), sv[l] if l < sv.size else 0.0,
+                float(np.sqrt(np.sum(sv[l:] ** 2))), out)
+
+    t1 = time.perf_counter()
+    nw = max(1, int(threads or _workers()))
+    ctx = threadpool_limits(1) if threadpool_limits is not None else None
+    try:
+        if ctx is not None:
+            ctx.__enter__()
+        if nw == 1:
+            results = [build_cluster(t) for t in order]
+        else:
+            with ThreadPoolExecutor(nw) as ex:
+                results = list(ex.map(build_cluster, order))
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    tim["clusters"] = time.perf_counter() - t1
+    rank = np.zeros(nc, np.int32)
+    Ubasis, Lmat = {}, {}
+    sv_dropped = np.zeros(nc)
+    sv_tail = np.zeros(nc)
+    for t, l, Ut, dropped, tail, Ls in results:
+        rank[t] = l
+        Ubasis[t] = Ut
+        sv_dropped[t] = dropped
+        sv_tail[t] = tail
+        for s, Lb in Ls:
+            Lmat[(t, s)] = Lb
+    del results
+
+    # couplings S_b = L_b Sigma_b^{-1} L_{b~}^T and their factors, as in build_operator
+    nadm = adm.shape[0]
+    kb_all = np.array([sigma[index[(min(int(t), int(s)), max(int(t), int(s)))]].size for t, s in adm], np.int32) \
+        if nadm else np.zeros(0, np.int32)
+    sizes = rank[adm[:, 0]].astype(np.int64) * rank[adm[:, 1]].astype(np.int64)
+    S_off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)[:nadm]
+    S = np.empty(int(sizes.sum()), np.complex128)
+    xsz = rank[adm[:, 0]].astype(np.int64) * kb_all
+    ysz = rank[adm[:, 1]].astype(np.int64) * kb_all
+    SX_off = np.concatenate([[0], np.cumsum(xsz)[:-1]]).astype(np.int64)[:nadm]
+    SY_off = np.concatenate([[0], np.cumsum(ysz)[:-1]]).astype(np.int64)[:nadm]
+    SX = np.empty(int(xsz.sum()), np.complex128)
+    SY = np.empty(int(ysz.sum()), np.complex128)
+    for b in range(nadm):
+        t, s = int(adm[b, 0]), int(adm[b, 1])
+        sb = sigma[index[(min(t, s), max(t, s))]]
+        Xf = Lmat[(t, s)] / sb[None, :]
+        S[S_off[b]:S_off[b] + sizes[b]] = (Xf @ Lmat[(s, t)].T).ravel(order="F")
+        SX[SX_off[b]:SX_off[b] + xsz[b]] = Xf.ravel(order="F")
+        SY[SY_off[b]:SY_off[b] + ysz[b]] = np.conj(Lmat[(s, t)]).ravel(order="F")
+    U_off = np.full(nc, -1, np.int64)
+    usz = size * rank
+    has = rank > 0
+    U_off[has] = np.concatenate([[0], np.cumsum(usz[has])[:-1]]) if has.any() else []
+    U = np.empty(int(usz.sum()), np.complex128)
+    for t, Ut in Ubasis.items():
+        U[U_off[t]:U_off[t] + usz[t]] = Ut.ravel(order="F")
+
+    nden = den.shape[0]
+    dsz = size[den[:, 0]] * size[den[:, 1]]
+    D_off = np.concatenate([[0], np.cumsum(dsz)[:-1]]).astype(np.int64) if nden else np.zeros(0, np.int64)
+    D = np.empty(int(dsz.sum()), np.complex128)
+    if nden:
+        # the index arrays are named so that they outlive the call
+        d_ro = np.ascontiguousarray(off[den[:, 0]])
+        d_rs = np.ascontiguousarray(size[den[:, 0]])
+        d_co = np.ascontiguousarray(off[den[:, 1]])
+        d_cs = np.ascontiguousarray(size[den[:, 1]])
+        lib.uhmb_dense_blocks(_ptr(pts), kappa, diag, nden, _ptr(d_ro), _ptr(d_rs), _ptr(d_co), _ptr(d_cs),
+                              _ptr(D_off), _ptr(D))
+    tim["total"] = time.perf_counter() - t0
+    tim["peak_factor_bytes"] = acct["peak"]
+    tim["total_factor_bytes"] = acct["total"]
+    tim["lock_waits"] = acct["waits"]
+    tim["threads"] = nw
+    zero = np.zeros(nadm, np.int64)
+    return HostOperator(
+        n=cloud.n, perm=tree.perm, off=tree.off, size=tree.size, level=tree.level, parent=tree.parent,
+        rank_row=rank.copy(), rank_col=rank.copy(), U_off=U_off, V_off=U_off.copy(), U=U, V=np.conj(U),
+        adm_row=adm[:, 0].astype(np.int32), adm_col=adm[:, 1].astype(np.int32), S_off=S_off, S=S,
+        adm_rank=kb_all, X_off=zero, Y_off=zero.copy(), X=np.zeros(0, np.complex128), Y=np.zeros(0, np.complex128),
+        den_row=den[:, 0].astype(np.int32), den_col=den[:, 1].astype(np.int32), D_off=D_off, D=D,
+        kappa=kappa, h=cloud.h, leaf=leaf, eta=eta, eps_aca=eps_aca, eps_comp=eps_comp, depth=tree.depth,
+        SX_off=SX_off, SY_off=SY_off, SX=SX, SY=SY, sv_dropped=sv_dropped, sv_tail=sv_tail, timings=tim)
 
 
 def symmetric_image(op: HostOperator) -> dict:

@@ -202,6 +202,27 @@ int uhmb_aca_copy(void* handle, int64_t cnt, const int64_t* idx, int64_t m, int6
 
 void uhmb_aca_free(void* handle) { delete static_cast<AcaBatch*>(handle); }
 
+// ACA of one block on the calling thread (no OpenMP), for construction schedules that
+// approximate blocks on demand.  X (m x kcap, row-major) = u and Y (n x kcap, row-major) =
+// conj(v), so A|_b ~ X Y^H in the first k columns (the rest zero); returns k, or -1 when
+// kcap < 1.
+int32_t uhmb_aca_block(const double* pts, double kappa, double diag, int64_t r0, int64_t m, int64_t c0,
+                       int64_t n, double eps, int32_t kcap, double* X, double* Y) {
+  if (kcap < 1) return -1;
+  const Geometry g{pts, kappa, diag};
+  AcaResult r;
+  aca_block(g, r0, m, c0, n, eps, kcap, r);
+  cplx* xo = reinterpret_cast<cplx*>(X);
+  cplx* yo = reinterpret_cast<cplx*>(Y);
+  std::memset(static_cast<void*>(xo), 0, sizeof(cplx) * m * kcap);
+  std::memset(static_cast<void*>(yo), 0, sizeof(cplx) * n * kcap);
+  for (int32_t l = 0; l < r.k; ++l) {
+    for (int64_t i = 0; i < m; ++i) xo[i * kcap + l] = r.u[(size_t)l * m + i];
+    for (int64_t j = 0; j < n; ++j) yo[j * kcap + l] = std::conj(r.v[(size_t)l * n + j]);
+  }
+  return r.k;
+}
+
 int uhmb_num_threads(void) { return omp_get_max_threads(); }
 
 }  // extern "C"
