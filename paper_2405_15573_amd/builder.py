@@ -312,7 +312,7 @@ def _eigh(G):
     return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
 
 
-def _pack_factors(res, pos, rel, m, n):
+def _pack_factors(res, pos, rel, m, n, on_device=False):
     """Factors of the blocks pos[rel] of one shape group of an ACA result (blocks pos are
     contiguous, all m x n with one cap c): X (cnt, m, kp) = u and Y (cnt, n, kp) = conj(v),
     zero beyond each block's rank, kp the group's largest rank.  Packed where the result
@@ -328,9 +328,64 @@ def _pack_factors(res, pos, rel, m, n):
     Vd = res.V[b0:b0 + len(pos) * c * n].view(len(pos), c, n).index_select(0, sel)[:, :kp, :]
     live = (torch.arange(kp, device=dev)[None, :] < torch.from_numpy(rank.astype(np.int64)).to(dev)[:, None])[:, :, None]
     zero = torch.zeros((), dtype=Ud.dtype, device=dev)
-    X = _to_host(torch.where(live, Ud, zero).transpose(1, 2).contiguous())
-    Y = _to_host(torch.conj_physical(torch.where(live, Vd, zero)).transpose(1, 2).contiguous())
-    return X, Y
+    X = torch.where(live, Ud, zero).transpose(1, 2).contiguous()
+    Y = torch.conj_physical(torch.where(live, Vd, zero)).transpose(1, 2).contiguous()
+    if on_device:
+        return X, Y, rank
+    return _to_host(X), _to_host(Y)
+
+
+def _chol_qr_batched(A, live, device):
+    """Cholesky QR, twice, of a batch of tall matrices A (cnt, m, kp) on `device`, with the
+    columns first scaled to unit norm; columns beyond a matrix's live count are zero and stay
+    zero.  Returns Q (device) and R (host, cnt x kp x kp) with A = Q R, R zero outside the
+    live block.  The Gram matrices and their Cholesky factors (kp x kp) are formed on the host."""
+    import torch
+    cnt, m, kp = A.shape
+    live_c = live[:, :, None] & live[:, None, :]
+    d = torch.linalg.vector_norm(A, dim=1).cpu().numpy()
+    d = np.where(live & (d > 0), d, 1.0)
+    Q = A / torch.from_numpy(d).to(device)[:, None, :]
+    R = np.broadcast_to(np.eye(kp, dtype=np.complex128), (cnt, kp, kp)).copy()
+    for _ in range(2):
+        G = _to_host(torch.bmm(Q.transpose(1, 2).conj().contiguous(), Q)).copy()
+        G = np.where(live_c, G, np.eye(kp))
+        Rk = np.conj(np.swapaxes(np.linalg.cholesky(G), 1, 2))   # G = Rk^* Rk
+        Rinv = np.ascontiguousarray(np.linalg.inv(Rk) * live_c)
+        Q = torch.bmm(Q, torch.from_numpy(Rinv).to(device))
+        R = Rk @ R
+    R = R * d[:, None, :] * live_c
+    return Q, R
+
+
+def _recompress_gpu(Xd, Yd, ranks, eps_rec, device="cuda"):
+    """Algebraic recompression (section 2.3) of a batch of ACA factorisations A_b ~ X_b Y_b^*
+    with the tall products on the GPU: X = Q_X R_X and Y = Q_Y R_Y by Cholesky QR
+    (_chol_qr_batched), the SVD of the small core R_X R_Y^* = W Sigma Z^* on the host, and
+    U_b = Q_X W, V_b = Q_Y Z truncated at sigma_i > eps_rec sigma_1.  Xd (cnt, m, kp) and
+    Yd (cnt, n, kp) are device tensors, zero beyond each block's ACA rank `ranks`.  Returns
+    per block (U_b, sigma_b, V_b) on the host."""
+    import torch
+    cnt, m, kp = Xd.shape
+    live = np.arange(kp)[None, :] < np.asarray(ranks)[:, None]
+    QX, RX = _chol_qr_batched(Xd, live, device)
+    QY, RY = _chol_qr_batched(Yd, live, device)
+    core = RX @ np.conj(np.swapaxes(RY, 1, 2))
+    nw = min(_workers(), cnt)
+    parts = _pmap(np.linalg.svd, np.array_split(core, nw)) if nw > 1 else [np.linalg.svd(core)]
+    W = np.concatenate([p[0] for p in parts])
+    sv = np.concatenate([p[1] for p in parts])
+    Zh = np.concatenate([p[2] for p in parts])
+    ks = np.array([max(1, int(np.count_nonzero(sv[c] > eps_rec * sv[c, 0]))) if sv[c, 0] > 0 else 1
+                   for c in range(cnt)])
+    kmax = int(ks.max())
+    keep = (np.arange(kmax)[None, :] < ks[:, None])[:, None, :]
+    Wk = np.ascontiguousarray(W[:, :, :kmax] * keep)
+    Zk = np.ascontiguousarray(np.conj(np.swapaxes(Zh, 1, 2))[:, :, :kmax] * keep)
+    U = _to_host(torch.bmm(QX, torch.from_numpy(Wk).to(device)))
+    V = _to_host(torch.bmm(QY, torch.from_numpy(Zk).to(device)))
+    return [(np.ascontiguousarray(U[c][:, :ks[c]]), sv[c, :ks[c]].copy(), np.ascontiguousarray(V[c][:, :ks[c]]))
+            for c in range(cnt)]
 
 
 def _compress_gpu(Xb, ks, eps_comp, device="cuda"):
@@ -394,7 +449,7 @@ def _compress_gpu(Xb, ks, eps_comp, device="cuda"):
              L[c][:ls[c], :]) for c in range(cnt)]
 
 
-def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_cap=128):
+def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_cap=128, eps_rec=None):
     """ACA of one level's blocks on the GPU (uhm_aca).  Blocks whose first pass stopped at
     its rank capacity run again with a four times larger one, up to kcap.  Returns the ranks
     and, per (shape, pass) group, (block indices, X (cnt, m, kp), Y (cnt, n, kp)) with
@@ -422,8 +477,13 @@ def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_
             keep = pos[final[pos]]
             if keep.size == 0:
                 continue
-            X, Y = _pack_factors(res, pos, keep - pos[0], int(m), int(n))
-            groups.append((idx[keep], int(m), int(n), X, Y))
+            if eps_rec is not None:   # recompress on the device; the group then holds (U_b, sigma_b, V_b)
+                Xd, Yd, rk = _pack_factors(res, pos, keep - pos[0], int(m), int(n), on_device=True)
+                groups.append((idx[keep], int(m), int(n), _recompress_gpu(Xd, Yd, rk, eps_rec), None))
+                del Xd, Yd
+            else:
+                X, Y = _pack_factors(res, pos, keep - pos[0], int(m), int(n))
+                groups.append((idx[keep], int(m), int(n), X, Y))
         todo = idx[~final]
         cap_now *= 4
         del res
@@ -433,7 +493,7 @@ def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_
 def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca: float = 1e-6,
                    eps_comp: float = 1e-6, eps_rec: float | None = None, kcap: int = 1024,
                    verbose: bool = False, construct: str = "host", compress_on: str = "host",
-                   compress_device: str = "cuda") -> HostOperator:
+                   compress_device: str = "cuda", recompress_on: str = "host") -> HostOperator:
     """Build the H form and the UH form of the point-kernel matrix A_ij = g(x_i, x_j),
     A_ii = 1/(2h), for one seeded cloud.
 
@@ -441,9 +501,13 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
     (uhm_aca) and the dense near-field blocks (uhm_kernel_blocks); the recompression and
     the uniform compression stay on the host.  construct="host" does everything on the
     host (OpenMP C++ and LAPACK).  compress_on="gpu" runs the large products of the uniform
-    compression (Alg. 2) as batched GEMMs on the GPU (_compress_gpu)."""
-    if construct not in ("host", "gpu") or compress_on not in ("host", "gpu"):
-        raise ValueError("construct and compress_on must be 'host' or 'gpu'")
+    compression (Alg. 2) as batched GEMMs on the GPU (_compress_gpu).  recompress_on="gpu"
+    (with construct="gpu") recompresses the ACA factors where they are, on the GPU
+    (_recompress_gpu), and copies only the recompressed factors to the host."""
+    if construct not in ("host", "gpu") or compress_on not in ("host", "gpu") or recompress_on not in ("host", "gpu"):
+        raise ValueError("construct, compress_on and recompress_on must be 'host' or 'gpu'")
+    if recompress_on == "gpu" and construct != "gpu":
+        raise ValueError("recompress_on='gpu' needs construct='gpu' (the ACA factors must be on the GPU)")
     lib = _native()
     if eps_rec is None:
         eps_rec = eps_aca / 10.0
@@ -482,7 +546,8 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
         ta = time.perf_counter()
         handle = None
         if construct == "gpu":
-            kout, gpu_groups, ks = _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps_aca, kcap)
+            kout, gpu_groups, ks = _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps_aca, kcap,
+                                                  eps_rec=eps_rec if recompress_on == "gpu" else None)
             t_aca_kernel += ks
         else:
             handle = lib.uhmb_aca_run(_ptr(pts), kappa, diag, nb, _ptr(roff), _ptr(rsz), _ptr(coff), _ptr(csz),
@@ -518,7 +583,13 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
 
         try:
             jobs = []
-            if handle is None:
+            if handle is None and recompress_on == "gpu":
+                for sel, m, n, facs, _ in gpu_groups:
+                    for b, (Ub, sb, Vb) in zip(sel, facs):
+                        key = (int(blk[b, 0]), int(blk[b, 1]))
+                        fac_U[key], fac_s[key], fac_V[key] = Ub, sb, Vb
+                del gpu_groups
+            elif handle is None:
                 for sel, m, n, X, Y in gpu_groups:
                     kp = X.shape[2]
                     step = max(1, len(list(_chunks(sel, 16 * (m + n) * kp * 4, parts=4 * _workers()))[0]))

@@ -172,3 +172,43 @@ def test_memory_ratio_soft_check():
     adm = (op.X.size + op.Y.size) / (op.U.size + op.V.size + op.S.size)
     assert 1.3 <= ratio <= 2.7
     assert adm > 1.0
+
+
+def test_recompression_by_cholesky_qr():
+    """builder._recompress_gpu (Cholesky QR of the column-scaled ACA factors, twice, then the
+    SVD of the small core), run with CPU tensors, against the Householder-QR recompression of
+    the same factors: the same ranks, and U Sigma V^* equal to 1e-12 of |X Y^*|."""
+    import torch
+    cloud = inputs.make_cloud("cube", 3000, seed=1)
+    tree = builder.build_tree(cloud.points, 64)
+    pts = np.ascontiguousarray(cloud.points[tree.perm])
+    adm, _ = builder.build_block_tree(tree, 1.0)
+    low = adm[adm[:, 0] < adm[:, 1]]
+    shape = np.stack([tree.size[low[:, 0]], tree.size[low[:, 1]]], 1)
+    m, n = (int(v) for v in shape[0])
+    sel = low[(shape[:, 0] == m) & (shape[:, 1] == n)][:40]
+    lib = builder._native()
+    facs = []
+    for t, s in sel:
+        X = np.empty((m, 64), np.complex128)
+        Y = np.empty((n, 64), np.complex128)
+        k = lib.uhmb_aca_block(builder._ptr(pts), cloud.kappa, 1.0 / (2 * cloud.h), int(tree.off[t]), m,
+                               int(tree.off[s]), n, 1e-6, 64, builder._ptr(X), builder._ptr(Y))
+        facs.append((X[:, :k].copy(), Y[:, :k].copy()))
+    ranks = np.array([f[0].shape[1] for f in facs])
+    kp = int(ranks.max())
+    Xb = np.zeros((len(facs), m, kp), np.complex128)
+    Yb = np.zeros((len(facs), n, kp), np.complex128)
+    for c, (X, Y) in enumerate(facs):
+        Xb[c, :, :X.shape[1]] = X
+        Yb[c, :, :Y.shape[1]] = Y
+    got = builder._recompress_gpu(torch.from_numpy(Xb), torch.from_numpy(Yb), ranks, 1e-7, device="cpu")
+    for (X, Y), (Ub, sb, Vb) in zip(facs, got):
+        QX, RX = np.linalg.qr(X)
+        QY, RY = np.linalg.qr(Y)
+        W, sv, Zh = np.linalg.svd(RX @ RY.conj().T)
+        r = max(1, int(np.count_nonzero(sv > 1e-7 * sv[0])))
+        ref = (QX @ W[:, :r]) * sv[:r] @ (QY @ Zh[:r].conj().T).conj().T
+        assert sb.size == r
+        assert np.linalg.norm(Ub.conj().T @ Ub - np.eye(r)) < 1e-13
+        assert np.linalg.norm((Ub * sb) @ Vb.conj().T - ref) <= 1e-12 * np.linalg.norm(X @ Y.conj().T)

@@ -220,3 +220,25 @@ def test_direct_operator_on_the_gpu(torch_dev):
         err = max(np.linalg.norm(y[:, j] - r[:, j]) / np.linalg.norm(r[:, j]) for j in range(3))
         print(f"  {form}: {err:.2e}", flush=True)
         assert err <= 1e-12
+
+
+@pytest.mark.parametrize("surface,n,leaf", [("sphere", 2048, 32), ("cube", 3000, 32)])
+def test_gpu_recompression_meets_the_builder_pins(torch_dev, surface, n, leaf):
+    """construct="gpu" with recompress_on="gpu": the ACA factors are recompressed on the GPU
+    (Cholesky QR of the column-scaled factors, the small core SVD on the host).  The operator
+    meets the builder's pins; with the host builder's ranks its product agrees with the
+    host-built operator's to 1e-9."""
+    import test_builder as tb
+    cloud = inputs.make_cloud(surface, n, seed=0)
+    print(f"case recompress_on=gpu {surface} n={cloud.n} leaf={leaf}", flush=True)
+    g = builder.build_operator(cloud, leaf=leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="gpu",
+                               recompress_on="gpu")
+    h = builder.build_operator(cloud, leaf=leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="host")
+    for fn in (tb.test_orthogonal_bases_and_conjugate_symmetry, tb.test_couplings_are_optimal,
+               tb.test_theorem_5_1_and_frobenius_identity, tb.test_algorithm_1_and_2_give_the_same_basis):
+        fn((cloud, g))
+    x = inputs.make_rhs(cloud.n, 2, seed=1)
+    d = rel(uniform.uh_mvp(vars(g), x), uniform.uh_mvp(vars(h), x))
+    same = np.array_equal(g.rank_row, h.rank_row) and np.array_equal(g.adm_rank, h.adm_rank)
+    print(f"  ranks equal to the host's: {same}; product difference {d:.2e}", flush=True)
+    assert d <= (1e-9 if same else 1e-5)
