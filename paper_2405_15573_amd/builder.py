@@ -335,6 +335,19 @@ def _pack_factors(res, pos, rel, m, n, on_device=False):
     return _to_host(X), _to_host(Y)
 
 
+def _chol_inv(G):
+    """R = chol(G)^* (upper, G = R^* R) and R^{-1} over a batch, split across the builder's
+    threads."""
+    def one(g):
+        r = np.conj(np.swapaxes(np.linalg.cholesky(g), 1, 2))
+        return r, np.linalg.inv(r)
+    nw = min(_workers(), G.shape[0])
+    if nw <= 1:
+        return one(G)
+    parts = _pmap(one, np.array_split(G, nw))
+    return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
+
+
 def _chol_qr_batched(A, live, device):
     """Cholesky QR, twice, of a batch of tall matrices A (cnt, m, kp) on `device`, with the
     columns first scaled to unit norm; columns beyond a matrix's live count are zero and stay
@@ -350,8 +363,8 @@ def _chol_qr_batched(A, live, device):
     for _ in range(2):
         G = _to_host(torch.bmm(Q.transpose(1, 2).conj().contiguous(), Q)).copy()
         G = np.where(live_c, G, np.eye(kp))
-        Rk = np.conj(np.swapaxes(np.linalg.cholesky(G), 1, 2))   # G = Rk^* Rk
-        Rinv = np.ascontiguousarray(np.linalg.inv(Rk) * live_c)
+        Rk, Rinv = _chol_inv(G)   # G = Rk^* Rk
+        Rinv = np.ascontiguousarray(Rinv * live_c)
         Q = torch.bmm(Q, torch.from_numpy(Rinv).to(device))
         R = Rk @ R
     R = R * d[:, None, :] * live_c
