@@ -212,3 +212,23 @@ def test_recompression_by_cholesky_qr():
         assert sb.size == r
         assert np.linalg.norm(Ub.conj().T @ Ub - np.eye(r)) < 1e-13
         assert np.linalg.norm((Ub * sb) @ Vb.conj().T - ref) <= 1e-12 * np.linalg.norm(X @ Y.conj().T)
+
+
+def test_gram_compression_with_cpu_tensors():
+    """The Gram-matrix form of Alg. 2's per-cluster step (compress_on="gpu"), run with CPU
+    tensors: both of its branches (n_tau <= K and n_tau > K occur on this cloud) give the
+    SVD route's ranks, meet the builder's pins, and the same product to 1e-9."""
+    cloud = inputs.make_cloud("cube", 3000, seed=0)
+    h = builder.build_operator(cloud, leaf=32, eta=1.0, eps_aca=1e-6, eps_comp=1e-6)
+    g = builder.build_operator(cloud, leaf=32, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, compress_on="gpu",
+                               compress_device="cpu")
+    has = g.rank_row > 0
+    kt = np.bincount(g.adm_row, weights=g.adm_rank, minlength=g.nclusters)
+    kmax = {int(sz): int(kt[has & (g.size == sz)].max()) for sz in np.unique(g.size[has])}   # a group's width
+    assert any(sz <= k for sz, k in kmax.items()) and any(sz > k for sz, k in kmax.items())
+    assert np.array_equal(g.rank_row, h.rank_row)
+    for fn in (test_orthogonal_bases_and_conjugate_symmetry, test_couplings_are_optimal,
+               test_theorem_5_1_and_frobenius_identity, test_algorithm_1_and_2_give_the_same_basis):
+        fn((cloud, g))
+    x = inputs.make_rhs(cloud.n, 2, seed=1)
+    assert rel(uniform.uh_mvp(vars(g), x), uniform.uh_mvp(vars(h), x)) <= 1e-9
