@@ -368,7 +368,8 @@ int uhm_kernel_blocks(const double* points, int64_t npoints, double kappa, doubl
 
 /*
  * ACA with partial pivoting (section 2.3; the variant of Bebendorf the paper cites) of each
- * block A|_b = A[row_off : row_off+m, col_off : col_off+n], one wavefront per block:
+ * block A|_b = A[row_off : row_off+m, col_off : col_off+n], one workgroup per block (1 to 16
+ * wavefronts, chosen per call from max_rows so that a thread holds about 8 rows):
  *   start from row i_1 = 0; at step k take the residual row r = A[i_k, :] - sum_{l<k}
  *   u_l[i_k] v_l, mark row i_k used, pick j_k maximising |r_j| (if r vanishes, retry with
  *   the unused row of smallest index), set v_k = r / r[j_k] and u_k = A[:, j_k] -

@@ -571,7 +571,7 @@ class AcaResult:
 
 
 def aca(points, kappa: float, diag: float, row_off, rows, col_off, cols, cap, eps: float, stream=None) -> AcaResult:
-    """ACA with partial pivoting of every block on the device (uhm_aca), one wavefront per
+    """ACA with partial pivoting of every block on the device (uhm_aca), one workgroup per
     block, in the order given.  cap: most terms per block (scalar or per block)."""
     import torch
     lib = load_library()
