@@ -18,6 +18,9 @@
   host builder meets (tests/test_builder.py): orthonormal bases, optimal couplings, Thm
   5.1's bounds, and Alg. 1's ranks and optimal projection error; with the host builder's
   ranks its product agrees with the host-built operator's to 1e-9.
+* So does the GPU recompression of the ACA factors (recompress_on="gpu").
+* An operator from the direct construction (no H form kept) multiplies on the GPU like any
+  other, in the general, symmetric and factored FP64 forms (1e-12 against the oracle).
 """
 import numpy as np
 import pytest
