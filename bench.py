@@ -426,22 +426,26 @@ def run_direct(args):
 
     from oracle import uniform
     from paper_2405_15573_amd import builder, inputs
+    import resource
     cloud = inputs.make_cloud("sphere", args.n, seed=args.seed)
-    t = time.perf_counter()
-    two = builder.build_operator(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6)
-    t_two = time.perf_counter() - t
-    log(f"two-phase {t_two:.1f} s")
     t = time.perf_counter()
     direct = builder.build_uniform_direct(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6)
     t_dir = time.perf_counter() - t
-    log(f"direct {t_dir:.1f} s: {json.dumps(direct.timings)}")
-    leaves = np.nonzero(np.bincount(two.parent[two.parent >= 0], minlength=two.nclusters) == 0)[0]
-    pick = np.random.default_rng(7).choice(leaves, size=4, replace=False)
-    pos = np.concatenate([np.arange(two.off[c], two.off[c] + two.size[c]) for c in pick])
-    x = inputs.make_rhs(cloud.n, 1, seed=args.seed)
-    a, _ = uniform.uh_mvp_rows(vars(two), x, pos)
-    b, _ = uniform.uh_mvp_rows(vars(direct), x, pos)
-    st = two.stats()
+    rss_direct = resource.getrusage(resource.RUSAGE_SELF).ru_maxrss / 2**20
+    log(f"direct {t_dir:.1f} s, peak resident set {rss_direct:.1f} GB: {json.dumps(direct.timings)}")
+    two = None
+    if not args.direct_only:
+        t = time.perf_counter()
+        two = builder.build_operator(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6)
+        t_two = time.perf_counter() - t
+        log(f"two-phase {t_two:.1f} s")
+        leaves = np.nonzero(np.bincount(two.parent[two.parent >= 0], minlength=two.nclusters) == 0)[0]
+        pick = np.random.default_rng(7).choice(leaves, size=4, replace=False)
+        pos = np.concatenate([np.arange(two.off[c], two.off[c] + two.size[c]) for c in pick])
+        x = inputs.make_rhs(cloud.n, 1, seed=args.seed)
+        a, _ = uniform.uh_mvp_rows(vars(two), x, pos)
+        b, _ = uniform.uh_mvp_rows(vars(direct), x, pos)
+    st = direct.stats()
     tm = direct.timings
     line = {
         "metric": "direct UH construction (Algs. 3-4, per-block locks) vs H-matrix then Alg. 2",
@@ -449,13 +453,17 @@ def run_direct(args):
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"sphere N={cloud.n}, leaf {args.leaf}, eta 1, tolerances 1e-6, host threads "
                                f"{tm['threads']}"},
-        "two_phase_s": round(t_two, 2), "direct_s": round(t_dir, 2),
+        "direct_s": round(t_dir, 2), "direct_peak_rss_gb": round(rss_direct, 2),
         "peak_factor_bytes": tm["peak_factor_bytes"], "total_factor_bytes": tm["total_factor_bytes"],
-        "uh_bytes": st["bytes_uh_c128"], "h_bytes": st["bytes_h_c128"], "lock_waits": tm["lock_waits"],
-        "ranks_equal": bool(np.array_equal(two.rank_row, direct.rank_row) and np.array_equal(two.adm_rank,
-                                                                                            direct.adm_rank)),
-        "sampled_rel_diff": float(np.linalg.norm(a - b) / np.linalg.norm(a)),
+        "uh_bytes": st["bytes_uh_c128"], "lock_waits": tm["lock_waits"],
+        "l_max": st["l_max"], "k_max": st["k_max"],
     }
+    if two is not None:
+        line.update({
+            "two_phase_s": round(t_two, 2), "h_bytes": two.stats()["bytes_h_c128"],
+            "ranks_equal": bool(np.array_equal(two.rank_row, direct.rank_row)
+                                and np.array_equal(two.adm_rank, direct.adm_rank)),
+            "sampled_rel_diff": float(np.linalg.norm(a - b) / np.linalg.norm(a))})
     print(json.dumps(line), flush=True)
 
 
@@ -561,6 +569,8 @@ def main():
     ap.add_argument("--compress", choices=("gpu", "host"), default="host",
                     help="headline: the uniform compression on the host (LAPACK SVDs) or with its large products "
                          "on the GPU (Gram-matrix form)")
+    ap.add_argument("--direct-only", action="store_true",
+                    help="direct mode: skip the two-phase build (which holds the H and UH forms at once)")
     ap.add_argument("--full-build", action="store_true",
                     help="construct mode: also build the whole operator with the ACA factors recompressed on the GPU")
     ap.add_argument("--copy-calibration", action="store_true",
