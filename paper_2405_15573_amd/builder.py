@@ -514,7 +514,8 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
     (uhm_aca) and the dense near-field blocks (uhm_kernel_blocks); the recompression and
     the uniform compression stay on the host.  construct="host" does everything on the
     host (OpenMP C++ and LAPACK).  compress_on="gpu" runs the large products of the uniform
-    compression (Alg. 2) as batched GEMMs on the GPU (_compress_gpu).  recompress_on="gpu"
+    compression (Alg. 2) as batched GEMMs (_compress_gpu) on compress_device (a torch device
+    name; "cpu" runs the same steps on the host, for tests).  recompress_on="gpu"
     (with construct="gpu") recompresses the ACA factors where they are, on the GPU
     (_recompress_gpu), and copies only the recompressed factors to the host."""
     if construct not in ("host", "gpu") or compress_on not in ("host", "gpu") or recompress_on not in ("host", "gpu"):
