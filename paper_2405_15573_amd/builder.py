@@ -27,6 +27,16 @@ Steps, in the paper's order:
 
 The result is a ``HostOperator`` holding both the H form (for the H-MVP comparator) and
 the UH form, in the flat, cluster-ordered layout declared in ``include/uhm.h``.
+
+Where the work runs (build_operator's options): the matrix sampling (ACA and the near
+field) on the host (OpenMP C++) or on the GPU (uhm_aca, uhm_kernel_blocks); the
+recompression on the host (LAPACK QR and SVD) or with its tall products on the GPU
+(Cholesky QR); the uniform compression on the host (LAPACK SVD per cluster) or with its
+large products on the GPU (the Gram-matrix form of the same subspace).
+
+build_uniform_direct is the direct construction of Algs. 3-4 (section 4.3) with one lock
+per block (section 4.4): blocks are approximated on demand and dropped once both of their
+clusters have used them, so the H form is never held whole.
 """
 from __future__ import annotations
 
