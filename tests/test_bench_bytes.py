@@ -33,3 +33,21 @@ def test_factored_form_counts_both_factors():
     # complex64 vectors for the low-precision forms
     ab = bench.algorithmic_bytes(_info(storage=6, elem_bytes=8, elems_coupling_in=80), 1000)
     assert ab["k_forward_tiles"] == 8 * 100 + 8 * 1010
+
+
+def test_bench_cli_on_the_host():
+    """The parts of bench.py that need no GPU: more than one GPU is refused with a message,
+    and the direct-construction mode runs end to end on a small cloud."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True)
+    assert r.returncode == 2 and "one GPU only" in r.stderr
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--mode", "direct", "--n", "3000"],
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["ranks_equal"] and line["sampled_rel_diff"] <= 1e-12
+    assert line["peak_factor_bytes"] < line["total_factor_bytes"]
