@@ -47,16 +47,3 @@ def dense_matvec(points, kappa, diag, x, rows=None, chunk=512):
         out[a:a + chunk] = dense_rows(points, kappa, diag, rows[a:a + chunk]) @ x2
     return out.reshape((rows.size,) + x.shape[1:])
 
-
-def spectral_norm(points, kappa, diag, iters=60, seed=0):
-    """||A||_2 of the dense matrix by power iteration on A^* A (small N)."""
-    a = dense_matrix(points, kappa, diag)
-    rng = np.random.default_rng(seed)
-    v = rng.normal(size=a.shape[1]) + 1j * rng.normal(size=a.shape[1])
-    v /= np.linalg.norm(v)
-    s = 0.0
-    for _ in range(iters):
-        w = a.conj().T @ (a @ v)
-        s = np.sqrt(np.linalg.norm(w))
-        v = w / np.linalg.norm(w)
-    return float(s)
