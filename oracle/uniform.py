@@ -223,7 +223,9 @@ _LIB = None
 def _lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liboracle.so")
+        # UHM_ORACLE_LIB selects another build of the same source (the sanitizer test's)
+        path = os.environ.get("UHM_ORACLE_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                                "liboracle.so")
         if not os.path.exists(path):
             from . import build as _b
             _b.build()

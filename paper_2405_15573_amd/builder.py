@@ -64,7 +64,8 @@ _LIB = None
 def _native():
     global _LIB
     if _LIB is None:
-        path = os.path.join(os.path.dirname(__file__), "libuhm_builder.so")
+        # UHM_BUILDER_LIB selects another build of the same source (a sanitizer build)
+        path = os.environ.get("UHM_BUILDER_LIB") or os.path.join(os.path.dirname(__file__), "libuhm_builder.so")
         if not os.path.exists(path):
             raise RuntimeError(
                 f"builder library {path} is missing: run __graft_entry__.build() first")
