@@ -201,6 +201,10 @@ typedef struct {
   int32_t max_iterations;   /* cap on Krylov iterations per solve, all cycles and refinements [2000] */
   int32_t max_refinements;  /* outer refinement steps when an inner operator is given [30] */
   double inner_tol;         /* residual reduction asked of each inner solve of the refinement [1e-4] */
+  int32_t inner_cycles;     /* with an inner operator: an inner solve also ends after this many
+                               GMRES(m) cycles, so that with 1 every restart of the inner GMRES is
+                               a refinement step (the restart residual is the true FP64 one);
+                               0 = end an inner solve at inner_tol only [0] */
 } uhm_gmres_opts;
 
 /* What uhm_solve_gmres did. */
@@ -226,8 +230,9 @@ typedef struct {
  *   inner: NULL for plain GMRES on op; otherwise an operator of the same matrix in
  *          complex64 or bf16-pair storage, and the solve is mixed-precision iterative
  *          refinement: r = B - A X with op (FP64), an inner GMRES(m) solves
- *          A_inner D = r to inner_tol (products with `inner`, everything else FP64),
- *          X += D, until max_j ||r_j|| / ||b_j|| <= tol.
+ *          A_inner D = r to inner_tol, or for opts->inner_cycles cycles when that is
+ *          positive (products with `inner`, everything else FP64), X += D, until
+ *          max_j ||r_j|| / ||b_j|| <= tol.
  * B (ldb >= n), X (ldx >= n): complex128 device arrays, n x nrhs column-major, user order.
  * Synchronous on `hip_stream`; allocates its workspace ((m+1) n nrhs complex128 for the
  * Krylov basis plus a few vectors) for the duration of the call.

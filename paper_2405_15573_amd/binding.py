@@ -49,7 +49,8 @@ class OpInfo(ctypes.Structure):
 
 
 class GmresOpts(ctypes.Structure):
-    _fields_ = [("restart", I32), ("max_iterations", I32), ("max_refinements", I32), ("inner_tol", ctypes.c_double)]
+    _fields_ = [("restart", I32), ("max_iterations", I32), ("max_refinements", I32), ("inner_tol", ctypes.c_double),
+                ("inner_cycles", I32)]
 
 
 class GmresInfo(ctypes.Structure):
@@ -190,6 +191,9 @@ class DeviceOperator:
 
     def matvec(self, x, y=None, stream=None):
         """y = A x for a torch tensor x (n,) or (n, r) on the device; returns y."""
+        return self._product("uhm_matvec", x, y, stream)
+
+    def _product(self, entry, x, y, stream):
         import torch
         want = torch.complex128 if self.storage in C128_FORMS else torch.complex64
         if x.dtype != want or not x.is_cuda:
@@ -211,9 +215,9 @@ class DeviceOperator:
         ldx = x2.stride(1) if nrhs > 1 else self.n
         ldy = y2.stride(1) if nrhs > 1 else self.n
         sh, _ = _stream_handle(stream)
-        rc = load_library().uhm_matvec(self._h, ctypes.c_void_p(x2.data_ptr()), ldx, ctypes.c_void_p(y2.data_ptr()),
-                                       ldy, nrhs, sh)
-        _check(rc, "uhm_matvec")
+        rc = getattr(load_library(), entry)(self._h, ctypes.c_void_p(x2.data_ptr()), ldx,
+                                            ctypes.c_void_p(y2.data_ptr()), ldy, nrhs, sh)
+        _check(rc, entry)
         if y is not None:
             return y
         return y2.reshape(self.n) if vec else y2
@@ -336,9 +340,10 @@ def upload_h(op, storage: str = "c128", stream=None) -> DeviceOperator:
 
 def solve_gmres(op: DeviceOperator, b, tol: float, inner: DeviceOperator | None = None, restart: int = 50,
                 max_iterations: int = 2000, max_refinements: int = 30, inner_tol: float = 1e-4, x=None,
-                stream=None, raise_on_noconv: bool = True):
+                stream=None, raise_on_noconv: bool = True, inner_cycles: int = 0):
     """Solve A X = B with GMRES(restart) (inner=None) or GMRES-IR with the low-precision
-    operator `inner`.  b: complex128 device tensor (n,) or (n, r).  Returns (x, info dict, code)."""
+    operator `inner` (inner_cycles > 0: an inner solve also ends after that many cycles).
+    b: complex128 device tensor (n,) or (n, r).  Returns (x, info dict, code)."""
     import torch
     if op.storage not in C128_FORMS:
         raise ValueError("the residual operator must be complex128")
@@ -355,7 +360,7 @@ def solve_gmres(op: DeviceOperator, b, tol: float, inner: DeviceOperator | None 
         x2 = x.reshape(op.n, 1) if x.dim() == 1 else x
     ldb = b2.stride(1) if r > 1 else op.n
     ldx = x2.stride(1) if r > 1 else op.n
-    o = GmresOpts(restart, max_iterations, max_refinements, inner_tol)
+    o = GmresOpts(restart, max_iterations, max_refinements, inner_tol, inner_cycles)
     inf = GmresInfo()
     sh, _ = _stream_handle(stream)
     rc = load_library().uhm_solve_gmres(op.handle, inner.handle if inner is not None else None,
@@ -431,7 +436,7 @@ class Krylov:
     at once through `krylov_step`."""
 
     def __init__(self, b, tol: float, mixed: bool, restart: int = 50, max_iterations: int = 2000,
-                 max_refinements: int = 30, inner_tol: float = 1e-4, stream=None):
+                 max_refinements: int = 30, inner_tol: float = 1e-4, stream=None, inner_cycles: int = 0):
         import torch
         b2 = b.reshape(-1, 1) if b.dim() == 1 else b
         if b2.dtype != torch.complex128:
@@ -440,7 +445,7 @@ class Krylov:
             b2 = b2.t().contiguous().t()
         self.n, self.r = b2.shape
         ldb = b2.stride(1) if self.r > 1 else self.n
-        o = GmresOpts(restart, max_iterations, max_refinements, inner_tol)
+        o = GmresOpts(restart, max_iterations, max_refinements, inner_tol, inner_cycles)
         out = P()
         sh, _ = _stream_handle(stream)
         _check(load_library().uhm_krylov_create(self.n, self.r, ctypes.c_void_p(b2.data_ptr()), ldb, float(tol),

@@ -520,6 +520,21 @@ struct uhm_krylov {
 namespace uhm_detail {
 namespace {
 
+// With inner_cycles > 0, an inner solve of the refinement ends after that many cycles.
+bool inner_cycles_spent(const uhm_krylov* K) {
+  return K->mixed && K->o.inner_cycles > 0 && K->cycles >= K->o.inner_cycles;
+}
+
+// The inner solve is over: x += d, then the true residual from the FP64 product of x.
+void inner_finish(uhm_krylov* K) {
+  Work& W = K->W;
+  hipLaunchKernelGGL(k_g_add, dim3(nblk(K->n * K->r)), dim3(kGB), 0, K->s, W.d.p, K->n, K->r, K->xacc.p, K->n, 0);
+  K->phase = uhm_krylov::OUTER;
+  K->req = UHM_KRYLOV_PRODUCT_HIGH;
+  K->req_in = K->xacc.p;
+  K->req_out = W.w.p;
+}
+
 // t = current inner residual; start a cycle, or finish the inner solve.
 int cycle_start(uhm_krylov* K) {
   Work& W = K->W;
@@ -533,14 +548,10 @@ int cycle_start(uhm_krylov* K) {
     K->done[c] = K->beta[c] <= K->rtol[c];
     all = all && K->done[c];
   }
-  if (all || K->iters >= K->o.max_iterations) {
+  if (all || K->iters >= K->o.max_iterations || inner_cycles_spent(K)) {
     // inner solve finished: d is in W.d
     if (K->mixed) {
-      hipLaunchKernelGGL(k_g_add, dim3(nblk(n * r)), dim3(kGB), 0, s, W.d.p, n, r, K->xacc.p, n, 0);
-      K->phase = uhm_krylov::OUTER;
-      K->req = UHM_KRYLOV_PRODUCT_HIGH;
-      K->req_in = K->xacc.p;
-      K->req_out = W.w.p;
+      inner_finish(K);
     } else {
       K->phase = uhm_krylov::INNER_FINAL_X;
       K->req = UHM_KRYLOV_PRODUCT_HIGH;
@@ -693,6 +704,11 @@ int arnoldi_next(uhm_krylov* K, bool all_done) {
   UHM_HIP(hipMemcpyAsync(W.ybuf.p, yv.data(), sizeof(cd) * yv.size(), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_g_combine, dim3(nblk(n * r)), dim3(kGB), 0, s, W.V.p, vstride, jm, W.ybuf.p, W.d.p, n, n, r);
   UHM_HIP(hipStreamSynchronize(s));
+  if (inner_cycles_spent(K)) {
+    // the refinement step follows at once: its FP64 residual replaces the inner one
+    inner_finish(K);
+    return UHM_OK;
+  }
   K->phase = uhm_krylov::CYCLE_END;
   K->req = K->mixed ? UHM_KRYLOV_PRODUCT_LOW : UHM_KRYLOV_PRODUCT_HIGH;
   K->req_in = W.d.p;
@@ -908,9 +924,10 @@ int uhm_krylov_create(int64_t n, int32_t nrhs, const void* B, int64_t ldb, doubl
   if (!out || !B) return fail(UHM_EINVAL, "null argument");
   *out = nullptr;
   if (n < 1 || nrhs < 1 || ldb < n || !(tol > 0.0)) return fail(UHM_EINVAL, "bad n, nrhs, leading dimension or tol");
-  uhm_gmres_opts o{50, 2000, 30, 1e-4};
+  uhm_gmres_opts o{50, 2000, 30, 1e-4, 0};
   if (opts) o = *opts;
-  if (o.restart < 1 || o.max_iterations < 1 || o.max_refinements < 1 || !(o.inner_tol > 0.0) || o.inner_tol >= 1.0)
+  if (o.restart < 1 || o.max_iterations < 1 || o.max_refinements < 1 || !(o.inner_tol > 0.0) || o.inner_tol >= 1.0 ||
+      o.inner_cycles < 0)
     return fail(UHM_EINVAL, "bad GMRES options");
   std::unique_ptr<uhm_krylov> K(new (std::nothrow) uhm_krylov);
   if (!K) return fail(UHM_ENOMEM, "host allocation");
