@@ -166,6 +166,9 @@ typedef struct {
   int64_t elems_coupling_in; /* UHM_C128_FACTORED: elements of the S_{Y,b} factors, read by the
                                 first coupling step (elems_coupling counts the assembled S_b
                                 and the S_{X,b} factors); 0 for the other forms */
+  int64_t scratch_bytes;     /* complex128 single-RHS forms: device scratch of one product (the
+                                workspace uhm_matvec grows, the part of uhm_matvec_noalloc's
+                                array a call takes); 0 for the many-RHS forms */
 } uhm_op_info;
 
 /*
@@ -194,6 +197,28 @@ int uhm_upload_h(const uhm_host_hmatrix* h, uhm_storage storage, void* hip_strea
  */
 int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs,
                void* hip_stream);
+
+/*
+ * uhm_matvec for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  It computes exactly what
+ * uhm_matvec computes (the same kernels in the same order, so the results are bitwise
+ * equal) but takes its product scratch (the per-leaf and per-tile partial sums and the
+ * rank-space vectors) from one file-scope device array of 512 MiB that the library holds on
+ * every GPU it runs on until the process ends, instead of the operator's own workspace.  It
+ * calls no hipMalloc or hipFree and allocates nothing else.
+ *   - Complex128 single-RHS storage forms only (UHM_C128, UHM_C128_SYM, UHM_C128_FACTORED
+ *     and H-matrix uploads); the many-RHS forms return UHM_ENOTSUP.
+ *   - An operator whose scratch exceeds 512 MiB is rejected with UHM_EINVAL (the
+ *     symmetric N = 262144 sphere operator of leaf 64 needs about 0.3 GiB).
+ *   - Every call on one GPU shares that GPU's array: calls that overlap on one GPU (on
+ *     different streams, or from different threads) race and give wrong results.  Calls
+ *     ordered on one stream are safe.  The array keeps the last call's contents; every
+ *     entry a product reads is written earlier in the same product, so nothing needs
+ *     clearing.
+ * Arguments, layout and the other errors as uhm_matvec.
+ */
+int uhm_matvec_noalloc(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs,
+                       void* hip_stream);
 
 /* Options of uhm_solve_gmres; a NULL pointer selects the defaults in brackets. */
 typedef struct {

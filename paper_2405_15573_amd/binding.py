@@ -45,7 +45,8 @@ class OpInfo(ctypes.Structure):
     _fields_ = [("n", I64), ("kind", I32), ("storage", I32), ("nleaves", I32), ("elem_bytes", I32),
                 ("nadm", I64), ("nden", I64), ("elems_forward", I64), ("elems_coupling", I64),
                 ("elems_backward", I64), ("elems_near", I64), ("rank_space", I64), ("device_bytes", I64),
-                ("partial_coupling", I64), ("partial_near", I64), ("elems_coupling_in", I64)]
+                ("partial_coupling", I64), ("partial_near", I64), ("elems_coupling_in", I64),
+                ("scratch_bytes", I64)]
 
 
 class GmresOpts(ctypes.Structure):
@@ -73,7 +74,7 @@ BLOCK_DTYPE = np.dtype({"names": [f for f, _ in BlockDesc._fields_],
 
 KRYLOV_DONE, KRYLOV_PRODUCT_HIGH, KRYLOV_PRODUCT_LOW = 0, 1, 2
 
-EXPORTS = ("uhm_upload", "uhm_upload_h", "uhm_matvec", "uhm_solve_gmres", "uhm_krylov_create", "uhm_krylov_next",
+EXPORTS = ("uhm_upload", "uhm_upload_h", "uhm_matvec", "uhm_matvec_noalloc", "uhm_solve_gmres", "uhm_krylov_create", "uhm_krylov_next",
            "uhm_krylov_advance", "uhm_krylov_result", "uhm_krylov_free", "uhm_krylov_step",
            "uhm_batch_create", "uhm_batch_run",
            "uhm_batch_tune", "uhm_batch_capture", "uhm_batch_free", "uhm_op_info_get", "uhm_set_timing",
@@ -97,6 +98,8 @@ def load_library(path: str = LIB_PATH):
     lib.uhm_upload_h.restype = ctypes.c_int
     lib.uhm_matvec.argtypes = [P, P, I64, P, I64, I32, P]
     lib.uhm_matvec.restype = ctypes.c_int
+    lib.uhm_matvec_noalloc.argtypes = [P, P, I64, P, I64, I32, P]
+    lib.uhm_matvec_noalloc.restype = ctypes.c_int
     lib.uhm_solve_gmres.argtypes = [P, P, P, I64, P, I64, I32, ctypes.c_double, ctypes.POINTER(GmresOpts),
                                     ctypes.POINTER(GmresInfo), P]
     lib.uhm_solve_gmres.restype = ctypes.c_int
@@ -192,6 +195,12 @@ class DeviceOperator:
     def matvec(self, x, y=None, stream=None):
         """y = A x for a torch tensor x (n,) or (n, r) on the device; returns y."""
         return self._product("uhm_matvec", x, y, stream)
+
+    def matvec_noalloc(self, x, y=None, stream=None):
+        """y = A x through uhm_matvec_noalloc (no device allocation in the library; the
+        product scratch is the library's file-scope array).  Pass y to keep the call itself
+        free of allocations: without it this wrapper allocates y with torch."""
+        return self._product("uhm_matvec_noalloc", x, y, stream)
 
     def _product(self, entry, x, y, stream):
         import torch

@@ -28,6 +28,8 @@
 // host image, so device accesses stay inside the allocations by construction.
 #include "uhm_internal.h"
 
+#include <mutex>
+
 namespace uhm_detail {
 
 thread_local std::string g_err;
@@ -1707,10 +1709,41 @@ int uhm_upload_h(const uhm_host_hmatrix* h, uhm_storage storage, void* hip_strea
   return UHM_OK;
 }
 
-int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs, void* hip_stream) {
-  if (!op) return fail(UHM_EINVAL, "null operator");
-  if (nrhs < 0) return fail(UHM_EINVAL, "nrhs < 0");
-  if (nrhs == 0) return UHM_OK;
+}  // extern "C"
+
+namespace {
+
+// Scratch of the complex128 single-RHS product: per-leaf forward partials, the coupling
+// source vector, coupling partials, the rank-space result, and (symmetric storage) the
+// transposed coupling and near-field partials.  Every entry a kernel reads is written
+// earlier in the same product, so the contents at entry do not matter.
+struct Fp64Ws {
+  cd *p, *xh, *part, *yh, *tpart, *td;
+};
+
+// Element counts of the six scratch areas, in the order of Fp64Ws.
+void fp64_ws_counts(const uhm_op* op, int64_t cnt[6]) {
+  cnt[0] = op->p_len;
+  cnt[1] = std::max(op->nxh, op->nsrc);
+  cnt[2] = op->kind == 0 ? (int64_t)op->nctiles * kRowChunk : 0;
+  cnt[3] = op->kind == 0 ? op->nyh : 0;
+  cnt[4] = op->sym ? op->ttot : 0;
+  cnt[5] = op->sym ? op->tdtot : 0;
+}
+
+// Offsets of the six areas in one scratch array, each on a 256-byte boundary (16
+// complex128 elements); returns the total element count.
+int64_t fp64_ws_layout(const uhm_op* op, int64_t off[6]) {
+  int64_t cnt[6], tot = 0;
+  fp64_ws_counts(op, cnt);
+  for (int k = 0; k < 6; ++k) {
+    off[k] = tot;
+    tot += (cnt[k] + 15) / 16 * 16;
+  }
+  return tot;
+}
+
+int check_vectors(const uhm_op* op, const void* X, int64_t ldx, const void* Y, int64_t ldy, int32_t nrhs) {
   if (!X || !Y) return fail(UHM_EINVAL, "null vector pointer");
   if (ldx < op->n || ldy < op->n) return fail(UHM_EINVAL, "leading dimension smaller than n");
   const char* xb = static_cast<const char*>(X);
@@ -1718,10 +1751,81 @@ int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int
   const size_t es = is_c128(op->storage) ? sizeof(cd) : sizeof(float2);
   if (xb < yb + (size_t)((nrhs - 1) * ldy + op->n) * es && yb < xb + (size_t)((nrhs - 1) * ldx + op->n) * es)
     return fail(UHM_EINVAL, "X and Y overlap");
+  return UHM_OK;
+}
+
+int matvec_fp64(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs, hipStream_t s,
+                const Fp64Ws& w);
+
+// File-scope scratch of uhm_matvec_noalloc, one copy per GPU.  Host code uses the
+// device address that hipGetSymbolAddress returns for the current device (g_scratch_dev),
+// never the array's name, which is a host-side stand-in.
+constexpr int64_t kNoallocScratchBytes = int64_t(512) << 20;
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+int scratch_address(void** out) {
+  int dev = -1;
+  UHM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(UHM_ENOTSUP, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    UHM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(UHM_EHIP, "hipGetSymbolAddress returned a null scratch address");
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return UHM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs, void* hip_stream) {
+  if (!op) return fail(UHM_EINVAL, "null operator");
+  if (nrhs < 0) return fail(UHM_EINVAL, "nrhs < 0");
+  if (nrhs == 0) return UHM_OK;
+  int rc = check_vectors(op, X, ldx, Y, ldy, nrhs);
+  if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if (op->lp) return lowp_matvec(op, X, ldx, Y, ldy, nrhs, s);
-  int rc = grow_workspace(op);
+  if ((rc = grow_workspace(op))) return rc;
+  const Fp64Ws w{op->ws_p.p, op->ws_xh.p, op->ws_part.p, op->ws_yh.p, op->ws_tpart.p, op->ws_td.p};
+  return matvec_fp64(op, X, ldx, Y, ldy, nrhs, s, w);
+}
+
+int uhm_matvec_noalloc(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs,
+                       void* hip_stream) {
+  if (!op) return fail(UHM_EINVAL, "null operator");
+  if (nrhs < 0) return fail(UHM_EINVAL, "nrhs < 0");
+  if (op->lp) return fail(UHM_ENOTSUP, "uhm_matvec_noalloc takes the complex128 single-RHS storage forms only");
+  if (nrhs == 0) return UHM_OK;
+  int rc = check_vectors(op, X, ldx, Y, ldy, nrhs);
   if (rc) return rc;
+  int64_t off[6];
+  const int64_t tot = fp64_ws_layout(op, off);
+  if (tot * (int64_t)sizeof(cd) > kNoallocScratchBytes)
+    return fail(UHM_EINVAL, "operator needs " + std::to_string(tot * (int64_t)sizeof(cd)) +
+                                " B of product scratch, more than the " + std::to_string(kNoallocScratchBytes) +
+                                " B that uhm_matvec_noalloc holds");
+  void* base = nullptr;
+  if ((rc = scratch_address(&base))) return rc;
+  cd* b = static_cast<cd*>(base);
+  const Fp64Ws w{b + off[0], b + off[1], b + off[2], b + off[3], b + off[4], b + off[5]};
+  return matvec_fp64(op, X, ldx, Y, ldy, nrhs, static_cast<hipStream_t>(hip_stream), w);
+}
+
+}  // extern "C"
+
+namespace {
+
+int matvec_fp64(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs, hipStream_t s,
+                const Fp64Ws& w) {
   const int nl = op->nleaves;
   for (int32_t r = 0; r < nrhs; ++r) {
     const cd* x = static_cast<const cd*>(X) + (int64_t)r * ldx;
@@ -1732,48 +1836,48 @@ int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int
         hipLaunchKernelGGL(op->kind == 0 ? k_forward_tiles<0> : k_forward_tiles<1>,
                            dim3((unsigned)((op->nftiles + kFwdWaves - 1) / kFwdWaves)), dim3(64 * kFwdWaves), 0, s,
                            op->F.p, op->ftiles.p, op->nftiles, op->fwd_off.p, op->fwd_cols.p, op->leaf_pos.p,
-                           op->leaf_n.p, op->perm.p, x, op->poff.p, op->ws_p.p);
+                           op->leaf_n.p, op->perm.p, x, op->poff.p, w.p);
       }
       {
         ScopedTiming tm(op, s, K_REDUCE_FWD);
-        hipLaunchKernelGGL(op->kind == 0 ? k_reduce_segments<0> : k_reduce_segments<1>, dim3((unsigned)((op->nxh + 255) / 256)), dim3(256), 0, s, op->ws_p.p,
+        hipLaunchKernelGGL(op->kind == 0 ? k_reduce_segments<0> : k_reduce_segments<1>, dim3((unsigned)((op->nxh + 255) / 256)), dim3(256), 0, s, w.p,
                            op->poff.p, op->out_seg.p, op->seg_start.p, op->seg_leaf0.p, op->seg_nleaf.p, op->seg_col.p,
-                           op->nxh, op->ws_xh.p);
+                           op->nxh, w.xh);
       }
     }
     if (op->nfactiles > 0) {
       ScopedTiming tm(op, s, K_FACTOR_IN);
       hipLaunchKernelGGL(k_factor_in, dim3((unsigned)((op->nfactiles + kCoupWaves - 1) / kCoupWaves)),
-                         dim3(64 * kCoupWaves), 0, s, op->FY.p, op->factiles.p, op->nfactiles, op->ws_xh.p,
-                         op->ws_xh.p);
+                         dim3(64 * kCoupWaves), 0, s, op->FY.p, op->factiles.p, op->nfactiles, w.xh,
+                         w.xh);
     }
-    const cd* zsrc = op->ws_xh.p;
+    const cd* zsrc = w.xh;
     if (op->sym) {
       if (op->nyh > 0) {
         if (op->nctiles > 0) {
           ScopedTiming tm(op, s, K_SYM_COUPLING);
           hipLaunchKernelGGL(k_coupling_sym, dim3((unsigned)((op->nctiles + kCoupWaves - 1) / kCoupWaves)),
                              dim3(64 * kCoupWaves), 0, s, op->S.p, op->stiles.p, op->nctiles, op->csrc.p,
-                             op->ws_xh.p, op->ws_part.p, op->ws_tpart.p);
+                             w.xh, w.part, w.tpart);
         }
         {
           ScopedTiming tm(op, s, K_SYM_REDUCE);
-          hipLaunchKernelGGL(k_reduce_sym, dim3((unsigned)((op->nyh + 255) / 256)), dim3(256), 0, s, op->ws_part.p,
-                             op->ws_tpart.p, op->yh_grp.p, op->grp_start.p, op->grp_t0.p, op->grp_nt.p, op->grp_s0.p,
-                             op->grp_ns.p, op->tsrc.p, op->nyh, op->ws_yh.p);
+          hipLaunchKernelGGL(k_reduce_sym, dim3((unsigned)((op->nyh + 255) / 256)), dim3(256), 0, s, w.part,
+                             w.tpart, op->yh_grp.p, op->grp_start.p, op->grp_t0.p, op->grp_nt.p, op->grp_s0.p,
+                             op->grp_ns.p, op->tsrc.p, op->nyh, w.yh);
         }
-        zsrc = op->ws_yh.p;
+        zsrc = w.yh;
       }
       {
         ScopedTiming tm(op, s, K_SYM_BACKWARD);
         hipLaunchKernelGGL(k_backward_sym, dim3(nl), dim3(64 * kSymBwdWaves), 0, s, op->B.p, op->bwd_off.p,
                            op->bwd_cols.p, op->bwd_tcol.p, op->td_off.p, op->zoff.p, op->zmap.p, op->leaf_pos.p,
-                           op->leaf_n.p, op->perm.p, zsrc, x, y, op->ws_td.p, nl);
+                           op->leaf_n.p, op->perm.p, zsrc, x, y, w.td, nl);
       }
       if (op->tdtot > 0) {
         ScopedTiming tm(op, s, K_SYM_FINISH);
         hipLaunchKernelGGL(k_finish_sym, dim3(nl), dim3(64), 0, s, op->fin_off.p, op->fin_cnt.p, op->fsrc.p,
-                           op->leaf_pos.p, op->leaf_n.p, op->perm.p, op->ws_td.p, y);
+                           op->leaf_pos.p, op->leaf_n.p, op->perm.p, w.td, y);
       }
       continue;
     }
@@ -1781,16 +1885,16 @@ int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int
       {
         ScopedTiming tm(op, s, K_COUPLING);
         hipLaunchKernelGGL(k_coupling, dim3((unsigned)((op->nctiles + kCoupWaves - 1) / kCoupWaves)),
-                           dim3(64 * kCoupWaves), 0, s, op->S.p, op->ctiles.p, op->nctiles, op->cblk.p, op->ws_xh.p,
-                           op->ws_part.p);
+                           dim3(64 * kCoupWaves), 0, s, op->S.p, op->ctiles.p, op->nctiles, op->cblk.p, w.xh,
+                           w.part);
       }
       {
         ScopedTiming tm(op, s, K_REDUCE_COUP);
         hipLaunchKernelGGL(k_reduce_coupling, dim3((unsigned)((op->nyh + 255) / 256)), dim3(256), 0, s,
-                           op->ws_part.p, op->yh_grp.p, op->grp_start.p, op->grp_t0.p, op->grp_nt.p, op->nyh,
-                           op->ws_yh.p);
+                           w.part, op->yh_grp.p, op->grp_start.p, op->grp_t0.p, op->grp_nt.p, op->nyh,
+                           w.yh);
       }
-      zsrc = op->ws_yh.p;
+      zsrc = w.yh;
     }
     {
       ScopedTiming tm(op, s, K_BACKWARD);
@@ -1803,9 +1907,15 @@ int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int
   return UHM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 int uhm_op_info_get(const uhm_op* op, uhm_op_info* info) {
   if (!op || !info) return fail(UHM_EINVAL, "null argument");
   *info = op->info;
+  int64_t off[6];
+  info->scratch_bytes = op->lp ? 0 : fp64_ws_layout(op, off) * (int64_t)sizeof(cd);
   return UHM_OK;
 }
 
