@@ -66,18 +66,32 @@ def algorithmic_bytes(info: dict, n: int, nrhs: int = 1) -> dict:
     return out
 
 
-def time_products(torch, dop, x, y, steps, warmup, stream):
+def time_products(torch, dop, x, y, steps, warmup, stream, per_product=None):
+    """Mean wall time per product over `steps` products (synchronised before and after),
+    and per-kernel HIP-event times.  per_product: a dict that receives the HIP-event time
+    of every product (events on `stream` around each) as mean / min / p50 in ms."""
+    import numpy as np
     for _ in range(warmup):
         dop.matvec(x, y, stream=stream)
     torch.cuda.synchronize()
     dop.set_timing(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)] \
+        if per_product is not None else None
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
+        if ev:
+            ev[k][0].record(stream)
         dop.matvec(x, y, stream=stream)
+        if ev:
+            ev[k][1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kt = dop.kernel_times()
     dop.set_timing(False)
+    if ev:
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        per_product.update(mean_ms=float(ms.mean()), min_ms=float(ms.min()), p50_ms=float(np.median(ms)),
+                           max_ms=float(ms.max()), count=int(ms.size))
     return (t1 - t0) / steps, {k: (v[0] / max(1, v[1]), v[1]) for k, v in kt.items() if v[1] > 0}
 
 
@@ -482,7 +496,7 @@ def run_serving(args):
     import torch
 
     from paper_2405_15573_amd import builder, inputs
-    from paper_2405_15573_amd.serving import Request, Server
+    from paper_2405_15573_amd.serving import Request, Server, solve_footprint
     # no ellipsoids: GMRES(50) stalls near 1e-2 on the ellipsoid operators at kappa*h = 0.6,
     # in FP64 as in mixed precision, so their requests would only measure the iteration cap
     pop = mixed_population(16, 4096, args.serve_max_n, args.seed + 1, surf=("sphere", "cube"))
@@ -490,12 +504,18 @@ def run_serving(args):
     t0 = time.perf_counter()
     for k, (surf, n) in enumerate(pop):
         cloud = inputs.make_cloud(surf, n, seed=args.seed + k)
-        hosts.append(builder.build_operator(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6))
+        hosts.append(builder.build_operator(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6,
+                                            construct=args.construct))
         log(f"  op {k}: {surf} N={cloud.n} built {hosts[-1].timings['total']:.1f}s")
     log(f"population built in {time.perf_counter() - t0:.1f} s")
-    srv = Server(hosts, low_storage=args.serve_storage, inner_tol=1e-3, max_iterations=4000)
+    srv = Server(hosts, low_storage=args.serve_storage, inner_tol=1e-3, max_iterations=args.serve_maxit,
+                 inner_cycles=args.inner_cycles)
+    budget = srv.admission.budget
     results = {}
-    for rate in [float(v) for v in args.rates.split(",")]:
+    runs = [(float(v), None) for v in args.rates.split(",")]
+    if args.serve_budget_mb > 0:   # the highest rate again, under a small HBM budget
+        runs.append((max(r for r, _ in runs), int(args.serve_budget_mb) << 20))
+    for rate, cap in runs:
         rng = np.random.default_rng([args.seed, 5, int(rate)])
         t = np.cumsum(rng.exponential(1.0 / rate, size=args.requests))
         reqs = []
@@ -506,20 +526,33 @@ def run_serving(args):
             b = inputs.make_rhs(hosts[op].n, r, seed=int(rate) * 100000 + i)
             reqs.append(Request(rid=i, op=op, b=torch.from_numpy(np.ascontiguousarray(b.T)).to("cuda").t(), tol=tol,
                                 arrival=float(t[i])))
-        log(f"rate {rate}/s: {args.requests} requests")
+        srv.admission.budget = cap if cap is not None else budget
+        srv.step_s, srv.steps, srv.step_solves = 0.0, 0, 0
+        key = str(int(rate)) + ("" if cap is None else f"_budget{args.serve_budget_mb}MB")
+        log(f"rate {rate}/s: {args.requests} requests, HBM budget {srv.admission.budget / 2**20:.0f} MB")
         done = srv.serve(reqs, log=log)
-        results[str(int(rate))] = Server.report(done)
-        log(f"  {results[str(int(rate))]}")
+        rep = Server.report(done)
+        rep.update(step_ms_mean=1e3 * srv.step_s / max(1, srv.steps), steps=srv.steps,
+                   solves_per_step_mean=srv.step_solves / max(1, srv.steps),
+                   capped_fraction=1.0 - rep.get("converged", 0) / max(1, rep.get("completed", 1)),
+                   hbm_budget_bytes=srv.admission.budget,
+                   largest_request_bytes=max(srv.footprint(q) for q in reqs))
+        results[key] = rep
+        log(f"  {rep}")
         del reqs, done
-    worst = max(results.values(), key=lambda v: v.get("p99_s", 0.0))
+    srv.admission.budget = budget
+    worst = max((v for k, v in results.items() if "budget" not in k), key=lambda v: v.get("p99_converged_s") or 0.0)
     line = {
-        "metric": "p99 GMRES solve latency (served, continuous batching)", "value": worst.get("p99_s"),
-        "unit": "s", "n_gpus": 1, "steps": args.requests, "warmup": 0, "ms_per_step": None,
+        "metric": "p99 GMRES solve latency over converged solves (served, continuous batching)",
+        "value": worst.get("p99_converged_s"),
+        "unit": "s", "n_gpus": 1, "steps": args.requests, "warmup": 0, "ms_per_step": worst.get("step_ms_mean"),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"16 resident operators (sphere, cube), N log-uniform in [4096, {args.serve_max_n}], GMRES-IR "
-                               f"({args.serve_storage} inner, FP64 residual), Poisson arrivals {args.rates}/s, "
-                               f"{args.requests} requests per rate, 1-8 RHS, tol 1e-6 or 1e-8",
+        "config": {"workload": f"16 resident operators (sphere, cube), N log-uniform in [4096, {args.serve_max_n}], "
+                               f"GMRES-IR ({args.serve_storage} inner, FP64 residual, {args.inner_cycles} inner "
+                               f"cycle(s) per refinement), Poisson arrivals {args.rates}/s, {args.requests} requests "
+                               f"per rate, 1-8 RHS, tol 1e-6 or 1e-8, iteration cap {args.serve_maxit}",
                    "operators": [(p[0], int(h.n)) for p, h in zip(pop, hosts)]},
+        "capped_fraction_at_worst_rate": worst.get("capped_fraction"),
         "per_rate": results,
     }
     print(json.dumps(line), flush=True)
@@ -533,6 +566,9 @@ def main():
     ap.add_argument("--n", type=int, default=262144)
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seeds", type=str, default="",
+                    help="headline: also time the headline product on the operators of these seeds "
+                         "(e.g. 0,1,2; each adds one operator build)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-h", action="store_true")
@@ -569,9 +605,12 @@ def main():
     ap.add_argument("--rates", type=str, default="50,100,200,400")
     ap.add_argument("--requests", type=int, default=200, help="requests per arrival rate (serving)")
     ap.add_argument("--max-n", type=int, default=65536, help="largest operator of the batched mix")
-    ap.add_argument("--serve-max-n", type=int, default=16384,
-                    help="largest operator of the serving mix (GMRES(50) on larger operators of these clouds "
-                         "needs thousands of iterations)")
+    ap.add_argument("--serve-max-n", type=int, default=65536,
+                    help="largest operator of the serving mix (GMRES(50) on larger spheres of this wavenumber "
+                         "does not reach 1e-8 in thousands of iterations)")
+    ap.add_argument("--serve-maxit", type=int, default=6000, help="iteration cap of a served solve")
+    ap.add_argument("--serve-budget-mb", type=int, default=2048,
+                    help="serving: run the highest rate once more under this HBM budget (0: skip)")
     ap.add_argument("--batch-storage", choices=("c64", "c64fact", "bf16pair", "bf16pairfact"), default="c64fact",
                     help="storage of the operators of the batched mode")
     ap.add_argument("--serve-storage", choices=("c64", "c64fact", "bf16pair", "bf16pairfact"), default="c64fact",
@@ -649,7 +688,8 @@ def main():
     y = torch.empty_like(x)
     torch.cuda.synchronize()
 
-    t_uh, k_uh = time_products(torch, duh, x, y, args.steps, args.warmup, stream)
+    pp_uh = {}
+    t_uh, k_uh = time_products(torch, duh, x, y, args.steps, args.warmup, stream, per_product=pp_uh)
     y_uh = y.cpu().numpy()
     ab = algorithmic_bytes(info, cloud.n)
     log(f"UH MVP {t_uh * 1e3:.3f} ms; kernels " + json.dumps({k: round(v[0], 4) for k, v in k_uh.items()}))
@@ -677,7 +717,8 @@ def main():
         log(f"symmetric upload {time.perf_counter() - ts:.1f} s")
         sinfo = dsym.info()
         ys = torch.empty_like(x)
-        t_sy, k_sy = time_products(torch, dsym, x, ys, args.steps, args.warmup, stream)
+        pp_sy = {}
+        t_sy, k_sy = time_products(torch, dsym, x, ys, args.steps, args.warmup, stream, per_product=pp_sy)
         y_sy = ys.cpu().numpy()
         abs_ = algorithmic_bytes(sinfo, cloud.n)
         tp = time.perf_counter()
@@ -685,6 +726,7 @@ def main():
         par_s = float(np.linalg.norm(y_sy[users_s] - ref_s[:, 0]) / np.linalg.norm(ref_s[:, 0]))
         log(f"symmetric sampled parity {par_s:.3e} in {time.perf_counter() - tp:.1f} s")
         sym = {"ms_per_mvp": t_sy * 1e3, "mvps_per_s": 1.0 / t_sy, "gbs": abs_["total"] / t_sy / 1e9,
+               "per_product_ms": pp_sy, "scratch_bytes": sinfo["scratch_bytes"],
                "vs_general_speedup": t_uh / t_sy,
                "bytes": abs_["total"], "bytes_per_kernel": abs_,
                "kernels_ms": {k: v[0] for k, v in k_sy.items()},
@@ -787,24 +829,72 @@ def main():
 
     cpu = None
     if not args.no_cpu:
+        import numpy as _np
         ncores = uniform.max_threads()
-        tc = time.perf_counter()
-        uniform.alg6(vars(op), x_np)  # warm-up (first touch of the operator pages)
-        first = time.perf_counter() - tc
-        reps = max(1, min(10, int(args.cpu_seconds / max(first, 1e-3))))
-        tc = time.perf_counter()
-        for _ in range(reps):
-            uniform.alg6(vars(op), x_np)
-        tcpu = (time.perf_counter() - tc) / reps
+
+        def cpu_times(fn, budget):
+            """Three warm-ups (the first touches the operator pages), then up to 10 timed
+            products within the budget; per-product seconds."""
+            tw = time.perf_counter()
+            fn()
+            first = time.perf_counter() - tw
+            fn()
+            fn()
+            reps = max(3, min(10, int(budget / max(first, 1e-3))))
+            ts = []
+            for _ in range(reps):
+                tc = time.perf_counter()
+                fn()
+                ts.append(time.perf_counter() - tc)
+            return _np.array(ts)
+
+        t6 = cpu_times(lambda: uniform.alg6(vars(op), x_np), args.cpu_seconds)
+        t5 = cpu_times(lambda: uniform.alg5(vars(op), x_np), args.cpu_seconds / 2)
+        tcpu = float(t6.mean())
         cpu = {"value": 1.0 / tcpu, "unit": "MVPs/s", "cores": ncores, "kind": "oracle",
-               "sample": f"{reps} full products of the same N={cloud.n} operator with the C Algorithm 6 "
-                         f"oracle (OpenMP, {ncores} threads) after one warm-up",
-               "gbs": ab["total"] / tcpu / 1e9, "ms_per_mvp": tcpu * 1e3}
-        log(f"CPU oracle {tcpu * 1e3:.1f} ms per MVP on {ncores} threads")
+               "sample": f"{t6.size} full products of the same N={cloud.n} operator with the C Algorithm 6 "
+                         f"oracle (OpenMP, {ncores} threads) after three warm-ups",
+               "gbs": ab["total"] / tcpu / 1e9, "ms_per_mvp": tcpu * 1e3,
+               "ms_per_mvp_min": float(t6.min()) * 1e3, "ms_per_mvp_p50": float(_np.median(t6)) * 1e3,
+               "h_mvp_alg5": {"ms_per_mvp": float(t5.mean()) * 1e3, "ms_per_mvp_min": float(t5.min()) * 1e3,
+                              "ms_per_mvp_p50": float(_np.median(t5)) * 1e3, "products": int(t5.size),
+                              "gbs": (abh["total"] / float(t5.mean()) / 1e9) if res_h else None},
+               "h_over_uh": float(t5.mean()) / tcpu}
+        log(f"CPU oracle {tcpu * 1e3:.1f} ms per MVP (Alg. 6), H-MVP {t5.mean() * 1e3:.1f} ms (Alg. 5) "
+            f"on {ncores} threads")
+
+    # further operator instances (the paper's protocol averages three): the headline product
+    # on the operators of the other seeds, built and timed the same way
+    per_seed = None
+    extra = [int(v) for v in args.seeds.split(",") if v.strip() and int(v) != args.seed]
+    if extra:
+        import numpy as _np
+        per_seed = {str(args.seed): pp_sy if sym is not None else pp_uh}
+        for sd in extra:
+            cl = inputs.make_cloud("sphere", args.n, seed=sd)
+            tb = time.perf_counter()
+            op_s = builder.build_operator(cl, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6,
+                                          construct=args.construct, compress_on=args.compress)
+            log(f"seed {sd}: built in {time.perf_counter() - tb:.1f} s")
+            img = builder.symmetric_image(op_s) if sym is not None else op_s
+            d_s = binding.upload(img, "c128sym" if sym is not None else "c128", stream=stream)
+            xs = torch.from_numpy(inputs.make_rhs(cl.n, 1, seed=sd)[:, 0]).to("cuda")
+            ys_ = torch.empty_like(xs)
+            pp = {}
+            t_s, _ = time_products(torch, d_s, xs, ys_, args.steps, args.warmup, stream, per_product=pp)
+            pp["wall_ms_per_mvp"] = t_s * 1e3
+            per_seed[str(sd)] = pp
+            log(f"seed {sd}: {t_s * 1e3:.3f} ms per MVP, events {json.dumps(pp)}")
+            d_s.free()
+            del op_s, img, xs, ys_
+        means = _np.array([v["mean_ms"] for v in per_seed.values()])
+        per_seed["over_seeds"] = {"mean_ms": float(means.mean()), "min_ms": float(min(v["min_ms"] for v in per_seed.values())),
+                                  "p50_of_means_ms": float(_np.median(means)), "seeds": [args.seed] + extra}
 
     # headline: the symmetric storage the paper's experiments use (Remark 4.4, section 6.1)
     # when it was run, else the general storage; both are reported
     general = {"ms_per_mvp": t_uh * 1e3, "mvps_per_s": 1.0 / t_uh, "gbs": ab["total"] / t_uh / 1e9,
+               "per_product_ms": pp_uh, "scratch_bytes": info["scratch_bytes"],
                "bytes": ab["total"], "kernels_ms": {k: v[0] for k, v in k_uh.items()},
                "parity_sampled_rel_err": parity}
     if sym is not None:
@@ -847,6 +937,8 @@ def main():
         "uh_speedup_over_h": (res_h["ms_per_mvp"] / (t_uh * 1e3)) if res_h else None,
         "uh_symmetric_speedup_over_h": (res_h["ms_per_mvp"] / (t_sy * 1e3)) if (res_h and sym) else None,
         "parity_sampled_rel_err": par_hd,
+        "per_product_ms": pp_sy if sym is not None else pp_uh,
+        "per_seed": per_seed,
         "operator": {k: st[k] for k in ("nadm", "nden", "c_sp", "l_max", "k_max", "bytes_uh_c128", "bytes_h_c128")},
         "build": {"construct": args.construct, "compress": args.compress, **{k: round(v, 3) for k, v in op.timings.items()}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

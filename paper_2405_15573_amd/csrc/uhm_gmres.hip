@@ -11,8 +11,11 @@
 // Kaufman and Stewart, 1976); the other columns skip the second pass.  Partial sums are
 // per wavefront over fixed row ranges and are reduced in a fixed order (deterministic).
 // The (m+1) x m Hessenberg matrices, the Givens rotations and the small triangular solves
-// are done on the host in FP64 from the few numbers each step produces, after one
-// synchronisation per step.
+// stay on the device in FP64 (one thread per column): a step's coefficients never leave the
+// GPU, and the host reads back only the number of columns still running.  A single solve
+// reads that count one step late, so the host never waits for the step it has just issued;
+// when the count says that every column stopped, at most one further step has been issued,
+// on columns that are all inactive, and it changes nothing.
 //
 // With an inner operator (complex64 or bf16 pairs) the solve is iterative refinement: the
 // residual r = b - A x is formed with the FP64 operator, an inner GMRES(m) whose products
@@ -214,10 +217,14 @@ __global__ __launch_bounds__(kGB) void k_a_update(const cd* __restrict__ V, int6
   a_update_body(blockIdx.x * (kGB / 64) + (threadIdx.x >> 6), blockIdx.y, V, vstride, nvec, h, w, n, r, nsub, need, w2);
 }
 
-// need[c] = (||w after the projection||^2 < ||w before||^2 / 2)
+// need[c] = (||w after the projection||^2 < ||w before||^2 / 2) for running columns
 __device__ __forceinline__ void a_decide_body(int c, const double* __restrict__ w0, const double* __restrict__ w1,
-                                              int nsub, int r, int* __restrict__ need) {
+                                              int nsub, int r, const int* __restrict__ act, int* __restrict__ need) {
   if (c >= r) return;
+  if (!act[c]) {
+    need[c] = 0;
+    return;
+  }
   double s0 = 0.0, s1 = 0.0;
   for (int sb = 0; sb < nsub; ++sb) {
     s0 += w0[(int64_t)c * nsub + sb];
@@ -226,35 +233,156 @@ __device__ __forceinline__ void a_decide_body(int c, const double* __restrict__ 
   need[c] = s1 < 0.5 * s0;
 }
 __global__ void k_a_decide(const double* __restrict__ w0, const double* __restrict__ w1, int nsub, int r,
-                           int* __restrict__ need) {
-  a_decide_body(blockIdx.x * blockDim.x + threadIdx.x, w0, w1, nsub, r, need);
+                           const int* __restrict__ act, int* __restrict__ need) {
+  a_decide_body(blockIdx.x * blockDim.x + threadIdx.x, w0, w1, nsub, r, act, need);
 }
 
 // out[c] = (||w||, need[c]) with ||w|| from the last pass the column ran
 __device__ __forceinline__ void a_final_body(int c, const double* __restrict__ w1, const double* __restrict__ w2,
-                                             const int* __restrict__ need, int nsub, int r, cd* __restrict__ out) {
+                                             const int* __restrict__ act, const int* __restrict__ need, int nsub,
+                                             int r, cd* __restrict__ out) {
   if (c >= r) return;
+  if (!act[c]) {
+    out[c] = make_double2(0.0, 0.0);
+    return;
+  }
   const double* src = need[c] ? w2 : w1;
   double s = 0.0;
   for (int sb = 0; sb < nsub; ++sb) s += src[(int64_t)c * nsub + sb];
   out[c] = make_double2(sqrt(s), (double)need[c]);
 }
-__global__ void k_a_final(const double* __restrict__ w1, const double* __restrict__ w2, const int* __restrict__ need,
-                          int nsub, int r, cd* __restrict__ out) {
-  a_final_body(blockIdx.x * blockDim.x + threadIdx.x, w1, w2, need, nsub, r, out);
+__global__ void k_a_final(const double* __restrict__ w1, const double* __restrict__ w2, const int* __restrict__ act,
+                          const int* __restrict__ need, int nsub, int r, cd* __restrict__ out) {
+  a_final_body(blockIdx.x * blockDim.x + threadIdx.x, w1, w2, act, need, nsub, r, out);
+}
+
+// ---- the least-squares problem of a cycle, on the device (one thread per column)
+// State of one solve's current cycle, column c: the rotated Hessenberg columns
+// H[(c m + j)(m+1) + i], the rotated right-hand side g[c (m+1) + i], the rotations
+// cs[c m + i], sn[c m + i], active[c] (the column still iterates), jc[c] (steps taken),
+// rtol[c] (residual estimate at which it stops), scale[c].x = 1 / ||w|| of the last step.
+struct Lsq {
+  cd *H, *g, *cs, *sn, *scale, *y;
+  int *active, *jc;
+  const int* need;
+  const double* rtol;
+  unsigned long long* reorth;  // column-steps that ran the second Gram-Schmidt pass
+  int m, r;
+};
+
+__device__ __forceinline__ cd c_mul(cd a, cd b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+// conj(a) b
+__device__ __forceinline__ cd c_cmul(cd a, cd b) { return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }
+__device__ __forceinline__ cd c_add(cd a, cd b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cd c_sub(cd a, cd b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// Step j of column c: the new Hessenberg column from the coefficients of both Gram-Schmidt
+// passes (h1 + h2, i <= j) and the norm of w (tail[c].x), the previous rotations applied, a
+// new rotation that annihilates the subdiagonal entry, g updated; the column stops once its
+// residual estimate |g_{j+1}| reaches rtol[c] or w vanishes.
+__device__ __forceinline__ void givens_body(int c, int j, const cd* __restrict__ h1, const cd* __restrict__ h2,
+                                            const cd* __restrict__ tail, const Lsq& q) {
+  if (c >= q.r) return;
+  if (!q.active[c]) {
+    q.scale[c] = make_double2(0.0, 0.0);
+    return;
+  }
+  const int m = q.m, r = q.r;
+  const double hn = tail[c].x;
+  if (q.need[c]) atomicAdd(q.reorth, 1ull);
+  q.scale[c] = make_double2(hn > 1e-300 ? 1.0 / hn : 0.0, 0.0);
+  cd* col = q.H + ((int64_t)c * m + j) * (m + 1);
+  for (int i = 0; i <= j; ++i) col[i] = c_add(h1[(int64_t)i * r + c], h2[(int64_t)i * r + c]);
+  col[j + 1] = make_double2(hn, 0.0);
+  const cd* csc = q.cs + (int64_t)c * m;
+  const cd* snc = q.sn + (int64_t)c * m;
+  for (int i = 0; i < j; ++i) {
+    const cd a = col[i], b = col[i + 1], ci = csc[i], si = snc[i];
+    col[i] = c_add(c_cmul(ci, a), c_cmul(si, b));
+    col[i + 1] = c_sub(c_mul(ci, b), c_mul(si, a));
+  }
+  const cd a = col[j], b = col[j + 1];
+  const double den = sqrt((a.x * a.x + a.y * a.y) + (b.x * b.x + b.y * b.y));
+  cd cj = make_double2(1.0, 0.0), sj = make_double2(0.0, 0.0);
+  if (den > 0.0) {
+    cj = make_double2(a.x / den, a.y / den);
+    sj = make_double2(b.x / den, b.y / den);
+  }
+  q.cs[(int64_t)c * m + j] = cj;
+  q.sn[(int64_t)c * m + j] = sj;
+  col[j] = c_add(c_cmul(cj, a), c_cmul(sj, b));
+  col[j + 1] = make_double2(0.0, 0.0);
+  cd* gc = q.g + (int64_t)c * (m + 1);
+  const cd gj = gc[j];
+  gc[j] = c_cmul(cj, gj);
+  const cd sg = c_mul(sj, gj);
+  gc[j + 1] = make_double2(-sg.x, -sg.y);
+  q.jc[c] = j + 1;
+  if (hypot(gc[j + 1].x, gc[j + 1].y) <= q.rtol[c] || hn <= 1e-300) q.active[c] = 0;
+}
+__global__ void k_a_givens(int j, const cd* __restrict__ h1, const cd* __restrict__ h2, const cd* __restrict__ tail,
+                           Lsq q) {
+  givens_body(blockIdx.x * blockDim.x + threadIdx.x, j, h1, h2, tail, q);
+}
+
+// count[0] = number of running columns (one wavefront)
+__global__ __launch_bounds__(64) void k_a_count(const int* __restrict__ active, int r, int* __restrict__ count) {
+  int v = 0;
+  for (int c = threadIdx.x; c < r; c += 64) v += active[c] != 0;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (threadIdx.x == 0) count[0] = v;
+}
+
+// End of a cycle: y_c = R_c^{-1} g_c by back substitution over the jc[c] steps of column c,
+// written to y[i r + c] for i < jm (zero beyond jc[c]).
+__device__ __forceinline__ void lsq_body(int c, int jm, const Lsq& q) {
+  if (c >= q.r) return;
+  const int m = q.m, r = q.r, k = q.jc[c];
+  const cd* Hc = q.H + (int64_t)c * m * (m + 1);
+  const cd* gc = q.g + (int64_t)c * (m + 1);
+  for (int i = jm - 1; i >= k; --i) q.y[(int64_t)i * r + c] = make_double2(0.0, 0.0);
+  for (int i = k - 1; i >= 0; --i) {
+    cd acc = gc[i];
+    for (int t = i + 1; t < k; ++t) acc = c_sub(acc, c_mul(Hc[(int64_t)t * (m + 1) + i], q.y[(int64_t)t * r + c]));
+    const cd dg = Hc[(int64_t)i * (m + 1) + i];
+    const double dd = dg.x * dg.x + dg.y * dg.y;
+    q.y[(int64_t)i * r + c] =
+        dd > 0.0 ? make_double2((acc.x * dg.x + acc.y * dg.y) / dd, (acc.y * dg.x - acc.x * dg.y) / dd)
+                 : make_double2(0.0, 0.0);
+  }
+}
+__global__ void k_a_lsq(int jm, Lsq q) { lsq_body(blockIdx.x * blockDim.x + threadIdx.x, jm, q); }
+
+// Start of a cycle from the residual norms beta: g = beta e_1, no steps, the column runs
+// unless beta <= rtol[c]; sc0[c] = 1 / beta (0 when beta = 0) scales the first vector.
+__device__ __forceinline__ void cycle_init_body(int c, const double* __restrict__ beta, const Lsq& q,
+                                                double* __restrict__ sc0) {
+  if (c >= q.r) return;
+  const double b = beta[c];
+  cd* gc = q.g + (int64_t)c * (q.m + 1);
+  gc[0] = make_double2(b, 0.0);
+  for (int i = 1; i <= q.m; ++i) gc[i] = make_double2(0.0, 0.0);
+  q.jc[c] = 0;
+  q.active[c] = !(b <= q.rtol[c]);
+  sc0[c] = b > 0.0 ? 1.0 / b : 0.0;
+}
+__global__ void k_a_cycle_init(const double* __restrict__ beta, Lsq q, double* __restrict__ sc0) {
+  cycle_init_body(blockIdx.x * blockDim.x + threadIdx.x, beta, q, sc0);
 }
 
 // ---- the same Arnoldi step for many solves in one launch per kernel
 // One solve's buffers: h1 = hbuf, h2 = hbuf + hoff, tail = hbuf + 2 hoff; partial norms
-// n0 = nrm, n1 = nrm + r nsub, n2 = nrm + 2 r nsub.
+// n0 = nrm, n1 = nrm + r nsub, n2 = nrm + 2 r nsub.  The first pass skips the columns that
+// have stopped (q.active), the second runs on the columns that need it.
 struct ArnDesc {
   const cd* V;
   cd *w, *part, *hbuf, *vnext;  // vnext: V_{j+1}
   double* nrm;
   int* need;
-  int64_t n, vstride, hoff, hsz;  // hsz: entries of hbuf copied back to the host
-  int64_t goff, soff;             // offsets of the solve's h in the gather area, of its scales
-  int32_t r, nvec, nsub, pad;
+  int* count;  // the solve's running-column count, in the area copied to the host
+  Lsq q;
+  int64_t n, vstride, hoff;
+  int32_t r, nvec, nsub, j;
 };
 
 // work item of the row kernels: (solve, column, block of kGB/64 row ranges)
@@ -262,7 +390,7 @@ __global__ __launch_bounds__(kGB) void k_ab_dots(const ArnDesc* __restrict__ D, 
   const int4 wk = work[blockIdx.x];
   const ArnDesc& d = D[wk.x];
   const int sb = wk.z * (kGB / 64) + (threadIdx.x >> 6);
-  a_dots_body(sb, wk.y, d.V, d.vstride, d.nvec, d.w, d.n, d.r, d.nsub, pass ? d.need : nullptr, d.part,
+  a_dots_body(sb, wk.y, d.V, d.vstride, d.nvec, d.w, d.n, d.r, d.nsub, pass ? d.need : d.q.active, d.part,
               pass ? nullptr : d.nrm);
 }
 __global__ __launch_bounds__(kGB) void k_ab_update(const ArnDesc* __restrict__ D, const int4* __restrict__ work, int pass) {
@@ -271,31 +399,22 @@ __global__ __launch_bounds__(kGB) void k_ab_update(const ArnDesc* __restrict__ D
   const int sb = wk.z * (kGB / 64) + (threadIdx.x >> 6);
   const int64_t rn = (int64_t)d.r * d.nsub;
   a_update_body(sb, wk.y, d.V, d.vstride, d.nvec, d.hbuf + (pass ? d.hoff : 0), d.w, d.n, d.r, d.nsub,
-                pass ? d.need : nullptr, d.nrm + (pass ? 2 : 1) * rn);
+                pass ? d.need : d.q.active, d.nrm + (pass ? 2 : 1) * rn);
 }
 // work item: (solve, block of kGB entries of h)
 __global__ __launch_bounds__(kGB) void k_ab_reduce(const ArnDesc* __restrict__ D, const int2* __restrict__ work, int pass) {
   const int2 wk = work[blockIdx.x];
   const ArnDesc& d = D[wk.x];
-  a_reduce_body((int64_t)wk.y * kGB + threadIdx.x, d.part, d.nsub, (int64_t)d.nvec * d.r, d.r, pass ? d.need : nullptr,
-                d.hbuf + (pass ? d.hoff : 0));
+  a_reduce_body((int64_t)wk.y * kGB + threadIdx.x, d.part, d.nsub, (int64_t)d.nvec * d.r, d.r,
+                pass ? d.need : d.q.active, d.hbuf + (pass ? d.hoff : 0));
 }
-// gather[d.goff + e] = d.hbuf[e], e < d.hsz; work item: (solve, block of kGB entries)
-__global__ __launch_bounds__(kGB) void k_ab_gather(const ArnDesc* __restrict__ D, const int2* __restrict__ work,
-                                                   cd* __restrict__ gather) {
-  const int2 wk = work[blockIdx.x];
-  const ArnDesc& d = D[wk.x];
-  const int64_t e = (int64_t)wk.y * kGB + threadIdx.x;
-  if (e < d.hsz) gather[d.goff + e] = d.hbuf[e];
-}
-// d.vnext[:, c] = d.w[:, c] * scale[d.soff + c].x; work item: (solve, block of kGB elements)
-__global__ __launch_bounds__(kGB) void k_ab_scale(const ArnDesc* __restrict__ D, const int2* __restrict__ work,
-                                                  const cd* __restrict__ scale) {
+// d.vnext[:, c] = d.w[:, c] * d.q.scale[c].x; work item: (solve, block of kGB elements)
+__global__ __launch_bounds__(kGB) void k_ab_scale(const ArnDesc* __restrict__ D, const int2* __restrict__ work) {
   const int2 wk = work[blockIdx.x];
   const ArnDesc& d = D[wk.x];
   const int64_t q = (int64_t)wk.y * kGB + threadIdx.x;
   if (q >= d.n * d.r) return;
-  const double sc = scale[d.soff + q / d.n].x;
+  const double sc = d.q.scale[q / d.n].x;
   const cd v = d.w[q];
   d.vnext[q] = make_double2(v.x * sc, v.y * sc);
 }
@@ -305,13 +424,27 @@ __global__ __launch_bounds__(64) void k_ab_decide(const ArnDesc* __restrict__ D,
   const int2 wk = work[blockIdx.x];
   const ArnDesc& d = D[wk.x];
   const int64_t rn = (int64_t)d.r * d.nsub;
-  a_decide_body(wk.y * 64 + threadIdx.x, d.nrm, d.nrm + rn, d.nsub, d.r, d.need);
+  a_decide_body(wk.y * 64 + threadIdx.x, d.nrm, d.nrm + rn, d.nsub, d.r, d.q.active, d.need);
 }
 __global__ __launch_bounds__(64) void k_ab_final(const ArnDesc* __restrict__ D, const int2* __restrict__ work) {
   const int2 wk = work[blockIdx.x];
   const ArnDesc& d = D[wk.x];
   const int64_t rn = (int64_t)d.r * d.nsub;
-  a_final_body(wk.y * 64 + threadIdx.x, d.nrm + rn, d.nrm + 2 * rn, d.need, d.nsub, d.r, d.hbuf + 2 * d.hoff);
+  a_final_body(wk.y * 64 + threadIdx.x, d.nrm + rn, d.nrm + 2 * rn, d.q.active, d.need, d.nsub, d.r,
+               d.hbuf + 2 * d.hoff);
+}
+__global__ __launch_bounds__(64) void k_ab_givens(const ArnDesc* __restrict__ D, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const ArnDesc& d = D[wk.x];
+  givens_body(wk.y * 64 + threadIdx.x, d.j, d.hbuf, d.hbuf + d.hoff, d.hbuf + 2 * d.hoff, d.q);
+}
+// work item: one solve; its running-column count into d.count
+__global__ __launch_bounds__(64) void k_ab_count(const ArnDesc* __restrict__ D) {
+  const ArnDesc& d = D[blockIdx.x];
+  int v = 0;
+  for (int c = threadIdx.x; c < d.r; c += 64) v += d.q.active[c] != 0;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (threadIdx.x == 0) d.count[0] = v;
 }
 
 // nrm_out[c] = sqrt(sum_ch nrm[c * nch + ch])
@@ -426,14 +559,15 @@ unsigned nblk(int64_t q) { return (unsigned)((q + kGB - 1) / kGB); }
 using C = std::complex<double>;
 using Clock = std::chrono::steady_clock;
 
-// Pinned host memory for the per-step device-to-host copies.
-struct PinnedHost {
-  cd* p = nullptr;
+// Pinned host memory for the small host <-> device copies of the control values.
+template <class T>
+struct Pinned {
+  T* p = nullptr;
   int alloc(int64_t count) {
-    UHM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), sizeof(cd) * (size_t)count, hipHostMallocDefault));
+    UHM_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), sizeof(T) * (size_t)count, hipHostMallocDefault));
     return UHM_OK;
   }
-  ~PinnedHost() {
+  ~Pinned() {
     if (p) (void)hipHostFree(p);
   }
 };
@@ -442,17 +576,27 @@ struct Work {
   int64_t n = 0;
   int r = 0, m = 0, nch = 0, nsub = 0;
   DevArray<cd> V, w, t, d, part, hbuf, ybuf;
-  DevArray<double> nrm, nrm_out;
+  DevArray<double> nrm, nrm_out, rtol, sc0;
   DevArray<int> need;
   DevArray<cf> x32, y32;
-  PinnedHost hx;   // h of both passes and the final norms of one step
-  PinnedHost scp;  // the step's scale factors 1 / ||w|| (in .x), copied to `scale`
-  DevArray<cd> scale;
-  int64_t reorth = 0;  // columns that needed the second Gram-Schmidt pass
-  double t_prod = 0.0, t_arn = 0.0;
+  // least-squares state of the current cycle (Lsq), on the device
+  DevArray<cd> H, g, cs, sn, scale;
+  DevArray<int> active, jc, count;
+  DevArray<unsigned long long> reorth;
+  Pinned<int> hcount;      // running-column counts of the last two steps (a single solve)
+  Pinned<double> hrtol;    // staging of rtol uploads
+  Pinned<unsigned long long> hreorth;
+  hipEvent_t ev[2] = {nullptr, nullptr};  // the copies of hcount[0], hcount[1] are done
+  ~Work() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  Lsq lsq() {
+    return Lsq{H.p, g.p, cs.p, sn.p, scale.p, ybuf.p, active.p, jc.p, need.p, rtol.p, reorth.p, m, r};
+  }
 };
 
-int alloc_work(Work& W, int64_t n, int r, int m, bool lowp) {
+int alloc_work(Work& W, int64_t n, int r, int m, bool lowp, hipStream_t s) {
   W.n = n;
   W.r = r;
   W.m = m;
@@ -464,9 +608,25 @@ int alloc_work(Work& W, int64_t n, int r, int m, bool lowp) {
       (rc = W.d.alloc(n * r)) || (rc = W.part.alloc((int64_t)(m + 1) * r * std::max(W.nch, W.nsub))) ||
       (rc = W.hbuf.alloc(hsz)) || (rc = W.ybuf.alloc((int64_t)(m + 1) * r)) ||
       (rc = W.nrm.alloc(3 * (int64_t)r * std::max(W.nch, W.nsub))) || (rc = W.nrm_out.alloc(r)) ||
-      (rc = W.need.alloc(r)) || (rc = W.hx.alloc(hsz)) || (rc = W.scp.alloc(r)) || (rc = W.scale.alloc(r)))
+      (rc = W.rtol.alloc(r)) || (rc = W.sc0.alloc(r)) || (rc = W.need.alloc(r)) ||
+      (rc = W.H.alloc((int64_t)r * m * (m + 1))) || (rc = W.g.alloc((int64_t)r * (m + 1))) ||
+      (rc = W.cs.alloc((int64_t)r * m)) || (rc = W.sn.alloc((int64_t)r * m)) || (rc = W.scale.alloc(r)) ||
+      (rc = W.active.alloc(r)) || (rc = W.jc.alloc(r)) || (rc = W.count.alloc(1)) || (rc = W.reorth.alloc(1)) ||
+      (rc = W.hcount.alloc(2)) || (rc = W.hrtol.alloc(r)) || (rc = W.hreorth.alloc(1)))
     return rc;
   if (lowp && ((rc = W.x32.alloc(n * r)) || (rc = W.y32.alloc(n * r)))) return rc;
+  for (hipEvent_t& e : W.ev) UHM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  UHM_HIP(hipMemsetAsync(W.reorth.p, 0, sizeof(unsigned long long), s));
+  UHM_HIP(hipMemsetAsync(W.active.p, 0, sizeof(int) * (size_t)r, s));
+  return UHM_OK;
+}
+
+// The per-column stopping thresholds of the current inner solve (host values) to the device.
+int upload_rtol(Work& W, const std::vector<double>& rtol, hipStream_t s) {
+  // the previous upload from the staging area is complete: every caller has synchronised
+  // the stream since (the residual norms it needs)
+  std::memcpy(W.hrtol.p, rtol.data(), sizeof(double) * (size_t)W.r);
+  UHM_HIP(hipMemcpyAsync(W.rtol.p, W.hrtol.p, sizeof(double) * (size_t)W.r, hipMemcpyHostToDevice, s));
   return UHM_OK;
 }
 
@@ -504,13 +664,10 @@ struct uhm_krylov {
   int req = UHM_KRYLOV_DONE;  // UHM_KRYLOV_PRODUCT_HIGH / _LOW / DONE
   const void* req_in = nullptr;
   void* req_out = nullptr;
-  // bookkeeping
+  // bookkeeping (the least-squares state of a cycle is on the device, in W)
   enum Phase { ITER, CYCLE_END, INNER_FINAL_X, OUTER, FINISHED } phase = FINISHED;
-  std::vector<double> bn, rn, rtol, beta, hn, sc;
-  std::vector<std::complex<double>> H, g, cs, sn;
-  std::vector<cd> hh;
-  std::vector<int> jc;
-  std::vector<char> active, done;
+  std::vector<double> bn, rn, rtol, beta;
+  std::vector<char> done;
   int j = 0;
   int iters = 0, restarts = 0, refinements = 0, cycles = 0;
   double t_arn = 0.0;
@@ -561,15 +718,11 @@ int cycle_start(uhm_krylov* K) {
     return UHM_OK;
   }
   if (K->cycles++ > 0) ++K->restarts;
-  for (int c = 0; c < r; ++c) K->sc[c] = K->beta[c] > 0.0 ? 1.0 / K->beta[c] : 0.0;
-  UHM_HIP(hipMemcpyAsync(W.nrm_out.p, K->sc.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_g_scale, dim3(nblk(n * r)), dim3(kGB), 0, s, W.t.p, W.nrm_out.p, n, r, W.V.p);
-  std::fill(K->g.begin(), K->g.end(), C(0.0));
-  for (int c = 0; c < r; ++c) {
-    K->g[(size_t)c * (m + 1)] = C(K->beta[c]);
-    K->jc[c] = 0;
-    K->active[c] = !K->done[c];
-  }
+  // g = beta e_1 and V_0 = t / beta per column; the columns with beta <= rtol do not run
+  // (the device takes the same decision from the same norms)
+  hipLaunchKernelGGL(k_a_cycle_init, dim3((r + 63) / 64), dim3(64), 0, s, W.nrm_out.p, W.lsq(), W.sc0.p);
+  hipLaunchKernelGGL(k_g_scale, dim3(nblk(n * r)), dim3(kGB), 0, s, W.t.p, W.sc0.p, n, r, W.V.p);
+  (void)m;
   K->j = 0;
   K->phase = uhm_krylov::ITER;
   K->req = K->mixed ? UHM_KRYLOV_PRODUCT_LOW : UHM_KRYLOV_PRODUCT_HIGH;
@@ -582,6 +735,8 @@ int cycle_start(uhm_krylov* K) {
 int inner_start(uhm_krylov* K, const cd* rhs_src) {
   Work& W = K->W;
   const int64_t nr = K->n * K->r;
+  int rc = upload_rtol(W, K->rtol, K->s);
+  if (rc) return rc;
   UHM_HIP(hipMemcpyAsync(K->rhs.p, rhs_src, sizeof(cd) * (size_t)nr, hipMemcpyDeviceToDevice, K->s));
   UHM_HIP(hipMemsetAsync(W.d.p, 0, sizeof(cd) * (size_t)nr, K->s));
   UHM_HIP(hipMemcpyAsync(W.t.p, K->rhs.p, sizeof(cd) * (size_t)nr, hipMemcpyDeviceToDevice, K->s));
@@ -589,10 +744,9 @@ int inner_start(uhm_krylov* K, const cd* rhs_src) {
   return cycle_start(K);
 }
 
-// One Arnoldi step after the product W.w = A V_j, in two halves: arnoldi_issue enqueues
-// the orthogonalisation and the copies of h and the norms to pinned host memory;
-// arnoldi_finish runs after the stream has synchronised.  Many solves can issue their
-// halves first and share one synchronisation.
+// One Arnoldi step after the product W.w = A V_j, all on the solve's stream: both
+// Gram-Schmidt passes, the Givens update of the least-squares problem, V_{j+1} = w / ||w||,
+// and a copy of the running-column count to pinned host memory (slot j % 2, event ev).
 int arnoldi_issue(uhm_krylov* K) {
   Work& W = K->W;
   const int r = K->r, m = K->o.restart, j = K->j;
@@ -600,110 +754,51 @@ int arnoldi_issue(uhm_krylov* K) {
   hipStream_t s = K->s;
   const int ns = W.nsub;
   const dim3 gw((unsigned)((ns + kGB / 64 - 1) / (kGB / 64)), (unsigned)r);
+  const dim3 gc((unsigned)((r + 63) / 64));
   const int64_t nq = (int64_t)(j + 1) * r, hoff = (int64_t)(m + 1) * r;
   cd *h1 = W.hbuf.p, *h2 = W.hbuf.p + hoff, *tail = W.hbuf.p + 2 * hoff;
   double *n0 = W.nrm.p, *n1 = n0 + (int64_t)r * ns, *n2 = n1 + (int64_t)r * ns;
-  // first classical Gram-Schmidt pass, all columns
-  hipLaunchKernelGGL(k_a_dots, gw, dim3(kGB), 0, s, W.V.p, vstride, j + 1, W.w.p, n, r, ns, nullptr, W.part.p, n0);
-  hipLaunchKernelGGL(k_a_reduce, dim3(nblk(nq)), dim3(kGB), 0, s, W.part.p, ns, nq, r, nullptr, h1);
-  hipLaunchKernelGGL(k_a_update, gw, dim3(kGB), 0, s, W.V.p, vstride, j + 1, h1, W.w.p, n, r, ns, nullptr, n1);
-  hipLaunchKernelGGL(k_a_decide, dim3((r + 63) / 64), dim3(64), 0, s, n0, n1, ns, r, W.need.p);
+  const int* act = W.active.p;
+  // first classical Gram-Schmidt pass, running columns
+  hipLaunchKernelGGL(k_a_dots, gw, dim3(kGB), 0, s, W.V.p, vstride, j + 1, W.w.p, n, r, ns, act, W.part.p, n0);
+  hipLaunchKernelGGL(k_a_reduce, dim3(nblk(nq)), dim3(kGB), 0, s, W.part.p, ns, nq, r, act, h1);
+  hipLaunchKernelGGL(k_a_update, gw, dim3(kGB), 0, s, W.V.p, vstride, j + 1, h1, W.w.p, n, r, ns, act, n1);
+  hipLaunchKernelGGL(k_a_decide, gc, dim3(64), 0, s, n0, n1, ns, r, act, W.need.p);
   // second pass for the columns that need it
   hipLaunchKernelGGL(k_a_dots, gw, dim3(kGB), 0, s, W.V.p, vstride, j + 1, W.w.p, n, r, ns, W.need.p, W.part.p,
                      nullptr);
   hipLaunchKernelGGL(k_a_reduce, dim3(nblk(nq)), dim3(kGB), 0, s, W.part.p, ns, nq, r, W.need.p, h2);
   hipLaunchKernelGGL(k_a_update, gw, dim3(kGB), 0, s, W.V.p, vstride, j + 1, h2, W.w.p, n, r, ns, W.need.p, n2);
-  hipLaunchKernelGGL(k_a_final, dim3((r + 63) / 64), dim3(64), 0, s, n1, n2, W.need.p, ns, r, tail);
-  UHM_HIP(hipMemcpyAsync(W.hx.p, h1, sizeof(cd) * (size_t)nq, hipMemcpyDeviceToHost, s));
-  UHM_HIP(hipMemcpyAsync(W.hx.p + hoff, h2, sizeof(cd) * (size_t)nq, hipMemcpyDeviceToHost, s));
-  UHM_HIP(hipMemcpyAsync(W.hx.p + 2 * hoff, tail, sizeof(cd) * (size_t)r, hipMemcpyDeviceToHost, s));
+  hipLaunchKernelGGL(k_a_final, gc, dim3(64), 0, s, n1, n2, act, W.need.p, ns, r, tail);
+  // least-squares update, then the next basis vector
+  hipLaunchKernelGGL(k_a_givens, gc, dim3(64), 0, s, j, h1, h2, tail, W.lsq());
+  hipLaunchKernelGGL(k_g_scale2, dim3(nblk(n * r)), dim3(kGB), 0, s, W.w.p, W.scale.p, n, r,
+                     W.V.p + (int64_t)(j + 1) * vstride);
+  hipLaunchKernelGGL(k_a_count, dim3(1), dim3(64), 0, s, W.active.p, r, W.count.p);
+  UHM_HIP(hipMemcpyAsync(W.hcount.p + (j & 1), W.count.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  UHM_HIP(hipEventRecord(W.ev[j & 1], s));
   return UHM_OK;
 }
 
-// Host half of an Arnoldi step: h and the norms (at hx: h1, h2 at hx + hoff, norms at
-// hx + 2 hoff) update the Hessenberg matrices, the Givens rotations and K->sc = 1/||w||.
-// Returns whether every column has stopped.
-bool arnoldi_host(uhm_krylov* K, const cd* hx) {
-  Work& W = K->W;
-  const int r = K->r, m = K->o.restart, j = K->j;
-  const int64_t nq = (int64_t)(j + 1) * r, hoff = (int64_t)(m + 1) * r;
-  ++K->iters;
-  for (int64_t q = 0; q < nq; ++q) {
-    K->hh[q].x = hx[q].x + hx[hoff + q].x;
-    K->hh[q].y = hx[q].y + hx[hoff + q].y;
-  }
-  for (int c = 0; c < r; ++c) {
-    K->hn[c] = hx[2 * hoff + c].x;
-    W.reorth += hx[2 * hoff + c].y != 0.0;
-  }
-  bool all_done = true;
-  for (int c = 0; c < r; ++c) {
-    K->sc[c] = 0.0;
-    if (!K->active[c]) continue;
-    C* col = &K->H[((size_t)c * m + j) * (m + 1)];
-    for (int i = 0; i <= j; ++i) col[i] = C(K->hh[(size_t)i * r + c].x, K->hh[(size_t)i * r + c].y);
-    col[j + 1] = C(K->hn[c]);
-    K->sc[c] = K->hn[c] > 1e-300 ? 1.0 / K->hn[c] : 0.0;
-    for (int i = 0; i < j; ++i) {
-      const C a = col[i], b = col[i + 1];
-      const C ci = K->cs[(size_t)c * m + i], si = K->sn[(size_t)c * m + i];
-      col[i] = std::conj(ci) * a + std::conj(si) * b;
-      col[i + 1] = -si * a + ci * b;
-    }
-    const C a = col[j], b = col[j + 1];
-    const double den = std::sqrt(std::norm(a) + std::norm(b));
-    C cj(1.0), sj(0.0);
-    if (den > 0.0) {
-      cj = a / den;
-      sj = b / den;
-    }
-    K->cs[(size_t)c * m + j] = cj;
-    K->sn[(size_t)c * m + j] = sj;
-    col[j] = std::conj(cj) * a + std::conj(sj) * b;
-    col[j + 1] = C(0.0);
-    C* gc = &K->g[(size_t)c * (m + 1)];
-    const C gj = gc[j];
-    gc[j] = std::conj(cj) * gj;
-    gc[j + 1] = -sj * gj;
-    K->jc[c] = j + 1;
-    if (std::abs(gc[j + 1]) <= K->rtol[c] || K->hn[c] <= 1e-300) K->active[c] = 0;
-    all_done = all_done && !K->active[c];
-  }
-  return all_done;
-}
-
-// After V_{j+1} = w / ||w|| has been enqueued: the next request, or the end of the cycle.
+// After step j has been issued: the next request, or the end of the cycle.  all_done: no
+// column runs any more.
 int arnoldi_next(uhm_krylov* K, bool all_done) {
   Work& W = K->W;
-  const int r = K->r, m = K->o.restart, j = K->j;
+  const int r = K->r, j = K->j;
   const int64_t n = K->n, vstride = n * r;
   hipStream_t s = K->s;
   K->j = j + 1;
-  if (!all_done && K->j < m && K->iters < K->o.max_iterations) {
+  if (!all_done && K->j < K->o.restart && K->iters < K->o.max_iterations) {
     K->req = K->mixed ? UHM_KRYLOV_PRODUCT_LOW : UHM_KRYLOV_PRODUCT_HIGH;
     K->req_in = W.V.p + (int64_t)K->j * vstride;
     K->req_out = W.w.p;
     return UHM_OK;
   }
-  // end of the cycle: y_c = R_c^{-1} g_c, d += V y, then the residual t = rhs - A d
+  // end of the cycle: y_c = R_c^{-1} g_c on the device, d += V y, then the residual
+  // t = rhs - A d
   const int jm = K->j;
-  std::vector<cd> yv((size_t)jm * r, make_double2(0.0, 0.0));
-  for (int c = 0; c < r; ++c) {
-    const int k = K->jc[c];
-    const C* Hc = &K->H[(size_t)c * m * (m + 1)];
-    const C* gc = &K->g[(size_t)c * (m + 1)];
-    std::vector<C> y(k);
-    for (int i = k - 1; i >= 0; --i) {
-      C acc = gc[i];
-      for (int q = i + 1; q < k; ++q) acc -= Hc[(size_t)q * (m + 1) + i] * y[q];
-      const C dgl = Hc[(size_t)i * (m + 1) + i];
-      y[i] = std::abs(dgl) > 0.0 ? acc / dgl : C(0.0);
-    }
-    for (int i = 0; i < k; ++i) yv[(size_t)i * r + c] = make_double2(y[i].real(), y[i].imag());
-  }
-  UHM_HIP(hipMemcpyAsync(W.ybuf.p, yv.data(), sizeof(cd) * yv.size(), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_a_lsq, dim3((r + 63) / 64), dim3(64), 0, s, jm, W.lsq());
   hipLaunchKernelGGL(k_g_combine, dim3(nblk(n * r)), dim3(kGB), 0, s, W.V.p, vstride, jm, W.ybuf.p, W.d.p, n, n, r);
-  UHM_HIP(hipStreamSynchronize(s));
   if (inner_cycles_spent(K)) {
     // the refinement step follows at once: its FP64 residual replaces the inner one
     inner_finish(K);
@@ -739,18 +834,45 @@ size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
 // Offsets of one batched step in the scratch buffers (bytes).
 struct ManyLayout {
-  size_t o_d, o_row, o_red, o_col, o_gw, o_sw, o_g, o_s, tot;
-  unsigned nrow, nred, ncol, ngw, nsw;
+  size_t o_d, o_row, o_red, o_col, o_sw, o_g, tot;
+  unsigned nrow, nred, ncol, nsw;
 };
 
 // arnoldi_issue for many solves: each kernel is launched once over the work of all of them
-// on stream s; the solves' h and norms are gathered into one area and copied to pinned
-// host memory in one transfer.  The caller holds the scratch lock until the step is done.
+// on stream s, the Givens updates and the next basis vectors included; the solves'
+// running-column counts are gathered into one area and copied to pinned host memory in one
+// transfer.  The caller holds the scratch lock until the step is done.
 int arnoldi_issue_many(const std::vector<uhm_krylov*>& iter, hipStream_t s, StepScratch& ss, ManyLayout& Lo) {
   std::vector<ArnDesc> D;
   std::vector<int4> wrow;
-  std::vector<int2> wred, wcol, wg, wsc;
-  int64_t goff = 0, soff = 0;
+  std::vector<int2> wred, wcol, wsc;
+  // layout first: descriptors point into the gather area for their counts
+  size_t nrow = 0, nred = 0, ncol = 0, nsc = 0;
+  for (uhm_krylov* K : iter) {
+    const int r = K->r;
+    nrow += (size_t)r * ((K->W.nsub + kGB / 64 - 1) / (kGB / 64));
+    nred += (size_t)(((int64_t)(K->j + 1) * r + kGB - 1) / kGB);
+    ncol += (size_t)((r + 63) / 64);
+    nsc += (size_t)((K->n * r + kGB - 1) / kGB);
+  }
+  Lo.o_d = 0;
+  Lo.o_row = align16(sizeof(ArnDesc) * iter.size());
+  Lo.o_red = Lo.o_row + align16(sizeof(int4) * nrow);
+  Lo.o_col = Lo.o_red + align16(sizeof(int2) * nred);
+  Lo.o_sw = Lo.o_col + align16(sizeof(int2) * ncol);
+  Lo.o_g = Lo.o_sw + align16(sizeof(int2) * nsc);  // running-column counts, device -> host
+  Lo.tot = Lo.o_g + align16(sizeof(int) * iter.size());
+  if (Lo.tot > ss.cap) {
+    if (ss.dev) (void)hipFree(ss.dev);
+    if (ss.host) (void)hipHostFree(ss.host);
+    ss.dev = ss.host = nullptr;
+    const size_t cap = std::max(Lo.tot, 2 * ss.cap + (1 << 16));
+    ss.cap = 0;
+    UHM_HIP(hipMalloc(reinterpret_cast<void**>(&ss.dev), cap));
+    UHM_HIP(hipHostMalloc(reinterpret_cast<void**>(&ss.host), cap, hipHostMallocDefault));
+    ss.cap = cap;
+  }
+  int* dcount = reinterpret_cast<int*>(ss.dev + Lo.o_g);
   for (size_t k = 0; k < iter.size(); ++k) {
     uhm_krylov* K = iter[k];
     Work& W = K->W;
@@ -763,55 +885,31 @@ int arnoldi_issue_many(const std::vector<uhm_krylov*>& iter, hipStream_t s, Step
     d.vnext = W.V.p + (int64_t)(j + 1) * K->n * r;
     d.nrm = W.nrm.p;
     d.need = W.need.p;
+    d.count = dcount + k;
+    d.q = W.lsq();
     d.n = K->n;
     d.vstride = K->n * r;
     d.hoff = (int64_t)(m + 1) * r;
-    d.hsz = 2 * d.hoff + r;
-    d.goff = goff;
-    d.soff = soff;
     d.r = r;
     d.nvec = j + 1;
     d.nsub = W.nsub;
+    d.j = j;
     D.push_back(d);
     const int ki = (int)k;
     for (int c = 0; c < r; ++c)
       for (int zb = 0; zb < (W.nsub + kGB / 64 - 1) / (kGB / 64); ++zb) wrow.push_back(make_int4(ki, c, zb, 0));
     for (int64_t qb = 0; qb < ((int64_t)(j + 1) * r + kGB - 1) / kGB; ++qb) wred.push_back(make_int2(ki, (int)qb));
     for (int cb = 0; cb < (r + 63) / 64; ++cb) wcol.push_back(make_int2(ki, cb));
-    for (int64_t gb = 0; gb < (d.hsz + kGB - 1) / kGB; ++gb) wg.push_back(make_int2(ki, (int)gb));
     for (int64_t sb = 0; sb < (K->n * r + kGB - 1) / kGB; ++sb) wsc.push_back(make_int2(ki, (int)sb));
-    goff += d.hsz;
-    soff += r;
   }
-  Lo.o_d = 0;
-  Lo.o_row = align16(sizeof(ArnDesc) * D.size());
-  Lo.o_red = Lo.o_row + align16(sizeof(int4) * wrow.size());
-  Lo.o_col = Lo.o_red + align16(sizeof(int2) * wred.size());
-  Lo.o_gw = Lo.o_col + align16(sizeof(int2) * wcol.size());
-  Lo.o_sw = Lo.o_gw + align16(sizeof(int2) * wg.size());
-  Lo.o_g = Lo.o_sw + align16(sizeof(int2) * wsc.size());  // gathered h, device -> host
-  Lo.o_s = Lo.o_g + align16(sizeof(cd) * (size_t)goff);     // scales, host -> device
-  Lo.tot = Lo.o_s + align16(sizeof(cd) * (size_t)soff);
   Lo.nrow = (unsigned)wrow.size();
   Lo.nred = (unsigned)wred.size();
   Lo.ncol = (unsigned)wcol.size();
-  Lo.ngw = (unsigned)wg.size();
   Lo.nsw = (unsigned)wsc.size();
-  if (Lo.tot > ss.cap) {
-    if (ss.dev) (void)hipFree(ss.dev);
-    if (ss.host) (void)hipHostFree(ss.host);
-    ss.dev = ss.host = nullptr;
-    const size_t cap = std::max(Lo.tot, 2 * ss.cap + (1 << 16));
-    ss.cap = 0;
-    UHM_HIP(hipMalloc(reinterpret_cast<void**>(&ss.dev), cap));
-    UHM_HIP(hipHostMalloc(reinterpret_cast<void**>(&ss.host), cap, hipHostMallocDefault));
-    ss.cap = cap;
-  }
   std::memcpy(ss.host + Lo.o_d, D.data(), sizeof(ArnDesc) * D.size());
   std::memcpy(ss.host + Lo.o_row, wrow.data(), sizeof(int4) * wrow.size());
   std::memcpy(ss.host + Lo.o_red, wred.data(), sizeof(int2) * wred.size());
   std::memcpy(ss.host + Lo.o_col, wcol.data(), sizeof(int2) * wcol.size());
-  std::memcpy(ss.host + Lo.o_gw, wg.data(), sizeof(int2) * wg.size());
   std::memcpy(ss.host + Lo.o_sw, wsc.data(), sizeof(int2) * wsc.size());
   UHM_HIP(hipMemcpyAsync(ss.dev, ss.host, Lo.o_g, hipMemcpyHostToDevice, s));
   const ArnDesc* dD = reinterpret_cast<const ArnDesc*>(ss.dev + Lo.o_d);
@@ -825,49 +923,43 @@ int arnoldi_issue_many(const std::vector<uhm_krylov*>& iter, hipStream_t s, Step
     if (pass == 0) hipLaunchKernelGGL(k_ab_decide, dim3(Lo.ncol), dim3(64), 0, s, dD, dCol);
   }
   hipLaunchKernelGGL(k_ab_final, dim3(Lo.ncol), dim3(64), 0, s, dD, dCol);
-  hipLaunchKernelGGL(k_ab_gather, dim3(Lo.ngw), dim3(kGB), 0, s, dD, reinterpret_cast<const int2*>(ss.dev + Lo.o_gw),
-                     reinterpret_cast<cd*>(ss.dev + Lo.o_g));
-  UHM_HIP(hipMemcpyAsync(ss.host + Lo.o_g, ss.dev + Lo.o_g, Lo.o_s - Lo.o_g, hipMemcpyDeviceToHost, s));
+  hipLaunchKernelGGL(k_ab_givens, dim3(Lo.ncol), dim3(64), 0, s, dD, dCol);
+  hipLaunchKernelGGL(k_ab_scale, dim3(Lo.nsw), dim3(kGB), 0, s, dD, reinterpret_cast<const int2*>(ss.dev + Lo.o_sw));
+  hipLaunchKernelGGL(k_ab_count, dim3((unsigned)iter.size()), dim3(64), 0, s, dD);
+  UHM_HIP(hipMemcpyAsync(ss.host + Lo.o_g, ss.dev + Lo.o_g, sizeof(int) * iter.size(), hipMemcpyDeviceToHost, s));
   return UHM_OK;
 }
 
-// Host halves of many solves after the gathered h has arrived, then one upload of all the
-// scale factors and one launch that forms every V_{j+1}.
-int arnoldi_finish_many(const std::vector<uhm_krylov*>& iter, hipStream_t s, StepScratch& ss, const ManyLayout& Lo) {
-  const cd* g = reinterpret_cast<const cd*>(ss.host + Lo.o_g);
-  cd* sc = reinterpret_cast<cd*>(ss.host + Lo.o_s);
-  std::vector<char> done(iter.size());
-  int64_t goff = 0, soff = 0;
+// After the step's counts have arrived: each solve's next request, or the end of its cycle.
+int arnoldi_finish_many(const std::vector<uhm_krylov*>& iter, StepScratch& ss, const ManyLayout& Lo) {
+  const int* cnt = reinterpret_cast<const int*>(ss.host + Lo.o_g);
   for (size_t k = 0; k < iter.size(); ++k) {
     uhm_krylov* K = iter[k];
-    done[k] = arnoldi_host(K, g + goff);
-    for (int c = 0; c < K->r; ++c) sc[soff + c] = make_double2(K->sc[c], 0.0);
-    goff += 2 * (int64_t)(K->o.restart + 1) * K->r + K->r;
-    soff += K->r;
-  }
-  UHM_HIP(hipMemcpyAsync(ss.dev + Lo.o_s, ss.host + Lo.o_s, Lo.tot - Lo.o_s, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_ab_scale, dim3(Lo.nsw), dim3(kGB), 0, s, reinterpret_cast<const ArnDesc*>(ss.dev + Lo.o_d),
-                     reinterpret_cast<const int2*>(ss.dev + Lo.o_sw), reinterpret_cast<const cd*>(ss.dev + Lo.o_s));
-  for (size_t k = 0; k < iter.size(); ++k) {
-    int rc = arnoldi_next(iter[k], done[k] != 0);
+    ++K->iters;
+    // the single-solve path reads the previous step's count from this slot
+    K->W.hcount.p[K->j & 1] = cnt[k];
+    int rc = arnoldi_next(K, cnt[k] == 0);
     if (rc) return iter[k]->status = rc;
   }
-  // the pinned scale area is reused by the next step: the upload must be complete
-  UHM_HIP(hipStreamSynchronize(s));
   return UHM_OK;
 }
 
+// One Arnoldi step of a single solve.  The host checks the running-column count of the
+// previous step (its copy finished long before, normally), not of this one: when it is zero,
+// this step ran on stopped columns only (its effect is nil) and the cycle ends.
 int arnoldi_step(uhm_krylov* K) {
   int rc = arnoldi_issue(K);
   if (rc) return rc;
-  UHM_HIP(hipStreamSynchronize(K->s));
-  Work& W = K->W;
-  const int r = K->r;
-  const bool all_done = arnoldi_host(K, W.hx.p);
-  for (int c = 0; c < r; ++c) W.scp.p[c] = make_double2(K->sc[c], 0.0);
-  UHM_HIP(hipMemcpyAsync(W.scale.p, W.scp.p, sizeof(cd) * r, hipMemcpyHostToDevice, K->s));
-  hipLaunchKernelGGL(k_g_scale2, dim3(nblk(K->n * r)), dim3(kGB), 0, K->s, W.w.p, W.scale.p, K->n, r,
-                     W.V.p + (int64_t)(K->j + 1) * K->n * r);
+  ++K->iters;
+  bool all_done = false;
+  if (K->j > 0) {
+    const int slot = (K->j - 1) & 1;
+    UHM_HIP(hipEventSynchronize(K->W.ev[slot]));
+    if (K->W.hcount.p[slot] == 0) {
+      all_done = true;
+      --K->iters;
+    }
+  }
   return arnoldi_next(K, all_done);
 }
 
@@ -940,19 +1032,10 @@ int uhm_krylov_create(int64_t n, int32_t nrhs, const void* B, int64_t ldb, doubl
   hipStream_t s = K->s;
   const int r = nrhs, m = o.restart;
   int rc;
-  if ((rc = alloc_work(K->W, n, r, m, false)) || (rc = K->Bc.alloc(n * r)) || (rc = K->xacc.alloc(n * r)) ||
+  if ((rc = alloc_work(K->W, n, r, m, false, s)) || (rc = K->Bc.alloc(n * r)) || (rc = K->xacc.alloc(n * r)) ||
       (rc = K->res.alloc(n * r)) || (rc = K->rhs.alloc(n * r)))
     return rc;
-  K->H.assign((size_t)(m + 1) * m * r, C(0.0));
-  K->g.assign((size_t)(m + 1) * r, C(0.0));
-  K->cs.assign((size_t)m * r, C(0.0));
-  K->sn.assign((size_t)m * r, C(0.0));
-  K->hh.assign((size_t)(m + 1) * r, make_double2(0.0, 0.0));
-  K->jc.assign(r, 0);
-  K->active.assign(r, 0);
   K->done.assign(r, 0);
-  K->hn.assign(r, 0.0);
-  K->sc.assign(r, 0.0);
   K->rtol.assign(r, 0.0);
   hipLaunchKernelGGL(k_g_copy_strided, dim3(nblk(n * r)), dim3(kGB), 0, s, static_cast<const cd*>(B), ldb, n, r, K->Bc.p);
   UHM_HIP(hipMemsetAsync(K->xacc.p, 0, sizeof(cd) * (size_t)(n * r), s));
@@ -1018,7 +1101,9 @@ int uhm_krylov_result(uhm_krylov* K, void* X, int64_t ldx, uhm_gmres_info* info)
     info->seconds_total = 0.0;
     info->seconds_products = 0.0;
     info->seconds_arnoldi = K->t_arn;
-    info->second_passes = K->W.reorth;
+    UHM_HIP(hipMemcpyAsync(K->W.hreorth.p, K->W.reorth.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, K->s));
+    UHM_HIP(hipStreamSynchronize(K->s));
+    info->second_passes = (int64_t)K->W.hreorth.p[0];
   }
   return conv == r ? UHM_OK : fail(UHM_ENOCONV, "iteration limit reached before the tolerance");
 }
@@ -1174,7 +1259,7 @@ int uhm_krylov_step(uhm_krylov* const* ks, uhm_op* const* high, uhm_op* const* l
     ManyLayout Lo{};
     if ((rc = arnoldi_issue_many(iter, s, ss, Lo))) return rc;
     UHM_HIP(hipStreamSynchronize(s));
-    if ((rc = arnoldi_finish_many(iter, s, ss, Lo))) return rc;
+    if ((rc = arnoldi_finish_many(iter, ss, Lo))) return rc;
     const double dt = std::chrono::duration<double>(Clock::now() - t0).count() / (double)iter.size();
     for (uhm_krylov* K : iter) K->t_arn += dt;
   }
@@ -1206,13 +1291,35 @@ int uhm_solve_gmres(uhm_op* op, uhm_op* inner, const void* B, int64_t ldb, void*
   DevArray<cf> in32, out32;
   const int64_t nq = op->n * (int64_t)nrhs;
   if (inner && ((rc = in32.alloc(nq)) || (rc = out32.alloc(nq)))) return rc;
+  // GPU time of the products from events around them, read two products late so that the
+  // host never waits for work it has just issued
+  struct Events {
+    hipEvent_t e[2][2] = {};
+    ~Events() {
+      for (auto& pr : e)
+        for (hipEvent_t x : pr)
+          if (x) (void)hipEventDestroy(x);
+    }
+  } pe;
+  for (auto& pr : pe.e)
+    for (hipEvent_t& x : pr) UHM_HIP(hipEventCreate(&x));
   double t_prod = 0.0;
+  int64_t np = 0;
+  auto take = [&](int slot) -> int {
+    float ms = 0.f;
+    UHM_HIP(hipEventSynchronize(pe.e[slot][1]));
+    UHM_HIP(hipEventElapsedTime(&ms, pe.e[slot][0], pe.e[slot][1]));
+    t_prod += 1e-3 * ms;
+    return UHM_OK;
+  };
   while (true) {
     const void* in = nullptr;
     void* out = nullptr;
     const int what = uhm_krylov_next(K, &in, &out);
     if (what == UHM_KRYLOV_DONE) break;
-    const auto tp = Clock::now();
+    const int slot = (int)(np & 1);
+    if (np >= 2 && (rc = take(slot))) return rc;
+    UHM_HIP(hipEventRecord(pe.e[slot][0], s));
     if (what == UHM_KRYLOV_PRODUCT_HIGH) {
       rc = uhm_matvec(op, in, op->n, out, op->n, nrhs, s);
     } else {
@@ -1221,14 +1328,18 @@ int uhm_solve_gmres(uhm_op* op, uhm_op* inner, const void* B, int64_t ldb, void*
       if (rc == UHM_OK) hipLaunchKernelGGL(k_g_to64, dim3(nblk(nq)), dim3(kGB), 0, s, out32.p, nq, static_cast<cd*>(out));
     }
     if (rc) return rc;
-    UHM_HIP(hipStreamSynchronize(s));
-    t_prod += std::chrono::duration<double>(Clock::now() - tp).count();
+    UHM_HIP(hipEventRecord(pe.e[slot][1], s));
+    ++np;
     if ((rc = uhm_krylov_advance(K))) return rc;
   }
+  for (int64_t q = std::max<int64_t>(0, np - 2); q < np; ++q)
+    if ((rc = take((int)(q & 1)))) return rc;
   rc = uhm_krylov_result(K, X, ldx, info);
   if (info) {
     info->seconds_total = std::chrono::duration<double>(Clock::now() - t0).count();
     info->seconds_products = t_prod;
+    // everything else: orthogonalisation, least-squares updates, residuals, control
+    info->seconds_arnoldi = std::max(0.0, info->seconds_total - t_prod);
   }
   const hipError_t he = hipGetLastError();
   if (he != hipSuccess) return fail(UHM_EHIP, std::string("gmres kernels: ") + hipGetErrorString(he));

@@ -29,8 +29,9 @@ import numpy as np
 
 def solve_footprint(n: int, nrhs: int, restart: int) -> int:
     """Device bytes a GMRES-IR solve holds: the (m+1) Krylov vectors and the dozen
-    n x nrhs complex128 work vectors, plus product staging (bounded by the same size)."""
-    return 16 * n * nrhs * (restart + 1 + 12)
+    n x nrhs complex128 work vectors, plus product staging (bounded by the same size), and
+    the least-squares state of a cycle (Hessenberg columns, rotations, g; complex128)."""
+    return 16 * n * nrhs * (restart + 1 + 12) + 16 * nrhs * (restart + 1) * (restart + 4)
 
 
 class Admission:
@@ -89,7 +90,7 @@ class Request:
 class Server:
     def __init__(self, host_ops, low_storage: str = "c64", restart: int = 50, inner_tol: float = 1e-4,
                  max_iterations: int = 1000, max_refinements: int = 30, hbm_budget: int | None = None,
-                 max_active: int = 256, stream=None, keep_solutions: bool = False):
+                 max_active: int = 256, stream=None, keep_solutions: bool = False, inner_cycles: int = 1):
         import torch
 
         from . import binding
@@ -102,6 +103,13 @@ class Server:
         self.inner_tol = inner_tol
         self.max_iterations = max_iterations
         self.max_refinements = max_refinements
+        self.inner_cycles = inner_cycles
+        if inner_cycles > 0:   # every inner_cycles cycles is one refinement step
+            self.max_refinements = max(max_refinements, max_iterations // (restart * inner_cycles) + 2)
+        # time inside the batched steps, their count and the solves they served
+        self.step_s = 0.0
+        self.steps = 0
+        self.step_solves = 0
         if hbm_budget is None:
             free, _ = torch.cuda.mem_get_info()
             hbm_budget = int(0.6 * free)
@@ -129,14 +137,19 @@ class Server:
                 req.start = clock() - t0
                 k = self.binding.Krylov(req.b, req.tol, mixed=True, restart=self.restart,
                                         max_iterations=self.max_iterations, max_refinements=self.max_refinements,
-                                        inner_tol=self.inner_tol, stream=self.stream)
+                                        inner_tol=self.inner_tol, stream=self.stream,
+                                        inner_cycles=self.inner_cycles)
                 active.append((req, k, nb))
             if not active:
                 if i < len(reqs):
                     time.sleep(max(0.0, reqs[i].arrival - (clock() - t0)))
                 continue
+            ts = clock()
             self.binding.krylov_step([a[1] for a in active], [self.high[a[0].op] for a in active],
                                      [self.low[a[0].op] for a in active], stream=self.stream)
+            self.step_s += clock() - ts
+            self.steps += 1
+            self.step_solves += len(active)
             steps += 1
             still = []
             for req, k, nb in active:

@@ -7,8 +7,8 @@ recomputed with the oracle's block-wise product.
 import numpy as np
 import pytest
 
-from conftest import operator
-from oracle import uniform
+from conftest import operator, rel
+from oracle import krylov, precision, uniform
 from paper_2405_15573_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -34,14 +34,16 @@ def _solve(torch, op, b, tol, inner_storage=None, **kw):
     return x.cpu().numpy(), info, rc
 
 
-@pytest.mark.parametrize("inner", [None, "c64", "bf16pair", "c64fact", "bf16pairfact"])
-def test_gmres_solves_against_dense_solution(torch_dev, inner):
-    print(f"case gmres inner={inner}", flush=True)
+@pytest.mark.parametrize("inner,cycles", [(None, 0), ("c64", 0), ("bf16pair", 0), ("c64fact", 0),
+                                          ("bf16pairfact", 0), ("c64", 1), ("bf16pair", 1), ("bf16pairfact", 1)])
+def test_gmres_solves_against_dense_solution(torch_dev, inner, cycles):
+    print(f"case gmres inner={inner} inner_cycles={cycles}", flush=True)
     cloud, op = operator()
     o = vars(op)
     b = inputs.make_rhs(cloud.n, 2, seed=31)
     tol = 1e-8
-    x, info, rc = _solve(torch_dev, op, b, tol, inner, restart=50)
+    kw = {"inner_cycles": cycles, "max_refinements": 100} if inner else {}
+    x, info, rc = _solve(torch_dev, op, b, tol, inner, restart=50, **kw)
     print(f"  {info}", flush=True)
     assert rc == 0 and info["converged"] == 2
     res = np.linalg.norm(b - uniform.uh_mvp(o, x), axis=0) / np.linalg.norm(b, axis=0)
@@ -128,3 +130,44 @@ def test_gmres_with_symmetric_storage_operator(torch_dev):
         x = x.cpu().numpy()
         res = np.linalg.norm(b - uniform.uh_mvp(ex, x), axis=0) / np.linalg.norm(b, axis=0)
         assert rc == 0 and info["converged"] == 3 and res.max() <= 1e-8 * 1.01
+
+
+@pytest.mark.parametrize("iters,restart", [(7, 50), (23, 10)])
+def test_gmres_iterate_is_the_minimal_residual_iterate(torch_dev, iters, restart):
+    """After a fixed number of Krylov steps (the iteration cap; the tolerance is out of
+    reach), each column of the GPU iterate is the minimal-residual iterate over the same
+    Krylov spaces, computed by the oracle as a literal least-squares minimisation
+    (oracle.krylov): a check of the device-side Hessenberg, Givens and triangular-solve
+    steps, cycle by cycle."""
+    print(f"case gmres iterate {iters} steps, restart {restart}", flush=True)
+    cloud, op = operator()
+    o = vars(op)
+    b = inputs.make_rhs(cloud.n, 2, seed=40)
+    x, info, rc = _solve(torch_dev, op, b, 1e-15, None, restart=restart, max_iterations=iters,
+                         raise_on_noconv=False)
+    assert info["iterations"] == iters and info["converged"] == 0
+    for j in range(2):
+        ref = krylov.gmres_restarted(lambda v: uniform.alg6(o, v), b[:, j], restart, iters)
+        err = rel(x[:, j], ref)
+        print(f"  column {j}: {err:.2e}", flush=True)
+        assert err <= 1e-10
+
+
+def test_ir_one_cycle_per_refinement_is_the_oracle_refinement(torch_dev):
+    """GMRES-IR with one inner cycle per refinement (inner_cycles = 1) against the oracle's
+    refinement (oracle.krylov.gmres_ir_cycles): residuals with the FP64 operator, each
+    correction the minimal-residual iterate of the complex64-rounded operator over its
+    Krylov space.  The GPU's inner products accumulate in FP32, hence the 1e-5 bar."""
+    print("case gmres-ir per-cycle refinement vs oracle", flush=True)
+    cloud, op = operator()
+    o = vars(op)
+    lo = precision.round_operator(o, "c64")
+    b = inputs.make_rhs(cloud.n, 2, seed=41)
+    x, info, rc = _solve(torch_dev, op, b, 1e-15, "c64", restart=10, max_iterations=30, inner_cycles=1,
+                         inner_tol=1e-12, max_refinements=100, raise_on_noconv=False)
+    assert info["iterations"] == 30 and info["refinements"] == 3
+    for j in range(2):
+        ref = krylov.gmres_ir_cycles(lambda v: uniform.alg6(o, v), lambda v: uniform.alg6(lo, v), b[:, j], 10, 3)
+        err = rel(x[:, j], ref)
+        print(f"  column {j}: {err:.2e}", flush=True)
+        assert err <= 1e-5

@@ -4,7 +4,8 @@ from paper_2405_15573_amd.serving import Admission, solve_footprint
 
 def test_footprint_grows_with_size_and_rhs():
     assert solve_footprint(1000, 2, 50) == 2 * solve_footprint(1000, 1, 50)
-    assert solve_footprint(2000, 1, 50) == 2 * solve_footprint(1000, 1, 50)
+    # the Krylov basis and work vectors grow with n; the least-squares state does not
+    assert solve_footprint(2000, 1, 50) - solve_footprint(1000, 1, 50) == 16 * 1000 * (50 + 13)
     assert solve_footprint(1000, 1, 50) > solve_footprint(1000, 1, 10)
 
 
