@@ -13,7 +13,11 @@
 // imaginary parts), so a wavefront loads a contiguous run with 16-byte lane loads.  The
 // vector operand (the "B" operand: gathered rows of x, u_sigma or u_tau) is staged in LDS
 // in FP32 (complex64 path) or as bf16 hi + lo parts (bf16 path), so that in the bf16 form
-// the only bf16 rounding is that of the stored operator.
+// the only bf16 rounding is that of the stored operator.  In the bf16 form the vectors that
+// feed a B operand (the gathered x, u_sigma, t_b, u_tau) are written split, once per
+// product, by the kernels that produce them: each element is (re_hi, re_lo, im_hi, im_lo),
+// 8 bytes, so staging a round copies bf16 parts instead of splitting FP32 values again in
+// every tile that reads them.
 //
 // MFMA lane layouts (checked on gfx950):
 //   v_mfma_f32_16x16x4_f32:  A lane l = A[l%16][l/16], B lane l = B[l/16][l%16]
@@ -104,6 +108,12 @@ struct Acc2 {
   __device__ auto im(int nt, int v) const { return i[nt][v]; }
 };
 
+// A complex vector element split into bf16 parts: v ~ (rh + rl) + i (ih + il), each part the
+// nearest bf16 (rl, il: of the FP32 remainder), 8 bytes like a complex64.
+struct bfs4 {
+  uint16_t rh, rl, ih, il;
+};
+
 // Storage traits.  CH: 16-byte words per lane chunk; RZ: k-rows per LDS round; KP: k-rows
 // of one column that a thread stages together (one packed LDS store per plane);
 // V: vector element; ACC: accumulator register tile; rows of an accumulator register:
@@ -114,6 +124,7 @@ template <>
 struct Tr<UHM_C64> {
   static constexpr int KB = 16, KPL = 4, CH = 2, RZ = 64, KP = 1;
   using V = cf;
+  using VB = cf;  // vectors that feed a B operand
   using ACC = v4f;
   template <int NT>
   using ACCS = Acc3<v4f, NT>;
@@ -126,6 +137,7 @@ template <>
 struct Tr<UHM_BF16PAIR> {
   static constexpr int KB = 32, KPL = 8, CH = 2, RZ = 64, KP = 4;
   using V = cf;
+  using VB = bfs4;
   using ACC = v4f;
   template <int NT>
   using ACCS = Acc2<v4f, NT>;
@@ -138,6 +150,7 @@ template <>
 struct Tr<UHM_C128_MULTI> {
   static constexpr int KB = 16, KPL = 4, CH = 4, RZ = 32, KP = 1;
   using V = cd;
+  using VB = cd;
   using ACC = v4d;
   // four products at every NT: three accumulators per column tile would leave one wave per
   // SIMD at NT >= 3, and one scheme for all NT keeps a column's rounding independent of
@@ -156,6 +169,25 @@ template <>
 __device__ __forceinline__ cf vzero<cf>() { return make_float2(0.f, 0.f); }
 template <>
 __device__ __forceinline__ cd vzero<cd>() { return make_double2(0.0, 0.0); }
+template <>
+__device__ __forceinline__ bfs4 vzero<bfs4>() { return bfs4{0, 0, 0, 0}; }
+
+// A V value (complex64 or complex128) as the B-operand element VB.
+template <class VB>
+__device__ __forceinline__ VB to_vb(cf v);
+template <>
+__device__ __forceinline__ cf to_vb<cf>(cf v) { return v; }
+template <>
+__device__ __forceinline__ bfs4 to_vb<bfs4>(cf v) {
+  const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
+  const __bf16 rl = (__bf16)(v.x - (float)rh), il = (__bf16)(v.y - (float)ih);
+  return bfs4{__builtin_bit_cast(uint16_t, rh), __builtin_bit_cast(uint16_t, rl), __builtin_bit_cast(uint16_t, ih),
+              __builtin_bit_cast(uint16_t, il)};
+}
+template <class VB>
+__device__ __forceinline__ VB to_vb(cd v);
+template <>
+__device__ __forceinline__ cd to_vb<cd>(cd v) { return v; }
 
 template <int ST, int NT>
 using LdsOf = typename Tr<ST>::template LDS<NT>;
@@ -165,34 +197,24 @@ __device__ __forceinline__ void lds_put(LdsF32<RZ, NT>& L, int k, int j, cf v) {
 template <int RZ, int NT>
 __device__ __forceinline__ void lds_put(LdsF64<RZ, NT>& L, int k, int j, cd v) { L.z[k * L.S + j] = v; }
 template <int RZ, int NT>
-__device__ __forceinline__ void lds_put(LdsBf16<RZ, NT>& L, int k, int j, cf v) {
-  const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
-  L.re_hi[j * L.ZT + k] = rh;
-  L.re_lo[j * L.ZT + k] = (__bf16)(v.x - (float)rh);
-  L.im_hi[j * L.ZT + k] = ih;
-  L.im_lo[j * L.ZT + k] = (__bf16)(v.y - (float)ih);
+__device__ __forceinline__ void lds_put(LdsBf16<RZ, NT>& L, int k, int j, bfs4 v) {
+  L.re_hi[j * L.ZT + k] = __builtin_bit_cast(__bf16, v.rh);
+  L.re_lo[j * L.ZT + k] = __builtin_bit_cast(__bf16, v.rl);
+  L.im_hi[j * L.ZT + k] = __builtin_bit_cast(__bf16, v.ih);
+  L.im_lo[j * L.ZT + k] = __builtin_bit_cast(__bf16, v.il);
 }
 // Rows k0 .. k0 + 3 (k0 a multiple of 4) of column j: one 8-byte store per plane.
 template <int RZ, int NT>
-__device__ __forceinline__ void lds_put4(LdsBf16<RZ, NT>& L, int k0, int j, const cf* v) {
-  uint16_t rh[4], rl[4], ih[4], il[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const __bf16 a = (__bf16)v[t].x, c = (__bf16)v[t].y;
-    const __bf16 al = (__bf16)(v[t].x - (float)a), cl = (__bf16)(v[t].y - (float)c);
-    rh[t] = __builtin_bit_cast(uint16_t, a);
-    rl[t] = __builtin_bit_cast(uint16_t, al);
-    ih[t] = __builtin_bit_cast(uint16_t, c);
-    il[t] = __builtin_bit_cast(uint16_t, cl);
-  }
-  auto pack = [](const uint16_t* h) {
-    return make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
-  };
+__device__ __forceinline__ void lds_put4(LdsBf16<RZ, NT>& L, int k0, int j, const bfs4* v) {
   const int o = j * L.ZT + k0;
-  *reinterpret_cast<uint2*>(&L.re_hi[o]) = pack(rh);
-  *reinterpret_cast<uint2*>(&L.re_lo[o]) = pack(rl);
-  *reinterpret_cast<uint2*>(&L.im_hi[o]) = pack(ih);
-  *reinterpret_cast<uint2*>(&L.im_lo[o]) = pack(il);
+  *reinterpret_cast<uint2*>(&L.re_hi[o]) =
+      make_uint2((uint32_t)v[0].rh | ((uint32_t)v[1].rh << 16), (uint32_t)v[2].rh | ((uint32_t)v[3].rh << 16));
+  *reinterpret_cast<uint2*>(&L.re_lo[o]) =
+      make_uint2((uint32_t)v[0].rl | ((uint32_t)v[1].rl << 16), (uint32_t)v[2].rl | ((uint32_t)v[3].rl << 16));
+  *reinterpret_cast<uint2*>(&L.im_hi[o]) =
+      make_uint2((uint32_t)v[0].ih | ((uint32_t)v[1].ih << 16), (uint32_t)v[2].ih | ((uint32_t)v[3].ih << 16));
+  *reinterpret_cast<uint2*>(&L.im_lo[o]) =
+      make_uint2((uint32_t)v[0].il | ((uint32_t)v[1].il << 16), (uint32_t)v[2].il | ((uint32_t)v[3].il << 16));
 }
 
 __device__ __forceinline__ void load_chunk(const uint4* p, bool act, ChunkF32& c) {
@@ -291,8 +313,9 @@ __device__ __forceinline__ void mma_block(const ChunkBf16& a, const LdsBf16<RZ, 
 }
 
 // Store the 16 x (16 NT) accumulator tile; register v of lane (g, i) holds row Tr::row(g, v).
-template <int ST, int NT>
-__device__ __forceinline__ void store_tile(typename Tr<ST>::V* out, int64_t row0, int hm, int R, int g, int i,
+// OV: V for partial sums and outputs, VB where the tile's values feed a later B operand.
+template <int ST, int NT, class OV = typename Tr<ST>::V>
+__device__ __forceinline__ void store_tile(OV* out, int64_t row0, int hm, int R, int g, int i,
                                            const typename Tr<ST>::template ACCS<NT>& c) {
   using V = typename Tr<ST>::V;
 #pragma unroll
@@ -304,7 +327,7 @@ __device__ __forceinline__ void store_tile(typename Tr<ST>::V* out, int64_t row0
         V o;
         o.x = c.re(nt, v);
         o.y = c.im(nt, v);
-        out[(row0 + r) * R + nt * 16 + i] = o;
+        out[(row0 + r) * R + nt * 16 + i] = to_vb<OV>(o);
       }
     }
 }
@@ -340,14 +363,15 @@ struct LpDesc {
   int32_t r, R;
 };
 
-// Xc[pos][j] = x[perm[pos] + j ldx] (cluster order, row-major, R columns, zero beyond r).
-template <class V>
+// Xc[pos][j] = x[perm[pos] + j ldx] (cluster order, row-major, R columns, zero beyond r),
+// as B-operand elements.
+template <class V, class VB>
 __device__ __forceinline__ void gather_body(int64_t q, const V* __restrict__ x, int64_t ldx, int r, int R,
-                                            const int32_t* __restrict__ perm, int64_t n, V* __restrict__ Xc) {
+                                            const int32_t* __restrict__ perm, int64_t n, VB* __restrict__ Xc) {
   if (q >= n * R) return;
   const int64_t pos = q / R;
   const int j = (int)(q - pos * R);
-  Xc[q] = j < r ? x[perm[pos] + (int64_t)j * ldx] : vzero<V>();
+  Xc[q] = j < r ? to_vb<VB>(x[perm[pos] + (int64_t)j * ldx]) : vzero<VB>();
 }
 
 template <class V>
@@ -374,7 +398,7 @@ struct Round {
   static constexpr int PQ = RZN * 16 * NT / (64 * kLpWaves);  // B elements per thread
   static_assert(PQ % T_::KP == 0, "slots come in whole groups of KP rows");
   typename T_::CHUNK a[KBR];
-  typename T_::V v[PQ];
+  typename T_::VB v[PQ];
   int32_t id[PQ];
   bool ok[PQ];
 };
@@ -428,7 +452,7 @@ __device__ __forceinline__ void round_values(Round<ST, NT>& Q, int nk, Src src) 
 }
 template <int ST, int NT>
 __device__ __forceinline__ void round_commit(LdsOf<ST, NT>& L, const Round<ST, NT>& Q, int nk) {
-  using V = typename Tr<ST>::V;
+  using V = typename Tr<ST>::VB;
   constexpr int KP = Tr<ST>::KP;
 #pragma unroll
   for (int u = 0; u < Round<ST, NT>::PQ; u += KP) {
@@ -460,7 +484,7 @@ __device__ __forceinline__ void forward_body(LdsOf<ST, NT>& L, int pan, const ui
                                              const int64_t* __restrict__ f_off, const int32_t* __restrict__ f_M,
                                              const int32_t* __restrict__ f_nkb, const int32_t* __restrict__ pan_pos,
                                              const int32_t* __restrict__ pan_n, const int64_t* __restrict__ poff,
-                                             const typename Tr<ST>::V* __restrict__ Xc, int R,
+                                             const typename Tr<ST>::VB* __restrict__ Xc, int R,
                                              typename Tr<ST>::V* __restrict__ p) {
   using T_ = Tr<ST>;
   using Q_ = Round<ST, NT>;
@@ -470,7 +494,7 @@ __device__ __forceinline__ void forward_body(LdsOf<ST, NT>& L, int pan, const ui
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, i = lane & 15;
   const uint4* base = F + f_off[pan];
   const int nmt = (M + 15) >> 4;
-  const typename T_::V* xl = Xc + (int64_t)pan_pos[pan] * R;
+  const typename T_::VB* xl = Xc + (int64_t)pan_pos[pan] * R;
   constexpr int KBR = Q_::KBR;
   // rows k < n of the leaf; padding rows read row 0 and are masked
   auto src = [&](int32_t k, int j, bool ok) { return xl + (ok ? (int64_t)k * R + j : 0); };
@@ -523,7 +547,7 @@ __device__ __forceinline__ void forward_body(LdsOf<ST, NT>& L, int pan, const ui
 }
 
 // xh[e][j] = sum over the panels of the segment of p[poff[panel] + col + e - start][j].
-template <class V>
+template <class V, class VB>
 __device__ __forceinline__ void reduce_segments_body(int64_t q, const V* __restrict__ p, int R,
                                                      const int64_t* __restrict__ poff,
                                                      const int32_t* __restrict__ out_seg,
@@ -531,7 +555,7 @@ __device__ __forceinline__ void reduce_segments_body(int64_t q, const V* __restr
                                                      const int32_t* __restrict__ seg_pan0,
                                                      const int32_t* __restrict__ seg_npan,
                                                      const int32_t* __restrict__ seg_col, int64_t nout,
-                                                     V* __restrict__ xh) {
+                                                     VB* __restrict__ xh) {
   if (q >= nout * R) return;
   const int64_t e = q / R;
   const int j = (int)(q - e * R);
@@ -544,15 +568,15 @@ __device__ __forceinline__ void reduce_segments_body(int64_t q, const V* __restr
     acc.x += v.x;
     acc.y += v.y;
   }
-  xh[q] = acc;
+  xh[q] = to_vb<VB>(acc);
 }
 
 // Partial u_tau of one coupling tile (wave w = m-tile w of the chunk).
-template <int ST, int NT>
+template <int ST, int NT, class OV = typename Tr<ST>::V>
 __device__ __forceinline__ void coupling_body(LdsOf<ST, NT>& L, const LpCoupTile& T,
                                               const uint4* __restrict__ S, const int32_t* __restrict__ colsrc,
-                                              const typename Tr<ST>::V* __restrict__ xh, int R,
-                                              typename Tr<ST>::V* __restrict__ part) {
+                                              const typename Tr<ST>::VB* __restrict__ xh, int R,
+                                              OV* __restrict__ part) {
   using T_ = Tr<ST>;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, i = lane & 15;
   const int nmt = (T.h + 15) >> 4;
@@ -581,7 +605,7 @@ __device__ __forceinline__ void coupling_body(LdsOf<ST, NT>& L, const LpCoupTile
     __syncthreads();
     if (w < nmt) round_mma<ST, NT>(Q, L, nkr, g, i, acc);
   }
-  if (w < nmt) store_tile<ST, NT>(part, (int64_t)T.part * 64 + 16 * w, hm, R, g, i, acc);
+  if (w < nmt) store_tile<ST, NT, OV>(part, (int64_t)T.part * 64 + 16 * w, hm, R, g, i, acc);
 }
 
 // Factor pass over all t rows of one column cluster sigma whose K = l_sigma fits one LDS
@@ -590,8 +614,8 @@ __device__ __forceinline__ void coupling_body(LdsOf<ST, NT>& L, const LpCoupTile
 template <int ST, int NT>
 __device__ __forceinline__ void factor_body(LdsOf<ST, NT>& L, const LpCoupTile& T, const uint4* __restrict__ S,
                                             const int32_t* __restrict__ colsrc,
-                                            const typename Tr<ST>::V* __restrict__ xh, int R,
-                                            typename Tr<ST>::V* __restrict__ out) {
+                                            const typename Tr<ST>::VB* __restrict__ xh, int R,
+                                            typename Tr<ST>::VB* __restrict__ out) {
   using T_ = Tr<ST>;
   using Q_ = Round<ST, NT>;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, i = lane & 15;
@@ -613,17 +637,17 @@ __device__ __forceinline__ void factor_body(LdsOf<ST, NT>& L, const LpCoupTile& 
     typename T_::template ACCS<NT> acc;
     acc.zero();
     round_mma<ST, NT>(Q, L, nkr, g, i, acc);
-    store_tile<ST, NT>(out, (int64_t)T.part * 64 + 16 * mt, hm, R, g, i, acc);
+    store_tile<ST, NT, typename Tr<ST>::VB>(out, (int64_t)T.part * 64 + 16 * mt, hm, R, g, i, acc);
   }
 }
 
-template <class V>
+template <class V, class VB>
 __device__ __forceinline__ void reduce_coupling_body(int64_t q, const V* __restrict__ part, int R,
                                                      const int32_t* __restrict__ yh_grp,
                                                      const int64_t* __restrict__ grp_start,
                                                      const int32_t* __restrict__ grp_t0,
                                                      const int32_t* __restrict__ grp_nt, int64_t nout,
-                                                     V* __restrict__ yh) {
+                                                     VB* __restrict__ yh) {
   if (q >= nout * R) return;
   const int64_t e = q / R;
   const int j = (int)(q - e * R);
@@ -636,7 +660,7 @@ __device__ __forceinline__ void reduce_coupling_body(int64_t q, const V* __restr
     acc.x += v.x;
     acc.y += v.y;
   }
-  yh[q] = acc;
+  yh[q] = to_vb<VB>(acc);
 }
 
 // Y_lambda = B_lambda Z_lambda for one leaf; Z gathered from yh (index >= 0), from the
@@ -646,8 +670,8 @@ __device__ __forceinline__ void backward_body(LdsOf<ST, NT>& L, int leaf, const 
                                               const int64_t* __restrict__ b_off, const int32_t* __restrict__ b_nkb,
                                               const int64_t* __restrict__ zoff, const int32_t* __restrict__ zmap,
                                               const int32_t* __restrict__ leaf_pos, const int32_t* __restrict__ leaf_n,
-                                              const typename Tr<ST>::V* __restrict__ yh,
-                                              const typename Tr<ST>::V* __restrict__ Xc, int R,
+                                              const typename Tr<ST>::VB* __restrict__ yh,
+                                              const typename Tr<ST>::VB* __restrict__ Xc, int R,
                                               typename Tr<ST>::V* __restrict__ Yc) {
   using T_ = Tr<ST>;
   const int n = leaf_n[leaf], nkb = b_nkb[leaf];
@@ -682,10 +706,11 @@ __device__ __forceinline__ void backward_body(LdsOf<ST, NT>& L, int leaf, const 
 
 // ---------------------------------------------------------------- single-operator kernels
 
-template <class V>
-__global__ __launch_bounds__(256) void k_lp_gather(const V* __restrict__ x, int64_t ldx, int r, int R,
-                                                   const int32_t* __restrict__ perm, int64_t n, V* __restrict__ Xc) {
-  gather_body<V>((int64_t)blockIdx.x * 256 + threadIdx.x, x, ldx, r, R, perm, n, Xc);
+template <int ST>
+__global__ __launch_bounds__(256) void k_lp_gather(const typename Tr<ST>::V* __restrict__ x, int64_t ldx, int r, int R,
+                                                   const int32_t* __restrict__ perm, int64_t n,
+                                                   typename Tr<ST>::VB* __restrict__ Xc) {
+  gather_body((int64_t)blockIdx.x * 256 + threadIdx.x, x, ldx, r, R, perm, n, Xc);
 }
 
 template <class V>
@@ -707,62 +732,65 @@ template <int ST, int NT>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lp_forward(
     const uint4* __restrict__ F, const int64_t* __restrict__ f_off, const int32_t* __restrict__ f_M,
     const int32_t* __restrict__ f_nkb, const int32_t* __restrict__ f_pos, const int32_t* __restrict__ f_n,
-    const int64_t* __restrict__ poff, const typename Tr<ST>::V* __restrict__ Xc, int R,
+    const int64_t* __restrict__ poff, const typename Tr<ST>::VB* __restrict__ Xc, int R,
     typename Tr<ST>::V* __restrict__ p) {
   __shared__ LdsOf<ST, NT> L;
   forward_body<ST, NT>(L, blockIdx.x, F, f_off, f_M, f_nkb, f_pos, f_n, poff, Xc, R, p);
 }
 
-template <class V>
-__global__ __launch_bounds__(256) void k_lp_reduce_segments(const V* __restrict__ p, int R, const int64_t* __restrict__ poff,
+template <int ST>
+__global__ __launch_bounds__(256) void k_lp_reduce_segments(const typename Tr<ST>::V* __restrict__ p, int R,
+                                                            const int64_t* __restrict__ poff,
                                                             const int32_t* __restrict__ out_seg,
                                                             const int64_t* __restrict__ seg_start,
                                                             const int32_t* __restrict__ seg_pan0,
                                                             const int32_t* __restrict__ seg_npan,
                                                             const int32_t* __restrict__ seg_col, int64_t nout,
-                                                            V* __restrict__ xh) {
-  reduce_segments_body<V>((int64_t)blockIdx.x * 256 + threadIdx.x, p, R, poff, out_seg, seg_start, seg_pan0, seg_npan,
-                          seg_col, nout, xh);
+                                                            typename Tr<ST>::VB* __restrict__ xh) {
+  reduce_segments_body((int64_t)blockIdx.x * 256 + threadIdx.x, p, R, poff, out_seg, seg_start, seg_pan0, seg_npan,
+                       seg_col, nout, xh);
 }
 
-template <int ST, int NT>
+// OV: the partial-sum element V, or VB for the factored first pass, whose tiles are the t_b
+// rows of the coupling source vector
+template <int ST, int NT, class OV>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lp_coupling(const uint4* __restrict__ S,
                                                                const LpCoupTile* __restrict__ tiles,
                                                                const int32_t* __restrict__ colsrc,
-                                                               const typename Tr<ST>::V* __restrict__ xh, int R,
-                                                               typename Tr<ST>::V* __restrict__ part) {
+                                                               const typename Tr<ST>::VB* __restrict__ xh, int R,
+                                                               OV* __restrict__ part) {
   __shared__ LdsOf<ST, NT> L;
   const LpCoupTile T = tiles[blockIdx.x];
-  coupling_body<ST, NT>(L, T, S, colsrc, xh, R, part);
+  coupling_body<ST, NT, OV>(L, T, S, colsrc, xh, R, part);
 }
 
 template <int ST, int NT>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lp_factor(const uint4* __restrict__ S,
                                                              const LpCoupTile* __restrict__ tiles,
                                                              const int32_t* __restrict__ colsrc,
-                                                             const typename Tr<ST>::V* __restrict__ xh, int R,
-                                                             typename Tr<ST>::V* __restrict__ out) {
+                                                             const typename Tr<ST>::VB* __restrict__ xh, int R,
+                                                             typename Tr<ST>::VB* __restrict__ out) {
   __shared__ LdsOf<ST, NT> L;
   const LpCoupTile T = tiles[blockIdx.x];
   factor_body<ST, NT>(L, T, S, colsrc, xh, R, out);
 }
 
-template <class V>
-__global__ __launch_bounds__(256) void k_lp_reduce_coupling(const V* __restrict__ part, int R,
+template <int ST>
+__global__ __launch_bounds__(256) void k_lp_reduce_coupling(const typename Tr<ST>::V* __restrict__ part, int R,
                                                             const int32_t* __restrict__ yh_grp,
                                                             const int64_t* __restrict__ grp_start,
                                                             const int32_t* __restrict__ grp_t0,
                                                             const int32_t* __restrict__ grp_nt, int64_t nout,
-                                                            V* __restrict__ yh) {
-  reduce_coupling_body<V>((int64_t)blockIdx.x * 256 + threadIdx.x, part, R, yh_grp, grp_start, grp_t0, grp_nt, nout, yh);
+                                                            typename Tr<ST>::VB* __restrict__ yh) {
+  reduce_coupling_body((int64_t)blockIdx.x * 256 + threadIdx.x, part, R, yh_grp, grp_start, grp_t0, grp_nt, nout, yh);
 }
 
 template <int ST, int NT>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lp_backward(
     const uint4* __restrict__ B, const int64_t* __restrict__ b_off, const int32_t* __restrict__ b_nkb,
     const int64_t* __restrict__ zoff, const int32_t* __restrict__ zmap, const int32_t* __restrict__ leaf_pos,
-    const int32_t* __restrict__ leaf_n, const typename Tr<ST>::V* __restrict__ yh,
-    const typename Tr<ST>::V* __restrict__ Xc, int R, typename Tr<ST>::V* __restrict__ Yc) {
+    const int32_t* __restrict__ leaf_n, const typename Tr<ST>::VB* __restrict__ yh,
+    const typename Tr<ST>::VB* __restrict__ Xc, int R, typename Tr<ST>::V* __restrict__ Yc) {
   __shared__ LdsOf<ST, NT> L;
   backward_body<ST, NT>(L, blockIdx.x, B, b_off, b_nkb, zoff, zmap, leaf_pos, leaf_n, yh, Xc, R, Yc);
 }
@@ -771,8 +799,10 @@ __global__ __launch_bounds__(64 * kLpWaves) void k_lp_backward(
 // work[b] = (operator, item): item is a 256-element block for the element-wise stages,
 // a leaf for forward/backward, a coupling tile index (into the descriptor's tile array).
 
-template <class V>
+template <int ST>
 __global__ __launch_bounds__(256) void k_lpb_gather(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
+  using V = typename Tr<ST>::V;
+  using VB = typename Tr<ST>::VB;
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];
   if (d.xcol) {
@@ -780,11 +810,11 @@ __global__ __launch_bounds__(256) void k_lpb_gather(const LpDesc* __restrict__ D
     if (q >= d.n * d.R) return;
     const int64_t pos = q / d.R;
     const int j = (int)(q - pos * d.R);
-    static_cast<V*>(d.Xc)[q] = j < d.r ? from_c128<V>(d.xcol[j][d.perm[pos]]) : vzero<V>();
+    static_cast<VB*>(d.Xc)[q] = j < d.r ? to_vb<VB>(from_c128<V>(d.xcol[j][d.perm[pos]])) : vzero<VB>();
     return;
   }
-  gather_body<V>((int64_t)wk.y * 256 + threadIdx.x, static_cast<const V*>(d.x), d.ldx, d.r, d.R, d.perm, d.n,
-                 static_cast<V*>(d.Xc));
+  gather_body((int64_t)wk.y * 256 + threadIdx.x, static_cast<const V*>(d.x), d.ldx, d.r, d.R, d.perm, d.n,
+              static_cast<VB*>(d.Xc));
 }
 
 template <class V>
@@ -808,56 +838,64 @@ template <int ST, int NT>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lpb_forward(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
   __shared__ LdsOf<ST, NT> L;
   using V = typename Tr<ST>::V;
+  using VB = typename Tr<ST>::VB;
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];
   forward_body<ST, NT>(L, wk.y, d.F, d.f_off, d.f_M, d.f_nkb, d.f_pos, d.f_n, d.poff,
-                       static_cast<const V*>(d.Xc), d.R, static_cast<V*>(d.p));
+                       static_cast<const VB*>(d.Xc), d.R, static_cast<V*>(d.p));
 }
 
-template <class V>
+template <int ST>
 __global__ __launch_bounds__(256) void k_lpb_reduce_segments(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
+  using V = typename Tr<ST>::V;
+  using VB = typename Tr<ST>::VB;
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];
-  reduce_segments_body<V>((int64_t)wk.y * 256 + threadIdx.x, static_cast<const V*>(d.p), d.R, d.poff, d.out_seg,
-                          d.seg_start, d.seg_pan0, d.seg_npan, d.seg_col, d.nxh, static_cast<V*>(d.xh));
+  reduce_segments_body((int64_t)wk.y * 256 + threadIdx.x, static_cast<const V*>(d.p), d.R, d.poff, d.out_seg,
+                       d.seg_start, d.seg_pan0, d.seg_npan, d.seg_col, d.nxh, static_cast<VB*>(d.xh));
 }
 
-template <int ST, int NT>
+// OV as in k_lp_coupling (VB for the factored first pass, whose descriptor's part points
+// into the coupling source vector)
+template <int ST, int NT, class OV>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lpb_coupling(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
   __shared__ LdsOf<ST, NT> L;
-  using V = typename Tr<ST>::V;
+  using VB = typename Tr<ST>::VB;
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];
   const LpCoupTile T = d.ctiles[wk.y];
-  coupling_body<ST, NT>(L, T, d.S, d.colsrc, static_cast<const V*>(d.xh), d.R, static_cast<V*>(d.part));
+  coupling_body<ST, NT, OV>(L, T, d.S, d.colsrc, static_cast<const VB*>(d.xh), d.R, static_cast<OV*>(d.part));
 }
 
 template <int ST, int NT>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lpb_factor(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
   __shared__ LdsOf<ST, NT> L;
-  using V = typename Tr<ST>::V;
+  using VB = typename Tr<ST>::VB;
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];
   const LpCoupTile T = d.ctiles[wk.y];
-  factor_body<ST, NT>(L, T, d.S, d.colsrc, static_cast<const V*>(d.xh), d.R, static_cast<V*>(d.part));
+  factor_body<ST, NT>(L, T, d.S, d.colsrc, static_cast<const VB*>(d.xh), d.R, static_cast<VB*>(d.part));
 }
 
-template <class V>
+template <int ST>
 __global__ __launch_bounds__(256) void k_lpb_reduce_coupling(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
+  using V = typename Tr<ST>::V;
+  using VB = typename Tr<ST>::VB;
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];
-  reduce_coupling_body<V>((int64_t)wk.y * 256 + threadIdx.x, static_cast<const V*>(d.part), d.R, d.yh_grp, d.grp_start,
-                          d.grp_t0, d.grp_nt, d.nyh, static_cast<V*>(d.yh));
+  reduce_coupling_body((int64_t)wk.y * 256 + threadIdx.x, static_cast<const V*>(d.part), d.R, d.yh_grp, d.grp_start,
+                       d.grp_t0, d.grp_nt, d.nyh, static_cast<VB*>(d.yh));
 }
 
 template <int ST, int NT>
 __global__ __launch_bounds__(64 * kLpWaves) void k_lpb_backward(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
   __shared__ LdsOf<ST, NT> L;
   using V = typename Tr<ST>::V;
+  using VB = typename Tr<ST>::VB;
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];
   backward_body<ST, NT>(L, wk.y, d.B, d.b_off, d.b_nkb, d.zoff, d.zmap, d.leaf_pos, d.leaf_n,
-                        static_cast<const V*>(d.yh), static_cast<const V*>(d.Xc), d.R, static_cast<V*>(d.Yc));
+                        static_cast<const VB*>(d.yh), static_cast<const VB*>(d.Xc), d.R, static_cast<V*>(d.Yc));
 }
 
 }  // namespace
@@ -1340,19 +1378,21 @@ int lowp_upload_t(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, 
 template <int ST, int NT>
 void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, int64_t ldy, int r, int R, hipStream_t s) {
   using V = typename Tr<ST>::V;
+  using VB = typename Tr<ST>::VB;
+  static_assert(sizeof(VB) == sizeof(V), "workspace sized by the vector element");
   const V* x = static_cast<const V*>(xv);
   V* y = static_cast<V*>(yv);
-  V* Xc = reinterpret_cast<V*>(lp->Xc.p);
+  VB* Xc = reinterpret_cast<VB*>(lp->Xc.p);
   V* Yc = reinterpret_cast<V*>(lp->Yc.p);
   V* p = reinterpret_cast<V*>(lp->p.p);
-  V* xh = reinterpret_cast<V*>(lp->xh.p);
+  VB* xh = reinterpret_cast<VB*>(lp->xh.p);
   V* part = reinterpret_cast<V*>(lp->part.p);
-  V* yh = reinterpret_cast<V*>(lp->yh.p);
+  VB* yh = reinterpret_cast<VB*>(lp->yh.p);
   const int nl = op->nleaves;
   const int64_t n = op->n;
   {
     ScopedTiming tm(op, s, K_LP_GATHER);
-    hipLaunchKernelGGL(k_lp_gather<V>, dim3((unsigned)((n * R + 255) / 256)), dim3(256), 0, s, x, ldx, r, R,
+    hipLaunchKernelGGL(k_lp_gather<ST>, dim3((unsigned)((n * R + 255) / 256)), dim3(256), 0, s, x, ldx, r, R,
                        op->perm.p, n, Xc);
   }
   if (lp->nxh > 0) {
@@ -1363,7 +1403,7 @@ void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, i
     }
     {
       ScopedTiming tm(op, s, K_LP_REDUCE_FWD);
-      hipLaunchKernelGGL(k_lp_reduce_segments<V>, dim3((unsigned)((lp->nxh * R + 255) / 256)), dim3(256), 0, s, p, R,
+      hipLaunchKernelGGL(k_lp_reduce_segments<ST>, dim3((unsigned)((lp->nxh * R + 255) / 256)), dim3(256), 0, s, p, R,
                          lp->poff.p, lp->out_seg.p, lp->seg_start.p, lp->seg_pan0.p, lp->seg_npan.p, lp->seg_col.p,
                          lp->nxh, xh);
     }
@@ -1376,18 +1416,18 @@ void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, i
   }
   if (lp->ntctiles > 0) {
     ScopedTiming tm(op, s, K_LP_FACTOR_IN);
-    hipLaunchKernelGGL((k_lp_coupling<ST, NT>), dim3(lp->ntctiles), dim3(64 * kLpWaves), 0, s, lp->ST.p, lp->tctiles.p,
-                       lp->tcolsrc.p, xh, R, xh + lp->nxh * R);
+    hipLaunchKernelGGL((k_lp_coupling<ST, NT, VB>), dim3(lp->ntctiles), dim3(64 * kLpWaves), 0, s, lp->ST.p,
+                       lp->tctiles.p, lp->tcolsrc.p, xh, R, xh + lp->nxh * R);
   }
   if (lp->nctiles > 0) {
     {
       ScopedTiming tm(op, s, K_LP_COUPLING);
-      hipLaunchKernelGGL((k_lp_coupling<ST, NT>), dim3(lp->nctiles), dim3(64 * kLpWaves), 0, s, lp->S.p, lp->ctiles.p,
-                         lp->colsrc.p, xh, R, part);
+      hipLaunchKernelGGL((k_lp_coupling<ST, NT, V>), dim3(lp->nctiles), dim3(64 * kLpWaves), 0, s, lp->S.p,
+                         lp->ctiles.p, lp->colsrc.p, xh, R, part);
     }
     {
       ScopedTiming tm(op, s, K_LP_REDUCE_COUP);
-      hipLaunchKernelGGL(k_lp_reduce_coupling<V>, dim3((unsigned)((lp->nyh * R + 255) / 256)), dim3(256), 0, s, part, R,
+      hipLaunchKernelGGL(k_lp_reduce_coupling<ST>, dim3((unsigned)((lp->nyh * R + 255) / 256)), dim3(256), 0, s, part, R,
                          lp->yh_grp.p, lp->grp_start.p, lp->grp_t0.p, lp->grp_nt.p, lp->nyh, yh);
     }
   }
@@ -1725,13 +1765,13 @@ void batch_launch_t(LowpBatch* B, hipStream_t s) {
   auto go = [&](auto kern, const DevArray<int2>& w, int threads) {
     if (w.n > 0) hipLaunchKernelGGL(kern, dim3((unsigned)w.n), dim3(threads), 0, s, D, w.p);
   };
-  go(k_lpb_gather<V>, B->w_gather, 256);
+  go(k_lpb_gather<ST>, B->w_gather, 256);
   go(k_lpb_forward<ST, NT>, B->w_forward, 64 * kLpWaves);
-  go(k_lpb_reduce_segments<V>, B->w_rseg, 256);
+  go(k_lpb_reduce_segments<ST>, B->w_rseg, 256);
   go(k_lpb_factor<ST, NT>, B->w_ffac, 64 * kLpWaves);  // factored couplings, first pass
-  go(k_lpb_coupling<ST, NT>, B->w_fcoup, 64 * kLpWaves);
-  go(k_lpb_coupling<ST, NT>, B->w_coup, 64 * kLpWaves);
-  go(k_lpb_reduce_coupling<V>, B->w_rcoup, 256);
+  go(k_lpb_coupling<ST, NT, typename Tr<ST>::VB>, B->w_fcoup, 64 * kLpWaves);
+  go(k_lpb_coupling<ST, NT, V>, B->w_coup, 64 * kLpWaves);
+  go(k_lpb_reduce_coupling<ST>, B->w_rcoup, 256);
   go(k_lpb_backward<ST, NT>, B->w_backward, 64 * kLpWaves);
   go(k_lpb_scatter<V>, B->w_scatter, 256);
 }
@@ -1782,13 +1822,13 @@ void step_launch(const LpDesc* D, const int2* const* w, const unsigned* cnt, hip
   auto go = [&](auto kern, int st, int threads) {
     if (cnt[st] > 0) hipLaunchKernelGGL(kern, dim3(cnt[st]), dim3(threads), 0, s, D, w[st]);
   };
-  go(k_lpb_gather<V>, 0, 256);
+  go(k_lpb_gather<ST>, 0, 256);
   go(k_lpb_forward<ST, NT>, 1, 64 * kLpWaves);
-  go(k_lpb_reduce_segments<V>, 2, 256);
+  go(k_lpb_reduce_segments<ST>, 2, 256);
   go(k_lpb_factor<ST, NT>, 8, 64 * kLpWaves);  // factored couplings, first pass
-  go(k_lpb_coupling<ST, NT>, 7, 64 * kLpWaves);
-  go(k_lpb_coupling<ST, NT>, 3, 64 * kLpWaves);
-  go(k_lpb_reduce_coupling<V>, 4, 256);
+  go(k_lpb_coupling<ST, NT, typename Tr<ST>::VB>, 7, 64 * kLpWaves);
+  go(k_lpb_coupling<ST, NT, V>, 3, 64 * kLpWaves);
+  go(k_lpb_reduce_coupling<ST>, 4, 256);
   go(k_lpb_backward<ST, NT>, 5, 64 * kLpWaves);
   go(k_lpb_scatter<V>, 6, 256);
 }
