@@ -393,14 +393,14 @@ def run_construct(args):
     worst = max((sm["approx_rel_diff"] for sm in sample), default=None)
     build = None
     if args.full_build:
-        # the whole operator with the ACA factors recompressed on the GPU, checked on sampled
-        # rows against the dense matrix (within 10 eps |(A x) on those rows|)
+        # the whole operator built with the GPU sampling (ACA, packing, near field), checked on
+        # sampled rows against the dense matrix (within 10 eps |(A x) on those rows|)
         from oracle import kernel, uniform
         del dev_pts
         torch.cuda.empty_cache()
         t = time.perf_counter()
         op = builder.build_operator(cloud, leaf=args.leaf, eta=1.0, eps_aca=eps, eps_comp=1e-6, construct="gpu",
-                                    recompress_on="gpu", verbose=True)
+                                    verbose=True)
         total = time.perf_counter() - t
         leaves = np.nonzero(np.bincount(op.parent[op.parent >= 0], minlength=op.nclusters) == 0)[0]
         pick = np.random.default_rng(12345).choice(leaves, size=4, replace=False)
@@ -411,7 +411,7 @@ def run_construct(args):
         dop = binding.upload(op, "c128")
         yfull = float(np.linalg.norm(dop.matvec(torch.from_numpy(x).to("cuda")).cpu().numpy()))
         dop.free()
-        build = {"construct": "gpu", "recompress": "gpu", "seconds": round(total, 2),
+        build = {"construct": "gpu", "seconds": round(total, 2),
                  **{k: round(v, 3) for k, v in op.timings.items()},
                  "sampled_err_vs_dense": float(np.linalg.norm(ref[:, 0] - dense)),
                  "ten_eps_norm_Ax_sampled_rows": 10 * 1e-6 * float(np.linalg.norm(dense)),
@@ -621,13 +621,10 @@ def main():
                          "current kernel source)")
     ap.add_argument("--construct", choices=("gpu", "host"), default="gpu",
                     help="headline: sample the operator's blocks (ACA, near field) on the GPU or on the host")
-    ap.add_argument("--compress", choices=("gpu", "host"), default="host",
-                    help="headline: the uniform compression on the host (LAPACK SVDs) or with its large products "
-                         "on the GPU (Gram-matrix form)")
     ap.add_argument("--direct-only", action="store_true",
                     help="direct mode: skip the two-phase build (which holds the H and UH forms at once)")
     ap.add_argument("--full-build", action="store_true",
-                    help="construct mode: also build the whole operator with the ACA factors recompressed on the GPU")
+                    help="construct mode: also build the whole operator and check it against the dense matrix")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (the calibration kernel for the byte counters)")
     args = ap.parse_args()
@@ -673,7 +670,7 @@ def main():
     cloud = inputs.make_cloud("sphere", args.n, seed=args.seed)
     log(f"building operator N={cloud.n} kappa={cloud.kappa:.3f} h={cloud.h:.5f}")
     op = builder.build_operator(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, verbose=True,
-                                construct=args.construct, compress_on=args.compress)
+                                construct=args.construct)
     st = op.stats()
     log(f"built in {time.perf_counter() - t0:.1f} s: {json.dumps(op.timings)}")
     log(json.dumps(st))
@@ -779,12 +776,18 @@ def main():
         lowp = {}
         r = args.lowp_rhs
         X64 = inputs.make_rhs(cloud.n, r, seed=args.seed + 7)
-        Xd = torch.from_numpy(np.ascontiguousarray(X64.T.astype(np.complex64))).to("cuda").t()
-        Yd = torch.empty((r, cloud.n), dtype=torch.complex64, device="cuda").t()
+        Xd32 = torch.from_numpy(np.ascontiguousarray(X64.T.astype(np.complex64))).to("cuda").t()
+        Yd32 = torch.empty((r, cloud.n), dtype=torch.complex64, device="cuda").t()
+        Xd128 = torch.from_numpy(np.ascontiguousarray(X64.T)).to("cuda").t()
+        Yd128 = torch.empty((r, cloud.n), dtype=torch.complex128, device="cuda").t()
         x1 = x.to(torch.complex64)
         y1 = torch.empty_like(x1)
+        # many right-hand sides on the matrix cores (bound by them for complex64 and FP64,
+        # by HBM for bf16 pairs: 8 r / e flop per operator byte), and one right-hand side in
+        # the streaming forms (HBM-bound)
         for st_name, peak_tf, e_bytes in (("c64", 157.3, 8), ("bf16pair", 2500.0, 4), ("c64fact", 157.3, 8),
-                                          ("bf16pairfact", 2500.0, 4)):
+                                          ("bf16pairfact", 2500.0, 4), ("c128multi", 78.6, 16),
+                                          ("c64stream", None, 8), ("bf16pairstream", None, 4)):
             tl = time.perf_counter()
             dl = binding.upload(op, storage=st_name, stream=stream)
             log(f"{st_name} upload {time.perf_counter() - tl:.1f} s")
@@ -792,24 +795,36 @@ def main():
             # elements the form multiplies (the factored forms apply fewer coupling elements)
             M_uh = li["elems_forward"] + li["elems_coupling"] + li["elems_coupling_in"] + li["elems_backward"] + \
                 li["elems_near"]
-            t_r, k_r = time_products(torch, dl, Xd, Yd, max(5, args.steps // 5), 2, stream)
-            t_1, k_1 = time_products(torch, dl, x1, y1, args.steps, args.warmup, stream)
-            y1n = y1.cpu().numpy().astype(np.complex128)
+            ve = 16 if st_name == "c128multi" else 8   # vector element bytes
+            ent = {"nrhs": r}
+            if peak_tf is not None:
+                Xd, Yd = (Xd128, Yd128) if ve == 16 else (Xd32, Yd32)
+                t_r, k_r = time_products(torch, dl, Xd, Yd, max(5, args.steps // 5), 2, stream)
+                flops = 8.0 * r * M_uh
+                bytes_r = e_bytes * M_uh + ve * r * (2 * cloud.n + 4 * info["rank_space"])
+                ent.update({
+                    "ms_per_mvp": t_r * 1e3, "rhs_per_s": r / t_r,
+                    "tflops": flops / t_r / 1e12, "mfma_peak_tflops": peak_tf,
+                    "mfma_frac": flops / t_r / 1e12 / peak_tf,
+                    "gbs": bytes_r / t_r / 1e9, "hbm_frac": bytes_r / t_r / 1e9 / HBM_PEAK_GBS,
+                    "kernels_ms": {k: v[0] for k, v in k_r.items()}})
+                log(f"{st_name}: {r} RHS {t_r * 1e3:.3f} ms ({flops / t_r / 1e12:.1f} TFLOP/s, "
+                    f"{bytes_r / t_r / 1e9:.0f} GB/s)")
+            if ve == 16:
+                xs1, ys1 = x, torch.empty_like(x)
+            else:
+                xs1, ys1 = x1, y1
+            t_1, k_1 = time_products(torch, dl, xs1, ys1, args.steps, args.warmup, stream)
+            y1n = ys1.cpu().numpy().astype(np.complex128)
             err_vs_fp64 = float(np.linalg.norm(y1n - y_uh) / np.linalg.norm(y_uh))
-            flops = 8.0 * r * M_uh
-            bytes_r = e_bytes * M_uh + 8 * r * (2 * cloud.n + 4 * info["rank_space"])
-            lowp[st_name] = {
-                "nrhs": r, "ms_per_mvp": t_r * 1e3, "rhs_per_s": r / t_r,
-                "tflops": flops / t_r / 1e12, "mfma_peak_tflops": peak_tf, "mfma_frac": flops / t_r / 1e12 / peak_tf,
-                "gbs": bytes_r / t_r / 1e9, "hbm_frac": bytes_r / t_r / 1e9 / HBM_PEAK_GBS,
-                "kernels_ms": {k: v[0] for k, v in k_r.items()},
-                "single_rhs_ms": t_1 * 1e3, "single_rhs_gbs": (e_bytes * M_uh + 16 * cloud.n) / t_1 / 1e9,
-                "rel_err_vs_fp64": err_vs_fp64,
-            }
-            log(f"{st_name}: {r} RHS {t_r * 1e3:.3f} ms ({flops / t_r / 1e12:.1f} TFLOP/s), 1 RHS {t_1 * 1e3:.3f} ms, "
-                f"err vs FP64 {err_vs_fp64:.2e}")
+            g1 = (e_bytes * M_uh + 2 * ve * cloud.n) / t_1 / 1e9
+            ent.update({"single_rhs_ms": t_1 * 1e3, "single_rhs_gbs": g1, "single_rhs_hbm_frac": g1 / HBM_PEAK_GBS,
+                        "single_rhs_kernels_ms": {k: v[0] for k, v in k_1.items()},
+                        "rel_err_vs_fp64": err_vs_fp64, "elem_bytes": e_bytes})
+            lowp[st_name] = ent
+            log(f"{st_name}: 1 RHS {t_1 * 1e3:.3f} ms ({g1:.0f} GB/s), err vs FP64 {err_vs_fp64:.2e}")
             dl.free()
-        del Xd, Yd
+        del Xd32, Yd32, Xd128, Yd128
 
     gm = None
     if not args.no_gmres:
@@ -874,7 +889,7 @@ def main():
             cl = inputs.make_cloud("sphere", args.n, seed=sd)
             tb = time.perf_counter()
             op_s = builder.build_operator(cl, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6,
-                                          construct=args.construct, compress_on=args.compress)
+                                          construct=args.construct)
             log(f"seed {sd}: built in {time.perf_counter() - tb:.1f} s")
             img = builder.symmetric_image(op_s) if sym is not None else op_s
             d_s = binding.upload(img, "c128sym" if sym is not None else "c128", stream=stream)
@@ -940,7 +955,7 @@ def main():
         "per_product_ms": pp_sy if sym is not None else pp_uh,
         "per_seed": per_seed,
         "operator": {k: st[k] for k in ("nadm", "nden", "c_sp", "l_max", "k_max", "bytes_uh_c128", "bytes_h_c128")},
-        "build": {"construct": args.construct, "compress": args.compress, **{k: round(v, 3) for k, v in op.timings.items()}},
+        "build": {"construct": args.construct, **{k: round(v, 3) for k, v in op.timings.items()}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "hbm_context": ctx,

@@ -71,7 +71,12 @@ typedef enum {
   UHM_C64_FACTORED = 6,     /* UHM_C64 with factored couplings where they store fewer elements
                                (the same rule); the image must carry adm_rank, SX and SY */
   UHM_BF16PAIR_FACTORED = 7, /* UHM_BF16PAIR with factored couplings, likewise */
-  UHM_C128_MULTI_FACTORED = 8 /* UHM_C128_MULTI with factored couplings, likewise */
+  UHM_C128_MULTI_FACTORED = 8, /* UHM_C128_MULTI with factored couplings, likewise */
+  UHM_C64_STREAM = 9,      /* complex64 storage in the layout of UHM_C128 (one lane per panel
+                              column or row, the operator streamed once per right-hand side),
+                              FP32 arithmetic; vectors complex64.  For one or a few right-hand
+                              sides, where the MFMA forms pad to 16 columns.  uhm_upload only */
+  UHM_BF16PAIR_STREAM = 10 /* the same with (re, im) bfloat16-pair storage; vectors complex64 */
 } uhm_storage;
 
 typedef struct uhm_op uhm_op; /* opaque; owned by the library until uhm_free */
@@ -421,6 +426,21 @@ int uhm_aca(const double* points, int64_t npoints, double kappa, double diag,
             const uhm_block_desc* blocks, int64_t nblocks, int32_t max_rows, int32_t max_cap, double eps,
             double* U, int64_t U_len, double* V, int64_t V_len, int32_t* piv, int64_t piv_len,
             int32_t* rank, int32_t* status, void* hip_stream);
+
+/*
+ * The factors of blocks sel[0..cnt) of an earlier uhm_aca call, packed for their algebraic
+ * recompression (section 2.3): block b = sel[c] (all of them m x n, rank[b] <= kp terms)
+ * gives X[c] = [u_0 .. u_{k-1} 0 ..] and Y[c] = [conj(v_0) .. conj(v_{k-1}) 0 ..], each a
+ * row-major m x kp (n x kp) complex128 matrix, so that A|_b ~ X[c] Y[c]^*.  blocks, rank, U,
+ * V are that call's device arrays (its descriptors, its outputs); sel, X (cnt m kp complex
+ * elements), Y (cnt n kp) and status (cnt) are device arrays.  status[c] = 1 for a packed
+ * block, -1 for one whose descriptor does not match (m, n), whose rank exceeds kp or its cap,
+ * or whose factors lie outside U_len / V_len (written as zeros).  Nothing is allocated;
+ * asynchronous on hip_stream.  Errors: UHM_EINVAL (sizes, null pointers), UHM_EHIP.
+ */
+int uhm_aca_pack(const uhm_block_desc* blocks, int64_t nblocks, const int32_t* rank, const double* U, int64_t U_len,
+                 const double* V, int64_t V_len, const int32_t* sel, int32_t cnt, int32_t m, int32_t n, int32_t kp,
+                 double* X, double* Y, int32_t* status, void* hip_stream);
 
 const char* uhm_strerror(int code);
 const char* uhm_last_error(void);

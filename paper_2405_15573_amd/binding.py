@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libuhm.so")
 
 UHM_OK, UHM_EINVAL, UHM_ENOMEM, UHM_EHIP, UHM_ENOCONV, UHM_ENOTSUP = 0, -1, -2, -3, -4, -5
 STORAGE = {"c128": 0, "c64": 1, "bf16pair": 2, "c128multi": 3, "c128sym": 4, "c128fact": 5, "c64fact": 6,
-           "bf16pairfact": 7, "c128multifact": 8}
+           "bf16pairfact": 7, "c128multifact": 8, "c64stream": 9, "bf16pairstream": 10}
 FACTORED_FORMS = ("c128fact", "c64fact", "bf16pairfact", "c128multifact")
 C128_FORMS = ("c128", "c128multi", "c128sym", "c128fact", "c128multifact")
 
@@ -79,7 +79,7 @@ EXPORTS = ("uhm_upload", "uhm_upload_h", "uhm_matvec", "uhm_matvec_noalloc", "uh
            "uhm_batch_create", "uhm_batch_run",
            "uhm_batch_tune", "uhm_batch_capture", "uhm_batch_free", "uhm_op_info_get", "uhm_set_timing",
            "uhm_kernel_times", "uhm_free", "uhm_strerror", "uhm_last_error", "uhm_version",
-           "uhm_kernel_blocks", "uhm_aca")
+           "uhm_kernel_blocks", "uhm_aca", "uhm_aca_pack")
 
 _LIB = None
 
@@ -145,6 +145,8 @@ def load_library(path: str = LIB_PATH):
     lib.uhm_kernel_blocks.argtypes = [P, I64, D, D, P, I64, P, I64, P, P]
     lib.uhm_kernel_blocks.restype = ctypes.c_int
     lib.uhm_aca.argtypes = [P, I64, D, D, P, I64, I32, I32, D, P, I64, P, I64, P, I64, P, P, P]
+    lib.uhm_aca_pack.argtypes = [P, I64, P, P, I64, P, I64, P, I32, I32, I32, I32, P, P, P, P]
+    lib.uhm_aca_pack.restype = ctypes.c_int
     lib.uhm_aca.restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -568,9 +570,10 @@ class AcaResult:
     (int32 tensor), the host arrays rank, status, and the per-block offsets u_off, v_off, p_off
     and caps."""
 
-    def __init__(self, U, V, piv, rank, status, desc):
+    def __init__(self, U, V, piv, rank, status, desc, desc_dev=None, rank_dev=None):
         self.U, self.V, self.piv = U, V, piv
         self.rank, self.status = rank, status
+        self.desc_dev, self.rank_dev = desc_dev, rank_dev   # the call's device descriptors and ranks
         self.u_off, self.v_off, self.p_off = desc["a_off"].copy(), desc["b_off"].copy(), desc["p_off"].copy()
         self.rows, self.cols, self.cap = (desc["rows"].astype(np.int64), desc["cols"].astype(np.int64),
                                           desc["cap"].astype(np.int64))
@@ -618,4 +621,30 @@ def aca(points, kappa: float, diag: float, row_off, rows, col_off, cols, cap, ep
         rk = rank.cpu().numpy()
     if (st < 0).any():
         raise UhmError(UHM_EINVAL, f"uhm_aca: {int((st < 0).sum())} descriptors rejected")
-    return AcaResult(U, V, piv, rk, st, d)
+    return AcaResult(U, V, piv, rk, st, d, dd, rank)
+
+
+def aca_pack(res: AcaResult, sel, m: int, n: int, kp: int, stream=None):
+    """The factors of blocks `sel` of an ACA result (all m x n) packed by uhm_aca_pack:
+    X (cnt, m, kp) and Y (cnt, n, kp) device tensors with A|_b ~ X Y^H, zero columns beyond
+    each block's rank."""
+    import torch
+    lib = load_library()
+    sel = np.ascontiguousarray(sel, dtype=np.int32)
+    cnt = int(sel.size)
+    h, stream = _stream_handle(stream)
+    with torch.cuda.stream(stream):
+        X = torch.empty((cnt, m, kp), dtype=torch.complex128, device="cuda")
+        Y = torch.empty((cnt, n, kp), dtype=torch.complex128, device="cuda")
+        status = torch.empty(max(1, cnt), dtype=torch.int32, device="cuda")
+        sd = torch.from_numpy(sel).to("cuda")
+        _check(lib.uhm_aca_pack(ctypes.c_void_p(res.desc_dev.data_ptr()), len(res.rows),
+                                ctypes.c_void_p(res.rank_dev.data_ptr()), ctypes.c_void_p(res.U.data_ptr()),
+                                res.U.numel(), ctypes.c_void_p(res.V.data_ptr()), res.V.numel(),
+                                ctypes.c_void_p(sd.data_ptr()), cnt, int(m), int(n), int(kp),
+                                ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                                ctypes.c_void_p(status.data_ptr()), h), "uhm_aca_pack")
+        st = status.cpu().numpy()[:cnt]
+    if (st != 1).any():
+        raise UhmError(UHM_EINVAL, f"uhm_aca_pack: {int((st != 1).sum())} blocks rejected")
+    return X, Y

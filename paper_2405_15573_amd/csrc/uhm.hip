@@ -1219,6 +1219,10 @@ int upload_sym(const uhm_host_operator* h, hipStream_t s, const TreeInfo& T, uhm
 
 }  // namespace
 
+namespace uhm_detail {
+int grow_workspace_fp64(uhm_op* op) { return grow_workspace(op); }
+}  // namespace uhm_detail
+
 extern "C" {
 
 int uhm_version(void) { return 1; }
@@ -1242,7 +1246,7 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
   *out = nullptr;
   if (storage != UHM_C128 && storage != UHM_C64 && storage != UHM_BF16PAIR && storage != UHM_C128_MULTI &&
       storage != UHM_C128_SYM && storage != UHM_C128_FACTORED && storage != UHM_C64_FACTORED &&
-      storage != UHM_BF16PAIR_FACTORED && storage != UHM_C128_MULTI_FACTORED)
+      storage != UHM_BF16PAIR_FACTORED && storage != UHM_C128_MULTI_FACTORED && !is_stream(storage))
     return fail(UHM_EINVAL, "unknown storage precision");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   TreeInfo T;
@@ -1302,7 +1306,7 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
   op->kind = 0;
   op->storage = storage;
   if ((rc = common_tree_upload(op.get(), T, h->perm, h->off, h->size, s))) return rc;
-  if (storage != UHM_C128 && storage != UHM_C128_FACTORED) {
+  if (storage != UHM_C128 && storage != UHM_C128_FACTORED && !is_stream(storage)) {
     if ((rc = lowp_upload(h, storage, s, T, op.get()))) return rc;
     *out = op.release();
     return UHM_OK;
@@ -1527,9 +1531,15 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
   I.elems_near = 0;
   for (int64_t b = 0; b < h->nden; ++b) I.elems_near += h->size[h->den_row[b]] * h->size[h->den_col[b]];
   I.rank_space = nxh;
-  I.device_bytes = (int64_t)(op->F.bytes() + op->S.bytes() + op->B.bytes() + op->zmap.bytes() + op->perm.bytes() +
-                             op->ctiles.bytes() + op->cblk.bytes() + op->out_seg.bytes() + op->yh_grp.bytes() +
-                             op->FY.bytes() + op->factiles.bytes());
+  if (is_stream(storage)) {
+    // the complex128 panels become the storage element
+    if ((rc = stream_compact(op.get(), s))) return rc;
+    I.elem_bytes = storage == UHM_C64_STREAM ? 8 : 4;
+  }
+  I.device_bytes = (int64_t)(op->F.bytes() + op->S.bytes() + op->B.bytes() + op->Fs.bytes() + op->Ss.bytes() +
+                             op->Bs.bytes() + op->zmap.bytes() + op->perm.bytes() + op->ctiles.bytes() +
+                             op->cblk.bytes() + op->out_seg.bytes() + op->yh_grp.bytes() + op->FY.bytes() +
+                             op->factiles.bytes());
   *out = op.release();
   return UHM_OK;
 }
@@ -1794,6 +1804,7 @@ int uhm_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if (op->lp) return lowp_matvec(op, X, ldx, Y, ldy, nrhs, s);
+  if (is_stream(op->storage)) return stream_matvec(op, X, ldx, Y, ldy, nrhs, s);
   if ((rc = grow_workspace(op))) return rc;
   const Fp64Ws w{op->ws_p.p, op->ws_xh.p, op->ws_part.p, op->ws_yh.p, op->ws_tpart.p, op->ws_td.p};
   return matvec_fp64(op, X, ldx, Y, ldy, nrhs, s, w);
@@ -1803,7 +1814,8 @@ int uhm_matvec_noalloc(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t 
                        void* hip_stream) {
   if (!op) return fail(UHM_EINVAL, "null operator");
   if (nrhs < 0) return fail(UHM_EINVAL, "nrhs < 0");
-  if (op->lp) return fail(UHM_ENOTSUP, "uhm_matvec_noalloc takes the complex128 single-RHS storage forms only");
+  if (op->lp || !is_c128(op->storage))
+    return fail(UHM_ENOTSUP, "uhm_matvec_noalloc takes the complex128 single-RHS storage forms only");
   if (nrhs == 0) return UHM_OK;
   int rc = check_vectors(op, X, ldx, Y, ldy, nrhs);
   if (rc) return rc;
@@ -1915,7 +1927,7 @@ int uhm_op_info_get(const uhm_op* op, uhm_op_info* info) {
   if (!op || !info) return fail(UHM_EINVAL, "null argument");
   *info = op->info;
   int64_t off[6];
-  info->scratch_bytes = op->lp ? 0 : fp64_ws_layout(op, off) * (int64_t)sizeof(cd);
+  info->scratch_bytes = (op->lp || !is_c128(op->storage)) ? 0 : fp64_ws_layout(op, off) * (int64_t)sizeof(cd);
   return UHM_OK;
 }
 

@@ -1129,6 +1129,8 @@ int uhm_krylov_step(uhm_krylov* const* ks, uhm_op* const* high, uhm_op* const* l
     if (K->req == UHM_KRYLOV_DONE) continue;
     uhm_op* A = K->req == UHM_KRYLOV_PRODUCT_HIGH ? high[k] : (low ? low[k] : nullptr);
     if (!A || A->n != K->n || A->kind != 0) return fail(UHM_EINVAL, "missing or mismatched operator for a solve");
+    if (!A->lp && !is_c128(A->storage))
+      return fail(UHM_ENOTSUP, "uhm_krylov_step takes complex128 or many-RHS low-precision operators");
     const bool want_hi = K->req == UHM_KRYLOV_PRODUCT_HIGH;
     const bool is_hi = is_c128(A->storage);
     if (want_hi != is_hi) return fail(UHM_EINVAL, "operator precision does not match the request");

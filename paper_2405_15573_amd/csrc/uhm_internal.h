@@ -247,6 +247,8 @@ struct uhm_op {
   DevArray<cd> B;
   DevArray<int64_t> bwd_off, zoff;
   DevArray<int32_t> bwd_cols, zmap;
+  // streaming low-precision forms: F, S and B converted to the storage element
+  DevArray<unsigned char> Fs, Ss, Bs;
   // symmetric storage (Remark 4.4): stored blocks applied as S_b and S_b^T, dense blocks
   // as A|_b and A|_b^T; the transposed products go through partial buffers
   bool sym = false;
@@ -310,6 +312,12 @@ struct ScopedTiming {
 };
 
 inline bool in_bounds(int64_t off, int64_t count, int64_t len) { return off >= 0 && count >= 0 && off + count <= len; }
+
+// Streaming low-precision forms (the complex128 layout with compact elements).
+inline bool is_stream(int storage) { return storage == UHM_C64_STREAM || storage == UHM_BF16PAIR_STREAM; }
+int stream_compact(uhm_op* op, hipStream_t s);
+int stream_matvec(uhm_op* op, const void* X, int64_t ldx, void* Y, int64_t ldy, int32_t nrhs, hipStream_t s);
+int grow_workspace_fp64(uhm_op* op);
 
 // Storage forms whose vectors and arithmetic are complex128.
 inline bool is_c128(int storage) {

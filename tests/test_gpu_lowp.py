@@ -49,22 +49,24 @@ def _run(torch, dop, x, ld_pad=0):
 CASES = [("sphere", 2048, 0, 32), ("sphere", 3000, 3, 64), ("cube", 1300, 5, 32), ("ellipsoid", 1500, 4, 32)]
 
 
-@pytest.mark.parametrize("storage", ["c64", "bf16pair"])
+@pytest.mark.parametrize("storage", ["c64", "bf16pair", "c64stream", "bf16pairstream"])
 @pytest.mark.parametrize("surface,n,seed,leaf", CASES)
 def test_lowp_single_rhs(torch_dev, storage, surface, n, seed, leaf):
+    """The MFMA forms (one column padded to 16) and the streaming forms (one lane per panel
+    column or row, the complex128 layout with compact elements)."""
     from paper_2405_15573_amd import binding
     print(f"case {storage} {surface} n={n} seed={seed} leaf={leaf}", flush=True)
     cloud, op = operator(surface=surface, n=n, seed=seed, leaf=leaf)
     dop = binding.upload(op, storage=storage)
     x = inputs.make_rhs(cloud.n, 1, seed=seed).astype(np.complex64).astype(np.complex128)
     y = _run(torch_dev, dop, x)
-    ref_r = uniform.uh_mvp(precision.round_operator(vars(op), storage), x)
+    ref_r = uniform.uh_mvp(precision.round_operator(vars(op), storage.replace("stream", "")), x)
     ref = uniform.uh_mvp(vars(op), x)
     e_arith = _col_rel(y, ref_r).max()
     e_full = _col_rel(y, ref).max()
     print(f"  arithmetic err {e_arith:.2e}  vs FP64 operator {e_full:.2e}", flush=True)
     assert e_arith <= 2e-5
-    assert e_full <= (1e-5 if storage == "c64" else 2e-2)
+    assert e_full <= (1e-5 if storage.startswith("c64") else 2e-2)
     assert dop.info()["storage"] == binding.STORAGE[storage]
 
 
@@ -84,14 +86,37 @@ def test_lowp_multi_rhs(torch_dev, storage, nrhs):
     assert np.linalg.norm(y[:, 0] - y0[:, 0]) / np.linalg.norm(y0[:, 0]) <= 1e-6
 
 
+@pytest.mark.parametrize("storage", ["c64stream", "bf16pairstream"])
+def test_stream_forms_several_columns_and_errors(torch_dev, storage):
+    """The streaming forms with several right-hand sides and padded leading dimensions (one
+    column after another: each equals its single-column product bitwise), and the calls they
+    refuse: the solver step and the allocation-free product take other forms."""
+    from paper_2405_15573_amd import binding
+    torch = torch_dev
+    print(f"case {storage} several columns", flush=True)
+    cloud, op = operator(n=3000, seed=3, leaf=64)
+    dop = binding.upload(op, storage=storage)
+    x = inputs.make_rhs(cloud.n, 5, seed=45).astype(np.complex64).astype(np.complex128)
+    y = _run(torch, dop, x, ld_pad=5)
+    ref_r = uniform.uh_mvp(precision.round_operator(vars(op), storage.replace("stream", "")), x)
+    assert _col_rel(y, ref_r).max() <= 2e-5
+    y2 = _run(torch, dop, x[:, 2:3])
+    assert np.array_equal(y[:, 2], y2[:, 0])
+    info = dop.info()
+    assert info["elem_bytes"] == (8 if storage == "c64stream" else 4) and info["scratch_bytes"] == 0
+    xt = torch.from_numpy(np.ascontiguousarray(x[:, 0].astype(np.complex64))).to("cuda")
+    with pytest.raises(binding.UhmError):
+        dop.matvec_noalloc(xt, torch.empty_like(xt))
+
+
 def test_lowp_dense_only(torch_dev):
     from paper_2405_15573_amd import binding
-    for storage in ("c64", "bf16pair"):
+    for storage in ("c64", "bf16pair", "c64stream", "bf16pairstream"):
         cloud, op = operator(n=60, leaf=32)
         dop = binding.upload(op, storage=storage)
         x = inputs.make_rhs(cloud.n, 3, seed=1).astype(np.complex64).astype(np.complex128)
         y = _run(torch_dev, dop, x)
-        ref_r = uniform.uh_mvp(precision.round_operator(vars(op), storage), x)
+        ref_r = uniform.uh_mvp(precision.round_operator(vars(op), storage.replace("stream", "")), x)
         assert _col_rel(y, ref_r).max() <= 2e-5
 
 
