@@ -305,175 +305,19 @@ def _to_host(t):
     return h.numpy()
 
 
-def _host_buffer(shape, dtype, pinned):
-    """A zeroed host array, page-locked when it is to be copied to the device."""
-    if not pinned:
-        return np.zeros(shape, dtype)
-    import torch
-    tdt = {np.dtype(np.complex128): torch.complex128, np.dtype(np.float64): torch.float64}[np.dtype(dtype)]
-    return torch.zeros(shape, dtype=tdt, pin_memory=True).numpy()
-
-
-def _eigh(G):
-    """np.linalg.eigh over a batch, split across the builder's threads."""
-    nw = min(_workers(), G.shape[0])
-    if nw <= 1:
-        return np.linalg.eigh(G)
-    parts = _pmap(np.linalg.eigh, np.array_split(G, nw))
-    return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
-
-
-def _pack_factors(res, pos, rel, m, n, on_device=False):
+def _pack_factors(res, pos, rel, m, n):
     """Factors of the blocks pos[rel] of one shape group of an ACA result (blocks pos are
-    contiguous, all m x n with one cap c): X (cnt, m, kp) = u and Y (cnt, n, kp) = conj(v),
-    zero beyond each block's rank, kp the group's largest rank.  Packed where the result
-    lives (the device) and copied to the host once."""
-    import torch
-    c = int(res.cap[pos[0]])
-    a0, b0 = int(res.u_off[pos[0]]), int(res.v_off[pos[0]])
+    contiguous, all m x n): X (cnt, m, kp) = u and Y (cnt, n, kp) = conj(v), zero beyond each
+    block's rank, kp the group's largest rank.  Packed on the device by uhm_aca_pack and
+    copied to the host once."""
+    from . import binding
     rank = res.rank[pos[rel]]
     kp = int(rank.max())
-    dev = res.U.device
-    sel = torch.from_numpy(np.ascontiguousarray(rel, dtype=np.int64)).to(dev)
-    Ud = res.U[a0:a0 + len(pos) * c * m].view(len(pos), c, m).index_select(0, sel)[:, :kp, :]
-    Vd = res.V[b0:b0 + len(pos) * c * n].view(len(pos), c, n).index_select(0, sel)[:, :kp, :]
-    live = (torch.arange(kp, device=dev)[None, :] < torch.from_numpy(rank.astype(np.int64)).to(dev)[:, None])[:, :, None]
-    zero = torch.zeros((), dtype=Ud.dtype, device=dev)
-    X = torch.where(live, Ud, zero).transpose(1, 2).contiguous()
-    Y = torch.conj_physical(torch.where(live, Vd, zero)).transpose(1, 2).contiguous()
-    if on_device:
-        return X, Y, rank
+    X, Y = binding.aca_pack(res, np.asarray(pos)[rel], int(m), int(n), kp)
     return _to_host(X), _to_host(Y)
 
 
-def _chol_inv(G):
-    """R = chol(G)^* (upper, G = R^* R) and R^{-1} over a batch, split across the builder's
-    threads."""
-    def one(g):
-        r = np.conj(np.swapaxes(np.linalg.cholesky(g), 1, 2))
-        return r, np.linalg.inv(r)
-    nw = min(_workers(), G.shape[0])
-    if nw <= 1:
-        return one(G)
-    parts = _pmap(one, np.array_split(G, nw))
-    return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
-
-
-def _chol_qr_batched(A, live, device):
-    """Cholesky QR, twice, of a batch of tall matrices A (cnt, m, kp) on `device`, with the
-    columns first scaled to unit norm; columns beyond a matrix's live count are zero and stay
-    zero.  Returns Q (device) and R (host, cnt x kp x kp) with A = Q R, R zero outside the
-    live block.  The Gram matrices and their Cholesky factors (kp x kp) are formed on the host."""
-    import torch
-    cnt, m, kp = A.shape
-    live_c = live[:, :, None] & live[:, None, :]
-    d = torch.linalg.vector_norm(A, dim=1).cpu().numpy()
-    d = np.where(live & (d > 0), d, 1.0)
-    Q = A / torch.from_numpy(d).to(device)[:, None, :]
-    R = np.broadcast_to(np.eye(kp, dtype=np.complex128), (cnt, kp, kp)).copy()
-    for _ in range(2):
-        G = _to_host(torch.bmm(Q.transpose(1, 2).conj().contiguous(), Q)).copy()
-        G = np.where(live_c, G, np.eye(kp))
-        Rk, Rinv = _chol_inv(G)   # G = Rk^* Rk
-        Rinv = np.ascontiguousarray(Rinv * live_c)
-        Q = torch.bmm(Q, torch.from_numpy(Rinv).to(device))
-        R = Rk @ R
-    R = R * d[:, None, :] * live_c
-    return Q, R
-
-
-def _recompress_gpu(Xd, Yd, ranks, eps_rec, device="cuda"):
-    """Algebraic recompression (section 2.3) of a batch of ACA factorisations A_b ~ X_b Y_b^*
-    with the tall products on the GPU: X = Q_X R_X and Y = Q_Y R_Y by Cholesky QR
-    (_chol_qr_batched), the SVD of the small core R_X R_Y^* = W Sigma Z^* on the host, and
-    U_b = Q_X W, V_b = Q_Y Z truncated at sigma_i > eps_rec sigma_1.  Xd (cnt, m, kp) and
-    Yd (cnt, n, kp) are device tensors, zero beyond each block's ACA rank `ranks`.  Returns
-    per block (U_b, sigma_b, V_b) on the host."""
-    import torch
-    cnt, m, kp = Xd.shape
-    live = np.arange(kp)[None, :] < np.asarray(ranks)[:, None]
-    QX, RX = _chol_qr_batched(Xd, live, device)
-    QY, RY = _chol_qr_batched(Yd, live, device)
-    core = RX @ np.conj(np.swapaxes(RY, 1, 2))
-    nw = min(_workers(), cnt)
-    parts = _pmap(np.linalg.svd, np.array_split(core, nw)) if nw > 1 else [np.linalg.svd(core)]
-    W = np.concatenate([p[0] for p in parts])
-    sv = np.concatenate([p[1] for p in parts])
-    Zh = np.concatenate([p[2] for p in parts])
-    ks = np.array([max(1, int(np.count_nonzero(sv[c] > eps_rec * sv[c, 0]))) if sv[c, 0] > 0 else 1
-                   for c in range(cnt)])
-    kmax = int(ks.max())
-    keep = (np.arange(kmax)[None, :] < ks[:, None])[:, None, :]
-    Wk = np.ascontiguousarray(W[:, :, :kmax] * keep)
-    Zk = np.ascontiguousarray(np.conj(np.swapaxes(Zh, 1, 2))[:, :, :kmax] * keep)
-    U = _to_host(torch.bmm(QX, torch.from_numpy(Wk).to(device)))
-    V = _to_host(torch.bmm(QY, torch.from_numpy(Zk).to(device)))
-    return [(np.ascontiguousarray(U[c][:, :ks[c]]), sv[c, :ks[c]].copy(), np.ascontiguousarray(V[c][:, :ks[c]]))
-            for c in range(cnt)]
-
-
-def _compress_gpu(Xb, ks, eps_comp, device="cuda"):
-    """Alg. 2's per-cluster step for a batch of row clusters of one size, with the large
-    products as batched GEMMs on the GPU and only small Hermitian eigenproblems on the host.
-
-    Xb (cnt, n, kp): the agglomerations X_tau = [U_b Sigma_b] (zero-padded columns); ks: the
-    true column counts.  The leading left singular subspace of X_tau comes from the
-    eigenvectors of the smaller Gram matrix: X X^* (n <= kp) gives it directly; otherwise
-    X^* X = W Lambda W^* gives Y = X W_l Lambda_l^{-1/2}, made orthonormal by one Cholesky
-    QR step.  The rank is l = #{sigma_i > eps sigma_1}, at most ks, with sigma_i^2 the
-    eigenvalues.  The coefficients are the projection L = Q^* X, and sigma_{l+1} and
-    sqrt(sum_{i>l} sigma_i^2) are taken from the residual X - Q L (its largest singular
-    value and its Frobenius norm).  Returns per cluster (l, Q (n x l), sigma_{l+1}, tail,
-    L (l x kp)).  `device` is where the products run (a torch device name)."""
-    import torch
-    cnt, n, kp = Xb.shape
-    Xd = torch.from_numpy(Xb).to(device)
-    XdH = Xd.transpose(1, 2).conj().contiguous()
-    ks = np.asarray(ks)
-
-    def ranks(lam):
-        sg = np.sqrt(np.maximum(lam[:, ::-1], 0.0))
-        ls = np.array([max(1, int(np.count_nonzero(sg[c] > eps_comp * sg[c, 0]))) if sg[c, 0] > 0 else 1
-                       for c in range(cnt)])
-        return np.minimum(ls, ks)
-
-    if n <= kp:
-        lam, W = _eigh(_to_host(torch.bmm(Xd, XdH)))
-        ls = ranks(lam)
-        lmax = int(ls.max())
-        Q = np.ascontiguousarray(W[:, :, ::-1][:, :, :lmax] * (np.arange(lmax)[None, None, :] < ls[:, None, None]))
-        Qd = torch.from_numpy(Q).to(device)
-    else:
-        lam, W = _eigh(_to_host(torch.bmm(XdH, Xd)))
-        ls = ranks(lam)
-        lmax = int(ls.max())
-        sg = np.sqrt(np.maximum(lam[:, ::-1][:, :lmax], 0.0))
-        live = np.arange(lmax)[None, :] < ls[:, None]
-        scale = np.where(live, 1.0 / np.where(live, sg, 1.0), 0.0)
-        Wl = np.ascontiguousarray(W[:, :, ::-1][:, :, :lmax] * scale[:, None, :])
-        Yd = torch.bmm(Xd, torch.from_numpy(Wl).to(device))
-        C = _to_host(torch.bmm(Yd.transpose(1, 2).conj().contiguous(), Yd)).copy()
-        C[:, np.arange(lmax), np.arange(lmax)] = np.where(live, C[:, np.arange(lmax), np.arange(lmax)], 1.0)
-        Rinv = np.linalg.inv(np.conj(np.swapaxes(np.linalg.cholesky(C), 1, 2)))   # C = R^* R, R upper
-        Rinv = np.ascontiguousarray(Rinv * (live[:, :, None] & live[:, None, :]))
-        Qd = torch.bmm(Yd, torch.from_numpy(Rinv).to(device))
-        del Yd
-    Ld = torch.bmm(Qd.transpose(1, 2).conj().contiguous(), Xd)
-    Rd = Xd - torch.bmm(Qd, Ld)
-    del Xd, XdH
-    small = Rd.transpose(1, 2).conj().contiguous()
-    Gr = _to_host(torch.bmm(Rd, small) if n <= kp else torch.bmm(small, Rd))
-    del Rd, small
-    lr = np.linalg.eigvalsh(Gr)
-    dropped = np.sqrt(np.maximum(lr[:, -1], 0.0))
-    tail = np.sqrt(np.maximum(np.trace(Gr, axis1=1, axis2=2).real, 0.0))
-    Q = _to_host(Qd)
-    L = _to_host(Ld)
-    return [(int(ls[c]), np.ascontiguousarray(Q[c][:, :ls[c]]), float(dropped[c]), float(tail[c]),
-             L[c][:ls[c], :]) for c in range(cnt)]
-
-
-def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_cap=128, eps_rec=None):
+def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_cap=128):
     """ACA of one level's blocks on the GPU (uhm_aca).  Blocks whose first pass stopped at
     its rank capacity run again with a four times larger one, up to kcap.  Returns the ranks
     and, per (shape, pass) group, (block indices, X (cnt, m, kp), Y (cnt, n, kp)) with
@@ -501,13 +345,8 @@ def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_
             keep = pos[final[pos]]
             if keep.size == 0:
                 continue
-            if eps_rec is not None:   # recompress on the device; the group then holds (U_b, sigma_b, V_b)
-                Xd, Yd, rk = _pack_factors(res, pos, keep - pos[0], int(m), int(n), on_device=True)
-                groups.append((idx[keep], int(m), int(n), _recompress_gpu(Xd, Yd, rk, eps_rec), None))
-                del Xd, Yd
-            else:
-                X, Y = _pack_factors(res, pos, keep - pos[0], int(m), int(n))
-                groups.append((idx[keep], int(m), int(n), X, Y))
+            X, Y = _pack_factors(res, pos, keep - pos[0], int(m), int(n))
+            groups.append((idx[keep], int(m), int(n), X, Y))
         todo = idx[~final]
         cap_now *= 4
         del res
@@ -516,23 +355,16 @@ def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_
 
 def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca: float = 1e-6,
                    eps_comp: float = 1e-6, eps_rec: float | None = None, kcap: int = 1024,
-                   verbose: bool = False, construct: str = "host", compress_on: str = "host",
-                   compress_device: str = "cuda", recompress_on: str = "host") -> HostOperator:
+                   verbose: bool = False, construct: str = "host") -> HostOperator:
     """Build the H form and the UH form of the point-kernel matrix A_ij = g(x_i, x_j),
     A_ii = 1/(2h), for one seeded cloud.
 
     construct="gpu" samples the matrix on the GPU: ACA of the admissible blocks
-    (uhm_aca) and the dense near-field blocks (uhm_kernel_blocks); the recompression and
-    the uniform compression stay on the host.  construct="host" does everything on the
-    host (OpenMP C++ and LAPACK).  compress_on="gpu" runs the large products of the uniform
-    compression (Alg. 2) as batched GEMMs (_compress_gpu) on compress_device (a torch device
-    name; "cpu" runs the same steps on the host, for tests).  recompress_on="gpu"
-    (with construct="gpu") recompresses the ACA factors where they are, on the GPU
-    (_recompress_gpu), and copies only the recompressed factors to the host."""
-    if construct not in ("host", "gpu") or compress_on not in ("host", "gpu") or recompress_on not in ("host", "gpu"):
-        raise ValueError("construct, compress_on and recompress_on must be 'host' or 'gpu'")
-    if recompress_on == "gpu" and construct != "gpu":
-        raise ValueError("recompress_on='gpu' needs construct='gpu' (the ACA factors must be on the GPU)")
+    (uhm_aca), whose factors are packed by shape on the device (uhm_aca_pack), and the dense
+    near-field blocks (uhm_kernel_blocks); the recompression and the uniform compression
+    run on the host.  construct="host" does everything on the host (OpenMP C++ and LAPACK)."""
+    if construct not in ("host", "gpu"):
+        raise ValueError("construct must be 'host' or 'gpu'")
     lib = _native()
     if eps_rec is None:
         eps_rec = eps_aca / 10.0
@@ -571,8 +403,7 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
         ta = time.perf_counter()
         handle = None
         if construct == "gpu":
-            kout, gpu_groups, ks = _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps_aca, kcap,
-                                                  eps_rec=eps_rec if recompress_on == "gpu" else None)
+            kout, gpu_groups, ks = _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps_aca, kcap)
             t_aca_kernel += ks
         else:
             handle = lib.uhmb_aca_run(_ptr(pts), kappa, diag, nb, _ptr(roff), _ptr(rsz), _ptr(coff), _ptr(csz),
@@ -608,13 +439,7 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
 
         try:
             jobs = []
-            if handle is None and recompress_on == "gpu":
-                for sel, m, n, facs, _ in gpu_groups:
-                    for b, (Ub, sb, Vb) in zip(sel, facs):
-                        key = (int(blk[b, 0]), int(blk[b, 1]))
-                        fac_U[key], fac_s[key], fac_V[key] = Ub, sb, Vb
-                del gpu_groups
-            elif handle is None:
+            if handle is None:
                 for sel, m, n, X, Y in gpu_groups:
                     kp = X.shape[2]
                     step = max(1, len(list(_chunks(sel, 16 * (m + n) * kp * 4, parts=4 * _workers()))[0]))
@@ -667,10 +492,10 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
     for t in clusters:
         ks = sum(fac_s[(min(t, s), max(t, s))].size for s in row_blocks[t])
         groups.setdefault((int(size[t])), []).append((int(t), ks))
-    def agglomerate(part, pinned=False):
+    def agglomerate(part):
         nt = int(size[part[0][0]])
         kp = max(k for _, k in part)
-        Xb = _host_buffer((len(part), nt, kp), np.complex128, pinned)
+        Xb = np.zeros((len(part), nt, kp), np.complex128)
         cols = []
         for c, (t, _) in enumerate(part):
             j = 0
@@ -699,23 +524,11 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
                         [(s, np.ascontiguousarray(SV[:, j:j + kb])) for s, j, kb in cols[c]]))
         return out
 
-    def compress_gpu(part):
-        Xb, cols = agglomerate(part, pinned=compress_device != "cpu")
-        out = []
-        for c, (l, Ut, dropped, tail, SV) in enumerate(_compress_gpu(Xb, [k for _, k in part], eps_comp,
-                                                                     compress_device)):
-            out.append((part[c][0], l, Ut, dropped, tail,
-                        [(s, np.ascontiguousarray(SV[:, j:j + kb])) for s, j, kb in cols[c]]))
-        return [out]
-
     jobs = []
     for nt, members in groups.items():
         kp_all = max(k for _, k in members)
-        if compress_on == "gpu":
-            jobs.extend(_chunks(members, 16 * nt * kp_all * 4, budget=1 << 32))
-        else:
-            jobs.extend(_chunks(members, 16 * nt * kp_all * 3, parts=2 * _workers()))
-    results = [r for job in jobs for r in compress_gpu(job)] if compress_on == "gpu" else _pmap(compress, jobs)
+        jobs.extend(_chunks(members, 16 * nt * kp_all * 3, parts=2 * _workers()))
+    results = _pmap(compress, jobs)
     for res in results:
         for t, l, Ut, dropped, tail, Ls in res:
             rank[t] = l

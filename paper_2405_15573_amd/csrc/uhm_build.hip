@@ -327,6 +327,44 @@ __global__ __launch_bounds__(64 * W) void k_aca(const double* __restrict__ pts, 
   }
 }
 
+// Packing of ACA factors for the recompression: one workgroup per selected block, one
+// thread per packed element in output order (row-major m x kp, then n x kp), so the writes
+// are contiguous; the reads walk the column-major factors, whose lines the workgroup's
+// neighbouring rows reuse from the caches.
+constexpr int kPackThreads = 256;
+__global__ __launch_bounds__(kPackThreads) void k_aca_pack(const uhm_block_desc* __restrict__ blocks, int64_t nblocks,
+                                                           const int32_t* __restrict__ rank,
+                                                           const double2* __restrict__ U, int64_t U_len,
+                                                           const double2* __restrict__ V, int64_t V_len,
+                                                           const int32_t* __restrict__ sel, int32_t m, int32_t n,
+                                                           int32_t kp, double2* __restrict__ X, double2* __restrict__ Y,
+                                                           int32_t* __restrict__ status) {
+  const int c = blockIdx.x;
+  const int32_t b = sel[c];
+  bool ok = b >= 0 && b < nblocks;
+  uhm_block_desc d{};
+  int32_t k = 0;
+  if (ok) {
+    d = blocks[b];
+    k = rank[b];
+    ok = d.rows == m && d.cols == n && k >= 0 && k <= kp && k <= d.cap && d.a_off >= 0 && d.b_off >= 0 &&
+         d.a_off + (int64_t)k * m <= U_len && d.b_off + (int64_t)k * n <= V_len;
+  }
+  if (!ok) k = 0;  // a rejected block is written as zeros
+  double2* Xc = X + (int64_t)c * m * kp;
+  double2* Yc = Y + (int64_t)c * n * kp;
+  for (int64_t q = threadIdx.x; q < (int64_t)m * kp; q += kPackThreads) {
+    const int i = (int)(q / kp), l = (int)(q - (int64_t)i * kp);
+    Xc[q] = l < k ? U[d.a_off + (int64_t)l * m + i] : make_double2(0.0, 0.0);
+  }
+  for (int64_t q = threadIdx.x; q < (int64_t)n * kp; q += kPackThreads) {
+    const int j = (int)(q / kp), l = (int)(q - (int64_t)j * kp);
+    const double2 v = l < k ? V[d.b_off + (int64_t)l * n + j] : make_double2(0.0, 0.0);
+    Yc[q] = make_double2(v.x, -v.y);
+  }
+  if (threadIdx.x == 0) status[c] = ok ? 1 : -1;
+}
+
 // Wavefronts per block for a launch: enough that each thread holds about 8 of the largest
 // block's rows, between 1 and 16.
 int aca_waves(int32_t max_rows) {
@@ -388,6 +426,21 @@ int uhm_aca(const double* points, int64_t npoints, double kappa, double diag, co
     default:
       return fail(UHM_EINVAL, "uhm_aca: internal wave count");
   }
+  UHM_HIP(hipGetLastError());
+  return UHM_OK;
+}
+
+int uhm_aca_pack(const uhm_block_desc* blocks, int64_t nblocks, const int32_t* rank, const double* U, int64_t U_len,
+                 const double* V, int64_t V_len, const int32_t* sel, int32_t cnt, int32_t m, int32_t n, int32_t kp,
+                 double* X, double* Y, int32_t* status, void* hip_stream) {
+  if (nblocks < 0 || U_len < 0 || V_len < 0 || cnt < 0 || m < 1 || n < 1 || kp < 1)
+    return fail(UHM_EINVAL, "uhm_aca_pack: bad size");
+  if (cnt == 0) return UHM_OK;
+  if (!blocks || !rank || !U || !V || !sel || !X || !Y || !status) return fail(UHM_EINVAL, "uhm_aca_pack: null pointer");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  k_aca_pack<<<dim3((unsigned)cnt), dim3(kPackThreads), 0, s>>>(
+      blocks, nblocks, rank, reinterpret_cast<const double2*>(U), U_len, reinterpret_cast<const double2*>(V), V_len, sel,
+      m, n, kp, reinterpret_cast<double2*>(X), reinterpret_cast<double2*>(Y), status);
   UHM_HIP(hipGetLastError());
   return UHM_OK;
 }

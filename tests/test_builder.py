@@ -131,35 +131,6 @@ def test_save_load_roundtrip(tmp_path, small_op):
     assert np.array_equal(op2.S, op.S) and np.array_equal(op2.perm, op.perm)
 
 
-def test_pack_factors_layout():
-    """The packing of GPU ACA output for the recompression (builder._pack_factors), on CPU
-    tensors: X[c] = u (m x kp), Y[c] = conj(v) (n x kp), zero beyond each block's rank, for
-    the selected blocks of a contiguous shape group, whatever the unused columns hold."""
-    import torch
-    from types import SimpleNamespace
-    from paper_2405_15573_amd import builder
-    rng = np.random.default_rng(3)
-    nb, m, n, c = 5, 7, 4, 3
-    ranks = np.array([2, 3, 1, 3, 2])
-    U = rng.normal(size=(nb, c, m)) + 1j * rng.normal(size=(nb, c, m))   # column l of block b at [b, l]
-    V = rng.normal(size=(nb, c, n)) + 1j * rng.normal(size=(nb, c, n))
-    Uf = np.concatenate([np.full(5, 9.0 + 9j), U.ravel()])
-    Vf = np.concatenate([np.full(5, 9.0 + 9j), V.ravel()])
-    res = SimpleNamespace(U=torch.from_numpy(Uf), V=torch.from_numpy(Vf), rank=np.concatenate([[1], ranks]),
-                          cap=np.full(nb + 1, c), u_off=np.concatenate([[0], 5 + np.arange(nb) * c * m]),
-                          v_off=np.concatenate([[0], 5 + np.arange(nb) * c * n]))
-    pos = np.arange(1, nb + 1)
-    rel = np.array([0, 1, 3, 4])
-    X, Y = builder._pack_factors(res, pos, rel, m, n)
-    kp = 3
-    assert X.shape == (4, m, kp) and Y.shape == (4, n, kp)
-    for q, r in enumerate(rel):
-        k = ranks[r]
-        assert np.array_equal(X[q, :, :k], U[r, :k, :].T)
-        assert np.array_equal(Y[q, :, :k], np.conj(V[r, :k, :]).T)
-        assert np.all(X[q, :, k:] == 0) and np.all(Y[q, :, k:] == 0)
-
-
 def test_memory_ratio_soft_check():
     """A soft check against the paper's Tables 1-2, not parity: the UH form stores less than
     the H form of the same operator, total memory H/UH within the paper's 1.3-2.7x.  The
@@ -172,63 +143,3 @@ def test_memory_ratio_soft_check():
     adm = (op.X.size + op.Y.size) / (op.U.size + op.V.size + op.S.size)
     assert 1.3 <= ratio <= 2.7
     assert adm > 1.0
-
-
-def test_recompression_by_cholesky_qr():
-    """builder._recompress_gpu (Cholesky QR of the column-scaled ACA factors, twice, then the
-    SVD of the small core), run with CPU tensors, against the Householder-QR recompression of
-    the same factors: the same ranks, and U Sigma V^* equal to 1e-12 of |X Y^*|."""
-    import torch
-    cloud = inputs.make_cloud("cube", 3000, seed=1)
-    tree = builder.build_tree(cloud.points, 64)
-    pts = np.ascontiguousarray(cloud.points[tree.perm])
-    adm, _ = builder.build_block_tree(tree, 1.0)
-    low = adm[adm[:, 0] < adm[:, 1]]
-    shape = np.stack([tree.size[low[:, 0]], tree.size[low[:, 1]]], 1)
-    m, n = (int(v) for v in shape[0])
-    sel = low[(shape[:, 0] == m) & (shape[:, 1] == n)][:40]
-    lib = builder._native()
-    facs = []
-    for t, s in sel:
-        X = np.empty((m, 64), np.complex128)
-        Y = np.empty((n, 64), np.complex128)
-        k = lib.uhmb_aca_block(builder._ptr(pts), cloud.kappa, 1.0 / (2 * cloud.h), int(tree.off[t]), m,
-                               int(tree.off[s]), n, 1e-6, 64, builder._ptr(X), builder._ptr(Y))
-        facs.append((X[:, :k].copy(), Y[:, :k].copy()))
-    ranks = np.array([f[0].shape[1] for f in facs])
-    kp = int(ranks.max())
-    Xb = np.zeros((len(facs), m, kp), np.complex128)
-    Yb = np.zeros((len(facs), n, kp), np.complex128)
-    for c, (X, Y) in enumerate(facs):
-        Xb[c, :, :X.shape[1]] = X
-        Yb[c, :, :Y.shape[1]] = Y
-    got = builder._recompress_gpu(torch.from_numpy(Xb), torch.from_numpy(Yb), ranks, 1e-7, device="cpu")
-    for (X, Y), (Ub, sb, Vb) in zip(facs, got):
-        QX, RX = np.linalg.qr(X)
-        QY, RY = np.linalg.qr(Y)
-        W, sv, Zh = np.linalg.svd(RX @ RY.conj().T)
-        r = max(1, int(np.count_nonzero(sv > 1e-7 * sv[0])))
-        ref = (QX @ W[:, :r]) * sv[:r] @ (QY @ Zh[:r].conj().T).conj().T
-        assert sb.size == r
-        assert np.linalg.norm(Ub.conj().T @ Ub - np.eye(r)) < 1e-13
-        assert np.linalg.norm((Ub * sb) @ Vb.conj().T - ref) <= 1e-12 * np.linalg.norm(X @ Y.conj().T)
-
-
-def test_gram_compression_with_cpu_tensors():
-    """The Gram-matrix form of Alg. 2's per-cluster step (compress_on="gpu"), run with CPU
-    tensors: both of its branches (n_tau <= K and n_tau > K occur on this cloud) give the
-    SVD route's ranks, meet the builder's pins, and the same product to 1e-9."""
-    cloud = inputs.make_cloud("cube", 3000, seed=0)
-    h = builder.build_operator(cloud, leaf=32, eta=1.0, eps_aca=1e-6, eps_comp=1e-6)
-    g = builder.build_operator(cloud, leaf=32, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, compress_on="gpu",
-                               compress_device="cpu")
-    has = g.rank_row > 0
-    kt = np.bincount(g.adm_row, weights=g.adm_rank, minlength=g.nclusters)
-    kmax = {int(sz): int(kt[has & (g.size == sz)].max()) for sz in np.unique(g.size[has])}   # a group's width
-    assert any(sz <= k for sz, k in kmax.items()) and any(sz > k for sz, k in kmax.items())
-    assert np.array_equal(g.rank_row, h.rank_row)
-    for fn in (test_orthogonal_bases_and_conjugate_symmetry, test_couplings_are_optimal,
-               test_theorem_5_1_and_frobenius_identity, test_algorithm_1_and_2_give_the_same_basis):
-        fn((cloud, g))
-    x = inputs.make_rhs(cloud.n, 2, seed=1)
-    assert rel(uniform.uh_mvp(vars(g), x), uniform.uh_mvp(vars(h), x)) <= 1e-9

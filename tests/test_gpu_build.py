@@ -14,11 +14,8 @@
   oracle's pin covers it on the CPU.
 * The builder with construct="gpu" gives the operator of construct="host": the same ranks
   and block structure, and the same product to 1e-9.
-* The Gram-matrix form of Alg. 2's per-cluster step (compress_on="gpu") meets the pins the
-  host builder meets (tests/test_builder.py): orthonormal bases, optimal couplings, Thm
-  5.1's bounds, and Alg. 1's ranks and optimal projection error; with the host builder's
-  ranks its product agrees with the host-built operator's to 1e-9.
-* So does the GPU recompression of the ACA factors (recompress_on="gpu").
+* The packing of the ACA factors for the recompression (uhm_aca_pack) gives each block's
+  u and conj(v) columns exactly, zero beyond its rank, and rejects a block of another shape.
 * An operator from the direct construction (no H form kept) multiplies on the GPU like any
   other, in the general, symmetric and factored FP64 forms (1e-12 against the oracle).
 """
@@ -184,22 +181,36 @@ def test_builder_gpu_construction(torch_dev, surface, n, seed, leaf):
     assert rel(uniform.h_mvp(vars(g), x), uniform.h_mvp(vars(h), x)) <= 1e-9
 
 
-@pytest.mark.parametrize("surface,n,leaf", [("sphere", 2048, 32), ("ellipsoid", 4000, 64), ("cube", 3000, 32)])
-def test_gpu_compression_meets_the_builder_pins(torch_dev, surface, n, leaf):
-    import test_builder as tb
-    cloud = inputs.make_cloud(surface, n, seed=0)
-    print(f"case compress_on=gpu {surface} n={cloud.n} leaf={leaf}", flush=True)
-    g = builder.build_operator(cloud, leaf=leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="gpu",
-                               compress_on="gpu")
-    h = builder.build_operator(cloud, leaf=leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="host")
-    for fn in (tb.test_orthogonal_bases_and_conjugate_symmetry, tb.test_couplings_are_optimal,
-               tb.test_theorem_5_1_and_frobenius_identity, tb.test_algorithm_1_and_2_give_the_same_basis):
-        fn((cloud, g))
-    x = inputs.make_rhs(cloud.n, 2, seed=1)
-    d = rel(uniform.uh_mvp(vars(g), x), uniform.uh_mvp(vars(h), x))
-    same = np.array_equal(g.rank_row, h.rank_row)
-    print(f"  ranks equal to the host's: {same}; product difference {d:.2e}", flush=True)
-    assert d <= (1e-9 if same else 1e-5)
+def test_aca_pack_layout(torch_dev):
+    """uhm_aca_pack against the ACA result read block by block (AcaResult.factors): for a
+    selection of blocks of one shape, X[c] = [u_0 .. u_{k-1} 0 ..] and Y[c] = conj of the v
+    columns, exactly; a selection holding a block of another shape is rejected."""
+    from paper_2405_15573_amd import binding
+    cloud = inputs.make_cloud("cube", 3000, seed=1)
+    tree = builder.build_tree(cloud.points, 64)
+    pts = np.ascontiguousarray(cloud.points[tree.perm])
+    adm, _ = builder.build_block_tree(tree, 1.0)
+    low = adm[adm[:, 0] < adm[:, 1]]
+    sz = tree.size
+    m, n = int(sz[low[0, 0]]), int(sz[low[0, 1]])
+    same = np.nonzero((sz[low[:, 0]] == m) & (sz[low[:, 1]] == n))[0][:12]
+    other = np.nonzero((sz[low[:, 0]] != m) | (sz[low[:, 1]] != n))[0][:2]
+    pick = np.concatenate([same, other])
+    blk = low[pick]
+    res = binding.aca(pts, cloud.kappa, 1.0 / (2 * cloud.h), tree.off[blk[:, 0]], sz[blk[:, 0]], tree.off[blk[:, 1]],
+                      sz[blk[:, 1]], 48, 1e-6)
+    sel = np.array([0, 2, 3, 5, 7, 8, 11])
+    kp = int(res.rank[sel].max()) + 2
+    X, Y = binding.aca_pack(res, sel, m, n, kp)
+    X, Y = X.cpu().numpy(), Y.cpu().numpy()
+    for c, b in enumerate(sel):
+        u, v, _, _ = res.factors(int(b))
+        k = u.shape[1]
+        assert np.array_equal(X[c, :, :k], u) and np.array_equal(Y[c, :, :k], np.conj(v))
+        assert np.all(X[c, :, k:] == 0) and np.all(Y[c, :, k:] == 0)
+    if other.size:
+        with pytest.raises(binding.UhmError):
+            binding.aca_pack(res, np.array([0, len(same)]), m, n, kp)
 
 
 def test_direct_operator_on_the_gpu(torch_dev):
@@ -223,25 +234,3 @@ def test_direct_operator_on_the_gpu(torch_dev):
         err = max(np.linalg.norm(y[:, j] - r[:, j]) / np.linalg.norm(r[:, j]) for j in range(3))
         print(f"  {form}: {err:.2e}", flush=True)
         assert err <= 1e-12
-
-
-@pytest.mark.parametrize("surface,n,leaf", [("sphere", 2048, 32), ("cube", 3000, 32)])
-def test_gpu_recompression_meets_the_builder_pins(torch_dev, surface, n, leaf):
-    """construct="gpu" with recompress_on="gpu": the ACA factors are recompressed on the GPU
-    (Cholesky QR of the column-scaled factors, the small core SVD on the host).  The operator
-    meets the builder's pins; with the host builder's ranks its product agrees with the
-    host-built operator's to 1e-9."""
-    import test_builder as tb
-    cloud = inputs.make_cloud(surface, n, seed=0)
-    print(f"case recompress_on=gpu {surface} n={cloud.n} leaf={leaf}", flush=True)
-    g = builder.build_operator(cloud, leaf=leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="gpu",
-                               recompress_on="gpu")
-    h = builder.build_operator(cloud, leaf=leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="host")
-    for fn in (tb.test_orthogonal_bases_and_conjugate_symmetry, tb.test_couplings_are_optimal,
-               tb.test_theorem_5_1_and_frobenius_identity, tb.test_algorithm_1_and_2_give_the_same_basis):
-        fn((cloud, g))
-    x = inputs.make_rhs(cloud.n, 2, seed=1)
-    d = rel(uniform.uh_mvp(vars(g), x), uniform.uh_mvp(vars(h), x))
-    same = np.array_equal(g.rank_row, h.rank_row) and np.array_equal(g.adm_rank, h.adm_rank)
-    print(f"  ranks equal to the host's: {same}; product difference {d:.2e}", flush=True)
-    assert d <= (1e-9 if same else 1e-5)
