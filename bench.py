@@ -196,13 +196,15 @@ def run_batched(args):
     t0 = time.perf_counter()
     for k, (surf, n) in enumerate(pop):
         cloud = inputs.make_cloud(surf, n, seed=args.seed + k)
-        h = builder.build_operator(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6)
+        h = builder.build_operator(cloud, leaf=args.leaf, eta=1.0, eps_aca=1e-6, eps_comp=1e-6,
+                                   construct=args.construct)
         d = binding.upload(h, storage=args.batch_storage, stream=stream)
         r = int(rng.integers(1, 17))
         inf = d.info()
         M = (inf["elems_forward"] + inf["elems_coupling"] + inf["elems_coupling_in"] + inf["elems_backward"]
              + inf["elems_near"])
-        bytes_total += 8 * M + 8 * r * 2 * cloud.n
+        eb = 4 if args.batch_storage.startswith("bf16") else 8   # stored element bytes
+        bytes_total += eb * M + 8 * r * 2 * cloud.n
         flops_total += 8.0 * r * M
         rsum += r
         x = inputs.make_rhs(cloud.n, r, seed=args.seed + 100 + k).astype(np.complex64)
@@ -251,6 +253,10 @@ def run_batched(args):
         "ms_one_operator_at_a_time": t_seq, "ms_batched_untuned": t_untuned, "ms_batched_tuned": t_tuned,
         "ms_batched_graph": t_graph, "speedup_vs_one_at_a_time": t_seq / t_graph, "tuned_schedule": choice,
         "gbs": bytes_total / (t_graph * 1e-3) / 1e9, "tflops": flops_total / (t_graph * 1e-3) / 1e12,
+        "hbm_frac": bytes_total / (t_graph * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "mfma_frac": flops_total / (t_graph * 1e-3) / 1e12 / (2500.0 if args.batch_storage.startswith("bf16")
+                                                             else 157.3),
+        "algorithmic_bytes": bytes_total, "algorithmic_flops": flops_total,
         "max_rel_diff_vs_one_at_a_time": err,
     }
     print(json.dumps(line), flush=True)

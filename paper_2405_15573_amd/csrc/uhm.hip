@@ -130,14 +130,19 @@ hipEvent_t get_event(uhm_op* op) {
 
 int common_tree_upload(uhm_op* op, const TreeInfo& T, const int64_t* perm, const int64_t* off, const int64_t* size,
                        hipStream_t s) {
-  std::vector<int32_t> p32(T.n), lp(T.leaves.size()), ln(T.leaves.size());
-  for (int64_t i = 0; i < T.n; ++i) p32[i] = (int32_t)perm[i];
+  std::vector<int32_t> p32(T.n), ip32(T.n), lp(T.leaves.size()), ln(T.leaves.size());
+  for (int64_t i = 0; i < T.n; ++i) {
+    p32[i] = (int32_t)perm[i];
+    ip32[perm[i]] = (int32_t)i;   // perm was checked to be a permutation
+  }
   for (size_t i = 0; i < T.leaves.size(); ++i) {
     lp[i] = (int32_t)off[T.leaves[i]];
     ln[i] = (int32_t)size[T.leaves[i]];
   }
   int rc;
-  if ((rc = op->perm.upload(p32, s)) || (rc = op->leaf_pos.upload(lp, s)) || (rc = op->leaf_n.upload(ln, s))) return rc;
+  if ((rc = op->perm.upload(p32, s)) || (rc = op->iperm.upload(ip32, s)) || (rc = op->leaf_pos.upload(lp, s)) ||
+      (rc = op->leaf_n.upload(ln, s)))
+    return rc;
   UHM_HIP(hipStreamSynchronize(s));
   op->n = T.n;
   op->nleaves = (int32_t)T.leaves.size();

@@ -219,6 +219,7 @@ struct uhm_op {
   uhm_op_info info{};
 
   DevArray<int32_t> perm, leaf_pos, leaf_n;
+  DevArray<int32_t> iperm;  // user index -> cluster position
   // forward panels and partial sums
   DevArray<cd> F;
   DevArray<int64_t> fwd_off, poff;

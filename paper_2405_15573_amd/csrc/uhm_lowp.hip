@@ -352,7 +352,7 @@ struct LpDesc {
   const uint4 *F, *S, *B;
   const int64_t *f_off, *poff, *b_off, *zoff, *seg_start, *grp_start;
   const int32_t *f_M, *f_nkb, *f_pos, *f_n, *b_nkb, *zmap, *colsrc, *out_seg, *seg_pan0, *seg_npan, *seg_col;
-  const int32_t *yh_grp, *grp_t0, *grp_nt, *leaf_pos, *leaf_n, *perm;
+  const int32_t *yh_grp, *grp_t0, *grp_nt, *leaf_pos, *leaf_n, *perm, *iperm;
   const LpCoupTile* ctiles;
   void *Xc, *Yc, *p, *xh, *part, *yh;
   const void* x;
@@ -363,25 +363,48 @@ struct LpDesc {
   int32_t r, R;
 };
 
-// Xc[pos][j] = x[perm[pos] + j ldx] (cluster order, row-major, R columns, zero beyond r),
-// as B-operand elements.
-template <class V, class VB>
-__device__ __forceinline__ void gather_body(int64_t q, const V* __restrict__ x, int64_t ldx, int r, int R,
-                                            const int32_t* __restrict__ perm, int64_t n, VB* __restrict__ Xc) {
-  if (q >= n * R) return;
-  const int64_t pos = q / R;
-  const int j = (int)(q - pos * R);
-  Xc[q] = j < r ? to_vb<VB>(x[perm[pos] + (int64_t)j * ldx]) : vzero<VB>();
+// The user-order vectors are column-major and the cluster-order images row-major, with rows
+// permuted.  Both directions go through a tile of 64 consecutive user rows staged in LDS:
+// each column's 64 user rows are one contiguous read or write, and each row's R values go
+// to or come from its cluster position as one contiguous run.
+constexpr int kGatherRows = 64;
+constexpr int kGatherThreads = 256;
+
+// Xc[iperm[i]][j] = x(i, j) for the tile's user rows i (zero for j >= r), as B-operand
+// elements.  load(i, j) returns the user-order element.
+template <class V, class VB, class Load>
+__device__ __forceinline__ void gather_tile(int64_t i0, int64_t n, int r, int R, const int32_t* __restrict__ iperm,
+                                            VB* __restrict__ Xc, V* lds, Load load) {
+  const int S = R + 1;
+  for (int e = threadIdx.x; e < kGatherRows * R; e += kGatherThreads) {
+    const int j = e / kGatherRows, il = e - j * kGatherRows;
+    const int64_t i = i0 + il;
+    lds[il * S + j] = (i < n && j < r) ? load(i, j) : vzero<V>();
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kGatherRows * R; e += kGatherThreads) {
+    const int il = e / R, j = e - il * R;
+    const int64_t i = i0 + il;
+    if (i < n) Xc[(int64_t)iperm[i] * R + j] = to_vb<VB>(lds[il * S + j]);
+  }
 }
 
-template <class V>
-__device__ __forceinline__ void scatter_body(int64_t q, const V* __restrict__ Yc, int r, int R,
-                                             const int32_t* __restrict__ perm, int64_t n, V* __restrict__ y,
-                                             int64_t ldy) {
-  if (q >= n * (int64_t)r) return;
-  const int j = (int)(q / n);
-  const int64_t pos = q - (int64_t)j * n;
-  y[perm[pos] + (int64_t)j * ldy] = Yc[pos * R + j];
+// y(i, j) = Yc[iperm[i]][j] for the tile's user rows i and j < r; store(i, j, v) writes it.
+template <class V, class Store>
+__device__ __forceinline__ void scatter_tile(int64_t i0, int64_t n, int r, int R, const int32_t* __restrict__ iperm,
+                                             const V* __restrict__ Yc, V* lds, Store store) {
+  const int S = R + 1;
+  for (int e = threadIdx.x; e < kGatherRows * r; e += kGatherThreads) {
+    const int il = e / r, j = e - il * r;
+    const int64_t i = i0 + il;
+    if (i < n) lds[il * S + j] = Yc[(int64_t)iperm[i] * R + j];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kGatherRows * r; e += kGatherThreads) {
+    const int j = e / kGatherRows, il = e - j * kGatherRows;
+    const int64_t i = i0 + il;
+    if (i < n) store(i, j, lds[il * S + j]);
+  }
 }
 
 // One LDS round covers up to KBR k-blocks.  Its memory requests are issued in batches so a
@@ -707,16 +730,22 @@ __device__ __forceinline__ void backward_body(LdsOf<ST, NT>& L, int leaf, const 
 // ---------------------------------------------------------------- single-operator kernels
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_lp_gather(const typename Tr<ST>::V* __restrict__ x, int64_t ldx, int r, int R,
-                                                   const int32_t* __restrict__ perm, int64_t n,
-                                                   typename Tr<ST>::VB* __restrict__ Xc) {
-  gather_body((int64_t)blockIdx.x * 256 + threadIdx.x, x, ldx, r, R, perm, n, Xc);
+__global__ __launch_bounds__(kGatherThreads) void k_lp_gather(const typename Tr<ST>::V* __restrict__ x, int64_t ldx,
+                                                              int r, int R, const int32_t* __restrict__ iperm,
+                                                              int64_t n, typename Tr<ST>::VB* __restrict__ Xc) {
+  using V = typename Tr<ST>::V;
+  __shared__ V lds[kGatherRows * (kLpRmax + 1)];
+  gather_tile((int64_t)blockIdx.x * kGatherRows, n, r, R, iperm, Xc, lds,
+              [&](int64_t i, int j) { return x[i + (int64_t)j * ldx]; });
 }
 
 template <class V>
-__global__ __launch_bounds__(256) void k_lp_scatter(const V* __restrict__ Yc, int r, int R, const int32_t* __restrict__ perm,
-                                                    int64_t n, V* __restrict__ y, int64_t ldy) {
-  scatter_body<V>((int64_t)blockIdx.x * 256 + threadIdx.x, Yc, r, R, perm, n, y, ldy);
+__global__ __launch_bounds__(kGatherThreads) void k_lp_scatter(const V* __restrict__ Yc, int r, int R,
+                                                               const int32_t* __restrict__ iperm, int64_t n,
+                                                               V* __restrict__ y, int64_t ldy) {
+  __shared__ V lds[kGatherRows * (kLpRmax + 1)];
+  scatter_tile((int64_t)blockIdx.x * kGatherRows, n, r, R, iperm, Yc, lds,
+               [&](int64_t i, int j, V v) { y[i + (int64_t)j * ldy] = v; });
 }
 
 // complex128 -> the storage's vector element, for inputs given as complex128 columns
@@ -799,39 +828,45 @@ __global__ __launch_bounds__(64 * kLpWaves) void k_lp_backward(
 // work[b] = (operator, item): item is a 256-element block for the element-wise stages,
 // a leaf for forward/backward, a coupling tile index (into the descriptor's tile array).
 
+// work item: (operator, tile of kGatherRows user rows)
 template <int ST>
-__global__ __launch_bounds__(256) void k_lpb_gather(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
+__global__ __launch_bounds__(kGatherThreads) void k_lpb_gather(const LpDesc* __restrict__ D,
+                                                               const int2* __restrict__ work) {
   using V = typename Tr<ST>::V;
   using VB = typename Tr<ST>::VB;
+  __shared__ V lds[kGatherRows * (kLpRmax + 1)];
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];
+  const int64_t i0 = (int64_t)wk.y * kGatherRows;
   if (d.xcol) {
-    const int64_t q = (int64_t)wk.y * 256 + threadIdx.x;
-    if (q >= d.n * d.R) return;
-    const int64_t pos = q / d.R;
-    const int j = (int)(q - pos * d.R);
-    static_cast<VB*>(d.Xc)[q] = j < d.r ? to_vb<VB>(from_c128<V>(d.xcol[j][d.perm[pos]])) : vzero<VB>();
-    return;
+    const cd* const* xc = d.xcol;
+    gather_tile(i0, d.n, d.r, d.R, d.iperm, static_cast<VB*>(d.Xc), lds,
+                [&](int64_t i, int j) { return from_c128<V>(xc[j][i]); });
+  } else {
+    const V* x = static_cast<const V*>(d.x);
+    const int64_t ldx = d.ldx;
+    gather_tile(i0, d.n, d.r, d.R, d.iperm, static_cast<VB*>(d.Xc), lds,
+                [&](int64_t i, int j) { return x[i + (int64_t)j * ldx]; });
   }
-  gather_body((int64_t)wk.y * 256 + threadIdx.x, static_cast<const V*>(d.x), d.ldx, d.r, d.R, d.perm, d.n,
-              static_cast<VB*>(d.Xc));
 }
 
 template <class V>
-__global__ __launch_bounds__(256) void k_lpb_scatter(const LpDesc* __restrict__ D, const int2* __restrict__ work) {
+__global__ __launch_bounds__(kGatherThreads) void k_lpb_scatter(const LpDesc* __restrict__ D,
+                                                                const int2* __restrict__ work) {
+  __shared__ V lds[kGatherRows * (kLpRmax + 1)];
   const int2 wk = work[blockIdx.x];
   const LpDesc& d = D[wk.x];
+  const int64_t i0 = (int64_t)wk.y * kGatherRows;
   if (d.ycol) {
-    const int64_t q = (int64_t)wk.y * 256 + threadIdx.x;
-    if (q >= d.n * (int64_t)d.r) return;
-    const int j = (int)(q / d.n);
-    const int64_t pos = q - (int64_t)j * d.n;
-    const V v = static_cast<const V*>(d.Yc)[pos * d.R + j];
-    d.ycol[j][d.perm[pos]] = make_double2((double)v.x, (double)v.y);
-    return;
+    cd* const* yc = d.ycol;
+    scatter_tile(i0, d.n, d.r, d.R, d.iperm, static_cast<const V*>(d.Yc), lds,
+                 [&](int64_t i, int j, V v) { yc[j][i] = make_double2((double)v.x, (double)v.y); });
+  } else {
+    V* y = static_cast<V*>(d.y);
+    const int64_t ldy = d.ldy;
+    scatter_tile(i0, d.n, d.r, d.R, d.iperm, static_cast<const V*>(d.Yc), lds,
+                 [&](int64_t i, int j, V v) { y[i + (int64_t)j * ldy] = v; });
   }
-  scatter_body<V>((int64_t)wk.y * 256 + threadIdx.x, static_cast<const V*>(d.Yc), d.r, d.R, d.perm, d.n,
-                  static_cast<V*>(d.y), d.ldy);
 }
 
 template <int ST, int NT>
@@ -1392,8 +1427,8 @@ void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, i
   const int64_t n = op->n;
   {
     ScopedTiming tm(op, s, K_LP_GATHER);
-    hipLaunchKernelGGL(k_lp_gather<ST>, dim3((unsigned)((n * R + 255) / 256)), dim3(256), 0, s, x, ldx, r, R,
-                       op->perm.p, n, Xc);
+    hipLaunchKernelGGL(k_lp_gather<ST>, dim3((unsigned)((n + kGatherRows - 1) / kGatherRows)), dim3(kGatherThreads), 0, s,
+                       x, ldx, r, R, op->iperm.p, n, Xc);
   }
   if (lp->nxh > 0) {
     {
@@ -1438,7 +1473,8 @@ void launch_all(uhm_op* op, LowpOp* lp, const void* xv, int64_t ldx, void* yv, i
   }
   {
     ScopedTiming tm(op, s, K_LP_SCATTER);
-    hipLaunchKernelGGL(k_lp_scatter<V>, dim3((unsigned)((n * r + 255) / 256)), dim3(256), 0, s, Yc, r, R, op->perm.p, n,
+    hipLaunchKernelGGL(k_lp_scatter<V>, dim3((unsigned)((n + kGatherRows - 1) / kGatherRows)), dim3(kGatherThreads), 0, s,
+                       Yc, r, R, op->iperm.p, n,
                        y, ldy);
   }
 }
@@ -1636,6 +1672,7 @@ LpDesc desc_of(uhm_op* op) {
   d.leaf_pos = op->leaf_pos.p;
   d.leaf_n = op->leaf_n.p;
   d.perm = op->perm.p;
+  d.iperm = op->iperm.p;
   d.n = op->n;
   d.nxh = lp->nxh;
   d.nyh = lp->nyh;
@@ -1702,8 +1739,8 @@ int configure(LowpBatch* B, const BatchConfig& cfg, hipStream_t s) {
     d.R = R;
     descs.push_back(d);
     const int32_t ki = (int32_t)k;
-    for (int64_t b = 0; b < ceil_div(op->n * R, 256); ++b) wg.push_back(make_int2(ki, (int32_t)b));
-    for (int64_t b = 0; b < ceil_div(op->n * bo.r, 256); ++b) wsc.push_back(make_int2(ki, (int32_t)b));
+    for (int64_t b = 0; b < ceil_div(op->n, kGatherRows); ++b) wg.push_back(make_int2(ki, (int32_t)b));
+    for (int64_t b = 0; b < ceil_div(op->n, kGatherRows); ++b) wsc.push_back(make_int2(ki, (int32_t)b));
     if (lp->nxh > 0) {
       for (int32_t l = 0; l < lp->npan; ++l) {
         wf.push_back(make_int2(ki, l));
@@ -1882,7 +1919,7 @@ int lowp_step_products(uhm_op* const* ops, const cd* const* const* xcol, cd* con
     d.R = R;
     descs.push_back(d);
     const int32_t ki = k;
-    for (int64_t b = 0; b < ceil_div(op->n * R, 256); ++b) w[0].push_back(make_int2(ki, (int32_t)b));
+    for (int64_t b = 0; b < ceil_div(op->n, kGatherRows); ++b) w[0].push_back(make_int2(ki, (int32_t)b));
     if (lp->nxh > 0) {
       for (int32_t pn = 0; pn < lp->npan; ++pn) w[1].push_back(make_int2(ki, pn));
       for (int64_t b = 0; b < ceil_div(lp->nxh * R, 256); ++b) w[2].push_back(make_int2(ki, (int32_t)b));
@@ -1891,7 +1928,7 @@ int lowp_step_products(uhm_op* const* ops, const cd* const* const* xcol, cd* con
     if (lp->nctiles > 0)
       for (int64_t b = 0; b < ceil_div(lp->nyh * R, 256); ++b) w[4].push_back(make_int2(ki, (int32_t)b));
     for (int32_t l = 0; l < op->nleaves; ++l) w[5].push_back(make_int2(ki, l));
-    for (int64_t b = 0; b < ceil_div(op->n * (int64_t)ncols[k], 256); ++b) w[6].push_back(make_int2(ki, (int32_t)b));
+    for (int64_t b = 0; b < ceil_div(op->n, kGatherRows); ++b) w[6].push_back(make_int2(ki, (int32_t)b));
     if (lp->ntctiles > 0) {
       const int32_t fi = nops + (int32_t)fdescs.size();
       fdescs.push_back(factor_desc(lp, d, lp->tctiles.p, e));
