@@ -5,7 +5,9 @@ one row per dispatch and counter (values in KiB).  Each counter is scaled by wha
 reads for a plain device copy of known size (a 1 GiB copy run in the same program), so
 that the result is in bytes of the same scale as the algorithmic byte counts.
 
-    python -m paper_2405_15573_amd.traffic FETCH.csv WRITE.csv --n 262144 -o out.json
+    python -m paper_2405_15573_amd.traffic FETCH.csv WRITE.csv --n 262144 -o out.json [--match REGEX]
+
+--match keeps the kernels whose short name matches the regular expression.
 """
 from __future__ import annotations
 
@@ -14,6 +16,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -60,14 +63,14 @@ def calibration_kib(path: str, counter: str) -> float:
     return sum(big[:CALIBRATION_COPIES]) / CALIBRATION_COPIES
 
 
-def summarize(fetch_csv: str, write_csv: str) -> dict:
+def summarize(fetch_csv: str, write_csv: str, match: str = "") -> dict:
     fetch = per_kernel(fetch_csv, "FETCH_SIZE")
     write = per_kernel(write_csv, "WRITE_SIZE")
     sf = COPY_BYTES / (calibration_kib(fetch_csv, "FETCH_SIZE") * 1024.0)
     sw = COPY_BYTES / (calibration_kib(write_csv, "WRITE_SIZE") * 1024.0)
     out = {}
     for k in set(fetch) | set(write):
-        if not k.startswith("k_"):
+        if not k.startswith("k_") or (match and not re.search(match, k)):
             continue
         f = sum(fetch.get(k, [0.0])) / max(1, len(fetch.get(k, [])))
         w = sum(write.get(k, [0.0])) / max(1, len(write.get(k, [])))
@@ -82,8 +85,9 @@ def main():
     ap.add_argument("write_csv")
     ap.add_argument("--n", type=int, required=True)
     ap.add_argument("-o", "--out", required=True)
+    ap.add_argument("--match", default="", help="keep kernels whose short name matches this regex")
     a = ap.parse_args()
-    s = summarize(a.fetch_csv, a.write_csv)
+    s = summarize(a.fetch_csv, a.write_csv, a.match)
     s["n"] = a.n
     s["source_sha256"] = kernel_source_sha256()
     s["bytes_per_launch"] = {k: v["bytes"] for k, v in s["kernels"].items()}

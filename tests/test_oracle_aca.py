@@ -12,8 +12,11 @@ What pins what:
                     * with min(m, n) terms and eps = 0 a random matrix is reproduced exactly;
                     * a zero first row is skipped; a rank cap stops the iteration and is
                       reported;
-                    * on two separated clusters of the Helmholtz kernel the error stays
-                      within a small multiple of eps at a rank far below the block size.
+                    * on two separated clusters of the Helmholtz kernel (the stopping rule):
+                      the error is at most 3 eps and at least the optimal error of its rank
+                      (Eckart-Young, from the block's singular values), and the rank lies
+                      between the optimal rank at eps and 3 past the optimal rank at eps/10,
+                      so a rule that stops a decade early or late is rejected.
 A last test plants plausible mistakes in copies of aca_partial and checks that these pins
 reject each one.
 """
@@ -103,17 +106,39 @@ def test_zero_row_skipped_and_cap_reported():
     assert u.shape[1] == 3 and not conv
 
 
-def test_helmholtz_separated_clusters():
+def _helmholtz_block():
     rng = np.random.default_rng(9)
     src = rng.uniform(-0.5, 0.5, size=(300, 3))
     dst = rng.uniform(-0.5, 0.5, size=(260, 3)) + np.array([3.0, 0.0, 0.0])
     pts = np.concatenate([src, dst])
-    kappa = 4.0
-    a = aca.kernel_block(pts, kappa, 1.0, np.arange(300), np.arange(300, 560))
+    return aca.kernel_block(pts, 4.0, 1.0, np.arange(300), np.arange(300, 560))
+
+
+def _stopping_rule_failures(fn=None):
+    """Checks of the stopping rule on the Helmholtz block; returns the failed ones."""
+    a = _helmholtz_block()
+    sv = np.linalg.svd(a, compute_uv=False)
+    # tail[k]: the smallest relative Frobenius error of any rank-k approximation
+    tail = np.append(np.sqrt(np.cumsum((sv ** 2)[::-1])[::-1]) / np.linalg.norm(a), 0.0)
+    ropt = lambda e: int(np.argmax(tail <= e))   # noqa: E731
+    failed = []
     for eps in (1e-4, 1e-6, 1e-8):
-        u, v, pr, pc, conv = _run(a, eps)
-        assert conv and u.shape[1] < 60
-        assert _rel(u @ v.T, a) <= 20 * eps
+        u, v, pr, pc, conv = _run(a, eps, fn=fn)
+        k = u.shape[1]
+        err = _rel(u @ v.T, a)
+        if not conv:
+            failed.append(f"{eps}: not converged")
+        if err > 3 * eps:
+            failed.append(f"{eps}: error {err:.2e} above 3 eps")
+        if err < tail[k] * (1 - 1e-6):
+            failed.append(f"{eps}: error below the optimum of rank {k}")
+        if not ropt(eps) <= k <= ropt(eps / 10) + 3:
+            failed.append(f"{eps}: rank {k} outside [{ropt(eps)}, {ropt(eps / 10) + 3}]")
+    return failed
+
+
+def test_helmholtz_separated_clusters():
+    assert _stopping_rule_failures() == []
 
 
 MISTAKES = {
@@ -124,6 +149,8 @@ MISTAKES = {
                  "r = np.conj(np.asarray(entry_row(i), dtype=np.complex128))"),
     "pivot_min": ("j = int(np.argmax(_mod2(r)))", "j = int(np.argmin(_mod2(r)))"),
     "reuse_rows": ("i = int(free[np.argmax(_mod2(u[free]))])", "i = int(np.argmax(_mod2(u)))"),
+    "stop_early": ("<= eps * np.linalg.norm(S)", "<= 10 * eps * np.linalg.norm(S)"),
+    "stop_late": ("<= eps * np.linalg.norm(S)", "<= 0.1 * eps * np.linalg.norm(S)"),
 }
 
 
@@ -157,4 +184,8 @@ def test_pins_reject_planted_mistakes(name):
     u, v, pr, pc, _ = _run(a, 0.0, cap=2, fn=fn)
     if pc[0] != int(np.argmax(np.abs(a[0]))):
         failed.append("first pivot")
+    try:
+        failed += _stopping_rule_failures(fn)
+    except Exception:
+        failed.append("raised")
     assert failed, name

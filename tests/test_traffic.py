@@ -48,3 +48,17 @@ def test_missing_calibration_is_an_error(tmp_path):
     _write(fp, "FETCH_SIZE", [("void (anonymous namespace)::k_coupling(int)", 1000.0)])
     with pytest.raises(RuntimeError):
         traffic.summarize(str(fp), str(fp))
+
+
+def test_match_keeps_only_the_named_kernels(tmp_path):
+    gib_kib = float(1 << 20)
+    cal = traffic.CALIBRATION_COPIES
+    rows = [("__amd_rocclr_copyBuffer", gib_kib)] * cal + [
+        ("void (anonymous namespace)::k_coupling(int)", 10.0), ("void (anonymous namespace)::k_aca<8>(int)", 99.0),
+        ("void (anonymous namespace)::k_coupling_sym(int)", 20.0)]
+    fp = tmp_path / "f.csv"
+    _write(fp, "FETCH_SIZE", rows)
+    wp = tmp_path / "w.csv"
+    _write(wp, "WRITE_SIZE", rows)
+    s = traffic.summarize(str(fp), str(wp), match=r"^k_coupling")
+    assert sorted(s["kernels"]) == ["k_coupling", "k_coupling_sym"]
