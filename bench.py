@@ -582,6 +582,8 @@ def main():
     ap.add_argument("--no-factored", action="store_true", help="skip the factored-coupling form")
     ap.add_argument("--no-lowp", action="store_true", help="skip the complex64 / bf16-pair multi-RHS forms")
     ap.add_argument("--lowp-rhs", type=int, default=64)
+    ap.add_argument("--lowp-forms", type=str, default="c64,bf16pair,c64fact,bf16pairfact,c128multi,c64stream,bf16pairstream",
+                    help="comma list of the precision forms to time")
     ap.add_argument("--no-gmres", action="store_true", help="skip the time-to-solution comparison")
     ap.add_argument("--gmres-rhs", type=int, default=64)
     ap.add_argument("--gmres-tol", type=float, default=1e-8)
@@ -791,9 +793,13 @@ def main():
         # many right-hand sides on the matrix cores (bound by them for complex64 and FP64,
         # by HBM for bf16 pairs: 8 r / e flop per operator byte), and one right-hand side in
         # the streaming forms (HBM-bound)
-        for st_name, peak_tf, e_bytes in (("c64", 157.3, 8), ("bf16pair", 2500.0, 4), ("c64fact", 157.3, 8),
-                                          ("bf16pairfact", 2500.0, 4), ("c128multi", 78.6, 16),
-                                          ("c64stream", None, 8), ("bf16pairstream", None, 4)):
+        wanted = [f for f in args.lowp_forms.split(",") if f]
+        forms = (("c64", 157.3, 8), ("bf16pair", 2500.0, 4), ("c64fact", 157.3, 8), ("bf16pairfact", 2500.0, 4),
+                 ("c128multi", 78.6, 16), ("c64stream", None, 8), ("bf16pairstream", None, 4))
+        unknown = set(wanted) - {f[0] for f in forms}
+        if unknown:
+            raise SystemExit(f"unknown precision forms: {sorted(unknown)}")
+        for st_name, peak_tf, e_bytes in (f for f in forms if f[0] in wanted):
             tl = time.perf_counter()
             dl = binding.upload(op, storage=st_name, stream=stream)
             log(f"{st_name} upload {time.perf_counter() - tl:.1f} s")

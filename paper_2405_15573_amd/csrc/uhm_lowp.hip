@@ -63,8 +63,11 @@ struct LdsF64 {
 };
 template <int RZ, int NT>
 struct LdsBf16 {
-  static constexpr int ZT = RZ + 8;  // plane row stride (per column j)
-  __bf16 re_hi[16 * NT * ZT], re_lo[16 * NT * ZT], im_hi[16 * NT * ZT], im_lo[16 * NT * ZT];
+  static constexpr int ZT = RZ + 8;  // plane row stride (per column j): 4 dwords past a multiple of 32
+  alignas(16) __bf16 re_hi[16 * NT * ZT];
+  alignas(16) __bf16 re_lo[16 * NT * ZT];
+  alignas(16) __bf16 im_hi[16 * NT * ZT];
+  alignas(16) __bf16 im_lo[16 * NT * ZT];
 };
 
 // k-rows per LDS round: the storage's base round rz, for R = 16 nt columns
@@ -115,7 +118,8 @@ struct bfs4 {
 };
 
 // Storage traits.  CH: 16-byte words per lane chunk; RZ: k-rows per LDS round; KP: k-rows
-// of one column that a thread stages together (one packed LDS store per plane);
+// of one column that a thread stages together (one packed LDS store per plane; bf16 pairs
+// take 8 where the round's slots allow, see kp_of);
 // V: vector element; ACC: accumulator register tile; rows of an accumulator register:
 // C64/BF16 lane (g, i) register v holds row 4g + v, C128 holds row g + 4v.
 template <int ST>
@@ -203,7 +207,26 @@ __device__ __forceinline__ void lds_put(LdsBf16<RZ, NT>& L, int k, int j, bfs4 v
   L.im_hi[j * L.ZT + k] = __builtin_bit_cast(__bf16, v.ih);
   L.im_lo[j * L.ZT + k] = __builtin_bit_cast(__bf16, v.il);
 }
-// Rows k0 .. k0 + 3 (k0 a multiple of 4) of column j: one 8-byte store per plane.
+// Rows k0 .. k0 + 7 (k0 a multiple of 8) of column j: one 16-byte store per plane, the
+// same bank pattern as the MFMA fragment reads (column stride 4 dwords past a multiple of
+// 32, so 8 consecutive columns cover the 32 banks once).
+template <int RZ, int NT>
+__device__ __forceinline__ void lds_put8(LdsBf16<RZ, NT>& L, int k0, int j, const bfs4* v) {
+  const int o = j * L.ZT + k0;
+  auto pack = [&](auto part) {
+    uint32_t w[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) w[t] = (uint32_t)part(v[2 * t]) | ((uint32_t)part(v[2 * t + 1]) << 16);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+  };
+  *reinterpret_cast<uint4*>(&L.re_hi[o]) = pack([](const bfs4& e) { return e.rh; });
+  *reinterpret_cast<uint4*>(&L.re_lo[o]) = pack([](const bfs4& e) { return e.rl; });
+  *reinterpret_cast<uint4*>(&L.im_hi[o]) = pack([](const bfs4& e) { return e.ih; });
+  *reinterpret_cast<uint4*>(&L.im_lo[o]) = pack([](const bfs4& e) { return e.il; });
+}
+// Rows k0 .. k0 + 3 (k0 a multiple of 4) of column j: one 8-byte store per plane.  Columns
+// 8 apart share banks here (2-way conflicts), so this serves only rounds whose slots do not
+// come in groups of 8.
 template <int RZ, int NT>
 __device__ __forceinline__ void lds_put4(LdsBf16<RZ, NT>& L, int k0, int j, const bfs4* v) {
   const int o = j * L.ZT + k0;
@@ -413,13 +436,24 @@ __device__ __forceinline__ void scatter_tile(int64_t i0, int64_t n, int r, int R
 // Every load of a batch is issued unconditionally from an address that is always in bounds
 // (out-of-range slots re-read a valid one) and results are masked where they are used, so
 // no load waits on a branch and the waits count only the batch they need.
+// k-rows of one column that a thread stages together: the storage's KP, raised to 8 for
+// bf16 pairs when the thread's PQ slots of a round come in whole groups of 8 (16-byte LDS
+// stores instead of 8-byte ones, which conflict).
+template <int ST, int NT>
+constexpr int kp_of() {
+  constexpr int pq = round_rows(Tr<ST>::RZ, NT) * 16 * NT / (64 * kLpWaves);
+  return Tr<ST>::KP == 1 ? 1 : (pq % 8 == 0 ? 8 : Tr<ST>::KP);
+}
+
 template <int ST, int NT>
 struct Round {
   using T_ = Tr<ST>;
   static constexpr int RZN = round_rows(T_::RZ, NT);
   static constexpr int KBR = RZN / T_::KB;                    // k-blocks per round
   static constexpr int PQ = RZN * 16 * NT / (64 * kLpWaves);  // B elements per thread
-  static_assert(PQ % T_::KP == 0, "slots come in whole groups of KP rows");
+  static constexpr int KP = kp_of<ST, NT>();
+  static_assert(PQ % KP == 0, "slots come in whole groups of KP rows");
+  static_assert(T_::KB % KP == 0, "a k-block holds whole groups");
   typename T_::CHUNK a[KBR];
   typename T_::VB v[PQ];
   int32_t id[PQ];
@@ -446,7 +480,7 @@ __device__ __forceinline__ void round_issue_a(Round<ST, NT>& Q, const uint4* til
 // k = KP (q / R) + u % KP, j = q % R (R = 16 NT), so a wave's loads of one k are contiguous.
 template <int ST, int NT>
 __device__ __forceinline__ void slot_kj(int u, int& k, int& j) {
-  constexpr int R = 16 * NT, KP = Tr<ST>::KP;
+  constexpr int R = 16 * NT, KP = kp_of<ST, NT>();
   const int q = threadIdx.x + (u / KP) * 64 * kLpWaves;
   k = KP * (q / R) + u % KP;
   j = q % R;
@@ -476,7 +510,7 @@ __device__ __forceinline__ void round_values(Round<ST, NT>& Q, int nk, Src src) 
 template <int ST, int NT>
 __device__ __forceinline__ void round_commit(LdsOf<ST, NT>& L, const Round<ST, NT>& Q, int nk) {
   using V = typename Tr<ST>::VB;
-  constexpr int KP = Tr<ST>::KP;
+  constexpr int KP = kp_of<ST, NT>();
 #pragma unroll
   for (int u = 0; u < Round<ST, NT>::PQ; u += KP) {
     int k, j;
@@ -488,7 +522,10 @@ __device__ __forceinline__ void round_commit(LdsOf<ST, NT>& L, const Round<ST, N
         V w[KP];
 #pragma unroll
         for (int t = 0; t < KP; ++t) w[t] = Q.ok[u + t] ? Q.v[u + t] : vzero<V>();
-        lds_put4(L, k, j, w);
+        if constexpr (KP == 8)
+          lds_put8(L, k, j, w);
+        else
+          lds_put4(L, k, j, w);
       }
     }
   }
