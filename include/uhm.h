@@ -239,7 +239,9 @@ typedef struct {
 
 /* What uhm_solve_gmres did. */
 typedef struct {
-  int32_t iterations;       /* Krylov iterations (products with the Krylov operator) */
+  int32_t iterations;       /* Krylov iterations (products with the Krylov operator); a cycle
+                               that stops on its tolerance takes one product more than its
+                               Krylov dimension, for the delayed second projection */
   int32_t restarts;         /* GMRES(m) cycles started after the first */
   int32_t refinements;      /* outer refinement steps (0 without an inner operator) */
   int32_t converged;        /* right-hand sides whose final true relative residual <= tol */
@@ -247,13 +249,15 @@ typedef struct {
   double seconds_total;     /* wall clock of the solve (synchronized) */
   double seconds_products;  /* of which spent in operator products */
   double seconds_arnoldi;   /* of which spent in the orthogonalisation and updates */
-  int64_t second_passes;    /* column-steps that needed the second Gram-Schmidt pass */
+  int64_t second_passes;    /* column-steps whose basis vector got its second projection
+                               (every step of every running column) */
 } uhm_gmres_info;
 
 /*
- * Solve A X = B by restarted GMRES(m) (textbook GMRES with classical Gram-Schmidt,
- * repeated once for a column whose norm drops below 1/sqrt(2) of its value in the first
- * pass (Daniel, Gragg, Kaufman and Stewart), FP64 Krylov vectors, Givens least-squares),
+ * Solve A X = B by restarted GMRES(m) (textbook GMRES with classical Gram-Schmidt applied
+ * twice, the second projection of each basis vector delayed by one step and fused with the
+ * first projection of the next (the one-reduction DCGS2 scheme of Swirydowicz et al. and
+ * Bielich et al.), FP64 Krylov vectors, Givens least-squares),
  * for nrhs right-hand sides at once, each with its own Krylov space.  X starts at zero
  * and is overwritten.
  *   op:    the operator A in a complex128 storage form (the true-residual operator).

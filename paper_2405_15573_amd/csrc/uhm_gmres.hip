@@ -2,20 +2,25 @@
 //
 // Every right-hand side has its own Krylov space; all of them advance in lockstep so that
 // each Arnoldi step is one batched product with the operator (uhm_matvec over nrhs
-// columns) plus batched FP64 kernels:
-//   dots     h_i = V_i^* w for i <= j (classical Gram-Schmidt), per column, with ||w||^2,
-//   update   w -= sum_i V_i h_i, with the partial sums of ||w||^2,
-//   scale    V_{j+1} = w / ||w||.
-// Classical Gram-Schmidt is repeated once for the columns whose norm fell below 1/sqrt(2)
-// of its value before the projection (the reorthogonalisation criterion of Daniel, Gragg,
-// Kaufman and Stewart, 1976); the other columns skip the second pass.  Partial sums are
-// per wavefront over fixed row ranges and are reduced in a fixed order (deterministic).
+// columns) plus batched FP64 kernels.  The basis is orthogonalised by classical
+// Gram-Schmidt applied twice, with the second pass of each vector delayed by one step and
+// fused with the first pass of the next (the one-reduction "DCGS2" scheme of Swirydowicz,
+// Langou, Ananthan, Yang and Thomas, and of Bielich et al.): at step j the last vector
+// t = V_j has had one projection, and w = A t.  One sweep over the basis forms
+// a = V^* t and b = V^* w (basis vectors 0 .. j-1), t^* t and t^* w; one sweep forms
+// the final V_j = (t - V a) / r_j, r_j = sqrt(t^* t - |a|^2), and the projected
+// w = (I - V V^*) w / r_j over V_0 .. V_j, with its norm.  The basis is read twice per
+// step instead of twice per projection.  The Hessenberg column of step j - 1 becomes final
+// at step j (the delayed projection changes it), so its Givens rotation and the residual
+// estimate it gives lag one step; at the end of a cycle one more sweep finalises the last
+// column without a product.  Partial sums are per wavefront over fixed row ranges and are
+// reduced in a fixed order (deterministic).
 // The (m+1) x m Hessenberg matrices, the Givens rotations and the small triangular solves
-// stay on the device in FP64 (one thread per column): a step's coefficients never leave the
-// GPU, and the host reads back only the number of columns still running.  A single solve
-// reads that count one step late, so the host never waits for the step it has just issued;
-// when the count says that every column stopped, at most one further step has been issued,
-// on columns that are all inactive, and it changes nothing.
+// stay on the device in FP64: a step's coefficients never leave the GPU, and the host
+// reads back only the number of columns still running.  A single solve reads that count one
+// step late, so the host never waits for the step it has just issued; when the count says
+// that every column stopped, at most one further step has been issued, on columns that are
+// all inactive, and it changes nothing.
 //
 // With an inner operator (complex64 or bf16 pairs) the solve is iterative refinement: the
 // residual r = b - A x is formed with the FP64 operator, an inner GMRES(m) whose products
@@ -67,86 +72,67 @@ __device__ __forceinline__ void block_sum2(double re, double im, double* sh, dou
 constexpr int kAWRows = 512;
 constexpr int kAPer = kAWRows / 64;
 
-// part[(i r + c) nsub + sb] = sum over the rows of wave sb of conj(V_i[row, c]) w[row, c];
-// w2[c nsub + sb] = the same rows' sum of |w|^2 (when w2 is given).  Columns with
-// need[c] == 0 are skipped (when need is given).
-__device__ __forceinline__ void a_dots_body(int sb, int c, const cd* __restrict__ V, int64_t vstride, int nvec,
+// Step j (>= 0) of column c, rows of wave sb: partial sums of a_i = V_i^* t and
+// b_i = V_i^* w for i < j, of t^* w and of t^* t, where t = V_j.  Entry e of the column,
+// at part[(e r + c) nsub + sb]: a_e (e < j), b_{e-j} (j <= e < 2j), t^* w (2j), t^* t
+// (2j + 1, real).  Columns that have stopped are skipped.
+__device__ __forceinline__ void a_dots_body(int sb, int c, const cd* __restrict__ V, int64_t vstride, int j,
                                             const cd* __restrict__ w, int64_t n, int r, int nsub,
-                                            const int* __restrict__ need, cd* __restrict__ part,
-                                            double* __restrict__ w2) {
+                                            const int* __restrict__ act, cd* __restrict__ part) {
   const int lane = threadIdx.x & 63;
-  if (sb >= nsub || (need && !need[c])) return;
+  if (sb >= nsub || !act[c]) return;
   const int64_t r0 = (int64_t)sb * kAWRows;
-  const cd* wc = w + (int64_t)c * n;
-  cd wv[kAPer];
-  double s2 = 0.0;
+  const int64_t lim = n - r0 - lane;  // rows q * 64 < lim are in range
+  const cd* tc = V + (int64_t)j * vstride + (int64_t)c * n + r0 + lane;
+  const cd* wc = w + (int64_t)c * n + r0 + lane;
+  cd tv[kAPer], wv[kAPer];
+  double tt = 0.0, twr = 0.0, twi = 0.0;
 #pragma unroll
   for (int q = 0; q < kAPer; ++q) {
-    const int64_t row = r0 + q * 64 + lane;
-    wv[q] = row < n ? wc[row] : make_double2(0.0, 0.0);
-    s2 = fma(wv[q].x, wv[q].x, fma(wv[q].y, wv[q].y, s2));
+    const bool ok = q * 64 < lim;
+    tv[q] = ok ? tc[q * 64] : make_double2(0.0, 0.0);
+    wv[q] = ok ? wc[q * 64] : make_double2(0.0, 0.0);
+    tt = fma(tv[q].x, tv[q].x, fma(tv[q].y, tv[q].y, tt));
+    twr = fma(tv[q].x, wv[q].x, fma(tv[q].y, wv[q].y, twr));
+    twi = fma(tv[q].x, wv[q].y, fma(-tv[q].y, wv[q].x, twi));
   }
-  if (w2) {
-    s2 = warp_sum(s2);
-    if (lane == 0) w2[(int64_t)c * nsub + sb] = s2;
-  }
-  const int64_t lim = n - r0 - lane;  // rows q * 64 < lim are in range
-  int i = 0;
-  for (; i + 1 < nvec; i += 2) {
-    const cd* va = V + (int64_t)i * vstride + (int64_t)c * n + r0 + lane;
-    const cd* vb = va + vstride;
-    cd a[kAPer], b[kAPer];
+  auto put = [&](int e, double re, double im) {
+    re = warp_sum(re);
+    im = warp_sum(im);
+    if (lane == 0) part[((int64_t)e * r + c) * nsub + sb] = make_double2(re, im);
+  };
+  for (int i = 0; i < j; ++i) {
+    const cd* vi = V + (int64_t)i * vstride + (int64_t)c * n + r0 + lane;
+    cd v[kAPer];
 #pragma unroll
-    for (int q = 0; q < kAPer; ++q) {
-      const bool ok = q * 64 < lim;
-      a[q] = ok ? va[q * 64] : make_double2(0.0, 0.0);
-      b[q] = ok ? vb[q * 64] : make_double2(0.0, 0.0);
-    }
+    for (int q = 0; q < kAPer; ++q) v[q] = q * 64 < lim ? vi[q * 64] : make_double2(0.0, 0.0);
     double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
 #pragma unroll
     for (int q = 0; q < kAPer; ++q) {
-      ar = fma(a[q].x, wv[q].x, fma(a[q].y, wv[q].y, ar));
-      ai = fma(a[q].x, wv[q].y, fma(-a[q].y, wv[q].x, ai));
-      br = fma(b[q].x, wv[q].x, fma(b[q].y, wv[q].y, br));
-      bi = fma(b[q].x, wv[q].y, fma(-b[q].y, wv[q].x, bi));
+      ar = fma(v[q].x, tv[q].x, fma(v[q].y, tv[q].y, ar));
+      ai = fma(v[q].x, tv[q].y, fma(-v[q].y, tv[q].x, ai));
+      br = fma(v[q].x, wv[q].x, fma(v[q].y, wv[q].y, br));
+      bi = fma(v[q].x, wv[q].y, fma(-v[q].y, wv[q].x, bi));
     }
-    ar = warp_sum(ar);
-    ai = warp_sum(ai);
-    br = warp_sum(br);
-    bi = warp_sum(bi);
-    if (lane == 0) {
-      part[((int64_t)i * r + c) * nsub + sb] = make_double2(ar, ai);
-      part[((int64_t)(i + 1) * r + c) * nsub + sb] = make_double2(br, bi);
-    }
+    put(i, ar, ai);
+    put(j + i, br, bi);
   }
-  if (i < nvec) {
-    const cd* va = V + (int64_t)i * vstride + (int64_t)c * n + r0 + lane;
-    double ar = 0.0, ai = 0.0;
-#pragma unroll
-    for (int q = 0; q < kAPer; ++q) {
-      const cd a = q * 64 < lim ? va[q * 64] : make_double2(0.0, 0.0);
-      ar = fma(a.x, wv[q].x, fma(a.y, wv[q].y, ar));
-      ai = fma(a.x, wv[q].y, fma(-a.y, wv[q].x, ai));
-    }
-    ar = warp_sum(ar);
-    ai = warp_sum(ai);
-    if (lane == 0) part[((int64_t)i * r + c) * nsub + sb] = make_double2(ar, ai);
-  }
+  put(2 * j, twr, twi);
+  put(2 * j + 1, tt, 0.0);
 }
 
-__global__ __launch_bounds__(kGB) void k_a_dots(const cd* __restrict__ V, int64_t vstride, int nvec,
+__global__ __launch_bounds__(kGB) void k_a_dots(const cd* __restrict__ V, int64_t vstride, int j,
                                                 const cd* __restrict__ w, int64_t n, int r, int nsub,
-                                                const int* __restrict__ need, cd* __restrict__ part,
-                                                double* __restrict__ w2) {
-  a_dots_body(blockIdx.x * (kGB / 64) + (threadIdx.x >> 6), blockIdx.y, V, vstride, nvec, w, n, r, nsub, need, part, w2);
+                                                const int* __restrict__ act, cd* __restrict__ part) {
+  a_dots_body(blockIdx.x * (kGB / 64) + (threadIdx.x >> 6), blockIdx.y, V, vstride, j, w, n, r, nsub, act, part);
 }
 
-// out[q] = sum_sb part[q nsub + sb], q = i r + c; zero for columns with need[c] == 0.
+// out[q] = sum_sb part[q nsub + sb], q = e r + c, for the running columns.
 __device__ __forceinline__ void a_reduce_body(int64_t q, const cd* __restrict__ part, int nsub, int64_t nq, int r,
-                                              const int* __restrict__ need, cd* __restrict__ out) {
+                                              const int* __restrict__ act, cd* __restrict__ out) {
   if (q >= nq) return;
   double re = 0.0, im = 0.0;
-  if (!need || need[q % r])
+  if (act[q % r])
     for (int sb = 0; sb < nsub; ++sb) {
       const cd v = part[q * nsub + sb];
       re += v.x;
@@ -155,118 +141,79 @@ __device__ __forceinline__ void a_reduce_body(int64_t q, const cd* __restrict__ 
   out[q] = make_double2(re, im);
 }
 __global__ __launch_bounds__(kGB) void k_a_reduce(const cd* __restrict__ part, int nsub, int64_t nq, int r,
-                                                  const int* __restrict__ need, cd* __restrict__ out) {
-  a_reduce_body((int64_t)blockIdx.x * kGB + threadIdx.x, part, nsub, nq, r, need, out);
+                                                  const int* __restrict__ act, cd* __restrict__ out) {
+  a_reduce_body((int64_t)blockIdx.x * kGB + threadIdx.x, part, nsub, nq, r, act, out);
 }
 
-// w[:, c] -= sum_i V_i[:, c] h[i r + c]; w2[c nsub + sb] = partial ||w_new||^2.
-__device__ __forceinline__ void a_update_body(int sb, int c, const cd* __restrict__ V, int64_t vstride, int nvec,
-                                              const cd* __restrict__ h, cd* __restrict__ w, int64_t n, int r,
-                                              int nsub, const int* __restrict__ need, double* __restrict__ w2) {
+// Step j of column c, rows of wave sb, with the column's update coefficients
+// (coef[e r + c]: gv_i (e = i < j), gw_i (e = j + i), sv (2j), sw (2j + 1), gt (2j + 2)):
+//   V_j = sv t + sum_i gv_i V_i   (j > 0; V_0 is final from the start of the cycle)
+//   w   = sw w + gt t + sum_i gw_i V_i
+// with t = V_j before the update; partial ||w||^2 at w2[c nsub + sb].  Each wave reads
+// and writes its own rows only.
+__device__ __forceinline__ void a_update_body(int sb, int c, cd* __restrict__ V, int64_t vstride, int j,
+                                              const cd* __restrict__ coef, cd* __restrict__ w, int64_t n, int r,
+                                              int nsub, const int* __restrict__ act, double* __restrict__ w2) {
   const int lane = threadIdx.x & 63;
-  if (sb >= nsub || (need && !need[c])) return;
+  if (sb >= nsub || !act[c]) return;
   const int64_t r0 = (int64_t)sb * kAWRows;
   const int64_t lim = n - r0 - lane;
+  cd* tc = V + (int64_t)j * vstride + (int64_t)c * n + r0 + lane;
   cd* wc = w + (int64_t)c * n + r0 + lane;
-  cd wv[kAPer];
+  const double sv = coef[(int64_t)(2 * j) * r + c].x, sw = coef[(int64_t)(2 * j + 1) * r + c].x;
+  const cd gt = coef[(int64_t)(2 * j + 2) * r + c];
+  cd tv[kAPer], wv[kAPer];
 #pragma unroll
-  for (int q = 0; q < kAPer; ++q) wv[q] = q * 64 < lim ? wc[q * 64] : make_double2(0.0, 0.0);
-  int i = 0;
-  for (; i + 1 < nvec; i += 2) {
-    const cd* va = V + (int64_t)i * vstride + (int64_t)c * n + r0 + lane;
-    const cd* vb = va + vstride;
-    const cd ha = h[(int64_t)i * r + c], hb = h[(int64_t)(i + 1) * r + c];
-    cd a[kAPer], b[kAPer];
-#pragma unroll
-    for (int q = 0; q < kAPer; ++q) {
-      const bool ok = q * 64 < lim;
-      a[q] = ok ? va[q * 64] : make_double2(0.0, 0.0);
-      b[q] = ok ? vb[q * 64] : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int q = 0; q < kAPer; ++q) {
-      wv[q].x -= a[q].x * ha.x - a[q].y * ha.y;
-      wv[q].y -= a[q].x * ha.y + a[q].y * ha.x;
-      wv[q].x -= b[q].x * hb.x - b[q].y * hb.y;
-      wv[q].y -= b[q].x * hb.y + b[q].y * hb.x;
-    }
+  for (int q = 0; q < kAPer; ++q) {
+    const bool ok = q * 64 < lim;
+    const cd t = ok ? tc[q * 64] : make_double2(0.0, 0.0);
+    const cd x = ok ? wc[q * 64] : make_double2(0.0, 0.0);
+    tv[q] = make_double2(sv * t.x, sv * t.y);
+    wv[q] = make_double2(fma(sw, x.x, gt.x * t.x - gt.y * t.y), fma(sw, x.y, gt.x * t.y + gt.y * t.x));
   }
-  if (i < nvec) {
-    const cd* va = V + (int64_t)i * vstride + (int64_t)c * n + r0 + lane;
-    const cd ha = h[(int64_t)i * r + c];
+  for (int i = 0; i < j; ++i) {
+    const cd* vi = V + (int64_t)i * vstride + (int64_t)c * n + r0 + lane;
+    const cd gv = coef[(int64_t)i * r + c], gw = coef[(int64_t)(j + i) * r + c];
+    cd v[kAPer];
+#pragma unroll
+    for (int q = 0; q < kAPer; ++q) v[q] = q * 64 < lim ? vi[q * 64] : make_double2(0.0, 0.0);
 #pragma unroll
     for (int q = 0; q < kAPer; ++q) {
-      const cd a = q * 64 < lim ? va[q * 64] : make_double2(0.0, 0.0);
-      wv[q].x -= a.x * ha.x - a.y * ha.y;
-      wv[q].y -= a.x * ha.y + a.y * ha.x;
+      tv[q].x = fma(gv.x, v[q].x, fma(-gv.y, v[q].y, tv[q].x));
+      tv[q].y = fma(gv.x, v[q].y, fma(gv.y, v[q].x, tv[q].y));
+      wv[q].x = fma(gw.x, v[q].x, fma(-gw.y, v[q].y, wv[q].x));
+      wv[q].y = fma(gw.x, v[q].y, fma(gw.y, v[q].x, wv[q].y));
     }
   }
   double s2 = 0.0;
 #pragma unroll
   for (int q = 0; q < kAPer; ++q)
     if (q * 64 < lim) {
+      if (j > 0) tc[q * 64] = tv[q];
       wc[q * 64] = wv[q];
       s2 = fma(wv[q].x, wv[q].x, fma(wv[q].y, wv[q].y, s2));
     }
   s2 = warp_sum(s2);
   if (lane == 0) w2[(int64_t)c * nsub + sb] = s2;
 }
-__global__ __launch_bounds__(kGB) void k_a_update(const cd* __restrict__ V, int64_t vstride, int nvec,
-                                                  const cd* __restrict__ h, cd* __restrict__ w, int64_t n, int r,
-                                                  int nsub, const int* __restrict__ need, double* __restrict__ w2) {
-  a_update_body(blockIdx.x * (kGB / 64) + (threadIdx.x >> 6), blockIdx.y, V, vstride, nvec, h, w, n, r, nsub, need, w2);
+__global__ __launch_bounds__(kGB) void k_a_update(cd* __restrict__ V, int64_t vstride, int j,
+                                                  const cd* __restrict__ coef, cd* __restrict__ w, int64_t n, int r,
+                                                  int nsub, const int* __restrict__ act, double* __restrict__ w2) {
+  a_update_body(blockIdx.x * (kGB / 64) + (threadIdx.x >> 6), blockIdx.y, V, vstride, j, coef, w, n, r, nsub, act, w2);
 }
 
-// need[c] = (||w after the projection||^2 < ||w before||^2 / 2) for running columns
-__device__ __forceinline__ void a_decide_body(int c, const double* __restrict__ w0, const double* __restrict__ w1,
-                                              int nsub, int r, const int* __restrict__ act, int* __restrict__ need) {
-  if (c >= r) return;
-  if (!act[c]) {
-    need[c] = 0;
-    return;
-  }
-  double s0 = 0.0, s1 = 0.0;
-  for (int sb = 0; sb < nsub; ++sb) {
-    s0 += w0[(int64_t)c * nsub + sb];
-    s1 += w1[(int64_t)c * nsub + sb];
-  }
-  need[c] = s1 < 0.5 * s0;
-}
-__global__ void k_a_decide(const double* __restrict__ w0, const double* __restrict__ w1, int nsub, int r,
-                           const int* __restrict__ act, int* __restrict__ need) {
-  a_decide_body(blockIdx.x * blockDim.x + threadIdx.x, w0, w1, nsub, r, act, need);
-}
-
-// out[c] = (||w||, need[c]) with ||w|| from the last pass the column ran
-__device__ __forceinline__ void a_final_body(int c, const double* __restrict__ w1, const double* __restrict__ w2,
-                                             const int* __restrict__ act, const int* __restrict__ need, int nsub,
-                                             int r, cd* __restrict__ out) {
-  if (c >= r) return;
-  if (!act[c]) {
-    out[c] = make_double2(0.0, 0.0);
-    return;
-  }
-  const double* src = need[c] ? w2 : w1;
-  double s = 0.0;
-  for (int sb = 0; sb < nsub; ++sb) s += src[(int64_t)c * nsub + sb];
-  out[c] = make_double2(sqrt(s), (double)need[c]);
-}
-__global__ void k_a_final(const double* __restrict__ w1, const double* __restrict__ w2, const int* __restrict__ act,
-                          const int* __restrict__ need, int nsub, int r, cd* __restrict__ out) {
-  a_final_body(blockIdx.x * blockDim.x + threadIdx.x, w1, w2, act, need, nsub, r, out);
-}
-
-// ---- the least-squares problem of a cycle, on the device (one thread per column)
-// State of one solve's current cycle, column c: the rotated Hessenberg columns
-// H[(c m + j)(m+1) + i], the rotated right-hand side g[c (m+1) + i], the rotations
-// cs[c m + i], sn[c m + i], active[c] (the column still iterates), jc[c] (steps taken),
-// rtol[c] (residual estimate at which it stops), scale[c].x = 1 / ||w|| of the last step.
+// ---- the least-squares problem of a cycle, on the device
+// State of one solve's current cycle, column c: the Hessenberg columns as the Arnoldi
+// relation A V = V Hu has them, Hu[(c m + j)(m+1) + i] (column j is provisional until step
+// j + 1), the same columns rotated, H, the rotated right-hand side g[c (m+1) + i], the
+// rotations cs[c m + i], sn[c m + i], active[c] (the column still iterates), jc[c] (final
+// columns), rtol[c] (residual estimate at which it stops), scale[c].x = 1 / ||w|| of the
+// last step.
 struct Lsq {
-  cd *H, *g, *cs, *sn, *scale, *y;
+  cd *H, *Hu, *g, *cs, *sn, *scale, *y;
   int *active, *jc;
-  const int* need;
   const double* rtol;
-  unsigned long long* reorth;  // column-steps that ran the second Gram-Schmidt pass
+  unsigned long long* reorth;  // column-steps whose vector got its second projection
   int m, r;
 };
 
@@ -275,54 +222,134 @@ __device__ __forceinline__ cd c_mul(cd a, cd b) { return make_double2(a.x * b.x 
 __device__ __forceinline__ cd c_cmul(cd a, cd b) { return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }
 __device__ __forceinline__ cd c_add(cd a, cd b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ cd c_sub(cd a, cd b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cd c_scale(double s, cd a) { return make_double2(s * a.x, s * a.y); }
 
-// Step j of column c: the new Hessenberg column from the coefficients of both Gram-Schmidt
-// passes (h1 + h2, i <= j) and the norm of w (tail[c].x), the previous rotations applied, a
-// new rotation that annihilates the subdiagonal entry, g updated; the column stops once its
-// residual estimate |g_{j+1}| reaches rtol[c] or w vanishes.
-__device__ __forceinline__ void givens_body(int c, int j, const cd* __restrict__ h1, const cd* __restrict__ h2,
-                                            const cd* __restrict__ tail, const Lsq& q) {
+// Final column k of column c's Hessenberg matrix: copied from Hu, the earlier rotations
+// applied, a new rotation that annihilates the subdiagonal entry, g updated; the column
+// stops once its residual estimate |g_{k+1}| reaches rtol[c] or the subdiagonal vanishes.
+__device__ __forceinline__ void rotate_column(int c, int k, const Lsq& q) {
+  const int m = q.m;
+  const cd* hu = q.Hu + ((int64_t)c * m + k) * (m + 1);
+  cd* col = q.H + ((int64_t)c * m + k) * (m + 1);
+  for (int i = 0; i <= k + 1; ++i) col[i] = hu[i];
+  const double hs = hypot(hu[k + 1].x, hu[k + 1].y);
+  const cd* csc = q.cs + (int64_t)c * m;
+  const cd* snc = q.sn + (int64_t)c * m;
+  for (int i = 0; i < k; ++i) {
+    const cd a = col[i], b = col[i + 1], ci = csc[i], si = snc[i];
+    col[i] = c_add(c_cmul(ci, a), c_cmul(si, b));
+    col[i + 1] = c_sub(c_mul(ci, b), c_mul(si, a));
+  }
+  const cd a = col[k], b = col[k + 1];
+  const double den = sqrt((a.x * a.x + a.y * a.y) + (b.x * b.x + b.y * b.y));
+  cd ck = make_double2(1.0, 0.0), sk = make_double2(0.0, 0.0);
+  if (den > 0.0) {
+    ck = make_double2(a.x / den, a.y / den);
+    sk = make_double2(b.x / den, b.y / den);
+  }
+  q.cs[(int64_t)c * m + k] = ck;
+  q.sn[(int64_t)c * m + k] = sk;
+  col[k] = c_add(c_cmul(ck, a), c_cmul(sk, b));
+  col[k + 1] = make_double2(0.0, 0.0);
+  cd* gc = q.g + (int64_t)c * (m + 1);
+  const cd gk = gc[k];
+  gc[k] = c_cmul(ck, gk);
+  const cd sg = c_mul(sk, gk);
+  gc[k + 1] = make_double2(-sg.x, -sg.y);
+  q.jc[c] = k + 1;
+  if (hypot(gc[k + 1].x, gc[k + 1].y) <= q.rtol[c] || hs <= 1e-300) q.active[c] = 0;
+}
+
+// Step j of column c, one wavefront, from the sums of a_dots_body (dv[e r + c]: a, b,
+// t^* w, t^* t).
+// 1. j > 0: the delayed projection of t = V_j gives r_j = sqrt(t^* t - |a|^2) and the final
+//    V_j = (t - V a) / r_j, so t = V a + r_j V_j: the provisional column j - 1 becomes
+//    Hu[i, j-1] += Hu[j, j-1] a_i (i < j), Hu[j, j-1] *= r_j, and is rotated (which may stop
+//    the column).  With `tail` (the end of a cycle, no product of V_j) that is all.
+// 2. The provisional column j.  A V_j = (w - V z) / r_j with z = Hu a (A applied to V a),
+//    so Hu[i, j] = (b_i - z_i) / r_j (i < j) and Hu[j, j] = c_j - z_j / r_j with
+//    c_j = V_j^* w / r_j = (t^* w - a^* b) / r_j^2.  The projected vector
+//    (I - V V^*) A V_j = (I - V V^*) w / r_j = (w - c_j t - sum_i (b_i - c_j a_i) V_i) / r_j
+//    gives the update coefficients of a_update_body.
+__device__ __forceinline__ void step_body(int c, int j, const cd* __restrict__ dv, cd* __restrict__ coef, bool tail,
+                                          const Lsq& q) {
+  const int lane = threadIdx.x & 63;
+  if (c >= q.r || !q.active[c]) return;
+  const int m = q.m, r = q.r;
+  auto A = [&](int i) { return dv[(int64_t)i * r + c]; };
+  auto B = [&](int i) { return dv[(int64_t)(j + i) * r + c]; };
+  double rj = 1.0;
+  if (j > 0) {
+    double aa = 0.0;
+    for (int i = lane; i < j; i += 64) {
+      const cd ai = A(i);
+      aa = fma(ai.x, ai.x, fma(ai.y, ai.y, aa));
+    }
+    aa = warp_sum(aa);
+    const double rho2 = dv[(int64_t)(2 * j + 1) * r + c].x - aa;
+    rj = rho2 > 0.0 ? sqrt(rho2) : 0.0;
+    cd* hp = q.Hu + ((int64_t)c * m + (j - 1)) * (m + 1);
+    const cd hs = hp[j];
+    for (int i = lane; i < j; i += 64) hp[i] = c_add(hp[i], c_mul(hs, A(i)));
+    __syncthreads();
+    if (lane == 0) {
+      hp[j] = c_scale(rj, hs);
+      atomicAdd(q.reorth, 1ull);
+      rotate_column(c, j - 1, q);
+    }
+    __syncthreads();
+    if (tail || !q.active[c]) return;
+  }
+  const double ir = 1.0 / rj;
+  double abr = 0.0, abi = 0.0;  // a^* b
+  for (int i = lane; i < j; i += 64) {
+    const cd t = c_cmul(A(i), B(i));
+    abr += t.x;
+    abi += t.y;
+  }
+  abr = warp_sum(abr);
+  abi = warp_sum(abi);
+  const cd tw = dv[(int64_t)(2 * j) * r + c];
+  const cd cj = c_scale(ir * ir, make_double2(tw.x - abr, tw.y - abi));
+  cd* hj = q.Hu + ((int64_t)c * m + j) * (m + 1);
+  for (int k = lane; k <= j; k += 64) {
+    // z_k = sum_i Hu[k, i] a_i over the columns i < j with an entry in row k (i >= k - 1)
+    cd z = make_double2(0.0, 0.0);
+    for (int i = k > 0 ? k - 1 : 0; i < j; ++i) z = c_add(z, c_mul(q.Hu[((int64_t)c * m + i) * (m + 1) + k], A(i)));
+    hj[k] = k < j ? c_scale(ir, c_sub(B(k), z)) : c_sub(cj, c_scale(ir, z));
+  }
+  for (int i = lane; i < j; i += 64) {
+    const cd ai = A(i), bi = B(i);
+    coef[(int64_t)i * r + c] = c_scale(-ir, ai);
+    coef[(int64_t)(j + i) * r + c] = c_scale(-ir, c_sub(bi, c_mul(cj, ai)));
+  }
+  if (lane == 0) {
+    coef[(int64_t)(2 * j) * r + c] = make_double2(ir, 0.0);
+    coef[(int64_t)(2 * j + 1) * r + c] = make_double2(ir, 0.0);
+    coef[(int64_t)(2 * j + 2) * r + c] = c_scale(-ir, cj);
+  }
+}
+__global__ __launch_bounds__(64) void k_a_step(int j, const cd* __restrict__ dv, cd* __restrict__ coef, int tail,
+                                               Lsq q) {
+  step_body(blockIdx.x, j, dv, coef, tail != 0, q);
+}
+
+// Step j, column c: ||w|| from the partial sums, the provisional subdiagonal entry
+// Hu[j + 1, j] and scale[c] = 1 / ||w|| (0 when w vanished, or the column stopped).
+__device__ __forceinline__ void norm_body(int c, int j, const double* __restrict__ w2, int nsub, const Lsq& q) {
   if (c >= q.r) return;
   if (!q.active[c]) {
     q.scale[c] = make_double2(0.0, 0.0);
     return;
   }
-  const int m = q.m, r = q.r;
-  const double hn = tail[c].x;
-  if (q.need[c]) atomicAdd(q.reorth, 1ull);
+  double s = 0.0;
+  for (int sb = 0; sb < nsub; ++sb) s += w2[(int64_t)c * nsub + sb];
+  const double hn = sqrt(s);
+  q.Hu[((int64_t)c * q.m + j) * (q.m + 1) + j + 1] = make_double2(hn, 0.0);
   q.scale[c] = make_double2(hn > 1e-300 ? 1.0 / hn : 0.0, 0.0);
-  cd* col = q.H + ((int64_t)c * m + j) * (m + 1);
-  for (int i = 0; i <= j; ++i) col[i] = c_add(h1[(int64_t)i * r + c], h2[(int64_t)i * r + c]);
-  col[j + 1] = make_double2(hn, 0.0);
-  const cd* csc = q.cs + (int64_t)c * m;
-  const cd* snc = q.sn + (int64_t)c * m;
-  for (int i = 0; i < j; ++i) {
-    const cd a = col[i], b = col[i + 1], ci = csc[i], si = snc[i];
-    col[i] = c_add(c_cmul(ci, a), c_cmul(si, b));
-    col[i + 1] = c_sub(c_mul(ci, b), c_mul(si, a));
-  }
-  const cd a = col[j], b = col[j + 1];
-  const double den = sqrt((a.x * a.x + a.y * a.y) + (b.x * b.x + b.y * b.y));
-  cd cj = make_double2(1.0, 0.0), sj = make_double2(0.0, 0.0);
-  if (den > 0.0) {
-    cj = make_double2(a.x / den, a.y / den);
-    sj = make_double2(b.x / den, b.y / den);
-  }
-  q.cs[(int64_t)c * m + j] = cj;
-  q.sn[(int64_t)c * m + j] = sj;
-  col[j] = c_add(c_cmul(cj, a), c_cmul(sj, b));
-  col[j + 1] = make_double2(0.0, 0.0);
-  cd* gc = q.g + (int64_t)c * (m + 1);
-  const cd gj = gc[j];
-  gc[j] = c_cmul(cj, gj);
-  const cd sg = c_mul(sj, gj);
-  gc[j + 1] = make_double2(-sg.x, -sg.y);
-  q.jc[c] = j + 1;
-  if (hypot(gc[j + 1].x, gc[j + 1].y) <= q.rtol[c] || hn <= 1e-300) q.active[c] = 0;
 }
-__global__ void k_a_givens(int j, const cd* __restrict__ h1, const cd* __restrict__ h2, const cd* __restrict__ tail,
-                           Lsq q) {
-  givens_body(blockIdx.x * blockDim.x + threadIdx.x, j, h1, h2, tail, q);
+__global__ void k_a_norm(int j, const double* __restrict__ w2, int nsub, Lsq q) {
+  norm_body(blockIdx.x * blockDim.x + threadIdx.x, j, w2, nsub, q);
 }
 
 // count[0] = number of running columns (one wavefront)
@@ -371,42 +398,48 @@ __global__ void k_a_cycle_init(const double* __restrict__ beta, Lsq q, double* _
 }
 
 // ---- the same Arnoldi step for many solves in one launch per kernel
-// One solve's buffers: h1 = hbuf, h2 = hbuf + hoff, tail = hbuf + 2 hoff; partial norms
-// n0 = nrm, n1 = nrm + r nsub, n2 = nrm + 2 r nsub.  The first pass skips the columns that
-// have stopped (q.active), the second runs on the columns that need it.
+// One solve's buffers: the reduced sums dv, the update coefficients coef, the partial norms
+// nrm (r nsub), vnext = V_{j+1}.
 struct ArnDesc {
-  const cd* V;
-  cd *w, *part, *hbuf, *vnext;  // vnext: V_{j+1}
+  cd *V, *w, *part, *dv, *coef, *vnext;
   double* nrm;
-  int* need;
   int* count;  // the solve's running-column count, in the area copied to the host
   Lsq q;
-  int64_t n, vstride, hoff;
-  int32_t r, nvec, nsub, j;
+  int64_t n, vstride;
+  int32_t r, nsub, j;
 };
 
 // work item of the row kernels: (solve, column, block of kGB/64 row ranges)
-__global__ __launch_bounds__(kGB) void k_ab_dots(const ArnDesc* __restrict__ D, const int4* __restrict__ work, int pass) {
+__global__ __launch_bounds__(kGB) void k_ab_dots(const ArnDesc* __restrict__ D, const int4* __restrict__ work) {
   const int4 wk = work[blockIdx.x];
   const ArnDesc& d = D[wk.x];
   const int sb = wk.z * (kGB / 64) + (threadIdx.x >> 6);
-  a_dots_body(sb, wk.y, d.V, d.vstride, d.nvec, d.w, d.n, d.r, d.nsub, pass ? d.need : d.q.active, d.part,
-              pass ? nullptr : d.nrm);
+  a_dots_body(sb, wk.y, d.V, d.vstride, d.j, d.w, d.n, d.r, d.nsub, d.q.active, d.part);
 }
-__global__ __launch_bounds__(kGB) void k_ab_update(const ArnDesc* __restrict__ D, const int4* __restrict__ work, int pass) {
+__global__ __launch_bounds__(kGB) void k_ab_update(const ArnDesc* __restrict__ D, const int4* __restrict__ work) {
   const int4 wk = work[blockIdx.x];
   const ArnDesc& d = D[wk.x];
   const int sb = wk.z * (kGB / 64) + (threadIdx.x >> 6);
-  const int64_t rn = (int64_t)d.r * d.nsub;
-  a_update_body(sb, wk.y, d.V, d.vstride, d.nvec, d.hbuf + (pass ? d.hoff : 0), d.w, d.n, d.r, d.nsub,
-                pass ? d.need : d.q.active, d.nrm + (pass ? 2 : 1) * rn);
+  a_update_body(sb, wk.y, d.V, d.vstride, d.j, d.coef, d.w, d.n, d.r, d.nsub, d.q.active, d.nrm);
 }
-// work item: (solve, block of kGB entries of h)
-__global__ __launch_bounds__(kGB) void k_ab_reduce(const ArnDesc* __restrict__ D, const int2* __restrict__ work, int pass) {
+// work item: (solve, block of kGB entries of the sums)
+__global__ __launch_bounds__(kGB) void k_ab_reduce(const ArnDesc* __restrict__ D, const int2* __restrict__ work) {
   const int2 wk = work[blockIdx.x];
   const ArnDesc& d = D[wk.x];
-  a_reduce_body((int64_t)wk.y * kGB + threadIdx.x, d.part, d.nsub, (int64_t)d.nvec * d.r, d.r,
-                pass ? d.need : d.q.active, d.hbuf + (pass ? d.hoff : 0));
+  a_reduce_body((int64_t)wk.y * kGB + threadIdx.x, d.part, d.nsub, (int64_t)(2 * d.j + 2) * d.r, d.r, d.q.active,
+                d.dv);
+}
+// work item: (solve, column), one wavefront
+__global__ __launch_bounds__(64) void k_ab_step(const ArnDesc* __restrict__ D, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const ArnDesc& d = D[wk.x];
+  step_body(wk.y, d.j, d.dv, d.coef, false, d.q);
+}
+// work item: (solve, block of 64 columns)
+__global__ __launch_bounds__(64) void k_ab_norm(const ArnDesc* __restrict__ D, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const ArnDesc& d = D[wk.x];
+  norm_body(wk.y * 64 + threadIdx.x, d.j, d.nrm, d.nsub, d.q);
 }
 // d.vnext[:, c] = d.w[:, c] * d.q.scale[c].x; work item: (solve, block of kGB elements)
 __global__ __launch_bounds__(kGB) void k_ab_scale(const ArnDesc* __restrict__ D, const int2* __restrict__ work) {
@@ -417,26 +450,6 @@ __global__ __launch_bounds__(kGB) void k_ab_scale(const ArnDesc* __restrict__ D,
   const double sc = d.q.scale[q / d.n].x;
   const cd v = d.w[q];
   d.vnext[q] = make_double2(v.x * sc, v.y * sc);
-}
-
-// work item: (solve, block of 64 columns)
-__global__ __launch_bounds__(64) void k_ab_decide(const ArnDesc* __restrict__ D, const int2* __restrict__ work) {
-  const int2 wk = work[blockIdx.x];
-  const ArnDesc& d = D[wk.x];
-  const int64_t rn = (int64_t)d.r * d.nsub;
-  a_decide_body(wk.y * 64 + threadIdx.x, d.nrm, d.nrm + rn, d.nsub, d.r, d.q.active, d.need);
-}
-__global__ __launch_bounds__(64) void k_ab_final(const ArnDesc* __restrict__ D, const int2* __restrict__ work) {
-  const int2 wk = work[blockIdx.x];
-  const ArnDesc& d = D[wk.x];
-  const int64_t rn = (int64_t)d.r * d.nsub;
-  a_final_body(wk.y * 64 + threadIdx.x, d.nrm + rn, d.nrm + 2 * rn, d.q.active, d.need, d.nsub, d.r,
-               d.hbuf + 2 * d.hoff);
-}
-__global__ __launch_bounds__(64) void k_ab_givens(const ArnDesc* __restrict__ D, const int2* __restrict__ work) {
-  const int2 wk = work[blockIdx.x];
-  const ArnDesc& d = D[wk.x];
-  givens_body(wk.y * 64 + threadIdx.x, d.j, d.hbuf, d.hbuf + d.hoff, d.hbuf + 2 * d.hoff, d.q);
 }
 // work item: one solve; its running-column count into d.count
 __global__ __launch_bounds__(64) void k_ab_count(const ArnDesc* __restrict__ D) {
@@ -575,12 +588,12 @@ struct Pinned {
 struct Work {
   int64_t n = 0;
   int r = 0, m = 0, nch = 0, nsub = 0;
-  DevArray<cd> V, w, t, d, part, hbuf, ybuf;
+  // dv: the reduced sums of a step, coef: its update coefficients (both (2m + 4) r)
+  DevArray<cd> V, w, t, d, part, dv, coef, ybuf;
   DevArray<double> nrm, nrm_out, rtol, sc0;
-  DevArray<int> need;
   DevArray<cf> x32, y32;
   // least-squares state of the current cycle (Lsq), on the device
-  DevArray<cd> H, g, cs, sn, scale;
+  DevArray<cd> H, Hu, g, cs, sn, scale;
   DevArray<int> active, jc, count;
   DevArray<unsigned long long> reorth;
   Pinned<int> hcount;      // running-column counts of the last two steps (a single solve)
@@ -592,7 +605,7 @@ struct Work {
       if (e) (void)hipEventDestroy(e);
   }
   Lsq lsq() {
-    return Lsq{H.p, g.p, cs.p, sn.p, scale.p, ybuf.p, active.p, jc.p, need.p, rtol.p, reorth.p, m, r};
+    return Lsq{H.p, Hu.p, g.p, cs.p, sn.p, scale.p, ybuf.p, active.p, jc.p, rtol.p, reorth.p, m, r};
   }
 };
 
@@ -602,14 +615,16 @@ int alloc_work(Work& W, int64_t n, int r, int m, bool lowp, hipStream_t s) {
   W.m = m;
   W.nch = (int)((n + kGRows - 1) / kGRows);
   W.nsub = (int)((n + kAWRows - 1) / kAWRows);
-  const int64_t hsz = 2 * (int64_t)(m + 1) * r + r;
+  // a step's sums: 2 j + 2 entries per column, j <= m (the end-of-cycle sweep has j = m);
+  // its coefficients: 2 j + 3
+  const int64_t nsum = (int64_t)(2 * m + 4) * r;
   int rc;
   if ((rc = W.V.alloc((int64_t)(m + 1) * n * r)) || (rc = W.w.alloc(n * r)) || (rc = W.t.alloc(n * r)) ||
-      (rc = W.d.alloc(n * r)) || (rc = W.part.alloc((int64_t)(m + 1) * r * std::max(W.nch, W.nsub))) ||
-      (rc = W.hbuf.alloc(hsz)) || (rc = W.ybuf.alloc((int64_t)(m + 1) * r)) ||
-      (rc = W.nrm.alloc(3 * (int64_t)r * std::max(W.nch, W.nsub))) || (rc = W.nrm_out.alloc(r)) ||
-      (rc = W.rtol.alloc(r)) || (rc = W.sc0.alloc(r)) || (rc = W.need.alloc(r)) ||
-      (rc = W.H.alloc((int64_t)r * m * (m + 1))) || (rc = W.g.alloc((int64_t)r * (m + 1))) ||
+      (rc = W.d.alloc(n * r)) || (rc = W.part.alloc(nsum * W.nsub)) || (rc = W.dv.alloc(nsum)) ||
+      (rc = W.coef.alloc(nsum)) || (rc = W.ybuf.alloc((int64_t)(m + 1) * r)) ||
+      (rc = W.nrm.alloc((int64_t)r * std::max(W.nch, W.nsub))) || (rc = W.nrm_out.alloc(r)) ||
+      (rc = W.rtol.alloc(r)) || (rc = W.sc0.alloc(r)) || (rc = W.H.alloc((int64_t)r * m * (m + 1))) ||
+      (rc = W.Hu.alloc((int64_t)r * m * (m + 1))) || (rc = W.g.alloc((int64_t)r * (m + 1))) ||
       (rc = W.cs.alloc((int64_t)r * m)) || (rc = W.sn.alloc((int64_t)r * m)) || (rc = W.scale.alloc(r)) ||
       (rc = W.active.alloc(r)) || (rc = W.jc.alloc(r)) || (rc = W.count.alloc(1)) || (rc = W.reorth.alloc(1)) ||
       (rc = W.hcount.alloc(2)) || (rc = W.hrtol.alloc(r)) || (rc = W.hreorth.alloc(1)))
@@ -744,34 +759,33 @@ int inner_start(uhm_krylov* K, const cd* rhs_src) {
   return cycle_start(K);
 }
 
-// One Arnoldi step after the product W.w = A V_j, all on the solve's stream: both
-// Gram-Schmidt passes, the Givens update of the least-squares problem, V_{j+1} = w / ||w||,
-// and a copy of the running-column count to pinned host memory (slot j % 2, event ev).
+// The sums of step j over the running columns: a = V^* t, b = V^* w (basis vectors
+// 0 .. j-1), t^* w and t^* t, t = V_j, reduced into W.dv.
+void step_sums(uhm_krylov* K, int j, const cd* w) {
+  Work& W = K->W;
+  const int r = K->r;
+  const int64_t n = K->n, vstride = n * r;
+  const dim3 gw((unsigned)((W.nsub + kGB / 64 - 1) / (kGB / 64)), (unsigned)r);
+  const int64_t nq = (int64_t)(2 * j + 2) * r;
+  hipLaunchKernelGGL(k_a_dots, gw, dim3(kGB), 0, K->s, W.V.p, vstride, j, w, n, r, W.nsub, W.active.p, W.part.p);
+  hipLaunchKernelGGL(k_a_reduce, dim3(nblk(nq)), dim3(kGB), 0, K->s, W.part.p, W.nsub, nq, r, W.active.p, W.dv.p);
+}
+
+// One Arnoldi step after the product W.w = A V_j, all on the solve's stream: the sums, the
+// delayed projection of V_j with the final Hessenberg column j - 1 and its rotation, the
+// projection of w and the provisional column j, V_{j+1} = w / ||w||, and a copy of the
+// running-column count to pinned host memory (slot j % 2, event ev).
 int arnoldi_issue(uhm_krylov* K) {
   Work& W = K->W;
-  const int r = K->r, m = K->o.restart, j = K->j;
+  const int r = K->r, j = K->j;
   const int64_t n = K->n, vstride = n * r;
   hipStream_t s = K->s;
-  const int ns = W.nsub;
-  const dim3 gw((unsigned)((ns + kGB / 64 - 1) / (kGB / 64)), (unsigned)r);
-  const dim3 gc((unsigned)((r + 63) / 64));
-  const int64_t nq = (int64_t)(j + 1) * r, hoff = (int64_t)(m + 1) * r;
-  cd *h1 = W.hbuf.p, *h2 = W.hbuf.p + hoff, *tail = W.hbuf.p + 2 * hoff;
-  double *n0 = W.nrm.p, *n1 = n0 + (int64_t)r * ns, *n2 = n1 + (int64_t)r * ns;
-  const int* act = W.active.p;
-  // first classical Gram-Schmidt pass, running columns
-  hipLaunchKernelGGL(k_a_dots, gw, dim3(kGB), 0, s, W.V.p, vstride, j + 1, W.w.p, n, r, ns, act, W.part.p, n0);
-  hipLaunchKernelGGL(k_a_reduce, dim3(nblk(nq)), dim3(kGB), 0, s, W.part.p, ns, nq, r, act, h1);
-  hipLaunchKernelGGL(k_a_update, gw, dim3(kGB), 0, s, W.V.p, vstride, j + 1, h1, W.w.p, n, r, ns, act, n1);
-  hipLaunchKernelGGL(k_a_decide, gc, dim3(64), 0, s, n0, n1, ns, r, act, W.need.p);
-  // second pass for the columns that need it
-  hipLaunchKernelGGL(k_a_dots, gw, dim3(kGB), 0, s, W.V.p, vstride, j + 1, W.w.p, n, r, ns, W.need.p, W.part.p,
-                     nullptr);
-  hipLaunchKernelGGL(k_a_reduce, dim3(nblk(nq)), dim3(kGB), 0, s, W.part.p, ns, nq, r, W.need.p, h2);
-  hipLaunchKernelGGL(k_a_update, gw, dim3(kGB), 0, s, W.V.p, vstride, j + 1, h2, W.w.p, n, r, ns, W.need.p, n2);
-  hipLaunchKernelGGL(k_a_final, gc, dim3(64), 0, s, n1, n2, act, W.need.p, ns, r, tail);
-  // least-squares update, then the next basis vector
-  hipLaunchKernelGGL(k_a_givens, gc, dim3(64), 0, s, j, h1, h2, tail, W.lsq());
+  const dim3 gw((unsigned)((W.nsub + kGB / 64 - 1) / (kGB / 64)), (unsigned)r);
+  step_sums(K, j, W.w.p);
+  hipLaunchKernelGGL(k_a_step, dim3((unsigned)r), dim3(64), 0, s, j, W.dv.p, W.coef.p, 0, W.lsq());
+  hipLaunchKernelGGL(k_a_update, gw, dim3(kGB), 0, s, W.V.p, vstride, j, W.coef.p, W.w.p, n, r, W.nsub, W.active.p,
+                     W.nrm.p);
+  hipLaunchKernelGGL(k_a_norm, dim3((unsigned)((r + 63) / 64)), dim3(64), 0, s, j, W.nrm.p, W.nsub, W.lsq());
   hipLaunchKernelGGL(k_g_scale2, dim3(nblk(n * r)), dim3(kGB), 0, s, W.w.p, W.scale.p, n, r,
                      W.V.p + (int64_t)(j + 1) * vstride);
   hipLaunchKernelGGL(k_a_count, dim3(1), dim3(64), 0, s, W.active.p, r, W.count.p);
@@ -794,9 +808,12 @@ int arnoldi_next(uhm_krylov* K, bool all_done) {
     K->req_out = W.w.p;
     return UHM_OK;
   }
-  // end of the cycle: y_c = R_c^{-1} g_c on the device, d += V y, then the residual
-  // t = rhs - A d
+  // end of the cycle: the last column is still provisional; the delayed projection of
+  // V_jm (no product) makes it final.  Then y_c = R_c^{-1} g_c on the device, d += V y,
+  // and the residual t = rhs - A d.
   const int jm = K->j;
+  step_sums(K, jm, W.V.p + (int64_t)jm * vstride);
+  hipLaunchKernelGGL(k_a_step, dim3((unsigned)r), dim3(64), 0, s, jm, W.dv.p, W.coef.p, 1, W.lsq());
   hipLaunchKernelGGL(k_a_lsq, dim3((r + 63) / 64), dim3(64), 0, s, jm, W.lsq());
   hipLaunchKernelGGL(k_g_combine, dim3(nblk(n * r)), dim3(kGB), 0, s, W.V.p, vstride, jm, W.ybuf.p, W.d.p, n, n, r);
   if (inner_cycles_spent(K)) {
@@ -834,8 +851,8 @@ size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
 // Offsets of one batched step in the scratch buffers (bytes).
 struct ManyLayout {
-  size_t o_d, o_row, o_red, o_col, o_sw, o_g, tot;
-  unsigned nrow, nred, ncol, nsw;
+  size_t o_d, o_row, o_red, o_step, o_col, o_sw, o_g, tot;
+  unsigned nrow, nred, nstep, ncol, nsw;
 };
 
 // arnoldi_issue for many solves: each kernel is launched once over the work of all of them
@@ -845,20 +862,22 @@ struct ManyLayout {
 int arnoldi_issue_many(const std::vector<uhm_krylov*>& iter, hipStream_t s, StepScratch& ss, ManyLayout& Lo) {
   std::vector<ArnDesc> D;
   std::vector<int4> wrow;
-  std::vector<int2> wred, wcol, wsc;
+  std::vector<int2> wred, wstep, wcol, wsc;
   // layout first: descriptors point into the gather area for their counts
-  size_t nrow = 0, nred = 0, ncol = 0, nsc = 0;
+  size_t nrow = 0, nred = 0, nstep = 0, ncol = 0, nsc = 0;
   for (uhm_krylov* K : iter) {
     const int r = K->r;
     nrow += (size_t)r * ((K->W.nsub + kGB / 64 - 1) / (kGB / 64));
-    nred += (size_t)(((int64_t)(K->j + 1) * r + kGB - 1) / kGB);
+    nred += (size_t)(((int64_t)(2 * K->j + 2) * r + kGB - 1) / kGB);
+    nstep += (size_t)r;
     ncol += (size_t)((r + 63) / 64);
     nsc += (size_t)((K->n * r + kGB - 1) / kGB);
   }
   Lo.o_d = 0;
   Lo.o_row = align16(sizeof(ArnDesc) * iter.size());
   Lo.o_red = Lo.o_row + align16(sizeof(int4) * nrow);
-  Lo.o_col = Lo.o_red + align16(sizeof(int2) * nred);
+  Lo.o_step = Lo.o_red + align16(sizeof(int2) * nred);
+  Lo.o_col = Lo.o_step + align16(sizeof(int2) * nstep);
   Lo.o_sw = Lo.o_col + align16(sizeof(int2) * ncol);
   Lo.o_g = Lo.o_sw + align16(sizeof(int2) * nsc);  // running-column counts, device -> host
   Lo.tot = Lo.o_g + align16(sizeof(int) * iter.size());
@@ -876,54 +895,53 @@ int arnoldi_issue_many(const std::vector<uhm_krylov*>& iter, hipStream_t s, Step
   for (size_t k = 0; k < iter.size(); ++k) {
     uhm_krylov* K = iter[k];
     Work& W = K->W;
-    const int r = K->r, m = K->o.restart, j = K->j;
+    const int r = K->r, j = K->j;
     ArnDesc d{};
     d.V = W.V.p;
     d.w = W.w.p;
     d.part = W.part.p;
-    d.hbuf = W.hbuf.p;
+    d.dv = W.dv.p;
+    d.coef = W.coef.p;
     d.vnext = W.V.p + (int64_t)(j + 1) * K->n * r;
     d.nrm = W.nrm.p;
-    d.need = W.need.p;
     d.count = dcount + k;
     d.q = W.lsq();
     d.n = K->n;
     d.vstride = K->n * r;
-    d.hoff = (int64_t)(m + 1) * r;
     d.r = r;
-    d.nvec = j + 1;
     d.nsub = W.nsub;
     d.j = j;
     D.push_back(d);
     const int ki = (int)k;
     for (int c = 0; c < r; ++c)
       for (int zb = 0; zb < (W.nsub + kGB / 64 - 1) / (kGB / 64); ++zb) wrow.push_back(make_int4(ki, c, zb, 0));
-    for (int64_t qb = 0; qb < ((int64_t)(j + 1) * r + kGB - 1) / kGB; ++qb) wred.push_back(make_int2(ki, (int)qb));
+    for (int64_t qb = 0; qb < ((int64_t)(2 * j + 2) * r + kGB - 1) / kGB; ++qb) wred.push_back(make_int2(ki, (int)qb));
+    for (int c = 0; c < r; ++c) wstep.push_back(make_int2(ki, c));
     for (int cb = 0; cb < (r + 63) / 64; ++cb) wcol.push_back(make_int2(ki, cb));
     for (int64_t sb = 0; sb < (K->n * r + kGB - 1) / kGB; ++sb) wsc.push_back(make_int2(ki, (int)sb));
   }
   Lo.nrow = (unsigned)wrow.size();
   Lo.nred = (unsigned)wred.size();
+  Lo.nstep = (unsigned)wstep.size();
   Lo.ncol = (unsigned)wcol.size();
   Lo.nsw = (unsigned)wsc.size();
   std::memcpy(ss.host + Lo.o_d, D.data(), sizeof(ArnDesc) * D.size());
   std::memcpy(ss.host + Lo.o_row, wrow.data(), sizeof(int4) * wrow.size());
   std::memcpy(ss.host + Lo.o_red, wred.data(), sizeof(int2) * wred.size());
+  std::memcpy(ss.host + Lo.o_step, wstep.data(), sizeof(int2) * wstep.size());
   std::memcpy(ss.host + Lo.o_col, wcol.data(), sizeof(int2) * wcol.size());
   std::memcpy(ss.host + Lo.o_sw, wsc.data(), sizeof(int2) * wsc.size());
   UHM_HIP(hipMemcpyAsync(ss.dev, ss.host, Lo.o_g, hipMemcpyHostToDevice, s));
   const ArnDesc* dD = reinterpret_cast<const ArnDesc*>(ss.dev + Lo.o_d);
   const int4* dRow = reinterpret_cast<const int4*>(ss.dev + Lo.o_row);
   const int2* dRed = reinterpret_cast<const int2*>(ss.dev + Lo.o_red);
+  const int2* dStep = reinterpret_cast<const int2*>(ss.dev + Lo.o_step);
   const int2* dCol = reinterpret_cast<const int2*>(ss.dev + Lo.o_col);
-  for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(k_ab_dots, dim3(Lo.nrow), dim3(kGB), 0, s, dD, dRow, pass);
-    hipLaunchKernelGGL(k_ab_reduce, dim3(Lo.nred), dim3(kGB), 0, s, dD, dRed, pass);
-    hipLaunchKernelGGL(k_ab_update, dim3(Lo.nrow), dim3(kGB), 0, s, dD, dRow, pass);
-    if (pass == 0) hipLaunchKernelGGL(k_ab_decide, dim3(Lo.ncol), dim3(64), 0, s, dD, dCol);
-  }
-  hipLaunchKernelGGL(k_ab_final, dim3(Lo.ncol), dim3(64), 0, s, dD, dCol);
-  hipLaunchKernelGGL(k_ab_givens, dim3(Lo.ncol), dim3(64), 0, s, dD, dCol);
+  hipLaunchKernelGGL(k_ab_dots, dim3(Lo.nrow), dim3(kGB), 0, s, dD, dRow);
+  hipLaunchKernelGGL(k_ab_reduce, dim3(Lo.nred), dim3(kGB), 0, s, dD, dRed);
+  hipLaunchKernelGGL(k_ab_step, dim3(Lo.nstep), dim3(64), 0, s, dD, dStep);
+  hipLaunchKernelGGL(k_ab_update, dim3(Lo.nrow), dim3(kGB), 0, s, dD, dRow);
+  hipLaunchKernelGGL(k_ab_norm, dim3(Lo.ncol), dim3(64), 0, s, dD, dCol);
   hipLaunchKernelGGL(k_ab_scale, dim3(Lo.nsw), dim3(kGB), 0, s, dD, reinterpret_cast<const int2*>(ss.dev + Lo.o_sw));
   hipLaunchKernelGGL(k_ab_count, dim3((unsigned)iter.size()), dim3(64), 0, s, dD);
   UHM_HIP(hipMemcpyAsync(ss.host + Lo.o_g, ss.dev + Lo.o_g, sizeof(int) * iter.size(), hipMemcpyDeviceToHost, s));
