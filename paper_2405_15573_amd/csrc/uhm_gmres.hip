@@ -44,9 +44,36 @@ using cf = float2;
 constexpr int kGB = 256;      // threads per block
 constexpr int kGRows = 2048;  // rows per block in the batched reductions
 
+// A DPP rotation by N lanes within each 16-lane row.
+template <int N>
+__device__ __forceinline__ double row_ror(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x120 + N, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x120 + N, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum of v over the 64 lanes of the wave (all lanes active), the same value in every lane.
+// Lane moves only, no LDS: the gfx950 lane swaps add the two halves (v_permlane32_swap)
+// and then the row pairs (v_permlane16_swap), so each lane holds the sum of its four lanes
+// L mod 16 + 16 k; four DPP rotations sum each 16-lane row; lane 0's total is broadcast.
+// The order of the additions is fixed.
 __device__ __forceinline__ double warp_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    v = __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+  }
+  {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+    v = __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+  }
+  v += row_ror<8>(v);
+  v += row_ror<4>(v);
+  v += row_ror<2>(v);
+  v += row_ror<1>(v);
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
 }
 
 // Block-wide sum of (re, im) into (out[0], out[1]) of thread 0; fixed order.
