@@ -46,7 +46,7 @@ enum {
   UHM_ENOMEM = -2,   /* a device or host allocation failed; the call had no side effects */
   UHM_EHIP = -3,     /* a HIP runtime call failed; see uhm_last_error */
   UHM_ENOCONV = -4,  /* an iterative solve stopped at its iteration limit */
-  UHM_ENOTSUP = -5   /* valid request that this build does not support */
+  UHM_ENOTSUP = -5   /* valid request that the library does not support */
 };
 
 /* Storage precision of the uploaded operator. */

@@ -1239,7 +1239,7 @@ const char* uhm_strerror(int code) {
     case UHM_ENOMEM: return "out of memory";
     case UHM_EHIP: return "HIP runtime error";
     case UHM_ENOCONV: return "iteration limit reached without convergence";
-    case UHM_ENOTSUP: return "not supported by this build";
+    case UHM_ENOTSUP: return "not supported by the library";
     default: return "unknown error";
   }
 }
@@ -1552,7 +1552,7 @@ int uhm_upload(const uhm_host_operator* h, uhm_storage storage, void* hip_stream
 int uhm_upload_h(const uhm_host_hmatrix* h, uhm_storage storage, void* hip_stream, uhm_op** out) {
   if (!h || !out) return fail(UHM_EINVAL, "null argument");
   *out = nullptr;
-  if (storage != UHM_C128) return fail(UHM_ENOTSUP, "storage precision not available in this build");
+  if (storage != UHM_C128) return fail(UHM_ENOTSUP, "the H-matrix form is stored in complex128 only");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   TreeInfo T;
   int rc = check_tree(h->n, h->perm, h->nclusters, h->off, h->size, h->parent, T);
