@@ -446,6 +446,40 @@ int uhm_aca_pack(const uhm_block_desc* blocks, int64_t nblocks, const int32_t* r
                  const double* V, int64_t V_len, const int32_t* sel, int32_t cnt, int32_t m, int32_t n, int32_t kp,
                  double* X, double* Y, int32_t* status, void* hip_stream);
 
+/*
+ * Alg. 2's per-cluster factorisation (section 4.2) for a batch of `batch` clusters of one
+ * shape: for each X_c (m x n complex128, column-major, X + 2*c*m*n; zero columns allowed)
+ * it returns the left singular vectors whose singular values exceed eps * sigma_1 (U_tau,
+ * rank l = at least 1) and the rows Sigma V^* = U_tau^* X_c, the same rank rule as a full
+ * SVD.  The SVD is taken as: Householder QR with column pivoting of X_c, stopped once the
+ * trailing part's Frobenius norm T is at most tol * ||X_c||_F (p steps; the singular values
+ * of the resulting p x n factor B are those of X_c to within T), an unpivoted QR of B^*,
+ * one-sided Jacobi on its p x p triangle, and the reflectors applied back.  tol = 1e-14 puts
+ * the difference at the level of rounding.
+ * X (destroyed), U, SV, sv, rank, psteps, stats, status and work are device arrays:
+ *   U[c]:  m x pmax complex (column-major, U + 2*c*m*pmax), columns 0..l-1 written;
+ *   SV[c]: pmax x n complex (column-major with leading dimension pmax, SV + 2*c*pmax*n),
+ *          rows 0..l-1 written: SV = U^* X;
+ *   sv[c*pmax + i]: singular values of B, descending (zeros beyond p);
+ *   rank[c] = l, psteps[c] = p;
+ *   stats[3c..3c+2] = ||X - U U^* X||_F (the dropped sigma_i(B) and T together), the first
+ *          dropped singular value (sigma_{l+1}(B); T if l = p < min(m, n); 0 if l = min(m, n)),
+ *          and T;
+ *   status[c] = 0, or bit 0: pmax steps ended before the tolerance (the result is that of
+ *          the truncated QR; call again with a larger pmax), bit 1: the Jacobi sweeps did not
+ *          converge within 60 sweeps.
+ * work: uhm_cluster_basis_work(batch, m, n, pmax) doubles of device memory (work_len counts
+ * doubles); nothing is allocated.  Limits: m <= 16384, 1 <= pmax <= min(m, n, 1024), batch
+ * <= 65535.  Asynchronous on hip_stream.  Errors: UHM_EINVAL (sizes, tol or eps negative or
+ * not finite, null pointers, work too small), UHM_EHIP.
+ */
+int uhm_cluster_basis(double* X, int32_t batch, int32_t m, int32_t n, int32_t pmax, double tol, double eps,
+                      double* U, double* SV, double* sv, int32_t* rank, int32_t* psteps, double* stats,
+                      int32_t* status, double* work, int64_t work_len, void* hip_stream);
+
+/* Workspace of uhm_cluster_basis in doubles, or -1 for sizes it rejects outright. */
+int64_t uhm_cluster_basis_work(int32_t batch, int32_t m, int32_t n, int32_t pmax);
+
 const char* uhm_strerror(int code);
 const char* uhm_last_error(void);
 int uhm_version(void);

@@ -79,7 +79,7 @@ EXPORTS = ("uhm_upload", "uhm_upload_h", "uhm_matvec", "uhm_matvec_noalloc", "uh
            "uhm_batch_create", "uhm_batch_run",
            "uhm_batch_tune", "uhm_batch_capture", "uhm_batch_free", "uhm_op_info_get", "uhm_set_timing",
            "uhm_kernel_times", "uhm_free", "uhm_strerror", "uhm_last_error", "uhm_version",
-           "uhm_kernel_blocks", "uhm_aca", "uhm_aca_pack")
+           "uhm_kernel_blocks", "uhm_aca", "uhm_aca_pack", "uhm_cluster_basis", "uhm_cluster_basis_work")
 
 _LIB = None
 
@@ -148,6 +148,10 @@ def load_library(path: str = LIB_PATH):
     lib.uhm_aca_pack.argtypes = [P, I64, P, P, I64, P, I64, P, I32, I32, I32, I32, P, P, P, P]
     lib.uhm_aca_pack.restype = ctypes.c_int
     lib.uhm_aca.restype = ctypes.c_int
+    lib.uhm_cluster_basis.argtypes = [P, I32, I32, I32, I32, D, D, P, P, P, P, P, P, P, P, I64, P]
+    lib.uhm_cluster_basis.restype = ctypes.c_int
+    lib.uhm_cluster_basis_work.argtypes = [I32, I32, I32, I32]
+    lib.uhm_cluster_basis_work.restype = I64
     _LIB = lib
     return lib
 
@@ -648,3 +652,54 @@ def aca_pack(res: AcaResult, sel, m: int, n: int, kp: int, stream=None):
     if (st != 1).any():
         raise UhmError(UHM_EINVAL, f"uhm_aca_pack: {int((st != 1).sum())} blocks rejected")
     return X, Y
+
+
+class ClusterBasis:
+    """Results of uhm_cluster_basis for a batch: device tensors U (batch, pmax, m) holding
+    U_c^T row by row (column i of U_c is U[c, i, :]), SV (batch, n, pmax) holding (Sigma
+    V^*)^T, sv (batch, pmax); host arrays rank, psteps, stats (batch, 3) and status."""
+
+    def __init__(self, U, SV, sv, rank, psteps, stats, status):
+        self.U, self.SV, self.sv = U, SV, sv
+        self.rank, self.psteps, self.stats, self.status = rank, psteps, stats, status
+
+    def basis(self, c: int):
+        """U_c (m x l) and Sigma V^* (l x n) of matrix c as host arrays."""
+        l = int(self.rank[c])
+        return self.U[c, :l, :].cpu().numpy().T, self.SV[c, :, :l].cpu().numpy().T
+
+
+def cluster_basis(X, eps: float, tol: float = 1e-14, pmax: int | None = None, stream=None) -> ClusterBasis:
+    """Alg. 2's factorisation of a batch of cluster matrices X (batch, m, n), complex128
+    (host or device; copied, so the argument is kept), on the device (uhm_cluster_basis)."""
+    import torch
+    lib = load_library()
+    Xt = torch.as_tensor(X)
+    batch, m, n = (int(v) for v in Xt.shape)
+    pmax = int(min(m, n, 1024) if pmax is None else pmax)
+    h, stream = _stream_handle(stream)
+    with torch.cuda.stream(stream):
+        # column-major per matrix: the (batch, n, m) layout of X^T
+        Xd = Xt.to(device="cuda", dtype=torch.complex128).transpose(1, 2).contiguous()
+        need = int(lib.uhm_cluster_basis_work(batch, m, n, pmax))
+        if need < 0:
+            raise UhmError(UHM_EINVAL, "uhm_cluster_basis_work: sizes rejected")
+        work = torch.empty(max(1, need), dtype=torch.float64, device="cuda")
+        U = torch.empty((batch, pmax, m), dtype=torch.complex128, device="cuda")
+        SV = torch.empty((batch, n, pmax), dtype=torch.complex128, device="cuda")
+        sv = torch.empty((batch, pmax), dtype=torch.float64, device="cuda")
+        rank = torch.empty(max(1, batch), dtype=torch.int32, device="cuda")
+        psteps = torch.empty(max(1, batch), dtype=torch.int32, device="cuda")
+        stats = torch.empty((max(1, batch), 3), dtype=torch.float64, device="cuda")
+        status = torch.empty(max(1, batch), dtype=torch.int32, device="cuda")
+        _check(lib.uhm_cluster_basis(ctypes.c_void_p(Xd.data_ptr()), batch, m, n, pmax, float(tol), float(eps),
+                                     ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(SV.data_ptr()),
+                                     ctypes.c_void_p(sv.data_ptr()), ctypes.c_void_p(rank.data_ptr()),
+                                     ctypes.c_void_p(psteps.data_ptr()), ctypes.c_void_p(stats.data_ptr()),
+                                     ctypes.c_void_p(status.data_ptr()), ctypes.c_void_p(work.data_ptr()), need, h),
+               "uhm_cluster_basis")
+        res = ClusterBasis(U, SV, sv, rank.cpu().numpy()[:batch], psteps.cpu().numpy()[:batch],
+                           stats.cpu().numpy()[:batch], status.cpu().numpy()[:batch])
+        del Xd, work
+    return res
+

@@ -1,0 +1,157 @@
+"""Alg. 2's per-cluster factorisation on the GPU (uhm_cluster_basis, section 4.2).
+
+Pins independent of both sides:
+* matrices built as Q1 diag(s) Q2^* with orthonormal Q1, Q2 have the singular values s
+  (a closed form), so the rank at eps * s_1 is known; the s are spaced so that none lies
+  within 1e-6 of the threshold;
+* Eckart-Young: the best rank-l projection error is s_{l+1} in the 2-norm and
+  sqrt(sum_{i>l} s_i^2) in the Frobenius norm;
+* U orthonormal and Sigma V^* = U^* X.
+On the builder's own cluster matrices the GPU bases are checked against the oracle's
+Alg. 1 (the SVD of the agglomerated block row of the assembled H-matrix): same ranks and
+the optimal projection error.
+"""
+import numpy as np
+import pytest
+
+from conftest import operator
+from oracle import uniform
+
+pytestmark = pytest.mark.gpu
+
+
+def _binding():
+    from paper_2405_15573_amd import binding
+    return binding
+
+
+def _prescribed(rng, m, n, s):
+    k = s.size
+    q1, _ = np.linalg.qr(rng.standard_normal((m, k)) + 1j * rng.standard_normal((m, k)))
+    q2, _ = np.linalg.qr(rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k)))
+    return (q1 * s) @ q2.conj().T
+
+
+def _decay(k, ratio, jitter, rng):
+    """Geometric singular values with a random jitter, none within 1e-3 (relative) of 1e-6."""
+    s = ratio ** np.arange(k) * np.exp(jitter * rng.uniform(-1, 1, k))
+    s = np.sort(s)[::-1] / s.max()
+    near = np.abs(s / 1e-6 - 1.0) < 1e-3
+    s[near] *= 1.01
+    return np.sort(s)[::-1]
+
+
+def _check(X, res, c, eps, s_true=None):
+    m, n = X.shape
+    U, SV = res.basis(c)
+    l = int(res.rank[c])
+    assert res.status[c] == 0
+    s_ref = np.linalg.svd(X, compute_uv=False) if s_true is None else s_true
+    l_ref = max(1, int(np.count_nonzero(s_ref > eps * s_ref[0]))) if s_ref[0] > 0 else 1
+    assert l == l_ref
+    assert U.shape == (m, l) and SV.shape == (l, n)
+    assert np.linalg.norm(U.conj().T @ U - np.eye(l)) < 1e-13
+    nx = np.linalg.norm(X)
+    assert np.linalg.norm(SV - U.conj().T @ X) <= 1e-13 * max(nx, 1e-300)
+    sv = res.sv.cpu().numpy()[c]
+    p = int(res.psteps[c])
+    kk = min(p, s_ref.size)
+    assert np.all(np.abs(sv[:kk] - s_ref[:kk]) <= 1e-13 * s_ref[0] + 1e-300)
+    best2 = s_ref[l] if l < s_ref.size else 0.0
+    assert np.linalg.norm(X - U @ SV, 2) <= best2 * (1 + 1e-6) + 1e-13 * s_ref[0]
+    bestF = np.sqrt(np.sum(s_ref[l:] ** 2))
+    assert abs(res.stats[c, 0] - bestF) <= 1e-6 * bestF + 1e-13 * s_ref[0]
+    assert abs(res.stats[c, 1] - best2) <= 1e-6 * best2 + 1e-13 * s_ref[0]
+    assert res.stats[c, 2] <= 1e-14 * nx * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("m,n,ratio", [(200, 300, 0.9), (300, 120, 0.85), (64, 250, 0.8), (1024, 700, 0.93),
+                                       (130, 70, 0.7)])
+def test_prescribed_singular_values(m, n, ratio):
+    rng = np.random.default_rng(m * 7 + n)
+    batch = 3
+    k = min(m, n)
+    Xs, ss = [], []
+    for c in range(batch):
+        s = _decay(k, ratio, 0.2, rng)
+        ss.append(s)
+        Xs.append(_prescribed(rng, m, n, s))
+    res = _binding().cluster_basis(np.stack(Xs), eps=1e-6)
+    for c in range(batch):
+        _check(Xs[c], res, c, 1e-6, ss[c])
+
+
+def test_ragged_batch_with_zero_padding_and_edge_cases():
+    """Matrices of one batch with different column counts (zero columns pad them, as the
+    builder pads a group of clusters), a zero matrix, and an exact rank-1 matrix."""
+    rng = np.random.default_rng(5)
+    m, n = 96, 160
+    Xs = []
+    for kc in (160, 97, 33, 1):
+        s = _decay(min(m, kc), 0.85, 0.1, rng)
+        X = np.zeros((m, n), complex)
+        X[:, :kc] = _prescribed(rng, m, kc, s)
+        Xs.append(X)
+    Xs.append(np.zeros((m, n), complex))
+    u = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    Xs.append(np.outer(u, v.conj()))
+    res = _binding().cluster_basis(np.stack(Xs), eps=1e-6)
+    for c in range(4):
+        _check(Xs[c], res, c, 1e-6)
+    # the zero matrix: rank 1, a unit vector, zero rows and zero error
+    U, SV = res.basis(4)
+    assert res.rank[4] == 1 and res.psteps[4] == 0 and res.status[4] == 0
+    assert abs(np.linalg.norm(U) - 1.0) < 1e-15 and np.all(SV == 0) and np.all(res.stats[4] == 0)
+    # rank 1: one QR step reaches the tolerance
+    _check(Xs[5], res, 5, 1e-6)
+    assert res.rank[5] == 1 and res.psteps[5] == 1
+
+
+def test_capacity_flag():
+    """pmax below the QR rank at the tolerance is reported in status bit 0."""
+    rng = np.random.default_rng(11)
+    X = _prescribed(rng, 120, 150, _decay(120, 0.95, 0.0, rng))
+    res = _binding().cluster_basis(X[None], eps=1e-6, pmax=40)
+    assert res.status[0] & 1 and res.psteps[0] == 40
+
+
+def test_rejects_bad_arguments():
+    b = _binding()
+    with pytest.raises(b.UhmError):
+        b.cluster_basis(np.zeros((1, 8, 8), complex), eps=1e-6, pmax=9)
+    with pytest.raises(b.UhmError):
+        b.cluster_basis(np.zeros((1, 8, 8), complex), eps=-1.0)
+
+
+def test_builder_clusters_match_algorithm_1():
+    """The GPU factorisation of the builder's thin factors X_tau gives Alg. 1's ranks and
+    optimal projection error on the assembled H-matrix (the oracle)."""
+    _, op = operator("sphere", 3000, leaf=32, seed=3)
+    o = vars(op)
+    ah = uniform.assemble_h(o)
+    b = _binding()
+    checked = 0
+    for t in np.nonzero(op.rank_row)[0][::7]:
+        t = int(t)
+        nt = int(op.size[t])
+        blocks = [q for q in range(op.nadm) if int(op.adm_row[q]) == t]
+        X = np.concatenate([op.X[op.X_off[q]:op.X_off[q] + nt * op.adm_rank[q]].reshape(op.adm_rank[q], nt).T
+                            for q in blocks], 1)
+        u1, sv = uniform.optimal_row_basis(ah, o, t, op.eps_comp)
+        if np.any(np.abs(sv - op.eps_comp * sv[0]) < 1e-9 * sv[0]):
+            continue  # a singular value on the threshold: the rank is rounding-dependent
+        res = b.cluster_basis(X[None], eps=op.eps_comp)
+        assert res.status[0] == 0
+        l = int(res.rank[0])
+        assert l == u1.shape[1]
+        U, _ = res.basis(0)
+        assert np.linalg.norm(U.conj().T @ U - np.eye(l)) < 1e-13
+        cols = [int(op.adm_col[q]) for q in blocks]
+        rows = op.perm[op.off[t]:op.off[t] + nt]
+        at = np.concatenate([ah[np.ix_(rows, op.perm[op.off[s]:op.off[s] + op.size[s]])] for s in cols], 1)
+        err = np.linalg.norm(at - U @ (U.conj().T @ at), 2)
+        best = sv[l] if l < sv.size else 0.0
+        assert err <= best * (1 + 1e-6) + 1e-13 * sv[0]
+        checked += 1
+    assert checked >= 8
