@@ -453,9 +453,11 @@ int uhm_aca_pack(const uhm_block_desc* blocks, int64_t nblocks, const int32_t* r
  * rank l = at least 1) and the rows Sigma V^* = U_tau^* X_c, the same rank rule as a full
  * SVD.  The SVD is taken as: Householder QR with column pivoting of X_c, stopped once the
  * trailing part's Frobenius norm T is at most tol * ||X_c||_F (p steps; the singular values
- * of the resulting p x n factor B are those of X_c to within T), an unpivoted QR of B^*,
- * one-sided Jacobi on its p x p triangle, and the reflectors applied back.  tol = 1e-14 puts
- * the difference at the level of rounding.
+ * of the resulting p x n factor B satisfy sigma_i(B)^2 <= sigma_i(X_c)^2 <= sigma_i(B)^2 +
+ * T^2, because the trailing part is orthogonal to the kept range), an unpivoted QR of B^*,
+ * one-sided Jacobi on its p x p triangle, and the reflectors applied back.  With tol^2 about
+ * 1e-16 eps (1e-11 for eps = 1e-6) a singular value at the threshold eps sigma_1 moves by
+ * less than a unit of rounding of sigma_1.
  * X (destroyed), U, SV, sv, rank, psteps, stats, status and work are device arrays:
  *   U[c]:  m x pmax complex (column-major, U + 2*c*m*pmax), columns 0..l-1 written;
  *   SV[c]: pmax x n complex (column-major with leading dimension pmax, SV + 2*c*pmax*n),
@@ -463,13 +465,13 @@ int uhm_aca_pack(const uhm_block_desc* blocks, int64_t nblocks, const int32_t* r
  *   sv[c*pmax + i]: singular values of B, descending (zeros beyond p);
  *   rank[c] = l, psteps[c] = p;
  *   stats[3c..3c+2] = ||X - U U^* X||_F (the dropped sigma_i(B) and T together), the first
- *          dropped singular value (sigma_{l+1}(B); T if l = p < min(m, n); 0 if l = min(m, n)),
- *          and T;
+ *          dropped singular value (sqrt(sigma_{l+1}(B)^2 + T^2), an upper bound of sigma_{l+1}(X_c)
+ *          within T^2 / (2 sigma_{l+1}); 0 if l = min(m, n)), and T;
  *   status[c] = 0, or bit 0: pmax steps ended before the tolerance (the result is that of
  *          the truncated QR; call again with a larger pmax), bit 1: the Jacobi sweeps did not
  *          converge within 60 sweeps.
  * work: uhm_cluster_basis_work(batch, m, n, pmax) doubles of device memory (work_len counts
- * doubles); nothing is allocated.  Limits: m <= 16384, 1 <= pmax <= min(m, n, 1024), batch
+ * doubles); nothing is allocated.  Limits: m <= 16384, 1 <= pmax <= min(m, n, 2048), batch
  * <= 65535.  Asynchronous on hip_stream.  Errors: UHM_EINVAL (sizes, tol or eps negative or
  * not finite, null pointers, work too small), UHM_EHIP.
  */

@@ -669,14 +669,17 @@ class ClusterBasis:
         return self.U[c, :l, :].cpu().numpy().T, self.SV[c, :, :l].cpu().numpy().T
 
 
-def cluster_basis(X, eps: float, tol: float = 1e-14, pmax: int | None = None, stream=None) -> ClusterBasis:
+def cluster_basis(X, eps: float, tol: float | None = None, pmax: int | None = None, stream=None) -> ClusterBasis:
     """Alg. 2's factorisation of a batch of cluster matrices X (batch, m, n), complex128
-    (host or device; copied, so the argument is kept), on the device (uhm_cluster_basis)."""
+    (host or device; copied, so the argument is kept), on the device (uhm_cluster_basis).
+    tol defaults to sqrt(1e-16 eps), where the rank test is that of a full SVD up to rounding."""
     import torch
     lib = load_library()
     Xt = torch.as_tensor(X)
     batch, m, n = (int(v) for v in Xt.shape)
-    pmax = int(min(m, n, 1024) if pmax is None else pmax)
+    pmax = int(min(m, n, 2048) if pmax is None else pmax)
+    if tol is None:
+        tol = float(np.sqrt(1e-16 * max(eps, 0.0)))
     h, stream = _stream_handle(stream)
     with torch.cuda.stream(stream):
         # column-major per matrix: the (batch, n, m) layout of X^T

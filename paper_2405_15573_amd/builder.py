@@ -355,16 +355,23 @@ def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_
 
 def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca: float = 1e-6,
                    eps_comp: float = 1e-6, eps_rec: float | None = None, kcap: int = 1024,
-                   verbose: bool = False, construct: str = "host") -> HostOperator:
+                   verbose: bool = False, construct: str = "host", factor: str | None = None) -> HostOperator:
     """Build the H form and the UH form of the point-kernel matrix A_ij = g(x_i, x_j),
     A_ii = 1/(2h), for one seeded cloud.
 
     construct="gpu" samples the matrix on the GPU: ACA of the admissible blocks
     (uhm_aca), whose factors are packed by shape on the device (uhm_aca_pack), and the dense
-    near-field blocks (uhm_kernel_blocks); the recompression and the uniform compression
-    run on the host.  construct="host" does everything on the host (OpenMP C++ and LAPACK)."""
+    near-field blocks (uhm_kernel_blocks); the recompression runs on the host.
+    construct="host" does everything on the host (OpenMP C++ and LAPACK).
+    factor chooses where Alg. 2's per-cluster SVD runs: "gpu" (uhm_cluster_basis, batched
+    over the clusters of one size; the default with construct="gpu") or "host" (LAPACK, the
+    default with construct="host")."""
     if construct not in ("host", "gpu"):
         raise ValueError("construct must be 'host' or 'gpu'")
+    if factor is None:
+        factor = construct
+    if factor not in ("host", "gpu"):
+        raise ValueError("factor must be 'host' or 'gpu'")
     lib = _native()
     if eps_rec is None:
         eps_rec = eps_aca / 10.0
@@ -524,11 +531,100 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
                         [(s, np.ascontiguousarray(SV[:, j:j + kb])) for s, j, kb in cols[c]]))
         return out
 
+    def compress_gpu_all(jobs):
+        """Alg. 2's SVDs on the GPU, one batched call per chunk of same-size clusters.  The next
+        chunk's cluster matrices are written into page-locked host memory by the thread pool
+        meanwhile (one DMA each way).  A cluster the GPU flags (step cap before the tolerance,
+        or Jacobi not converged) is taken by the host SVD instead."""
+        import torch
+        from . import binding
+        out = []
+        tw = {"compress_fill_wait": 0.0, "compress_gpu": 0.0, "compress_post": 0.0, "compress_host_fallback_s": 0.0}
+        fallback = 0
+        per_size = {}
+
+        def fill(part, pool):
+            nt = int(size[part[0][0]])
+            kp = max(k for _, k in part)
+            buf = torch.empty((len(part), nt, kp), dtype=torch.complex128, pin_memory=True)
+            Xb = buf.numpy()
+            cols = [None] * len(part)
+
+            def one(c):
+                t, _ = part[c]
+                j, cl = 0, []
+                for s in row_blocks[t]:
+                    Ub, sb, _ = block_factors(t, s)
+                    kb = sb.size
+                    np.multiply(Ub, sb[None, :], out=Xb[c, :, j:j + kb])
+                    cl.append((s, j, kb))
+                    j += kb
+                Xb[c, :, j:] = 0.0
+                cols[c] = cl
+
+            list(pool.map(one, range(len(part))))
+            return buf, cols
+
+        with ThreadPoolExecutor(_workers()) as pool, ThreadPoolExecutor(1) as pre:
+            nxt = pre.submit(fill, jobs[0], pool) if jobs else None
+            for q, part in enumerate(jobs):
+                ta = time.perf_counter()
+                buf, cols = nxt.result()
+                nxt = pre.submit(fill, jobs[q + 1], pool) if q + 1 < len(jobs) else None
+                tb = time.perf_counter()
+                nt, kp = buf.shape[1], buf.shape[2]
+                res = binding.cluster_basis(buf.to("cuda", non_blocking=True), eps=eps_comp,
+                                            pmax=min(nt, kp, 2048))
+                tc = time.perf_counter()
+                bad = set(np.nonzero(res.status != 0)[0].tolist())
+                lmax = int(res.rank.max())
+                Uh = res.U[:, :lmax, :].cpu().numpy()
+                SVh = res.SV[:, :, :lmax].cpu().numpy()
+                del res.U, res.SV, res.sv, buf
+                for c, (t, ks) in enumerate(part):
+                    if c in bad:
+                        continue
+                    l = int(res.rank[c])
+                    SV = SVh[c, :, :l].T   # views into the copied batch, no further copies
+                    out.append((t, l, Uh[c, :l, :].T, float(res.stats[c, 1]), float(res.stats[c, 0]),
+                                [(s, SV[:, j:j + kb]) for s, j, kb in cols[c]]))
+                td = time.perf_counter()
+                if bad:
+                    fallback += len(bad)
+                    out.extend(compress([part[c] for c in sorted(bad)]))
+                te = time.perf_counter()
+                del Uh, SVh
+                tw["compress_fill_wait"] += tb - ta
+                tw["compress_gpu"] += tc - tb
+                tw["compress_post"] += td - tc
+                tw["compress_host_fallback_s"] += te - td
+                e = per_size.setdefault(int(nt), [0, 0, 0, 0.0, 0.0])
+                e[0] += len(part)
+                e[1] = max(e[1], int(res.psteps.max()))
+                e[2] = max(e[2], lmax)
+                e[3] += tc - tb
+                e[4] += te - tc
+        tim.update(tw)
+        tim["compress_host_fallback"] = fallback
+        if verbose:
+            for nt in sorted(per_size):
+                c, pm, lm, g, hp = per_size[nt]
+                print(f"  uniform compression, {c} clusters of {nt}: p <= {pm}, l <= {lm}, GPU {g:.2f} s, "
+                      f"host {hp:.2f} s", file=sys.stderr, flush=True)
+        return [out]
+
     jobs = []
-    for nt, members in groups.items():
-        kp_all = max(k for _, k in members)
-        jobs.extend(_chunks(members, 16 * nt * kp_all * 3, parts=2 * _workers()))
-    results = _pmap(compress, jobs)
+    if factor == "gpu":
+        for nt, members in groups.items():
+            kp_all = max(k for _, k in members)
+            # about 4 GiB of cluster matrices per call
+            jobs.extend(_chunks(members, 16 * nt * kp_all, budget=1 << 32))
+        results = compress_gpu_all(jobs)
+    else:
+        for nt, members in groups.items():
+            kp_all = max(k for _, k in members)
+            jobs.extend(_chunks(members, 16 * nt * kp_all * 3, parts=2 * _workers()))
+        results = _pmap(compress, jobs)
     for res in results:
         for t, l, Ut, dropped, tail, Ls in res:
             rank[t] = l

@@ -8,9 +8,14 @@
 //
 //  1. Householder QR with column pivoting, X Pi = Q [R; 0] + (trailing part), stopped once
 //     the trailing part's Frobenius norm T is at most tol * ||X||_F.  Then X = Q_p B + E with
-//     B = R Pi^T (p x k) and ||E||_2 <= T, so by Weyl's inequality the singular values of B
-//     are those of X to within T: with tol at a few units of rounding, the rank test on them
-//     is the one a full SVD takes.  One launch per step; every workgroup of a matrix
+//     B = R Pi^T = Q_p^* X (p x k) and E = (I - Q_p Q_p^*) X, ||E||_F = T.  The range of E is
+//     orthogonal to that of Q_p, so X^* X = B^* B + E^* E and
+//       sigma_i(B)^2 <= sigma_i(X)^2 <= sigma_i(B)^2 + T^2:
+//     near the rank threshold eps sigma_1 a singular value moves by at most T^2 / (2 eps
+//     sigma_1).  For the same reason the projection error of the basis U taken from B is
+//     at most sqrt(sigma_{l+1}(X)^2 + T^2) in the 2-norm, and its Frobenius norm is exactly
+//     sqrt(sum_{i>l} sigma_i(B)^2 + T^2).  With tol^2 about 1e-16 eps the rank test on B is
+//     the one a full SVD of X takes, up to rounding.  One launch per step; every workgroup of a matrix
 //     recomputes the pivot (largest remaining column norm, lowest index on ties) and the
 //     trailing sum in the same order, so all of them take the same decisions.  Columns are
 //     never moved: a pivot column is retired (norm marker -1) and R is kept in the original
@@ -33,7 +38,7 @@
 namespace uhm_detail {
 namespace {
 
-constexpr int kFacMaxP = 1024;      // largest kept QR rank (columns of J)
+constexpr int kFacMaxP = 2048;      // largest kept QR rank (columns of J)
 constexpr int kFacMaxRows = 16384;  // largest cluster: 16 rows per thread in the U kernel
 constexpr int kStepThreads = 256;
 constexpr int kStepCols = 16;  // columns per workgroup in a QR step: 4 per wavefront
@@ -401,7 +406,9 @@ __global__ __launch_bounds__(kStepThreads) void k_fac_finish(FacWs ws, int32_t m
     const double T2 = ws.fro(c)[1];
     double tail2 = T2;
     for (int t = p - 1; t >= l; --t) tail2 += s_sig[s_ord[t]] * s_sig[s_ord[t]];
-    const double dropped = l < p ? s_sig[s_ord[l]] : (p < min(m, n) ? sqrt(T2) : 0.0);
+    // sigma_{l+1}(X) <= sqrt(sigma_{l+1}(B)^2 + T^2)
+    const double sl = l < p ? s_sig[s_ord[l]] : 0.0;
+    const double dropped = l < min(m, n) ? sqrt(sl * sl + T2) : 0.0;
     st[6] = l;
     rank[c] = l;
     psteps[c] = p;
@@ -414,7 +421,7 @@ __global__ __launch_bounds__(kStepThreads) void k_fac_finish(FacWs ws, int32_t m
 
 // The kept columns of J, in singular-value order, orthonormalised again by classical
 // Gram-Schmidt applied twice; the result goes to the R2 area (R2 is no longer needed).
-// One workgroup per matrix, one row per thread (p <= 1024).
+// One workgroup per matrix, rows tid and tid + 1024 per thread (p <= 2048).
 __global__ __launch_bounds__(kBigThreads) void k_fac_orth(FacWs ws, int32_t P) {
   const int c = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -430,10 +437,14 @@ __global__ __launch_bounds__(kBigThreads) void k_fac_orth(FacWs ws, int32_t P) {
     for (int r = tid; r < P; r += kBigThreads) Q[r] = make_double2(r == 0 ? 1.0 : 0.0, 0.0);
     return;
   }
+  const int r1 = tid + kBigThreads;
   for (int i = 0; i < l; ++i) {
-    double2 v = tid < p ? J[(int64_t)ord[i] * P + tid] : make_double2(0.0, 0.0);
+    const double2* ji = J + (int64_t)ord[i] * P;
+    double2 v = tid < p ? ji[tid] : make_double2(0.0, 0.0);
+    double2 v1 = r1 < p ? ji[r1] : make_double2(0.0, 0.0);
     for (int pass = 0; pass < 2; ++pass) {
       if (tid < p) s_v[tid] = v;
+      if (r1 < p) s_v[r1] = v1;
       __syncthreads();
       for (int k = wv; k < i; k += kBigThreads / 64) {
         const double2* qk = Q + (int64_t)k * P;
@@ -455,15 +466,23 @@ __global__ __launch_bounds__(kBigThreads) void k_fac_orth(FacWs ws, int32_t P) {
           v.y -= t.y;
         }
       }
+      if (r1 < p) {
+        for (int k = 0; k < i; ++k) {
+          const double2 t = cmul(Q[(int64_t)k * P + r1], s_h[k]);
+          v1.x -= t.x;
+          v1.y -= t.y;
+        }
+      }
       __syncthreads();
     }
-    double s = fwave_sum(v.x * v.x + v.y * v.y);
+    double s = fwave_sum(v.x * v.x + v.y * v.y + v1.x * v1.x + v1.y * v1.y);
     if (lane == 0) s_red[wv] = s;
     __syncthreads();
     double nrm2 = 0.0;
     for (int w = 0; w < kBigThreads / 64; ++w) nrm2 += s_red[w];
     const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
     if (tid < p) Q[(int64_t)i * P + tid] = make_double2(v.x * inv, v.y * inv);
+    if (r1 < p) Q[(int64_t)i * P + r1] = make_double2(v1.x * inv, v1.y * inv);
     __syncthreads();
   }
 }
@@ -598,7 +617,7 @@ int uhm_cluster_basis(double* X, int32_t batch, int32_t m, int32_t n, int32_t pm
   if (batch < 0 || m < 1 || n < 1) return fail(UHM_EINVAL, "uhm_cluster_basis: bad size");
   if (m > kFacMaxRows) return fail(UHM_EINVAL, "uhm_cluster_basis: more than 16384 rows");
   if (pmax < 1 || pmax > kFacMaxP || pmax > std::min(m, n))
-    return fail(UHM_EINVAL, "uhm_cluster_basis: pmax must be in 1..min(m, n, 1024)");
+    return fail(UHM_EINVAL, "uhm_cluster_basis: pmax must be in 1..min(m, n, 2048)");
   if (!(tol >= 0.0) || !std::isfinite(tol) || !(eps >= 0.0) || !std::isfinite(eps))
     return fail(UHM_EINVAL, "uhm_cluster_basis: tol and eps must be finite and >= 0");
   if (batch == 0) return UHM_OK;

@@ -181,6 +181,24 @@ def test_builder_gpu_construction(torch_dev, surface, n, seed, leaf):
     assert rel(uniform.h_mvp(vars(g), x), uniform.h_mvp(vars(h), x)) <= 1e-9
 
 
+def test_gpu_factorised_operator_meets_the_builder_pins(torch_dev):
+    """With Alg. 2's SVDs on the GPU (uhm_cluster_basis) the operator meets the same pins as
+    the host build: orthonormal bases, optimal couplings, Thm 5.1 and the Frobenius identity,
+    and Alg. 1's ranks and projection errors; its ranks equal the host factorisation's."""
+    import test_builder as tb
+    cloud = inputs.make_cloud("sphere", 2048, seed=0)
+    print(f"case builder factor=gpu sphere n={cloud.n} leaf=32", flush=True)
+    g = builder.build_operator(cloud, leaf=32, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="host", factor="gpu")
+    h = builder.build_operator(cloud, leaf=32, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="host", factor="host")
+    assert g.timings["compress_host_fallback"] == 0
+    assert np.array_equal(g.rank_row, h.rank_row)
+    x = inputs.make_rhs(cloud.n, 2, seed=1)
+    assert rel(uniform.uh_mvp(vars(g), x), uniform.uh_mvp(vars(h), x)) <= 1e-9
+    for check in (tb.test_orthogonal_bases_and_conjugate_symmetry, tb.test_couplings_are_optimal,
+                  tb.test_theorem_5_1_and_frobenius_identity, tb.test_algorithm_1_and_2_give_the_same_basis):
+        check((cloud, g))
+
+
 def test_aca_pack_layout(torch_dev):
     """uhm_aca_pack against the ACA result read block by block (AcaResult.factors): for a
     selection of blocks of one shape, X[c] = [u_0 .. u_{k-1} 0 ..] and Y[c] = conj of the v
