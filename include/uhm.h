@@ -482,6 +482,31 @@ int uhm_cluster_basis(double* X, int32_t batch, int32_t m, int32_t n, int32_t pm
 /* Workspace of uhm_cluster_basis in doubles, or -1 for sizes it rejects outright. */
 int64_t uhm_cluster_basis_work(int32_t batch, int32_t m, int32_t n, int32_t pmax);
 
+/*
+ * The algebraic recompression of ACA factors (section 2.3) for a batch of `batch` blocks of
+ * one shape: for each block A|_b ~ X_c Y_c^* (X_c m x kp and Y_c n x kp complex128,
+ * column-major at X + 2*c*m*kp and Y + 2*c*n*kp; zero columns allowed) it returns the SVD
+ * truncated at eps * sigma_1, U_c Sigma_c V_c^* with k = rank[c] >= 1 terms.  Taken as:
+ * unpivoted Householder QR of both factors (X = Q_X R_X, Y = Q_Y R_Y), one-sided Jacobi on
+ * M = R_Y R_X^* (M J = W Sigma, so X Y^* = (Q_X J) Sigma (Q_Y W)^*), the kept columns of J
+ * and W orthonormalised again and carried back through the reflectors.
+ * X, Y (both destroyed), U, V, sv, rank, status and work are device arrays:
+ *   U[c]: m x kp complex (column-major, U + 2*c*m*kp), columns 0..k-1 written;
+ *   V[c]: n x kp complex (V + 2*c*n*kp), columns 0..k-1 written;
+ *   sv[c*kp + i]: the singular values of X_c Y_c^*, descending;
+ *   status[c] = 0, or 2 when the Jacobi sweeps did not converge within 60 sweeps.
+ * work: uhm_block_recompress_work(batch, m, n, kp) doubles of device memory (work_len counts
+ * doubles); nothing is allocated.  Limits: m, n <= 16384, 1 <= kp <= min(m, n, 2048), batch
+ * <= 65535.  Asynchronous on hip_stream.  Errors: UHM_EINVAL (sizes, eps negative or not
+ * finite, null pointers, work too small), UHM_EHIP.
+ */
+int uhm_block_recompress(double* X, double* Y, int32_t batch, int32_t m, int32_t n, int32_t kp, double eps,
+                         double* U, double* V, double* sv, int32_t* rank, int32_t* status, double* work,
+                         int64_t work_len, void* hip_stream);
+
+/* Workspace of uhm_block_recompress in doubles, or -1 for sizes it rejects outright. */
+int64_t uhm_block_recompress_work(int32_t batch, int32_t m, int32_t n, int32_t kp);
+
 const char* uhm_strerror(int code);
 const char* uhm_last_error(void);
 int uhm_version(void);

@@ -79,7 +79,8 @@ EXPORTS = ("uhm_upload", "uhm_upload_h", "uhm_matvec", "uhm_matvec_noalloc", "uh
            "uhm_batch_create", "uhm_batch_run",
            "uhm_batch_tune", "uhm_batch_capture", "uhm_batch_free", "uhm_op_info_get", "uhm_set_timing",
            "uhm_kernel_times", "uhm_free", "uhm_strerror", "uhm_last_error", "uhm_version",
-           "uhm_kernel_blocks", "uhm_aca", "uhm_aca_pack", "uhm_cluster_basis", "uhm_cluster_basis_work")
+           "uhm_kernel_blocks", "uhm_aca", "uhm_aca_pack", "uhm_cluster_basis", "uhm_cluster_basis_work",
+           "uhm_block_recompress", "uhm_block_recompress_work")
 
 _LIB = None
 
@@ -152,6 +153,10 @@ def load_library(path: str = LIB_PATH):
     lib.uhm_cluster_basis.restype = ctypes.c_int
     lib.uhm_cluster_basis_work.argtypes = [I32, I32, I32, I32]
     lib.uhm_cluster_basis_work.restype = I64
+    lib.uhm_block_recompress.argtypes = [P, P, I32, I32, I32, I32, D, P, P, P, P, P, P, I64, P]
+    lib.uhm_block_recompress.restype = ctypes.c_int
+    lib.uhm_block_recompress_work.argtypes = [I32, I32, I32, I32]
+    lib.uhm_block_recompress_work.restype = I64
     _LIB = lib
     return lib
 
@@ -705,4 +710,40 @@ def cluster_basis(X, eps: float, tol: float | None = None, pmax: int | None = No
                            stats.cpu().numpy()[:batch], status.cpu().numpy()[:batch])
         del Xd, work
     return res
+
+
+def block_recompress(X, Y, eps: float, stream=None):
+    """The recompression of a batch of ACA factor pairs (uhm_block_recompress): X (batch, m,
+    kp) and Y (batch, n, kp) complex128 with A|_b ~ X[c] Y[c]^H (host or device; copied).
+    Returns device tensors U (batch, kp, m) and V (batch, kp, n) holding U_c^T and V_c^T row
+    by row, sv (batch, kp), and host arrays rank and status."""
+    import torch
+    lib = load_library()
+    Xt, Yt = torch.as_tensor(X), torch.as_tensor(Y)
+    batch, m, kp = (int(v) for v in Xt.shape)
+    n = int(Yt.shape[1])
+    if tuple(Yt.shape) != (batch, n, kp):
+        raise UhmError(UHM_EINVAL, "block_recompress: X and Y disagree in batch or kp")
+    h, stream = _stream_handle(stream)
+    with torch.cuda.stream(stream):
+        Xd = Xt.to(device="cuda", dtype=torch.complex128).transpose(1, 2).contiguous()
+        Yd = Yt.to(device="cuda", dtype=torch.complex128).transpose(1, 2).contiguous()
+        need = int(lib.uhm_block_recompress_work(batch, m, n, kp))
+        if need < 0:
+            raise UhmError(UHM_EINVAL, "uhm_block_recompress_work: sizes rejected")
+        work = torch.empty(max(1, need), dtype=torch.float64, device="cuda")
+        U = torch.empty((batch, kp, m), dtype=torch.complex128, device="cuda")
+        V = torch.empty((batch, kp, n), dtype=torch.complex128, device="cuda")
+        sv = torch.empty((batch, kp), dtype=torch.float64, device="cuda")
+        rank = torch.empty(max(1, batch), dtype=torch.int32, device="cuda")
+        status = torch.empty(max(1, batch), dtype=torch.int32, device="cuda")
+        _check(lib.uhm_block_recompress(ctypes.c_void_p(Xd.data_ptr()), ctypes.c_void_p(Yd.data_ptr()), batch, m, n,
+                                        kp, float(eps), ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(V.data_ptr()),
+                                        ctypes.c_void_p(sv.data_ptr()), ctypes.c_void_p(rank.data_ptr()),
+                                        ctypes.c_void_p(status.data_ptr()), ctypes.c_void_p(work.data_ptr()), need, h),
+               "uhm_block_recompress")
+        rk = rank.cpu().numpy()[:batch]
+        stt = status.cpu().numpy()[:batch]
+        del Xd, Yd, work
+    return U, V, sv, rk, stt
 

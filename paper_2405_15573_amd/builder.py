@@ -305,23 +305,26 @@ def _to_host(t):
     return h.numpy()
 
 
-def _pack_factors(res, pos, rel, m, n):
+def _pack_factors(res, pos, rel, m, n, device=False):
     """Factors of the blocks pos[rel] of one shape group of an ACA result (blocks pos are
     contiguous, all m x n): X (cnt, m, kp) = u and Y (cnt, n, kp) = conj(v), zero beyond each
     block's rank, kp the group's largest rank.  Packed on the device by uhm_aca_pack and
-    copied to the host once."""
+    copied to the host once, or kept on the device (device=True)."""
     from . import binding
     rank = res.rank[pos[rel]]
     kp = int(rank.max())
     X, Y = binding.aca_pack(res, np.asarray(pos)[rel], int(m), int(n), kp)
+    if device:
+        return X, Y
     return _to_host(X), _to_host(Y)
 
 
-def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_cap=128):
+def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_cap=128, device=False):
     """ACA of one level's blocks on the GPU (uhm_aca).  Blocks whose first pass stopped at
     its rank capacity run again with a four times larger one, up to kcap.  Returns the ranks
     and, per (shape, pass) group, (block indices, X (cnt, m, kp), Y (cnt, n, kp)) with
-    A|_b ~ X Y^H and zero columns beyond each block's rank (the layout of uhmb_aca_copy)."""
+    A|_b ~ X Y^H and zero columns beyond each block's rank (the layout of uhmb_aca_copy);
+    host arrays, or device tensors with device=True."""
     from . import binding
     nb = roff.shape[0]
     kout = np.zeros(nb, np.int32)
@@ -345,7 +348,7 @@ def _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps, kcap, first_
             keep = pos[final[pos]]
             if keep.size == 0:
                 continue
-            X, Y = _pack_factors(res, pos, keep - pos[0], int(m), int(n))
+            X, Y = _pack_factors(res, pos, keep - pos[0], int(m), int(n), device=device)
             groups.append((idx[keep], int(m), int(n), X, Y))
         todo = idx[~final]
         cap_now *= 4
@@ -410,7 +413,8 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
         ta = time.perf_counter()
         handle = None
         if construct == "gpu":
-            kout, gpu_groups, ks = _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps_aca, kcap)
+            kout, gpu_groups, ks = _aca_level_gpu(dev_pts, kappa, diag, roff, rsz, coff, csz, eps_aca, kcap,
+                                                  device=factor == "gpu")
             t_aca_kernel += ks
         else:
             handle = lib.uhmb_aca_run(_ptr(pts), kappa, diag, nb, _ptr(roff), _ptr(rsz), _ptr(coff), _ptr(csz),
@@ -444,9 +448,41 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
             lib.uhmb_aca_copy(handle, cnt, _ptr(idx), int(m), int(n), kp, _ptr(X), _ptr(Y))
             return recompress_xy(part, X, Y)
 
+        def recompress_dev(sel, X, Y):
+            """The recompression of one shape group on the GPU (uhm_block_recompress), in calls of
+            at most 65535 blocks and about 4 GiB of factors and workspace."""
+            from . import binding
+            m, kp, n = X.shape[1], X.shape[2], Y.shape[1]
+            per = 16 * kp * (6 * (m + n) + 8 * kp)   # factors, their copies, workspace and results
+            step = max(1, min(65535, (1 << 32) // per))
+            for a in range(0, len(sel), step):
+                part = sel[a:a + step]
+                U, V, sv, rk, stt = binding.block_recompress(X[a:a + step], Y[a:a + step], eps_rec)
+                kmax = int(rk.max())
+                Uh = U[:, :kmax, :].cpu().numpy()
+                Vh = V[:, :kmax, :].cpu().numpy()
+                svh = sv[:, :kmax].cpu().numpy()
+                del U, V, sv
+                bad = np.nonzero(stt != 0)[0]
+                for c, b in enumerate(part):
+                    k = int(rk[c])
+                    key = (int(blk[b, 0]), int(blk[b, 1]))
+                    fac_U[key] = Uh[c, :k, :].T
+                    fac_V[key] = Vh[c, :k, :].T
+                    fac_s[key] = svh[c, :k].copy()
+                if bad.size:   # Jacobi not converged: the host SVD for those blocks
+                    for key, Ub, Vb, sb in recompress_xy([part[c] for c in bad], X[a:a + step][bad].cpu().numpy(),
+                                                         Y[a:a + step][bad].cpu().numpy()):
+                        fac_U[key], fac_V[key], fac_s[key] = Ub, Vb, sb
+                    tim["recompress_host_fallback"] = tim.get("recompress_host_fallback", 0) + int(bad.size)
+
         try:
             jobs = []
-            if handle is None:
+            if handle is None and factor == "gpu":
+                for sel, m, n, X, Y in gpu_groups:
+                    recompress_dev(sel, X, Y)
+                del gpu_groups
+            elif handle is None:
                 for sel, m, n, X, Y in gpu_groups:
                     kp = X.shape[2]
                     step = max(1, len(list(_chunks(sel, 16 * (m + n) * kp * 4, parts=4 * _workers()))[0]))

@@ -1,11 +1,11 @@
-// Alg. 2's per-cluster factorisation on the GPU (section 4.2), for a batch of clusters.
+// Dense factorisations of the construction on the GPU, batched over matrices of one shape:
+// Alg. 2's per-cluster SVD (section 4.2) and the algebraic recompression of ACA factors
+// (section 2.3).
 //
-// For a cluster tau, Alg. 2 takes the SVD of the thin factor X_tau (n_tau x k_tau: the
-// scaled left factors of the blocks in tau's block row) and keeps the left singular
+// Alg. 2.  For a cluster tau, Alg. 2 takes the SVD of the thin factor X_tau (n_tau x k_tau:
+// the scaled left factors of the blocks in tau's block row) and keeps the left singular
 // vectors whose singular values exceed eps * sigma_1.  They form U_tau, and U_tau^* X_tau =
-// Sigma V^* gives the rows from which the couplings follow.  The SVD is taken in four
-// steps, each a batched launch over the clusters of one shape:
-//
+// Sigma V^* gives the rows from which the couplings follow.  The SVD is taken in four steps:
 //  1. Householder QR with column pivoting, X Pi = Q [R; 0] + (trailing part), stopped once
 //     the trailing part's Frobenius norm T is at most tol * ||X||_F.  Then X = Q_p B + E with
 //     B = R Pi^T = Q_p^* X (p x k) and E = (I - Q_p Q_p^*) X, ||E||_F = T.  The range of E is
@@ -15,11 +15,11 @@
 //     sigma_1).  For the same reason the projection error of the basis U taken from B is
 //     at most sqrt(sigma_{l+1}(X)^2 + T^2) in the 2-norm, and its Frobenius norm is exactly
 //     sqrt(sum_{i>l} sigma_i(B)^2 + T^2).  With tol^2 about 1e-16 eps the rank test on B is
-//     the one a full SVD of X takes, up to rounding.  One launch per step; every workgroup of a matrix
-//     recomputes the pivot (largest remaining column norm, lowest index on ties) and the
-//     trailing sum in the same order, so all of them take the same decisions.  Columns are
-//     never moved: a pivot column is retired (norm marker -1) and R is kept in the original
-//     column order, which is B itself.
+//     the one a full SVD of X takes, up to rounding.  One launch per step; every workgroup
+//     of a matrix recomputes the pivot (largest remaining column norm, lowest index on ties)
+//     and the trailing sum in the same order, so all of them take the same decisions.
+//     Columns are never moved: a pivot column is retired (norm marker -1) and R is kept in
+//     the original column order, which is B itself.
 //  2. Unpivoted Householder QR of B^* = Q2 R2, R2 p x p (the same step kernel).
 //  3. One-sided (Hestenes) Jacobi on the columns of R2, with the rotations accumulated in J:
 //     R2 J = W Sigma, so B = R2^* Q2^* = J Sigma (Q2 W)^*: the left singular vectors of B are
@@ -28,8 +28,14 @@
 //     1e-12, so the kept columns of J are orthonormalised again (classical Gram-Schmidt
 //     applied twice, largest singular value first).
 //  4. U = Q_p [J_l; 0] (the reflectors of step 1 applied in reverse order, the columns held
-//     in registers) and Sigma V^* = J_l^* B.  The Frobenius projection error is exact:
-//     ||X - U U^* X||_F^2 = sum of the dropped sigma_i(B)^2 + T^2.
+//     in registers) and Sigma V^* = J_l^* B.
+//
+// Recompression.  A block A|_b ~ X Y^* from ACA (k terms) is brought to its SVD truncated at
+// eps sigma_1: unpivoted QR of both factors, X = Q_X R_X and Y = Q_Y R_Y; one-sided Jacobi
+// on M = R_Y R_X^*, M J = W Sigma (the columns of W come out orthogonal relative to their
+// own norms, whatever those are), so X Y^* = Q_X M^* Q_Y^* = (Q_X J) Sigma (Q_Y W)^*; the
+// kept columns of J and of W are orthonormalised again as above and carried back through
+// the reflectors.
 #include "uhm_internal.h"
 
 #include <climits>
@@ -38,8 +44,8 @@
 namespace uhm_detail {
 namespace {
 
-constexpr int kFacMaxP = 2048;      // largest kept QR rank (columns of J)
-constexpr int kFacMaxRows = 16384;  // largest cluster: 16 rows per thread in the U kernel
+constexpr int kFacMaxP = 2048;      // largest Jacobi order (columns of J)
+constexpr int kFacMaxRows = 16384;  // largest row count: 16 rows per thread in the apply kernel
 constexpr int kStepThreads = 256;
 constexpr int kStepCols = 16;  // columns per workgroup in a QR step: 4 per wavefront
 constexpr int kBigThreads = 1024;
@@ -60,65 +66,38 @@ __device__ __forceinline__ double fwave_sum(double x) {
   return x;
 }
 
-// Per-matrix workspace regions (offsets in doubles from the matrix's base).
-struct FacWs {
-  double* base;
-  int64_t per;
-  int64_t o_w, o_om, o_c, o_cq, o_r2, o_j, o_nu, o_ord, o_st;
-  __host__ __device__ double* mat(int c) const { return base + (int64_t)c * per; }
-  __host__ __device__ double2* W(int c) const { return reinterpret_cast<double2*>(mat(c) + o_w); }
-  __host__ __device__ double* om(int c) const { return mat(c) + o_om; }
-  __host__ __device__ double2* C(int c) const { return reinterpret_cast<double2*>(mat(c) + o_c); }
-  // a second copy of B^*, which the QR of B^* consumes
-  __host__ __device__ double2* Cq(int c) const { return reinterpret_cast<double2*>(mat(c) + o_cq); }
-  __host__ __device__ double2* R2(int c) const { return reinterpret_cast<double2*>(mat(c) + o_r2); }
-  __host__ __device__ double2* J(int c) const { return reinterpret_cast<double2*>(mat(c) + o_j); }
-  __host__ __device__ double* nu(int c) const { return mat(c) + o_nu; }
-  __host__ __device__ int32_t* ord(int c) const { return reinterpret_cast<int32_t*>(mat(c) + o_ord); }
-  // st: [0] p (steps of the pivoted QR), [1] its stop flag, [2] steps of the second QR,
-  // [3] its stop flag, [4] Jacobi sweeps, [5] Jacobi did not converge, [6] rank l,
-  // [7] the pivoted QR reached pmax before the tolerance;
-  // as doubles from st + 8: [0] ||X||_F^2, [1] T^2
-  __host__ __device__ int32_t* st(int c) const { return reinterpret_cast<int32_t*>(mat(c) + o_st); }
-  __host__ __device__ double* fro(int c) const { return mat(c) + o_st + 8; }
+// One array per matrix of the batch: matrix c's array starts at p + c * stride.
+template <class T>
+struct Arr {
+  T* p;
+  int64_t stride;
+  __host__ __device__ T* at(int c) const { return p + (int64_t)c * stride; }
 };
+using CArr = Arr<double2>;
+using DArr = Arr<double>;
+using IArr = Arr<int32_t>;
 
-int64_t round_up(int64_t x) { return (x + 31) / 32 * 32; }
-
-FacWs layout(double* base, int32_t m, int32_t n, int32_t P) {
-  FacWs w{};
-  w.base = base;
-  int64_t o = 0;
-  w.o_w = o;
-  o += round_up(2 * (int64_t)P * m);
-  w.o_om = o;
-  o += round_up(P);
-  w.o_c = o;
-  o += round_up(2 * (int64_t)n * P);
-  w.o_cq = o;
-  o += round_up(2 * (int64_t)n * P);
-  w.o_r2 = o;
-  o += round_up(2 * (int64_t)P * P);
-  w.o_j = o;
-  o += round_up(2 * (int64_t)P * P);
-  w.o_nu = o;
-  o += round_up(2 * (int64_t)std::max(n, P));
-  w.o_ord = o;
-  o += round_up((P + 1) / 2);
-  w.o_st = o;
-  o += 32;
-  w.per = o;
-  return w;
+// Workspace: each matrix owns `per` doubles; regions are carved out in 256-byte units.
+struct Carve {
+  int64_t per = 0;
+  int64_t take(int64_t doubles) {
+    const int64_t o = per;
+    per += (doubles + 31) / 32 * 32;
+    return o;
+  }
+};
+template <class T>
+Arr<T> region(double* base, int64_t per, int64_t off) {
+  return Arr<T>{reinterpret_cast<T*>(base + off), (int64_t)(per * sizeof(double) / sizeof(T))};
 }
 
 // Squared column norms of a rows x cols matrix (lda = rows) into nu's first buffer: one
 // wavefront per column, kStepCols columns per workgroup.
-__global__ __launch_bounds__(kStepThreads) void k_fac_norms(const double2* __restrict__ A, int64_t a_stride,
-                                                            int32_t rows, int32_t cols, FacWs ws) {
+__global__ __launch_bounds__(kStepThreads) void k_col_norms(CArr A, int32_t rows, int32_t cols, DArr nu) {
   const int c = blockIdx.y;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const double2* Am = A + (int64_t)c * a_stride;
-  double* nu = ws.nu(c);
+  const double2* Am = A.at(c);
+  double* nm = nu.at(c);
   for (int q = 0; q < kStepCols / 4; ++q) {
     const int j = blockIdx.x * kStepCols + wv * (kStepCols / 4) + q;
     if (j >= cols) break;
@@ -129,34 +108,39 @@ __global__ __launch_bounds__(kStepThreads) void k_fac_norms(const double2* __res
       s += v.x * v.x + v.y * v.y;
     }
     s = fwave_sum(s);
-    if (lane == 0) nu[j] = s;
+    if (lane == 0) nm[j] = s;
   }
 }
 
 struct QrStep {
-  double2* A;  // rows x cols per matrix, column-major (lda = rows), updated in place
-  int64_t a_stride;
+  CArr A;  // rows x cols per matrix, column-major (lda = rows), updated in place
   int32_t rows, cols;
-  int32_t which;    // 0: the pivoted QR of X (state st[0..1]); 1: the QR of B^* (st[2..3])
-  int32_t kcap;     // step limit (the pivoted QR also stops at the tolerance)
-  double tol2;      // pivoted: stop when T^2 <= tol2 * ||X||_F^2
-  int32_t keep_w;   // store the reflectors (pivoted QR)
-  // R[k][j] goes to out[k * rs + j * cs] of the matrix's R area, conjugated if rconj
+  DArr nu;   // 2 * cols squared column norms (double-buffered by step parity)
+  CArr W;    // reflector k at W + k * rows (W.p null: not kept)
+  DArr om;   // omega_k
+  CArr R;    // R[k][j] at R[k * rs + j * cs], conjugated if rconj
+  CArr Rq;   // a second copy of R (Rq.p may be null)
   int32_t rs, cs, rconj;
+  IArr st;   // [0] steps taken, [1] stopped, [2] the step cap came before the tolerance
+  IArr lim;  // per-matrix step limit at lim.at(c)[0] (lim.p null: none)
+  DArr fro;  // pivoted: [0] ||A||_F^2, [1] T^2 (the trailing sum at the stop)
+  int32_t kcap;
+  double tol2;  // pivoted: stop when T^2 <= tol2 * ||A||_F^2
+  int32_t pivoted;
 };
 
 // One Householder step k for every matrix of the batch.  Grid (ceil(cols / 16), batch).
 // The reflector of step k is P = I - omega w w^*, w = x - beta e_k on rows k.., x the pivot
 // column, beta = -e^{i arg x_k} ||x|| (so that w_k carries no cancellation), omega =
 // 1 / (||x|| (||x|| + |x_k|)); P x = beta e_k.
-__global__ __launch_bounds__(kStepThreads) void k_qr_step(QrStep a, FacWs ws, int32_t k) {
+__global__ __launch_bounds__(kStepThreads) void k_qr_step(QrStep a, int32_t k) {
   const int c = blockIdx.y;
-  int32_t* st = ws.st(c) + 2 * a.which;
+  int32_t* st = a.st.at(c);
   if (st[1]) return;  // stopped in an earlier step
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const double* nu = ws.nu(c) + (k & 1) * (int64_t)a.cols;
-  double* nu2 = ws.nu(c) + ((k + 1) & 1) * (int64_t)a.cols;
-  const int32_t lim = a.which == 0 ? a.kcap : min(a.kcap, ws.st(c)[0]);
+  const double* nu = a.nu.at(c) + (k & 1) * (int64_t)a.cols;
+  double* nu2 = a.nu.at(c) + ((k + 1) & 1) * (int64_t)a.cols;
+  const int32_t lim = a.lim.p ? min(a.kcap, a.lim.at(c)[0]) : a.kcap;
 
   // trailing sum and pivot over the live columns, in one fixed order
   __shared__ double s_sum[kStepThreads], s_mx[kStepThreads];
@@ -190,27 +174,25 @@ __global__ __launch_bounds__(kStepThreads) void k_qr_step(QrStep a, FacWs ws, in
     __syncthreads();
   }
   const double tr = s_sum[0];
-  double* fro = ws.fro(c);
-  const double f2 = k == 0 ? tr : fro[0];
-  const bool piv_mode = a.which == 0;
-  const bool stop = k >= lim || k >= a.rows || (piv_mode && (tr <= a.tol2 * f2 || s_mx[0] <= 0.0));
-  if (stop) {
+  double* fro = a.pivoted ? a.fro.at(c) : nullptr;
+  const double f2 = k == 0 || !fro ? tr : fro[0];
+  const bool met = a.pivoted && (tr <= a.tol2 * f2 || s_mx[0] <= 0.0);
+  if (k >= lim || k >= a.rows || met) {
     if (blockIdx.x == 0 && tid == 0) {
       st[0] = k;
       st[1] = 1;
-      if (piv_mode) {
+      if (fro) {
         fro[0] = f2;
         fro[1] = tr;
-        // the step cap (pmax < min(rows, cols)) came before the tolerance
-        ws.st(c)[7] = (k < a.rows && k < a.cols && !(tr <= a.tol2 * f2 || s_mx[0] <= 0.0)) ? 1 : 0;
       }
+      st[2] = a.pivoted && !met && k < a.rows && k < a.cols ? 1 : 0;
     }
     return;
   }
-  if (piv_mode && k == 0 && blockIdx.x == 0 && tid == 0) fro[0] = tr;
-  const int piv = piv_mode ? s_ix[0] : k;
+  if (fro && k == 0 && blockIdx.x == 0 && tid == 0) fro[0] = tr;
+  const int piv = a.pivoted ? s_ix[0] : k;
 
-  double2* Am = a.A + (int64_t)c * a.a_stride;
+  double2* Am = a.A.at(c);
   const double2* x = Am + (int64_t)piv * a.rows;
   const double nx = sqrt(fmax(nu[piv], 0.0));
   const double2 al = x[k];
@@ -219,18 +201,18 @@ __global__ __launch_bounds__(kStepThreads) void k_qr_step(QrStep a, FacWs ws, in
   const double2 beta = make_double2(-ph.x * nx, -ph.y * nx);
   const double2 wk = make_double2(ph.x * (aa + nx), ph.y * (aa + nx));
   const double om = nx > 0.0 ? 1.0 / (nx * (nx + aa)) : 0.0;
-  double2* R = a.which == 0 ? ws.C(c) : ws.R2(c);
-  double2* Rq = a.which == 0 ? ws.Cq(c) : nullptr;
+  double2* R = a.R.at(c);
+  double2* Rq = a.Rq.p ? a.Rq.at(c) : nullptr;
 
   for (int q = 0; q < kStepCols / 4; ++q) {
     const int j = blockIdx.x * kStepCols + wv * (kStepCols / 4) + q;
     if (j >= a.cols) break;
     const int64_t ro = (int64_t)k * a.rs + (int64_t)j * a.cs;
     if (j == piv) {
-      if (a.keep_w) {
-        double2* w = ws.W(c) + (int64_t)k * a.rows;
+      if (a.W.p) {
+        double2* w = a.W.at(c) + (int64_t)k * a.rows;
         for (int i = lane; i < a.rows; i += 64) w[i] = i < k ? make_double2(0.0, 0.0) : (i == k ? wk : x[i]);
-        if (lane == 0) ws.om(c)[k] = om;
+        if (lane == 0) a.om.at(c)[k] = om;
       }
       if (lane == 0) {
         R[ro] = a.rconj ? cconj(beta) : beta;
@@ -281,37 +263,38 @@ __global__ __launch_bounds__(kStepThreads) void k_qr_step(QrStep a, FacWs ws, in
   }
 }
 
-// One-sided Jacobi on the p x p matrix R2 (ld P), one workgroup of 16 wavefronts per
-// matrix.  Round r of a sweep pairs the columns by the circle method (index 0 fixed, the
-// others rotated), so the pairs of a round are disjoint and one wavefront takes each.  A
-// pair (i, j) with Gram entries alpha, beta, gamma is rotated when |gamma| > tol sqrt(alpha
-// beta): with e = gamma / |gamma|, zeta = (beta - alpha) / (2 |gamma|) and t the smaller
-// root of t^2 + 2 zeta t - 1 = 0, c = 1 / sqrt(1 + t^2), s = c t,
+// One-sided Jacobi on the p x p matrix R (ld P; p = pp.at(c)[0]), rotations accumulated in
+// V (set to the identity here), one workgroup of 16 wavefronts per matrix.  Round r of a
+// sweep pairs the columns by the circle method (index 0 fixed, the others rotated), so the
+// pairs of a round are disjoint and one wavefront takes each.  A pair (i, j) with Gram
+// entries alpha, beta, gamma is rotated when |gamma| > tol sqrt(alpha beta): with e = gamma
+// / |gamma|, zeta = (beta - alpha) / (2 |gamma|) and t the smaller root of t^2 + 2 zeta t -
+// 1 = 0, c = 1 / sqrt(1 + t^2), s = c t,
 //   a_i <- c a_i - s conj(e) a_j,   a_j <- s e a_i + c a_j,
-// which makes a_i^* a_j vanish; the same rotation is applied to J.
-__global__ __launch_bounds__(kBigThreads) void k_fac_jacobi(FacWs ws, int32_t P, double tol, int32_t max_sweeps) {
+// which makes a_i^* a_j vanish.  sst: [1] sweeps, [2] not converged.
+__global__ __launch_bounds__(kBigThreads) void k_jacobi(CArr Ra, CArr Va, int32_t P, IArr pp, IArr sst, double tol,
+                                                        int32_t max_sweeps) {
   const int c = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  int32_t* st = ws.st(c);
-  const int p = st[0];
-  double2* R = ws.R2(c);
-  double2* V = ws.J(c);
+  const int p = pp.at(c)[0];
+  double2* R = Ra.at(c);
+  double2* V = Va.at(c);
   for (int64_t q = tid; q < (int64_t)P * P; q += kBigThreads) {
     const int r = (int)(q % P), col = (int)(q / P);
     V[q] = make_double2(r == col && r < p ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
   __shared__ int s_rot;
-  const int pp = p + (p & 1);
+  const int pq = p + (p & 1);
   int sweep = 0;
   bool conv = p < 2;
   while (!conv && sweep < max_sweeps) {
     if (tid == 0) s_rot = 0;
     __syncthreads();
-    for (int r = 0; r < pp - 1; ++r) {
-      for (int q = wv; q < pp / 2; q += kBigThreads / 64) {
-        const int a0 = q == 0 ? 0 : (r + q - 1) % (pp - 1) + 1;
-        const int b0 = (r + (pp - 1 - q) - 1) % (pp - 1) + 1;
+    for (int r = 0; r < pq - 1; ++r) {
+      for (int q = wv; q < pq / 2; q += kBigThreads / 64) {
+        const int a0 = q == 0 ? 0 : (r + q - 1) % (pq - 1) + 1;
+        const int b0 = (r + (pq - 1 - q) - 1) % (pq - 1) + 1;
         const int i = min(a0, b0), j = max(a0, b0);
         if (j >= p) continue;
         double2* ci = R + (int64_t)i * P;
@@ -357,28 +340,41 @@ __global__ __launch_bounds__(kBigThreads) void k_fac_jacobi(FacWs ws, int32_t P,
     __syncthreads();
   }
   if (tid == 0) {
-    st[4] = sweep;
-    st[5] = conv ? 0 : 1;
+    sst.at(c)[1] = sweep;
+    sst.at(c)[2] = conv ? 0 : 1;
   }
 }
 
-// Singular values (column norms of the rotated R2), their order, the rank rule of Alg. 2
-// and the error figures.  One workgroup per matrix.
-__global__ __launch_bounds__(kStepThreads) void k_fac_finish(FacWs ws, int32_t m, int32_t n, int32_t P, double eps,
-                                                             double* __restrict__ sv, int32_t* __restrict__ rank,
-                                                             int32_t* __restrict__ psteps, double* __restrict__ stats,
-                                                             int32_t* __restrict__ status) {
+struct Finish {
+  CArr R;  // the rotated matrix (ld P); singular values are its column norms
+  int32_t P;
+  IArr pp;          // p at pp.at(c)[0]
+  IArr sst;         // [2] Jacobi not converged (read), [3] rank l (written)
+  IArr ord;         // P ints: columns in singular-value order (written)
+  double eps;       // rank rule: sigma > eps * sigma_1, at least 1
+  DArr fro;         // T^2 at fro.at(c)[1] (fro.p null: 0)
+  IArr qst;         // the pivoted QR's state, [2] = step cap first (qst.p null: none)
+  int32_t m, n;     // shape, for the dropped value
+  double* sv;       // P per matrix
+  int32_t* rank;
+  int32_t* psteps;  // may be null
+  double* stats;    // 3 per matrix, may be null
+  int32_t* status;
+};
+
+// Singular values (column norms of the rotated matrix), their order, the rank rule and the
+// error figures.  One workgroup per matrix.
+__global__ __launch_bounds__(kStepThreads) void k_finish(Finish f) {
   const int c = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  int32_t* st = ws.st(c);
-  const int p = st[0];
-  const double2* R = ws.R2(c);
+  const int p = f.pp.at(c)[0];
+  const double2* R = f.R.at(c);
   __shared__ double s_sig[kFacMaxP];
   __shared__ int s_ord[kFacMaxP];
   for (int i = wv; i < p; i += kStepThreads / 64) {
     double s = 0.0;
     for (int row = lane; row < p; row += 64) {
-      const double2 v = R[(int64_t)i * P + row];
+      const double2 v = R[(int64_t)i * f.P + row];
       s += v.x * v.x + v.y * v.y;
     }
     s = fwave_sum(s);
@@ -392,54 +388,56 @@ __global__ __launch_bounds__(kStepThreads) void k_fac_finish(FacWs ws, int32_t m
     s_ord[pos] = i;
   }
   __syncthreads();
-  int32_t* ord = ws.ord(c);
-  for (int t = tid; t < P; t += kStepThreads) {
-    sv[(int64_t)c * P + t] = t < p ? s_sig[s_ord[t]] : 0.0;
+  int32_t* ord = f.ord.at(c);
+  for (int t = tid; t < f.P; t += kStepThreads) {
+    f.sv[(int64_t)c * f.P + t] = t < p ? s_sig[s_ord[t]] : 0.0;
     if (t < p) ord[t] = s_ord[t];
   }
   if (tid == 0) {
     const double smax = p > 0 ? s_sig[s_ord[0]] : 0.0;
     int l = 0;
     if (smax > 0.0)
-      while (l < p && s_sig[s_ord[l]] > eps * smax) ++l;
+      while (l < p && s_sig[s_ord[l]] > f.eps * smax) ++l;
     l = l < 1 ? 1 : l;
-    const double T2 = ws.fro(c)[1];
-    double tail2 = T2;
-    for (int t = p - 1; t >= l; --t) tail2 += s_sig[s_ord[t]] * s_sig[s_ord[t]];
-    // sigma_{l+1}(X) <= sqrt(sigma_{l+1}(B)^2 + T^2)
-    const double sl = l < p ? s_sig[s_ord[l]] : 0.0;
-    const double dropped = l < min(m, n) ? sqrt(sl * sl + T2) : 0.0;
-    st[6] = l;
-    rank[c] = l;
-    psteps[c] = p;
-    stats[3 * (int64_t)c] = sqrt(tail2);
-    stats[3 * (int64_t)c + 1] = dropped;
-    stats[3 * (int64_t)c + 2] = sqrt(T2);
-    status[c] = (st[5] ? 2 : 0) | (st[7] ? 1 : 0);
+    f.sst.at(c)[3] = l;
+    f.rank[c] = l;
+    if (f.psteps) f.psteps[c] = p;
+    if (f.stats) {
+      const double T2 = f.fro.p ? f.fro.at(c)[1] : 0.0;
+      double tail2 = T2;
+      for (int t = p - 1; t >= l; --t) tail2 += s_sig[s_ord[t]] * s_sig[s_ord[t]];
+      // sigma_{l+1}(X) <= sqrt(sigma_{l+1}(B)^2 + T^2)
+      const double sl = l < p ? s_sig[s_ord[l]] : 0.0;
+      f.stats[3 * (int64_t)c] = sqrt(tail2);
+      f.stats[3 * (int64_t)c + 1] = l < min(f.m, f.n) ? sqrt(sl * sl + T2) : 0.0;
+      f.stats[3 * (int64_t)c + 2] = sqrt(T2);
+    }
+    const int cap = f.qst.p ? f.qst.at(c)[2] : 0;
+    f.status[c] = (f.sst.at(c)[2] ? 2 : 0) | (cap ? 1 : 0);
   }
 }
 
-// The kept columns of J, in singular-value order, orthonormalised again by classical
-// Gram-Schmidt applied twice; the result goes to the R2 area (R2 is no longer needed).
-// One workgroup per matrix, rows tid and tid + 1024 per thread (p <= 2048).
-__global__ __launch_bounds__(kBigThreads) void k_fac_orth(FacWs ws, int32_t P) {
+// Columns ord[0..l) of src (p rows, ld lds) orthonormalised by classical Gram-Schmidt
+// applied twice, in that order, into dst (ld ldd).  One workgroup per matrix, rows tid and
+// tid + 1024 per thread (p <= 2048).  A zero matrix (p = 0) gives e_1.
+__global__ __launch_bounds__(kBigThreads) void k_orth(CArr src, int32_t lds, IArr ord_a, IArr pp, IArr sst, CArr dst,
+                                                      int32_t ldd) {
   const int c = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int32_t* st = ws.st(c);
-  const int p = st[0], l = st[6];
-  const double2* J = ws.J(c);
-  const int32_t* ord = ws.ord(c);
-  double2* Q = ws.R2(c);
+  const int p = pp.at(c)[0], l = sst.at(c)[3];
+  const double2* J = src.at(c);
+  const int32_t* ord = ord_a.at(c);
+  double2* Q = dst.at(c);
   __shared__ double2 s_v[kFacMaxP];
   __shared__ double2 s_h[kFacMaxP];
   __shared__ double s_red[kBigThreads / 64];
-  if (p == 0) {  // a zero matrix: U = e_1
-    for (int r = tid; r < P; r += kBigThreads) Q[r] = make_double2(r == 0 ? 1.0 : 0.0, 0.0);
+  if (p == 0) {
+    if (tid == 0) Q[0] = make_double2(1.0, 0.0);
     return;
   }
   const int r1 = tid + kBigThreads;
   for (int i = 0; i < l; ++i) {
-    const double2* ji = J + (int64_t)ord[i] * P;
+    const double2* ji = J + (int64_t)ord[i] * lds;
     double2 v = tid < p ? ji[tid] : make_double2(0.0, 0.0);
     double2 v1 = r1 < p ? ji[r1] : make_double2(0.0, 0.0);
     for (int pass = 0; pass < 2; ++pass) {
@@ -447,7 +445,7 @@ __global__ __launch_bounds__(kBigThreads) void k_fac_orth(FacWs ws, int32_t P) {
       if (r1 < p) s_v[r1] = v1;
       __syncthreads();
       for (int k = wv; k < i; k += kBigThreads / 64) {
-        const double2* qk = Q + (int64_t)k * P;
+        const double2* qk = Q + (int64_t)k * ldd;
         double hr = 0.0, hi = 0.0;
         for (int row = lane; row < p; row += 64) {
           const double2 t = cdotc(qk[row], s_v[row]);
@@ -461,14 +459,14 @@ __global__ __launch_bounds__(kBigThreads) void k_fac_orth(FacWs ws, int32_t P) {
       __syncthreads();
       if (tid < p) {
         for (int k = 0; k < i; ++k) {
-          const double2 t = cmul(Q[(int64_t)k * P + tid], s_h[k]);
+          const double2 t = cmul(Q[(int64_t)k * ldd + tid], s_h[k]);
           v.x -= t.x;
           v.y -= t.y;
         }
       }
       if (r1 < p) {
         for (int k = 0; k < i; ++k) {
-          const double2 t = cmul(Q[(int64_t)k * P + r1], s_h[k]);
+          const double2 t = cmul(Q[(int64_t)k * ldd + r1], s_h[k]);
           v1.x -= t.x;
           v1.y -= t.y;
         }
@@ -481,45 +479,56 @@ __global__ __launch_bounds__(kBigThreads) void k_fac_orth(FacWs ws, int32_t P) {
     double nrm2 = 0.0;
     for (int w = 0; w < kBigThreads / 64; ++w) nrm2 += s_red[w];
     const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
-    if (tid < p) Q[(int64_t)i * P + tid] = make_double2(v.x * inv, v.y * inv);
-    if (r1 < p) Q[(int64_t)i * P + r1] = make_double2(v1.x * inv, v1.y * inv);
+    if (tid < p) Q[(int64_t)i * ldd + tid] = make_double2(v.x * inv, v.y * inv);
+    if (r1 < p) Q[(int64_t)i * ldd + r1] = make_double2(v1.x * inv, v1.y * inv);
     __syncthreads();
   }
 }
 
-// U = Q_p [Jo; 0]: the reflectors of the pivoted QR applied in reverse order to CPW = 16 /
-// RPT kept columns per workgroup, held in registers (RPT rows per thread, rows tid + 1024 t).
+struct Apply {
+  CArr W;       // reflector k at W + k * rows
+  DArr om;
+  int32_t rows;
+  IArr nref;    // reflectors at nref.at(c)[0]
+  CArr src;     // kept columns, rows 0..p-1 (p at pp.at(c)[0], at least 1), ld lds
+  int32_t lds;
+  IArr pp;
+  IArr sst;     // l at sst.at(c)[3]
+  CArr dst;     // rows x l, ld rows
+};
+
+// dst = Q [src; 0] with Q = P_0 P_1 ... the reflectors applied in reverse order, CPW = 16 /
+// RPT kept columns per workgroup held in registers (RPT rows per thread, rows tid + 1024 t).
 template <int RPT>
-__global__ __launch_bounds__(kBigThreads) void k_fac_u(FacWs ws, int32_t m, int32_t P, double2* __restrict__ U) {
+__global__ __launch_bounds__(kBigThreads) void k_apply_q(Apply a) {
   constexpr int CPW = 16 / RPT;
   constexpr int NW = kBigThreads / 64;
   const int c = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int32_t* st = ws.st(c);
-  const int p = st[0], l = st[6];
+  const int nr = a.nref.at(c)[0], l = a.sst.at(c)[3];
+  const int p = a.pp.at(c)[0] > 0 ? a.pp.at(c)[0] : 1;  // a zero matrix keeps e_1 in row 0
   const int i0 = blockIdx.x * CPW;
   if (i0 >= l) return;
-  const double2* Jo = ws.R2(c);
+  const double2* S = a.src.at(c);
   __shared__ double2 s_d[2][NW][CPW];
   double2 z[CPW][RPT];
-  const int prow = p > 0 ? p : 1;  // a zero matrix keeps e_1 in row 0
 #pragma unroll
   for (int q = 0; q < CPW; ++q)
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
       const int row = tid + kBigThreads * t;
-      z[q][t] = (row < prow && i0 + q < l) ? Jo[(int64_t)(i0 + q) * P + row] : make_double2(0.0, 0.0);
+      z[q][t] = (row < p && i0 + q < l) ? S[(int64_t)(i0 + q) * a.lds + row] : make_double2(0.0, 0.0);
     }
-  const double2* Wm = ws.W(c);
-  const double* omv = ws.om(c);
-  for (int k = p - 1; k >= 0; --k) {
-    const double2* w = Wm + (int64_t)k * m;
+  const double2* Wm = a.W.at(c);
+  const double* omv = a.om.at(c);
+  for (int k = nr - 1; k >= 0; --k) {
+    const double2* w = Wm + (int64_t)k * a.rows;
     const double om = omv[k];
     double2 wr[RPT];
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
       const int row = tid + kBigThreads * t;
-      wr[t] = (row >= k && row < m) ? w[row] : make_double2(0.0, 0.0);
+      wr[t] = (row >= k && row < a.rows) ? w[row] : make_double2(0.0, 0.0);
     }
     const int buf = k & 1;
 #pragma unroll
@@ -552,30 +561,49 @@ __global__ __launch_bounds__(kBigThreads) void k_fac_u(FacWs ws, int32_t m, int3
       }
     }
   }
-  double2* Um = U + (int64_t)c * m * P;
+  double2* D = a.dst.at(c);
 #pragma unroll
   for (int q = 0; q < CPW; ++q) {
     if (i0 + q >= l) break;
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
       const int row = tid + kBigThreads * t;
-      if (row < m) Um[(int64_t)(i0 + q) * m + row] = z[q][t];
+      if (row < a.rows) D[(int64_t)(i0 + q) * a.rows + row] = z[q][t];
     }
   }
+}
+
+int launch_apply(const Apply& a, int32_t colcap, int32_t batch, hipStream_t s) {
+  const int rpt = (a.rows + kBigThreads - 1) / kBigThreads;
+#define UHM_APPLY(R)                                                                                             \
+  k_apply_q<R><<<dim3((unsigned)((colcap + 16 / R - 1) / (16 / R)), (unsigned)batch), dim3(kBigThreads), 0, s>>>(a)
+  if (rpt <= 1)
+    UHM_APPLY(1);
+  else if (rpt <= 2)
+    UHM_APPLY(2);
+  else if (rpt <= 4)
+    UHM_APPLY(4);
+  else if (rpt <= 8)
+    UHM_APPLY(8);
+  else
+    UHM_APPLY(16);
+#undef UHM_APPLY
+  UHM_HIP(hipGetLastError());
+  return UHM_OK;
 }
 
 // Sigma V^* = Jo^* B for the kept rows: SV[i][j] = conj(sum_k Jo[k][i] C[j][k]) (B = C^*),
 // 16 x 16 output tiles staged through LDS.  Grid (ceil(n / 16), ceil(P / 16), batch).
 constexpr int kSvT = 16;
-__global__ __launch_bounds__(kSvT* kSvT) void k_fac_sv(FacWs ws, int32_t n, int32_t P, double2* __restrict__ SV) {
+__global__ __launch_bounds__(kSvT* kSvT) void k_fac_sv(CArr Joa, int32_t P, IArr pp, IArr sst, CArr Ca, int32_t n,
+                                                       double2* __restrict__ SV) {
   const int c = blockIdx.z;
-  const int32_t* st = ws.st(c);
-  const int p = st[0], l = st[6];
+  const int p = pp.at(c)[0], l = sst.at(c)[3];
   const int i0 = blockIdx.y * kSvT, j0 = blockIdx.x * kSvT;
   if (i0 >= l) return;
   const int ti = threadIdx.x % kSvT, tj = threadIdx.x / kSvT;
-  const double2* Jo = ws.R2(c);
-  const double2* C = ws.C(c);
+  const double2* Jo = Joa.at(c);
+  const double2* C = Ca.at(c);
   __shared__ double2 s_j[kSvT][kSvT + 1];  // [k][i]
   __shared__ double2 s_c[kSvT][kSvT + 1];  // [k][j]
   double ar = 0.0, ai = 0.0;
@@ -599,6 +627,82 @@ __global__ __launch_bounds__(kSvT* kSvT) void k_fac_sv(FacWs ws, int32_t n, int3
   if (i < l && j < n) SV[(int64_t)c * P * n + (int64_t)j * P + i] = make_double2(ar, -ai);
 }
 
+// M = R_Y R_X^* (kp x kp; both upper triangular, ld kp): M[i][j] = sum_{l >= max(i, j)}
+// R_Y[i][l] conj(R_X[j][l]).  Grid (ceil(kp / 16), ceil(kp / 16), batch), one thread per entry.
+__global__ __launch_bounds__(256) void k_rr(CArr RYa, CArr RXa, int32_t kp, CArr Ma) {
+  const int c = blockIdx.z;
+  const int i = blockIdx.y * 16 + threadIdx.x % 16, j = blockIdx.x * 16 + threadIdx.x / 16;
+  if (i >= kp || j >= kp) return;
+  const double2* RY = RYa.at(c);
+  const double2* RX = RXa.at(c);
+  double ar = 0.0, ai = 0.0;
+  for (int l = max(i, j); l < kp; ++l) {
+    const double2 t = cdotc(RX[j + (int64_t)l * kp], RY[i + (int64_t)l * kp]);
+    ar += t.x;
+    ai += t.y;
+  }
+  Ma.at(c)[i + (int64_t)j * kp] = make_double2(ar, ai);
+}
+
+// Per-matrix workspace of the cluster factorisation (offsets in doubles).
+struct ClusterWs {
+  int64_t per, o_w, o_om, o_c, o_cq, o_r2, o_j, o_nu, o_ord, o_st;
+};
+ClusterWs cluster_ws(int32_t m, int32_t n, int32_t P) {
+  Carve cv;
+  ClusterWs w{};
+  w.o_w = cv.take(2 * (int64_t)P * m);
+  w.o_om = cv.take(P);
+  w.o_c = cv.take(2 * (int64_t)n * P);
+  w.o_cq = cv.take(2 * (int64_t)n * P);
+  w.o_r2 = cv.take(2 * (int64_t)P * P);
+  w.o_j = cv.take(2 * (int64_t)P * P);
+  w.o_nu = cv.take(2 * (int64_t)std::max(n, P));
+  w.o_ord = cv.take((P + 1) / 2);
+  // ints [0..3] the pivoted QR, [4..7] the QR of B^*, [8..11] Jacobi; doubles from 8:
+  // ||X||_F^2, T^2
+  w.o_st = cv.take(32);
+  w.per = cv.per;
+  return w;
+}
+
+// Per-matrix workspace of the recompression (offsets in doubles).
+struct RecWs {
+  int64_t per, o_wx, o_omx, o_wy, o_omy, o_rx, o_ry, o_m, o_j, o_qj, o_qw, o_nux, o_nuy, o_ord, o_st;
+};
+RecWs rec_ws(int32_t m, int32_t n, int32_t kp) {
+  Carve cv;
+  RecWs w{};
+  const int64_t kk = 2 * (int64_t)kp * kp;
+  w.o_wx = cv.take(2 * (int64_t)kp * m);
+  w.o_omx = cv.take(kp);
+  w.o_wy = cv.take(2 * (int64_t)kp * n);
+  w.o_omy = cv.take(kp);
+  w.o_rx = cv.take(kk);
+  w.o_ry = cv.take(kk);
+  w.o_m = cv.take(kk);
+  w.o_j = cv.take(kk);
+  w.o_qj = cv.take(kk);
+  w.o_qw = cv.take(kk);
+  w.o_nux = cv.take(2 * (int64_t)kp);
+  w.o_nuy = cv.take(2 * (int64_t)kp);
+  w.o_ord = cv.take((kp + 1) / 2);
+  w.o_st = cv.take(32);  // ints [0..3] the QR of X, [4..7] the QR of Y, [8..11] Jacobi
+  w.per = cv.per;
+  return w;
+}
+
+int run_qr(const QrStep& q, int32_t batch, int32_t steps, hipStream_t s) {
+  for (int32_t k = 0; k <= steps; ++k) {
+    k_qr_step<<<dim3((unsigned)((q.cols + kStepCols - 1) / kStepCols), (unsigned)batch), dim3(kStepThreads), 0, s>>>(
+        q, k);
+    UHM_HIP(hipGetLastError());
+  }
+  return UHM_OK;
+}
+
+double jacobi_tol(int32_t P) { return std::sqrt((double)P) * 2.220446049250313e-16; }
+
 }  // namespace
 }  // namespace uhm_detail
 
@@ -608,7 +712,7 @@ extern "C" {
 
 int64_t uhm_cluster_basis_work(int32_t batch, int32_t m, int32_t n, int32_t pmax) {
   if (batch < 0 || m < 1 || n < 1 || pmax < 1) return -1;
-  return layout(nullptr, m, n, pmax).per * (int64_t)batch;
+  return cluster_ws(m, n, pmax).per * (int64_t)batch;
 }
 
 int uhm_cluster_basis(double* X, int32_t batch, int32_t m, int32_t n, int32_t pmax, double tol, double eps,
@@ -624,62 +728,121 @@ int uhm_cluster_basis(double* X, int32_t batch, int32_t m, int32_t n, int32_t pm
   if (batch > 65535) return fail(UHM_EINVAL, "uhm_cluster_basis: more than 65535 matrices in one call");
   if (!X || !U || !SV || !sv || !rank || !psteps || !stats || !status || !work)
     return fail(UHM_EINVAL, "uhm_cluster_basis: null pointer");
-  FacWs ws = layout(work, m, n, pmax);
+  const int32_t P = pmax;
+  const ClusterWs ws = cluster_ws(m, n, P);
   if (work_len < ws.per * (int64_t)batch) return fail(UHM_EINVAL, "uhm_cluster_basis: workspace too small");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  double2* Xc = reinterpret_cast<double2*>(X);
   UHM_HIP(hipMemsetAsync(work, 0, sizeof(double) * (size_t)(ws.per * (int64_t)batch), s));
-  const int32_t P = pmax;
+  const int64_t per = ws.per;
+  const CArr Xa{reinterpret_cast<double2*>(X), (int64_t)m * n};
+  const CArr Wa = region<double2>(work, per, ws.o_w), Ca = region<double2>(work, per, ws.o_c),
+             Cq = region<double2>(work, per, ws.o_cq), R2 = region<double2>(work, per, ws.o_r2),
+             Ja = region<double2>(work, per, ws.o_j);
+  const DArr om = region<double>(work, per, ws.o_om), nu = region<double>(work, per, ws.o_nu),
+             fro = region<double>(work, per, ws.o_st + 8);
+  const IArr ord = region<int32_t>(work, per, ws.o_ord), st = region<int32_t>(work, per, ws.o_st);
+  const IArr stA = st, stB{st.p + 4, st.stride}, stS{st.p + 8, st.stride};
+  const CArr none{nullptr, 0};
+  const DArr dnone{nullptr, 0};
+  const IArr inone{nullptr, 0};
   const int32_t kcap = std::min(std::min(m, n), P);
-  k_fac_norms<<<dim3((unsigned)((n + kStepCols - 1) / kStepCols), (unsigned)batch), dim3(kStepThreads), 0, s>>>(
-      Xc, (int64_t)m * n, m, n, ws);
+  int rc;
+
+  // 1. pivoted QR of X to the tolerance; B^* into C (kept) and Cq (consumed by step 2)
+  k_col_norms<<<dim3((unsigned)((n + kStepCols - 1) / kStepCols), (unsigned)batch), dim3(kStepThreads), 0, s>>>(
+      Xa, m, n, nu);
   UHM_HIP(hipGetLastError());
-  QrStep q1{Xc, (int64_t)m * n, m, n, 0, kcap, tol * tol, 1, n, 1, 1};
-  for (int32_t k = 0; k <= kcap; ++k) {
-    k_qr_step<<<dim3((unsigned)((n + kStepCols - 1) / kStepCols), (unsigned)batch), dim3(kStepThreads), 0, s>>>(q1, ws,
-                                                                                                              k);
-    UHM_HIP(hipGetLastError());
-  }
-  // B^* (n x P, column-major) is in each matrix's C and Cq areas; the QR of the Cq copy gives R2
-  FacWs wc = ws;
-  double2* Cbase = ws.Cq(0);
-  const int64_t c_stride = ws.per / 2;  // in complex elements
-  k_fac_norms<<<dim3((unsigned)((P + kStepCols - 1) / kStepCols), (unsigned)batch), dim3(kStepThreads), 0, s>>>(
-      Cbase, c_stride, n, P, wc);
+  const QrStep q1{Xa, m, n, nu, Wa, om, Ca, Cq, n, 1, 1, stA, inone, fro, kcap, tol * tol, 1};
+  if ((rc = run_qr(q1, batch, kcap, s))) return rc;
+  // 2. QR of B^* (n x P, column-major in Cq): R2 (P x P, ld P)
+  k_col_norms<<<dim3((unsigned)((P + kStepCols - 1) / kStepCols), (unsigned)batch), dim3(kStepThreads), 0, s>>>(
+      Cq, n, P, nu);
   UHM_HIP(hipGetLastError());
-  QrStep q2{Cbase, c_stride, n, P, 1, P, 0.0, 0, 1, P, 0};
-  for (int32_t k = 0; k <= P; ++k) {
-    k_qr_step<<<dim3((unsigned)((P + kStepCols - 1) / kStepCols), (unsigned)batch), dim3(kStepThreads), 0, s>>>(q2, ws,
-                                                                                                              k);
-    UHM_HIP(hipGetLastError());
-  }
-  const double jtol = std::sqrt((double)P) * 2.220446049250313e-16;
-  k_fac_jacobi<<<dim3((unsigned)batch), dim3(kBigThreads), 0, s>>>(ws, P, jtol, 60);
+  const QrStep q2{Cq, n, P, nu, none, dnone, R2, none, 1, P, 0, stB, stA, dnone, P, 0.0, 0};
+  if ((rc = run_qr(q2, batch, P, s))) return rc;
+  // 3. one-sided Jacobi on R2, the rank rule, the kept columns of J orthonormalised (into R2)
+  k_jacobi<<<dim3((unsigned)batch), dim3(kBigThreads), 0, s>>>(R2, Ja, P, stA, stS, jacobi_tol(P), 60);
   UHM_HIP(hipGetLastError());
-  k_fac_finish<<<dim3((unsigned)batch), dim3(kStepThreads), 0, s>>>(ws, m, n, P, eps, sv, rank, psteps, stats, status);
+  const Finish f{R2, P, stA, stS, ord, eps, fro, stA, m, n, sv, rank, psteps, stats, status};
+  k_finish<<<dim3((unsigned)batch), dim3(kStepThreads), 0, s>>>(f);
   UHM_HIP(hipGetLastError());
-  k_fac_orth<<<dim3((unsigned)batch), dim3(kBigThreads), 0, s>>>(ws, P);
+  k_orth<<<dim3((unsigned)batch), dim3(kBigThreads), 0, s>>>(Ja, P, ord, stA, stS, R2, P);
   UHM_HIP(hipGetLastError());
-  double2* Uc = reinterpret_cast<double2*>(U);
-  const int rpt = (m + kBigThreads - 1) / kBigThreads;
-#define UHM_FAC_U(R)                                                                                       \
-  k_fac_u<R><<<dim3((unsigned)((P + 16 / R - 1) / (16 / R)), (unsigned)batch), dim3(kBigThreads), 0, s>>>( \
-      ws, m, P, Uc)
-  if (rpt <= 1)
-    UHM_FAC_U(1);
-  else if (rpt <= 2)
-    UHM_FAC_U(2);
-  else if (rpt <= 4)
-    UHM_FAC_U(4);
-  else if (rpt <= 8)
-    UHM_FAC_U(8);
-  else
-    UHM_FAC_U(16);
-#undef UHM_FAC_U
-  UHM_HIP(hipGetLastError());
+  // 4. U = Q_p [Jo; 0] and Sigma V^* = Jo^* B
+  const Apply ap{Wa, om, m, stA, R2, P, stA, stS, CArr{reinterpret_cast<double2*>(U), (int64_t)m * P}};
+  if ((rc = launch_apply(ap, P, batch, s))) return rc;
   k_fac_sv<<<dim3((unsigned)((n + kSvT - 1) / kSvT), (unsigned)((P + kSvT - 1) / kSvT), (unsigned)batch),
-             dim3(kSvT * kSvT), 0, s>>>(ws, n, P, reinterpret_cast<double2*>(SV));
+             dim3(kSvT * kSvT), 0, s>>>(R2, P, stA, stS, Ca, n, reinterpret_cast<double2*>(SV));
   UHM_HIP(hipGetLastError());
+  return UHM_OK;
+}
+
+int64_t uhm_block_recompress_work(int32_t batch, int32_t m, int32_t n, int32_t kp) {
+  if (batch < 0 || m < 1 || n < 1 || kp < 1) return -1;
+  return rec_ws(m, n, kp).per * (int64_t)batch;
+}
+
+int uhm_block_recompress(double* X, double* Y, int32_t batch, int32_t m, int32_t n, int32_t kp, double eps,
+                         double* U, double* V, double* sv, int32_t* rank, int32_t* status, double* work,
+                         int64_t work_len, void* hip_stream) {
+  if (batch < 0 || m < 1 || n < 1) return fail(UHM_EINVAL, "uhm_block_recompress: bad size");
+  if (m > kFacMaxRows || n > kFacMaxRows) return fail(UHM_EINVAL, "uhm_block_recompress: more than 16384 rows");
+  if (kp < 1 || kp > kFacMaxP || kp > std::min(m, n))
+    return fail(UHM_EINVAL, "uhm_block_recompress: kp must be in 1..min(m, n, 2048)");
+  if (!(eps >= 0.0) || !std::isfinite(eps))
+    return fail(UHM_EINVAL, "uhm_block_recompress: eps must be finite and >= 0");
+  if (batch == 0) return UHM_OK;
+  if (batch > 65535) return fail(UHM_EINVAL, "uhm_block_recompress: more than 65535 blocks in one call");
+  if (!X || !Y || !U || !V || !sv || !rank || !status || !work)
+    return fail(UHM_EINVAL, "uhm_block_recompress: null pointer");
+  const RecWs ws = rec_ws(m, n, kp);
+  if (work_len < ws.per * (int64_t)batch) return fail(UHM_EINVAL, "uhm_block_recompress: workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  UHM_HIP(hipMemsetAsync(work, 0, sizeof(double) * (size_t)(ws.per * (int64_t)batch), s));
+  const int64_t per = ws.per;
+  const CArr Xa{reinterpret_cast<double2*>(X), (int64_t)m * kp}, Ya{reinterpret_cast<double2*>(Y), (int64_t)n * kp};
+  const CArr WX = region<double2>(work, per, ws.o_wx), WY = region<double2>(work, per, ws.o_wy),
+             RX = region<double2>(work, per, ws.o_rx), RY = region<double2>(work, per, ws.o_ry),
+             Ma = region<double2>(work, per, ws.o_m), Ja = region<double2>(work, per, ws.o_j),
+             QJ = region<double2>(work, per, ws.o_qj), QW = region<double2>(work, per, ws.o_qw);
+  const DArr omx = region<double>(work, per, ws.o_omx), omy = region<double>(work, per, ws.o_omy),
+             nux = region<double>(work, per, ws.o_nux), nuy = region<double>(work, per, ws.o_nuy);
+  const IArr ord = region<int32_t>(work, per, ws.o_ord), st = region<int32_t>(work, per, ws.o_st);
+  const IArr stX = st, stY{st.p + 4, st.stride}, stS{st.p + 8, st.stride};
+  const CArr none{nullptr, 0};
+  const DArr dnone{nullptr, 0};
+  const IArr inone{nullptr, 0};
+  int rc;
+  // 1. unpivoted QR of both factors (all kp steps), R upper triangular (ld kp)
+  k_col_norms<<<dim3((unsigned)((kp + kStepCols - 1) / kStepCols), (unsigned)batch), dim3(kStepThreads), 0, s>>>(
+      Xa, m, kp, nux);
+  UHM_HIP(hipGetLastError());
+  k_col_norms<<<dim3((unsigned)((kp + kStepCols - 1) / kStepCols), (unsigned)batch), dim3(kStepThreads), 0, s>>>(
+      Ya, n, kp, nuy);
+  UHM_HIP(hipGetLastError());
+  const QrStep qx{Xa, m, kp, nux, WX, omx, RX, none, 1, kp, 0, stX, inone, dnone, kp, 0.0, 0};
+  const QrStep qy{Ya, n, kp, nuy, WY, omy, RY, none, 1, kp, 0, stY, inone, dnone, kp, 0.0, 0};
+  if ((rc = run_qr(qx, batch, kp, s))) return rc;
+  if ((rc = run_qr(qy, batch, kp, s))) return rc;
+  // 2. M = R_Y R_X^*; one-sided Jacobi M J = W Sigma (order kp = the steps of the QR of X)
+  k_rr<<<dim3((unsigned)((kp + 15) / 16), (unsigned)((kp + 15) / 16), (unsigned)batch), dim3(256), 0, s>>>(RY, RX, kp,
+                                                                                                         Ma);
+  UHM_HIP(hipGetLastError());
+  k_jacobi<<<dim3((unsigned)batch), dim3(kBigThreads), 0, s>>>(Ma, Ja, kp, stX, stS, jacobi_tol(kp), 60);
+  UHM_HIP(hipGetLastError());
+  const Finish f{Ma, kp, stX, stS, ord, eps, dnone, inone, m, n, sv, rank, nullptr, nullptr, status};
+  k_finish<<<dim3((unsigned)batch), dim3(kStepThreads), 0, s>>>(f);
+  UHM_HIP(hipGetLastError());
+  // 3. the kept columns of J and of M J (normalised) orthonormalised, then U = Q_X [J_k; 0]
+  // and V = Q_Y [W_k; 0]
+  k_orth<<<dim3((unsigned)batch), dim3(kBigThreads), 0, s>>>(Ja, kp, ord, stX, stS, QJ, kp);
+  UHM_HIP(hipGetLastError());
+  k_orth<<<dim3((unsigned)batch), dim3(kBigThreads), 0, s>>>(Ma, kp, ord, stX, stS, QW, kp);
+  UHM_HIP(hipGetLastError());
+  const Apply au{WX, omx, m, stX, QJ, kp, stX, stS, CArr{reinterpret_cast<double2*>(U), (int64_t)m * kp}};
+  if ((rc = launch_apply(au, kp, batch, s))) return rc;
+  const Apply av{WY, omy, n, stY, QW, kp, stX, stS, CArr{reinterpret_cast<double2*>(V), (int64_t)n * kp}};
+  if ((rc = launch_apply(av, kp, batch, s))) return rc;
   return UHM_OK;
 }
 

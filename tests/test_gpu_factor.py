@@ -10,6 +10,10 @@ Pins independent of both sides:
 On the builder's own cluster matrices the GPU bases are checked against the oracle's
 Alg. 1 (the SVD of the agglomerated block row of the assembled H-matrix): same ranks and
 the optimal projection error.
+
+The recompression of ACA factors (uhm_block_recompress, section 2.3) is pinned the same
+way: X = Q1 diag(s) G and Y = Q2 G^{-*} with G invertible give X Y^* = Q1 diag(s) Q2^*, whose
+truncated SVD is known in closed form.
 """
 import numpy as np
 import pytest
@@ -175,3 +179,67 @@ def test_builder_clusters_match_algorithm_1():
         assert err <= best * (1 + 1e-6) + 1e-13 * sv[0]
         checked += 1
     assert checked >= 8
+
+
+def _factor_pair(rng, m, n, s, cond=10.0):
+    """X, Y with X Y^* = Q1 diag(s) Q2^* and a mixing G of condition number about cond."""
+    k = s.size
+    q1, _ = np.linalg.qr(rng.standard_normal((m, k)) + 1j * rng.standard_normal((m, k)))
+    q2, _ = np.linalg.qr(rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k)))
+    a, _ = np.linalg.qr(rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k)))
+    b, _ = np.linalg.qr(rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k)))
+    g = (a * np.geomspace(1.0, 1.0 / cond, k)) @ b
+    return (q1 * s) @ g, q2 @ np.linalg.inv(g).conj().T
+
+
+def _check_rec(X, Y, U, V, sv, k, eps, s_true):
+    A = X @ Y.conj().T
+    k_ref = max(1, int(np.count_nonzero(s_true > eps * s_true[0]))) if s_true[0] > 0 else 1
+    assert k == k_ref
+    Uk, Vk = U[:, :k], V[:, :k]
+    assert np.linalg.norm(Uk.conj().T @ Uk - np.eye(k)) < 1e-13
+    assert np.linalg.norm(Vk.conj().T @ Vk - np.eye(k)) < 1e-13
+    kk = min(s_true.size, sv.size)
+    assert np.all(np.abs(sv[:kk] - s_true[:kk]) <= 1e-12 * s_true[0])
+    best = s_true[k] if k < s_true.size else 0.0
+    assert np.linalg.norm(A - (Uk * sv[:k]) @ Vk.conj().T, 2) <= best * (1 + 1e-6) + 1e-12 * s_true[0]
+
+
+@pytest.mark.parametrize("m,n,k", [(64, 64, 20), (128, 256, 37), (300, 200, 64), (1024, 512, 90)])
+def test_recompression_prescribed(m, n, k):
+    rng = np.random.default_rng(m + n + k)
+    batch = 4
+    eps = 1e-7
+    Xs, Ys, ss = [], [], []
+    for c in range(batch):
+        kc = k - 3 * c   # ragged ranks: zero columns pad the shorter factors
+        s = _decay(kc, 0.7, 0.2, rng)
+        X, Y = _factor_pair(rng, m, n, s)
+        Xp = np.zeros((m, k), complex)
+        Yp = np.zeros((n, k), complex)
+        Xp[:, :kc], Yp[:, :kc] = X, Y
+        Xs.append(Xp)
+        Ys.append(Yp)
+        ss.append(s)
+    U, V, sv, rk, st = _binding().block_recompress(np.stack(Xs), np.stack(Ys), eps)
+    assert np.all(st == 0)
+    U, V, sv = U.cpu().numpy(), V.cpu().numpy(), sv.cpu().numpy()
+    for c in range(batch):
+        _check_rec(Xs[c], Ys[c], U[c].T, V[c].T, sv[c], int(rk[c]), eps, ss[c])
+
+
+def test_recompression_degenerate_blocks():
+    """A zero block (rank 1, sigma 0) and an exact rank-1 block in one batch."""
+    rng = np.random.default_rng(8)
+    m, n, k = 80, 50, 6
+    X = np.zeros((2, m, k), complex)
+    Y = np.zeros((2, n, k), complex)
+    X[1, :, 0] = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    Y[1, :, 0] = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    U, V, sv, rk, st = _binding().block_recompress(X, Y, 1e-7)
+    sv = sv.cpu().numpy()
+    assert np.all(st == 0) and rk[0] == 1 and rk[1] == 1 and np.all(sv[0] == 0)
+    assert abs(sv[1, 0] - np.linalg.norm(X[1, :, 0]) * np.linalg.norm(Y[1, :, 0])) <= 1e-13 * sv[1, 0]
+    u, v = U.cpu().numpy()[1, 0], V.cpu().numpy()[1, 0]
+    assert np.linalg.norm(np.outer(u * sv[1, 0], v.conj()) - X[1] @ Y[1].conj().T) <= 1e-13 * sv[1, 0]
+
