@@ -472,8 +472,10 @@ int uhm_aca_pack(const uhm_block_desc* blocks, int64_t nblocks, const int32_t* r
  *          converge within 60 sweeps.
  * work: uhm_cluster_basis_work(batch, m, n, pmax) doubles of device memory (work_len counts
  * doubles); nothing is allocated.  Limits: m <= 16384, 1 <= pmax <= min(m, n, 2048), batch
- * <= 65535.  Asynchronous on hip_stream.  Errors: UHM_EINVAL (sizes, tol or eps negative or
- * not finite, null pointers, work too small), UHM_EHIP.
+ * <= 65535.  Enqueued on hip_stream; the Jacobi stage reads one counter back per sweep, so
+ * the call synchronises that stream about ten times and returns with the rest enqueued.
+ * Errors: UHM_EINVAL (sizes, tol or eps negative or not finite, null pointers, work too
+ * small), UHM_EHIP.
  */
 int uhm_cluster_basis(double* X, int32_t batch, int32_t m, int32_t n, int32_t pmax, double tol, double eps,
                       double* U, double* SV, double* sv, int32_t* rank, int32_t* psteps, double* stats,
@@ -497,8 +499,9 @@ int64_t uhm_cluster_basis_work(int32_t batch, int32_t m, int32_t n, int32_t pmax
  *   status[c] = 0, or 2 when the Jacobi sweeps did not converge within 60 sweeps.
  * work: uhm_block_recompress_work(batch, m, n, kp) doubles of device memory (work_len counts
  * doubles); nothing is allocated.  Limits: m, n <= 16384, 1 <= kp <= min(m, n, 2048), batch
- * <= 65535.  Asynchronous on hip_stream.  Errors: UHM_EINVAL (sizes, eps negative or not
- * finite, null pointers, work too small), UHM_EHIP.
+ * <= 65535.  Enqueued on hip_stream, synchronised once per Jacobi sweep as in
+ * uhm_cluster_basis.  Errors: UHM_EINVAL (sizes, eps negative or not finite, null pointers,
+ * work too small), UHM_EHIP.
  */
 int uhm_block_recompress(double* X, double* Y, int32_t batch, int32_t m, int32_t n, int32_t kp, double eps,
                          double* U, double* V, double* sv, int32_t* rank, int32_t* status, double* work,

@@ -23,8 +23,9 @@
 //  2. Unpivoted Householder QR of B^* = Q2 R2, R2 p x p (the same step kernel).
 //  3. One-sided (Hestenes) Jacobi on the columns of R2, with the rotations accumulated in J:
 //     R2 J = W Sigma, so B = R2^* Q2^* = J Sigma (Q2 W)^*: the left singular vectors of B are
-//     the columns of J and its singular values are the column norms.  Round-robin pairs, one
-//     wavefront per pair.  The accumulated rotations lose orthogonality at the level of
+//     the columns of J and its singular values are the column norms.  Round-robin pairs: one
+//     launch per round over the whole batch, one wavefront per pair, and one read-back per
+//     sweep.  The accumulated rotations lose orthogonality at the level of
 //     1e-12, so the kept columns of J are orthonormalised again (classical Gram-Schmidt
 //     applied twice, largest singular value first).
 //  4. U = Q_p [J_l; 0] (the reflectors of step 1 applied in reverse order, the columns held
@@ -264,85 +265,124 @@ __global__ __launch_bounds__(kStepThreads) void k_qr_step(QrStep a, int32_t k) {
 }
 
 // One-sided Jacobi on the p x p matrix R (ld P; p = pp.at(c)[0]), rotations accumulated in
-// V (set to the identity here), one workgroup of 16 wavefronts per matrix.  Round r of a
-// sweep pairs the columns by the circle method (index 0 fixed, the others rotated), so the
-// pairs of a round are disjoint and one wavefront takes each.  A pair (i, j) with Gram
-// entries alpha, beta, gamma is rotated when |gamma| > tol sqrt(alpha beta): with e = gamma
-// / |gamma|, zeta = (beta - alpha) / (2 |gamma|) and t the smaller root of t^2 + 2 zeta t -
-// 1 = 0, c = 1 / sqrt(1 + t^2), s = c t,
+// V.  A sweep is P' - 1 rounds (P' = P rounded up to even) of the circle schedule: index 0
+// fixed, the others rotated, so the pairs of a round are disjoint; each round is one launch
+// over the whole batch, one wavefront per pair, and pairs with a column >= p are skipped.
+// A pair (i, j) with Gram entries alpha, beta, gamma is rotated when |gamma| > tol
+// sqrt(alpha beta): with e = gamma / |gamma|, zeta = (beta - alpha) / (2 |gamma|) and t the
+// smaller root of t^2 + 2 zeta t - 1 = 0, c = 1 / sqrt(1 + t^2), s = c t,
 //   a_i <- c a_i - s conj(e) a_j,   a_j <- s e a_i + c a_j,
-// which makes a_i^* a_j vanish.  sst: [1] sweeps, [2] not converged.
-__global__ __launch_bounds__(kBigThreads) void k_jacobi(CArr Ra, CArr Va, int32_t P, IArr pp, IArr sst, double tol,
-                                                        int32_t max_sweeps) {
-  const int c = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+// which makes a_i^* a_j vanish.  sst per matrix: [0] a rotation in this sweep, [1] sweeps,
+// [2] still running (not converged), [3] rank (written later).
+constexpr int kJacWaves = 4;
+
+__global__ __launch_bounds__(256) void k_jacobi_init(CArr Va, int32_t P, IArr pp, IArr sst) {
+  const int c = blockIdx.y;
   const int p = pp.at(c)[0];
-  double2* R = Ra.at(c);
   double2* V = Va.at(c);
-  for (int64_t q = tid; q < (int64_t)P * P; q += kBigThreads) {
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < (int64_t)P * P; q += (int64_t)gridDim.x * 256) {
     const int r = (int)(q % P), col = (int)(q / P);
     V[q] = make_double2(r == col && r < p ? 1.0 : 0.0, 0.0);
   }
-  __syncthreads();
-  __shared__ int s_rot;
-  const int pq = p + (p & 1);
-  int sweep = 0;
-  bool conv = p < 2;
-  while (!conv && sweep < max_sweeps) {
-    if (tid == 0) s_rot = 0;
-    __syncthreads();
-    for (int r = 0; r < pq - 1; ++r) {
-      for (int q = wv; q < pq / 2; q += kBigThreads / 64) {
-        const int a0 = q == 0 ? 0 : (r + q - 1) % (pq - 1) + 1;
-        const int b0 = (r + (pq - 1 - q) - 1) % (pq - 1) + 1;
-        const int i = min(a0, b0), j = max(a0, b0);
-        if (j >= p) continue;
-        double2* ci = R + (int64_t)i * P;
-        double2* cj = R + (int64_t)j * P;
-        double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
-        for (int row = lane; row < p; row += 64) {
-          const double2 x = ci[row], y = cj[row];
-          al += x.x * x.x + x.y * x.y;
-          be += y.x * y.x + y.y * y.y;
-          const double2 g = cdotc(x, y);
-          gr += g.x;
-          gi += g.y;
-        }
-        al = fwave_sum(al);
-        be = fwave_sum(be);
-        gr = fwave_sum(gr);
-        gi = fwave_sum(gi);
-        const double g = hypot(gr, gi);
-        if (!(al > 0.0 && be > 0.0 && g > tol * sqrt(al * be))) continue;
-        const double2 e = make_double2(gr / g, gi / g);
-        const double z = (be - al) / (2.0 * g);
-        const double t = fabs(z) > 1e100 ? 0.5 / z : (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
-        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-        const double2 se = make_double2(sn * e.x, sn * e.y);  // s e
-        double2* vi = V + (int64_t)i * P;
-        double2* vj = V + (int64_t)j * P;
-        for (int row = lane; row < p; row += 64) {
-          const double2 x = ci[row], y = cj[row];
-          const double2 a1 = cdotc(se, y), b1 = cmul(se, x);  // s conj(e) y, s e x
-          ci[row] = make_double2(cs * x.x - a1.x, cs * x.y - a1.y);
-          cj[row] = make_double2(b1.x + cs * y.x, b1.y + cs * y.y);
-          const double2 u = vi[row], v = vj[row];
-          const double2 a2 = cdotc(se, v), b2 = cmul(se, u);
-          vi[row] = make_double2(cs * u.x - a2.x, cs * u.y - a2.y);
-          vj[row] = make_double2(b2.x + cs * v.x, b2.y + cs * v.y);
-        }
-        if (lane == 0) s_rot = 1;
-      }
-      __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int32_t* t = sst.at(c);
+    t[0] = 0;
+    t[1] = 0;
+    t[2] = p >= 2 ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(64 * kJacWaves) void k_jacobi_round(CArr Ra, CArr Va, int32_t P, IArr pp, IArr sst,
+                                                                 int32_t r, double tol) {
+  const int c = blockIdx.y;
+  int32_t* t = sst.at(c);
+  if (!t[2]) return;
+  const int lane = threadIdx.x & 63;
+  const int q = blockIdx.x * kJacWaves + (threadIdx.x >> 6);
+  const int pq = P + (P & 1);
+  if (q >= pq / 2) return;
+  const int p = pp.at(c)[0];
+  const int a0 = q == 0 ? 0 : (r + q - 1) % (pq - 1) + 1;
+  const int b0 = (r + (pq - 1 - q) - 1) % (pq - 1) + 1;
+  const int i = min(a0, b0), j = max(a0, b0);
+  if (j >= p) return;
+  double2* R = Ra.at(c);
+  double2* V = Va.at(c);
+  double2* ci = R + (int64_t)i * P;
+  double2* cj = R + (int64_t)j * P;
+  double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+  for (int row = lane; row < p; row += 64) {
+    const double2 x = ci[row], y = cj[row];
+    al += x.x * x.x + x.y * x.y;
+    be += y.x * y.x + y.y * y.y;
+    const double2 g = cdotc(x, y);
+    gr += g.x;
+    gi += g.y;
+  }
+  al = fwave_sum(al);
+  be = fwave_sum(be);
+  gr = fwave_sum(gr);
+  gi = fwave_sum(gi);
+  const double g = hypot(gr, gi);
+  if (!(al > 0.0 && be > 0.0 && g > tol * sqrt(al * be))) return;
+  const double2 e = make_double2(gr / g, gi / g);
+  const double z = (be - al) / (2.0 * g);
+  const double tt = fabs(z) > 1e100 ? 0.5 / z : (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+  const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+  const double2 se = make_double2(sn * e.x, sn * e.y);  // s e
+  double2* vi = V + (int64_t)i * P;
+  double2* vj = V + (int64_t)j * P;
+  for (int row = lane; row < p; row += 64) {
+    const double2 x = ci[row], y = cj[row];
+    const double2 a1 = cdotc(se, y), b1 = cmul(se, x);  // s conj(e) y, s e x
+    ci[row] = make_double2(cs * x.x - a1.x, cs * x.y - a1.y);
+    cj[row] = make_double2(b1.x + cs * y.x, b1.y + cs * y.y);
+    const double2 u = vi[row], v = vj[row];
+    const double2 a2 = cdotc(se, v), b2 = cmul(se, u);
+    vi[row] = make_double2(cs * u.x - a2.x, cs * u.y - a2.y);
+    vj[row] = make_double2(b2.x + cs * v.x, b2.y + cs * v.y);
+  }
+  if (lane == 0) t[0] = 1;
+}
+
+// End of a sweep: a matrix with no rotation in it has converged; the rest are counted.
+__global__ __launch_bounds__(256) void k_jacobi_sweep_end(IArr sst, int32_t batch, int32_t* __restrict__ active) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= batch) return;
+  int32_t* t = sst.at(c);
+  if (t[2]) {
+    t[1] += 1;
+    if (!t[0])
+      t[2] = 0;
+    else
+      atomicAdd(active, 1);
+  }
+  t[0] = 0;
+}
+
+// The sweeps of one batch: one launch per round, and the count of running matrices read back
+// after each sweep.  active: one device int.
+int run_jacobi(CArr R, CArr V, int32_t P, IArr pp, IArr sst, int32_t batch, double tol, int32_t max_sweeps,
+               int32_t* active, hipStream_t s) {
+  const int64_t pq = P + (P & 1);
+  const unsigned gx = (unsigned)std::min<int64_t>((pq * pq + 255) / 256, 1024);
+  k_jacobi_init<<<dim3(gx, (unsigned)batch), dim3(256), 0, s>>>(V, P, pp, sst);
+  UHM_HIP(hipGetLastError());
+  const unsigned rx = (unsigned)((pq / 2 + kJacWaves - 1) / kJacWaves);
+  for (int32_t sweep = 0; sweep < max_sweeps && pq >= 2; ++sweep) {
+    for (int32_t r = 0; r < pq - 1; ++r) {
+      k_jacobi_round<<<dim3(rx, (unsigned)batch), dim3(64 * kJacWaves), 0, s>>>(R, V, P, pp, sst, r, tol);
+      UHM_HIP(hipGetLastError());
     }
-    conv = s_rot == 0;
-    ++sweep;
-    __syncthreads();
+    UHM_HIP(hipMemsetAsync(active, 0, sizeof(int32_t), s));
+    k_jacobi_sweep_end<<<dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s>>>(sst, batch, active);
+    UHM_HIP(hipGetLastError());
+    int32_t left = 0;
+    UHM_HIP(hipMemcpyAsync(&left, active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    UHM_HIP(hipStreamSynchronize(s));
+    if (left == 0) break;
   }
-  if (tid == 0) {
-    sst.at(c)[1] = sweep;
-    sst.at(c)[2] = conv ? 0 : 1;
-  }
+  return UHM_OK;
 }
 
 struct Finish {
@@ -498,11 +538,12 @@ struct Apply {
 };
 
 // dst = Q [src; 0] with Q = P_0 P_1 ... the reflectors applied in reverse order, CPW = 16 /
-// RPT kept columns per workgroup held in registers (RPT rows per thread, rows tid + 1024 t).
-template <int RPT>
-__global__ __launch_bounds__(kBigThreads) void k_apply_q(Apply a) {
+// RPT kept columns per workgroup of NT threads held in registers (RPT rows per thread, rows
+// tid + NT t).
+template <int RPT, int NT>
+__global__ __launch_bounds__(NT) void k_apply_q(Apply a) {
   constexpr int CPW = 16 / RPT;
-  constexpr int NW = kBigThreads / 64;
+  constexpr int NW = NT / 64;
   const int c = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nr = a.nref.at(c)[0], l = a.sst.at(c)[3];
@@ -516,7 +557,7 @@ __global__ __launch_bounds__(kBigThreads) void k_apply_q(Apply a) {
   for (int q = 0; q < CPW; ++q)
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
-      const int row = tid + kBigThreads * t;
+      const int row = tid + NT * t;
       z[q][t] = (row < p && i0 + q < l) ? S[(int64_t)(i0 + q) * a.lds + row] : make_double2(0.0, 0.0);
     }
   const double2* Wm = a.W.at(c);
@@ -527,7 +568,7 @@ __global__ __launch_bounds__(kBigThreads) void k_apply_q(Apply a) {
     double2 wr[RPT];
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
-      const int row = tid + kBigThreads * t;
+      const int row = tid + NT * t;
       wr[t] = (row >= k && row < a.rows) ? w[row] : make_double2(0.0, 0.0);
     }
     const int buf = k & 1;
@@ -567,7 +608,7 @@ __global__ __launch_bounds__(kBigThreads) void k_apply_q(Apply a) {
     if (i0 + q >= l) break;
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
-      const int row = tid + kBigThreads * t;
+      const int row = tid + NT * t;
       if (row < a.rows) D[(int64_t)(i0 + q) * a.rows + row] = z[q][t];
     }
   }
@@ -575,18 +616,26 @@ __global__ __launch_bounds__(kBigThreads) void k_apply_q(Apply a) {
 
 int launch_apply(const Apply& a, int32_t colcap, int32_t batch, hipStream_t s) {
   const int rpt = (a.rows + kBigThreads - 1) / kBigThreads;
-#define UHM_APPLY(R)                                                                                             \
-  k_apply_q<R><<<dim3((unsigned)((colcap + 16 / R - 1) / (16 / R)), (unsigned)batch), dim3(kBigThreads), 0, s>>>(a)
-  if (rpt <= 1)
-    UHM_APPLY(1);
+#define UHM_APPLY(R, T)                                                                                  \
+  k_apply_q<R, T><<<dim3((unsigned)((colcap + 16 / R - 1) / (16 / R)), (unsigned)batch), dim3(T), 0, s>>>(a)
+  if (a.rows <= 64)
+    UHM_APPLY(1, 64);
+  else if (a.rows <= 128)
+    UHM_APPLY(1, 128);
+  else if (a.rows <= 256)
+    UHM_APPLY(1, 256);
+  else if (a.rows <= 512)
+    UHM_APPLY(1, 512);
+  else if (rpt <= 1)
+    UHM_APPLY(1, 1024);
   else if (rpt <= 2)
-    UHM_APPLY(2);
+    UHM_APPLY(2, 1024);
   else if (rpt <= 4)
-    UHM_APPLY(4);
+    UHM_APPLY(4, 1024);
   else if (rpt <= 8)
-    UHM_APPLY(8);
+    UHM_APPLY(8, 1024);
   else
-    UHM_APPLY(16);
+    UHM_APPLY(16, 1024);
 #undef UHM_APPLY
   UHM_HIP(hipGetLastError());
   return UHM_OK;
@@ -712,7 +761,7 @@ extern "C" {
 
 int64_t uhm_cluster_basis_work(int32_t batch, int32_t m, int32_t n, int32_t pmax) {
   if (batch < 0 || m < 1 || n < 1 || pmax < 1) return -1;
-  return cluster_ws(m, n, pmax).per * (int64_t)batch;
+  return cluster_ws(m, n, pmax).per * (int64_t)batch + 32;
 }
 
 int uhm_cluster_basis(double* X, int32_t batch, int32_t m, int32_t n, int32_t pmax, double tol, double eps,
@@ -730,7 +779,7 @@ int uhm_cluster_basis(double* X, int32_t batch, int32_t m, int32_t n, int32_t pm
     return fail(UHM_EINVAL, "uhm_cluster_basis: null pointer");
   const int32_t P = pmax;
   const ClusterWs ws = cluster_ws(m, n, P);
-  if (work_len < ws.per * (int64_t)batch) return fail(UHM_EINVAL, "uhm_cluster_basis: workspace too small");
+  if (work_len < ws.per * (int64_t)batch + 32) return fail(UHM_EINVAL, "uhm_cluster_basis: workspace too small");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   UHM_HIP(hipMemsetAsync(work, 0, sizeof(double) * (size_t)(ws.per * (int64_t)batch), s));
   const int64_t per = ws.per;
@@ -761,8 +810,9 @@ int uhm_cluster_basis(double* X, int32_t batch, int32_t m, int32_t n, int32_t pm
   const QrStep q2{Cq, n, P, nu, none, dnone, R2, none, 1, P, 0, stB, stA, dnone, P, 0.0, 0};
   if ((rc = run_qr(q2, batch, P, s))) return rc;
   // 3. one-sided Jacobi on R2, the rank rule, the kept columns of J orthonormalised (into R2)
-  k_jacobi<<<dim3((unsigned)batch), dim3(kBigThreads), 0, s>>>(R2, Ja, P, stA, stS, jacobi_tol(P), 60);
-  UHM_HIP(hipGetLastError());
+  if ((rc = run_jacobi(R2, Ja, P, stA, stS, batch, jacobi_tol(P), 60,
+                       reinterpret_cast<int32_t*>(work + ws.per * (int64_t)batch), s)))
+    return rc;
   const Finish f{R2, P, stA, stS, ord, eps, fro, stA, m, n, sv, rank, psteps, stats, status};
   k_finish<<<dim3((unsigned)batch), dim3(kStepThreads), 0, s>>>(f);
   UHM_HIP(hipGetLastError());
@@ -779,7 +829,7 @@ int uhm_cluster_basis(double* X, int32_t batch, int32_t m, int32_t n, int32_t pm
 
 int64_t uhm_block_recompress_work(int32_t batch, int32_t m, int32_t n, int32_t kp) {
   if (batch < 0 || m < 1 || n < 1 || kp < 1) return -1;
-  return rec_ws(m, n, kp).per * (int64_t)batch;
+  return rec_ws(m, n, kp).per * (int64_t)batch + 32;
 }
 
 int uhm_block_recompress(double* X, double* Y, int32_t batch, int32_t m, int32_t n, int32_t kp, double eps,
@@ -796,7 +846,8 @@ int uhm_block_recompress(double* X, double* Y, int32_t batch, int32_t m, int32_t
   if (!X || !Y || !U || !V || !sv || !rank || !status || !work)
     return fail(UHM_EINVAL, "uhm_block_recompress: null pointer");
   const RecWs ws = rec_ws(m, n, kp);
-  if (work_len < ws.per * (int64_t)batch) return fail(UHM_EINVAL, "uhm_block_recompress: workspace too small");
+  if (work_len < ws.per * (int64_t)batch + 32)
+    return fail(UHM_EINVAL, "uhm_block_recompress: workspace too small");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   UHM_HIP(hipMemsetAsync(work, 0, sizeof(double) * (size_t)(ws.per * (int64_t)batch), s));
   const int64_t per = ws.per;
@@ -828,8 +879,9 @@ int uhm_block_recompress(double* X, double* Y, int32_t batch, int32_t m, int32_t
   k_rr<<<dim3((unsigned)((kp + 15) / 16), (unsigned)((kp + 15) / 16), (unsigned)batch), dim3(256), 0, s>>>(RY, RX, kp,
                                                                                                          Ma);
   UHM_HIP(hipGetLastError());
-  k_jacobi<<<dim3((unsigned)batch), dim3(kBigThreads), 0, s>>>(Ma, Ja, kp, stX, stS, jacobi_tol(kp), 60);
-  UHM_HIP(hipGetLastError());
+  if ((rc = run_jacobi(Ma, Ja, kp, stX, stS, batch, jacobi_tol(kp), 60,
+                       reinterpret_cast<int32_t*>(work + ws.per * (int64_t)batch), s)))
+    return rc;
   const Finish f{Ma, kp, stX, stS, ord, eps, dnone, inone, m, n, sv, rank, nullptr, nullptr, status};
   k_finish<<<dim3((unsigned)batch), dim3(kStepThreads), 0, s>>>(f);
   UHM_HIP(hipGetLastError());
