@@ -305,6 +305,19 @@ def _to_host(t):
     return h.numpy()
 
 
+def _to_host_copy(t):
+    """As _to_host, then copied into pageable memory by torch's threaded host copy, so the
+    page-locked block goes back to torch's cache for the next transfer (results that the
+    builder keeps for the rest of the build would otherwise pin memory for that long)."""
+    import torch
+    h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+    h.copy_(t)
+    out = torch.empty(t.shape, dtype=t.dtype)
+    out.copy_(h)
+    del h
+    return out.numpy()
+
+
 def _pack_factors(res, pos, rel, m, n, device=False):
     """Factors of the blocks pos[rel] of one shape group of an ACA result (blocks pos are
     contiguous, all m x n): X (cnt, m, kp) = u and Y (cnt, n, kp) = conj(v), zero beyond each
@@ -451,16 +464,20 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
         def recompress_dev(sel, X, Y):
             """The recompression of one shape group on the GPU (uhm_block_recompress), in calls of
             at most 65535 blocks and about 4 GiB of factors and workspace."""
+            import torch
             from . import binding
             m, kp, n = X.shape[1], X.shape[2], Y.shape[1]
             per = 16 * kp * (6 * (m + n) + 8 * kp)   # factors, their copies, workspace and results
             step = max(1, min(65535, (1 << 32) // per))
             for a in range(0, len(sel), step):
                 part = sel[a:a + step]
+                tq = time.perf_counter()
                 U, V, sv, rk, stt = binding.block_recompress(X[a:a + step], Y[a:a + step], eps_rec)
+                torch.cuda.synchronize()
+                tq1 = time.perf_counter()
                 kmax = int(rk.max())
-                Uh = U[:, :kmax, :].cpu().numpy()
-                Vh = V[:, :kmax, :].cpu().numpy()
+                Uh = _to_host_copy(U[:, :kmax, :].contiguous())
+                Vh = _to_host_copy(V[:, :kmax, :].contiguous())
                 svh = sv[:, :kmax].cpu().numpy()
                 del U, V, sv
                 bad = np.nonzero(stt != 0)[0]
@@ -470,6 +487,9 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
                     fac_U[key] = Uh[c, :k, :].T
                     fac_V[key] = Vh[c, :k, :].T
                     fac_s[key] = svh[c, :k].copy()
+                if verbose:
+                    print(f"    recompression of {len(part)} blocks {m} x {n}, kp {kp}: GPU {tq1 - tq:.2f} s, "
+                          f"host {time.perf_counter() - tq1:.2f} s", file=sys.stderr, flush=True)
                 if bad.size:   # Jacobi not converged: the host SVD for those blocks
                     for key, Ub, Vb, sb in recompress_xy([part[c] for c in bad], X[a:a + step][bad].cpu().numpy(),
                                                          Y[a:a + step][bad].cpu().numpy()):
@@ -614,8 +634,8 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
                 tc = time.perf_counter()
                 bad = set(np.nonzero(res.status != 0)[0].tolist())
                 lmax = int(res.rank.max())
-                Uh = res.U[:, :lmax, :].cpu().numpy()
-                SVh = res.SV[:, :, :lmax].cpu().numpy()
+                Uh = _to_host_copy(res.U[:, :lmax, :].contiguous())
+                SVh = _to_host_copy(res.SV[:, :, :lmax].contiguous())
                 del res.U, res.SV, res.sv, buf
                 for c, (t, ks) in enumerate(part):
                     if c in bad:
