@@ -130,25 +130,30 @@ struct QrStep {
   int32_t pivoted;
 };
 
-// One Householder step k for every matrix of the batch.  Grid (ceil(cols / 16), batch).
 // The reflector of step k is P = I - omega w w^*, w = x - beta e_k on rows k.., x the pivot
 // column, beta = -e^{i arg x_k} ||x|| (so that w_k carries no cancellation), omega =
 // 1 / (||x|| (||x|| + |x_k|)); P x = beta e_k.
-__global__ __launch_bounds__(kStepThreads) void k_qr_step(QrStep a, int32_t k) {
-  const int c = blockIdx.y;
-  int32_t* st = a.st.at(c);
-  if (st[1]) return;  // stopped in an earlier step
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const double* nu = a.nu.at(c) + (k & 1) * (int64_t)a.cols;
-  double* nu2 = a.nu.at(c) + ((k + 1) & 1) * (int64_t)a.cols;
-  const int32_t lim = a.lim.p ? min(a.kcap, a.lim.at(c)[0]) : a.kcap;
+struct StepHead {
+  int piv;
+  double2 beta, wk;
+  double om;
+};
 
-  // trailing sum and pivot over the live columns, in one fixed order
-  __shared__ double s_sum[kStepThreads], s_mx[kStepThreads];
-  __shared__ int s_ix[kStepThreads];
+// The part of a step every workgroup of a matrix takes alike: the trailing sum and the
+// pivot over the live columns (reduced in one fixed order), the stop test, and the
+// reflector.  Returns false when the matrix has stopped (in this step or before).
+template <int NT>
+__device__ bool qr_head(const QrStep& a, int32_t k, int c, StepHead& h) {
+  __shared__ double s_sum[NT], s_mx[NT];
+  __shared__ int s_ix[NT];
+  int32_t* st = a.st.at(c);
+  if (st[1]) return false;  // stopped in an earlier step
+  const int tid = threadIdx.x;
+  const double* nu = a.nu.at(c) + (k & 1) * (int64_t)a.cols;
+  const int32_t lim = a.lim.p ? min(a.kcap, a.lim.at(c)[0]) : a.kcap;
   double sum = 0.0, mx = -1.0;
   int ix = INT_MAX;
-  for (int j = tid; j < a.cols; j += kStepThreads) {
+  for (int j = tid; j < a.cols; j += NT) {
     const double v = nu[j];
     if (v >= 0.0) {
       sum += v;
@@ -162,7 +167,7 @@ __global__ __launch_bounds__(kStepThreads) void k_qr_step(QrStep a, int32_t k) {
   s_mx[tid] = mx;
   s_ix[tid] = ix;
   __syncthreads();
-  for (int s = kStepThreads / 2; s > 0; s >>= 1) {
+  for (int s = NT / 2; s > 0; s >>= 1) {
     if (tid < s) {
       s_sum[tid] += s_sum[tid + s];
       const double m2 = s_mx[tid + s];
@@ -188,78 +193,194 @@ __global__ __launch_bounds__(kStepThreads) void k_qr_step(QrStep a, int32_t k) {
       }
       st[2] = a.pivoted && !met && k < a.rows && k < a.cols ? 1 : 0;
     }
-    return;
+    return false;
   }
   if (fro && k == 0 && blockIdx.x == 0 && tid == 0) fro[0] = tr;
-  const int piv = a.pivoted ? s_ix[0] : k;
-
-  double2* Am = a.A.at(c);
-  const double2* x = Am + (int64_t)piv * a.rows;
-  const double nx = sqrt(fmax(nu[piv], 0.0));
+  h.piv = a.pivoted ? s_ix[0] : k;
+  const double2* x = a.A.at(c) + (int64_t)h.piv * a.rows;
+  const double nx = sqrt(fmax(nu[h.piv], 0.0));
   const double2 al = x[k];
   const double aa = hypot(al.x, al.y);
   const double2 ph = aa > 0.0 ? make_double2(al.x / aa, al.y / aa) : make_double2(1.0, 0.0);
-  const double2 beta = make_double2(-ph.x * nx, -ph.y * nx);
-  const double2 wk = make_double2(ph.x * (aa + nx), ph.y * (aa + nx));
-  const double om = nx > 0.0 ? 1.0 / (nx * (nx + aa)) : 0.0;
+  h.beta = make_double2(-ph.x * nx, -ph.y * nx);
+  h.wk = make_double2(ph.x * (aa + nx), ph.y * (aa + nx));
+  h.om = nx > 0.0 ? 1.0 / (nx * (nx + aa)) : 0.0;
+  return true;
+}
+
+// The pivot column's part of a step (its reflector, R entry and retired marker), and the
+// R entry and marker of a column retired before; `lead` is the one thread that writes the
+// scalars.  The reflector is written by the threads t = 0..NT-1 of the caller.
+__device__ __forceinline__ void qr_retire(const QrStep& a, int32_t k, int c, const StepHead& h, int j, bool lead,
+                                          int t0, int nt) {
+  const int64_t ro = (int64_t)k * a.rs + (int64_t)j * a.cs;
+  double* nu2 = a.nu.at(c) + ((k + 1) & 1) * (int64_t)a.cols;
   double2* R = a.R.at(c);
   double2* Rq = a.Rq.p ? a.Rq.at(c) : nullptr;
+  if (j == h.piv) {
+    if (a.W.p) {
+      const double2* x = a.A.at(c) + (int64_t)h.piv * a.rows;
+      double2* w = a.W.at(c) + (int64_t)k * a.rows;
+      for (int i = t0; i < a.rows; i += nt) w[i] = i < k ? make_double2(0.0, 0.0) : (i == k ? h.wk : x[i]);
+      if (lead) a.om.at(c)[k] = h.om;
+    }
+    if (lead) {
+      R[ro] = a.rconj ? cconj(h.beta) : h.beta;
+      if (Rq) Rq[ro] = R[ro];
+      nu2[j] = -1.0;
+    }
+  } else if (lead) {  // retired in an earlier step: R is upper triangular in pivot order
+    R[ro] = make_double2(0.0, 0.0);
+    if (Rq) Rq[ro] = make_double2(0.0, 0.0);
+    nu2[j] = -1.0;
+  }
+}
 
+__device__ __forceinline__ void qr_store(const QrStep& a, int32_t k, int c, int j, double2 rk, double nn) {
+  const int64_t ro = (int64_t)k * a.rs + (int64_t)j * a.cs;
+  double2* R = a.R.at(c);
+  R[ro] = a.rconj ? cconj(rk) : rk;
+  if (a.Rq.p) a.Rq.at(c)[ro] = R[ro];
+  a.nu.at(c)[((k + 1) & 1) * (int64_t)a.cols + j] = nn;
+}
+
+// One Householder step k for every matrix of the batch, matrices of at most 64 * RPL rows:
+// a wavefront per column, kStepCols columns per workgroup, grid (ceil(cols / 16), batch).
+// The pivot column (once per wavefront) and each updated column are held in registers (RPL
+// rows per lane), so a column is read once and written once.
+template <int RPL>
+__global__ __launch_bounds__(kStepThreads) void k_qr_step(QrStep a, int32_t k) {
+  const int c = blockIdx.y;
+  StepHead h;
+  if (!qr_head<kStepThreads>(a, k, c, h)) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double* nu = a.nu.at(c) + (k & 1) * (int64_t)a.cols;
+  double2* Am = a.A.at(c);
+  const double2* x = Am + (int64_t)h.piv * a.rows;
+  double2 xc[RPL];
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int i = k + lane + 64 * t;
+    xc[t] = i < a.rows ? (i == k ? h.wk : x[i]) : make_double2(0.0, 0.0);
+  }
   for (int q = 0; q < kStepCols / 4; ++q) {
     const int j = blockIdx.x * kStepCols + wv * (kStepCols / 4) + q;
     if (j >= a.cols) break;
-    const int64_t ro = (int64_t)k * a.rs + (int64_t)j * a.cs;
-    if (j == piv) {
-      if (a.W.p) {
-        double2* w = a.W.at(c) + (int64_t)k * a.rows;
-        for (int i = lane; i < a.rows; i += 64) w[i] = i < k ? make_double2(0.0, 0.0) : (i == k ? wk : x[i]);
-        if (lane == 0) a.om.at(c)[k] = om;
-      }
-      if (lane == 0) {
-        R[ro] = a.rconj ? cconj(beta) : beta;
-        if (Rq) Rq[ro] = R[ro];
-        nu2[j] = -1.0;
-      }
-      continue;
-    }
-    if (nu[j] < 0.0) {  // retired in an earlier step: R is upper triangular in pivot order
-      if (lane == 0) {
-        R[ro] = make_double2(0.0, 0.0);
-        if (Rq) Rq[ro] = make_double2(0.0, 0.0);
-        nu2[j] = -1.0;
-      }
+    if (j == h.piv || nu[j] < 0.0) {
+      qr_retire(a, k, c, h, j, lane == 0, lane, 64);
       continue;
     }
     double2* y = Am + (int64_t)j * a.rows;
+    double2 yc[RPL];
     double sr = 0.0, si = 0.0;
-    for (int i = k + lane; i < a.rows; i += 64) {
-      const double2 wi = i == k ? wk : x[i];
-      const double2 t = cdotc(wi, y[i]);
-      sr += t.x;
-      si += t.y;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int i = k + lane + 64 * t;
+      yc[t] = i < a.rows ? y[i] : make_double2(0.0, 0.0);
+      const double2 v = cdotc(xc[t], yc[t]);
+      sr += v.x;
+      si += v.y;
     }
     sr = fwave_sum(sr);
     si = fwave_sum(si);
-    const double2 f = make_double2(om * sr, om * si);
+    const double2 f = make_double2(h.om * sr, h.om * si);
     double nn = 0.0;
     double2 rk = make_double2(0.0, 0.0);
-    for (int i = k + lane; i < a.rows; i += 64) {
-      const double2 wi = i == k ? wk : x[i];
-      const double2 fw = cmul(f, wi);
-      double2 v = y[i];
-      v.x -= fw.x;
-      v.y -= fw.y;
-      y[i] = v;
-      if (i == k)
-        rk = v;
-      else
-        nn += v.x * v.x + v.y * v.y;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int i = k + lane + 64 * t;
+      if (i < a.rows) {
+        const double2 fw = cmul(f, xc[t]);
+        const double2 v = make_double2(yc[t].x - fw.x, yc[t].y - fw.y);
+        y[i] = v;
+        if (i == k)
+          rk = v;
+        else
+          nn += v.x * v.x + v.y * v.y;
+      }
     }
     nn = fwave_sum(nn);
-    if (lane == 0) {  // lane 0 holds row k
-      R[ro] = a.rconj ? cconj(rk) : rk;
-      if (Rq) Rq[ro] = R[ro];
-      nu2[j] = nn;
+    if (lane == 0) qr_store(a, k, c, j, rk, nn);  // lane 0 holds row k
+  }
+}
+
+// The same step for matrices of more rows: a workgroup of NT threads per column (RPL rows
+// per thread, rows k + tid + NT t), kWideCols columns per workgroup in turn, the partial
+// sums of the NT / 64 wavefronts combined in LDS in one fixed order.
+constexpr int kWideCols = 8;
+template <int NT, int RPL>
+__global__ __launch_bounds__(NT) void k_qr_step_wide(QrStep a, int32_t k) {
+  constexpr int NW = NT / 64;
+  const int c = blockIdx.y;
+  StepHead h;
+  if (!qr_head<NT>(a, k, c, h)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  __shared__ double s_a[2][NW], s_b[2][NW];
+  const double* nu = a.nu.at(c) + (k & 1) * (int64_t)a.cols;
+  double2* Am = a.A.at(c);
+  const double2* x = Am + (int64_t)h.piv * a.rows;
+  double2 xc[RPL];
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int i = k + tid + NT * t;
+    xc[t] = i < a.rows ? (i == k ? h.wk : x[i]) : make_double2(0.0, 0.0);
+  }
+  for (int q = 0; q < kWideCols; ++q) {
+    const int j = blockIdx.x * kWideCols + q;
+    if (j >= a.cols) break;
+    if (j == h.piv || nu[j] < 0.0) {
+      qr_retire(a, k, c, h, j, tid == 0, tid, NT);
+      continue;
+    }
+    double2* y = Am + (int64_t)j * a.rows;
+    double2 yc[RPL];
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int i = k + tid + NT * t;
+      yc[t] = i < a.rows ? y[i] : make_double2(0.0, 0.0);
+      const double2 v = cdotc(xc[t], yc[t]);
+      sr += v.x;
+      si += v.y;
+    }
+    sr = fwave_sum(sr);
+    si = fwave_sum(si);
+    const int b = q & 1;
+    if (lane == 0) {
+      s_a[b][wv] = sr;
+      s_b[b][wv] = si;
+    }
+    __syncthreads();
+    sr = 0.0;
+    si = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      sr += s_a[b][w];
+      si += s_b[b][w];
+    }
+    const double2 f = make_double2(h.om * sr, h.om * si);
+    double nn = 0.0;
+    double2 rk = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int i = k + tid + NT * t;
+      if (i < a.rows) {
+        const double2 fw = cmul(f, xc[t]);
+        const double2 v = make_double2(yc[t].x - fw.x, yc[t].y - fw.y);
+        y[i] = v;
+        if (i == k)
+          rk = v;
+        else
+          nn += v.x * v.x + v.y * v.y;
+      }
+    }
+    nn = fwave_sum(nn);
+    __syncthreads();  // every wavefront has read s_a[b] before it is written again
+    if (lane == 0) s_a[b][wv] = nn;
+    __syncthreads();
+    if (tid == 0) {  // thread 0 holds row k
+      double t2 = 0.0;
+      for (int w = 0; w < NW; ++w) t2 += s_a[b][w];
+      qr_store(a, k, c, j, rk, t2);
     }
   }
 }
@@ -741,10 +862,25 @@ RecWs rec_ws(int32_t m, int32_t n, int32_t kp) {
   return w;
 }
 
+// The steps of one QR over a batch: a wavefront per column up to 512 rows, else a
+// workgroup of 128 to 1024 threads per column (8 rows per thread; 16 above 8192 rows).
 int run_qr(const QrStep& q, int32_t batch, int32_t steps, hipStream_t s) {
+  if (q.rows > 16 * kBigThreads) return fail(UHM_EINVAL, "QR step: more than 16384 rows");
+  const dim3 gn((unsigned)((q.cols + kStepCols - 1) / kStepCols), (unsigned)batch);
+  const dim3 gw((unsigned)((q.cols + kWideCols - 1) / kWideCols), (unsigned)batch);
   for (int32_t k = 0; k <= steps; ++k) {
-    k_qr_step<<<dim3((unsigned)((q.cols + kStepCols - 1) / kStepCols), (unsigned)batch), dim3(kStepThreads), 0, s>>>(
-        q, k);
+    if (q.rows <= 64 * 8)
+      k_qr_step<8><<<gn, dim3(kStepThreads), 0, s>>>(q, k);
+    else if (q.rows <= 128 * 8)
+      k_qr_step_wide<128, 8><<<gw, dim3(128), 0, s>>>(q, k);
+    else if (q.rows <= 256 * 8)
+      k_qr_step_wide<256, 8><<<gw, dim3(256), 0, s>>>(q, k);
+    else if (q.rows <= 512 * 8)
+      k_qr_step_wide<512, 8><<<gw, dim3(512), 0, s>>>(q, k);
+    else if (q.rows <= 1024 * 8)
+      k_qr_step_wide<1024, 8><<<gw, dim3(1024), 0, s>>>(q, k);
+    else
+      k_qr_step_wide<1024, 16><<<gw, dim3(1024), 0, s>>>(q, k);
     UHM_HIP(hipGetLastError());
   }
   return UHM_OK;
