@@ -93,7 +93,8 @@ Arr<T> region(double* base, int64_t per, int64_t off) {
 }
 
 // Squared column norms of a rows x cols matrix (lda = rows) into nu's first buffer: one
-// wavefront per column, kStepCols columns per workgroup.
+// wavefront per column, kStepCols columns per workgroup.  A zero column is marked retired
+// (-1) at once: its R entries are zero and the QR steps leave it alone.
 __global__ __launch_bounds__(kStepThreads) void k_col_norms(CArr A, int32_t rows, int32_t cols, DArr nu) {
   const int c = blockIdx.y;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(kStepThreads) void k_col_norms(CArr A, int32_t rows
       s += v.x * v.x + v.y * v.y;
     }
     s = fwave_sum(s);
-    if (lane == 0) nm[j] = s;
+    if (lane == 0) nm[j] = s > 0.0 ? s : -1.0;
   }
 }
 
@@ -413,14 +414,16 @@ __global__ __launch_bounds__(256) void k_jacobi_init(CArr Va, int32_t P, IArr pp
   }
 }
 
-__global__ __launch_bounds__(64 * kJacWaves) void k_jacobi_round(CArr Ra, CArr Va, int32_t P, IArr pp, IArr sst,
-                                                                 int32_t r, double tol) {
+// Round r of the circle schedule over ns + (ns & 1) indices (ns >= every matrix's p; R and V
+// have leading dimension P).
+__global__ __launch_bounds__(64 * kJacWaves) void k_jacobi_round(CArr Ra, CArr Va, int32_t P, int32_t ns, IArr pp,
+                                                                 IArr sst, int32_t r, double tol) {
   const int c = blockIdx.y;
   int32_t* t = sst.at(c);
   if (!t[2]) return;
   const int lane = threadIdx.x & 63;
   const int q = blockIdx.x * kJacWaves + (threadIdx.x >> 6);
-  const int pq = P + (P & 1);
+  const int pq = ns + (ns & 1);
   if (q >= pq / 2) return;
   const int p = pp.at(c)[0];
   const int a0 = q == 0 ? 0 : (r + q - 1) % (pq - 1) + 1;
@@ -466,6 +469,12 @@ __global__ __launch_bounds__(64 * kJacWaves) void k_jacobi_round(CArr Ra, CArr V
   if (lane == 0) t[0] = 1;
 }
 
+// The largest value of v.at(c)[0] over the batch, into *out (set to 0 before).
+__global__ __launch_bounds__(256) void k_batch_max(IArr v, int32_t batch, int32_t* __restrict__ out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c < batch) atomicMax(out, v.at(c)[0]);
+}
+
 // End of a sweep: a matrix with no rotation in it has converged; the rest are counted.
 __global__ __launch_bounds__(256) void k_jacobi_sweep_end(IArr sst, int32_t batch, int32_t* __restrict__ active) {
   const int c = blockIdx.x * 256 + threadIdx.x;
@@ -481,18 +490,103 @@ __global__ __launch_bounds__(256) void k_jacobi_sweep_end(IArr sst, int32_t batc
   t[0] = 0;
 }
 
+// Orders up to 64: one workgroup per matrix keeps R and V in LDS (2 x 64 KB) through all
+// sweeps, the pairs of a round taken by its 8 wavefronts and the rounds separated by
+// barriers; the schedule is the same circle over p + (p & 1) indices.
+constexpr int kJacLds = 64;
+__global__ __launch_bounds__(512) void k_jacobi_lds(CArr Ra, CArr Va, int32_t P, IArr pp, IArr sst, double tol,
+                                                    int32_t max_sweeps) {
+  __shared__ double2 sR[kJacLds * kJacLds];
+  __shared__ double2 sV[kJacLds * kJacLds];
+  __shared__ int s_rot;
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int p = pp.at(c)[0];
+  double2* R = Ra.at(c);
+  double2* V = Va.at(c);
+  for (int q = tid; q < P * P; q += 512) {
+    const int r = q % P, col = q / P;
+    sR[r + col * kJacLds] = R[q];
+    sV[r + col * kJacLds] = make_double2(r == col && r < p ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  const int pq = p + (p & 1);
+  int sweep = 0;
+  bool conv = p < 2;
+  while (!conv && sweep < max_sweeps) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < pq - 1; ++r) {
+      for (int q = wv; q < pq / 2; q += 8) {
+        const int a0 = q == 0 ? 0 : (r + q - 1) % (pq - 1) + 1;
+        const int b0 = (r + (pq - 1 - q) - 1) % (pq - 1) + 1;
+        const int i = min(a0, b0), j = max(a0, b0);
+        if (j >= p) continue;
+        double2* ci = sR + i * kJacLds;
+        double2* cj = sR + j * kJacLds;
+        const double2 x = lane < p ? ci[lane] : make_double2(0.0, 0.0);
+        const double2 y = lane < p ? cj[lane] : make_double2(0.0, 0.0);
+        const double2 gg = cdotc(x, y);
+        const double al = fwave_sum(x.x * x.x + x.y * x.y);
+        const double be = fwave_sum(y.x * y.x + y.y * y.y);
+        const double gr = fwave_sum(gg.x), gi = fwave_sum(gg.y);
+        const double g = hypot(gr, gi);
+        if (!(al > 0.0 && be > 0.0 && g > tol * sqrt(al * be))) continue;
+        const double2 e = make_double2(gr / g, gi / g);
+        const double z = (be - al) / (2.0 * g);
+        const double tt = fabs(z) > 1e100 ? 0.5 / z : (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        const double2 se = make_double2(sn * e.x, sn * e.y);  // s e
+        if (lane < p) {
+          const double2 a1 = cdotc(se, y), b1 = cmul(se, x);
+          ci[lane] = make_double2(cs * x.x - a1.x, cs * x.y - a1.y);
+          cj[lane] = make_double2(b1.x + cs * y.x, b1.y + cs * y.y);
+          double2* vi = sV + i * kJacLds;
+          double2* vj = sV + j * kJacLds;
+          const double2 u = vi[lane], v = vj[lane];
+          const double2 a2 = cdotc(se, v), b2 = cmul(se, u);
+          vi[lane] = make_double2(cs * u.x - a2.x, cs * u.y - a2.y);
+          vj[lane] = make_double2(b2.x + cs * v.x, b2.y + cs * v.y);
+        }
+        if (lane == 0) s_rot = 1;
+      }
+      __syncthreads();
+    }
+    conv = s_rot == 0;
+    ++sweep;
+    __syncthreads();
+  }
+  for (int q = tid; q < P * P; q += 512) {
+    const int r = q % P, col = q / P;
+    R[q] = sR[r + col * kJacLds];
+    V[q] = sV[r + col * kJacLds];
+  }
+  if (tid == 0) {
+    int32_t* t = sst.at(c);
+    t[0] = 0;
+    t[1] = sweep;
+    t[2] = conv ? 0 : 1;
+  }
+}
+
 // The sweeps of one batch: one launch per round, and the count of running matrices read back
-// after each sweep.  active: one device int.
-int run_jacobi(CArr R, CArr V, int32_t P, IArr pp, IArr sst, int32_t batch, double tol, int32_t max_sweeps,
-               int32_t* active, hipStream_t s) {
-  const int64_t pq = P + (P & 1);
-  const unsigned gx = (unsigned)std::min<int64_t>((pq * pq + 255) / 256, 1024);
+// after each sweep (active: one device int); orders up to 64 in LDS, one launch in all.  ns:
+// the largest order in the batch (the round schedule's size); P: the leading dimension.
+int run_jacobi(CArr R, CArr V, int32_t P, int32_t ns, IArr pp, IArr sst, int32_t batch, double tol,
+               int32_t max_sweeps, int32_t* active, hipStream_t s) {
+  if (P <= kJacLds) {
+    k_jacobi_lds<<<dim3((unsigned)batch), dim3(512), 0, s>>>(R, V, P, pp, sst, tol, max_sweeps);
+    UHM_HIP(hipGetLastError());
+    return UHM_OK;
+  }
+  const int64_t pq = ns + (ns & 1);
+  const unsigned gx = (unsigned)std::min<int64_t>(((int64_t)P * P + 255) / 256, 1024);
   k_jacobi_init<<<dim3(gx, (unsigned)batch), dim3(256), 0, s>>>(V, P, pp, sst);
   UHM_HIP(hipGetLastError());
   const unsigned rx = (unsigned)((pq / 2 + kJacWaves - 1) / kJacWaves);
   for (int32_t sweep = 0; sweep < max_sweeps && pq >= 2; ++sweep) {
     for (int32_t r = 0; r < pq - 1; ++r) {
-      k_jacobi_round<<<dim3(rx, (unsigned)batch), dim3(64 * kJacWaves), 0, s>>>(R, V, P, pp, sst, r, tol);
+      k_jacobi_round<<<dim3(rx, (unsigned)batch), dim3(64 * kJacWaves), 0, s>>>(R, V, P, ns, pp, sst, r, tol);
       UHM_HIP(hipGetLastError());
     }
     UHM_HIP(hipMemsetAsync(active, 0, sizeof(int32_t), s));
@@ -939,14 +1033,25 @@ int uhm_cluster_basis(double* X, int32_t batch, int32_t m, int32_t n, int32_t pm
   UHM_HIP(hipGetLastError());
   const QrStep q1{Xa, m, n, nu, Wa, om, Ca, Cq, n, 1, 1, stA, inone, fro, kcap, tol * tol, 1};
   if ((rc = run_qr(q1, batch, kcap, s))) return rc;
-  // 2. QR of B^* (n x P, column-major in Cq): R2 (P x P, ld P)
-  k_col_norms<<<dim3((unsigned)((P + kStepCols - 1) / kStepCols), (unsigned)batch), dim3(kStepThreads), 0, s>>>(
-      Cq, n, P, nu);
+  // the batch's largest p sizes the steps of the QR of B^* and the Jacobi schedule
+  int32_t* dmax = reinterpret_cast<int32_t*>(work + ws.per * (int64_t)batch) + 1;
+  UHM_HIP(hipMemsetAsync(dmax, 0, sizeof(int32_t), s));
+  k_batch_max<<<dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s>>>(stA, batch, dmax);
   UHM_HIP(hipGetLastError());
-  const QrStep q2{Cq, n, P, nu, none, dnone, R2, none, 1, P, 0, stB, stA, dnone, P, 0.0, 0};
-  if ((rc = run_qr(q2, batch, P, s))) return rc;
+  int32_t pbat = 0;
+  UHM_HIP(hipMemcpyAsync(&pbat, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  UHM_HIP(hipStreamSynchronize(s));
+  if (pbat < 0 || pbat > P) return fail(UHM_EHIP, "uhm_cluster_basis: QR step count out of range");
+  // 2. QR of B^* (n x pbat: the columns beyond are zero in every matrix; column-major in Cq):
+  // R2 (ld P)
+  const int32_t pc = std::max(pbat, 1);
+  k_col_norms<<<dim3((unsigned)((pc + kStepCols - 1) / kStepCols), (unsigned)batch), dim3(kStepThreads), 0, s>>>(
+      Cq, n, pc, nu);
+  UHM_HIP(hipGetLastError());
+  const QrStep q2{Cq, n, pc, nu, none, dnone, R2, none, 1, P, 0, stB, stA, dnone, P, 0.0, 0};
+  if ((rc = run_qr(q2, batch, pbat, s))) return rc;
   // 3. one-sided Jacobi on R2, the rank rule, the kept columns of J orthonormalised (into R2)
-  if ((rc = run_jacobi(R2, Ja, P, stA, stS, batch, jacobi_tol(P), 60,
+  if ((rc = run_jacobi(R2, Ja, P, pbat, stA, stS, batch, jacobi_tol(P), 60,
                        reinterpret_cast<int32_t*>(work + ws.per * (int64_t)batch), s)))
     return rc;
   const Finish f{R2, P, stA, stS, ord, eps, fro, stA, m, n, sv, rank, psteps, stats, status};
@@ -1015,7 +1120,7 @@ int uhm_block_recompress(double* X, double* Y, int32_t batch, int32_t m, int32_t
   k_rr<<<dim3((unsigned)((kp + 15) / 16), (unsigned)((kp + 15) / 16), (unsigned)batch), dim3(256), 0, s>>>(RY, RX, kp,
                                                                                                          Ma);
   UHM_HIP(hipGetLastError());
-  if ((rc = run_jacobi(Ma, Ja, kp, stX, stS, batch, jacobi_tol(kp), 60,
+  if ((rc = run_jacobi(Ma, Ja, kp, kp, stX, stS, batch, jacobi_tol(kp), 60,
                        reinterpret_cast<int32_t*>(work + ws.per * (int64_t)batch), s)))
     return rc;
   const Finish f{Ma, kp, stX, stS, ord, eps, dnone, inone, m, n, sv, rank, nullptr, nullptr, status};
