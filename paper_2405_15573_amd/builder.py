@@ -710,27 +710,44 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
     SY_off = np.concatenate([[0], np.cumsum(ysz)[:-1]]).astype(np.int64)[:nadm]
     SX = np.empty(int(xsz.sum()), np.complex128)
     SY = np.empty(int(ysz.sum()), np.complex128)
-    for b in range(nadm):
-        t, s = int(adm[b, 0]), int(adm[b, 1])
-        sb = fac_s[(min(t, s), max(t, s))]
-        Xf = Lmat[(t, s)] / sb[None, :]
-        Yf = np.conj(Lmat[(s, t)])
-        S[S_off[b]:S_off[b] + sizes[b]] = (Xf @ Lmat[(s, t)].T).ravel(order="F")
-        SX[SX_off[b]:SX_off[b] + xsz[b]] = Xf.ravel(order="F")
-        SY[SY_off[b]:SY_off[b] + ysz[b]] = Yf.ravel(order="F")
+    lt_of, ls_of = rank[adm[:, 0]], rank[adm[:, 1]]
+
+    def couple(bs):
+        """Blocks bs written straight into their column-major places (disjoint slices; numpy
+        drops the GIL in the copies, so the thread pool also spreads the first-touch faults of
+        the fresh arrays)."""
+        for b in bs:
+            t, s = int(adm[b, 0]), int(adm[b, 1])
+            sb = fac_s[(min(t, s), max(t, s))]
+            lt, ls, kb = int(lt_of[b]), int(ls_of[b]), int(adm_rank[b])
+            Xf = SX[SX_off[b]:SX_off[b] + xsz[b]].reshape(kb, lt).T
+            np.divide(Lmat[(t, s)], sb[None, :], out=Xf)
+            np.conjugate(Lmat[(s, t)], out=SY[SY_off[b]:SY_off[b] + ysz[b]].reshape(kb, ls).T)
+            S[S_off[b]:S_off[b] + sizes[b]].reshape(ls, lt).T[...] = Xf @ Lmat[(s, t)].T
+
+    _pmap(couple, np.array_split(np.arange(nadm), max(1, min(nadm, 8 * _workers()))))
     tim["couplings"] = time.perf_counter() - t3
     if verbose:
         print(f"  couplings {tim['couplings']:.1f} s", file=sys.stderr, flush=True)
 
     # ---- bases (V = conj(U) by symmetry), H factors
+    t5 = time.perf_counter()
     U_off = np.full(nc, -1, np.int64)
     usz = size * rank
     has = rank > 0
     U_off[has] = np.concatenate([[0], np.cumsum(usz[has])[:-1]]) if has.any() else []
     U = np.empty(int(usz.sum()), np.complex128)
-    for t, Ut in Ubasis.items():
-        U[U_off[t]:U_off[t] + usz[t]] = Ut.ravel(order="F")
-    V = np.conj(U)
+    V = np.empty_like(U)
+
+    def bases(ts):
+        for t in ts:
+            t = int(t)
+            u = U[U_off[t]:U_off[t] + usz[t]]
+            u.reshape(int(rank[t]), int(size[t])).T[...] = Ubasis[t]
+            np.conjugate(u, out=V[U_off[t]:U_off[t] + usz[t]])
+
+    with_basis = np.array(sorted(Ubasis), dtype=np.int64)
+    _pmap(bases, np.array_split(with_basis, max(1, min(len(with_basis), 8 * _workers()))))
 
     xs = size[adm[:, 0]] * adm_rank
     ys = size[adm[:, 1]] * adm_rank
@@ -738,12 +755,26 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
     Y_off = np.concatenate([[0], np.cumsum(ys)[:-1]]).astype(np.int64)[:nadm]
     Xh = np.empty(int(xs.sum()), np.complex128)
     Yh = np.empty(int(ys.sum()), np.complex128)
-    for b in range(nadm):
-        t, s = int(adm[b, 0]), int(adm[b, 1])
-        Ub, sb, Vb = block_factors(t, s)
-        Xh[X_off[b]:X_off[b] + xs[b]] = (Ub * sb[None, :]).ravel(order="F")
-        Yh[Y_off[b]:Y_off[b] + ys[b]] = Vb.ravel(order="F")
+
+    def h_factors(bs):
+        for b in bs:
+            t, s = int(adm[b, 0]), int(adm[b, 1])
+            kb = int(adm_rank[b])
+            xd = Xh[X_off[b]:X_off[b] + xs[b]].reshape(kb, int(size[t])).T
+            yd = Yh[Y_off[b]:Y_off[b] + ys[b]].reshape(kb, int(size[s])).T
+            if t < s:
+                sb = fac_s[(t, s)]
+                np.multiply(fac_U[(t, s)], sb[None, :], out=xd)
+                yd[...] = fac_V[(t, s)]
+            else:   # the mirror of block (s, t): U_b = conj(V), V_b = conj(U)
+                sb = fac_s[(s, t)]
+                np.conjugate(fac_V[(s, t)], out=xd)
+                xd *= sb[None, :]
+                np.conjugate(fac_U[(s, t)], out=yd)
+
+    _pmap(h_factors, np.array_split(np.arange(nadm), max(1, min(nadm, 8 * _workers()))))
     del fac_U, fac_V, Lmat
+    tim["factors"] = time.perf_counter() - t5
 
     # ---- dense near field
     t4 = time.perf_counter()
