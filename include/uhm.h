@@ -510,6 +510,37 @@ int uhm_block_recompress(double* X, double* Y, int32_t batch, int32_t m, int32_t
 /* Workspace of uhm_block_recompress in doubles, or -1 for sizes it rejects outright. */
 int64_t uhm_block_recompress_work(int32_t batch, int32_t m, int32_t n, int32_t kp);
 
+/* One admissible block b = (tau, sigma) for uhm_couplings; offsets count complex elements
+ * (sig_off: doubles). */
+typedef struct uhm_coupling_desc {
+  int64_t a_off;   /* L_{tau,b}: L[a_off + q*lt + i] = (U_tau^* X_b)[i][q], i < lt, q < kb */
+  int64_t b_off;   /* L_{sigma,b}: L[b_off + q*ls + j], the mirrored block's rows */
+  int64_t sig_off; /* sigma_b: sigma[sig_off + q], q < kb (all > 0) */
+  int64_t s_off;   /* S_b, lt x ls column-major, at S + s_off */
+  int64_t x_off;   /* S_{X,b}, lt x kb column-major, at SX + x_off */
+  int64_t y_off;   /* S_{Y,b}, ls x kb column-major, at SY + y_off */
+  int32_t lt;      /* l_tau >= 1 */
+  int32_t ls;      /* l_sigma >= 1 */
+  int32_t kb;      /* the block's rank k_b >= 1 */
+  int32_t reserved; /* 0 */
+} uhm_coupling_desc;
+
+/*
+ * The couplings of the construction (section 4.1; factored form, section 4.2) for every
+ * block of `blocks`: with L_{tau,b} = U_tau^* U_b Sigma_b (lt x kb, the rows of Alg. 2's
+ * Sigma V^* that belong to block b) and L_{sigma,b} the same for the mirrored block,
+ *   S_{X,b} = L_{tau,b} Sigma_b^{-1},  S_{Y,b} = conj(L_{sigma,b}),  S_b = S_{X,b} L_{sigma,b}^T,
+ * so that S_b = U_tau^* A|_b V_sigma for the block's factors.  L, sigma, blocks, S, SX, SY and
+ * status are device arrays (lengths in complex elements, sigma_len in doubles); status[b] =
+ * 1 for a block written, -1 for a descriptor whose sizes or ranges do not fit the lengths
+ * (nothing written for it).  One workgroup per block; nothing is allocated; asynchronous
+ * on hip_stream.  Errors: UHM_EINVAL (negative lengths, null pointers with nblocks > 0),
+ * UHM_EHIP.
+ */
+int uhm_couplings(const double* L, int64_t L_len, const double* sigma, int64_t sigma_len,
+                  const uhm_coupling_desc* blocks, int64_t nblocks, double* S, int64_t S_len, double* SX, int64_t SX_len,
+                  double* SY, int64_t SY_len, int32_t* status, void* hip_stream);
+
 const char* uhm_strerror(int code);
 const char* uhm_last_error(void);
 int uhm_version(void);

@@ -72,6 +72,17 @@ BLOCK_DTYPE = np.dtype({"names": [f for f, _ in BlockDesc._fields_],
                         "offsets": [getattr(BlockDesc, f).offset for f, _ in BlockDesc._fields_],
                         "itemsize": ctypes.sizeof(BlockDesc)})
 
+
+class CouplingDesc(ctypes.Structure):
+    _fields_ = [("a_off", I64), ("b_off", I64), ("sig_off", I64), ("s_off", I64), ("x_off", I64), ("y_off", I64),
+                ("lt", I32), ("ls", I32), ("kb", I32), ("reserved", I32)]
+
+
+COUPLING_DTYPE = np.dtype({"names": [f for f, _ in CouplingDesc._fields_],
+                           "formats": [np.int64 if t is I64 else np.int32 for _, t in CouplingDesc._fields_],
+                           "offsets": [getattr(CouplingDesc, f).offset for f, _ in CouplingDesc._fields_],
+                           "itemsize": ctypes.sizeof(CouplingDesc)})
+
 KRYLOV_DONE, KRYLOV_PRODUCT_HIGH, KRYLOV_PRODUCT_LOW = 0, 1, 2
 
 EXPORTS = ("uhm_upload", "uhm_upload_h", "uhm_matvec", "uhm_matvec_noalloc", "uhm_solve_gmres", "uhm_krylov_create", "uhm_krylov_next",
@@ -80,7 +91,7 @@ EXPORTS = ("uhm_upload", "uhm_upload_h", "uhm_matvec", "uhm_matvec_noalloc", "uh
            "uhm_batch_tune", "uhm_batch_capture", "uhm_batch_free", "uhm_op_info_get", "uhm_set_timing",
            "uhm_kernel_times", "uhm_free", "uhm_strerror", "uhm_last_error", "uhm_version",
            "uhm_kernel_blocks", "uhm_aca", "uhm_aca_pack", "uhm_cluster_basis", "uhm_cluster_basis_work",
-           "uhm_block_recompress", "uhm_block_recompress_work")
+           "uhm_block_recompress", "uhm_block_recompress_work", "uhm_couplings")
 
 _LIB = None
 
@@ -157,6 +168,8 @@ def load_library(path: str = LIB_PATH):
     lib.uhm_block_recompress.restype = ctypes.c_int
     lib.uhm_block_recompress_work.argtypes = [I32, I32, I32, I32]
     lib.uhm_block_recompress_work.restype = I64
+    lib.uhm_couplings.argtypes = [P, I64, P, I64, P, I64, P, I64, P, I64, P, I64, P, P]
+    lib.uhm_couplings.restype = ctypes.c_int
     _LIB = lib
     return lib
 
@@ -746,4 +759,32 @@ def block_recompress(X, Y, eps: float, stream=None):
         stt = status.cpu().numpy()[:batch]
         del Xd, Yd, work
     return U, V, sv, rk, stt
+
+
+def couplings(L, sigma, desc, S_len: int, SX_len: int, SY_len: int, stream=None):
+    """The couplings S_b, S_{X,b}, S_{Y,b} of every block in desc (a COUPLING_DTYPE record array)
+    on the device (uhm_couplings).  L: complex128 device tensor of the clusters' coefficient
+    rows, sigma: float64 (host or device).  Returns flat complex128 device tensors S, SX, SY."""
+    import torch
+    lib = load_library()
+    desc = np.ascontiguousarray(desc, dtype=COUPLING_DTYPE)
+    nb = int(desc.shape[0])
+    h, stream = _stream_handle(stream)
+    with torch.cuda.stream(stream):
+        sig = torch.as_tensor(sigma).to(device="cuda", dtype=torch.float64).contiguous()
+        S = torch.empty(max(1, S_len), dtype=torch.complex128, device="cuda")
+        SX = torch.empty(max(1, SX_len), dtype=torch.complex128, device="cuda")
+        SY = torch.empty(max(1, SY_len), dtype=torch.complex128, device="cuda")
+        status = torch.zeros(max(1, nb), dtype=torch.int32, device="cuda")
+        dd = torch.from_numpy(desc.view(np.uint8)).to("cuda") if nb else torch.empty(1, dtype=torch.uint8,
+                                                                                      device="cuda")
+        _check(lib.uhm_couplings(ctypes.c_void_p(L.data_ptr()), int(L.numel()), ctypes.c_void_p(sig.data_ptr()),
+                                 int(sig.numel()), ctypes.c_void_p(dd.data_ptr()), nb, ctypes.c_void_p(S.data_ptr()),
+                                 int(S_len), ctypes.c_void_p(SX.data_ptr()), int(SX_len),
+                                 ctypes.c_void_p(SY.data_ptr()), int(SY_len), ctypes.c_void_p(status.data_ptr()), h),
+               "uhm_couplings")
+        st = status.cpu().numpy()[:nb]
+    if (st != 1).any():
+        raise UhmError(UHM_EINVAL, f"uhm_couplings: {int((st != 1).sum())} descriptors rejected")
+    return S, SX, SY
 

@@ -305,6 +305,21 @@ def _to_host(t):
     return h.numpy()
 
 
+def _copy_into(dst, src, step=1 << 26):
+    """The flat device tensor src into the flat host array dst, through one page-locked
+    staging buffer of at most `step` elements and torch's threaded host copy."""
+    import torch
+    n = int(dst.size)
+    if n == 0:
+        return
+    buf = torch.empty(min(n, step), dtype=src.dtype, pin_memory=True)
+    d = torch.from_numpy(dst)
+    for a in range(0, n, step):
+        b = min(n, a + step)
+        buf[:b - a].copy_(src[a:b])
+        d[a:b].copy_(buf[:b - a])
+
+
 def _to_host_copy(t):
     """As _to_host, then copied into pageable memory by torch's threaded host copy, so the
     page-locked block goes back to torch's cache for the next transfer (results that the
@@ -635,21 +650,21 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
                 bad = set(np.nonzero(res.status != 0)[0].tolist())
                 lmax = int(res.rank.max())
                 Uh = _to_host_copy(res.U[:, :lmax, :].contiguous())
-                SVh = _to_host_copy(res.SV[:, :, :lmax].contiguous())
+                # Sigma V^* stays on the device for the couplings: per cluster (ks x l) at [c, :ks, :l]
+                dev_L.append(([t for t, _ in part], [ks for _, ks in part], res.rank.copy(), bad,
+                              res.SV[:, :, :lmax].contiguous()))
                 del res.U, res.SV, res.sv, buf
                 for c, (t, ks) in enumerate(part):
                     if c in bad:
                         continue
                     l = int(res.rank[c])
-                    SV = SVh[c, :, :l].T   # views into the copied batch, no further copies
-                    out.append((t, l, Uh[c, :l, :].T, float(res.stats[c, 1]), float(res.stats[c, 0]),
-                                [(s, SV[:, j:j + kb]) for s, j, kb in cols[c]]))
+                    out.append((t, l, Uh[c, :l, :].T, float(res.stats[c, 1]), float(res.stats[c, 0]), []))
                 td = time.perf_counter()
                 if bad:
                     fallback += len(bad)
                     out.extend(compress([part[c] for c in sorted(bad)]))
                 te = time.perf_counter()
-                del Uh, SVh
+                del Uh
                 tw["compress_fill_wait"] += tb - ta
                 tw["compress_gpu"] += tc - tb
                 tw["compress_post"] += td - tc
@@ -669,6 +684,7 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
                       f"host {hp:.2f} s", file=sys.stderr, flush=True)
         return [out]
 
+    dev_L = []   # per GPU chunk: (clusters, their column counts, ranks, flagged, Sigma V^* on the device)
     jobs = []
     if factor == "gpu":
         for nt, members in groups.items():
@@ -681,8 +697,11 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
             kp_all = max(k for _, k in members)
             jobs.extend(_chunks(members, 16 * nt * kp_all * 3, parts=2 * _workers()))
         results = _pmap(compress, jobs)
+    host_L = {}   # GPU mode: Sigma V^* (l x ks) of the clusters the host factorised
     for res in results:
         for t, l, Ut, dropped, tail, Ls in res:
+            if factor == "gpu" and Ls:
+                host_L[t] = np.concatenate([Lb for _, Lb in Ls], axis=1)
             rank[t] = l
             Ubasis[t] = Ut
             sv_dropped[t] = dropped
@@ -712,6 +731,59 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
     SY = np.empty(int(ysz.sum()), np.complex128)
     lt_of, ls_of = rank[adm[:, 0]], rank[adm[:, 1]]
 
+    def couplings_gpu():
+        """All couplings on the GPU (uhm_couplings) from the clusters' Sigma V^* rows, which the
+        GPU factorisation left on the device (the host factorisation's, for flagged clusters,
+        are uploaded); S, S_X and S_Y come back through page-locked staging."""
+        import torch
+        from . import binding
+        ks_of = np.zeros(nc, np.int64)
+        for members in groups.values():
+            for t, ks in members:
+                ks_of[t] = ks
+        lsz = ks_of * rank.astype(np.int64)
+        L_off = np.concatenate([[0], np.cumsum(lsz)[:-1]]).astype(np.int64)
+        Lbuf = torch.empty(max(1, int(lsz.sum())), dtype=torch.complex128, device="cuda")
+        for clist, kslist, rk, bad, SVd in dev_L:
+            for c, t in enumerate(clist):
+                if c in bad:
+                    continue
+                ks, l = int(kslist[c]), int(rank[t])
+                Lbuf[L_off[t]:L_off[t] + ks * l].view(ks, l).copy_(SVd[c, :ks, :l])
+        dev_L.clear()
+        for t, Lh in host_L.items():
+            ks, l = int(ks_of[t]), int(rank[t])
+            Lbuf[L_off[t]:L_off[t] + ks * l].view(ks, l).copy_(torch.from_numpy(np.ascontiguousarray(Lh.T)))
+        # j: the first column of block b in its row cluster's agglomeration (row_blocks order,
+        # which is the order of adm); the mirrored block by its key
+        order = np.argsort(adm[:, 0], kind="stable")
+        rk_s = adm_rank[order].astype(np.int64)
+        rows_s = adm[order, 0]
+        csum = np.cumsum(rk_s) - rk_s
+        first = np.r_[True, rows_s[1:] != rows_s[:-1]] if nadm else np.zeros(0, bool)
+        start = np.maximum.accumulate(np.where(first, np.arange(nadm), 0)) if nadm else np.zeros(0, np.int64)
+        j_of = np.empty(nadm, np.int64)
+        j_of[order] = csum - csum[start]
+        key = adm[:, 0].astype(np.int64) * nc + adm[:, 1]
+        mkey = adm[:, 1].astype(np.int64) * nc + adm[:, 0]
+        ko = np.argsort(key)
+        mirror = ko[np.searchsorted(key[ko], mkey)]
+        if not np.array_equal(key[mirror], mkey):
+            raise RuntimeError("a block without its mirror")
+        sig = np.concatenate([fac_s[(min(int(t), int(s)), max(int(t), int(s)))] for t, s in adm]) if nadm \
+            else np.zeros(1)
+        desc = np.zeros(nadm, binding.COUPLING_DTYPE)
+        t_, s_ = adm[:, 0].astype(np.int64), adm[:, 1].astype(np.int64)
+        desc["a_off"] = L_off[t_] + j_of * rank[t_]
+        desc["b_off"] = L_off[s_] + j_of[mirror] * rank[s_]
+        desc["sig_off"] = np.cumsum(adm_rank.astype(np.int64)) - adm_rank
+        desc["s_off"], desc["x_off"], desc["y_off"] = S_off, SX_off, SY_off
+        desc["lt"], desc["ls"], desc["kb"] = rank[t_], rank[s_], adm_rank
+        Sd, SXd, SYd = binding.couplings(Lbuf, sig, desc, S.size, SX.size, SY.size)
+        del Lbuf
+        for dst, src in ((S, Sd), (SX, SXd), (SY, SYd)):
+            _copy_into(dst, src)
+
     def couple(bs):
         """Blocks bs written straight into their column-major places (disjoint slices; numpy
         drops the GIL in the copies, so the thread pool also spreads the first-touch faults of
@@ -725,7 +797,10 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
             np.conjugate(Lmat[(s, t)], out=SY[SY_off[b]:SY_off[b] + ysz[b]].reshape(kb, ls).T)
             S[S_off[b]:S_off[b] + sizes[b]].reshape(ls, lt).T[...] = Xf @ Lmat[(s, t)].T
 
-    _pmap(couple, np.array_split(np.arange(nadm), max(1, min(nadm, 8 * _workers()))))
+    if factor == "gpu":
+        couplings_gpu()
+    else:
+        _pmap(couple, np.array_split(np.arange(nadm), max(1, min(nadm, 8 * _workers()))))
     tim["couplings"] = time.perf_counter() - t3
     if verbose:
         print(f"  couplings {tim['couplings']:.1f} s", file=sys.stderr, flush=True)

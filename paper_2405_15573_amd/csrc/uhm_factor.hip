@@ -908,6 +908,52 @@ __global__ __launch_bounds__(256) void k_rr(CArr RYa, CArr RXa, int32_t kp, CArr
   Ma.at(c)[i + (int64_t)j * kp] = make_double2(ar, ai);
 }
 
+// The couplings of the construction, one workgroup per admissible block b = (tau, sigma):
+// S_{X,b} = L_{tau,b} Sigma_b^{-1} (l_tau x k_b), S_{Y,b} = conj(L_{sigma,b}) (l_sigma x k_b) and
+// S_b = S_{X,b} L_{sigma,b}^T (l_tau x l_sigma), all column-major.  L_{tau,b}[i][q] =
+// L[a_off + q l_tau + i] (the k_b rows of cluster tau's coefficient block that belong to b).
+// Consecutive threads take consecutive rows, so the reads of a column are contiguous.
+constexpr int kCoupThreads = 256;
+__global__ __launch_bounds__(kCoupThreads) void k_couplings(const double2* __restrict__ L, int64_t L_len,
+                                                            const double* __restrict__ sig, int64_t sig_len,
+                                                            const uhm_coupling_desc* __restrict__ desc,
+                                                            int64_t nblocks, double2* __restrict__ S, int64_t S_len,
+                                                            double2* __restrict__ SX, int64_t SX_len,
+                                                            double2* __restrict__ SY, int64_t SY_len,
+                                                            int32_t* __restrict__ status) {
+  const int64_t b = blockIdx.x;
+  if (b >= nblocks) return;
+  const uhm_coupling_desc d = desc[b];
+  const int64_t lt = d.lt, ls = d.ls, kb = d.kb;
+  const bool ok = lt >= 1 && ls >= 1 && kb >= 1 && d.a_off >= 0 && d.a_off + kb * lt <= L_len && d.b_off >= 0 &&
+                  d.b_off + kb * ls <= L_len && d.sig_off >= 0 && d.sig_off + kb <= sig_len && d.s_off >= 0 &&
+                  d.s_off + lt * ls <= S_len && d.x_off >= 0 && d.x_off + lt * kb <= SX_len && d.y_off >= 0 &&
+                  d.y_off + ls * kb <= SY_len;
+  if (threadIdx.x == 0) status[b] = ok ? 1 : -1;
+  if (!ok) return;
+  const double2* A = L + d.a_off;
+  const double2* B = L + d.b_off;
+  const double* sg = sig + d.sig_off;
+  for (int64_t e = threadIdx.x; e < lt * kb; e += kCoupThreads) {
+    const int64_t q = e / lt;
+    const double inv = 1.0 / sg[q];
+    const double2 a = A[e];
+    SX[d.x_off + e] = make_double2(a.x * inv, a.y * inv);
+  }
+  for (int64_t e = threadIdx.x; e < ls * kb; e += kCoupThreads) SY[d.y_off + e] = cconj(B[e]);
+  for (int64_t e = threadIdx.x; e < lt * ls; e += kCoupThreads) {
+    const int64_t i = e % lt, j = e / lt;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t q = 0; q < kb; ++q) {
+      const double2 x = A[q * lt + i], y = B[q * ls + j];
+      const double inv = 1.0 / sg[q];
+      ar += (x.x * y.x - x.y * y.y) * inv;
+      ai += (x.x * y.y + x.y * y.x) * inv;
+    }
+    S[d.s_off + e] = make_double2(ar, ai);
+  }
+}
+
 // Per-matrix workspace of the cluster factorisation (offsets in doubles).
 struct ClusterWs {
   int64_t per, o_w, o_om, o_c, o_cq, o_r2, o_j, o_nu, o_ord, o_st;
@@ -1136,6 +1182,22 @@ int uhm_block_recompress(double* X, double* Y, int32_t batch, int32_t m, int32_t
   if ((rc = launch_apply(au, kp, batch, s))) return rc;
   const Apply av{WY, omy, n, stY, QW, kp, stX, stS, CArr{reinterpret_cast<double2*>(V), (int64_t)n * kp}};
   if ((rc = launch_apply(av, kp, batch, s))) return rc;
+  return UHM_OK;
+}
+
+int uhm_couplings(const double* L, int64_t L_len, const double* sigma, int64_t sigma_len,
+                  const uhm_coupling_desc* blocks, int64_t nblocks, double* S, int64_t S_len, double* SX, int64_t SX_len,
+                  double* SY, int64_t SY_len, int32_t* status, void* hip_stream) {
+  if (L_len < 0 || sigma_len < 0 || nblocks < 0 || S_len < 0 || SX_len < 0 || SY_len < 0)
+    return fail(UHM_EINVAL, "uhm_couplings: negative size");
+  if (nblocks == 0) return UHM_OK;
+  if (!L || !sigma || !blocks || !S || !SX || !SY || !status) return fail(UHM_EINVAL, "uhm_couplings: null pointer");
+  if (nblocks > INT32_MAX) return fail(UHM_EINVAL, "uhm_couplings: too many blocks for one launch");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  k_couplings<<<dim3((unsigned)nblocks), dim3(kCoupThreads), 0, s>>>(
+      reinterpret_cast<const double2*>(L), L_len, sigma, sigma_len, blocks, nblocks, reinterpret_cast<double2*>(S),
+      S_len, reinterpret_cast<double2*>(SX), SX_len, reinterpret_cast<double2*>(SY), SY_len, status);
+  UHM_HIP(hipGetLastError());
   return UHM_OK;
 }
 

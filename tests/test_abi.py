@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 STRUCTS = (("uhm_host_operator", binding.HostOperator), ("uhm_host_hmatrix", binding.HostHMatrix),
            ("uhm_op_info", binding.OpInfo), ("uhm_gmres_opts", binding.GmresOpts), ("uhm_gmres_info", binding.GmresInfo),
-           ("uhm_block_desc", binding.BlockDesc))
+           ("uhm_block_desc", binding.BlockDesc), ("uhm_coupling_desc", binding.CouplingDesc))
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -58,9 +58,10 @@ def test_struct_layouts_match_header(tmp_path):
 
 def test_block_record_matches_struct():
     import ctypes
-    assert binding.BLOCK_DTYPE.itemsize == ctypes.sizeof(binding.BlockDesc)
-    for f, _ in binding.BlockDesc._fields_:
-        assert binding.BLOCK_DTYPE.fields[f][1] == getattr(binding.BlockDesc, f).offset
+    for dt, st in ((binding.BLOCK_DTYPE, binding.BlockDesc), (binding.COUPLING_DTYPE, binding.CouplingDesc)):
+        assert dt.itemsize == ctypes.sizeof(st)
+        for f, _ in st._fields_:
+            assert dt.fields[f][1] == getattr(st, f).offset
 
 
 def test_construction_entry_points_validate_before_any_device_work():

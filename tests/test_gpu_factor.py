@@ -243,3 +243,33 @@ def test_recompression_degenerate_blocks():
     u, v = U.cpu().numpy()[1, 0], V.cpu().numpy()[1, 0]
     assert np.linalg.norm(np.outer(u * sv[1, 0], v.conj()) - X[1] @ Y[1].conj().T) <= 1e-13 * sv[1, 0]
 
+
+
+def test_couplings_against_their_formulas():
+    """uhm_couplings: S_X = L_t Sigma^{-1}, S_Y = conj(L_s), S = S_X L_s^T for blocks reading
+    shared coefficient rows at arbitrary offsets; a descriptor outside the buffers is rejected."""
+    import torch
+    b = _binding()
+    rng = np.random.default_rng(4)
+    L = rng.standard_normal(5000) + 1j * rng.standard_normal(5000)
+    sig = rng.uniform(0.5, 2.0, 200)
+    shapes = [(7, 5, 3), (1, 1, 1), (30, 12, 9), (16, 16, 16)]
+    desc = np.zeros(len(shapes), b.COUPLING_DTYPE)
+    so = xo = yo = 0
+    for q, (lt, ls, kb) in enumerate(shapes):
+        desc[q] = (37 * q + 11, 900 + 53 * q, 17 * q, so, xo, yo, lt, ls, kb, 0)
+        so, xo, yo = so + lt * ls, xo + lt * kb, yo + ls * kb
+    Ld = torch.from_numpy(L).to("cuda")
+    S, SX, SY = (t.cpu().numpy() for t in b.couplings(Ld, sig, desc, so, xo, yo))
+    for d in desc:
+        lt, ls, kb = int(d["lt"]), int(d["ls"]), int(d["kb"])
+        A = L[d["a_off"]:d["a_off"] + kb * lt].reshape(kb, lt).T
+        B = L[d["b_off"]:d["b_off"] + kb * ls].reshape(kb, ls).T
+        sx = A / sig[d["sig_off"]:d["sig_off"] + kb][None, :]
+        assert np.allclose(SX[d["x_off"]:d["x_off"] + lt * kb].reshape(kb, lt).T, sx, rtol=1e-15, atol=0)
+        assert np.array_equal(SY[d["y_off"]:d["y_off"] + ls * kb].reshape(kb, ls).T, np.conj(B))
+        assert np.allclose(S[d["s_off"]:d["s_off"] + lt * ls].reshape(ls, lt).T, sx @ B.T, rtol=1e-13, atol=1e-13)
+    bad = desc.copy()
+    bad[2]["a_off"] = 5000 - 10   # runs past the end of L
+    with pytest.raises(b.UhmError):
+        b.couplings(Ld, sig, bad, so, xo, yo)
