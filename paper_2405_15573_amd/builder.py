@@ -506,8 +506,9 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
                     print(f"    recompression of {len(part)} blocks {m} x {n}, kp {kp}: GPU {tq1 - tq:.2f} s, "
                           f"host {time.perf_counter() - tq1:.2f} s", file=sys.stderr, flush=True)
                 if bad.size:   # Jacobi not converged: the host SVD for those blocks
-                    for key, Ub, Vb, sb in recompress_xy([part[c] for c in bad], X[a:a + step][bad].cpu().numpy(),
-                                                         Y[a:a + step][bad].cpu().numpy()):
+                    bi = torch.as_tensor(bad, device=X.device)
+                    for key, Ub, Vb, sb in recompress_xy([part[c] for c in bad], X[a:a + step][bi].cpu().numpy(),
+                                                         Y[a:a + step][bi].cpu().numpy()):
                         fac_U[key], fac_V[key], fac_s[key] = Ub, Vb, sb
                     tim["recompress_host_fallback"] = tim.get("recompress_host_fallback", 0) + int(bad.size)
 

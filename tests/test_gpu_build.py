@@ -199,6 +199,40 @@ def test_gpu_factorised_operator_meets_the_builder_pins(torch_dev):
         check((cloud, g))
 
 
+def test_gpu_factorisation_fallbacks(torch_dev, monkeypatch):
+    """Clusters the GPU flags (step cap before the tolerance) and blocks whose Jacobi did not
+    converge are taken by the host SVD; the flagged clusters' coefficient rows then reach
+    the GPU couplings from the host.  Forced here by capping every cluster batch at 8 QR
+    steps and flagging every third recompressed block: the operator still equals the host
+    build's."""
+    from paper_2405_15573_amd import binding
+    real_basis, real_rec = binding.cluster_basis, binding.block_recompress
+
+    def capped_basis(X, eps, tol=None, pmax=None, stream=None):
+        return real_basis(X, eps, tol=tol, pmax=min(8, pmax or 8), stream=stream)
+
+    def flagged_rec(X, Y, eps, stream=None):
+        U, V, sv, rk, st = real_rec(X, Y, eps, stream=stream)
+        st = st.copy()
+        st[::3] = 2
+        return U, V, sv, rk, st
+
+    monkeypatch.setattr(binding, "cluster_basis", capped_basis)
+    monkeypatch.setattr(binding, "block_recompress", flagged_rec)
+    cloud = inputs.make_cloud("sphere", 2048, seed=0)
+    print(f"case builder factor=gpu with forced fallbacks n={cloud.n}", flush=True)
+    g = builder.build_operator(cloud, leaf=32, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="gpu")
+    monkeypatch.setattr(binding, "cluster_basis", real_basis)
+    monkeypatch.setattr(binding, "block_recompress", real_rec)
+    h = builder.build_operator(cloud, leaf=32, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="host", factor="host")
+    assert g.timings["compress_host_fallback"] > 0 and g.timings["recompress_host_fallback"] > 0
+    assert np.array_equal(g.rank_row, h.rank_row) and np.array_equal(g.adm_rank, h.adm_rank)
+    x = inputs.make_rhs(cloud.n, 2, seed=1)
+    assert rel(uniform.uh_mvp(vars(g), x), uniform.uh_mvp(vars(h), x)) <= 1e-9
+    import test_builder as tb
+    tb.test_couplings_are_optimal((cloud, g))
+
+
 def test_aca_pack_layout(torch_dev):
     """uhm_aca_pack against the ACA result read block by block (AcaResult.factors): for a
     selection of blocks of one shape, X[c] = [u_0 .. u_{k-1} 0 ..] and Y[c] = conj of the v
