@@ -305,6 +305,11 @@ def _to_host(t):
     return h.numpy()
 
 
+# the largest cluster or block side the GPU factorisations take (uhm_cluster_basis,
+# uhm_block_recompress); larger ones are factorised on the host
+_GPU_MAX_ROWS = 16384
+
+
 def _copy_into(dst, src, step=1 << 26):
     """The flat device tensor src into the flat host array dst, through one page-locked
     staging buffer of at most `step` elements and torch's threaded host copy."""
@@ -516,7 +521,11 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
             jobs = []
             if handle is None and factor == "gpu":
                 for sel, m, n, X, Y in gpu_groups:
-                    recompress_dev(sel, X, Y)
+                    if max(m, n) > _GPU_MAX_ROWS:   # beyond the GPU kernels' row limit: the host SVD
+                        for key, Ub, Vb, sb in recompress_xy(sel, _to_host(X), _to_host(Y)):
+                            fac_U[key], fac_V[key], fac_s[key] = Ub, Vb, sb
+                    else:
+                        recompress_dev(sel, X, Y)
                 del gpu_groups
             elif handle is None:
                 for sel, m, n, X, Y in gpu_groups:
@@ -688,11 +697,16 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
     dev_L = []   # per GPU chunk: (clusters, their column counts, ranks, flagged, Sigma V^* on the device)
     jobs = []
     if factor == "gpu":
+        host_jobs = []
         for nt, members in groups.items():
             kp_all = max(k for _, k in members)
-            # about 4 GiB of cluster matrices per call
-            jobs.extend(_chunks(members, 16 * nt * kp_all, budget=1 << 32))
-        results = compress_gpu_all(jobs)
+            if nt > _GPU_MAX_ROWS:   # beyond the GPU kernels' row limit: the host SVD
+                host_jobs.extend(_chunks(members, 16 * nt * kp_all * 3, parts=2 * _workers()))
+                continue
+            # about 4 GiB of cluster matrices per call, at most 65535 clusters
+            for part in _chunks(members, 16 * nt * kp_all, budget=1 << 32):
+                jobs.extend(part[a:a + 65535] for a in range(0, len(part), 65535))
+        results = compress_gpu_all(jobs) + _pmap(compress, host_jobs)
     else:
         for nt, members in groups.items():
             kp_all = max(k for _, k in members)

@@ -233,6 +233,21 @@ def test_gpu_factorisation_fallbacks(torch_dev, monkeypatch):
     tb.test_couplings_are_optimal((cloud, g))
 
 
+def test_gpu_factorisation_row_limit(torch_dev, monkeypatch):
+    """Clusters and blocks beyond the GPU factorisations' row limit are factorised on the
+    host within the same build (the limit lowered to 64 rows here): same operator as the
+    host build's."""
+    monkeypatch.setattr(builder, "_GPU_MAX_ROWS", 64)
+    cloud = inputs.make_cloud("sphere", 2048, seed=0)
+    print(f"case builder factor=gpu with a 64-row GPU limit n={cloud.n}", flush=True)
+    g = builder.build_operator(cloud, leaf=32, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="gpu")
+    monkeypatch.undo()
+    h = builder.build_operator(cloud, leaf=32, eta=1.0, eps_aca=1e-6, eps_comp=1e-6, construct="host", factor="host")
+    assert np.array_equal(g.rank_row, h.rank_row) and np.array_equal(g.adm_rank, h.adm_rank)
+    x = inputs.make_rhs(cloud.n, 2, seed=1)
+    assert rel(uniform.uh_mvp(vars(g), x), uniform.uh_mvp(vars(h), x)) <= 1e-9
+
+
 def test_aca_pack_layout(torch_dev):
     """uhm_aca_pack against the ACA result read block by block (AcaResult.factors): for a
     selection of blocks of one shape, X[c] = [u_0 .. u_{k-1} 0 ..] and Y[c] = conj of the v
