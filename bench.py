@@ -654,15 +654,6 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     binding.load_library()
-    if args.mode == "batched":
-        return run_batched(args)
-    if args.mode == "serving":
-        return run_serving(args)
-    if args.mode == "gmres":
-        return run_gmres_sizes(args)
-    if args.mode == "construct":
-        return run_construct(args)
-
     if args.copy_calibration:
         a = torch.empty(1 << 26, dtype=torch.complex128, device="cuda")  # 1 GiB
         a.fill_(1.0)
@@ -673,6 +664,15 @@ def main():
         torch.cuda.synchronize()
         del a, b
         log(f"copy calibration: {trmod.CALIBRATION_COPIES} copies of 1 GiB")
+
+    if args.mode == "batched":
+        return run_batched(args)
+    if args.mode == "serving":
+        return run_serving(args)
+    if args.mode == "gmres":
+        return run_gmres_sizes(args)
+    if args.mode == "construct":
+        return run_construct(args)
 
     t0 = time.perf_counter()
     cloud = inputs.make_cloud("sphere", args.n, seed=args.seed)

@@ -6,8 +6,12 @@ reads for a plain device copy of known size (a 1 GiB copy run in the same progra
 that the result is in bytes of the same scale as the algorithmic byte counts.
 
     python -m paper_2405_15573_amd.traffic FETCH.csv WRITE.csv --n 262144 -o out.json [--match REGEX]
+        [--trace KERNEL_TRACE.csv]
 
---match keeps the kernels whose short name matches the regular expression.
+--match keeps the kernels whose short name matches the regular expression.  --trace reads
+the kernel trace of the FETCH_SIZE run (rocprofv3 --kernel-trace in the same command) and
+adds, per kernel, the bytes and the time summed over all its dispatches and their ratio,
+for kernels whose dispatches differ in size.
 """
 from __future__ import annotations
 
@@ -79,6 +83,34 @@ def summarize(fetch_csv: str, write_csv: str, match: str = "") -> dict:
     return {"copy_fetch_scale": sf, "copy_write_scale": sw, "kernels": out}
 
 
+def durations(trace_csv: str) -> dict:
+    """Kernel durations (s) from a rocprofv3 kernel-trace CSV, by short name."""
+    out = defaultdict(list)
+    with open(trace_csv) as f:
+        for r in csv.DictReader(f):
+            out[_short(r["Kernel_Name"])].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+    return out
+
+
+def totals(fetch_csv: str, write_csv: str, trace_csv: str, match: str = "") -> dict:
+    """Per kernel: bytes (copy-calibrated FETCH_SIZE + WRITE_SIZE) and time summed over its
+    dispatches, and their ratio in TB/s."""
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    dur = durations(trace_csv)
+    sf = COPY_BYTES / (calibration_kib(fetch_csv, "FETCH_SIZE") * 1024.0)
+    sw = COPY_BYTES / (calibration_kib(write_csv, "WRITE_SIZE") * 1024.0)
+    out = {}
+    for k in set(fetch) | set(write):
+        if not k.startswith("k_") or (match and not re.search(match, k)):
+            continue
+        b = sum(fetch.get(k, [])) * 1024.0 * sf + sum(write.get(k, [])) * 1024.0 * sw
+        t = sum(dur.get(k, []))
+        out[k] = {"total_bytes": b, "total_seconds": t, "dispatches": len(dur.get(k, [])),
+                  "tb_per_s": b / t / 1e12 if t > 0 else None}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("fetch_csv")
@@ -86,8 +118,12 @@ def main():
     ap.add_argument("--n", type=int, required=True)
     ap.add_argument("-o", "--out", required=True)
     ap.add_argument("--match", default="", help="keep kernels whose short name matches this regex")
+    ap.add_argument("--trace", default="", help="kernel trace of the FETCH_SIZE run: adds summed bytes, time, TB/s")
     a = ap.parse_args()
     s = summarize(a.fetch_csv, a.write_csv, a.match)
+    if a.trace:
+        s["totals"] = totals(a.fetch_csv, a.write_csv, a.trace, a.match)
+        print(json.dumps(s["totals"]))
     s["n"] = a.n
     s["source_sha256"] = kernel_source_sha256()
     s["bytes_per_launch"] = {k: v["bytes"] for k, v in s["kernels"].items()}

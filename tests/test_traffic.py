@@ -62,3 +62,26 @@ def test_match_keeps_only_the_named_kernels(tmp_path):
     _write(wp, "WRITE_SIZE", rows)
     s = traffic.summarize(str(fp), str(wp), match=r"^k_coupling")
     assert sorted(s["kernels"]) == ["k_coupling", "k_coupling_sym"]
+
+
+def test_totals_sum_bytes_and_time_over_dispatches(tmp_path):
+    """Dispatches of different sizes: the rate is summed bytes over summed time, not the
+    mean of per-dispatch rates."""
+    gib_kib = float(1 << 20)
+    cal = traffic.CALIBRATION_COPIES
+    k = "void uhm_detail::(anonymous namespace)::k_qr_step<8>(QrStep, int)"
+    fetch = [("__amd_rocclr_copyBuffer", gib_kib)] * cal + [(k, 1000.0), (k, 3000.0)]
+    write = [("__amd_rocclr_copyBuffer", gib_kib)] * cal + [(k, 500.0), (k, 500.0)]
+    fp, wp, tp = tmp_path / "f.csv", tmp_path / "w.csv", tmp_path / "t.csv"
+    _write(fp, "FETCH_SIZE", fetch)
+    _write(wp, "WRITE_SIZE", write)
+    with open(tp, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        w.writerow({"Dispatch_Id": 10, "Kernel_Name": k, "Start_Timestamp": 1000, "End_Timestamp": 3000})
+        w.writerow({"Dispatch_Id": 11, "Kernel_Name": k, "Start_Timestamp": 5000, "End_Timestamp": 11000})
+    t = traffic.totals(str(fp), str(wp), str(tp))["k_qr_step<8>"]
+    assert t["dispatches"] == 2
+    assert abs(t["total_bytes"] - 5000.0 * 1024) < 1e-6
+    assert abs(t["total_seconds"] - 8000e-9) < 1e-18
+    assert abs(t["tb_per_s"] - 5000.0 * 1024 / 8000e-9 / 1e12) < 1e-12
