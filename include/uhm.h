@@ -448,7 +448,7 @@ int uhm_aca_pack(const uhm_block_desc* blocks, int64_t nblocks, const int32_t* r
 
 /*
  * Alg. 2's per-cluster factorisation (section 4.2) for a batch of `batch` clusters of one
- * shape: for each X_c (m x n complex128, column-major, X + 2*c*m*n; zero columns allowed)
+ * shape: for each X_c (m x n complex128, row-major, X + 2*c*m*n; zero columns allowed)
  * it returns the left singular vectors whose singular values exceed eps * sigma_1 (U_tau,
  * rank l = at least 1) and the rows Sigma V^* = U_tau^* X_c, the same rank rule as a full
  * SVD.  The SVD is taken as: Householder QR with column pivoting of X_c, stopped once the
@@ -458,7 +458,8 @@ int uhm_aca_pack(const uhm_block_desc* blocks, int64_t nblocks, const int32_t* r
  * one-sided Jacobi on its p x p triangle, and the reflectors applied back.  With tol^2 about
  * 1e-16 eps (1e-11 for eps = 1e-6) a singular value at the threshold eps sigma_1 moves by
  * less than a unit of rounding of sigma_1.
- * X (destroyed), U, SV, sv, rank, psteps, stats, status and work are device arrays:
+ * X (only read: the library factorises a column-major copy in work), U, SV, sv, rank,
+ * psteps, stats, status and work are device arrays:
  *   U[c]:  m x pmax complex (column-major, U + 2*c*m*pmax), columns 0..l-1 written;
  *   SV[c]: pmax x n complex (column-major with leading dimension pmax, SV + 2*c*pmax*n),
  *          rows 0..l-1 written: SV = U^* X;
@@ -477,7 +478,7 @@ int uhm_aca_pack(const uhm_block_desc* blocks, int64_t nblocks, const int32_t* r
  * Errors: UHM_EINVAL (sizes, tol or eps negative or not finite, null pointers, work too
  * small), UHM_EHIP.
  */
-int uhm_cluster_basis(double* X, int32_t batch, int32_t m, int32_t n, int32_t pmax, double tol, double eps,
+int uhm_cluster_basis(const double* X, int32_t batch, int32_t m, int32_t n, int32_t pmax, double tol, double eps,
                       double* U, double* SV, double* sv, int32_t* rank, int32_t* psteps, double* stats,
                       int32_t* status, double* work, int64_t work_len, void* hip_stream);
 
@@ -487,12 +488,13 @@ int64_t uhm_cluster_basis_work(int32_t batch, int32_t m, int32_t n, int32_t pmax
 /*
  * The algebraic recompression of ACA factors (section 2.3) for a batch of `batch` blocks of
  * one shape: for each block A|_b ~ X_c Y_c^* (X_c m x kp and Y_c n x kp complex128,
- * column-major at X + 2*c*m*kp and Y + 2*c*n*kp; zero columns allowed) it returns the SVD
+ * row-major at X + 2*c*m*kp and Y + 2*c*n*kp; zero columns allowed) it returns the SVD
  * truncated at eps * sigma_1, U_c Sigma_c V_c^* with k = rank[c] >= 1 terms.  Taken as:
  * unpivoted Householder QR of both factors (X = Q_X R_X, Y = Q_Y R_Y), one-sided Jacobi on
  * M = R_Y R_X^* (M J = W Sigma, so X Y^* = (Q_X J) Sigma (Q_Y W)^*), the kept columns of J
  * and W orthonormalised again and carried back through the reflectors.
- * X, Y (both destroyed), U, V, sv, rank, status and work are device arrays:
+ * X, Y (only read: the library works on column-major copies in work), U, V, sv, rank,
+ * status and work are device arrays:
  *   U[c]: m x kp complex (column-major, U + 2*c*m*kp), columns 0..k-1 written;
  *   V[c]: n x kp complex (V + 2*c*n*kp), columns 0..k-1 written;
  *   sv[c*kp + i]: the singular values of X_c Y_c^*, descending;
@@ -503,7 +505,7 @@ int64_t uhm_cluster_basis_work(int32_t batch, int32_t m, int32_t n, int32_t pmax
  * uhm_cluster_basis.  Errors: UHM_EINVAL (sizes, eps negative or not finite, null pointers,
  * work too small), UHM_EHIP.
  */
-int uhm_block_recompress(double* X, double* Y, int32_t batch, int32_t m, int32_t n, int32_t kp, double eps,
+int uhm_block_recompress(const double* X, const double* Y, int32_t batch, int32_t m, int32_t n, int32_t kp, double eps,
                          double* U, double* V, double* sv, int32_t* rank, int32_t* status, double* work,
                          int64_t work_len, void* hip_stream);
 

@@ -689,7 +689,7 @@ class ClusterBasis:
 
 def cluster_basis(X, eps: float, tol: float | None = None, pmax: int | None = None, stream=None) -> ClusterBasis:
     """Alg. 2's factorisation of a batch of cluster matrices X (batch, m, n), complex128
-    (host or device; copied, so the argument is kept), on the device (uhm_cluster_basis).
+    (host or device, row-major; the library only reads it), on the device (uhm_cluster_basis).
     tol defaults to sqrt(1e-16 eps), where the rank test is that of a full SVD up to rounding."""
     import torch
     lib = load_library()
@@ -700,8 +700,7 @@ def cluster_basis(X, eps: float, tol: float | None = None, pmax: int | None = No
         tol = float(np.sqrt(1e-16 * max(eps, 0.0)))
     h, stream = _stream_handle(stream)
     with torch.cuda.stream(stream):
-        # column-major per matrix: the (batch, n, m) layout of X^T
-        Xd = Xt.to(device="cuda", dtype=torch.complex128).transpose(1, 2).contiguous()
+        Xd = Xt.to(device="cuda", dtype=torch.complex128).contiguous()
         need = int(lib.uhm_cluster_basis_work(batch, m, n, pmax))
         if need < 0:
             raise UhmError(UHM_EINVAL, "uhm_cluster_basis_work: sizes rejected")
@@ -727,7 +726,8 @@ def cluster_basis(X, eps: float, tol: float | None = None, pmax: int | None = No
 
 def block_recompress(X, Y, eps: float, stream=None):
     """The recompression of a batch of ACA factor pairs (uhm_block_recompress): X (batch, m,
-    kp) and Y (batch, n, kp) complex128 with A|_b ~ X[c] Y[c]^H (host or device; copied).
+    kp) and Y (batch, n, kp) complex128 with A|_b ~ X[c] Y[c]^H (host or device, row-major;
+    only read).
     Returns device tensors U (batch, kp, m) and V (batch, kp, n) holding U_c^T and V_c^T row
     by row, sv (batch, kp), and host arrays rank and status."""
     import torch
@@ -739,8 +739,8 @@ def block_recompress(X, Y, eps: float, stream=None):
         raise UhmError(UHM_EINVAL, "block_recompress: X and Y disagree in batch or kp")
     h, stream = _stream_handle(stream)
     with torch.cuda.stream(stream):
-        Xd = Xt.to(device="cuda", dtype=torch.complex128).transpose(1, 2).contiguous()
-        Yd = Yt.to(device="cuda", dtype=torch.complex128).transpose(1, 2).contiguous()
+        Xd = Xt.to(device="cuda", dtype=torch.complex128).contiguous()
+        Yd = Yt.to(device="cuda", dtype=torch.complex128).contiguous()
         need = int(lib.uhm_block_recompress_work(batch, m, n, kp))
         if need < 0:
             raise UhmError(UHM_EINVAL, "uhm_block_recompress_work: sizes rejected")

@@ -954,13 +954,43 @@ __global__ __launch_bounds__(kCoupThreads) void k_couplings(const double2* __res
   }
 }
 
+// Row-major rows x cols matrices (the caller's layout) into column-major copies in the
+// workspace, through 32 x 32 LDS tiles so that reads and writes are both contiguous.  Grid
+// (ceil(cols / 32), ceil(rows / 32), batch), 256 threads.
+__global__ __launch_bounds__(256) void k_to_colmajor(const double2* __restrict__ src, int64_t s_stride, int32_t rows,
+                                                     int32_t cols, CArr dst) {
+  __shared__ double2 tile[32][33];
+  const int c = blockIdx.z;
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const double2* S = src + (int64_t)c * s_stride;
+  double2* D = dst.at(c);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows of 32 per pass
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, q = c0 + tx;
+    tile[k][tx] = (r < rows && q < cols) ? S[(int64_t)r * cols + q] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int q = c0 + k, r = r0 + tx;
+    if (q < cols && r < rows) D[(int64_t)q * rows + r] = tile[tx][k];
+  }
+}
+
+int to_colmajor(const double* src, int32_t batch, int32_t rows, int32_t cols, CArr dst, hipStream_t s) {
+  k_to_colmajor<<<dim3((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32), (unsigned)batch), dim3(256), 0, s>>>(
+      reinterpret_cast<const double2*>(src), (int64_t)rows * cols, rows, cols, dst);
+  UHM_HIP(hipGetLastError());
+  return UHM_OK;
+}
+
 // Per-matrix workspace of the cluster factorisation (offsets in doubles).
 struct ClusterWs {
-  int64_t per, o_w, o_om, o_c, o_cq, o_r2, o_j, o_nu, o_ord, o_st;
+  int64_t per, o_x, o_w, o_om, o_c, o_cq, o_r2, o_j, o_nu, o_ord, o_st;
 };
 ClusterWs cluster_ws(int32_t m, int32_t n, int32_t P) {
   Carve cv;
   ClusterWs w{};
+  w.o_x = cv.take(2 * (int64_t)m * n);  // the column-major copy of X, factorised in place
   w.o_w = cv.take(2 * (int64_t)P * m);
   w.o_om = cv.take(P);
   w.o_c = cv.take(2 * (int64_t)n * P);
@@ -978,12 +1008,14 @@ ClusterWs cluster_ws(int32_t m, int32_t n, int32_t P) {
 
 // Per-matrix workspace of the recompression (offsets in doubles).
 struct RecWs {
-  int64_t per, o_wx, o_omx, o_wy, o_omy, o_rx, o_ry, o_m, o_j, o_qj, o_qw, o_nux, o_nuy, o_ord, o_st;
+  int64_t per, o_x, o_y, o_wx, o_omx, o_wy, o_omy, o_rx, o_ry, o_m, o_j, o_qj, o_qw, o_nux, o_nuy, o_ord, o_st;
 };
 RecWs rec_ws(int32_t m, int32_t n, int32_t kp) {
   Carve cv;
   RecWs w{};
   const int64_t kk = 2 * (int64_t)kp * kp;
+  w.o_x = cv.take(2 * (int64_t)m * kp);  // column-major copies of the factors
+  w.o_y = cv.take(2 * (int64_t)n * kp);
   w.o_wx = cv.take(2 * (int64_t)kp * m);
   w.o_omx = cv.take(kp);
   w.o_wy = cv.take(2 * (int64_t)kp * n);
@@ -1040,7 +1072,7 @@ int64_t uhm_cluster_basis_work(int32_t batch, int32_t m, int32_t n, int32_t pmax
   return cluster_ws(m, n, pmax).per * (int64_t)batch + 32;
 }
 
-int uhm_cluster_basis(double* X, int32_t batch, int32_t m, int32_t n, int32_t pmax, double tol, double eps,
+int uhm_cluster_basis(const double* X, int32_t batch, int32_t m, int32_t n, int32_t pmax, double tol, double eps,
                       double* U, double* SV, double* sv, int32_t* rank, int32_t* psteps, double* stats,
                       int32_t* status, double* work, int64_t work_len, void* hip_stream) {
   if (batch < 0 || m < 1 || n < 1) return fail(UHM_EINVAL, "uhm_cluster_basis: bad size");
@@ -1059,7 +1091,9 @@ int uhm_cluster_basis(double* X, int32_t batch, int32_t m, int32_t n, int32_t pm
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   UHM_HIP(hipMemsetAsync(work, 0, sizeof(double) * (size_t)(ws.per * (int64_t)batch), s));
   const int64_t per = ws.per;
-  const CArr Xa{reinterpret_cast<double2*>(X), (int64_t)m * n};
+  const CArr Xa = region<double2>(work, per, ws.o_x);
+  int rc;
+  if ((rc = to_colmajor(X, batch, m, n, Xa, s))) return rc;
   const CArr Wa = region<double2>(work, per, ws.o_w), Ca = region<double2>(work, per, ws.o_c),
              Cq = region<double2>(work, per, ws.o_cq), R2 = region<double2>(work, per, ws.o_r2),
              Ja = region<double2>(work, per, ws.o_j);
@@ -1071,7 +1105,6 @@ int uhm_cluster_basis(double* X, int32_t batch, int32_t m, int32_t n, int32_t pm
   const DArr dnone{nullptr, 0};
   const IArr inone{nullptr, 0};
   const int32_t kcap = std::min(std::min(m, n), P);
-  int rc;
 
   // 1. pivoted QR of X to the tolerance; B^* into C (kept) and Cq (consumed by step 2)
   k_col_norms<<<dim3((unsigned)((n + kStepCols - 1) / kStepCols), (unsigned)batch), dim3(kStepThreads), 0, s>>>(
@@ -1119,7 +1152,7 @@ int64_t uhm_block_recompress_work(int32_t batch, int32_t m, int32_t n, int32_t k
   return rec_ws(m, n, kp).per * (int64_t)batch + 32;
 }
 
-int uhm_block_recompress(double* X, double* Y, int32_t batch, int32_t m, int32_t n, int32_t kp, double eps,
+int uhm_block_recompress(const double* X, const double* Y, int32_t batch, int32_t m, int32_t n, int32_t kp, double eps,
                          double* U, double* V, double* sv, int32_t* rank, int32_t* status, double* work,
                          int64_t work_len, void* hip_stream) {
   if (batch < 0 || m < 1 || n < 1) return fail(UHM_EINVAL, "uhm_block_recompress: bad size");
@@ -1138,7 +1171,9 @@ int uhm_block_recompress(double* X, double* Y, int32_t batch, int32_t m, int32_t
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   UHM_HIP(hipMemsetAsync(work, 0, sizeof(double) * (size_t)(ws.per * (int64_t)batch), s));
   const int64_t per = ws.per;
-  const CArr Xa{reinterpret_cast<double2*>(X), (int64_t)m * kp}, Ya{reinterpret_cast<double2*>(Y), (int64_t)n * kp};
+  const CArr Xa = region<double2>(work, per, ws.o_x), Ya = region<double2>(work, per, ws.o_y);
+  int rc;
+  if ((rc = to_colmajor(X, batch, m, kp, Xa, s)) || (rc = to_colmajor(Y, batch, n, kp, Ya, s))) return rc;
   const CArr WX = region<double2>(work, per, ws.o_wx), WY = region<double2>(work, per, ws.o_wy),
              RX = region<double2>(work, per, ws.o_rx), RY = region<double2>(work, per, ws.o_ry),
              Ma = region<double2>(work, per, ws.o_m), Ja = region<double2>(work, per, ws.o_j),
@@ -1150,7 +1185,6 @@ int uhm_block_recompress(double* X, double* Y, int32_t batch, int32_t m, int32_t
   const CArr none{nullptr, 0};
   const DArr dnone{nullptr, 0};
   const IArr inone{nullptr, 0};
-  int rc;
   // 1. unpivoted QR of both factors (all kp steps), R upper triangular (ld kp)
   k_col_norms<<<dim3((unsigned)((kp + kStepCols - 1) / kStepCols), (unsigned)batch), dim3(kStepThreads), 0, s>>>(
       Xa, m, kp, nux);
