@@ -89,8 +89,25 @@ def test_prescribed_singular_values(m, n, ratio):
         ss.append(s)
         Xs.append(_prescribed(rng, m, n, s))
     res = _binding().cluster_basis(np.stack(Xs), eps=1e-6)
-    # the Jacobi orders span its three forms: in LDS (<= 64), column blocks in LDS (<= 1152)
-    # and column rounds (above)
+    # the Jacobi orders span both of its forms: all sweeps in LDS (orders up to 64) and one
+    # launch per round of the circle schedule (above)
+    print(f"  QR steps p = {res.psteps.tolist()}", flush=True)
+    for c in range(batch):
+        _check(Xs[c], res, c, 1e-6, ss[c])
+
+
+@pytest.mark.parametrize("m,n,ratio", [(16384, 64, 0.8), (9000, 120, 0.85), (2048, 2048, 0.987)])
+def test_maximum_sizes(m, n, ratio):
+    """The largest shapes the entry point takes: 16384 rows (the widest QR-step and
+    reflector kernels, above 8192 rows), and singular values decaying as 0.987^i, whose QR
+    reaches the tolerance 1e-11 only after about 2030 steps: a Jacobi order near pmax's
+    limit of 2048."""
+    rng = np.random.default_rng(m + 3 * n)
+    batch = 2
+    k = min(m, n)
+    ss = [_decay(k, ratio, 0.2, rng) for _ in range(batch)]
+    Xs = [_prescribed(rng, m, n, s) for s in ss]
+    res = _binding().cluster_basis(np.stack(Xs), eps=1e-6)
     print(f"  QR steps p = {res.psteps.tolist()}", flush=True)
     for c in range(batch):
         _check(Xs[c], res, c, 1e-6, ss[c])
@@ -202,15 +219,22 @@ def _factor_pair(rng, m, n, s, cond=10.0):
 
 def _check_rec(X, Y, U, V, sv, k, eps, s_true):
     A = X @ Y.conj().T
+    m, kp = X.shape
+    n = Y.shape[0]
     k_ref = max(1, int(np.count_nonzero(s_true > eps * s_true[0]))) if s_true[0] > 0 else 1
     assert k == k_ref
     Uk, Vk = U[:, :k], V[:, :k]
-    assert np.linalg.norm(Uk.conj().T @ Uk - np.eye(k)) < 1e-13
-    assert np.linalg.norm(Vk.conj().T @ Vk - np.eye(k)) < 1e-13
+    # rounding, as for the cluster factorisation: eps_mach sqrt(rows kp) |X Y^*| from the
+    # QRs of the factors, eps_mach k in the Gram matrices of the twice-orthogonalised sets
+    emach = np.finfo(float).eps
+    ab = max(1e-12, 4 * emach * np.sqrt(max(m, n) * kp)) * s_true[0]
+    orth = max(1e-13, 2 * emach * k)
+    assert np.linalg.norm(Uk.conj().T @ Uk - np.eye(k)) < orth
+    assert np.linalg.norm(Vk.conj().T @ Vk - np.eye(k)) < orth
     kk = min(s_true.size, sv.size)
-    assert np.all(np.abs(sv[:kk] - s_true[:kk]) <= 1e-12 * s_true[0])
+    assert np.all(np.abs(sv[:kk] - s_true[:kk]) <= ab)
     best = s_true[k] if k < s_true.size else 0.0
-    assert np.linalg.norm(A - (Uk * sv[:k]) @ Vk.conj().T, 2) <= best * (1 + 1e-6) + 1e-12 * s_true[0]
+    assert np.linalg.norm(A - (Uk * sv[:k]) @ Vk.conj().T, 2) <= best * (1 + 1e-6) + ab
 
 
 @pytest.mark.parametrize("m,n,k", [(64, 64, 20), (128, 256, 37), (300, 200, 64), (1024, 512, 90)])
@@ -234,6 +258,26 @@ def test_recompression_prescribed(m, n, k):
     U, V, sv = U.cpu().numpy(), V.cpu().numpy(), sv.cpu().numpy()
     for c in range(batch):
         _check_rec(Xs[c], Ys[c], U[c].T, V[c].T, sv[c], int(rk[c]), eps, ss[c])
+
+
+@pytest.mark.parametrize("m,n,k,ratio", [(16384, 200, 40, 0.7), (200, 16384, 40, 0.7), (2048, 2048, 2048, 0.99)])
+def test_recompression_maximum_sizes(m, n, k, ratio):
+    """The largest shapes: 16384 rows on either factor (the widest QR-step and reflector
+    kernels), and kp = 2048 (the largest Jacobi order; 0.99^i keeps every singular value
+    above the underflow, and about 1600 of them above eps = 1e-7)."""
+    rng = np.random.default_rng(m + 2 * n + k)
+    batch = 1 if k > 100 else 2
+    eps = 1e-7
+    ss = [_decay(k, ratio, 0.2, rng) for _ in range(batch)]
+    pairs = [_factor_pair(rng, m, n, s) for s in ss]
+    X = np.stack([p[0] for p in pairs])
+    Y = np.stack([p[1] for p in pairs])
+    U, V, sv, rk, st = _binding().block_recompress(X, Y, eps)
+    print(f"  ranks {rk.tolist()}", flush=True)
+    assert np.all(st == 0)
+    U, V, sv = U.cpu().numpy(), V.cpu().numpy(), sv.cpu().numpy()
+    for c in range(batch):
+        _check_rec(X[c], Y[c], U[c].T, V[c].T, sv[c], int(rk[c]), eps, ss[c])
 
 
 def test_recompression_degenerate_blocks():
