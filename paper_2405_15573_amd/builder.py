@@ -83,8 +83,36 @@ def _native():
         lib.uhmb_aca_block.restype = I32
         lib.uhmb_num_threads.argtypes = []
         lib.uhmb_num_threads.restype = ctypes.c_int
+        lib.uhmb_scaled_copy.argtypes = [P, I64]
+        lib.uhmb_scaled_copy.restype = ctypes.c_int
         _LIB = lib
     return _LIB
+
+
+# one record of uhmb_scaled_copy: dst[i drs + q dcs] = f(src[i srs + q scs]) * scale[q]
+# (byte addresses, strides in complex elements; f = conj when conj != 0)
+COPY_DTYPE = np.dtype([("src", np.uint64), ("dst", np.uint64), ("scale", np.uint64), ("srs", np.int64),
+                       ("scs", np.int64), ("drs", np.int64), ("dcs", np.int64), ("rows", np.int32),
+                       ("cols", np.int32), ("conj", np.int32), ("pad", np.int32)])
+
+
+def _scaled_copy(recs):
+    """Run uhmb_scaled_copy over a list of COPY_DTYPE tuples (the GIL is released meanwhile)."""
+    if not recs:
+        return
+    arr = np.array(recs, dtype=COPY_DTYPE)
+    _native().uhmb_scaled_copy(_ptr(arr), len(arr))
+
+
+def _view(a: np.ndarray, dtype=np.complex128):
+    """(address, row stride, column stride) of a 2-D array, strides in elements; a copy is
+    returned beside them when the array is not of that type or its strides are not whole
+    elements (the caller keeps it alive)."""
+    item = np.dtype(dtype).itemsize
+    if a.dtype != dtype or any(st % item for st in a.strides):
+        a = np.ascontiguousarray(a, dtype=dtype)
+    st = a.strides
+    return a.__array_interface__["data"][0], st[0] // item, (st[1] // item if a.ndim > 1 else 0), a
 
 
 def _ptr(a: np.ndarray):
@@ -565,6 +593,20 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
             return fac_U[(t, s)], fac_s[(t, s)], fac_V[(t, s)]
         return np.conj(fac_V[(s, t)]), fac_s[(s, t)], np.conj(fac_U[(s, t)])
 
+    views = {}   # stored block (t < s) -> addresses and strides of U_b, V_b, Sigma_b, and k_b
+
+    def factor_views(key):
+        """(U address, row stride, column stride, the same for V, Sigma address, k_b) of a
+        stored block, for uhmb_scaled_copy; copies made for it are kept in the entry."""
+        v = views.get(key)
+        if v is None:
+            ua, urs, ucs, uk = _view(fac_U[key])
+            va, vrs, vcs, vk = _view(fac_V[key])
+            sv = np.ascontiguousarray(fac_s[key], dtype=np.float64)
+            v = (ua, urs, ucs, va, vrs, vcs, sv.__array_interface__["data"][0], int(sv.size), (uk, vk, sv))
+            views[key] = v
+        return v
+
     # ---- uniform compression, one SVD per cluster (row side; column side by symmetry)
     t2 = time.perf_counter()
     row_blocks = {}
@@ -624,34 +666,45 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
         fallback = 0
         per_size = {}
 
-        def fill(part, pool):
+        def fill(part):
+            """The batch's matrices X_tau = [U_b Sigma_b ...] (conj(V_b) Sigma_b for a mirrored
+            block) written by the native copy into page-locked memory, zero columns after."""
+            t0 = time.perf_counter()
             nt = int(size[part[0][0]])
             kp = max(k for _, k in part)
             buf = torch.empty((len(part), nt, kp), dtype=torch.complex128, pin_memory=True)
-            Xb = buf.numpy()
+            base = buf.data_ptr()
             cols = [None] * len(part)
-
-            def one(c):
-                t, _ = part[c]
+            recs = []
+            for c, (t, _) in enumerate(part):
                 j, cl = 0, []
+                row0 = base + 16 * c * nt * kp
                 for s in row_blocks[t]:
-                    Ub, sb, _ = block_factors(t, s)
-                    kb = sb.size
-                    np.multiply(Ub, sb[None, :], out=Xb[c, :, j:j + kb])
+                    if t < s:
+                        ua, urs, ucs, _, _, _, sa, kb, _ = factor_views((t, s))
+                        recs.append((ua, row0 + 16 * j, sa, urs, ucs, kp, 1, nt, kb, 0, 0))
+                    else:
+                        _, _, _, va, vrs, vcs, sa, kb, _ = factor_views((s, t))
+                        recs.append((va, row0 + 16 * j, sa, vrs, vcs, kp, 1, nt, kb, 1, 0))
                     cl.append((s, j, kb))
                     j += kb
-                Xb[c, :, j:] = 0.0
+                if j < kp:
+                    recs.append((0, row0 + 16 * j, 0, 0, 0, kp, 1, nt, kp - j, 0, 0))
                 cols[c] = cl
+            _scaled_copy(recs)
+            return buf, cols, time.perf_counter() - t0
 
-            list(pool.map(one, range(len(part))))
-            return buf, cols
-
-        with ThreadPoolExecutor(_workers()) as pool, ThreadPoolExecutor(1) as pre:
-            nxt = pre.submit(fill, jobs[0], pool) if jobs else None
+        # fills run back to back on one thread, up to two batches ahead of the GPU
+        depth = 2
+        fill_s = 0.0
+        with ThreadPoolExecutor(1) as pre:
+            ahead = [pre.submit(fill, jobs[i]) for i in range(min(depth, len(jobs)))]
             for q, part in enumerate(jobs):
                 ta = time.perf_counter()
-                buf, cols = nxt.result()
-                nxt = pre.submit(fill, jobs[q + 1], pool) if q + 1 < len(jobs) else None
+                buf, cols, tf = ahead.pop(0).result()
+                fill_s += tf
+                if q + depth < len(jobs):
+                    ahead.append(pre.submit(fill, jobs[q + depth]))
                 tb = time.perf_counter()
                 nt, kp = buf.shape[1], buf.shape[2]
                 res = binding.cluster_basis(buf.to("cuda", non_blocking=True), eps=eps_comp,
@@ -685,6 +738,7 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
                 e[2] = max(e[2], lmax)
                 e[3] += tc - tb
                 e[4] += te - tc
+        tw["compress_fill"] = fill_s
         tim.update(tw)
         tim["compress_host_fallback"] = fallback
         if verbose:
@@ -706,6 +760,12 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
             # about 4 GiB of cluster matrices per call, at most 65535 clusters
             for part in _chunks(members, 16 * nt * kp_all, budget=1 << 32):
                 jobs.extend(part[a:a + 65535] for a in range(0, len(part), 65535))
+        # the smallest clusters first, their first batch an eighth of the rest: the GPU starts
+        # after a short fill, and the later fills run while it works
+        jobs.sort(key=lambda part: int(size[part[0][0]]))
+        if jobs and len(jobs[0]) >= 16:
+            head = len(jobs[0]) // 8
+            jobs[:1] = [jobs[0][:head], jobs[0][head:]]
         results = compress_gpu_all(jobs) + _pmap(compress, host_jobs)
     else:
         for nt, members in groups.items():
@@ -846,24 +906,24 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
     Xh = np.empty(int(xs.sum()), np.complex128)
     Yh = np.empty(int(ys.sum()), np.complex128)
 
-    def h_factors(bs):
-        for b in bs:
-            t, s = int(adm[b, 0]), int(adm[b, 1])
-            kb = int(adm_rank[b])
-            xd = Xh[X_off[b]:X_off[b] + xs[b]].reshape(kb, int(size[t])).T
-            yd = Yh[Y_off[b]:Y_off[b] + ys[b]].reshape(kb, int(size[s])).T
-            if t < s:
-                sb = fac_s[(t, s)]
-                np.multiply(fac_U[(t, s)], sb[None, :], out=xd)
-                yd[...] = fac_V[(t, s)]
-            else:   # the mirror of block (s, t): U_b = conj(V), V_b = conj(U)
-                sb = fac_s[(s, t)]
-                np.conjugate(fac_V[(s, t)], out=xd)
-                xd *= sb[None, :]
-                np.conjugate(fac_U[(s, t)], out=yd)
-
-    _pmap(h_factors, np.array_split(np.arange(nadm), max(1, min(nadm, 8 * _workers()))))
-    del fac_U, fac_V, Lmat
+    # X_b = U_b Sigma_b and Y_b = V_b column-major, by the native copy; the mirror of a
+    # stored block (s, t) has U_b = conj(V), V_b = conj(U)
+    xa0, ya0 = Xh.__array_interface__["data"][0], Yh.__array_interface__["data"][0]
+    recs = []
+    for b in range(nadm):
+        t, s = int(adm[b, 0]), int(adm[b, 1])
+        kb, mt, ms = int(adm_rank[b]), int(size[t]), int(size[s])
+        xa, ya = xa0 + 16 * int(X_off[b]), ya0 + 16 * int(Y_off[b])
+        if t < s:
+            ua, urs, ucs, va, vrs, vcs, sa, _, _ = factor_views((t, s))
+            recs.append((ua, xa, sa, urs, ucs, 1, mt, mt, kb, 0, 0))
+            recs.append((va, ya, 0, vrs, vcs, 1, ms, ms, kb, 0, 0))
+        else:
+            ua, urs, ucs, va, vrs, vcs, sa, _, _ = factor_views((s, t))
+            recs.append((va, xa, sa, vrs, vcs, 1, mt, mt, kb, 1, 0))
+            recs.append((ua, ya, 0, urs, ucs, 1, ms, ms, kb, 1, 0))
+    _scaled_copy(recs)
+    del recs, views, fac_U, fac_V, Lmat
     tim["factors"] = time.perf_counter() - t5
 
     # ---- dense near field

@@ -223,6 +223,42 @@ int32_t uhmb_aca_block(const double* pts, double kappa, double diag, int64_t r0,
   return r.k;
 }
 
+// Scaled copies of complex128 matrices, for laying out the agglomerated block rows X_tau
+// and the H-matrix factors: for each record e and i < rows, q < cols,
+//   dst[i * drs + q * dcs] = f(src[i * srs + q * scs]) * scale[q],
+// f = conj when conj != 0, no scaling when scale is 0, zeros written when src is 0.
+// Addresses are byte addresses, strides count complex elements.  The records are spread
+// over the OpenMP threads; their destinations must not overlap.
+struct uhmb_copy {
+  uint64_t src, dst, scale;
+  int64_t srs, scs, drs, dcs;
+  int32_t rows, cols, conj, pad;
+};
+
+int uhmb_scaled_copy(const uhmb_copy* rec, int64_t nrec) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t e = 0; e < nrec; ++e) {
+    const uhmb_copy r = rec[e];
+    cplx* d = reinterpret_cast<cplx*>(r.dst);
+    const cplx* sp = reinterpret_cast<const cplx*>(r.src);
+    const double* sc = reinterpret_cast<const double*>(r.scale);
+    auto value = [&](int64_t i, int64_t q) {
+      if (!sp) return cplx(0.0, 0.0);
+      cplx v = sp[i * r.srs + q * r.scs];
+      if (r.conj) v = std::conj(v);
+      return sc ? cplx(v.real() * sc[q], v.imag() * sc[q]) : v;
+    };
+    if (r.dcs == 1) {  // rows of the destination contiguous
+      for (int64_t i = 0; i < r.rows; ++i)
+        for (int64_t q = 0; q < r.cols; ++q) d[i * r.drs + q] = value(i, q);
+    } else {
+      for (int64_t q = 0; q < r.cols; ++q)
+        for (int64_t i = 0; i < r.rows; ++i) d[i * r.drs + q * r.dcs] = value(i, q);
+    }
+  }
+  return 0;
+}
+
 int uhmb_num_threads(void) { return omp_get_max_threads(); }
 
 }  // extern "C"
