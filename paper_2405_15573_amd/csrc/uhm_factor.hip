@@ -401,10 +401,12 @@ constexpr int kJacWaves = 4;
 __global__ __launch_bounds__(256) void k_jacobi_init(CArr Va, int32_t P, IArr pp, IArr sst) {
   const int c = blockIdx.y;
   const int p = pp.at(c)[0];
-  double2* V = Va.at(c);
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < (int64_t)P * P; q += (int64_t)gridDim.x * 256) {
-    const int r = (int)(q % P), col = (int)(q / P);
-    V[q] = make_double2(r == col && r < p ? 1.0 : 0.0, 0.0);
+  if (Va.p) {  // no accumulator: the rotations are not kept
+    double2* V = Va.at(c);
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < (int64_t)P * P; q += (int64_t)gridDim.x * 256) {
+      const int r = (int)(q % P), col = (int)(q / P);
+      V[q] = make_double2(r == col && r < p ? 1.0 : 0.0, 0.0);
+    }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     int32_t* t = sst.at(c);
@@ -431,7 +433,6 @@ __global__ __launch_bounds__(64 * kJacWaves) void k_jacobi_round(CArr Ra, CArr V
   const int i = min(a0, b0), j = max(a0, b0);
   if (j >= p) return;
   double2* R = Ra.at(c);
-  double2* V = Va.at(c);
   double2* ci = R + (int64_t)i * P;
   double2* cj = R + (int64_t)j * P;
   double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
@@ -454,17 +455,21 @@ __global__ __launch_bounds__(64 * kJacWaves) void k_jacobi_round(CArr Ra, CArr V
   const double tt = fabs(z) > 1e100 ? 0.5 / z : (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
   const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
   const double2 se = make_double2(sn * e.x, sn * e.y);  // s e
-  double2* vi = V + (int64_t)i * P;
-  double2* vj = V + (int64_t)j * P;
   for (int row = lane; row < p; row += 64) {
     const double2 x = ci[row], y = cj[row];
     const double2 a1 = cdotc(se, y), b1 = cmul(se, x);  // s conj(e) y, s e x
     ci[row] = make_double2(cs * x.x - a1.x, cs * x.y - a1.y);
     cj[row] = make_double2(b1.x + cs * y.x, b1.y + cs * y.y);
-    const double2 u = vi[row], v = vj[row];
-    const double2 a2 = cdotc(se, v), b2 = cmul(se, u);
-    vi[row] = make_double2(cs * u.x - a2.x, cs * u.y - a2.y);
-    vj[row] = make_double2(b2.x + cs * v.x, b2.y + cs * v.y);
+  }
+  if (Va.p) {
+    double2* vi = Va.at(c) + (int64_t)i * P;
+    double2* vj = Va.at(c) + (int64_t)j * P;
+    for (int row = lane; row < p; row += 64) {
+      const double2 u = vi[row], v = vj[row];
+      const double2 a2 = cdotc(se, v), b2 = cmul(se, u);
+      vi[row] = make_double2(cs * u.x - a2.x, cs * u.y - a2.y);
+      vj[row] = make_double2(b2.x + cs * v.x, b2.y + cs * v.y);
+    }
   }
   if (lane == 0) t[0] = 1;
 }
@@ -502,8 +507,8 @@ __global__ __launch_bounds__(512) void k_jacobi_lds(CArr Ra, CArr Va, int32_t P,
   const int c = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int p = pp.at(c)[0];
+  const bool acc = Va.p != nullptr;  // accumulate the rotations in V
   double2* R = Ra.at(c);
-  double2* V = Va.at(c);
   for (int q = tid; q < P * P; q += 512) {
     const int r = q % P, col = q / P;
     sR[r + col * kJacLds] = R[q];
@@ -541,6 +546,8 @@ __global__ __launch_bounds__(512) void k_jacobi_lds(CArr Ra, CArr Va, int32_t P,
           const double2 a1 = cdotc(se, y), b1 = cmul(se, x);
           ci[lane] = make_double2(cs * x.x - a1.x, cs * x.y - a1.y);
           cj[lane] = make_double2(b1.x + cs * y.x, b1.y + cs * y.y);
+        }
+        if (acc && lane < p) {
           double2* vi = sV + i * kJacLds;
           double2* vj = sV + j * kJacLds;
           const double2 u = vi[lane], v = vj[lane];
@@ -559,7 +566,7 @@ __global__ __launch_bounds__(512) void k_jacobi_lds(CArr Ra, CArr Va, int32_t P,
   for (int q = tid; q < P * P; q += 512) {
     const int r = q % P, col = q / P;
     R[q] = sR[r + col * kJacLds];
-    V[q] = sV[r + col * kJacLds];
+    if (acc) Va.at(c)[q] = sV[r + col * kJacLds];
   }
   if (tid == 0) {
     int32_t* t = sst.at(c);
@@ -976,6 +983,29 @@ __global__ __launch_bounds__(256) void k_to_colmajor(const double2* __restrict__
   }
 }
 
+// dst = src^* on the leading k x k block of two P x P column-major matrices (ld P), through
+// 32 x 32 LDS tiles.  Grid (ceil(k / 32), ceil(k / 32), batch), 256 threads.
+__global__ __launch_bounds__(256) void k_ctrans(CArr src, CArr dst, int32_t P, int32_t k) {
+  __shared__ double2 tile[32][33];
+  const int c = blockIdx.z;
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;  // a tile of src: rows r0.., columns c0..
+  const double2* S = src.at(c);
+  double2* D = dst.at(c);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int q = ty; q < 32; q += 8) {  // column c0 + q of src, rows r0 + tx
+    const int r = r0 + tx, col = c0 + q;
+    tile[q][tx] = (r < k && col < k) ? S[(int64_t)col * P + r] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int q = ty; q < 32; q += 8) {  // column r0 + q of dst, rows c0 + tx: src(r0 + q, c0 + tx)^*
+    const int r = c0 + tx, col = r0 + q;
+    if (r < k && col < k) {
+      const double2 v = tile[tx][q];
+      D[(int64_t)col * P + r] = make_double2(v.x, -v.y);
+    }
+  }
+}
+
 int to_colmajor(const double* src, int32_t batch, int32_t rows, int32_t cols, CArr dst, hipStream_t s) {
   k_to_colmajor<<<dim3((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32), (unsigned)batch), dim3(256), 0, s>>>(
       reinterpret_cast<const double2*>(src), (int64_t)rows * cols, rows, cols, dst);
@@ -1129,11 +1159,19 @@ int uhm_cluster_basis(const double* X, int32_t batch, int32_t m, int32_t n, int3
   UHM_HIP(hipGetLastError());
   const QrStep q2{Cq, n, pc, nu, none, dnone, R2, none, 1, P, 0, stB, stA, dnone, P, 0.0, 0};
   if ((rc = run_qr(q2, batch, pbat, s))) return rc;
-  // 3. one-sided Jacobi on R2, the rank rule, the kept columns of J orthonormalised (into R2)
-  if ((rc = run_jacobi(R2, Ja, P, pbat, stA, stS, batch, jacobi_tol(P), 60,
+  // 3. one-sided Jacobi on the columns of M = R2^* (in Ja; B = R2^* Q2^*, so the left
+  // singular vectors of B are those of M): M J = W Sigma, and W's columns are the rotated
+  // columns scaled by 1 / sigma, so the rotations J need not be kept.  Then the rank rule,
+  // and the kept columns of M J orthonormalised (into R2).
+  if (pbat > 0) {
+    const unsigned tk = (unsigned)((pbat + 31) / 32);
+    k_ctrans<<<dim3(tk, tk, (unsigned)batch), dim3(256), 0, s>>>(R2, Ja, P, pbat);
+    UHM_HIP(hipGetLastError());
+  }
+  if ((rc = run_jacobi(Ja, none, P, pbat, stA, stS, batch, jacobi_tol(P), 60,
                        reinterpret_cast<int32_t*>(work + ws.per * (int64_t)batch), s)))
     return rc;
-  const Finish f{R2, P, stA, stS, ord, eps, fro, stA, m, n, sv, rank, psteps, stats, status};
+  const Finish f{Ja, P, stA, stS, ord, eps, fro, stA, m, n, sv, rank, psteps, stats, status};
   k_finish<<<dim3((unsigned)batch), dim3(kStepThreads), 0, s>>>(f);
   UHM_HIP(hipGetLastError());
   k_orth<<<dim3((unsigned)batch), dim3(kBigThreads), 0, s>>>(Ja, P, ord, stA, stS, R2, P);
