@@ -455,7 +455,8 @@ int uhm_aca_pack(const uhm_block_desc* blocks, int64_t nblocks, const int32_t* r
  * trailing part's Frobenius norm T is at most tol * ||X_c||_F (p steps; the singular values
  * of the resulting p x n factor B satisfy sigma_i(B)^2 <= sigma_i(X_c)^2 <= sigma_i(B)^2 +
  * T^2, because the trailing part is orthogonal to the kept range), an unpivoted QR of B^*,
- * one-sided Jacobi on its p x p triangle, and the reflectors applied back.  With tol^2 about
+ * one-sided Jacobi on the columns of that triangle's conjugate transpose (whose rotated
+ * columns are the left singular vectors, scaled), and the reflectors applied back.  With tol^2 about
  * 1e-16 eps (1e-11 for eps = 1e-6) a singular value at the threshold eps sigma_1 moves by
  * less than a unit of rounding of sigma_1.
  * X (only read: the library factorises a column-major copy in work), U, SV, sv, rank,

@@ -21,15 +21,17 @@
 //     Columns are never moved: a pivot column is retired (norm marker -1) and R is kept in
 //     the original column order, which is B itself.
 //  2. Unpivoted Householder QR of B^* = Q2 R2, R2 p x p (the same step kernel).
-//  3. One-sided (Hestenes) Jacobi on the columns of R2, with the rotations accumulated in J:
-//     R2 J = W Sigma, so B = R2^* Q2^* = J Sigma (Q2 W)^*: the left singular vectors of B are
-//     the columns of J and its singular values are the column norms.  Round-robin pairs: one
-//     launch per round over the whole batch, one wavefront per pair, and one read-back per
-//     sweep.  The accumulated rotations lose orthogonality at the level of
-//     1e-12, so the kept columns of J are orthonormalised again (classical Gram-Schmidt
-//     applied twice, largest singular value first).
-//  4. U = Q_p [J_l; 0] (the reflectors of step 1 applied in reverse order, the columns held
-//     in registers) and Sigma V^* = J_l^* B.
+//  3. One-sided (Hestenes) Jacobi on the columns of M = R2^*: M J = W Sigma, and since
+//     B = R2^* Q2^* = M Q2^*, the left singular vectors of B are the columns of W, which are
+//     the rotated columns scaled by 1 / sigma_i (the column norms); the rotations J are not
+//     kept.  A rotated column carries an absolute error of about eps_mach sigma_1, so the
+//     direction of w_i is off by about eps_mach sigma_1 / sigma_i, and its share of the
+//     projection error stays at eps_mach sigma_1.  Round-robin pairs: one launch per round
+//     over the whole batch, one wavefront per pair, and one read-back per sweep.  The kept
+//     columns are orthonormalised (classical Gram-Schmidt applied twice, largest singular
+//     value first) into W_l.
+//  4. U = Q_p [W_l; 0] (the reflectors of step 1 applied in reverse order, the columns held
+//     in registers) and Sigma V^* = W_l^* B.
 //
 // Recompression.  A block A|_b ~ X Y^* from ACA (k terms) is brought to its SVD truncated at
 // eps sigma_1: unpivoted QR of both factors, X = Q_X R_X and Y = Q_Y R_Y; one-sided Jacobi
@@ -45,7 +47,7 @@
 namespace uhm_detail {
 namespace {
 
-constexpr int kFacMaxP = 2048;      // largest Jacobi order (columns of J)
+constexpr int kFacMaxP = 2048;      // largest Jacobi order
 constexpr int kFacMaxRows = 16384;  // largest row count: 16 rows per thread in the apply kernel
 constexpr int kStepThreads = 256;
 constexpr int kStepCols = 16;  // columns per workgroup in a QR step: 4 per wavefront
@@ -386,8 +388,8 @@ __global__ __launch_bounds__(NT) void k_qr_step_wide(QrStep a, int32_t k) {
   }
 }
 
-// One-sided Jacobi on the p x p matrix R (ld P; p = pp.at(c)[0]), rotations accumulated in
-// V.  A sweep is P' - 1 rounds (P' = P rounded up to even) of the circle schedule: index 0
+// One-sided Jacobi on the p x p matrix R (ld P; p = pp.at(c)[0]), the rotations accumulated
+// in V unless V is null.  A sweep is P' - 1 rounds (P' = P rounded up to even) of the circle schedule: index 0
 // fixed, the others rotated, so the pairs of a round are disjoint; each round is one launch
 // over the whole batch, one wavefront per pair, and pairs with a column >= p are skipped.
 // A pair (i, j) with Gram entries alpha, beta, gamma is rotated when |gamma| > tol
