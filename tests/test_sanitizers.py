@@ -2,7 +2,7 @@
 
 The C oracle (oracle/uhm_oracle.c: Algorithms 5 and 6) and the host builder
 (csrc/builder_native.cpp: dense blocks, ACA with partial pivoting, the direct
-construction's per-block ACA) are compiled with -fsanitize=address,undefined and no error
+construction's per-block ACA, the scaled copies that lay out the H factors) are compiled with -fsanitize=address,undefined and no error
 recovery, and a child Python process loads those builds (the ASan runtime preloaded) and
 runs them on small ragged clouds: the two-phase and direct builders, and Algorithms 5 and 6
 at 1 and 3 threads, checked against the block-wise definitions.  Any invalid access or
