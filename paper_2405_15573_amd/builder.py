@@ -115,6 +115,70 @@ def _view(a: np.ndarray, dtype=np.complex128):
     return a.__array_interface__["data"][0], st[0] // item, (st[1] // item if a.ndim > 1 else 0), a
 
 
+def _row_records(part, row_blocks, factor_views, base: int, nt: int, kp: int):
+    """uhmb_scaled_copy records that write the cluster matrices of part (a list of (tau, .))
+    as a row-major batch at byte address base, nt x kp each: X_tau = [U_b Sigma_b ...] over
+    tau's block row, conj(V_b) Sigma_b for a mirrored block (s, tau), zero columns after.
+    factor_views(key) gives a stored block's addresses and strides (as in build_operator).
+    Returns the records and, per cluster, its (s, first column, k_b) list."""
+    recs, cols = [], []
+    for c, (t, _) in enumerate(part):
+        j, cl = 0, []
+        row0 = base + 16 * c * nt * kp
+        for s in row_blocks[t]:
+            if t < s:
+                ua, urs, ucs, _, _, _, sa, kb, _ = factor_views((t, s))
+                recs.append((ua, row0 + 16 * j, sa, urs, ucs, kp, 1, nt, kb, 0, 0))
+            else:
+                _, _, _, va, vrs, vcs, sa, kb, _ = factor_views((s, t))
+                recs.append((va, row0 + 16 * j, sa, vrs, vcs, kp, 1, nt, kb, 1, 0))
+            cl.append((s, j, kb))
+            j += kb
+        if j < kp:
+            recs.append((0, row0 + 16 * j, 0, 0, 0, kp, 1, nt, kp - j, 0, 0))
+        cols.append(cl)
+    return recs, cols
+
+
+def _hfactor_records(adm, adm_rank, size, X_off, Y_off, xa0: int, ya0: int, factor_views):
+    """uhmb_scaled_copy records for the H-matrix factors of every admissible block b = (t, s):
+    X_b = U_b Sigma_b and Y_b = V_b, column-major at element offsets X_off[b], Y_off[b] of
+    the arrays at byte addresses xa0, ya0; the mirror of a stored block (s, t) has
+    U_b = conj(V), V_b = conj(U)."""
+    recs = []
+    for b in range(adm.shape[0]):
+        t, s = int(adm[b, 0]), int(adm[b, 1])
+        kb, mt, ms = int(adm_rank[b]), int(size[t]), int(size[s])
+        xa, ya = xa0 + 16 * int(X_off[b]), ya0 + 16 * int(Y_off[b])
+        if t < s:
+            ua, urs, ucs, va, vrs, vcs, sa, _, _ = factor_views((t, s))
+            recs.append((ua, xa, sa, urs, ucs, 1, mt, mt, kb, 0, 0))
+            recs.append((va, ya, 0, vrs, vcs, 1, ms, ms, kb, 0, 0))
+        else:
+            ua, urs, ucs, va, vrs, vcs, sa, _, _ = factor_views((s, t))
+            recs.append((va, xa, sa, vrs, vcs, 1, mt, mt, kb, 1, 0))
+            recs.append((ua, ya, 0, urs, ucs, 1, ms, ms, kb, 1, 0))
+    return recs
+
+
+def _factor_views_of(fac_U, fac_V, fac_s):
+    """factor_views(key) over the stored blocks' factors: (U address, row stride, column
+    stride, the same for V, Sigma address, k_b, kept arrays), made once per block."""
+    views = {}
+
+    def factor_views(key):
+        v = views.get(key)
+        if v is None:
+            ua, urs, ucs, uk = _view(fac_U[key])
+            va, vrs, vcs, vk = _view(fac_V[key])
+            sv = np.ascontiguousarray(fac_s[key], dtype=np.float64)
+            v = (ua, urs, ucs, va, vrs, vcs, sv.__array_interface__["data"][0], int(sv.size), (uk, vk, sv))
+            views[key] = v
+        return v
+
+    return factor_views
+
+
 def _ptr(a: np.ndarray):
     return ctypes.c_void_p(a.ctypes.data)
 
@@ -593,19 +657,8 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
             return fac_U[(t, s)], fac_s[(t, s)], fac_V[(t, s)]
         return np.conj(fac_V[(s, t)]), fac_s[(s, t)], np.conj(fac_U[(s, t)])
 
-    views = {}   # stored block (t < s) -> addresses and strides of U_b, V_b, Sigma_b, and k_b
-
-    def factor_views(key):
-        """(U address, row stride, column stride, the same for V, Sigma address, k_b) of a
-        stored block, for uhmb_scaled_copy; copies made for it are kept in the entry."""
-        v = views.get(key)
-        if v is None:
-            ua, urs, ucs, uk = _view(fac_U[key])
-            va, vrs, vcs, vk = _view(fac_V[key])
-            sv = np.ascontiguousarray(fac_s[key], dtype=np.float64)
-            v = (ua, urs, ucs, va, vrs, vcs, sv.__array_interface__["data"][0], int(sv.size), (uk, vk, sv))
-            views[key] = v
-        return v
+    # stored block (t < s) -> addresses and strides of U_b, V_b, Sigma_b, for uhmb_scaled_copy
+    factor_views = _factor_views_of(fac_U, fac_V, fac_s)
 
     # ---- uniform compression, one SVD per cluster (row side; column side by symmetry)
     t2 = time.perf_counter()
@@ -673,24 +726,7 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
             nt = int(size[part[0][0]])
             kp = max(k for _, k in part)
             buf = torch.empty((len(part), nt, kp), dtype=torch.complex128, pin_memory=True)
-            base = buf.data_ptr()
-            cols = [None] * len(part)
-            recs = []
-            for c, (t, _) in enumerate(part):
-                j, cl = 0, []
-                row0 = base + 16 * c * nt * kp
-                for s in row_blocks[t]:
-                    if t < s:
-                        ua, urs, ucs, _, _, _, sa, kb, _ = factor_views((t, s))
-                        recs.append((ua, row0 + 16 * j, sa, urs, ucs, kp, 1, nt, kb, 0, 0))
-                    else:
-                        _, _, _, va, vrs, vcs, sa, kb, _ = factor_views((s, t))
-                        recs.append((va, row0 + 16 * j, sa, vrs, vcs, kp, 1, nt, kb, 1, 0))
-                    cl.append((s, j, kb))
-                    j += kb
-                if j < kp:
-                    recs.append((0, row0 + 16 * j, 0, 0, 0, kp, 1, nt, kp - j, 0, 0))
-                cols[c] = cl
+            recs, cols = _row_records(part, row_blocks, factor_views, buf.data_ptr(), nt, kp)
             _scaled_copy(recs)
             return buf, cols, time.perf_counter() - t0
 
@@ -906,24 +942,10 @@ def build_operator(cloud: PointCloud, leaf: int = 64, eta: float = 1.0, eps_aca:
     Xh = np.empty(int(xs.sum()), np.complex128)
     Yh = np.empty(int(ys.sum()), np.complex128)
 
-    # X_b = U_b Sigma_b and Y_b = V_b column-major, by the native copy; the mirror of a
-    # stored block (s, t) has U_b = conj(V), V_b = conj(U)
-    xa0, ya0 = Xh.__array_interface__["data"][0], Yh.__array_interface__["data"][0]
-    recs = []
-    for b in range(nadm):
-        t, s = int(adm[b, 0]), int(adm[b, 1])
-        kb, mt, ms = int(adm_rank[b]), int(size[t]), int(size[s])
-        xa, ya = xa0 + 16 * int(X_off[b]), ya0 + 16 * int(Y_off[b])
-        if t < s:
-            ua, urs, ucs, va, vrs, vcs, sa, _, _ = factor_views((t, s))
-            recs.append((ua, xa, sa, urs, ucs, 1, mt, mt, kb, 0, 0))
-            recs.append((va, ya, 0, vrs, vcs, 1, ms, ms, kb, 0, 0))
-        else:
-            ua, urs, ucs, va, vrs, vcs, sa, _, _ = factor_views((s, t))
-            recs.append((va, xa, sa, vrs, vcs, 1, mt, mt, kb, 1, 0))
-            recs.append((ua, ya, 0, urs, ucs, 1, ms, ms, kb, 1, 0))
-    _scaled_copy(recs)
-    del recs, views, fac_U, fac_V, Lmat
+    # X_b = U_b Sigma_b and Y_b = V_b column-major, by the native copy
+    _scaled_copy(_hfactor_records(adm, adm_rank, size, X_off, Y_off, Xh.__array_interface__["data"][0],
+                                  Yh.__array_interface__["data"][0], factor_views))
+    del factor_views, fac_U, fac_V, Lmat
     tim["factors"] = time.perf_counter() - t5
 
     # ---- dense near field
